@@ -1,0 +1,239 @@
+/*
+ * rw.h - C ABI of librw, a gfx950 (MI355X) implementation of precomputed-eigenvector random-walker
+ * segmentation (Andrews & Hamarneh, "Adaptable Precomputation for Random Walker Image Segmentation
+ * and Registration").
+ *
+ * Conventions (every entry point):
+ *   - Returns an int status: RW_OK (0) or a negative RW_E* code.  No exception or abort crosses the
+ *     ABI.  rw_last_error() returns a message for the calling thread's last failure.
+ *   - All device memory is owned by the caller: inputs, outputs, the graph buffer and workspaces
+ *     are device pointers the caller allocated (sizes from the *_bytes / *_workspace_bytes queries).
+ *     The library never allocates device memory.  Host arrays (seeds, edit lists) are read during
+ *     the call and not retained.
+ *   - Work is enqueued on the given HIP stream.  Calls that must inspect a device result (a status
+ *     word, a convergence test) synchronize that stream before returning; all others return after
+ *     enqueueing.
+ *   - Images have dims (nx, ny, nz) (nz = 1 in 2D) and N = nx*ny*nz nodes numbered
+ *     i = x + nx*(y + ny*z).  Blocks of vectors are column-major N x b: vector j occupies
+ *     [j*N, (j+1)*N).  Label maps are C x N (label k's map contiguous).
+ *   - Edges are numbered e = dir*N + tail for the edge joining `tail` and tail + offset(dir), with
+ *     forward directions in this order: 2D 4-connected (+x, +y); 2D 8-connected (+x, +y, +x+y, +x-y);
+ *     3D 6-connected (+x, +y, +z).  An id whose head lies outside the grid is invalid.
+ */
+#ifndef RW_H
+#define RW_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define RW_OK 0
+#define RW_EINVAL (-1)       /* an argument is out of range or inconsistent */
+#define RW_ENOCONV (-2)      /* an iteration hit its limit; the best iterate is left in the outputs */
+#define RW_EUNANCHORED (-3)  /* a connected component of the graph holds no seed (gamma = 0) */
+#define RW_ESINGULAR (-4)    /* a small dense system has a pivot below its threshold */
+#define RW_EWORKSPACE (-5)   /* the buffer passed is smaller than the query returned */
+#define RW_EHIP (-6)         /* a HIP runtime call failed */
+
+/* ---- element types ---- */
+#define RW_F64 0
+#define RW_F32 1
+#define RW_BF16 2
+
+/* ---- edge-weight forms (Sec. II-A, eq. (2)) ---- */
+#define RW_WEIGHT_SQUARED 0  /* w = s_e * exp(-beta (J_i - J_j)^2) (default) */
+#define RW_WEIGHT_ABS 1      /* w = s_e * exp(-beta |J_i - J_j|)   (the paper's printed form) */
+
+typedef struct rw_graph_s* rw_graph;
+
+typedef struct {
+  int32_t ndim;        /* 2 or 3 */
+  int64_t dims[3];     /* nx, ny, nz; nz = 1 when ndim = 2; each >= 1, N >= 2 */
+  int32_t conn;        /* 4 or 8 when ndim = 2; 6 when ndim = 3 */
+  int32_t dtype;       /* RW_F64 or RW_F32: type of the stored weights and of rw_apply_laplacian */
+  int32_t weight_form; /* RW_WEIGHT_SQUARED or RW_WEIGHT_ABS */
+  int32_t normalized;  /* 1: the operator is L_hat = D^{-1/2} L D^{-1/2} (Sec. II-C); 0: L = D - W */
+} rw_graph_desc;
+
+const char* rw_last_error(void);
+int rw_version(void);
+
+/* ======================================================================================
+ * Graph (Sec. II-A eq. (2); Sec. II-C)
+ * ====================================================================================== */
+
+/* Bytes of device memory rw_build_graph needs for this description. */
+int rw_graph_bytes(const rw_graph_desc* desc, size_t* bytes);
+
+/* Build the weighted image graph of intensities J (device, N values of J_dtype = RW_F64 or RW_F32)
+ * with parameter beta >= 0 into the caller's device buffer graph_buf (>= rw_graph_bytes; it must
+ * stay allocated while the handle is used; J is copied).  Computes per forward edge the weight, a
+ * presence bit (uint8 mask per node, bit dir), the degree d, d^{-1/2} (0 where d = 0), the unit null
+ * vector (D^{1/2}1/||D^{1/2}1|| or 1/sqrt(N)) and the operator's coefficients.  Every edge starts
+ * present with scale 1.  *out receives a host handle; free it with rw_graph_destroy.
+ * Errors: RW_EINVAL (bad description, beta < 0 or not finite, null pointers), RW_EWORKSPACE. */
+int rw_build_graph(const rw_graph_desc* desc, const void* J_dev, int J_dtype, double beta,
+                   void* graph_buf, size_t buf_bytes, hipStream_t stream, rw_graph* out);
+
+int rw_graph_destroy(rw_graph g);
+
+/* Device views of the graph's arrays (for tests and for callers that fuse their own work).
+ * Arrays of `dtype` are the graph's dtype; planes are ndir x N, direction-major. */
+typedef struct {
+  int64_t N;
+  int32_t ndir;
+  int32_t dtype;
+  double beta;
+  const double* J;      /* N, FP64 copy of the intensities */
+  const void* weight;   /* ndir x N: w_e = s_e * exp(...) (0 where absent / off-grid) */
+  const void* scale;    /* ndir x N: s_e (0 where absent / off-grid) */
+  const void* coef;     /* ndir x N: off-diagonal magnitude of the operator, w_e d_i^{-1/2} d_j^{-1/2} or w_e */
+  const void* diag;     /* N: diagonal of the operator (1 or 0 for L_hat, d for L) */
+  const void* dinv;     /* N: d^{-1/2} (0 where d = 0) */
+  const void* ghat;     /* N: unit null vector */
+  const double* degree; /* N: d in FP64 */
+  const uint8_t* mask;  /* N: bit dir set iff the forward edge in direction dir is present */
+} rw_graph_view;
+int rw_graph_get_view(rw_graph g, rw_graph_view* view);
+
+/* Edits of the graph, applied in array order (Sec. III-B changes beta; the others are weight and
+ * topology edits).  Edge ids must be valid and present (else RW_EINVAL, nothing applied).
+ * SET_BETA recomputes every weight from J with the new beta and keeps the edge scales;
+ * SCALE_EDGES / SCALE_BOX multiply the scale of the listed edges / of the present edges with both
+ * endpoints inside [box_lo, box_hi) by `value` (> 0); REMOVE_EDGES sets their scale to 0 and clears
+ * their mask bits.  Degrees, d^{-1/2}, the null vector and the operator are rebuilt afterwards. */
+#define RW_EDIT_SET_BETA 0
+#define RW_EDIT_SCALE_EDGES 1
+#define RW_EDIT_SCALE_BOX 2
+#define RW_EDIT_REMOVE_EDGES 3
+typedef struct {
+  int32_t kind;
+  double value;              /* new beta, or the scale factor */
+  const int64_t* edge_ids;   /* host array of n edge ids (SCALE_EDGES, REMOVE_EDGES) */
+  int64_t n;
+  int64_t box_lo[3];         /* SCALE_BOX: inclusive lower corner (x, y, z) */
+  int64_t box_hi[3];         /* SCALE_BOX: exclusive upper corner */
+} rw_edit;
+int rw_edit_graph(rw_graph g, const rw_edit* edits, int n_edits, hipStream_t stream);
+
+/* ======================================================================================
+ * Stencil operator (Sec. II-A: L = D - W; Sec. II-C: L_hat)
+ * ====================================================================================== */
+
+/* Y = op(X) for a column-major N x b block in the graph's dtype (X, Y distinct device buffers),
+ * op = L_hat or L per the graph description.  Matrix-free over the 4/8/6-point stencil. */
+int rw_apply_laplacian(rw_graph g, const void* X, void* Y, int64_t b, hipStream_t stream);
+
+/* Fused form used by polynomial filters: Y = alpha * op(X) + beta * X + gamma * Z (Z may be null
+ * when gamma = 0; Z may alias Y). */
+int rw_apply_laplacian_axpby(rw_graph g, const void* X, void* Y, const void* Z, int64_t b,
+                             double alpha, double beta, double gamma, hipStream_t stream);
+
+/* ======================================================================================
+ * Offline eigenpairs (Sec. II-B eq. (6): the m smallest eigenpairs, null pair included)
+ * ====================================================================================== */
+typedef struct {
+  double tol;        /* stop when ||op q_i - lambda_i q_i|| <= tol for every returned pair */
+  int32_t max_iter;  /* outer (filter + Rayleigh-Ritz) iterations */
+  int32_t degree;    /* Chebyshev filter degree per outer iteration (0 -> library default) */
+  int32_t guard;     /* block columns beyond m (0 -> max(8, ceil(m/10))) */
+  uint64_t seed;     /* seed of the random start block */
+  int32_t warm;      /* 1: start from the columns already in Q (m of them) */
+  int32_t q_dtype;   /* RW_F64 or RW_F32: storage of Q and of the block iteration */
+} rw_eig_opts;
+
+typedef struct {
+  int32_t iters;        /* outer iterations run */
+  int32_t n_converged;  /* pairs meeting tol */
+  int64_t spmm_columns; /* total columns passed through the stencil operator */
+  double max_residual;  /* max_i ||op q_i - lambda_i q_i|| */
+  double seconds;       /* wall time of the call */
+} rw_eig_info;
+
+int rw_eig_workspace_bytes(rw_graph g, int m, const rw_eig_opts* opts, size_t* bytes);
+
+/* Compute the m smallest eigenpairs of the graph operator into Q (device, column-major N x m of
+ * opts->q_dtype) and lambda (device, m FP64, increasing).  Column 0 is the analytic unit null
+ * vector with lambda = 0; columns 1.. are orthonormal and orthogonal to it.
+ * Errors: RW_EINVAL (m < 2 or m + guard > N - 1, bad opts), RW_EWORKSPACE, RW_ENOCONV (the best
+ * iterate is left in Q, lambda). */
+int rw_precompute_eig(rw_graph g, int m, const rw_eig_opts* opts, void* Q, double* lambda, void* work,
+                      size_t work_bytes, hipStream_t stream, rw_eig_info* info);
+
+/* ======================================================================================
+ * Online update after graph edits (Sec. III-B)
+ * ====================================================================================== */
+#define RW_UPDATE_DIAG_RQ 0 /* the paper: Q kept (null vector replaced, re-orthonormalized in order),
+                                lambda_i <- q_i^T op_new q_i (eqs. (26)-(28)) */
+#define RW_UPDATE_RR 1      /* Rayleigh-Ritz of op_new on the same span: Q <- Q V, lambda <- Ritz values */
+#define RW_UPDATE_RR_REFINE 2 /* RR, then filtered subspace iterations warm-started from Q until
+                                 the residuals are <= opts->tol */
+
+int rw_update_workspace_bytes(rw_graph g, int m, const rw_eig_opts* opts, size_t* bytes);
+
+/* Apply the edits to the graph (as rw_edit_graph), then update the stored pairs (Q, lambda) of m
+ * columns (Q of opts->q_dtype) for the new operator by `mode`.
+ * Errors: RW_EINVAL, RW_EWORKSPACE, RW_ENOCONV (mode 2). */
+int rw_update_eig(rw_graph g, const rw_edit* edits, int n_edits, int mode, const rw_eig_opts* opts,
+                  void* Q, double* lambda, int m, void* work, size_t work_bytes, hipStream_t stream,
+                  rw_eig_info* info);
+
+/* ======================================================================================
+ * Online random-walker solve in the eigenbasis (Sec. II-B eqs. (7)-(17), gamma = 0 case after
+ * eq. (17); choice of m, Sec. III-A1 eq. (24))
+ * ====================================================================================== */
+typedef struct {
+  int32_t m_used;    /* eigenpairs used */
+  double f_max;      /* S * eps^2 (0 when eps <= 0) */
+  double f_worst;    /* max over labels of the fit (eq. (24)) at m_used (0 when eps <= 0) */
+  double min_pivot;  /* smallest |pivot| / max|entry| of the reduced system's LU */
+} rw_solve_info;
+
+int rw_solve_workspace_bytes(rw_graph g, int m_avail, int64_t S, int C, size_t* bytes);
+
+/* Label probabilities of the gamma = 0 random walker from the stored pairs (Q, lambda):
+ *   Q        device, column-major N x (>= m_avail) of q_dtype (RW_F64, RW_F32 or RW_BF16) with
+ *            column 0 the graph's unit null vector and the other columns orthogonal to it (as
+ *            rw_precompute_eig / rw_update_eig return them); lambda device FP64, lambda[0] = 0;
+ *   seeds    host arrays seed_node[S] (0 <= node < N) and seed_label[S] (0 <= label < C); any order;
+ *            a repeated node with the same label counts once, with different labels is RW_EINVAL;
+ *   eps      <= 0: use m = m_avail; > 0: m = the smallest m in [2, m_avail] whose fit of every
+ *            label's seeds (eq. (24), rho = sqrt(1^T D 1) or sqrt(N)) is <= S * eps^2;
+ *   U        device C x N of the graph's dtype; seed rows are one-hot, a label without seeds is 0.
+ * Seeds are sorted ascending and the reduced (m x m) system
+ *   (Lambda - Q_s^T B Q_n) Y = Q_s^T op_ss U_hat_s
+ * is solved (FP64 LU with partial pivoting); U_hat_n = Q_n Y, U = D^{-1/2} U_hat on non-seeds.
+ * This system is algebraically the (S+1) x (S+1) bordered seed system of the paper's gamma = 0 case
+ * with F_s eliminated.  The call synchronizes `stream`.
+ * Errors: RW_EINVAL, RW_EWORKSPACE, RW_ESINGULAR (pivot < 1e-14 * max|entry|). */
+int rw_solve_seeds(rw_graph g, const void* Q, int q_dtype, const double* lambda, int m_avail,
+                   const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, double eps,
+                   void* U, void* work, size_t work_bytes, hipStream_t stream, rw_solve_info* info);
+
+/* ======================================================================================
+ * Exact random walker by conjugate gradients (Sec. II-A eq. (5), gamma = 0)
+ * ====================================================================================== */
+typedef struct {
+  int32_t iters;        /* CG iterations (max over labels) */
+  double rel_residual;  /* max over labels of ||b - L_n u|| / ||b|| */
+} rw_cg_info;
+
+int rw_cg_workspace_bytes(rw_graph g, int C, size_t* bytes);
+
+/* Solve L_n U_n = -B^T U_s for every label by Jacobi-preconditioned CG in FP64 to a relative
+ * residual <= tol (max_iter iterations at most).  U: device C x N FP64; if x0_given != 0 its
+ * non-seed entries are the initial guess, else CG starts from 0.  Seed rows are one-hot on exit.
+ * The call synchronizes `stream`.  Errors: RW_EINVAL, RW_EWORKSPACE, RW_ENOCONV. */
+int rw_cg_solve(rw_graph g, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C,
+                double tol, int max_iter, int x0_given, double* U, void* work, size_t work_bytes,
+                hipStream_t stream, rw_cg_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RW_H */

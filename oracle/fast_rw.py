@@ -21,8 +21,18 @@ rows of U sum to 1 for any truncation.
 Normalized Laplacian (Sec. II-C): every quantity is taken in hat variables, L -> L_hat,
 U_s -> D_s^{1/2} U_s, g -> D^{1/2} 1 / ||D^{1/2} 1||, and U = D^{-1/2} U_hat at the end.
 A node with d = 0 (no edges at all) gets U = 0.
+
+Exact mode.  R^T carries Lambda'^{-1}, so when the graph has weakly coupled regions (eigenvalues
+1e-9 .. 1e-17 above zero) the bordered system has entries of size 1/lambda and its FP64 solution
+loses up to all of its digits.  With exact=True the seed-side steps (B Q'_n, B R^T, the bordered
+solve and Y = Lambda'^{-1} Q'_s^T F_s) are carried out in exact rational arithmetic on the given FP64
+inputs (Python fractions), Y and c are rounded once to FP64, and only the final reconstruction
+Q'_n Y + g_n c^T runs in FP64.  This evaluates the same equations, in the same order, without
+rounding in the ill-conditioned part.
 """
 from __future__ import annotations
+
+from fractions import Fraction
 
 import numpy as np
 
@@ -42,7 +52,85 @@ def _seed_blocks(graph, seed_node):
     return M, s, n, Ms, B_full
 
 
-def fast_rw_coeffs(graph, Q, lam, seed_node, seed_label, C, m=None):
+def _exact_solve(A, b):
+    """Gaussian elimination with (first non-zero) pivoting over the rationals; A n x n, b n x k."""
+    n = len(A)
+    A = [row[:] for row in A]
+    b = [row[:] for row in b]
+    for k in range(n):
+        p = next((i for i in range(k, n) if A[i][k] != 0), None)
+        if p is None:
+            raise np.linalg.LinAlgError("singular bordered system")
+        A[k], A[p] = A[p], A[k]
+        b[k], b[p] = b[p], b[k]
+        inv = 1 / A[k][k]
+        for i in range(k + 1, n):
+            f = A[i][k] * inv
+            if f == 0:
+                continue
+            Ai, Ak = A[i], A[k]
+            for j in range(k + 1, n):
+                if Ak[j] != 0:
+                    Ai[j] -= f * Ak[j]
+            bi, bk = b[i], b[k]
+            for j in range(len(bi)):
+                bi[j] -= f * bk[j]
+            Ai[k] = Fraction(0)
+    x = [[Fraction(0)] * len(b[0]) for _ in range(n)]
+    for k in range(n - 1, -1, -1):
+        for j in range(len(b[0])):
+            acc = b[k][j]
+            for i in range(k + 1, n):
+                if A[k][i] != 0:
+                    acc -= A[k][i] * x[i][j]
+            x[k][j] = acc / A[k][k]
+    return x
+
+
+def _coeffs_exact(graph, Qp, lp, ghat, s, Ms, B, Uhat_s, C):
+    F = Fraction
+    S, mp = s.size, Qp.shape[1]
+    Bc = B.tocsr()
+    Qs = [[F(float(v)) for v in row] for row in Qp[s]]
+    inv_l = [1 / F(float(v)) for v in lp]
+    BQn = []                                          # B Q'_n, exactly
+    Bg = []                                           # B g_n, exactly
+    for i in range(S):
+        lo, hi = Bc.indptr[i], Bc.indptr[i + 1]
+        cols, vals = Bc.indices[lo:hi], Bc.data[lo:hi]
+        row = [F(0)] * mp
+        gsum = F(0)
+        for t, bv in zip(cols, vals):
+            fb = F(float(bv))
+            gsum += fb * F(float(ghat[t]))
+            qt = Qp[t]
+            for j in range(mp):
+                row[j] += fb * F(float(qt[j]))
+        BQn.append(row)
+        Bg.append(gsum)
+    A = [[BQn[i][j] * inv_l[j] for j in range(mp)] for i in range(S)]      # B Q'_n Lambda'^{-1}
+    K = [[(F(1) if i == k else F(0)) - sum(A[i][j] * Qs[k][j] for j in range(mp)) for k in range(S)]
+         + [-Bg[i]] for i in range(S)]
+    K.append([F(float(ghat[v])) for v in s] + [F(0)])
+    Msc = Ms.tocsr()
+    rhs = []
+    for i in range(S):
+        lo, hi = Msc.indptr[i], Msc.indptr[i + 1]
+        acc = [F(0)] * C
+        for t, mv in zip(Msc.indices[lo:hi], Msc.data[lo:hi]):
+            for c in range(C):
+                if Uhat_s[t, c] != 0:
+                    acc[c] += F(float(mv)) * F(float(Uhat_s[t, c]))
+        rhs.append(acc)
+    rhs.append([F(0)] * C)
+    sol = _exact_solve(K, rhs)
+    Fs, c = sol[:S], sol[S]
+    Y = np.array([[float(inv_l[j] * sum(Qs[k][j] * Fs[k][cc] for k in range(S))) for cc in range(C)]
+                  for j in range(mp)])
+    return Y, np.array([float(v) for v in c])
+
+
+def fast_rw_coeffs(graph, Q, lam, seed_node, seed_label, C, m=None, exact=False):
     """Solve the gamma = 0 bordered system.  Returns (Qp, Y, c) such that the hat-variable
     probabilities at a non-seed node i are  Qp[i] @ Y + ghat[i] * c."""
     m = Q.shape[1] if m is None else m
@@ -52,6 +140,9 @@ def fast_rw_coeffs(graph, Q, lam, seed_node, seed_label, C, m=None):
     M, s, n, Ms, B = _seed_blocks(graph, seed_node)
     S = s.size
     Uhat_s = graph.hat_scale()[s][:, None] * one_hot(seed_label, C)
+    if exact:
+        Y, c = _coeffs_exact(graph, Qp, lp, ghat, s, Ms, B, Uhat_s, C)
+        return Qp, Y, c
     Qs = Qp[s]                                       # Q'_s
     BQn = B @ Qp                                     # B Q'_n      (S x m')
     BRt = BQn @ (Qs / lp[None, :]).T                 # B R^T = B Q'_n Lambda'^{-1} Q'_s^T   (S x S)
@@ -68,9 +159,9 @@ def fast_rw_coeffs(graph, Q, lam, seed_node, seed_label, C, m=None):
     return Qp, Y, c
 
 
-def fast_rw(graph, Q, lam, seed_node, seed_label, C, m=None, rows=None):
+def fast_rw(graph, Q, lam, seed_node, seed_label, C, m=None, rows=None, exact=False):
     """Label probabilities U (N x C, or len(rows) x C) of the gamma = 0 fast random walker."""
-    Qp, Y, c = fast_rw_coeffs(graph, Q, lam, seed_node, seed_label, C, m)
+    Qp, Y, c = fast_rw_coeffs(graph, Q, lam, seed_node, seed_label, C, m, exact=exact)
     ghat = graph.ghat()
     hs = graph.hat_scale()
     N = graph.N

@@ -1,0 +1,363 @@
+"""Python binding of librw (include/rw.h): precomputed-eigenvector random-walker segmentation on
+MI355X (gfx950).
+
+This module only marshals arguments: every step of the computation runs in the HIP library.
+PyTorch provides device memory (torch tensors on a ROCm device) and the current HIP stream.
+The library must have been built (python -m paper_1607_04174_amd.build); importing the binding
+without it raises immediately - there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librw.so")
+
+RW_OK, RW_EINVAL, RW_ENOCONV, RW_EUNANCHORED, RW_ESINGULAR, RW_EWORKSPACE, RW_EHIP = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "RW_OK", -1: "RW_EINVAL", -2: "RW_ENOCONV", -3: "RW_EUNANCHORED", -4: "RW_ESINGULAR",
+                -5: "RW_EWORKSPACE", -6: "RW_EHIP"}
+RW_F64, RW_F32, RW_BF16 = 0, 1, 2
+RW_EDIT_SET_BETA, RW_EDIT_SCALE_EDGES, RW_EDIT_SCALE_BOX, RW_EDIT_REMOVE_EDGES = 0, 1, 2, 3
+RW_UPDATE_DIAG_RQ, RW_UPDATE_RR, RW_UPDATE_RR_REFINE = 0, 1, 2
+
+_TORCH_DT = {torch.float64: RW_F64, torch.float32: RW_F32, torch.bfloat16: RW_BF16}
+_DT_TORCH = {v: k for k, v in _TORCH_DT.items()}
+
+
+class RWError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class rw_graph_desc(ct.Structure):
+    _fields_ = [("ndim", ct.c_int32), ("dims", ct.c_int64 * 3), ("conn", ct.c_int32), ("dtype", ct.c_int32),
+                ("weight_form", ct.c_int32), ("normalized", ct.c_int32)]
+
+
+class rw_graph_view(ct.Structure):
+    _fields_ = [("N", ct.c_int64), ("ndir", ct.c_int32), ("dtype", ct.c_int32), ("beta", ct.c_double),
+                ("J", ct.c_void_p), ("weight", ct.c_void_p), ("scale", ct.c_void_p), ("coef", ct.c_void_p),
+                ("diag", ct.c_void_p), ("dinv", ct.c_void_p), ("ghat", ct.c_void_p), ("degree", ct.c_void_p),
+                ("mask", ct.c_void_p)]
+
+
+class rw_edit(ct.Structure):
+    _fields_ = [("kind", ct.c_int32), ("value", ct.c_double), ("edge_ids", ct.c_void_p), ("n", ct.c_int64),
+                ("box_lo", ct.c_int64 * 3), ("box_hi", ct.c_int64 * 3)]
+
+
+class rw_eig_opts(ct.Structure):
+    _fields_ = [("tol", ct.c_double), ("max_iter", ct.c_int32), ("degree", ct.c_int32), ("guard", ct.c_int32),
+                ("seed", ct.c_uint64), ("warm", ct.c_int32), ("q_dtype", ct.c_int32)]
+
+
+class rw_eig_info(ct.Structure):
+    _fields_ = [("iters", ct.c_int32), ("n_converged", ct.c_int32), ("spmm_columns", ct.c_int64),
+                ("max_residual", ct.c_double), ("seconds", ct.c_double)]
+
+
+class rw_solve_info(ct.Structure):
+    _fields_ = [("m_used", ct.c_int32), ("f_max", ct.c_double), ("f_worst", ct.c_double),
+                ("min_pivot", ct.c_double)]
+
+
+class rw_cg_info(ct.Structure):
+    _fields_ = [("iters", ct.c_int32), ("rel_residual", ct.c_double)]
+
+
+_lib = None
+
+_SIGS = {
+    "rw_last_error": (ct.c_char_p, []),
+    "rw_version": (ct.c_int, []),
+    "rw_graph_bytes": (ct.c_int, [ct.POINTER(rw_graph_desc), ct.POINTER(ct.c_size_t)]),
+    "rw_build_graph": (ct.c_int, [ct.POINTER(rw_graph_desc), ct.c_void_p, ct.c_int, ct.c_double, ct.c_void_p,
+                                  ct.c_size_t, ct.c_void_p, ct.POINTER(ct.c_void_p)]),
+    "rw_graph_destroy": (ct.c_int, [ct.c_void_p]),
+    "rw_graph_get_view": (ct.c_int, [ct.c_void_p, ct.POINTER(rw_graph_view)]),
+    "rw_edit_graph": (ct.c_int, [ct.c_void_p, ct.POINTER(rw_edit), ct.c_int, ct.c_void_p]),
+    "rw_apply_laplacian": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p]),
+    "rw_apply_laplacian_axpby": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64,
+                                            ct.c_double, ct.c_double, ct.c_double, ct.c_void_p]),
+    "rw_eig_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(rw_eig_opts), ct.POINTER(ct.c_size_t)]),
+    "rw_precompute_eig": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(rw_eig_opts), ct.c_void_p, ct.c_void_p,
+                                     ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.POINTER(rw_eig_info)]),
+    "rw_update_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(rw_eig_opts),
+                                             ct.POINTER(ct.c_size_t)]),
+    "rw_update_eig": (ct.c_int, [ct.c_void_p, ct.POINTER(rw_edit), ct.c_int, ct.c_int, ct.POINTER(rw_eig_opts),
+                                 ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_size_t, ct.c_void_p,
+                                 ct.POINTER(rw_eig_info)]),
+    "rw_solve_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_int64, ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_solve_seeds": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p,
+                                  ct.c_void_p, ct.c_int64, ct.c_int, ct.c_double, ct.c_void_p, ct.c_void_p,
+                                  ct.c_size_t, ct.c_void_p, ct.POINTER(rw_solve_info)]),
+    "rw_cg_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_cg_solve": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int, ct.c_double, ct.c_int,
+                               ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p,
+                               ct.POINTER(rw_cg_info)]),
+}
+
+
+def lib():
+    """The loaded librw (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1607_04174_amd.build`")
+        L = ct.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def declared_symbols():
+    return list(_SIGS)
+
+
+def _check(status: int):
+    if status != RW_OK:
+        raise RWError(status, lib().rw_last_error().decode(errors="replace"))
+
+
+def _stream(device=None):
+    return ct.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ct.c_void_p(t.data_ptr()) if t is not None else ct.c_void_p(0)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------------------------------------
+# graph
+# ---------------------------------------------------------------------------------------------
+class Graph:
+    """Weighted image graph (Sec. II-A eq. (2)) living in a device buffer owned by this object."""
+
+    def __init__(self, J: torch.Tensor, dims: Sequence[int], conn: int, beta: float, dtype=torch.float32,
+                 weight_form: str = "squared", normalized: bool = True):
+        dims = tuple(int(v) for v in dims) + (1,) * (3 - len(dims))
+        self.dims = dims
+        self.ndim = 2 if dims[2] == 1 else 3
+        self.N = dims[0] * dims[1] * dims[2]
+        self.conn = conn
+        self.dtype = dtype
+        self.normalized = normalized
+        self.device = J.device
+        d = rw_graph_desc()
+        d.ndim = self.ndim
+        for k in range(3):
+            d.dims[k] = dims[k]
+        d.conn = conn
+        d.dtype = _TORCH_DT[dtype]
+        d.weight_form = 0 if weight_form == "squared" else 1
+        d.normalized = 1 if normalized else 0
+        self._desc = d
+        nb = ct.c_size_t()
+        _check(lib().rw_graph_bytes(ct.byref(d), ct.byref(nb)))
+        self.buf = torch.empty(nb.value, dtype=torch.uint8, device=J.device)
+        J = J.contiguous()
+        if J.numel() != self.N or J.dtype not in (torch.float32, torch.float64):
+            raise ValueError("J must hold N float32/float64 values")
+        self._J = J
+        h = ct.c_void_p()
+        _check(lib().rw_build_graph(ct.byref(d), _ptr(J), _TORCH_DT[J.dtype], float(beta), _ptr(self.buf), nb.value,
+                                    _stream(J.device), ct.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.rw_graph_destroy(h)
+            self.handle = None
+
+    def view(self):
+        """dict of torch tensors aliasing the graph's device arrays."""
+        v = rw_graph_view()
+        _check(lib().rw_graph_get_view(self.handle, ct.byref(v)))
+        base = self.buf.data_ptr()
+        N, nd = v.N, v.ndir
+        tdt = _DT_TORCH[v.dtype]
+        es = torch.empty((), dtype=tdt).element_size()
+
+        def sl(ptr, count, dt, esz):
+            off = ptr - base
+            return self.buf[off: off + count * esz].view(dt)
+
+        return {"beta": v.beta, "J": sl(v.J, N, torch.float64, 8),
+                "weight": sl(v.weight, nd * N, tdt, es).view(nd, N), "scale": sl(v.scale, nd * N, tdt, es).view(nd, N),
+                "coef": sl(v.coef, nd * N, tdt, es).view(nd, N), "diag": sl(v.diag, N, tdt, es),
+                "dinv": sl(v.dinv, N, tdt, es), "ghat": sl(v.ghat, N, tdt, es),
+                "degree": sl(v.degree, N, torch.float64, 8), "mask": sl(v.mask, N, torch.uint8, 1)}
+
+
+def build_graph(J, dims, conn, beta, dtype=torch.float32, weight_form="squared", normalized=True) -> Graph:
+    return Graph(J, dims, conn, beta, dtype, weight_form, normalized)
+
+
+def _edits(edits):
+    arr = (rw_edit * max(1, len(edits)))()
+    keep = []
+    for k, e in enumerate(edits):
+        kind = {"set_beta": RW_EDIT_SET_BETA, "scale_edges": RW_EDIT_SCALE_EDGES, "scale_box": RW_EDIT_SCALE_BOX,
+                "remove_edges": RW_EDIT_REMOVE_EDGES}[e.kind]
+        arr[k].kind = kind
+        arr[k].value = float(e.value)
+        if e.edge_ids is not None:
+            ids = np.ascontiguousarray(np.asarray(e.edge_ids, dtype=np.int64))
+            keep.append(ids)
+            arr[k].edge_ids = ids.ctypes.data
+            arr[k].n = ids.size
+        lo = tuple(e.box_lo) + (0,) * (3 - len(e.box_lo))
+        hi = tuple(e.box_hi) + (1,) * (3 - len(e.box_hi))
+        for q in range(3):
+            arr[k].box_lo[q] = int(lo[q])
+            arr[k].box_hi[q] = int(hi[q])
+    return arr, keep
+
+
+def edit_graph(g: Graph, edits) -> None:
+    """Apply edits (objects with kind, value, box_lo, box_hi, edge_ids) in order."""
+    arr, keep = _edits(edits)
+    _check(lib().rw_edit_graph(g.handle, arr, len(edits), _stream(g.device)))
+
+
+def apply_laplacian(g: Graph, X: torch.Tensor, Y: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Y = op X for X of shape (b, N) (each row one vector, i.e. column-major N x b)."""
+    X = X.contiguous()
+    b = X.numel() // g.N
+    if Y is None:
+        Y = torch.empty_like(X)
+    _check(lib().rw_apply_laplacian(g.handle, _ptr(X), _ptr(Y), b, _stream(g.device)))
+    return Y
+
+
+def apply_laplacian_axpby(g: Graph, X, Y, Z, alpha, beta, gamma):
+    b = X.numel() // g.N
+    _check(lib().rw_apply_laplacian_axpby(g.handle, _ptr(X), _ptr(Y), _ptr(Z), b, float(alpha), float(beta),
+                                          float(gamma), _stream(g.device)))
+    return Y
+
+
+# ---------------------------------------------------------------------------------------------
+# eigenpairs and updates
+# ---------------------------------------------------------------------------------------------
+def _eig_opts(tol, max_iter, degree, guard, seed, warm, q_dtype):
+    o = rw_eig_opts()
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.degree = int(degree)
+    o.guard = int(guard)
+    o.seed = int(seed)
+    o.warm = int(warm)
+    o.q_dtype = _TORCH_DT[q_dtype]
+    return o
+
+
+def precompute_eig(g: Graph, m: int, tol: float = 1e-5, max_iter: int = 200, degree: int = 0, guard: int = 0,
+                   seed: int = 0, q_dtype=None, Q: Optional[torch.Tensor] = None, warm: bool = False,
+                   raise_on_noconv: bool = True):
+    """The m smallest eigenpairs.  Returns (Q (m, N) tensor, lambda (m,) float64 tensor, info dict)."""
+    q_dtype = q_dtype or g.dtype
+    o = _eig_opts(tol, max_iter, degree, guard, seed, warm, q_dtype)
+    if Q is None:
+        Q = torch.empty((m, g.N), dtype=q_dtype, device=g.device)
+    lam = torch.empty(m, dtype=torch.float64, device=g.device)
+    nb = ct.c_size_t()
+    _check(lib().rw_eig_workspace_bytes(g.handle, m, ct.byref(o), ct.byref(nb)))
+    work = _workspace(nb.value, g.device)
+    info = rw_eig_info()
+    st = lib().rw_precompute_eig(g.handle, m, ct.byref(o), _ptr(Q), _ptr(lam), _ptr(work), nb.value,
+                                 _stream(g.device), ct.byref(info))
+    if st != RW_OK and not (st == RW_ENOCONV and not raise_on_noconv):
+        _check(st)
+    return Q, lam, {"iters": info.iters, "n_converged": info.n_converged, "spmm_columns": info.spmm_columns,
+                    "max_residual": info.max_residual, "seconds": info.seconds, "status": st}
+
+
+def update_eig(g: Graph, edits, Q: torch.Tensor, lam: torch.Tensor, mode: int = RW_UPDATE_RR, tol: float = 1e-5,
+               max_iter: int = 200, degree: int = 0, guard: int = 0, raise_on_noconv: bool = True):
+    """Apply edits to g and update (Q, lam) in place by `mode`.  Returns the info dict."""
+    m = Q.shape[0]
+    o = _eig_opts(tol, max_iter, degree, guard, 0, 1, Q.dtype)
+    nb = ct.c_size_t()
+    _check(lib().rw_update_workspace_bytes(g.handle, m, ct.byref(o), ct.byref(nb)))
+    work = _workspace(nb.value, g.device)
+    arr, keep = _edits(edits)
+    info = rw_eig_info()
+    st = lib().rw_update_eig(g.handle, arr, len(edits), int(mode), ct.byref(o), _ptr(Q), _ptr(lam), m, _ptr(work),
+                             nb.value, _stream(g.device), ct.byref(info))
+    if st != RW_OK and not (st == RW_ENOCONV and not raise_on_noconv):
+        _check(st)
+    return {"iters": info.iters, "n_converged": info.n_converged, "spmm_columns": info.spmm_columns,
+            "max_residual": info.max_residual, "seconds": info.seconds, "status": st}
+
+
+# ---------------------------------------------------------------------------------------------
+# online solve
+# ---------------------------------------------------------------------------------------------
+class SolveWorkspace:
+    """Reusable device workspace for solve_seeds (grown on demand)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes, device):
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = _workspace(nbytes, device)
+        return self.buf
+
+
+def solve_seeds(g: Graph, Q: torch.Tensor, lam: torch.Tensor, seed_node, seed_label, C: int, eps: float = 0.0,
+                m_avail: Optional[int] = None, U: Optional[torch.Tensor] = None,
+                workspace: Optional[SolveWorkspace] = None):
+    """Label probabilities (C, N) in the graph's dtype from the eigenbasis.  Returns (U, info dict)."""
+    m_avail = Q.shape[0] if m_avail is None else int(m_avail)
+    nodes = np.ascontiguousarray(np.asarray(seed_node, dtype=np.int64))
+    labels = np.ascontiguousarray(np.asarray(seed_label, dtype=np.int32))
+    S = nodes.size
+    if U is None:
+        U = torch.empty((C, g.N), dtype=g.dtype, device=g.device)
+    nb = ct.c_size_t()
+    _check(lib().rw_solve_workspace_bytes(g.handle, m_avail, max(S, 1), C, ct.byref(nb)))
+    work = (workspace or SolveWorkspace()).get(nb.value, g.device)
+    info = rw_solve_info()
+    _check(lib().rw_solve_seeds(g.handle, _ptr(Q), _TORCH_DT[Q.dtype], _ptr(lam), m_avail,
+                                ct.c_void_p(nodes.ctypes.data), ct.c_void_p(labels.ctypes.data), S, C, float(eps),
+                                _ptr(U), _ptr(work), work.numel(), _stream(g.device), ct.byref(info)))
+    return U, {"m_used": info.m_used, "f_max": info.f_max, "f_worst": info.f_worst, "min_pivot": info.min_pivot}
+
+
+def cg_solve(g: Graph, seed_node, seed_label, C: int, tol: float = 1e-12, max_iter: int = 100000,
+             U0: Optional[torch.Tensor] = None, raise_on_noconv: bool = True):
+    """Exact random walker by FP64 CG.  Returns (U (C, N) float64, info dict)."""
+    nodes = np.ascontiguousarray(np.asarray(seed_node, dtype=np.int64))
+    labels = np.ascontiguousarray(np.asarray(seed_label, dtype=np.int32))
+    if U0 is not None:
+        U = U0.to(torch.float64).contiguous().clone()
+    else:
+        U = torch.empty((C, g.N), dtype=torch.float64, device=g.device)
+    nb = ct.c_size_t()
+    _check(lib().rw_cg_workspace_bytes(g.handle, C, ct.byref(nb)))
+    work = _workspace(nb.value, g.device)
+    info = rw_cg_info()
+    st = lib().rw_cg_solve(g.handle, ct.c_void_p(nodes.ctypes.data), ct.c_void_p(labels.ctypes.data), nodes.size, C,
+                           float(tol), int(max_iter), 1 if U0 is not None else 0, _ptr(U), _ptr(work), nb.value,
+                           _stream(g.device), ct.byref(info))
+    if st != RW_OK and not (st == RW_ENOCONV and not raise_on_noconv):
+        _check(st)
+    return U, {"iters": info.iters, "rel_residual": info.rel_residual, "status": st}

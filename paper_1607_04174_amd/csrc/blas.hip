@@ -1,0 +1,406 @@
+// Tall-skinny block kernels: Gram products X^T Y with FP64 accumulation (deterministic two-stage
+// reduction), block rotations X V, residual norms, conversions and the random start block.
+#include <cmath>
+
+#include "rw_internal.h"
+
+namespace rw {
+
+// ---------------------------------------------------------------------------------------------
+// Gram: G = X^T Y.  Stage 1: block (tx, ty, chunk) computes a 64 x 64 tile of the product over a
+// chunk of rows, staging 32-row slabs of X and Y in LDS as FP64; each of the 256 threads owns a
+// 4 x 4 sub-tile (rows tx + 16 a, cols ty + 16 b).  Stage 2 sums the chunk partials in order.
+// FP32 x FP32 products are exact in FP64, so FP32 inputs lose nothing before the accumulation.
+// ---------------------------------------------------------------------------------------------
+constexpr int kGT = 64;      // tile edge
+constexpr int kGK = 32;      // rows per LDS slab
+constexpr int64_t kGramRowsPerChunk = 4096;
+
+static int64_t gram_chunks(int64_t rows, int bx, int by) {
+  int64_t tiles = (int64_t)((bx + kGT - 1) / kGT) * ((by + kGT - 1) / kGT);
+  int64_t want = std::max<int64_t>(1, 2048 / std::max<int64_t>(1, tiles));
+  int64_t by_rows = (rows + kGramRowsPerChunk - 1) / kGramRowsPerChunk;
+  int64_t c = std::min<int64_t>(want, by_rows);
+  return std::max<int64_t>(1, c);
+}
+
+size_t gram_partial_count(int64_t rows, int bx, int by) {
+  return (size_t)gram_chunks(rows, bx, by) * bx * by;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram(const T* X, int64_t ldx, const T* Y, int64_t ldy,
+                                              int64_t rows, int bx, int by, int64_t chunk_rows,
+                                              double* out, int64_t out_stride) {
+  __shared__ double sX[kGK][kGT + 1];
+  __shared__ double sY[kGK][kGT + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i0 = blockIdx.x * kGT, j0 = blockIdx.y * kGT;
+  const int64_t r_begin = blockIdx.z * chunk_rows;
+  const int64_t r_end = std::min<int64_t>(rows, r_begin + chunk_rows);
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  const int lr = threadIdx.x & 31;      // row within slab
+  const int lc = threadIdx.x >> 5;      // 0..7: column group
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGK) {
+    const int64_t row = r0 + lr;
+    const bool rin = row < r_end;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int col = lc + 8 * k;
+      int ci = i0 + col, cj = j0 + col;
+      sX[lr][col] = (rin && ci < bx) ? (double)Elem<T>::ld(X, (int64_t)ci * ldx + row) : 0.0;
+      sY[lr][col] = (rin && cj < by) ? (double)Elem<T>::ld(Y, (int64_t)cj * ldy + row) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < kGK; ++k) {
+      double xv[4], yv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) xv[a] = sX[k][tx + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) yv[b] = sY[k][ty + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(xv[a], yv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  double* o = out + blockIdx.z * out_stride;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
+      if (i < bx && j < by) o[(int64_t)j * bx + i] = acc[a][b];
+    }
+}
+
+__global__ void k_sum_chunks(const double* partial, int64_t count, int64_t nchunks, double* G) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  double s = 0.0;
+  for (int64_t c = 0; c < nchunks; ++c) s += partial[c * count + k];
+  G[k] = s;
+}
+
+int gram(int dt, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t rows, int bx, int by,
+         double* G, double* partial, hipStream_t s) {
+  if (bx <= 0 || by <= 0) return RW_OK;
+  int64_t nch = gram_chunks(rows, bx, by);
+  int64_t chunk_rows = (rows + nch - 1) / nch;
+  chunk_rows = (chunk_rows + kGK - 1) / kGK * kGK;
+  if (chunk_rows == 0) chunk_rows = kGK;
+  nch = std::max<int64_t>(1, (rows + chunk_rows - 1) / chunk_rows);
+  dim3 grid((bx + kGT - 1) / kGT, (by + kGT - 1) / kGT, (unsigned)nch);
+  int64_t count = (int64_t)bx * by;
+  double* dst = nch == 1 ? G : partial;
+  if (dt == RW_F64)
+    k_gram<double><<<grid, 256, 0, s>>>((const double*)X, ldx, (const double*)Y, ldy, rows, bx, by, chunk_rows, dst, count);
+  else if (dt == RW_F32)
+    k_gram<float><<<grid, 256, 0, s>>>((const float*)X, ldx, (const float*)Y, ldy, rows, bx, by, chunk_rows, dst, count);
+  else
+    k_gram<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)X, ldx, (const uint16_t*)Y, ldy, rows, bx, by, chunk_rows, dst, count);
+  RW_LAUNCH_CHECK();
+  if (nch > 1) {
+    k_sum_chunks<<<nblocks(count, 256), 256, 0, s>>>(partial, count, nch, G);
+    RW_LAUNCH_CHECK();
+  }
+  return RW_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Z = X V (+ beta Z): X rows x k (type T), V FP64 k x n, Z rows x n (type T).  64 x 64 output tile
+// per 256-thread block, 32-wide k slabs in LDS; compute in Elem<T>::C.
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm(const T* X, int64_t ldx, const double* V, int64_t ldv, T* Z,
+                                              int64_t ldz, int64_t rows, int k, int n, double beta) {
+  using C = typename Elem<T>::C;
+  __shared__ C sX[kGK][kGT + 1];   // [kk][row]
+  __shared__ C sV[kGK][kGT + 1];   // [kk][col]
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * kGT;
+  const int c0 = blockIdx.y * kGT;
+  C acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = C(0);
+  for (int k0 = 0; k0 < k; k0 += kGK) {
+    // X slab: 64 rows x 32 k; thread loads rows (t & 63), k-columns (t >> 6) + 4 q
+    {
+      int lr = threadIdx.x & 63, lk = threadIdx.x >> 6;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        int kk = lk + 4 * q;
+        int64_t row = r0 + lr;
+        sX[kk][lr] = (row < rows && k0 + kk < k) ? Elem<T>::ld(X, (int64_t)(k0 + kk) * ldx + row) : C(0);
+      }
+      int lkk = threadIdx.x & 31, lcol = threadIdx.x >> 5;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        int col = lcol + 8 * q;
+        sV[lkk][col] = (k0 + lkk < k && c0 + col < n) ? (C)V[(int64_t)(c0 + col) * ldv + k0 + lkk] : C(0);
+      }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kGK; ++kk) {
+      C xv[4], vv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) xv[a] = sX[kk][tx + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) vv[b] = sV[kk][ty + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(xv[a], vv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int64_t row = r0 + tx + 16 * a;
+      int col = c0 + ty + 16 * b;
+      if (row < rows && col < n) {
+        int64_t idx = (int64_t)col * ldz + row;
+        C v = acc[a][b];
+        if (beta != 0.0) v += (C)beta * Elem<T>::ld(Z, idx);
+        Elem<T>::st(Z, idx, v);
+      }
+    }
+}
+
+int gemm_tn(int dt, const void* X, int64_t ldx, const double* V, int64_t ldv, void* Z, int64_t ldz,
+            int64_t rows, int k, int n, double beta, hipStream_t s) {
+  if (rows <= 0 || n <= 0) return RW_OK;
+  dim3 grid((unsigned)((rows + kGT - 1) / kGT), (n + kGT - 1) / kGT);
+  if (dt == RW_F64)
+    k_gemm<double><<<grid, 256, 0, s>>>((const double*)X, ldx, V, ldv, (double*)Z, ldz, rows, k, n, beta);
+  else if (dt == RW_F32)
+    k_gemm<float><<<grid, 256, 0, s>>>((const float*)X, ldx, V, ldv, (float*)Z, ldz, rows, k, n, beta);
+  else
+    k_gemm<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)X, ldx, V, ldv, (uint16_t*)Z, ldz, rows, k, n, beta);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// conversions
+// ---------------------------------------------------------------------------------------------
+template <typename S, typename D>
+__global__ void k_convert(const S* src, int64_t lds, D* dst, int64_t ldd, int64_t rows, int cols) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int c = blockIdx.y;
+  if (r >= rows || c >= cols) return;
+  typename Elem<S>::C v = Elem<S>::ld(src, (int64_t)c * lds + r);
+  Elem<D>::st(dst, (int64_t)c * ldd + r, (typename Elem<D>::C)v);
+}
+
+template <typename S>
+static int convert_from(const S* src, int64_t lds, int dt_dst, void* dst, int64_t ldd, int64_t rows, int cols,
+                        hipStream_t s) {
+  dim3 grid(nblocks(rows, 256), cols);
+  if (dt_dst == RW_F64) k_convert<S, double><<<grid, 256, 0, s>>>(src, lds, (double*)dst, ldd, rows, cols);
+  else if (dt_dst == RW_F32) k_convert<S, float><<<grid, 256, 0, s>>>(src, lds, (float*)dst, ldd, rows, cols);
+  else k_convert<S, uint16_t><<<grid, 256, 0, s>>>(src, lds, (uint16_t*)dst, ldd, rows, cols);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+int convert_block(int dt_src, const void* src, int64_t lds, int dt_dst, void* dst, int64_t ldd, int64_t rows,
+                  int cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return RW_OK;
+  RW_CHECK(cols <= 65535, RW_EINVAL, "too many columns to convert");
+  if (dt_src == RW_F64) return convert_from((const double*)src, lds, dt_dst, dst, ldd, rows, cols, s);
+  if (dt_src == RW_F32) return convert_from((const float*)src, lds, dt_dst, dst, ldd, rows, cols, s);
+  return convert_from((const uint16_t*)src, lds, dt_dst, dst, ldd, rows, cols, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// residual norms ||A_j - theta_j B_j|| in FP64, deterministic (per-column block partials)
+// ---------------------------------------------------------------------------------------------
+constexpr int kNormChunks = 64;
+
+template <typename T>
+__global__ void k_colnorm_partial(const T* A, const T* B, const double* theta, int64_t rows, int64_t ld,
+                                  double* partial) {
+  const int col = blockIdx.y;
+  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = blockIdx.x * per, r1 = std::min<int64_t>(rows, r0 + per);
+  double th = theta ? theta[col] : 0.0;
+  double acc = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    double v = (double)Elem<T>::ld(A, (int64_t)col * ld + r);
+    if (theta) v -= th * (double)Elem<T>::ld(B, (int64_t)col * ld + r);
+    acc += v * v;
+  }
+  __shared__ double sh[256];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)col * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ void k_colnorm_final(const double* partial, int nchunks, int cols, double* out) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int k = 0; k < nchunks; ++k) s += partial[(int64_t)c * nchunks + k];
+  out[c] = sqrt(s);
+}
+
+int residual_norms(int dt, const void* A, const void* B, const double* theta, int64_t rows, int cols, int64_t ld,
+                   double* out, double* partial, hipStream_t s) {
+  if (cols <= 0) return RW_OK;
+  RW_CHECK(cols <= 65535, RW_EINVAL, "too many columns");
+  dim3 grid(kNormChunks, cols);
+  if (dt == RW_F64) k_colnorm_partial<double><<<grid, 256, 0, s>>>((const double*)A, (const double*)B, theta, rows, ld, partial);
+  else if (dt == RW_F32) k_colnorm_partial<float><<<grid, 256, 0, s>>>((const float*)A, (const float*)B, theta, rows, ld, partial);
+  else k_colnorm_partial<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)A, (const uint16_t*)B, theta, rows, ld, partial);
+  RW_LAUNCH_CHECK();
+  k_colnorm_final<<<nblocks(cols, 256), 256, 0, s>>>(partial, kNormChunks, cols, out);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+size_t norm_partial_count(int cols) { return (size_t)kNormChunks * cols; }
+
+// ---------------------------------------------------------------------------------------------
+// random start block: standard normals from a counter-based generator (splitmix64 of the element
+// index and seed, then Box-Muller), identical on every launch for the same seed
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ void k_fill_random(T* X, int64_t ld, int64_t rows, int cols, uint64_t seed) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int c = blockIdx.y;
+  if (r >= rows) return;
+  uint64_t h = splitmix64(seed ^ splitmix64((uint64_t)c * 0x100000001b3ull + (uint64_t)r));
+  double u1 = ((h >> 11) + 1.0) * (1.0 / 9007199254740993.0);  // (0, 1]
+  uint64_t h2 = splitmix64(h);
+  double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);          // [0, 1)
+  double v = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  Elem<T>::st(X, (int64_t)c * ld + r, (typename Elem<T>::C)v);
+}
+
+int fill_random(int dt, void* X, int64_t ld, int64_t rows, int cols, uint64_t seed, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return RW_OK;
+  dim3 grid(nblocks(rows, 256), cols);
+  if (dt == RW_F64) k_fill_random<double><<<grid, 256, 0, s>>>((double*)X, ld, rows, cols, seed);
+  else if (dt == RW_F32) k_fill_random<float><<<grid, 256, 0, s>>>((float*)X, ld, rows, cols, seed);
+  else k_fill_random<uint16_t><<<grid, 256, 0, s>>>((uint16_t*)X, ld, rows, cols, seed);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// X -= v (v^T X) for a unit vector v
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_rank1_sub(T* X, int64_t ld, const T* v, const double* t, int64_t rows, int cols) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int c = blockIdx.y;
+  if (r >= rows) return;
+  using C = typename Elem<T>::C;
+  int64_t idx = (int64_t)c * ld + r;
+  C val = Elem<T>::ld(X, idx) - (C)t[c] * Elem<T>::ld(v, r);
+  Elem<T>::st(X, idx, val);
+}
+
+int project_out(int dt, void* X, int64_t ld, const void* v, int64_t rows, int cols, double* tmp, double* partial,
+                hipStream_t s) {
+  if (cols <= 0) return RW_OK;
+  RW_TRY(gram(dt, v, rows, X, ld, rows, 1, cols, tmp, partial, s));
+  dim3 grid(nblocks(rows, 256), cols);
+  if (dt == RW_F64) k_rank1_sub<double><<<grid, 256, 0, s>>>((double*)X, ld, (const double*)v, tmp, rows, cols);
+  else if (dt == RW_F32) k_rank1_sub<float><<<grid, 256, 0, s>>>((float*)X, ld, (const float*)v, tmp, rows, cols);
+  else k_rank1_sub<uint16_t><<<grid, 256, 0, s>>>((uint16_t*)X, ld, (const uint16_t*)v, tmp, rows, cols);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+}  // namespace rw
+
+namespace rw {
+
+// ---------------------------------------------------------------------------------------------
+// column dot products d_j = a_j^T b_j in FP64 (deterministic per-column partials)
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_coldot_partial(const T* A, const T* B, int64_t rows, int64_t ld, double* partial) {
+  const int col = blockIdx.y;
+  const int64_t per = (rows + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = blockIdx.x * per, r1 = std::min<int64_t>(rows, r0 + per);
+  double acc = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x)
+    acc += (double)Elem<T>::ld(A, (int64_t)col * ld + r) * (double)Elem<T>::ld(B, (int64_t)col * ld + r);
+  __shared__ double sh[256];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)col * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ void k_coldot_final(const double* partial, int nchunks, int cols, double* out) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int k = 0; k < nchunks; ++k) s += partial[(int64_t)c * nchunks + k];
+  out[c] = s;
+}
+
+int col_dots(int dt, const void* A, const void* B, int64_t rows, int cols, int64_t ld, double* out, double* partial,
+             hipStream_t s) {
+  if (cols <= 0) return RW_OK;
+  RW_CHECK(cols <= 65535, RW_EINVAL, "too many columns");
+  dim3 grid(kNormChunks, cols);
+  if (dt == RW_F64) k_coldot_partial<double><<<grid, 256, 0, s>>>((const double*)A, (const double*)B, rows, ld, partial);
+  else if (dt == RW_F32) k_coldot_partial<float><<<grid, 256, 0, s>>>((const float*)A, (const float*)B, rows, ld, partial);
+  else k_coldot_partial<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)A, (const uint16_t*)B, rows, ld, partial);
+  RW_LAUNCH_CHECK();
+  k_coldot_final<<<nblocks(cols, 256), 256, 0, s>>>(partial, kNormChunks, cols, out);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+// max |x_i| over a vector (single block, fixed order)
+__global__ void k_absmax(const double* x, int64_t n, double* out) {
+  __shared__ double sh[1024];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fabs(x[i]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+int absmax(const double* x, int64_t n, double* out, hipStream_t s) {
+  k_absmax<<<1, 1024, 0, s>>>(x, n, out);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+}  // namespace rw

@@ -1,0 +1,372 @@
+// Offline eigenpairs of the graph operator (Sec. II-B eq. (6): the m smallest, null pair included)
+// and their online update after graph edits (Sec. III-B eqs. (26)-(28), plus Rayleigh-Ritz).
+//
+// Eigensolver: block Chebyshev-filtered subspace iteration with Rayleigh-Ritz.  The known null
+// vector (eigenvalue 0) is deflated analytically: the block lives in its orthogonal complement and
+// the null vector is written as column 0 of Q.  Each outer iteration applies a degree-d Chebyshev
+// polynomial of the operator that damps [a, b] (a = the largest Ritz value of the block,
+// b = 2 for L_hat, the Gershgorin bound 2 max d for L), i.e. d fused stencil passes over the block,
+// then one Rayleigh-Ritz step: G = F^T F and H = F^T op F in FP64, G = V s V^T, W = V s^{-1/2},
+// eig(W^T H W) = Z Theta Z^T, X = F W Z.  All dense work is FP64; the block itself is in the graph's
+// type.  On MI355X the cost is dominated by the HBM-bound stencil passes, which the polynomial
+// filter amortizes over one FP64 Gram / eigendecomposition per outer iteration.
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "rw_internal.h"
+
+namespace rw {
+
+struct EigWork {
+  char* B[4];
+  double *G, *V, *s, *W, *H, *T, *Hp, *Z, *WZ, *theta, *res, *jac, *tmp, *partial;
+  int* info;
+};
+
+static int guard_of(int m, const rw_eig_opts* o) {
+  if (o && o->guard > 0) return o->guard;
+  return std::max(8, (m + 9) / 10);
+}
+
+static size_t eig_layout(const Graph* g, int nb, void* base, EigWork* w) {
+  Carver c(base);
+  size_t es = dtype_size(g->dtype);
+  EigWork t;
+  for (int k = 0; k < 4; ++k) t.B[k] = c.take<char>((size_t)g->N * nb * es);
+  size_t n2 = (size_t)nb * nb;
+  t.G = c.take<double>(n2); t.V = c.take<double>(n2); t.W = c.take<double>(n2); t.H = c.take<double>(n2);
+  t.T = c.take<double>(n2); t.Hp = c.take<double>(n2); t.Z = c.take<double>(n2); t.WZ = c.take<double>(n2);
+  t.jac = c.take<double>(n2);
+  t.s = c.take<double>(nb); t.theta = c.take<double>(nb); t.res = c.take<double>(nb);
+  t.tmp = c.take<double>(std::max(nb, 16));
+  size_t pc = std::max({gram_partial_count(g->N, nb, nb), norm_partial_count(nb), gram_partial_count(g->N, 1, nb)});
+  t.partial = c.take<double>(pc);
+  t.info = c.take<int>(16);
+  if (w) *w = t;
+  return c.used;
+}
+
+// W(:, j) = V(:, j) / sqrt(max(s_j, floor_rel * s_max)),  s ascending (s_max = s[n-1])
+__global__ void k_scale_cols(const double* V, const double* s, double* W, int n, double floor_rel) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  int j = (int)(t / n);
+  double smax = fmax(s[n - 1], 1e-300);
+  double sj = fmax(s[j], floor_rel * smax);
+  W[t] = V[t] / sqrt(sj);
+}
+
+__global__ void k_symmetrize(double* A, int n) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  int i = (int)(t % n), j = (int)(t / n);
+  if (i < j) {
+    double v = 0.5 * (A[t] + A[j + (int64_t)i * n]);
+    A[t] = v;
+    A[j + (int64_t)i * n] = v;
+  }
+}
+
+// copy column block src (rows x cols, ld_s) into dst (ld_d), with type conversion
+static int copy_cols(int dts, const void* src, int64_t lds, int dtd, void* dst, int64_t ldd, int64_t rows, int cols,
+                     hipStream_t s) {
+  return convert_block(dts, src, lds, dtd, dst, ldd, rows, cols, s);
+}
+
+struct Ctx {
+  const Graph* g;
+  int dt;
+  int64_t N;
+  EigWork w;
+  hipStream_t s;
+  int64_t spmm_cols = 0;
+  double floor_rel;
+};
+
+// One Rayleigh-Ritz step on the block F (nb columns).  Outputs X = F W Z, LX = op X, theta, res.
+static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX) {
+  const Graph* g = c.g;
+  EigWork& w = c.w;
+  RW_TRY(gram(c.dt, F, c.N, F, c.N, c.N, nb, nb, w.G, w.partial, c.s));
+  RW_TRY(syev_batched(w.G, w.s, w.V, nb, 1, w.jac, c.s));
+  k_scale_cols<<<nblocks((int64_t)nb * nb, 256), 256, 0, c.s>>>(w.V, w.s, w.W, nb, c.floor_rel);
+  RW_LAUNCH_CHECK();
+  RW_TRY(stencil_apply(g, F, LF, nullptr, nb, 1.0, 0.0, 0.0, c.s));
+  c.spmm_cols += nb;
+  RW_TRY(gram(c.dt, F, c.N, LF, c.N, c.N, nb, nb, w.H, w.partial, c.s));
+  RW_TRY(gemm_tn(RW_F64, w.H, nb, w.W, nb, w.T, nb, nb, nb, nb, 0.0, c.s));       // T = H W
+  RW_TRY(gram(RW_F64, w.W, nb, w.T, nb, nb, nb, nb, w.Hp, w.partial, c.s));        // Hp = W^T H W
+  k_symmetrize<<<nblocks((int64_t)nb * nb, 256), 256, 0, c.s>>>(w.Hp, nb);
+  RW_LAUNCH_CHECK();
+  RW_TRY(syev_batched(w.Hp, w.theta, w.Z, nb, 1, w.jac, c.s));
+  RW_TRY(gemm_tn(RW_F64, w.W, nb, w.Z, nb, w.WZ, nb, nb, nb, nb, 0.0, c.s));      // WZ = W Z
+  RW_TRY(gemm_tn(c.dt, F, c.N, w.WZ, nb, X, c.N, c.N, nb, nb, 0.0, c.s));        // X = F W Z
+  RW_TRY(gemm_tn(c.dt, LF, c.N, w.WZ, nb, LX, c.N, c.N, nb, nb, 0.0, c.s));      // op X
+  RW_TRY(residual_norms(c.dt, LX, X, w.theta, c.N, nb, c.N, w.res, w.partial, c.s));
+  return RW_OK;
+}
+
+static double upper_bound(const Graph* g, EigWork& w, hipStream_t s, int* st) {
+  *st = RW_OK;
+  if (g->normalized) return 2.0;
+  if ((*st = absmax(g->degree, g->N, w.tmp, s)) != RW_OK) return 0.0;
+  double dmax = 0.0;
+  if (hipMemcpyAsync(&dmax, w.tmp, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    set_error("reading the degree bound failed");
+    *st = RW_EHIP;
+  }
+  return 2.0 * dmax * 1.0000001 + 1e-300;
+}
+
+// Chebyshev-filtered subspace iteration.  On entry block B[0] holds the start vectors (nb columns).
+static int chfsi(Ctx& c, int m, int nb, const rw_eig_opts* o, void* Q, double* lambda, rw_eig_info* info) {
+  const Graph* g = c.g;
+  EigWork& w = c.w;
+  const int k = m - 1;
+  int st = RW_OK;
+  const double bup = upper_bound(g, w, c.s, &st);
+  RW_TRY(st);
+  RW_TRY(project_out(c.dt, w.B[0], c.N, g->ghat, c.N, nb, w.tmp, w.partial, c.s));
+  int ix = 2, ilx = 3;
+  RW_TRY(rr_step(c, nb, w.B[0], w.B[1], w.B[ix], w.B[ilx]));
+  std::vector<double> th(nb), rs(nb);
+  const double amp_target = c.dt == RW_F64 ? 1e8 : 1e4;
+  int it = 0;
+  int nconv = 0;
+  double maxres = INFINITY;
+  const int max_iter = o->max_iter > 0 ? o->max_iter : 200;
+  for (;;) {
+    RW_HIP(hipMemcpyAsync(th.data(), w.theta, nb * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    RW_HIP(hipMemcpyAsync(rs.data(), w.res, nb * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    RW_HIP(hipStreamSynchronize(c.s));
+    nconv = 0;
+    maxres = 0.0;
+    for (int j = 0; j < k; ++j) {
+      maxres = std::max(maxres, rs[j]);
+      if (rs[j] <= o->tol) ++nconv;
+    }
+    if (nconv == k || it >= max_iter) break;
+    ++it;
+    // filter bounds
+    double a = th[nb - 1], a0 = std::max(th[0], 0.0);
+    if (!(a < bup)) a = 0.5 * bup;
+    if (!(a0 < a)) a0 = 0.0;
+    const double e = 0.5 * (bup - a), cc = 0.5 * (bup + a);
+    int deg = o->degree;
+    if (deg <= 0) {
+      double t0 = (cc - a0) / e;
+      double ac = t0 > 1.0 ? std::acosh(t0) : 1e-3;
+      deg = (int)std::ceil(std::acosh(amp_target) / ac);
+      deg = std::min(64, std::max(4, deg));
+    }
+    // buffers: Y0 = X, Y1, Y2 free
+    int b0 = ix, b1 = -1, b2 = -1;
+    {
+      int fr[3], nf = 0;
+      for (int q = 0; q < 4; ++q)
+        if (q != ix) fr[nf++] = q;
+      b1 = fr[0];
+      b2 = fr[1];
+    }
+    double sigma = e / (a0 - cc);
+    const double tau = 2.0 / sigma;
+    // Y1 = (op X - c X) sigma / e
+    RW_TRY(stencil_apply(g, w.B[b0], w.B[b1], nullptr, nb, sigma / e, -cc * sigma / e, 0.0, c.s));
+    c.spmm_cols += nb;
+    for (int i = 2; i <= deg; ++i) {
+      double sn = 1.0 / (tau - sigma);
+      // Y2 = (op Y1 - c Y1) 2 sn / e - sigma sn Y0
+      RW_TRY(stencil_apply(g, w.B[b1], w.B[b2], w.B[b0], nb, 2.0 * sn / e, -2.0 * cc * sn / e, -sigma * sn, c.s));
+      c.spmm_cols += nb;
+      int t = b0;
+      b0 = b1;
+      b1 = b2;
+      b2 = t;
+      sigma = sn;
+    }
+    // filtered block in b1; the other three are free
+    RW_TRY(project_out(c.dt, w.B[b1], c.N, g->ghat, c.N, nb, w.tmp, w.partial, c.s));
+    int fr[3], nf = 0;
+    for (int q = 0; q < 4; ++q)
+      if (q != b1) fr[nf++] = q;
+    RW_TRY(rr_step(c, nb, w.B[b1], w.B[fr[0]], w.B[fr[1]], w.B[fr[2]]));
+    ix = fr[1];
+    ilx = fr[2];
+  }
+  // final clean-up Rayleigh-Ritz on the converged block (restores orthonormality to working precision)
+  {
+    int fr[3], nf = 0;
+    for (int q = 0; q < 4; ++q)
+      if (q != ix) fr[nf++] = q;
+    RW_TRY(rr_step(c, nb, w.B[ix], w.B[fr[0]], w.B[fr[1]], w.B[fr[2]]));
+    ix = fr[1];
+    RW_HIP(hipMemcpyAsync(rs.data(), w.res, nb * sizeof(double), hipMemcpyDeviceToHost, c.s));
+    RW_HIP(hipStreamSynchronize(c.s));
+    nconv = 0;
+    maxres = 0.0;
+    for (int j = 0; j < k; ++j) {
+      maxres = std::max(maxres, rs[j]);
+      if (rs[j] <= o->tol) ++nconv;
+    }
+  }
+  // outputs: Q = [ghat, X(:, 0:k)], lambda = [0, theta(0:k)]
+  const int qdt = o->q_dtype;
+  RW_TRY(copy_cols(c.dt, g->ghat, c.N, qdt, Q, c.N, c.N, 1, c.s));
+  RW_TRY(copy_cols(c.dt, w.B[ix], c.N, qdt, (char*)Q + dtype_size(qdt) * c.N, c.N, c.N, k, c.s));
+  const double zero = 0.0;
+  RW_HIP(hipMemcpyAsync(lambda, &zero, sizeof(double), hipMemcpyHostToDevice, c.s));
+  RW_HIP(hipMemcpyAsync(lambda + 1, w.theta, k * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+  RW_HIP(hipStreamSynchronize(c.s));
+  if (info) {
+    info->iters = it;
+    info->n_converged = nconv + 1;
+    info->spmm_columns = c.spmm_cols;
+    info->max_residual = maxres;
+  }
+  if (nconv < k) {
+    set_error("eigensolver: %d of %d pairs above tol %.3g after %d iterations (max residual %.3g)", k - nconv, k,
+              o->tol, it, maxres);
+    return RW_ENOCONV;
+  }
+  return RW_OK;
+}
+
+static int validate_eig(const Graph* g, int m, const rw_eig_opts* o, int* nb) {
+  RW_CHECK(o != nullptr, RW_EINVAL, "null options");
+  RW_CHECK(o->q_dtype == g->dtype, RW_EINVAL, "Q dtype must equal the graph dtype");
+  RW_CHECK(std::isfinite(o->tol) && o->tol > 0.0, RW_EINVAL, "tol must be > 0");
+  RW_CHECK(m >= 2, RW_EINVAL, "m must be >= 2");
+  *nb = m - 1 + guard_of(m, o);
+  RW_CHECK(*nb <= g->N - 1, RW_EINVAL, "m + guard = %d exceeds N - 1 = %lld", *nb + 1, (long long)(g->N - 1));
+  RW_CHECK(*nb <= 1022, RW_EINVAL, "block of %d columns exceeds the dense eigensolver limit", *nb);
+  return RW_OK;
+}
+
+}  // namespace rw
+
+using namespace rw;
+
+extern "C" {
+
+int rw_eig_workspace_bytes(rw_graph h, int m, const rw_eig_opts* opts, size_t* bytes) {
+  RW_CHECK(h != nullptr && bytes != nullptr, RW_EINVAL, "null argument");
+  int nb = 0;
+  RW_TRY(validate_eig(&h->g, m, opts, &nb));
+  *bytes = eig_layout(&h->g, nb, nullptr, nullptr);
+  return RW_OK;
+}
+
+int rw_precompute_eig(rw_graph h, int m, const rw_eig_opts* opts, void* Q, double* lambda, void* work,
+                      size_t work_bytes, hipStream_t stream, rw_eig_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  RW_CHECK(h != nullptr && Q != nullptr && lambda != nullptr && work != nullptr, RW_EINVAL, "null argument");
+  const Graph* g = &h->g;
+  int nb = 0;
+  RW_TRY(validate_eig(g, m, opts, &nb));
+  Ctx c;
+  c.g = g;
+  c.dt = g->dtype;
+  c.N = g->N;
+  c.s = stream;
+  c.floor_rel = g->dtype == RW_F64 ? 1e-28 : 1e-14;
+  size_t need = eig_layout(g, nb, work, &c.w);
+  RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "eig workspace too small: %zu < %zu", work_bytes, need);
+  if (opts->warm) {
+    RW_TRY(copy_cols(opts->q_dtype, (const char*)Q + dtype_size(opts->q_dtype) * g->N, g->N, c.dt, c.w.B[0], g->N,
+                     g->N, m - 1, stream));
+    RW_TRY(fill_random(c.dt, c.w.B[0] + dtype_size(c.dt) * g->N * (m - 1), g->N, g->N, nb - (m - 1), opts->seed,
+                       stream));
+  } else {
+    RW_TRY(fill_random(c.dt, c.w.B[0], g->N, g->N, nb, opts->seed, stream));
+  }
+  int st = chfsi(c, m, nb, opts, Q, lambda, info);
+  if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+int rw_update_workspace_bytes(rw_graph h, int m, const rw_eig_opts* opts, size_t* bytes) {
+  return rw_eig_workspace_bytes(h, m, opts, bytes);
+}
+
+int rw_update_eig(rw_graph h, const rw_edit* edits, int n_edits, int mode, const rw_eig_opts* opts, void* Q,
+                  double* lambda, int m, void* work, size_t work_bytes, hipStream_t stream, rw_eig_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  RW_CHECK(h != nullptr && Q != nullptr && lambda != nullptr && work != nullptr, RW_EINVAL, "null argument");
+  RW_CHECK(mode >= RW_UPDATE_DIAG_RQ && mode <= RW_UPDATE_RR_REFINE, RW_EINVAL, "unknown update mode %d", mode);
+  Graph* g = &h->g;
+  int nb = 0;
+  RW_TRY(validate_eig(g, m, opts, &nb));
+  Ctx c;
+  c.g = g;
+  c.dt = g->dtype;
+  c.N = g->N;
+  c.s = stream;
+  c.floor_rel = g->dtype == RW_F64 ? 1e-28 : 1e-14;
+  size_t need = eig_layout(g, nb, work, &c.w);
+  RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "update workspace too small: %zu < %zu", work_bytes, need);
+  RW_TRY(rw_edit_graph(h, edits, n_edits, stream));
+  EigWork& w = c.w;
+  const int k = m - 1;
+  const size_t es = dtype_size(c.dt);
+  RW_TRY(copy_cols(opts->q_dtype, (const char*)Q + dtype_size(opts->q_dtype) * g->N, g->N, c.dt, w.B[0], g->N, g->N,
+                   k, stream));
+  int st = RW_OK;
+  if (mode == RW_UPDATE_RR_REFINE) {
+    RW_TRY(fill_random(c.dt, w.B[0] + es * g->N * k, g->N, g->N, nb - k, opts->seed ^ 0x5eedull, stream));
+    st = chfsi(c, m, nb, opts, Q, lambda, info);
+  } else {
+    RW_TRY(project_out(c.dt, w.B[0], c.N, g->ghat, c.N, k, w.tmp, w.partial, stream));
+    int ix = 0;
+    if (mode == RW_UPDATE_DIAG_RQ) {
+      // order-preserving orthonormalization (Cholesky QR, twice), then lambda_i = q_i^T op q_i
+      int src = 0;
+      for (int pass = 0; pass < 2; ++pass) {
+        int dst = pass == 0 ? 1 : 2;
+        RW_TRY(gram(c.dt, w.B[src], c.N, w.B[src], c.N, c.N, k, k, w.G, w.partial, stream));
+        RW_TRY(chol_batched(w.G, k, 1, w.info, stream));
+        int bad = 0;
+        RW_HIP(hipMemcpyAsync(&bad, w.info, sizeof(int), hipMemcpyDeviceToHost, stream));
+        RW_HIP(hipStreamSynchronize(stream));
+        RW_CHECK(bad == 0, RW_ESINGULAR, "stored eigenvectors are linearly dependent after the edit (pivot %d)", bad);
+        RW_TRY(chol_upper_inverse(w.G, w.W, k, stream));
+        RW_TRY(gemm_tn(c.dt, w.B[src], c.N, w.W, k, w.B[dst], c.N, c.N, k, k, 0.0, stream));
+        src = dst;
+      }
+      ix = 2;
+      RW_TRY(stencil_apply(g, w.B[ix], w.B[3], nullptr, k, 1.0, 0.0, 0.0, stream));
+      c.spmm_cols += k;
+      RW_TRY(col_dots(c.dt, w.B[ix], w.B[3], c.N, k, c.N, w.theta, w.partial, stream));
+      RW_TRY(residual_norms(c.dt, w.B[3], w.B[ix], w.theta, c.N, k, c.N, w.res, w.partial, stream));
+    } else {
+      RW_TRY(rr_step(c, k, w.B[0], w.B[1], w.B[2], w.B[3]));
+      ix = 2;
+    }
+    const int qdt = opts->q_dtype;
+    RW_TRY(copy_cols(c.dt, g->ghat, c.N, qdt, Q, c.N, c.N, 1, stream));
+    RW_TRY(copy_cols(c.dt, w.B[ix], c.N, qdt, (char*)Q + dtype_size(qdt) * c.N, c.N, c.N, k, stream));
+    const double zero = 0.0;
+    RW_HIP(hipMemcpyAsync(lambda, &zero, sizeof(double), hipMemcpyHostToDevice, stream));
+    RW_HIP(hipMemcpyAsync(lambda + 1, w.theta, k * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    std::vector<double> rs(k);
+    RW_HIP(hipMemcpyAsync(rs.data(), w.res, k * sizeof(double), hipMemcpyDeviceToHost, stream));
+    RW_HIP(hipStreamSynchronize(stream));
+    if (info) {
+      info->iters = 0;
+      info->spmm_columns = c.spmm_cols;
+      double mr = 0.0;
+      int nc = 0;
+      for (double r : rs) {
+        mr = std::max(mr, r);
+        nc += r <= opts->tol;
+      }
+      info->max_residual = mr;
+      info->n_converged = nc + 1;
+    }
+  }
+  if (info) info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,378 @@
+// Image graph: edge weights, degrees, null vector and stencil coefficients (Sec. II-A eq. (2),
+// Sec. II-C), and graph edits (Sec. III-B and weight / topology edits).
+#include <cmath>
+#include <cstdarg>
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "rw_internal.h"
+
+namespace rw {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+static constexpr int64_t kEditStage = 65536;  // edge ids staged per chunk of an edit list
+
+template <typename T>
+__global__ void k_graph_init(GridDev G, const void* Jsrc, int Jdt, double* J, T* scale, uint8_t* mask) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= G.N) return;
+  J[i] = Jdt == RW_F64 ? static_cast<const double*>(Jsrc)[i] : (double)static_cast<const float*>(Jsrc)[i];
+  int64_t x = i % G.nx, y = (i / G.nx) % G.ny, z = i / (G.nx * G.ny);
+  uint8_t m = 0;
+  for (int d = 0; d < G.ndir; ++d) {
+    bool ok = head_in(G, x, y, z, d);
+    scale[d * G.N + i] = ok ? T(1) : T(0);
+    if (ok) m |= uint8_t(1u << d);
+  }
+  mask[i] = m;
+}
+
+// w_e = s_e * exp(-beta * f(J_tail - J_head)), computed in FP64 and rounded once to T.
+template <typename T>
+__global__ void k_weights(GridDev G, const double* J, double beta, int form, const T* scale,
+                          const uint8_t* mask, T* weight) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= G.N) return;
+  uint8_t m = mask[i];
+  for (int d = 0; d < G.ndir; ++d) {
+    double w = 0.0;
+    if ((m >> d) & 1u) {
+      double diff = J[i] - J[i + G.off[d]];
+      double e = form == RW_WEIGHT_SQUARED ? diff * diff : fabs(diff);
+      w = (double)scale[d * G.N + i] * exp(-beta * e);
+    }
+    weight[d * G.N + i] = T(w);
+  }
+}
+
+// degree: forward edges stored at i, backward edges stored at the tail i - off[d]; fixed order.
+template <typename T>
+__global__ void k_degree(GridDev G, const T* weight, double* degree, double* partial) {
+  double local = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t x = i % G.nx, y = (i / G.nx) % G.ny, z = i / (G.nx * G.ny);
+    double d = 0.0;
+    for (int k = 0; k < G.ndir; ++k) d += (double)weight[k * G.N + i];
+    for (int k = 0; k < G.ndir; ++k)
+      if (tail_in(G, x, y, z, k)) d += (double)weight[k * G.N + i - G.off[k]];
+    degree[i] = d;
+    local += d;
+  }
+  // block reduction in fixed order
+  __shared__ double sh[256];
+  sh[threadIdx.x] = local;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_partials(const double* partial, int n, double* out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += partial[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+template <typename T>
+__global__ void k_finish(GridDev G, int normalized, const double* degree, const double* sums,
+                         const T* weight, const uint8_t* mask, T* dinv, T* ghat, T* diag, T* coef) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= G.N) return;
+  double d = degree[i];
+  double di = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+  dinv[i] = T(di);
+  if (normalized) {
+    ghat[i] = T(sqrt(d) / sqrt(sums[0]));
+    diag[i] = T(d > 0.0 ? 1.0 : 0.0);
+  } else {
+    ghat[i] = T(1.0 / sqrt((double)G.N));
+    diag[i] = T(d);
+  }
+  uint8_t m = mask[i];
+  for (int k = 0; k < G.ndir; ++k) {
+    double c = 0.0;
+    if ((m >> k) & 1u) {
+      double w = (double)weight[k * G.N + i];
+      if (normalized) {
+        double dh = degree[i + G.off[k]];
+        double dhi = dh > 0.0 ? 1.0 / sqrt(dh) : 0.0;
+        c = w * di * dhi;
+      } else {
+        c = w;
+      }
+    }
+    coef[k * G.N + i] = T(c);
+  }
+}
+
+template <typename T>
+__global__ void k_scale_box(GridDev G, int64_t x0, int64_t y0, int64_t z0, int64_t x1, int64_t y1,
+                            int64_t z1, double v, const uint8_t* mask, T* scale) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= G.N) return;
+  int64_t x = i % G.nx, y = (i / G.nx) % G.ny, z = i / (G.nx * G.ny);
+  if (x < x0 || x >= x1 || y < y0 || y >= y1 || z < z0 || z >= z1) return;
+  uint8_t m = mask[i];
+  for (int d = 0; d < G.ndir; ++d) {
+    if (!((m >> d) & 1u)) continue;
+    int64_t a = x + G.dx[d], b = y + G.dy[d], c = z + G.dz[d];
+    if (a < x0 || a >= x1 || b < y0 || b >= y1 || c < z0 || c >= z1) continue;
+    scale[d * G.N + i] = T((double)scale[d * G.N + i] * v);
+  }
+}
+
+// ids are distinct within one launch (checked on the host), so no two threads touch one slot.
+template <typename T>
+__global__ void k_edit_ids(const int64_t* ids, int64_t n, double v, int remove, T* scale) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int64_t e = ids[k];
+  scale[e] = remove ? T(0) : T((double)scale[e] * v);
+}
+
+size_t graph_layout(const rw_graph_desc& d, Graph* g, void* buf) {
+  int64_t N = d.dims[0] * d.dims[1] * d.dims[2];
+  int nd = d.ndim == 3 ? 3 : (d.conn == 8 ? 4 : 2);
+  size_t es = dtype_size(d.dtype);
+  Carver c(buf);
+  double* J = c.take<double>(N);
+  char* scale = c.take<char>(nd * N * es);
+  char* weight = c.take<char>(nd * N * es);
+  char* coef = c.take<char>(nd * N * es);
+  char* diag = c.take<char>(N * es);
+  char* dinv = c.take<char>(N * es);
+  char* ghat = c.take<char>(N * es);
+  double* degree = c.take<double>(N);
+  uint8_t* mask = c.take<uint8_t>(N);
+  double* partial = c.take<double>(kReduceBlocks);
+  double* sums = c.take<double>(8);
+  c.take<int64_t>(kEditStage);
+  if (g) {
+    g->J = J; g->scale = scale; g->weight = weight; g->coef = coef; g->diag = diag; g->dinv = dinv;
+    g->ghat = ghat; g->degree = degree; g->mask = mask; g->partial = partial; g->sums = sums;
+  }
+  return c.used;
+}
+
+static int64_t* edit_stage(const Graph* g) {
+  // the staging area is the last block of the layout: recompute its offset
+  rw_graph_desc d{};
+  d.ndim = g->ndim; d.dims[0] = g->nx; d.dims[1] = g->ny; d.dims[2] = g->nz; d.conn = g->conn;
+  d.dtype = g->dtype;
+  size_t total = graph_layout(d, nullptr, nullptr);
+  size_t off = total - kEditStage * sizeof(int64_t);
+  return reinterpret_cast<int64_t*>(reinterpret_cast<char*>(g->J) + off);
+}
+
+template <typename T>
+static int rebuild_t(Graph* g, hipStream_t s) {
+  GridDev G = grid_of(g);
+  const int t = 256;
+  k_weights<T><<<nblocks(g->N, t), t, 0, s>>>(G, g->J, g->beta, g->weight_form, (const T*)g->scale,
+                                                g->mask, (T*)g->weight);
+  RW_LAUNCH_CHECK();
+  int nb = (int)std::min<int64_t>(kReduceBlocks, nblocks(g->N, t));
+  k_degree<T><<<nb, t, 0, s>>>(G, (const T*)g->weight, g->degree, g->partial);
+  RW_LAUNCH_CHECK();
+  k_sum_partials<<<1, 256, 0, s>>>(g->partial, nb, g->sums);
+  RW_LAUNCH_CHECK();
+  k_finish<T><<<nblocks(g->N, t), t, 0, s>>>(G, g->normalized, g->degree, g->sums, (const T*)g->weight,
+                                               g->mask, (T*)g->dinv, (T*)g->ghat, (T*)g->diag, (T*)g->coef);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+int graph_rebuild(Graph* g, hipStream_t s) {
+  return g->dtype == RW_F64 ? rebuild_t<double>(g, s) : rebuild_t<float>(g, s);
+}
+
+static int validate_desc(const rw_graph_desc* d) {
+  RW_CHECK(d != nullptr, RW_EINVAL, "null graph description");
+  RW_CHECK(d->ndim == 2 || d->ndim == 3, RW_EINVAL, "ndim must be 2 or 3 (got %d)", d->ndim);
+  RW_CHECK(d->dims[0] >= 1 && d->dims[1] >= 1 && d->dims[2] >= 1, RW_EINVAL, "dims must be >= 1");
+  RW_CHECK(d->ndim == 3 || d->dims[2] == 1, RW_EINVAL, "a 2D graph needs dims[2] == 1");
+  RW_CHECK(d->ndim == 2 ? (d->conn == 4 || d->conn == 8) : d->conn == 6, RW_EINVAL,
+           "connectivity %d is not valid for %dD", d->conn, d->ndim);
+  RW_CHECK(d->dtype == RW_F64 || d->dtype == RW_F32, RW_EINVAL, "graph dtype must be F64 or F32");
+  RW_CHECK(d->weight_form == RW_WEIGHT_SQUARED || d->weight_form == RW_WEIGHT_ABS, RW_EINVAL,
+           "unknown weight form %d", d->weight_form);
+  int64_t N = d->dims[0] * d->dims[1] * d->dims[2];
+  RW_CHECK(N >= 2 && N < (int64_t(1) << 40), RW_EINVAL, "N = %lld out of range", (long long)N);
+  return RW_OK;
+}
+
+}  // namespace rw
+
+using namespace rw;
+
+extern "C" {
+
+const char* rw_last_error(void) { return g_last_error.c_str(); }
+int rw_version(void) { return 1; }
+
+int rw_graph_bytes(const rw_graph_desc* desc, size_t* bytes) {
+  RW_TRY(validate_desc(desc));
+  RW_CHECK(bytes != nullptr, RW_EINVAL, "null bytes pointer");
+  *bytes = graph_layout(*desc, nullptr, nullptr);
+  return RW_OK;
+}
+
+int rw_build_graph(const rw_graph_desc* desc, const void* J_dev, int J_dtype, double beta,
+                   void* graph_buf, size_t buf_bytes, hipStream_t stream, rw_graph* out) {
+  RW_TRY(validate_desc(desc));
+  RW_CHECK(out != nullptr && J_dev != nullptr && graph_buf != nullptr, RW_EINVAL, "null pointer argument");
+  RW_CHECK(J_dtype == RW_F64 || J_dtype == RW_F32, RW_EINVAL, "J dtype must be F64 or F32");
+  RW_CHECK(std::isfinite(beta) && beta >= 0.0, RW_EINVAL, "beta must be finite and >= 0 (got %g)", beta);
+  size_t need = graph_layout(*desc, nullptr, nullptr);
+  RW_CHECK(buf_bytes >= need, RW_EWORKSPACE, "graph buffer too small: %zu < %zu", buf_bytes, need);
+  RW_CHECK((reinterpret_cast<uintptr_t>(graph_buf) & 255) == 0, RW_EINVAL, "graph buffer must be 256-byte aligned");
+  rw_graph h = new rw_graph_s();
+  Graph* g = &h->g;
+  g->ndim = desc->ndim;
+  g->nx = desc->dims[0]; g->ny = desc->dims[1]; g->nz = desc->dims[2];
+  g->N = g->nx * g->ny * g->nz;
+  g->conn = desc->conn;
+  g->dtype = desc->dtype;
+  g->weight_form = desc->weight_form;
+  g->normalized = desc->normalized ? 1 : 0;
+  g->beta = beta;
+  static const int d2_4[2][3] = {{1, 0, 0}, {0, 1, 0}};
+  static const int d2_8[4][3] = {{1, 0, 0}, {0, 1, 0}, {1, 1, 0}, {1, -1, 0}};
+  static const int d3_6[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  const int(*dirs)[3] = g->ndim == 3 ? d3_6 : (g->conn == 8 ? d2_8 : d2_4);
+  g->ndir = g->ndim == 3 ? 3 : (g->conn == 8 ? 4 : 2);
+  for (int k = 0; k < g->ndir; ++k) {
+    g->dx[k] = dirs[k][0]; g->dy[k] = dirs[k][1]; g->dz[k] = dirs[k][2];
+    g->off[k] = dirs[k][0] + g->nx * (dirs[k][1] + g->ny * (int64_t)dirs[k][2]);
+  }
+  graph_layout(*desc, g, graph_buf);
+  GridDev G = grid_of(g);
+  if (g->dtype == RW_F64)
+    k_graph_init<double><<<nblocks(g->N, 256), 256, 0, stream>>>(G, J_dev, J_dtype, g->J, (double*)g->scale, g->mask);
+  else
+    k_graph_init<float><<<nblocks(g->N, 256), 256, 0, stream>>>(G, J_dev, J_dtype, g->J, (float*)g->scale, g->mask);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) { delete h; set_error("graph init launch: %s", hipGetErrorString(e)); return RW_EHIP; }
+  int st = graph_rebuild(g, stream);
+  if (st != RW_OK) { delete h; return st; }
+  *out = h;
+  return RW_OK;
+}
+
+int rw_graph_destroy(rw_graph g) {
+  delete g;
+  return RW_OK;
+}
+
+int rw_graph_get_view(rw_graph h, rw_graph_view* v) {
+  RW_CHECK(h != nullptr && v != nullptr, RW_EINVAL, "null argument");
+  const Graph* g = &h->g;
+  v->N = g->N; v->ndir = g->ndir; v->dtype = g->dtype; v->beta = g->beta;
+  v->J = g->J; v->weight = g->weight; v->scale = g->scale; v->coef = g->coef; v->diag = g->diag;
+  v->dinv = g->dinv; v->ghat = g->ghat; v->degree = g->degree; v->mask = g->mask;
+  return RW_OK;
+}
+
+int rw_edit_graph(rw_graph h, const rw_edit* edits, int n_edits, hipStream_t stream) {
+  RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
+  RW_CHECK(n_edits >= 0 && (n_edits == 0 || edits != nullptr), RW_EINVAL, "bad edit list");
+  Graph* g = &h->g;
+  if (n_edits == 0) return RW_OK;
+  // host-side validation against a copy of the presence mask, updated as the list is walked
+  std::vector<uint8_t> mask(g->N);
+  RW_HIP(hipMemcpyAsync(mask.data(), g->mask, g->N, hipMemcpyDeviceToHost, stream));
+  RW_HIP(hipStreamSynchronize(stream));
+  std::vector<uint8_t> mask0 = mask;
+  for (int k = 0; k < n_edits; ++k) {
+    const rw_edit& e = edits[k];
+    switch (e.kind) {
+      case RW_EDIT_SET_BETA:
+        RW_CHECK(std::isfinite(e.value) && e.value >= 0.0, RW_EINVAL, "edit %d: beta must be >= 0", k);
+        break;
+      case RW_EDIT_SCALE_BOX:
+        RW_CHECK(std::isfinite(e.value) && e.value > 0.0, RW_EINVAL, "edit %d: scale must be > 0", k);
+        break;
+      case RW_EDIT_SCALE_EDGES:
+      case RW_EDIT_REMOVE_EDGES: {
+        if (e.kind == RW_EDIT_SCALE_EDGES)
+          RW_CHECK(std::isfinite(e.value) && e.value > 0.0, RW_EINVAL, "edit %d: scale must be > 0", k);
+        RW_CHECK(e.n >= 0 && (e.n == 0 || e.edge_ids != nullptr), RW_EINVAL, "edit %d: bad id list", k);
+        std::vector<uint8_t> seen;
+        for (int64_t j = 0; j < e.n; ++j) {
+          int64_t id = e.edge_ids[j];
+          RW_CHECK(id >= 0 && id < g->ndir * g->N, RW_EINVAL, "edit %d: edge id %lld out of range", k, (long long)id);
+          int d = (int)(id / g->N);
+          int64_t t = id % g->N;
+          RW_CHECK((mask[t] >> d) & 1u, RW_EINVAL, "edit %d: edge %lld is not present", k, (long long)id);
+          if (e.kind == RW_EDIT_REMOVE_EDGES) mask[t] &= uint8_t(~(1u << d));
+        }
+        if (e.kind == RW_EDIT_SCALE_EDGES) {  // distinct ids: sort a copy
+          std::vector<int64_t> ids(e.edge_ids, e.edge_ids + e.n);
+          std::sort(ids.begin(), ids.end());
+          for (size_t j = 1; j < ids.size(); ++j)
+            RW_CHECK(ids[j] != ids[j - 1], RW_EINVAL, "edit %d: edge %lld listed twice", k, (long long)ids[j]);
+        }
+        break;
+      }
+      default:
+        RW_CHECK(false, RW_EINVAL, "edit %d: unknown kind %d", k, e.kind);
+    }
+  }
+  // apply in order
+  GridDev G = grid_of(g);
+  int64_t* stage = edit_stage(g);
+  for (int k = 0; k < n_edits; ++k) {
+    const rw_edit& e = edits[k];
+    if (e.kind == RW_EDIT_SET_BETA) {
+      g->beta = e.value;
+    } else if (e.kind == RW_EDIT_SCALE_BOX) {
+      if (g->dtype == RW_F64)
+        k_scale_box<double><<<nblocks(g->N, 256), 256, 0, stream>>>(G, e.box_lo[0], e.box_lo[1], e.box_lo[2], e.box_hi[0],
+                                                                      e.box_hi[1], e.box_hi[2], e.value, g->mask, (double*)g->scale);
+      else
+        k_scale_box<float><<<nblocks(g->N, 256), 256, 0, stream>>>(G, e.box_lo[0], e.box_lo[1], e.box_lo[2], e.box_hi[0],
+                                                                     e.box_hi[1], e.box_hi[2], e.value, g->mask, (float*)g->scale);
+      RW_LAUNCH_CHECK();
+    } else {
+      int rem = e.kind == RW_EDIT_REMOVE_EDGES;
+      for (int64_t j0 = 0; j0 < e.n; j0 += kEditStage) {
+        int64_t cnt = std::min<int64_t>(kEditStage, e.n - j0);
+        RW_HIP(hipMemcpyAsync(stage, e.edge_ids + j0, cnt * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+        if (g->dtype == RW_F64)
+          k_edit_ids<double><<<nblocks(cnt, 256), 256, 0, stream>>>(stage, cnt, e.value, rem, (double*)g->scale);
+        else
+          k_edit_ids<float><<<nblocks(cnt, 256), 256, 0, stream>>>(stage, cnt, e.value, rem, (float*)g->scale);
+        RW_LAUNCH_CHECK();
+        // the staging area is reused by the next chunk only after this kernel has read it
+        RW_HIP(hipStreamSynchronize(stream));
+      }
+    }
+  }
+  if (mask != mask0) RW_HIP(hipMemcpyAsync(g->mask, mask.data(), g->N, hipMemcpyHostToDevice, stream));
+  RW_TRY(graph_rebuild(g, stream));
+  RW_HIP(hipStreamSynchronize(stream));
+  return RW_OK;
+}
+
+}  // extern "C"

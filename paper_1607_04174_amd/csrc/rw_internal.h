@@ -1,0 +1,199 @@
+// Internal declarations shared by the librw translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/rw.h"
+
+namespace rw {
+
+// ---- error reporting ---------------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+
+#define RW_HIP(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      ::rw::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return RW_EHIP;                                                                       \
+    }                                                                                       \
+  } while (0)
+
+#define RW_CHECK(cond, code, ...)      \
+  do {                                 \
+    if (!(cond)) {                     \
+      ::rw::set_error(__VA_ARGS__);    \
+      return (code);                   \
+    }                                  \
+  } while (0)
+
+#define RW_TRY(expr)              \
+  do {                            \
+    int s_ = (expr);              \
+    if (s_ != RW_OK) return s_;   \
+  } while (0)
+
+#define RW_LAUNCH_CHECK() RW_HIP(hipGetLastError())
+
+// ---- workspace carving -------------------------------------------------------------------------
+// A bump allocator over a caller-owned device buffer; every block is 256-byte aligned.  With a null
+// base it only measures.
+struct Carver {
+  char* base;
+  size_t used = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+};
+
+inline size_t dtype_size(int dt) { return dt == RW_F64 ? 8 : (dt == RW_F32 ? 4 : 2); }
+
+// ---- the graph handle --------------------------------------------------------------------------
+struct Graph {
+  int ndim = 2;
+  int64_t nx = 1, ny = 1, nz = 1, N = 0;
+  int conn = 4, ndir = 2;
+  int dtype = RW_F64;
+  int weight_form = RW_WEIGHT_SQUARED;
+  int normalized = 1;
+  double beta = 0.0;
+  int dx[4] = {0, 0, 0, 0}, dy[4] = {0, 0, 0, 0}, dz[4] = {0, 0, 0, 0};
+  int64_t off[4] = {0, 0, 0, 0};
+  // device arrays inside the caller's graph buffer
+  double* J = nullptr;      // N
+  void* scale = nullptr;    // ndir x N (dtype)
+  void* weight = nullptr;   // ndir x N (dtype)
+  void* coef = nullptr;     // ndir x N (dtype)
+  void* diag = nullptr;     // N (dtype)
+  void* dinv = nullptr;     // N (dtype)
+  void* ghat = nullptr;     // N (dtype)
+  double* degree = nullptr; // N
+  uint8_t* mask = nullptr;  // N
+  double* partial = nullptr;  // reduction partials (kReduceBlocks)
+  double* sums = nullptr;     // [0] = sum of degrees
+};
+
+constexpr int kReduceBlocks = 1024;
+
+// kernel-side copy of the grid geometry
+struct GridDev {
+  int64_t nx, ny, nz, N;
+  int ndir;
+  int dx[4], dy[4], dz[4];
+  int64_t off[4];
+};
+
+inline GridDev grid_of(const Graph* g) {
+  GridDev d;
+  d.nx = g->nx; d.ny = g->ny; d.nz = g->nz; d.N = g->N; d.ndir = g->ndir;
+  for (int k = 0; k < 4; ++k) {
+    d.dx[k] = g->dx[k]; d.dy[k] = g->dy[k]; d.dz[k] = g->dz[k]; d.off[k] = g->off[k];
+  }
+  return d;
+}
+
+// is the head (x,y,z) + dir inside the grid?
+__device__ __forceinline__ bool head_in(const GridDev& G, int64_t x, int64_t y, int64_t z, int d) {
+  int64_t a = x + G.dx[d], b = y + G.dy[d], c = z + G.dz[d];
+  return a >= 0 && a < G.nx && b >= 0 && b < G.ny && c >= 0 && c < G.nz;
+}
+// is the tail (x,y,z) - dir inside the grid?
+__device__ __forceinline__ bool tail_in(const GridDev& G, int64_t x, int64_t y, int64_t z, int d) {
+  int64_t a = x - G.dx[d], b = y - G.dy[d], c = z - G.dz[d];
+  return a >= 0 && a < G.nx && b >= 0 && b < G.ny && c >= 0 && c < G.nz;
+}
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// bf16 storage helpers (round-to-nearest-even on store)
+__device__ __forceinline__ float bf16_to_f32(uint16_t v) { return __uint_as_float(((uint32_t)v) << 16); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// typed element access for the three storage types
+template <typename T> struct Elem;
+template <> struct Elem<double> {
+  using C = double;  // compute type
+  __device__ static double ld(const double* p, int64_t i) { return p[i]; }
+  __device__ static void st(double* p, int64_t i, double v) { p[i] = v; }
+};
+template <> struct Elem<float> {
+  using C = float;
+  __device__ static float ld(const float* p, int64_t i) { return p[i]; }
+  __device__ static void st(float* p, int64_t i, float v) { p[i] = v; }
+};
+template <> struct Elem<uint16_t> {
+  using C = float;
+  __device__ static float ld(const uint16_t* p, int64_t i) { return bf16_to_f32(p[i]); }
+  __device__ static void st(uint16_t* p, int64_t i, float v) { p[i] = f32_to_bf16(v); }
+};
+
+size_t graph_layout(const rw_graph_desc& d, Graph* g, void* buf);  // returns bytes
+int graph_rebuild(Graph* g, hipStream_t s);   // weights -> degree, dinv, ghat, coef, diag
+
+// ---- stencil operator --------------------------------------------------------------------------
+// Y = alpha * op(X) + beta * X + gamma * Z   (column-major N x b, graph dtype)
+int stencil_apply(const Graph* g, const void* X, void* Y, const void* Z, int64_t b, double alpha,
+                  double beta, double gamma, hipStream_t s);
+
+// ---- tall-skinny dense kernels (blas.hip) -------------------------------------------------------
+// G (FP64, bx x by, column-major, ld = bx) = X^T Y for column-major X (rows x bx, ld ldx) and
+// Y (rows x by, ld ldy) of element type dt (RW_F64 / RW_F32 / RW_BF16).  Deterministic two-stage
+// reduction over row chunks through `partial` (gram_partial_count doubles).
+size_t gram_partial_count(int64_t rows, int bx, int by);
+int gram(int dt, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t rows, int bx, int by,
+         double* G, double* partial, hipStream_t s);
+// Z (rows x n, ld ldz, type dt) = X (rows x k, ld ldx, type dt) * V (FP64, k x n, ld ldv)
+//   (+ beta * Z when beta != 0)
+int gemm_tn(int dt, const void* X, int64_t ldx, const double* V, int64_t ldv, void* Z, int64_t ldz,
+            int64_t rows, int k, int n, double beta, hipStream_t s);
+// copy / convert a column-major block (rows x cols) between element types
+int convert_block(int dt_src, const void* src, int64_t lds, int dt_dst, void* dst, int64_t ldd,
+                  int64_t rows, int cols, hipStream_t s);
+// column norms (FP64 out) of R = A - B diag(theta) (theta may be null: plain norms of A)
+size_t norm_partial_count(int cols);
+int residual_norms(int dt, const void* A, const void* B, const double* theta, int64_t rows, int cols,
+                   int64_t ld, double* out, double* partial, hipStream_t s);
+// d_j = a_j^T b_j (FP64) for column-major A, B (rows x cols, ld)
+int col_dots(int dt, const void* A, const void* B, int64_t rows, int cols, int64_t ld, double* out,
+             double* partial, hipStream_t s);
+// out[0] = max_i |x_i|
+int absmax(const double* x, int64_t n, double* out, hipStream_t s);
+// fill a block with deterministic pseudo-random normals (counter-based: splitmix64 + Box-Muller)
+int fill_random(int dt, void* X, int64_t ld, int64_t rows, int cols, uint64_t seed, hipStream_t s);
+// X -= v (v^T X) for a unit vector v (rows), X column-major rows x cols
+int project_out(int dt, void* X, int64_t ld, const void* v, int64_t rows, int cols, double* tmp,
+                double* partial, hipStream_t s);
+
+// ---- small dense FP64 kernels, one workgroup per matrix (dense.hip) ------------------------------
+// In-place lower Cholesky of count matrices (n x n, ld n, stride n*n); info[b] = 0 or (k+1) of the
+// first non-positive pivot.
+int chol_batched(double* A, int n, int count, int* info, hipStream_t s);
+// Rinv = (L^T)^{-1} (upper triangular) for the lower factor L; n x n
+int chol_upper_inverse(const double* L, double* Rinv, int n, hipStream_t s);
+// Symmetric eigendecomposition by cyclic Jacobi: A (n x n, destroyed) -> w (ascending),
+// V (n x n, columns = eigenvectors).  count matrices, strides n*n / n.
+int syev_batched(double* A, double* w, double* V, int n, int count, double* work, hipStream_t s);
+size_t syev_work_count(int n, int count);
+// Solve A X = B by LU with partial pivoting (A: n x n, B: n x nrhs, both destroyed/overwritten;
+// X returned in B).  stat[0] = min |pivot| / max |a_ij| (0 if a pivot is below the threshold).
+int lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s);
+
+}  // namespace rw
+
+struct rw_graph_s {
+  rw::Graph g;
+};

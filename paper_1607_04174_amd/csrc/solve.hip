@@ -1,0 +1,545 @@
+// Online random-walker solve in the precomputed eigenbasis (Sec. II-B eqs. (7)-(17); the gamma = 0
+// case after eq. (17)) and the seed-driven choice of m (Sec. III-A1 eq. (24)).
+//
+// Reduced system.  With the null vector as Q's column 0 (eigenvalue 0), the gamma = 0 bordered seed
+// system in (F_s, c) is equivalent to an m x m system in the coefficients Y of U_hat_n = Q_n Y:
+// the ansatz gives F_s = op_ss U_hat_s + B Q_n Y, and the conditions Q'_s^T F_s = Lambda' Y' (from
+// U_n = R^T F_s + g_n c^T) and g_s^T F_s = 0 (from g^T F = 0, F_n = 0) are the rows of
+//     (Lambda - Q_s^T B Q_n) Y = Q_s^T op_ss U_hat_s.
+// Its size is m, not S, and Lambda enters without inversion, so near-null eigenvalues need no
+// clamping.  The reconstruction U = D^{-1/2} Q Y is one tall-skinny pass over Q.
+#include <cmath>
+#include <vector>
+
+#include "rw_internal.h"
+
+namespace rw {
+
+constexpr int kMaxCand = 16;   // candidate m values evaluated per probe of the choice of m
+
+struct SolveWork {
+  uint8_t* map;       // N: 0 = not a seed, else label + 1
+  int64_t* seeds;     // S
+  int32_t* labels;    // S
+  double* Qs;         // S x ma   (seed rows of Q)
+  double* GB;         // S x ma   (B Q_n)
+  double* Hs;         // S x C    (op_ss U_hat_s)
+  double* Us;         // S x C    (U_hat_s)
+  double* T;          // ma x ma  (Q_s^T B Q_n)
+  double* R;          // ma x C   (Q_s^T op_ss U_hat_s)
+  double* Gq;         // ma x ma  (Q_s^T Q_s)
+  double* Gb;         // ma x C   (Q_s^T U_hat_s)
+  double* fvals;      // kMaxCand x C
+  double* tr_scratch; // kMaxCand x C x (ms*ms + 4 ms)
+  double* K;          // ma x ma
+  double* Y;          // ma x C
+  double* stat;       // 8
+  double* partial;
+};
+
+static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base, SolveWork* w) {
+  Carver c(base);
+  int64_t ms = std::min<int64_t>(S, ma);
+  SolveWork t;
+  t.map = c.take<uint8_t>(g->N);
+  t.seeds = c.take<int64_t>(S);
+  t.labels = c.take<int32_t>(S);
+  t.Qs = c.take<double>(S * ma);
+  t.GB = c.take<double>(S * ma);
+  t.Hs = c.take<double>(S * C);
+  t.Us = c.take<double>(S * C);
+  t.T = c.take<double>((size_t)ma * ma);
+  t.R = c.take<double>((size_t)ma * C);
+  t.Gq = c.take<double>((size_t)ma * ma);
+  t.Gb = c.take<double>((size_t)ma * C);
+  t.fvals = c.take<double>((size_t)kMaxCand * C);
+  t.tr_scratch = c.take<double>((size_t)kMaxCand * C * (ms * ms + 4 * ms));
+  t.K = c.take<double>((size_t)ma * ma);
+  t.Y = c.take<double>((size_t)ma * C);
+  t.stat = c.take<double>(8);
+  size_t pc = std::max(gram_partial_count(S, ma, ma), gram_partial_count(S, ma, C));
+  t.partial = c.take<double>(pc);
+  if (w) *w = t;
+  return c.used;
+}
+
+// ---------------------------------------------------------------------------------------------
+// seed bookkeeping
+// ---------------------------------------------------------------------------------------------
+__global__ void k_clear_map(uint8_t* map, int64_t N) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N) map[i] = 0;
+}
+
+__global__ void k_set_map(uint8_t* map, const int64_t* seeds, const int32_t* labels, int64_t S) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < S) map[seeds[k]] = (uint8_t)(labels[k] + 1);
+}
+
+// One block per seed.  Threads over columns j gather Q_s(i, j) and (B Q_n)(i, j) =
+// -sum over non-seed neighbours t of coef(i,t) Q(t, j); threads over labels form U_hat_s and
+// op_ss U_hat_s (diag U_hat_s(i) - sum over seed neighbours of coef U_hat_s(t)).
+template <typename TQ, typename TG>
+__global__ void k_seed_gather(GridDev G, int normalized, const TQ* Q, int ma, const int64_t* seeds,
+                              const int32_t* labels, const uint8_t* map, const TG* coef, const TG* diag,
+                              const double* degree, int64_t S, int C, double* Qs, double* GB, double* Hs,
+                              double* Us) {
+  const int64_t k = blockIdx.x;
+  const int64_t i = seeds[k];
+  const int64_t x = i % G.nx, y = (i / G.nx) % G.ny, z = i / (G.nx * G.ny);
+  int64_t nb[8];
+  double cf[8];
+  int cnt = 0;
+  for (int d = 0; d < G.ndir; ++d) {
+    if (head_in(G, x, y, z, d)) { nb[cnt] = i + G.off[d]; cf[cnt] = (double)coef[d * G.N + i]; ++cnt; }
+    if (tail_in(G, x, y, z, d)) { nb[cnt] = i - G.off[d]; cf[cnt] = (double)coef[d * G.N + i - G.off[d]]; ++cnt; }
+  }
+  for (int j = threadIdx.x; j < ma; j += blockDim.x) {
+    const TQ* qc = Q + (int64_t)j * G.N;
+    Qs[k + (int64_t)j * S] = (double)Elem<TQ>::ld(qc, i);
+    double acc = 0.0;
+    for (int t = 0; t < cnt; ++t)
+      if (map[nb[t]] == 0) acc -= cf[t] * (double)Elem<TQ>::ld(qc, nb[t]);
+    GB[k + (int64_t)j * S] = acc;
+  }
+  for (int lab = threadIdx.x; lab < C; lab += blockDim.x) {
+    auto uhat = [&](int64_t node, int mlab) -> double {
+      if (mlab - 1 != lab) return 0.0;
+      return normalized ? sqrt(degree[node]) : 1.0;
+    };
+    double own = uhat(i, map[i]);
+    double acc = (double)diag[i] * own;
+    for (int t = 0; t < cnt; ++t) {
+      int ml = map[nb[t]];
+      if (ml != 0) acc -= cf[t] * uhat(nb[t], ml);
+    }
+    Hs[k + (int64_t)lab * S] = acc;
+    Us[k + (int64_t)lab * S] = own;
+  }
+}
+
+// K = diag(lambda) - T (leading m x m of the ma x ma T);  Yrhs = leading m rows of R
+__global__ void k_build_reduced(const double* T, const double* R, const double* lambda, int ma, int m, int C,
+                                double* K, double* Y) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < (int64_t)m * m) {
+    int i = (int)(t % m), j = (int)(t / m);
+    K[t] = (i == j ? lambda[i] : 0.0) - T[i + (int64_t)j * ma];
+  }
+  if (t < (int64_t)m * C) {
+    int i = (int)(t % m), c = (int)(t / m);
+    Y[t] = R[i + (int64_t)c * ma];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// reconstruction: U(lab, i) = s_i * sum_j Q(i, j) Y(j, lab) on non-seeds (s = d^{-1/2} or 1),
+// one-hot on seeds.  Y lives in LDS; each thread owns one node and CB labels.
+// ---------------------------------------------------------------------------------------------
+template <typename TQ, typename TU, int CB>
+__global__ __launch_bounds__(256) void k_reconstruct(const TQ* Q, int64_t N, int m, const double* Y, int C,
+                                                      int lab0, const uint8_t* map, const TU* dinv, int normalized,
+                                                      TU* U) {
+  using CT = typename Elem<TQ>::C;
+  extern __shared__ char smem[];
+  CT* sY = reinterpret_cast<CT*>(smem);
+  for (int t = threadIdx.x; t < m * CB; t += blockDim.x) {
+    int j = t / CB, c = t % CB;
+    int lab = lab0 + c;
+    sY[t] = lab < C ? (CT)Y[j + (int64_t)lab * m] : CT(0);
+  }
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  CT acc[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) acc[c] = CT(0);
+  int j = 0;
+  for (; j + 4 <= m; j += 4) {
+    CT q0 = Elem<TQ>::ld(Q, (int64_t)j * N + i);
+    CT q1 = Elem<TQ>::ld(Q, (int64_t)(j + 1) * N + i);
+    CT q2 = Elem<TQ>::ld(Q, (int64_t)(j + 2) * N + i);
+    CT q3 = Elem<TQ>::ld(Q, (int64_t)(j + 3) * N + i);
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      acc[c] = fma(q0, sY[(j + 0) * CB + c], acc[c]);
+      acc[c] = fma(q1, sY[(j + 1) * CB + c], acc[c]);
+      acc[c] = fma(q2, sY[(j + 2) * CB + c], acc[c]);
+      acc[c] = fma(q3, sY[(j + 3) * CB + c], acc[c]);
+    }
+  }
+  for (; j < m; ++j) {
+    CT q = Elem<TQ>::ld(Q, (int64_t)j * N + i);
+#pragma unroll
+    for (int c = 0; c < CB; ++c) acc[c] = fma(q, sY[j * CB + c], acc[c]);
+  }
+  const int ml = map[i];
+  const CT sc = normalized ? (CT)dinv[i] : CT(1);
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    int lab = lab0 + c;
+    if (lab >= C) break;
+    CT v = ml ? (ml - 1 == lab ? CT(1) : CT(0)) : sc * acc[c];
+    U[(int64_t)lab * N + i] = (TU)v;
+  }
+}
+
+template <typename TQ, typename TU>
+static int reconstruct_t(const Graph* g, const void* Q, int m, const double* Y, int C, const uint8_t* map,
+                         void* U, hipStream_t s) {
+  using CT = typename Elem<TQ>::C;
+  for (int lab0 = 0; lab0 < C; lab0 += 8) {
+    int rem = C - lab0;
+    if (rem <= 4) {
+      size_t sh = (size_t)m * 4 * sizeof(CT);
+      k_reconstruct<TQ, TU, 4><<<nblocks(g->N, 256), 256, sh, s>>>((const TQ*)Q, g->N, m, Y, C, lab0, map,
+                                                                    (const TU*)g->dinv, g->normalized, (TU*)U);
+    } else {
+      size_t sh = (size_t)m * 8 * sizeof(CT);
+      k_reconstruct<TQ, TU, 8><<<nblocks(g->N, 256), 256, sh, s>>>((const TQ*)Q, g->N, m, Y, C, lab0, map,
+                                                                    (const TU*)g->dinv, g->normalized, (TU*)U);
+    }
+    RW_LAUNCH_CHECK();
+  }
+  return RW_OK;
+}
+
+static int reconstruct(const Graph* g, const void* Q, int qdt, int m, const double* Y, int C, const uint8_t* map,
+                       void* U, hipStream_t s) {
+  RW_CHECK((size_t)m * 8 * 8 <= 65536, RW_EINVAL, "m = %d too large for the reconstruction tile", m);
+  if (g->dtype == RW_F64) {
+    if (qdt == RW_F64) return reconstruct_t<double, double>(g, Q, m, Y, C, map, U, s);
+    if (qdt == RW_F32) return reconstruct_t<float, double>(g, Q, m, Y, C, map, U, s);
+    return reconstruct_t<uint16_t, double>(g, Q, m, Y, C, map, U, s);
+  }
+  if (qdt == RW_F64) return reconstruct_t<double, float>(g, Q, m, Y, C, map, U, s);
+  if (qdt == RW_F32) return reconstruct_t<float, float>(g, Q, m, Y, C, map, U, s);
+  return reconstruct_t<uint16_t, float>(g, Q, m, Y, C, map, U, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Choice of m (Sec. III-A1): f_k(m) = min_{||a|| <= rho} ||Q_s[:, :m] a - b_k||^2.
+// One block per (candidate m, label).  With ms = min(S, m): for m <= S the m x m normal matrix
+// G = Q_s^T Q_s (leading block) with g = Q_s^T b; for m > S the S x S matrix P = Q_s Q_s^T over the
+// first m columns with b.  mu = 0 when the (minimum-norm) least-squares solution is feasible, else
+// the Hebden / More-Sorensen Newton iteration on 1/||a(mu)|| - 1/rho, one Cholesky per step.
+// ---------------------------------------------------------------------------------------------
+__device__ bool blk_chol(double* A, int n, double shift) {
+  // lower Cholesky of (A + shift I) in place; returns false on a non-positive pivot
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      double akk = A[k + (int64_t)k * n] + shift;
+      if (!(akk > 0.0) || !isfinite(akk)) bad = 1;
+      else A[k + (int64_t)k * n] = sqrt(akk);
+    }
+    __syncthreads();
+    if (bad) break;
+    const double piv = A[k + (int64_t)k * n];
+    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A[i + (int64_t)k * n] /= piv;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int64_t t = threadIdx.x; t < (int64_t)m * m; t += blockDim.x) {
+      int i = k + 1 + (int)(t % m), j = k + 1 + (int)(t / m);
+      if (i >= j) A[i + (int64_t)j * n] -= A[i + (int64_t)k * n] * A[j + (int64_t)k * n];
+    }
+    __syncthreads();
+  }
+  const bool ok = !bad;
+  __syncthreads();
+  return ok;
+}
+
+constexpr int kMaxFitDim = 512;   // largest min(S, m) the choice of m handles
+
+// x <- L^{-1} x (forward) or L^{-T} x (backward) with the lower factor L (global) and x in LDS.
+// Wave 0 does the work; every lane forms the full dot product by butterfly reduction and writes the
+// same x[i], so each lane only ever reads values it wrote itself.
+__device__ void blk_trsv(const double* L, int n, double* x, bool transpose) {
+  if (threadIdx.x < 64) {
+    if (!transpose) {
+      for (int i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < i; k += 64) acc += L[i + (int64_t)k * n] * x[k];
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        x[i] = (x[i] - acc) / L[i + (int64_t)i * n];
+      }
+    } else {
+      for (int i = n - 1; i >= 0; --i) {
+        double acc = 0.0;
+        for (int k = i + 1 + threadIdx.x; k < n; k += 64) acc += L[k + (int64_t)i * n] * x[k];
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        x[i] = (x[i] - acc) / L[i + (int64_t)i * n];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__device__ double blk_dot(const double* a, const double* b, int n) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += a[i] * b[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_fit_seeds(const int* cand, int ncand, int C, int64_t S, int ma,
+                                                   const double* Qs, const double* Gq, const double* Gb,
+                                                   const double* Us, double rho, double* scratch,
+                                                   int64_t stride, double* fvals) {
+  const int ci = blockIdx.x, lab = blockIdx.y;
+  const int m = cand[ci];
+  const int ms = (int)std::min<int64_t>(S, m);
+  const bool small_m = m <= S;
+  double* A = scratch + ((int64_t)lab * ncand + ci) * stride;   // ms x ms factor
+  __shared__ double rhs[kMaxFitDim], x[kMaxFitDim], y[kMaxFitDim];
+  // right-hand side: g = Q_s^T b (m <= S) or b (m > S); ||b||^2
+  for (int i = threadIdx.x; i < ms; i += blockDim.x)
+    rhs[i] = small_m ? Gb[i + (int64_t)lab * ma] : Us[i + (int64_t)lab * S];
+  __shared__ double bnorm2_s;
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int64_t i = 0; i < S; ++i) acc += Us[i + (int64_t)lab * S] * Us[i + (int64_t)lab * S];
+    bnorm2_s = acc;
+  }
+  __syncthreads();
+  const double bnorm2 = bnorm2_s;
+  auto load_matrix = [&]() {
+    if (small_m) {
+      for (int64_t t = threadIdx.x; t < (int64_t)ms * ms; t += blockDim.x) {
+        int i = (int)(t % ms), j = (int)(t / ms);
+        A[t] = Gq[i + (int64_t)j * ma];
+      }
+    } else {
+      for (int64_t t = threadIdx.x; t < (int64_t)ms * ms; t += blockDim.x) {
+        int i = (int)(t % ms), j = (int)(t / ms);
+        double acc = 0.0;
+        for (int c = 0; c < m; ++c) acc += Qs[i + (int64_t)c * S] * Qs[j + (int64_t)c * S];
+        A[t] = acc;
+      }
+    }
+    __syncthreads();
+  };
+  // evaluate at mu: ||a||^2, D = -d||a||^2/dmu and f; false if the factorization fails
+  double na2 = 0.0, dd = 0.0, fv = 0.0;
+  auto eval = [&](double mu) -> bool {
+    load_matrix();
+    if (!blk_chol(A, ms, mu)) return false;
+    for (int i = threadIdx.x; i < ms; i += blockDim.x) x[i] = rhs[i];
+    __syncthreads();
+    blk_trsv(A, ms, x, false);
+    blk_trsv(A, ms, x, true);            // x = (M + mu I)^{-1} rhs
+    for (int i = threadIdx.x; i < ms; i += blockDim.x) y[i] = x[i];
+    __syncthreads();
+    blk_trsv(A, ms, y, false);           // y = L^{-1} x
+    double xx = blk_dot(x, x, ms), yy = blk_dot(y, y, ms), xr = blk_dot(x, rhs, ms);
+    if (small_m) {                        // x = alpha
+      na2 = xx;
+      dd = 2.0 * yy;
+      fv = bnorm2 - xr - mu * xx;
+    } else {                              // x = z with alpha = Q_s^T z
+      na2 = xr - mu * xx;
+      dd = 2.0 * (xx - mu * yy);
+      fv = mu * mu * xx;
+    }
+    if (fv < 0.0) fv = 0.0;
+    return true;
+  };
+  double mu = 0.0;
+  bool ok = eval(0.0);
+  if (!ok || na2 > rho * rho) {
+    // Newton from the left of the root (monotone for this concave secular function)
+    if (!ok) {
+      load_matrix();
+      double tr = 0.0;
+      for (int i = 0; i < ms; ++i) tr += A[i + (int64_t)i * ms];
+      mu = 1e-13 * (tr / ms) + 1e-300;
+      ok = eval(mu);
+    }
+    for (int it = 0; it < 100 && ok; ++it) {
+      double na = sqrt(na2);
+      if (fabs(na - rho) <= 1e-12 * rho || dd <= 0.0) break;
+      double step = 2.0 * na2 * (na - rho) / (rho * dd);
+      if (!(step > 0.0)) break;
+      mu += step;
+      ok = eval(mu);
+    }
+  }
+  if (threadIdx.x == 0) fvals[ci + (int64_t)lab * ncand] = ok ? fv : INFINITY;
+}
+
+// ---------------------------------------------------------------------------------------------
+
+static int host_seeds(const Graph* g, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C,
+                      std::vector<int64_t>* nodes, std::vector<int32_t>* labels) {
+  RW_CHECK(S >= 1, RW_EINVAL, "at least one seed is required");
+  RW_CHECK(seed_node != nullptr && seed_label != nullptr, RW_EINVAL, "null seed arrays");
+  RW_CHECK(C >= 1 && C <= 255, RW_EINVAL, "C must be in [1, 255] (got %d)", C);
+  std::vector<std::pair<int64_t, int32_t>> v((size_t)S);
+  for (int64_t k = 0; k < S; ++k) {
+    RW_CHECK(seed_node[k] >= 0 && seed_node[k] < g->N, RW_EINVAL, "seed %lld: node %lld out of range",
+             (long long)k, (long long)seed_node[k]);
+    RW_CHECK(seed_label[k] >= 0 && seed_label[k] < C, RW_EINVAL, "seed %lld: label %d out of range",
+             (long long)k, seed_label[k]);
+    v[k] = {seed_node[k], seed_label[k]};
+  }
+  std::sort(v.begin(), v.end());
+  nodes->clear();
+  labels->clear();
+  for (size_t k = 0; k < v.size(); ++k) {
+    if (k > 0 && v[k].first == v[k - 1].first) {
+      RW_CHECK(v[k].second == v[k - 1].second, RW_EINVAL, "node %lld seeded with labels %d and %d",
+               (long long)v[k].first, v[k - 1].second, v[k].second);
+      continue;
+    }
+    nodes->push_back(v[k].first);
+    labels->push_back(v[k].second);
+  }
+  return RW_OK;
+}
+
+}  // namespace rw
+
+using namespace rw;
+
+extern "C" {
+
+int rw_solve_workspace_bytes(rw_graph h, int m_avail, int64_t S, int C, size_t* bytes) {
+  RW_CHECK(h != nullptr && bytes != nullptr, RW_EINVAL, "null argument");
+  RW_CHECK(m_avail >= 2 && S >= 1 && C >= 1, RW_EINVAL, "bad sizes");
+  *bytes = solve_layout(&h->g, m_avail, S, C, nullptr, nullptr);
+  return RW_OK;
+}
+
+int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda, int m_avail,
+                   const int64_t* seed_node, const int32_t* seed_label, int64_t S_in, int C, double eps, void* U,
+                   void* work, size_t work_bytes, hipStream_t stream, rw_solve_info* info) {
+  RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
+  const Graph* g = &h->g;
+  RW_CHECK(Q != nullptr && lambda != nullptr && U != nullptr && work != nullptr, RW_EINVAL, "null pointer argument");
+  RW_CHECK(q_dtype == RW_F64 || q_dtype == RW_F32 || q_dtype == RW_BF16, RW_EINVAL, "bad Q dtype");
+  RW_CHECK(m_avail >= 2 && m_avail <= g->N, RW_EINVAL, "m_avail = %d out of range", m_avail);
+  std::vector<int64_t> nodes;
+  std::vector<int32_t> labels;
+  RW_TRY(host_seeds(g, seed_node, seed_label, S_in, C, &nodes, &labels));
+  const int64_t S = (int64_t)nodes.size();
+  RW_CHECK(S < g->N, RW_EINVAL, "every node is a seed");
+  SolveWork w;
+  size_t need = solve_layout(g, m_avail, S_in, C, work, &w);  // sized for S_in >= S
+  RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "solve workspace too small: %zu < %zu", work_bytes, need);
+  // seeds to the device; map of seeded nodes
+  RW_HIP(hipMemcpyAsync(w.seeds, nodes.data(), S * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+  RW_HIP(hipMemcpyAsync(w.labels, labels.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  k_clear_map<<<nblocks(g->N, 256), 256, 0, stream>>>(w.map, g->N);
+  RW_LAUNCH_CHECK();
+  k_set_map<<<nblocks(S, 256), 256, 0, stream>>>(w.map, w.seeds, w.labels, S);
+  RW_LAUNCH_CHECK();
+  const GridDev G = grid_of(g);
+  const int ma = m_avail;
+#define RW_GATHER(TQ, TG)                                                                                     \
+  k_seed_gather<TQ, TG><<<(unsigned)S, 256, 0, stream>>>(G, g->normalized, (const TQ*)Q, ma, w.seeds, w.labels, \
+                                                         w.map, (const TG*)g->coef, (const TG*)g->diag, g->degree, S, \
+                                                         C, w.Qs, w.GB, w.Hs, w.Us)
+  if (g->dtype == RW_F64) {
+    if (q_dtype == RW_F64) RW_GATHER(double, double);
+    else if (q_dtype == RW_F32) RW_GATHER(float, double);
+    else RW_GATHER(uint16_t, double);
+  } else {
+    if (q_dtype == RW_F64) RW_GATHER(double, float);
+    else if (q_dtype == RW_F32) RW_GATHER(float, float);
+    else RW_GATHER(uint16_t, float);
+  }
+#undef RW_GATHER
+  RW_LAUNCH_CHECK();
+  // T = Q_s^T (B Q_n),  R = Q_s^T (op_ss U_hat_s)
+  RW_TRY(gram(RW_F64, w.Qs, S, w.GB, S, S, ma, ma, w.T, w.partial, stream));
+  RW_TRY(gram(RW_F64, w.Qs, S, w.Hs, S, S, ma, C, w.R, w.partial, stream));
+  // choice of m
+  int m = ma;
+  double f_max = 0.0, f_worst = 0.0;
+  if (eps > 0.0) {
+    f_max = (double)S * eps * eps;
+    RW_TRY(gram(RW_F64, w.Qs, S, w.Qs, S, S, ma, ma, w.Gq, w.partial, stream));
+    RW_TRY(gram(RW_F64, w.Qs, S, w.Us, S, S, ma, C, w.Gb, w.partial, stream));
+    double rho2 = 0.0;
+    if (g->normalized) {
+      RW_HIP(hipMemcpyAsync(&rho2, g->sums, sizeof(double), hipMemcpyDeviceToHost, stream));
+      RW_HIP(hipStreamSynchronize(stream));
+    } else {
+      rho2 = (double)g->N;
+    }
+    const double rho = std::sqrt(rho2);
+    // search: lo = largest m known to fail (1 = none), hi = smallest m known to pass (ma + 1 = none)
+    int lo = 1, hi = ma + 1;
+    std::vector<double> fh((size_t)kMaxCand * C);
+    std::vector<int> cand;
+    // candidate list lives in the first kMaxCand ints of the K buffer (unused until the final solve)
+    int* cand_buf = reinterpret_cast<int*>(w.K);
+    const int64_t msmax = std::min<int64_t>(S, ma);
+    RW_CHECK(msmax <= kMaxFitDim, RW_EINVAL, "choice of m supports min(S, m_avail) <= %d", kMaxFitDim);
+    const int64_t stride = msmax * msmax + 4 * msmax;
+    std::vector<std::pair<int, double>> evaluated;
+    while (hi - lo > 1) {
+      cand.clear();
+      int span = hi - lo - 1;
+      int nc = std::min(span, kMaxCand);
+      for (int q = 1; q <= nc; ++q) {
+        int mm = lo + (int)(((int64_t)span * q + nc - 1) / nc);
+        if (mm < 2) mm = 2;
+        if (cand.empty() || mm > cand.back()) cand.push_back(mm);
+      }
+      int ncand = (int)cand.size();
+      RW_HIP(hipMemcpyAsync(cand_buf, cand.data(), ncand * sizeof(int), hipMemcpyHostToDevice, stream));
+      k_fit_seeds<<<dim3(ncand, C), 256, 0, stream>>>(cand_buf, ncand, C, S, ma, w.Qs, w.Gq, w.Gb, w.Us, rho,
+                                                      w.tr_scratch, stride, w.fvals);
+      RW_LAUNCH_CHECK();
+      RW_HIP(hipMemcpyAsync(fh.data(), w.fvals, (size_t)ncand * C * sizeof(double), hipMemcpyDeviceToHost, stream));
+      RW_HIP(hipStreamSynchronize(stream));
+      int first_pass = -1;
+      for (int q = 0; q < ncand; ++q) {
+        double worst = 0.0;
+        for (int c = 0; c < C; ++c) worst = std::max(worst, fh[(size_t)c * ncand + q]);
+        evaluated.push_back({cand[q], worst});
+        if (first_pass < 0 && worst <= f_max) first_pass = q;
+      }
+      if (first_pass < 0) {
+        lo = cand.back();
+      } else {
+        hi = cand[first_pass];
+        if (first_pass > 0) lo = cand[first_pass - 1];
+      }
+    }
+    m = hi <= ma ? hi : ma;
+    f_worst = INFINITY;
+    for (auto& e : evaluated)
+      if (e.first == m) f_worst = e.second;
+  }
+  // reduced system and solve
+  k_build_reduced<<<nblocks((int64_t)m * std::max(m, C), 256), 256, 0, stream>>>(w.T, w.R, lambda, ma, m, C, w.K, w.Y);
+  RW_LAUNCH_CHECK();
+  RW_TRY(lu_solve(w.K, m, w.Y, C, w.stat, stream));
+  double stat = 0.0;
+  RW_HIP(hipMemcpyAsync(&stat, w.stat, sizeof(double), hipMemcpyDeviceToHost, stream));
+  RW_HIP(hipStreamSynchronize(stream));
+  RW_CHECK(stat > 0.0, RW_ESINGULAR, "reduced seed system is singular to working precision (m = %d)", m);
+  RW_TRY(reconstruct(g, Q, q_dtype, m, w.Y, C, w.map, U, stream));
+  if (info) {
+    info->m_used = m;
+    info->f_max = f_max;
+    info->f_worst = f_worst;
+    info->min_pivot = stat;
+  }
+  return RW_OK;
+}
+
+}  // extern "C"

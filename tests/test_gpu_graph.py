@@ -1,0 +1,125 @@
+"""GPU parity: graph build, edits and the stencil operator against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1607_04174_amd as rw
+import rwsynth
+from oracle.graph import Graph as OGraph
+
+from gpu_common import banner, dev, need_gpu, setup_case, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("2d4_f64", rwsynth.small("a", (67, 45), 4, n_shapes=3), torch.float64),
+    ("2d8_f32", rwsynth.small("b", (70, 33), 8, n_shapes=4), torch.float32),
+    ("2d8_f64", rwsynth.small("c", (33, 70), 8, n_shapes=4), torch.float64),
+    ("3d6_f32", rwsynth.small("d", (21, 17, 9), 6, n_shapes=3), torch.float32),
+    ("3d6_f64", rwsynth.small("e", (9, 23, 13), 6, n_shapes=3), torch.float64),
+]
+
+
+def _rtol(dt):
+    return 1e-15 if dt == torch.float64 else 0.0
+
+
+def _weight_rtol(og):
+    """exp(x) has condition number |x|: the argument x = -beta dJ^2 is rounded differently by the two
+    sides (operation order), so the FP64 weights can differ by ~ 4 u (1 + |x|) relative."""
+    diff = og.J[og.tail] - og.J[og.head]
+    x = og.beta * diff * diff
+    rt = np.zeros((len(og.weights_by_dir()), og.N))
+    rt[og.dir, og.tail] = 4 * 2.0 ** -53 * (1 + x)
+    return rt
+
+
+def _check_graph(gg, og, dt):
+    v = gg.view()
+    np.testing.assert_array_equal(v["mask"].cpu().numpy(), og.mask_bits())
+    w_ref = og.weights_by_dir()
+    w = v["weight"].cpu().numpy().astype(np.float64)
+    if dt == torch.float64:
+        assert np.all(np.abs(w - w_ref) <= _weight_rtol(og) * w_ref)
+    else:
+        # FP32 weight = the FP64 weight rounded once (1 ulp allowed for the exp difference)
+        np.testing.assert_allclose(w, w_ref.astype(np.float32).astype(np.float64), rtol=1.2e-7, atol=0)
+    d_ref = og.degree()
+    tol = 1e-14 if dt == torch.float64 else 1e-6
+    np.testing.assert_allclose(v["degree"].cpu().numpy(), d_ref, rtol=tol)
+    np.testing.assert_allclose(v["ghat"].cpu().numpy().astype(np.float64), og.ghat(), rtol=10 * tol, atol=1e-300)
+
+
+@pytest.mark.parametrize("name,w,dt", CASES, ids=[c[0] for c in CASES])
+def test_graph_build_matches_oracle(name, w, dt):
+    need_gpu()
+    banner(f"graph build {name}")
+    J, rid, node, lab = setup_case(w)
+    gg = rw.Graph(to_dev(J, torch.float64), w.dims, w.conn, 90.0, dtype=dt)
+    og = OGraph(J, w.dims, w.conn, 90.0)
+    _check_graph(gg, og, dt)
+
+
+@pytest.mark.parametrize("name,w,dt", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("normalized", [True, False])
+def test_stencil_matches_oracle(name, w, dt, normalized):
+    need_gpu()
+    banner(f"stencil {name} normalized={normalized}")
+    J, rid, node, lab = setup_case(w)
+    gg = rw.Graph(to_dev(J, torch.float64), w.dims, w.conn, 90.0, dtype=dt, normalized=normalized)
+    og = OGraph(J, w.dims, w.conn, 90.0, normalized=normalized)
+    M = og.M()
+    rng = np.random.default_rng(4)
+    for b in (1, 3, 37):
+        X = rng.standard_normal((b, og.N))
+        Y = rw.apply_laplacian(gg, to_dev(X, dt)).cpu().numpy().astype(np.float64)
+        Xr = X.astype(np.float32).astype(np.float64) if dt == torch.float32 else X
+        Yref = (M @ Xr.T).T
+        err = np.linalg.norm(Y - Yref) / np.linalg.norm(Yref)
+        assert err < (1e-13 if dt == torch.float64 else 2e-6), err
+    # fused form: Y = a op X + b X + c Z
+    X = rng.standard_normal((5, og.N))
+    Z = rng.standard_normal((5, og.N))
+    Yd = torch.empty_like(to_dev(X, dt))
+    rw.apply_laplacian_axpby(gg, to_dev(X, dt), Yd, to_dev(Z, dt), 0.7, -0.3, 1.9)
+    Xr, Zr = (X.astype(np.float32).astype(np.float64), Z.astype(np.float32).astype(np.float64)) \
+        if dt == torch.float32 else (X, Z)
+    ref = 0.7 * (M @ Xr.T).T - 0.3 * Xr + 1.9 * Zr
+    err = np.linalg.norm(Yd.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err < (1e-13 if dt == torch.float64 else 2e-6), err
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_edits_match_oracle(dt):
+    need_gpu()
+    banner(f"edits {dt}")
+    w = rwsynth.small("ed", (48, 40), 8, n_shapes=4)
+    J, rid, node, lab = setup_case(w)
+    gg = rw.Graph(to_dev(J, torch.float64), w.dims, w.conn, 90.0, dtype=dt)
+    og = OGraph(J, w.dims, w.conn, 90.0)
+    rng = np.random.default_rng(11)
+    valid = rwsynth.edge_ids_valid(w.dims, w.conn)
+    rem = np.sort(rng.choice(valid, 60, replace=False))
+    sc = np.sort(rng.choice(np.setdiff1d(valid, rem), 25, replace=False))
+    edits = [rwsynth.Edit("set_beta", 150.0),
+             rwsynth.Edit("scale_box", 0.1, (5, 7, 0), (21, 30, 1)),
+             rwsynth.Edit("scale_edges", 3.0, edge_ids=sc),
+             rwsynth.Edit("remove_edges", edge_ids=rem)]
+    rw.edit_graph(gg, edits)
+    for e in edits:
+        og.apply_edit(e)
+    _check_graph(gg, og, dt)
+    # removing an edge twice is an error and leaves the graph unchanged
+    with pytest.raises(rw.RWError) as ei:
+        rw.edit_graph(gg, [rwsynth.Edit("remove_edges", edge_ids=rem[:2])])
+    assert ei.value.status == rw.RW_EINVAL
+    _check_graph(gg, og, dt)
+
+
+def test_invalid_graph_arguments():
+    need_gpu()
+    J = to_dev(np.zeros(12), torch.float64)
+    with pytest.raises(rw.RWError):
+        rw.Graph(J, (4, 3), 6, 1.0)          # 6-connectivity is 3D only
+    with pytest.raises(rw.RWError):
+        rw.Graph(J, (4, 3), 4, -1.0)         # beta < 0

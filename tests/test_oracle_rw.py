@@ -106,3 +106,24 @@ def test_fast_rw_ignores_null_components_of_stored_basis():
     Q2[:, 1:] += np.outer(g.ghat(), np.linspace(0.01, 0.05, 11))
     Q2[:, 1:] /= np.linalg.norm(Q2[:, 1:], axis=0)
     np.testing.assert_allclose(fast_rw(g, Q2, lam, node, lab, 2), fast_rw(g, Q, lam, node, lab, 2), atol=1e-12)
+
+
+def test_exact_mode_agrees_and_survives_near_null_eigenvalues():
+    """Exact rational evaluation of the bordered system equals the FP64 one on a well-conditioned
+    basis, and keeps the rows stochastic where weakly coupled regions give eigenvalues ~1e-13."""
+    w = rwsynth.small("t", (12, 11), 4, C=3, seeds_per_label=3, n_shapes=3)
+    J, rid = rwsynth.phantom(w)
+    node, lab = rwsynth.seeds(w, rid)
+    g = Graph(J, (12, 11, 1), 4, beta=10.0)          # low contrast: well separated spectrum
+    lam, Q = dense_eigpairs(g, 20)
+    assert lam[1] > 1e-4
+    np.testing.assert_allclose(fast_rw(g, Q, lam, node, lab, 3, exact=True), fast_rw(g, Q, lam, node, lab, 3),
+                               atol=1e-13)
+    w = rwsynth.small("s1", (23, 19), 4, m=40, C=3, seeds_per_label=4, n_shapes=3)
+    J, rid = rwsynth.phantom(w)
+    node, lab = rwsynth.seeds(w, rid)
+    g = Graph(J, w.dims, 4, beta=90.0)
+    lam, Q = dense_eigpairs(g, 10)
+    assert lam[1] < 1e-9                              # weakly coupled region
+    U = fast_rw(g, Q, lam, node, lab, 3, exact=True)
+    np.testing.assert_allclose(U.sum(axis=1), 1.0, atol=1e-13)
