@@ -233,6 +233,23 @@ int rw_cg_solve(rw_graph g, const int64_t* seed_node, const int32_t* seed_label,
                 double tol, int max_iter, int x0_given, double* U, void* work, size_t work_bytes,
                 hipStream_t stream, rw_cg_info* info);
 
+/* ======================================================================================
+ * Dense FP64 building blocks used by the steps above (exposed for testing and reuse)
+ * ====================================================================================== */
+
+/* Symmetric eigendecomposition of `count` matrices A (device, n x n column-major each, stride n*n,
+ * read only; only the symmetric part is used) by the parallel cyclic Jacobi method: w (device,
+ * count x n, ascending) and V (device, count x n x n eigenvectors as columns, or null).  1 <= n <= 1022.
+ * work: device buffer of rw_dense_syev_workspace_bytes.  Errors: RW_EINVAL, RW_EWORKSPACE. */
+int rw_dense_syev_workspace_bytes(int n, int count, size_t* bytes);
+int rw_dense_syev(const double* A, double* w, double* V, int n, int count, void* work, size_t work_bytes,
+                  hipStream_t stream);
+
+/* Solve A X = B by LU with partial pivoting (device, A n x n and B n x nrhs column-major, both
+ * overwritten; X returned in B).  stat (device, 1 double) = min |pivot| / max |a_ij|, or 0 when a pivot
+ * falls below 1e-14 max |a_ij| (B is then not a solution). */
+int rw_dense_lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -97,6 +97,10 @@ _SIGS = {
     "rw_solve_seeds": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p,
                                   ct.c_void_p, ct.c_int64, ct.c_int, ct.c_double, ct.c_void_p, ct.c_void_p,
                                   ct.c_size_t, ct.c_void_p, ct.POINTER(rw_solve_info)]),
+    "rw_dense_syev_workspace_bytes": (ct.c_int, [ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_dense_syev": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_size_t,
+                                 ct.c_void_p]),
+    "rw_dense_lu_solve": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p]),
     "rw_cg_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_size_t)]),
     "rw_cg_solve": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int, ct.c_double, ct.c_int,
                                ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p,
@@ -361,3 +365,31 @@ def cg_solve(g: Graph, seed_node, seed_label, C: int, tol: float = 1e-12, max_it
     if st != RW_OK and not (st == RW_ENOCONV and not raise_on_noconv):
         _check(st)
     return U, {"iters": info.iters, "rel_residual": info.rel_residual, "status": st}
+
+
+# ---------------------------------------------------------------------------------------------
+# dense building blocks
+# ---------------------------------------------------------------------------------------------
+def dense_syev(A: torch.Tensor, vectors: bool = True):
+    """Eigenpairs of a batch of symmetric FP64 matrices A (count, n, n) (each read as column-major).
+    Returns (w (count, n), V (count, n, n) with V[b, j] the j-th eigenvector, or None)."""
+    A = A.contiguous()
+    count, n = A.shape[0], A.shape[1]
+    w = torch.empty((count, n), dtype=torch.float64, device=A.device)
+    V = torch.empty((count, n, n), dtype=torch.float64, device=A.device) if vectors else None
+    nb = ct.c_size_t()
+    _check(lib().rw_dense_syev_workspace_bytes(n, count, ct.byref(nb)))
+    work = _workspace(nb.value, A.device)
+    _check(lib().rw_dense_syev(_ptr(A), _ptr(w), _ptr(V), n, count, _ptr(work), nb.value, _stream(A.device)))
+    return w, V
+
+
+def dense_lu_solve(A: torch.Tensor, B: torch.Tensor):
+    """Solve A X = B (A (n, n), B (nrhs, n): both column-major views).  Returns (X, stat)."""
+    A = A.clone().contiguous()
+    X = B.clone().contiguous()
+    n = A.shape[0]
+    nrhs = X.numel() // n
+    stat = torch.empty(1, dtype=torch.float64, device=A.device)
+    _check(lib().rw_dense_lu_solve(_ptr(A), n, _ptr(X), nrhs, _ptr(stat), _stream(A.device)))
+    return X, float(stat.item())

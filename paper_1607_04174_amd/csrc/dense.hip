@@ -67,41 +67,89 @@ int chol_upper_inverse(const double* L, double* Rinv, int n, hipStream_t s) {
 
 // ---------------------------------------------------------------------------------------------
 // Symmetric eigendecomposition by the cyclic Jacobi method with the round-robin ("tournament")
-// ordering: each round rotates n/2 disjoint index pairs at once (Golub & Van Loan, Sec. 8.5), all
-// rows first, then all columns and the eigenvector accumulator.  Sweeps stop when a sweep performs
-// no rotation.  Eigenvalues are returned ascending with their vectors.
+// ordering (Golub & Van Loan, Sec. 8.5): each round rotates n/2 disjoint index pairs at once.
+// With J the product of the round's rotations, J^T A J splits into independent 2 x 2 blocks: the
+// block of pairs (P1, P2) becomes J1^T A[P1,P2] J2, and the diagonal block of a pair becomes
+// diag(a_pp - t a_pq, a_qq + t a_pq).  One thread updates one 2 x 2 block, so a round is one pass
+// over the matrix with no strided row/column sweeps.  The matrix lives in LDS (packed upper
+// triangle) when it fits, else in global memory (L2-resident).  Right-hand sides are rotated along
+// (giving V^T R), and the rotations are logged so that a second kernel can replay them into V with
+// rows spread over several workgroups.  Sweeps stop when a sweep performs no rotation.
 // ---------------------------------------------------------------------------------------------
 constexpr int kJacobiThreads = 1024;
-constexpr int kJacobiMaxSweeps = 40;
+constexpr int kJacobiMaxSweeps = 30;
+constexpr size_t kLdsLimit = 160 * 1024 - 2048;   // dynamic LDS budget (static arrays use the rest)
 
 __device__ __forceinline__ int rr_player(int pos, int round, int n2) {
-  // position 0 is fixed; positions 1..n2-1 rotate
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n2 - 1);
 }
 
-__global__ __launch_bounds__(kJacobiThreads) void k_jacobi(double* As, double* ws, double* Vs, double* Vtmp_s,
-                                                           int n) {
-  double* A = As + (int64_t)blockIdx.x * n * n;
-  double* V = Vtmp_s + (int64_t)blockIdx.x * n * n;
-  double* Vout = Vs + (int64_t)blockIdx.x * n * n;
-  double* w = ws + (int64_t)blockIdx.x * n;
-  const int n2 = n + (n & 1);
+struct LdsStore {   // packed upper triangle in LDS
+  double* a;
+  __device__ __forceinline__ int64_t at(int i, int j) const {
+    if (i > j) { int t = i; i = j; j = t; }
+    return (int64_t)j * (j + 1) / 2 + i;
+  }
+  __device__ __forceinline__ double ld(int i, int j) const { return a[at(i, j)]; }
+  __device__ __forceinline__ void st(int i, int j, double v) const { a[at(i, j)] = v; }
+  __device__ __forceinline__ void st_sym(int i, int j, double v) const { a[at(i, j)] = v; }
+};
+
+struct GlbStore {   // full n2 x n2 column-major copy in global memory
+  double* a;
+  int n2;
+  __device__ __forceinline__ double ld(int i, int j) const { return a[i + (int64_t)j * n2]; }
+  __device__ __forceinline__ void st_sym(int i, int j, double v) const {
+    a[i + (int64_t)j * n2] = v;
+    a[j + (int64_t)i * n2] = v;
+  }
+};
+
+__host__ __device__ size_t syev_log_count(int n) {
+  int n2 = n + (n & 1);
+  return (size_t)kJacobiMaxSweeps * (n2 - 1) * (n2 / 2) * 2;
+}
+
+// per-matrix work: [glb copy n2*n2][log][perm n][sweeps 8][rhs n2*nrhs (global variant)]
+static size_t syev_stride(int n, bool vectors, bool glb, int nrhs) {
+  int n2 = n + (n & 1);
+  size_t s = glb ? (size_t)n2 * n2 : 0;
+  if (vectors) s += syev_log_count(n);
+  s += n + 8;
+  if (glb) s += (size_t)n2 * nrhs;
+  return (s + 31) / 32 * 32;
+}
+
+static size_t lds_bytes(int n, int nrhs) {
+  int n2 = n + (n & 1), np = n2 / 2;
+  return (size_t)n2 * (n2 + 1) / 2 * 8 + (size_t)np * 16 + (size_t)np * 8 + (size_t)n2 * nrhs * 8 + 256;
+}
+
+size_t syev_work_count(int n, int count, bool vectors, int nrhs) {
+  bool glb = lds_bytes(n, nrhs) > kLdsLimit;
+  return syev_stride(n, vectors, glb, nrhs) * count;
+}
+
+template <class Store>
+__device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, double* log, double* wout, double* permout,
+                            double* sweeps_out, double* cs, double* sn, int* pq) {
   const int np = n2 / 2;
-  __shared__ double cs[512], sn[512];
-  __shared__ int pp[512], qq[512];
   __shared__ int rotated;
-  __shared__ double fro;
-  for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += blockDim.x) V[t] = (t % n == t / n) ? 1.0 : 0.0;
-  // Frobenius norm for the absolute threshold (one wave, fixed order)
+  __shared__ double fro_s;
+  // Frobenius norm (one wave, fixed order) for the absolute threshold
   if (threadIdx.x < 64) {
     double acc = 0.0;
-    for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += 64) acc += A[t] * A[t];
+    for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += 64) {
+      double v = S.ld((int)(t % n), (int)(t / n));
+      acc += v * v;
+    }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (threadIdx.x == 0) fro = sqrt(acc);
+    if (threadIdx.x == 0) fro_s = sqrt(acc);
   }
   __syncthreads();
-  const double abs_tiny = fro * 1e-16 + 1e-300;
-  for (int sweep = 0; sweep < kJacobiMaxSweeps; ++sweep) {
+  const double abs_tiny = fro_s * 1e-16 + 1e-300;
+  int sweep = 0;
+  for (; sweep < kJacobiMaxSweeps; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < n2 - 1; ++round) {
@@ -110,71 +158,233 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi(double* As, double* w
         if (p > q) { int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0;
         if (q < n) {
-          double apq = A[p + (int64_t)q * n];
-          double app = A[p + (int64_t)p * n], aqq = A[q + (int64_t)q * n];
+          double apq = S.ld(p, q), app = S.ld(p, p), aqq = S.ld(q, q);
           if (fabs(apq) > abs_tiny && fabs(apq) > 1e-15 * sqrt(fabs(app) * fabs(aqq))) {
             double tau = (aqq - app) / (2.0 * apq);
             double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
+            S.st_sym(p, p, app - t * apq);
+            S.st_sym(q, q, aqq + t * apq);
+            S.st_sym(p, q, 0.0);
             rotated = 1;
           }
         }
-        pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s;
+        cs[k] = c;
+        sn[k] = s;
+        pq[2 * k] = p;
+        pq[2 * k + 1] = q;
+        if (log) {
+          double* L = log + (((int64_t)sweep * (n2 - 1) + round) * np + k) * 2;
+          L[0] = c;
+          L[1] = s;
+        }
       }
       __syncthreads();
-      // rows p, q of A <- J^T A
-      for (int64_t t = threadIdx.x; t < (int64_t)np * n; t += blockDim.x) {
-        int k = (int)(t / n), col = (int)(t % n);
-        double s = sn[k];
-        if (s == 0.0) continue;
-        double c = cs[k];
-        int p = pp[k], q = qq[k];
-        double ap = A[p + (int64_t)col * n], aq = A[q + (int64_t)col * n];
-        A[p + (int64_t)col * n] = c * ap - s * aq;
-        A[q + (int64_t)col * n] = s * ap + c * aq;
+      // off-diagonal 2 x 2 blocks (pair k1 < pair k2) and right-hand sides
+      const int64_t nblk = (int64_t)np * np;
+      for (int64_t t = threadIdx.x; t < nblk; t += blockDim.x) {
+        int k1 = (int)(t % np), k2 = (int)(t / np);
+        if (k1 >= k2) continue;
+        double s1 = sn[k1], s2 = sn[k2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        double c1 = cs[k1], c2 = cs[k2];
+        int p1 = pq[2 * k1], q1 = pq[2 * k1 + 1], p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
+        if (q1 >= n) { s1 = 0.0; c1 = 1.0; }
+        if (q2 >= n) { s2 = 0.0; c2 = 1.0; }
+        double b00 = S.ld(p1, p2), b01 = q2 < n ? S.ld(p1, q2) : 0.0;
+        double b10 = q1 < n ? S.ld(q1, p2) : 0.0, b11 = (q1 < n && q2 < n) ? S.ld(q1, q2) : 0.0;
+        // rows: J1^T B
+        double r00 = c1 * b00 - s1 * b10, r01 = c1 * b01 - s1 * b11;
+        double r10 = s1 * b00 + c1 * b10, r11 = s1 * b01 + c1 * b11;
+        // columns: (J1^T B) J2
+        S.st_sym(p1, p2, c2 * r00 - s2 * r01);
+        if (q2 < n) S.st_sym(p1, q2, s2 * r00 + c2 * r01);
+        if (q1 < n) S.st_sym(q1, p2, c2 * r10 - s2 * r11);
+        if (q1 < n && q2 < n) S.st_sym(q1, q2, s2 * r10 + c2 * r11);
       }
-      __syncthreads();
-      // columns p, q of A <- A J and of V <- V J
-      for (int64_t t = threadIdx.x; t < (int64_t)np * n; t += blockDim.x) {
-        int k = (int)(t / n), row = (int)(t % n);
-        double s = sn[k];
-        if (s == 0.0) continue;
-        double c = cs[k];
-        int p = pp[k], q = qq[k];
-        double ap = A[row + (int64_t)p * n], aq = A[row + (int64_t)q * n];
-        A[row + (int64_t)p * n] = c * ap - s * aq;
-        A[row + (int64_t)q * n] = s * ap + c * aq;
-        double vp = V[row + (int64_t)p * n], vq = V[row + (int64_t)q * n];
-        V[row + (int64_t)p * n] = c * vp - s * vq;
-        V[row + (int64_t)q * n] = s * vp + c * vq;
+      if (rhs) {
+        for (int64_t t = threadIdx.x; t < (int64_t)np * nrhs; t += blockDim.x) {
+          int k = (int)(t % np), r = (int)(t / np);
+          double s = sn[k];
+          if (s == 0.0) continue;
+          double c = cs[k];
+          int p = pq[2 * k], q = pq[2 * k + 1];
+          double vp = rhs[p + (int64_t)r * n2], vq = rhs[q + (int64_t)r * n2];
+          rhs[p + (int64_t)r * n2] = c * vp - s * vq;
+          rhs[q + (int64_t)r * n2] = s * vp + c * vq;
+        }
       }
       __syncthreads();
     }
-    const int any = rotated;   // read by every thread before thread 0 may reset it
+    const int any = rotated;
     __syncthreads();
-    if (!any) break;
+    if (!any) { ++sweep; break; }
   }
-  // sort ascending (stable by index) and write out
+  // eigenvalues ascending (stable by index); perm[i] = sorted position of index i
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double wi = A[i + (int64_t)i * n];
+    double wi = S.ld(i, i);
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      double wj = A[j + (int64_t)j * n];
+      double wj = S.ld(j, j);
       rank += (wj < wi) || (wj == wi && j < i);
     }
-    w[rank] = wi;
-    for (int r = 0; r < n; ++r) Vout[r + (int64_t)rank * n] = V[r + (int64_t)i * n];
+    wout[rank] = wi;
+    permout[i] = (double)rank;
+  }
+  if (threadIdx.x == 0) sweeps_out[0] = (double)sweep;
+}
+
+__global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(const double* As, int n, double* ws, double* Rs, int nrhs,
+                                                                double* work, int64_t stride, int want_log) {
+  extern __shared__ double smem[];
+  const int n2 = n + (n & 1), np = n2 / 2;
+  const double* A = As + (int64_t)blockIdx.x * n * n;
+  double* wk = work + (int64_t)blockIdx.x * stride;
+  double* log = want_log ? wk : nullptr;
+  double* perm = wk + (want_log ? syev_log_count(n) : 0);
+  double* a = smem;
+  double* cs = a + (size_t)n2 * (n2 + 1) / 2;
+  double* sn = cs + np;
+  int* pq = reinterpret_cast<int*>(sn + np);
+  double* rhs = reinterpret_cast<double*>(pq + 2 * np);
+  LdsStore S{a};
+  for (int64_t t = threadIdx.x; t < (int64_t)n2 * (n2 + 1) / 2; t += blockDim.x) a[t] = 0.0;
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += blockDim.x) {
+    int i = (int)(t % n), j = (int)(t / n);
+    if (i <= j) S.st_sym(i, j, 0.5 * (A[t] + A[j + (int64_t)i * n]));
+  }
+  double* R = Rs ? Rs + (int64_t)blockIdx.x * n * nrhs : nullptr;
+  if (R)
+    for (int64_t t = threadIdx.x; t < (int64_t)n2 * nrhs; t += blockDim.x) {
+      int i = (int)(t % n2), r = (int)(t / n2);
+      rhs[t] = i < n ? R[i + (int64_t)r * n] : 0.0;
+    }
+  __syncthreads();
+  jacobi_body(S, n, n2, R ? rhs : nullptr, nrhs, log, ws + (int64_t)blockIdx.x * n, perm, perm + n, cs, sn, pq);
+  __syncthreads();
+  if (R)
+    for (int64_t t = threadIdx.x; t < (int64_t)n * nrhs; t += blockDim.x) {
+      int i = (int)(t % n), r = (int)(t / n);
+      R[(int)perm[i] + (int64_t)r * n] = rhs[i + (int64_t)r * n2];
+    }
+}
+
+__global__ __launch_bounds__(kJacobiThreads) void k_jacobi_glb(const double* As, int n, double* ws, double* Rs, int nrhs,
+                                                                double* work, int64_t stride, int want_log) {
+  const int n2 = n + (n & 1), np = n2 / 2;
+  __shared__ double cs[512], sn[512];
+  __shared__ int pq[1024];
+  const double* A = As + (int64_t)blockIdx.x * n * n;
+  double* wk = work + (int64_t)blockIdx.x * stride;
+  double* a = wk;
+  double* log = want_log ? wk + (size_t)n2 * n2 : nullptr;
+  double* perm = wk + (size_t)n2 * n2 + (want_log ? syev_log_count(n) : 0);
+  double* rhs = perm + n + 8;
+  GlbStore S{a, n2};
+  for (int64_t t = threadIdx.x; t < (int64_t)n2 * n2; t += blockDim.x) {
+    int i = (int)(t % n2), j = (int)(t / n2);
+    a[t] = (i < n && j < n) ? 0.5 * (A[i + (int64_t)j * n] + A[j + (int64_t)i * n]) : 0.0;
+  }
+  double* R = Rs ? Rs + (int64_t)blockIdx.x * n * nrhs : nullptr;
+  if (R)
+    for (int64_t t = threadIdx.x; t < (int64_t)n2 * nrhs; t += blockDim.x) {
+      int i = (int)(t % n2), r = (int)(t / n2);
+      rhs[t] = i < n ? R[i + (int64_t)r * n] : 0.0;
+    }
+  __syncthreads();
+  jacobi_body(S, n, n2, R ? rhs : nullptr, nrhs, log, ws + (int64_t)blockIdx.x * n, perm, perm + n, cs, sn, pq);
+  __syncthreads();
+  if (R)
+    for (int64_t t = threadIdx.x; t < (int64_t)n * nrhs; t += blockDim.x) {
+      int i = (int)(t % n), r = (int)(t / n);
+      R[(int)perm[i] + (int64_t)r * n] = rhs[i + (int64_t)r * n2];
+    }
+}
+
+// V from the logged rotations: V = J(1) J(2) ... applied to the identity; rows are independent, so
+// each workgroup replays every rotation on a slab of kReplayRows rows held in LDS, then writes the
+// columns in sorted order.
+constexpr int kReplayRows = 32;
+
+__global__ __launch_bounds__(256) void k_jacobi_replay(int n, int rows_per_block, const double* work, int64_t stride,
+                                                       int64_t log_off, double* Vs) {
+  extern __shared__ double vs[];
+  const int n2 = n + (n & 1), np = n2 / 2;
+  const int b = blockIdx.y;
+  const int r0 = blockIdx.x * rows_per_block;
+  const int rows = min(rows_per_block, n - r0);
+  const double* wk = work + (int64_t)b * stride;
+  const double* log = wk + log_off;
+  const double* perm = log + syev_log_count(n);
+  const int sweeps = (int)perm[n];
+  const int ld = n2 + 1;
+  for (int t = threadIdx.x; t < rows_per_block * ld; t += blockDim.x) {
+    int r = t / ld, c = t % ld;
+    vs[t] = (r < rows && c == r0 + r) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sw = 0; sw < sweeps; ++sw)
+    for (int round = 0; round < n2 - 1; ++round) {
+      const double* L = log + ((int64_t)sw * (n2 - 1) + round) * np * 2;
+      for (int t = threadIdx.x; t < rows * np; t += blockDim.x) {
+        int r = t % rows, k = t / rows;
+        double s = L[2 * k + 1];
+        if (s == 0.0) continue;
+        double c = L[2 * k];
+        int p = rr_player(k, round, n2), q = rr_player(n2 - 1 - k, round, n2);
+        if (p > q) { int x = p; p = q; q = x; }
+        double* v = vs + r * ld;
+        double vp = v[p], vq = v[q];
+        v[p] = c * vp - s * vq;
+        v[q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  double* V = Vs + (int64_t)b * n * n;
+  for (int t = threadIdx.x; t < rows * n; t += blockDim.x) {
+    int r = t % rows, col = t / rows;
+    V[(r0 + r) + (int64_t)((int)perm[col]) * n] = vs[r * ld + col];
   }
 }
 
-size_t syev_work_count(int n, int count) { return (size_t)n * n * count; }
-
-int syev_batched(double* A, double* w, double* V, int n, int count, double* work, hipStream_t s) {
+int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int n, int count, double* work,
+                 hipStream_t s) {
   if (n <= 0 || count <= 0) return RW_OK;
   RW_CHECK(n <= 1022, RW_EINVAL, "Jacobi eigensolver limited to n <= 1022 (got %d)", n);
-  k_jacobi<<<count, kJacobiThreads, 0, s>>>(A, w, V, work, n);
+  const bool vectors = V != nullptr;
+  const int nr = R ? nrhs : 0;
+  const bool glb = lds_bytes(n, nr) > kLdsLimit;
+  const int64_t stride = (int64_t)syev_stride(n, vectors, glb, nr);
+  if (glb) {
+    k_jacobi_glb<<<count, kJacobiThreads, 0, s>>>(A, n, w, R, nr, work, stride, vectors ? 1 : 0);
+  } else {
+    size_t sh = lds_bytes(n, R ? nrhs : 0);
+    static bool attr_set = false;
+    if (!attr_set) {
+      RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_lds),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+      attr_set = true;
+    }
+    k_jacobi_lds<<<count, kJacobiThreads, sh, s>>>(A, n, w, R, R ? nrhs : 0, work, stride, vectors ? 1 : 0);
+  }
   RW_LAUNCH_CHECK();
+  if (vectors) {
+    int n2 = n + (n & 1);
+    int rpb = (int)std::min<size_t>(kReplayRows, kLdsLimit / ((size_t)(n2 + 1) * sizeof(double)));
+    size_t sh = (size_t)rpb * (n2 + 1) * sizeof(double);
+    static bool attr2 = false;
+    if (!attr2) {
+      RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_replay),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+      attr2 = true;
+    }
+    dim3 grid((n + rpb - 1) / rpb, count);
+    int64_t log_off = glb ? (int64_t)n2 * n2 : 0;
+    k_jacobi_replay<<<grid, 256, sh, s>>>(n, rpb, work, stride, log_off, V);
+    RW_LAUNCH_CHECK();
+  }
   return RW_OK;
 }
 
@@ -275,3 +485,29 @@ int lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s)
 }
 
 }  // namespace rw
+
+using namespace rw;
+
+extern "C" {
+
+int rw_dense_syev_workspace_bytes(int n, int count, size_t* bytes) {
+  RW_CHECK(bytes != nullptr && n >= 1 && n <= 1022 && count >= 1, RW_EINVAL, "bad sizes");
+  *bytes = syev_work_count(n, count, true, 0) * sizeof(double);
+  return RW_OK;
+}
+
+int rw_dense_syev(const double* A, double* w, double* V, int n, int count, void* work, size_t work_bytes,
+                  hipStream_t stream) {
+  RW_CHECK(A != nullptr && w != nullptr && work != nullptr, RW_EINVAL, "null argument");
+  RW_CHECK(n >= 1 && n <= 1022 && count >= 1, RW_EINVAL, "bad sizes");
+  size_t need = syev_work_count(n, count, V != nullptr, 0) * sizeof(double);
+  RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "syev workspace too small: %zu < %zu", work_bytes, need);
+  return syev_batched(A, w, V, nullptr, 0, n, count, static_cast<double*>(work), stream);
+}
+
+int rw_dense_lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t stream) {
+  RW_CHECK(A != nullptr && B != nullptr && stat != nullptr && n >= 1 && nrhs >= 0, RW_EINVAL, "bad argument");
+  return lu_solve(A, n, B, nrhs, stat, stream);
+}
+
+}  // extern "C"

@@ -20,7 +20,7 @@ namespace rw {
 
 struct EigWork {
   char* B[4];
-  double *G, *V, *s, *W, *H, *T, *Hp, *Z, *WZ, *theta, *res, *jac, *tmp, *partial;
+  double *G, *G2, *V, *s, *W, *H, *T, *Hp, *Z, *WZ, *theta, *res, *syw, *tmp, *partial;
   int* info;
 };
 
@@ -37,7 +37,8 @@ static size_t eig_layout(const Graph* g, int nb, void* base, EigWork* w) {
   size_t n2 = (size_t)nb * nb;
   t.G = c.take<double>(n2); t.V = c.take<double>(n2); t.W = c.take<double>(n2); t.H = c.take<double>(n2);
   t.T = c.take<double>(n2); t.Hp = c.take<double>(n2); t.Z = c.take<double>(n2); t.WZ = c.take<double>(n2);
-  t.jac = c.take<double>(n2);
+  t.G2 = c.take<double>(n2);
+  t.syw = c.take<double>(syev_work_count(nb, 1, true, 0));
   t.s = c.take<double>(nb); t.theta = c.take<double>(nb); t.res = c.take<double>(nb);
   t.tmp = c.take<double>(std::max(nb, 16));
   size_t pc = std::max({gram_partial_count(g->N, nb, nb), norm_partial_count(nb), gram_partial_count(g->N, 1, nb)});
@@ -84,14 +85,32 @@ struct Ctx {
   double floor_rel;
 };
 
+__global__ void k_copy_d(const double* a, double* b, int64_t n) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < n) b[t] = a[t];
+}
+
 // One Rayleigh-Ritz step on the block F (nb columns).  Outputs X = F W Z, LX = op X, theta, res.
+// W makes F W orthonormal: W = R^{-1} from the Cholesky factor of G = F^T F (Cholesky QR), or, if
+// G is numerically singular, W = V s^{-1/2} from its eigendecomposition with small s floored.
 static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX) {
   const Graph* g = c.g;
   EigWork& w = c.w;
+  const int64_t n2 = (int64_t)nb * nb;
   RW_TRY(gram(c.dt, F, c.N, F, c.N, c.N, nb, nb, w.G, w.partial, c.s));
-  RW_TRY(syev_batched(w.G, w.s, w.V, nb, 1, w.jac, c.s));
-  k_scale_cols<<<nblocks((int64_t)nb * nb, 256), 256, 0, c.s>>>(w.V, w.s, w.W, nb, c.floor_rel);
+  k_copy_d<<<nblocks(n2, 256), 256, 0, c.s>>>(w.G, w.G2, n2);
   RW_LAUNCH_CHECK();
+  RW_TRY(chol_batched(w.G2, nb, 1, w.info, c.s));
+  int bad = 0;
+  RW_HIP(hipMemcpyAsync(&bad, w.info, sizeof(int), hipMemcpyDeviceToHost, c.s));
+  RW_HIP(hipStreamSynchronize(c.s));
+  if (bad == 0) {
+    RW_TRY(chol_upper_inverse(w.G2, w.W, nb, c.s));
+  } else {
+    RW_TRY(syev_batched(w.G, w.s, w.V, nullptr, 0, nb, 1, w.syw, c.s));
+    k_scale_cols<<<nblocks(n2, 256), 256, 0, c.s>>>(w.V, w.s, w.W, nb, c.floor_rel);
+    RW_LAUNCH_CHECK();
+  }
   RW_TRY(stencil_apply(g, F, LF, nullptr, nb, 1.0, 0.0, 0.0, c.s));
   c.spmm_cols += nb;
   RW_TRY(gram(c.dt, F, c.N, LF, c.N, c.N, nb, nb, w.H, w.partial, c.s));
@@ -99,7 +118,7 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX) {
   RW_TRY(gram(RW_F64, w.W, nb, w.T, nb, nb, nb, nb, w.Hp, w.partial, c.s));        // Hp = W^T H W
   k_symmetrize<<<nblocks((int64_t)nb * nb, 256), 256, 0, c.s>>>(w.Hp, nb);
   RW_LAUNCH_CHECK();
-  RW_TRY(syev_batched(w.Hp, w.theta, w.Z, nb, 1, w.jac, c.s));
+  RW_TRY(syev_batched(w.Hp, w.theta, w.Z, nullptr, 0, nb, 1, w.syw, c.s));
   RW_TRY(gemm_tn(RW_F64, w.W, nb, w.Z, nb, w.WZ, nb, nb, nb, nb, 0.0, c.s));      // WZ = W Z
   RW_TRY(gemm_tn(c.dt, F, c.N, w.WZ, nb, X, c.N, c.N, nb, nb, 0.0, c.s));        // X = F W Z
   RW_TRY(gemm_tn(c.dt, LF, c.N, w.WZ, nb, LX, c.N, c.N, nb, nb, 0.0, c.s));      // op X

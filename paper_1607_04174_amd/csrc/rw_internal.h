@@ -184,10 +184,12 @@ int project_out(int dt, void* X, int64_t ld, const void* v, int64_t rows, int co
 int chol_batched(double* A, int n, int count, int* info, hipStream_t s);
 // Rinv = (L^T)^{-1} (upper triangular) for the lower factor L; n x n
 int chol_upper_inverse(const double* L, double* Rinv, int n, hipStream_t s);
-// Symmetric eigendecomposition by cyclic Jacobi: A (n x n, destroyed) -> w (ascending),
-// V (n x n, columns = eigenvectors).  count matrices, strides n*n / n.
-int syev_batched(double* A, double* w, double* V, int n, int count, double* work, hipStream_t s);
-size_t syev_work_count(int n, int count);
+// Symmetric eigendecomposition (parallel cyclic Jacobi) of count matrices A (n x n, stride n*n, read
+// only): w (ascending, stride n); V (n x n eigenvectors, or null); R (n x nrhs per matrix, or null)
+// is replaced by V^T R.  work: syev_work_count doubles.
+int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int n, int count, double* work,
+                 hipStream_t s);
+size_t syev_work_count(int n, int count, bool vectors, int nrhs);
 // Solve A X = B by LU with partial pivoting (A: n x n, B: n x nrhs, both destroyed/overwritten;
 // X returned in B).  stat[0] = min |pivot| / max |a_ij| (0 if a pivot is below the threshold).
 int lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s);

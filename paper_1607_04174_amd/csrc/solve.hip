@@ -30,7 +30,10 @@ struct SolveWork {
   double* Gq;         // ma x ma  (Q_s^T Q_s)
   double* Gb;         // ma x C   (Q_s^T U_hat_s)
   double* fvals;      // kMaxCand x C
-  double* tr_scratch; // kMaxCand x C x (ms*ms + 4 ms)
+  double* fitA;       // kMaxCand x ms x ms  (ms = min(S, ma))
+  double* fitR;       // kMaxCand x ms x C
+  double* fitW;       // kMaxCand x ms
+  double* fitWork;    // Jacobi work
   double* K;          // ma x ma
   double* Y;          // ma x C
   double* stat;       // 8
@@ -53,7 +56,10 @@ static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base,
   t.Gq = c.take<double>((size_t)ma * ma);
   t.Gb = c.take<double>((size_t)ma * C);
   t.fvals = c.take<double>((size_t)kMaxCand * C);
-  t.tr_scratch = c.take<double>((size_t)kMaxCand * C * (ms * ms + 4 * ms));
+  t.fitA = c.take<double>((size_t)kMaxCand * ms * ms);
+  t.fitR = c.take<double>((size_t)kMaxCand * ms * C);
+  t.fitW = c.take<double>((size_t)kMaxCand * ms);
+  t.fitWork = c.take<double>(syev_work_count((int)ms, kMaxCand, false, C));
   t.K = c.take<double>((size_t)ma * ma);
   t.Y = c.take<double>((size_t)ma * C);
   t.stat = c.take<double>(8);
@@ -219,163 +225,109 @@ static int reconstruct(const Graph* g, const void* Q, int qdt, int m, const doub
 
 // ---------------------------------------------------------------------------------------------
 // Choice of m (Sec. III-A1): f_k(m) = min_{||a|| <= rho} ||Q_s[:, :m] a - b_k||^2.
-// One block per (candidate m, label).  With ms = min(S, m): for m <= S the m x m normal matrix
-// G = Q_s^T Q_s (leading block) with g = Q_s^T b; for m > S the S x S matrix P = Q_s Q_s^T over the
-// first m columns with b.  mu = 0 when the (minimum-norm) least-squares solution is feasible, else
-// the Hebden / More-Sorensen Newton iteration on 1/||a(mu)|| - 1/rho, one Cholesky per step.
+// Per candidate m, with ms = min(S, m): for m <= S the m x m normal matrix G = Q_s^T Q_s (leading
+// block) and g_k = Q_s^T b_k; for m > S the S x S matrix P = Q_s Q_s^T over the first m columns and
+// b_k.  One eigendecomposition per candidate (shared by the labels, right-hand sides rotated along)
+// turns the constrained problem into the secular equation ||a(mu)|| = rho in mu >= 0:
+//   m <= S:  ||a||^2 = sum g_i^2 / (w_i + mu)^2,     f = ||b||^2 - sum g_i^2 (w_i + 2 mu) / (w_i + mu)^2
+//   m >  S:  ||a||^2 = sum b_i^2 w_i / (w_i + mu)^2, f = sum b_i^2 mu^2 / (w_i + mu)^2
+// with (w_i) the eigenvalues and (g_i), (b_i) the rotated right-hand sides.  mu = 0 when the
+// minimum-norm least-squares fit is feasible, else bisection (geometric) to relative 1e-15.
+// Candidate matrices are zero-padded to a common size; padding adds w = 0 with zero right-hand side.
 // ---------------------------------------------------------------------------------------------
-__device__ bool blk_chol(double* A, int n, double shift) {
-  // lower Cholesky of (A + shift I) in place; returns false on a non-positive pivot
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (threadIdx.x == 0) {
-      double akk = A[k + (int64_t)k * n] + shift;
-      if (!(akk > 0.0) || !isfinite(akk)) bad = 1;
-      else A[k + (int64_t)k * n] = sqrt(akk);
-    }
-    __syncthreads();
-    if (bad) break;
-    const double piv = A[k + (int64_t)k * n];
-    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A[i + (int64_t)k * n] /= piv;
-    __syncthreads();
-    const int m = n - k - 1;
-    for (int64_t t = threadIdx.x; t < (int64_t)m * m; t += blockDim.x) {
-      int i = k + 1 + (int)(t % m), j = k + 1 + (int)(t / m);
-      if (i >= j) A[i + (int64_t)j * n] -= A[i + (int64_t)k * n] * A[j + (int64_t)k * n];
-    }
-    __syncthreads();
-  }
-  const bool ok = !bad;
-  __syncthreads();
-  return ok;
-}
-
-constexpr int kMaxFitDim = 512;   // largest min(S, m) the choice of m handles
-
-// x <- L^{-1} x (forward) or L^{-T} x (backward) with the lower factor L (global) and x in LDS.
-// Wave 0 does the work; every lane forms the full dot product by butterfly reduction and writes the
-// same x[i], so each lane only ever reads values it wrote itself.
-__device__ void blk_trsv(const double* L, int n, double* x, bool transpose) {
-  if (threadIdx.x < 64) {
-    if (!transpose) {
-      for (int i = 0; i < n; ++i) {
-        double acc = 0.0;
-        for (int k = threadIdx.x; k < i; k += 64) acc += L[i + (int64_t)k * n] * x[k];
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        x[i] = (x[i] - acc) / L[i + (int64_t)i * n];
-      }
-    } else {
-      for (int i = n - 1; i >= 0; --i) {
-        double acc = 0.0;
-        for (int k = i + 1 + threadIdx.x; k < n; k += 64) acc += L[k + (int64_t)i * n] * x[k];
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        x[i] = (x[i] - acc) / L[i + (int64_t)i * n];
-      }
-    }
-  }
-  __syncthreads();
-}
-
-__device__ double blk_dot(const double* a, const double* b, int n) {
-  __shared__ double red[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += a[i] * b[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  double r = red[0];
-  __syncthreads();
-  return r;
-}
-
-__global__ __launch_bounds__(256) void k_fit_seeds(const int* cand, int ncand, int C, int64_t S, int ma,
-                                                   const double* Qs, const double* Gq, const double* Gb,
-                                                   const double* Us, double rho, double* scratch,
-                                                   int64_t stride, double* fvals) {
-  const int ci = blockIdx.x, lab = blockIdx.y;
+__global__ void k_fit_build(const int* cand, int64_t S, int ma, int C, int ms, const double* Qs, const double* Gq,
+                            const double* Gb, const double* Us, double* A, double* R) {
+  const int ci = blockIdx.x;
   const int m = cand[ci];
-  const int ms = (int)std::min<int64_t>(S, m);
+  double* Ab = A + (int64_t)ci * ms * ms;
+  double* Rb = R + (int64_t)ci * ms * C;
+  if (m <= S) {
+    for (int64_t t = threadIdx.x; t < (int64_t)ms * ms; t += blockDim.x) {
+      int i = (int)(t % ms), j = (int)(t / ms);
+      Ab[t] = (i < m && j < m) ? Gq[i + (int64_t)j * ma] : 0.0;
+    }
+    for (int64_t t = threadIdx.x; t < (int64_t)ms * C; t += blockDim.x) {
+      int i = (int)(t % ms), k = (int)(t / ms);
+      Rb[t] = i < m ? Gb[i + (int64_t)k * ma] : 0.0;
+    }
+  } else {   // ms == S
+    for (int64_t t = threadIdx.x; t < (int64_t)ms * ms; t += blockDim.x) {
+      int i = (int)(t % ms), j = (int)(t / ms);
+      double acc = 0.0;
+      for (int c = 0; c < m; ++c) acc += Qs[i + (int64_t)c * S] * Qs[j + (int64_t)c * S];
+      Ab[t] = acc;
+    }
+    for (int64_t t = threadIdx.x; t < (int64_t)ms * C; t += blockDim.x) {
+      int i = (int)(t % ms), k = (int)(t / ms);
+      Rb[t] = Us[i + (int64_t)k * S];
+    }
+  }
+}
+
+__global__ void k_fit_secular(const int* cand, int ncand, int64_t S, int C, int ms, const double* W,
+                              const double* R, const double* Us, double rho, double* fvals) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncand * C) return;
+  const int ci = t % ncand, k = t / ncand;
+  const int m = cand[ci];
   const bool small_m = m <= S;
-  double* A = scratch + ((int64_t)lab * ncand + ci) * stride;   // ms x ms factor
-  __shared__ double rhs[kMaxFitDim], x[kMaxFitDim], y[kMaxFitDim];
-  // right-hand side: g = Q_s^T b (m <= S) or b (m > S); ||b||^2
-  for (int i = threadIdx.x; i < ms; i += blockDim.x)
-    rhs[i] = small_m ? Gb[i + (int64_t)lab * ma] : Us[i + (int64_t)lab * S];
-  __shared__ double bnorm2_s;
-  if (threadIdx.x == 0) {
+  const double* w = W + (int64_t)ci * ms;
+  const double* g = R + (int64_t)ci * ms * C + (int64_t)k * ms;
+  double bnorm2 = 0.0;
+  for (int64_t i = 0; i < S; ++i) bnorm2 += Us[i + (int64_t)k * S] * Us[i + (int64_t)k * S];
+  const double rho2 = rho * rho;
+  auto norm2 = [&](double mu) -> double {
     double acc = 0.0;
-    for (int64_t i = 0; i < S; ++i) acc += Us[i + (int64_t)lab * S] * Us[i + (int64_t)lab * S];
-    bnorm2_s = acc;
-  }
-  __syncthreads();
-  const double bnorm2 = bnorm2_s;
-  auto load_matrix = [&]() {
+    for (int i = 0; i < ms; ++i) {
+      double gi2 = g[i] * g[i];
+      if (gi2 == 0.0) continue;
+      double wi = fmax(w[i], 0.0);
+      double den = wi + mu;
+      if (den <= 0.0) return (double)INFINITY;
+      acc += small_m ? gi2 / (den * den) : gi2 * wi / (den * den);
+    }
+    return acc;
+  };
+  auto fval = [&](double mu) -> double {
+    double acc = 0.0;
     if (small_m) {
-      for (int64_t t = threadIdx.x; t < (int64_t)ms * ms; t += blockDim.x) {
-        int i = (int)(t % ms), j = (int)(t / ms);
-        A[t] = Gq[i + (int64_t)j * ma];
+      for (int i = 0; i < ms; ++i) {
+        double gi2 = g[i] * g[i];
+        if (gi2 == 0.0) continue;
+        double wi = fmax(w[i], 0.0), den = wi + mu;
+        acc += gi2 * (wi + 2.0 * mu) / (den * den);
       }
-    } else {
-      for (int64_t t = threadIdx.x; t < (int64_t)ms * ms; t += blockDim.x) {
-        int i = (int)(t % ms), j = (int)(t / ms);
-        double acc = 0.0;
-        for (int c = 0; c < m; ++c) acc += Qs[i + (int64_t)c * S] * Qs[j + (int64_t)c * S];
-        A[t] = acc;
-      }
+      return fmax(bnorm2 - acc, 0.0);
     }
-    __syncthreads();
-  };
-  // evaluate at mu: ||a||^2, D = -d||a||^2/dmu and f; false if the factorization fails
-  double na2 = 0.0, dd = 0.0, fv = 0.0;
-  auto eval = [&](double mu) -> bool {
-    load_matrix();
-    if (!blk_chol(A, ms, mu)) return false;
-    for (int i = threadIdx.x; i < ms; i += blockDim.x) x[i] = rhs[i];
-    __syncthreads();
-    blk_trsv(A, ms, x, false);
-    blk_trsv(A, ms, x, true);            // x = (M + mu I)^{-1} rhs
-    for (int i = threadIdx.x; i < ms; i += blockDim.x) y[i] = x[i];
-    __syncthreads();
-    blk_trsv(A, ms, y, false);           // y = L^{-1} x
-    double xx = blk_dot(x, x, ms), yy = blk_dot(y, y, ms), xr = blk_dot(x, rhs, ms);
-    if (small_m) {                        // x = alpha
-      na2 = xx;
-      dd = 2.0 * yy;
-      fv = bnorm2 - xr - mu * xx;
-    } else {                              // x = z with alpha = Q_s^T z
-      na2 = xr - mu * xx;
-      dd = 2.0 * (xx - mu * yy);
-      fv = mu * mu * xx;
+    for (int i = 0; i < ms; ++i) {
+      double gi2 = g[i] * g[i];
+      if (gi2 == 0.0) continue;
+      double wi = fmax(w[i], 0.0), den = wi + mu;
+      acc += den > 0.0 ? gi2 * (mu / den) * (mu / den) : gi2;
     }
-    if (fv < 0.0) fv = 0.0;
-    return true;
+    return acc;
   };
+  // min-norm fit at mu = 0 for m > S includes the null-space components of P in f
   double mu = 0.0;
-  bool ok = eval(0.0);
-  if (!ok || na2 > rho * rho) {
-    // Newton from the left of the root (monotone for this concave secular function)
-    if (!ok) {
-      load_matrix();
-      double tr = 0.0;
-      for (int i = 0; i < ms; ++i) tr += A[i + (int64_t)i * ms];
-      mu = 1e-13 * (tr / ms) + 1e-300;
-      ok = eval(mu);
+  if (!(norm2(0.0) <= rho2)) {
+    double gn = 0.0, wmax = 0.0;
+    for (int i = 0; i < ms; ++i) {
+      gn += g[i] * g[i];
+      wmax = fmax(wmax, w[i]);
     }
-    for (int it = 0; it < 100 && ok; ++it) {
-      double na = sqrt(na2);
-      if (fabs(na - rho) <= 1e-12 * rho || dd <= 0.0) break;
-      double step = 2.0 * na2 * (na - rho) / (rho * dd);
-      if (!(step > 0.0)) break;
-      mu += step;
-      ok = eval(mu);
+    double hi = small_m ? sqrt(gn) / rho : sqrt(fmax(wmax, 1e-300) * gn) / rho;
+    hi = fmax(hi, 1e-300);
+    while (norm2(hi) > rho2) hi *= 2.0;
+    double lo = 0.0;
+    for (int it = 0; it < 400 && hi - lo > 1e-15 * hi; ++it) {
+      double mid = lo > 0.0 ? sqrt(lo * hi) : 0.5 * hi;
+      if (mid <= lo || mid >= hi) mid = 0.5 * (lo + hi);
+      if (norm2(mid) > rho2) lo = mid;
+      else hi = mid;
     }
+    mu = hi;
   }
-  if (threadIdx.x == 0) fvals[ci + (int64_t)lab * ncand] = ok ? fv : INFINITY;
+  fvals[ci + (int64_t)k * ncand] = fval(mu);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -485,9 +437,8 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
     std::vector<int> cand;
     // candidate list lives in the first kMaxCand ints of the K buffer (unused until the final solve)
     int* cand_buf = reinterpret_cast<int*>(w.K);
-    const int64_t msmax = std::min<int64_t>(S, ma);
-    RW_CHECK(msmax <= kMaxFitDim, RW_EINVAL, "choice of m supports min(S, m_avail) <= %d", kMaxFitDim);
-    const int64_t stride = msmax * msmax + 4 * msmax;
+    const int msmax = (int)std::min<int64_t>(S, ma);
+    RW_CHECK(msmax <= 1022, RW_EINVAL, "choice of m supports min(S, m_avail) <= 1022");
     std::vector<std::pair<int, double>> evaluated;
     while (hi - lo > 1) {
       cand.clear();
@@ -500,8 +451,11 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
       }
       int ncand = (int)cand.size();
       RW_HIP(hipMemcpyAsync(cand_buf, cand.data(), ncand * sizeof(int), hipMemcpyHostToDevice, stream));
-      k_fit_seeds<<<dim3(ncand, C), 256, 0, stream>>>(cand_buf, ncand, C, S, ma, w.Qs, w.Gq, w.Gb, w.Us, rho,
-                                                      w.tr_scratch, stride, w.fvals);
+      k_fit_build<<<ncand, 256, 0, stream>>>(cand_buf, S, ma, C, msmax, w.Qs, w.Gq, w.Gb, w.Us, w.fitA, w.fitR);
+      RW_LAUNCH_CHECK();
+      RW_TRY(syev_batched(w.fitA, w.fitW, nullptr, w.fitR, C, msmax, ncand, w.fitWork, stream));
+      k_fit_secular<<<nblocks(ncand * C, 64), 64, 0, stream>>>(cand_buf, ncand, S, C, msmax, w.fitW, w.fitR, w.Us,
+                                                                rho, w.fvals);
       RW_LAUNCH_CHECK();
       RW_HIP(hipMemcpyAsync(fh.data(), w.fvals, (size_t)ncand * C * sizeof(double), hipMemcpyDeviceToHost, stream));
       RW_HIP(hipStreamSynchronize(stream));
