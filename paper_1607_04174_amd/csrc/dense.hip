@@ -10,26 +10,27 @@ namespace rw {
 // ---------------------------------------------------------------------------------------------
 // Cholesky A = L L^T (lower, in place; the strict upper triangle is left untouched)
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_chol(double* As, int n, int* info) {
+__global__ __launch_bounds__(1024) void k_chol(double* As, int n, int* info) {
   double* A = As + (int64_t)blockIdx.x * n * n;
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int k = 0; k < n; ++k) {
     if (threadIdx.x == 0) {
-      double akk = A[k + (int64_t)k * n];
+      double akk = A[k + k * n];
       if (!(akk > 0.0) || !isfinite(akk)) bad = k + 1;
-      else A[k + (int64_t)k * n] = sqrt(akk);
+      else A[k + k * n] = sqrt(akk);
     }
     __syncthreads();
     if (bad) break;
-    const double piv = A[k + (int64_t)k * n];
-    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A[i + (int64_t)k * n] /= piv;
+    const double piv = A[k + k * n];
+    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) A[i + k * n] /= piv;
     __syncthreads();
-    const int m = n - k - 1;
-    for (int64_t t = threadIdx.x; t < (int64_t)m * m; t += blockDim.x) {
-      int i = k + 1 + (int)(t % m), j = k + 1 + (int)(t / m);
-      if (i >= j) A[i + (int64_t)j * n] -= A[i + (int64_t)k * n] * A[j + (int64_t)k * n];
+    // trailing lower triangle: rows i >= j > k
+    for (int j = k + 1 + ty; j < n; j += 32) {
+      const double ljk = A[j + k * n];
+      for (int i = j + tx; i < n; i += 32) A[i + j * n] -= A[i + k * n] * ljk;
     }
     __syncthreads();
   }
@@ -38,29 +39,34 @@ __global__ __launch_bounds__(256) void k_chol(double* As, int n, int* info) {
 
 int chol_batched(double* A, int n, int count, int* info, hipStream_t s) {
   if (n <= 0 || count <= 0) return RW_OK;
-  k_chol<<<count, 256, 0, s>>>(A, n, info);
+  k_chol<<<count, 1024, 0, s>>>(A, n, info);
   RW_LAUNCH_CHECK();
   return RW_OK;
 }
 
-// Rinv = (L^T)^{-1}: thread j back-substitutes column j of the upper-triangular inverse.
-__global__ void k_upper_inverse(const double* L, double* Rinv, int n) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
+// Rinv = (L^T)^{-1}: one wave back-substitutes column j of the upper-triangular inverse; each step's
+// dot product is a butterfly reduction, so every lane obtains every x_i.
+__global__ __launch_bounds__(256) void k_upper_inverse(const double* L, double* Rinv, int n) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (j >= n) return;
   double* x = Rinv + (int64_t)j * n;
-  for (int i = n - 1; i > j; --i) x[i] = 0.0;
+  for (int i = j + 1 + lane; i < n; i += 64) x[i] = 0.0;
   // R(i,k) = L(k,i) = L[k + i*n]
-  x[j] = 1.0 / L[j + (int64_t)j * n];
+  const double xj = 1.0 / L[j + j * n];
+  if (lane == 0) x[j] = xj;
   for (int i = j - 1; i >= 0; --i) {
     double acc = 0.0;
-    for (int k = i + 1; k <= j; ++k) acc += L[k + (int64_t)i * n] * x[k];
-    x[i] = -acc / L[i + (int64_t)i * n];
+    for (int k = i + 1 + lane; k <= j; k += 64) acc += L[k + i * n] * (k == j ? xj : x[k]);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    // every lane holds the same xi and stores it, so a lane's later read of x[i] follows its own store
+    x[i] = -acc / L[i + i * n];
   }
 }
 
 int chol_upper_inverse(const double* L, double* Rinv, int n, hipStream_t s) {
   if (n <= 0) return RW_OK;
-  k_upper_inverse<<<nblocks(n, 64), 64, 0, s>>>(L, Rinv, n);
+  k_upper_inverse<<<(n + 3) / 4, 256, 0, s>>>(L, Rinv, n);
   RW_LAUNCH_CHECK();
   return RW_OK;
 }
@@ -84,24 +90,36 @@ __device__ __forceinline__ int rr_player(int pos, int round, int n2) {
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n2 - 1);
 }
 
+// Workgroup barrier that orders only LDS traffic: it does not wait for outstanding global stores
+// (used where waves exchange data through LDS alone; global writes there are never read back
+// inside the kernel).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 struct LdsStore {   // packed upper triangle in LDS
+  static constexpr bool kLdsOnly = true;
+  __device__ static void sync() { lds_barrier(); }
   double* a;
-  __device__ __forceinline__ int64_t at(int i, int j) const {
-    if (i > j) { int t = i; i = j; j = t; }
-    return (int64_t)j * (j + 1) / 2 + i;
+  __device__ __forceinline__ int at(int i, int j) const {
+    int lo = i < j ? i : j, hi = i < j ? j : i;
+    return (hi * (hi + 1) >> 1) + lo;
   }
   __device__ __forceinline__ double ld(int i, int j) const { return a[at(i, j)]; }
-  __device__ __forceinline__ void st(int i, int j, double v) const { a[at(i, j)] = v; }
   __device__ __forceinline__ void st_sym(int i, int j, double v) const { a[at(i, j)] = v; }
 };
 
 struct GlbStore {   // full n2 x n2 column-major copy in global memory
+  static constexpr bool kLdsOnly = false;
+  __device__ static void sync() { __syncthreads(); }
   double* a;
   int n2;
-  __device__ __forceinline__ double ld(int i, int j) const { return a[i + (int64_t)j * n2]; }
+  __device__ __forceinline__ double ld(int i, int j) const { return a[i + j * n2]; }
   __device__ __forceinline__ void st_sym(int i, int j, double v) const {
-    a[i + (int64_t)j * n2] = v;
-    a[j + (int64_t)i * n2] = v;
+    a[i + j * n2] = v;
+    a[j + i * n2] = v;
   }
 };
 
@@ -139,19 +157,25 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
   // Frobenius norm (one wave, fixed order) for the absolute threshold
   if (threadIdx.x < 64) {
     double acc = 0.0;
-    for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += 64) {
-      double v = S.ld((int)(t % n), (int)(t / n));
-      acc += v * v;
-    }
+    for (int j = 0; j < n; ++j)
+      for (int i = threadIdx.x; i < n; i += 64) {
+        double v = S.ld(i, j);
+        acc += v * v;
+      }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (threadIdx.x == 0) fro_s = sqrt(acc);
   }
-  __syncthreads();
-  const double abs_tiny = fro_s * 1e-16 + 1e-300;
+  Store::sync();
+  // thresholds: rounding noise regenerates off-diagonal entries of size ~eps |A|, so rotations below
+  // sqrt(n) eps relative to the diagonal, or eps |A|_F absolute, are skipped; a sweep without
+  // rotations ends the iteration
+  const double abs_tiny = fro_s * 2.3e-16 + 1e-300;
+  const double rel_tol = 2.3e-16 * sqrt((double)n) * 2.0;
+  const int ta = threadIdx.x & 31, tb = threadIdx.x >> 5;   // 32 x 32 thread grid over pair blocks
   int sweep = 0;
   for (; sweep < kJacobiMaxSweeps; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
-    __syncthreads();
+    Store::sync();
     for (int round = 0; round < n2 - 1; ++round) {
       for (int k = threadIdx.x; k < np; k += blockDim.x) {
         int p = rr_player(k, round, n2), q = rr_player(n2 - 1 - k, round, n2);
@@ -159,7 +183,7 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
         double c = 1.0, s = 0.0;
         if (q < n) {
           double apq = S.ld(p, q), app = S.ld(p, p), aqq = S.ld(q, q);
-          if (fabs(apq) > abs_tiny && fabs(apq) > 1e-15 * sqrt(fabs(app) * fabs(aqq))) {
+          if (fabs(apq) > abs_tiny && fabs(apq) > rel_tol * sqrt(fabs(app) * fabs(aqq))) {
             double tau = (aqq - app) / (2.0 * apq);
             double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
@@ -175,50 +199,79 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
         pq[2 * k] = p;
         pq[2 * k + 1] = q;
         if (log) {
-          double* L = log + (((int64_t)sweep * (n2 - 1) + round) * np + k) * 2;
+          double* L = log + ((size_t)(sweep * (n2 - 1) + round) * np + k) * 2;
           L[0] = c;
           L[1] = s;
         }
       }
-      __syncthreads();
-      // off-diagonal 2 x 2 blocks (pair k1 < pair k2) and right-hand sides
-      const int64_t nblk = (int64_t)np * np;
-      for (int64_t t = threadIdx.x; t < nblk; t += blockDim.x) {
-        int k1 = (int)(t % np), k2 = (int)(t / np);
-        if (k1 >= k2) continue;
-        double s1 = sn[k1], s2 = sn[k2];
-        if (s1 == 0.0 && s2 == 0.0) continue;
-        double c1 = cs[k1], c2 = cs[k2];
-        int p1 = pq[2 * k1], q1 = pq[2 * k1 + 1], p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
-        if (q1 >= n) { s1 = 0.0; c1 = 1.0; }
-        if (q2 >= n) { s2 = 0.0; c2 = 1.0; }
-        double b00 = S.ld(p1, p2), b01 = q2 < n ? S.ld(p1, q2) : 0.0;
-        double b10 = q1 < n ? S.ld(q1, p2) : 0.0, b11 = (q1 < n && q2 < n) ? S.ld(q1, q2) : 0.0;
-        // rows: J1^T B
-        double r00 = c1 * b00 - s1 * b10, r01 = c1 * b01 - s1 * b11;
-        double r10 = s1 * b00 + c1 * b10, r11 = s1 * b01 + c1 * b11;
-        // columns: (J1^T B) J2
-        S.st_sym(p1, p2, c2 * r00 - s2 * r01);
-        if (q2 < n) S.st_sym(p1, q2, s2 * r00 + c2 * r01);
-        if (q1 < n) S.st_sym(q1, p2, c2 * r10 - s2 * r11);
-        if (q1 < n && q2 < n) S.st_sym(q1, q2, s2 * r10 + c2 * r11);
+      Store::sync();
+      // off-diagonal 2 x 2 blocks of pairs k1 < k2 on a 32 x 32 thread grid: a thread's pairs k1
+      // (ta, ta + 32, ...) are read from LDS once per round; the pair k2 is shared by the 32 lanes of
+      // a half-wave.  Loads of up to four blocks are issued before their stores so that memory
+      // latency overlaps.
+      {
+        constexpr int KMAX = 16;                 // np <= 511
+        double c1v[KMAX], s1v[KMAX];
+        int p1v[KMAX], q1v[KMAX];
+        int nk1 = 0;
+        for (int k1 = ta; k1 < np && nk1 < KMAX; k1 += 32, ++nk1) {
+          c1v[nk1] = cs[k1];
+          s1v[nk1] = sn[k1];
+          p1v[nk1] = pq[2 * k1];
+          q1v[nk1] = pq[2 * k1 + 1];
+        }
+        for (int k2 = tb; k2 < np; k2 += 32) {
+          const double c2 = cs[k2], s2 = sn[k2];
+          const int p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
+          double bv[4][4];
+          int idx[4];
+          int cnt = 0;
+          auto flush = [&]() {
+            for (int u = 0; u < cnt; ++u) {
+              const int j = idx[u];
+              const double c1 = c1v[j], s1 = s1v[j];
+              const int p1 = p1v[j], q1 = q1v[j];
+              const double b00 = bv[u][0], b01 = bv[u][1], b10 = bv[u][2], b11 = bv[u][3];
+              const double r00 = c1 * b00 - s1 * b10, r01 = c1 * b01 - s1 * b11;   // rows: J1^T B
+              const double r10 = s1 * b00 + c1 * b10, r11 = s1 * b01 + c1 * b11;
+              S.st_sym(p1, p2, c2 * r00 - s2 * r01);                              // columns: (J1^T B) J2
+              if (q2 < n) S.st_sym(p1, q2, s2 * r00 + c2 * r01);
+              if (q1 < n) S.st_sym(q1, p2, c2 * r10 - s2 * r11);
+              if (q1 < n && q2 < n) S.st_sym(q1, q2, s2 * r10 + c2 * r11);
+            }
+            cnt = 0;
+          };
+          for (int j = 0; j < nk1; ++j) {
+            const int k1 = ta + 32 * j;
+            if (k1 >= k2) break;
+            if (s1v[j] == 0.0 && s2 == 0.0) continue;
+            const int p1 = p1v[j], q1 = q1v[j];
+            idx[cnt] = j;
+            bv[cnt][0] = S.ld(p1, p2);
+            bv[cnt][1] = q2 < n ? S.ld(p1, q2) : 0.0;
+            bv[cnt][2] = q1 < n ? S.ld(q1, p2) : 0.0;
+            bv[cnt][3] = (q1 < n && q2 < n) ? S.ld(q1, q2) : 0.0;
+            if (++cnt == 4) flush();
+          }
+          flush();
+        }
       }
       if (rhs) {
-        for (int64_t t = threadIdx.x; t < (int64_t)np * nrhs; t += blockDim.x) {
-          int k = (int)(t % np), r = (int)(t / np);
+        for (int t = threadIdx.x; t < np * nrhs; t += blockDim.x) {
+          int k = t % np, r = t / np;
           double s = sn[k];
           if (s == 0.0) continue;
           double c = cs[k];
           int p = pq[2 * k], q = pq[2 * k + 1];
-          double vp = rhs[p + (int64_t)r * n2], vq = rhs[q + (int64_t)r * n2];
-          rhs[p + (int64_t)r * n2] = c * vp - s * vq;
-          rhs[q + (int64_t)r * n2] = s * vp + c * vq;
+          double vp = rhs[p + r * n2], vq = rhs[q + r * n2];
+          rhs[p + r * n2] = c * vp - s * vq;
+          rhs[q + r * n2] = s * vp + c * vq;
         }
       }
-      __syncthreads();
+      Store::sync();
     }
     const int any = rotated;
-    __syncthreads();
+    Store::sync();
     if (!any) { ++sweep; break; }
   }
   // eigenvalues ascending (stable by index); perm[i] = sorted position of index i
@@ -307,6 +360,7 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_glb(const double* As,
 // each workgroup replays every rotation on a slab of kReplayRows rows held in LDS, then writes the
 // columns in sorted order.
 constexpr int kReplayRows = 32;
+constexpr int kReplayStage = 8;   // rounds of rotations staged in LDS per barrier pair
 
 __global__ __launch_bounds__(256) void k_jacobi_replay(int n, int rows_per_block, const double* work, int64_t stride,
                                                        int64_t log_off, double* Vs) {
@@ -320,28 +374,44 @@ __global__ __launch_bounds__(256) void k_jacobi_replay(int n, int rows_per_block
   const double* perm = log + syev_log_count(n);
   const int sweeps = (int)perm[n];
   const int ld = n2 + 1;
+  double* stage = vs + rows_per_block * ld;        // kReplayStage x np x (c, s)
+  int* spq = reinterpret_cast<int*>(stage + kReplayStage * np * 2);   // kReplayStage x np x (p, q)
   for (int t = threadIdx.x; t < rows_per_block * ld; t += blockDim.x) {
-    int r = t / ld, c = t % ld;
+    int r = t / ld, c = t - r * ld;
     vs[t] = (r < rows && c == r0 + r) ? 1.0 : 0.0;
   }
-  __syncthreads();
-  for (int sw = 0; sw < sweeps; ++sw)
-    for (int round = 0; round < n2 - 1; ++round) {
-      const double* L = log + ((int64_t)sw * (n2 - 1) + round) * np * 2;
-      for (int t = threadIdx.x; t < rows * np; t += blockDim.x) {
-        int r = t % rows, k = t / rows;
+  const int total_rounds = sweeps * (n2 - 1);
+  for (int g0 = 0; g0 < total_rounds; g0 += kReplayStage) {
+    const int ng = min(kReplayStage, total_rounds - g0);
+    lds_barrier();
+    for (int t = threadIdx.x; t < ng * np * 2; t += blockDim.x) stage[t] = log[(size_t)g0 * np * 2 + t];
+    for (int t = threadIdx.x; t < ng * np; t += blockDim.x) {
+      int gi = t / np, k = t - gi * np;
+      int round = (g0 + gi) % (n2 - 1);
+      int p = rr_player(k, round, n2), q = rr_player(n2 - 1 - k, round, n2);
+      spq[2 * t] = p < q ? p : q;
+      spq[2 * t + 1] = p < q ? q : p;
+    }
+    lds_barrier();
+    for (int gi = 0; gi < ng; ++gi) {
+      const double* L = stage + gi * np * 2;
+      const int* PQ = spq + gi * np * 2;
+      for (int t = threadIdx.x; t < kReplayRows * np; t += blockDim.x) {
+        int r = t & (kReplayRows - 1), k = t >> 5;
+        if (r >= rows) continue;
         double s = L[2 * k + 1];
         if (s == 0.0) continue;
         double c = L[2 * k];
-        int p = rr_player(k, round, n2), q = rr_player(n2 - 1 - k, round, n2);
-        if (p > q) { int x = p; p = q; q = x; }
+        int p = PQ[2 * k], q = PQ[2 * k + 1];
         double* v = vs + r * ld;
         double vp = v[p], vq = v[q];
         v[p] = c * vp - s * vq;
         v[q] = s * vp + c * vq;
       }
-      __syncthreads();
+      lds_barrier();
     }
+  }
+  lds_barrier();
   double* V = Vs + (int64_t)b * n * n;
   for (int t = threadIdx.x; t < rows * n; t += blockDim.x) {
     int r = t % rows, col = t / rows;
@@ -372,8 +442,9 @@ int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int
   RW_LAUNCH_CHECK();
   if (vectors) {
     int n2 = n + (n & 1);
-    int rpb = (int)std::min<size_t>(kReplayRows, kLdsLimit / ((size_t)(n2 + 1) * sizeof(double)));
-    size_t sh = (size_t)rpb * (n2 + 1) * sizeof(double);
+    const size_t stage_bytes = (size_t)kReplayStage * (n2 / 2) * 2 * (sizeof(double) + sizeof(int));
+    int rpb = (int)std::min<size_t>(kReplayRows, (kLdsLimit - stage_bytes) / ((size_t)(n2 + 1) * sizeof(double)));
+    size_t sh = (size_t)rpb * (n2 + 1) * sizeof(double) + stage_bytes;
     static bool attr2 = false;
     if (!attr2) {
       RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_replay),

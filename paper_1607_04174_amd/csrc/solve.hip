@@ -264,58 +264,61 @@ __global__ void k_fit_build(const int* cand, int64_t S, int ma, int C, int ms, c
   }
 }
 
-__global__ void k_fit_secular(const int* cand, int ncand, int64_t S, int C, int ms, const double* W,
-                              const double* R, const double* Us, double rho, double* fvals) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ncand * C) return;
-  const int ci = t % ncand, k = t / ncand;
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// one wave per (candidate, label); lane-parallel sums reduced by butterflies, so all lanes agree
+__global__ __launch_bounds__(64) void k_fit_secular(const int* cand, int ncand, int64_t S, int C, int ms,
+                                                    const double* W, const double* R, const double* Us, double rho,
+                                                    double* fvals) {
+  const int ci = blockIdx.x, k = blockIdx.y;
+  const int lane = threadIdx.x;
   const int m = cand[ci];
   const bool small_m = m <= S;
   const double* w = W + (int64_t)ci * ms;
   const double* g = R + (int64_t)ci * ms * C + (int64_t)k * ms;
-  double bnorm2 = 0.0;
-  for (int64_t i = 0; i < S; ++i) bnorm2 += Us[i + (int64_t)k * S] * Us[i + (int64_t)k * S];
+  double bn = 0.0;
+  for (int64_t i = lane; i < S; i += 64) bn += Us[i + (int64_t)k * S] * Us[i + (int64_t)k * S];
+  const double bnorm2 = wave_sum(bn);
   const double rho2 = rho * rho;
   auto norm2 = [&](double mu) -> double {
     double acc = 0.0;
-    for (int i = 0; i < ms; ++i) {
-      double gi2 = g[i] * g[i];
-      if (gi2 == 0.0) continue;
-      double wi = fmax(w[i], 0.0);
-      double den = wi + mu;
-      if (den <= 0.0) return (double)INFINITY;
-      acc += small_m ? gi2 / (den * den) : gi2 * wi / (den * den);
-    }
-    return acc;
-  };
-  auto fval = [&](double mu) -> double {
-    double acc = 0.0;
-    if (small_m) {
-      for (int i = 0; i < ms; ++i) {
-        double gi2 = g[i] * g[i];
-        if (gi2 == 0.0) continue;
-        double wi = fmax(w[i], 0.0), den = wi + mu;
-        acc += gi2 * (wi + 2.0 * mu) / (den * den);
-      }
-      return fmax(bnorm2 - acc, 0.0);
-    }
-    for (int i = 0; i < ms; ++i) {
+    int inf = 0;
+    for (int i = lane; i < ms; i += 64) {
       double gi2 = g[i] * g[i];
       if (gi2 == 0.0) continue;
       double wi = fmax(w[i], 0.0), den = wi + mu;
-      acc += den > 0.0 ? gi2 * (mu / den) * (mu / den) : gi2;
+      if (den <= 0.0) { inf = 1; continue; }
+      acc += small_m ? gi2 / (den * den) : gi2 * wi / (den * den);
     }
-    return acc;
+    double tot = wave_sum(acc);
+    double anyinf = wave_sum((double)inf);
+    return anyinf > 0.0 ? (double)INFINITY : tot;
   };
-  // min-norm fit at mu = 0 for m > S includes the null-space components of P in f
+  auto fval = [&](double mu) -> double {
+    double acc = 0.0;
+    for (int i = lane; i < ms; i += 64) {
+      double gi2 = g[i] * g[i];
+      if (gi2 == 0.0) continue;
+      double wi = fmax(w[i], 0.0), den = wi + mu;
+      if (small_m) acc += gi2 * (wi + 2.0 * mu) / (den * den);
+      else acc += den > 0.0 ? gi2 * (mu / den) * (mu / den) : gi2;
+    }
+    double tot = wave_sum(acc);
+    return small_m ? fmax(bnorm2 - tot, 0.0) : tot;
+  };
   double mu = 0.0;
   if (!(norm2(0.0) <= rho2)) {
-    double gn = 0.0, wmax = 0.0;
-    for (int i = 0; i < ms; ++i) {
+    double gn = 0.0, wm = 0.0;
+    for (int i = lane; i < ms; i += 64) {
       gn += g[i] * g[i];
-      wmax = fmax(wmax, w[i]);
+      wm = fmax(wm, w[i]);
     }
-    double hi = small_m ? sqrt(gn) / rho : sqrt(fmax(wmax, 1e-300) * gn) / rho;
+    gn = wave_sum(gn);
+    for (int o = 32; o > 0; o >>= 1) wm = fmax(wm, __shfl_xor(wm, o));
+    double hi = small_m ? sqrt(gn) / rho : sqrt(fmax(wm, 1e-300) * gn) / rho;
     hi = fmax(hi, 1e-300);
     while (norm2(hi) > rho2) hi *= 2.0;
     double lo = 0.0;
@@ -327,7 +330,8 @@ __global__ void k_fit_secular(const int* cand, int ncand, int64_t S, int C, int 
     }
     mu = hi;
   }
-  fvals[ci + (int64_t)k * ncand] = fval(mu);
+  const double f = fval(mu);
+  if (lane == 0) fvals[ci + (int64_t)k * ncand] = f;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -454,8 +458,8 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
       k_fit_build<<<ncand, 256, 0, stream>>>(cand_buf, S, ma, C, msmax, w.Qs, w.Gq, w.Gb, w.Us, w.fitA, w.fitR);
       RW_LAUNCH_CHECK();
       RW_TRY(syev_batched(w.fitA, w.fitW, nullptr, w.fitR, C, msmax, ncand, w.fitWork, stream));
-      k_fit_secular<<<nblocks(ncand * C, 64), 64, 0, stream>>>(cand_buf, ncand, S, C, msmax, w.fitW, w.fitR, w.Us,
-                                                                rho, w.fvals);
+      k_fit_secular<<<dim3(ncand, C), 64, 0, stream>>>(cand_buf, ncand, S, C, msmax, w.fitW, w.fitR, w.Us, rho,
+                                                        w.fvals);
       RW_LAUNCH_CHECK();
       RW_HIP(hipMemcpyAsync(fh.data(), w.fvals, (size_t)ncand * C * sizeof(double), hipMemcpyDeviceToHost, stream));
       RW_HIP(hipStreamSynchronize(stream));
