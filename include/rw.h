@@ -233,6 +233,41 @@ int rw_cg_solve(rw_graph g, const int64_t* seed_node, const int32_t* seed_label,
                 double tol, int max_iter, int x0_given, double* U, void* work, size_t work_bytes,
                 hipStream_t stream, rw_cg_info* info);
 
+/* Same solver for an explicit right-hand side: L_n X_n = B_n (B: device C x N FP64, its seed rows are
+ * ignored); X (device C x N FP64) is zero on the seed rows on exit, and its non-seed entries are the
+ * initial guess when x0_given != 0.  Used for the adjoint system of the gradient form. */
+int rw_cg_solve_rhs(rw_graph g, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C,
+                    const double* B, double tol, int max_iter, int x0_given, double* X, void* work,
+                    size_t work_bytes, hipStream_t stream, rw_cg_info* info);
+
+/* ======================================================================================
+ * Differentiation of the exact random walker (adjoint of Sec. II-A eq. (5), gamma = 0)
+ * ====================================================================================== */
+
+/* Replace the per-edge scales s_e (device ndir x N, graph dtype; entries of absent edges are ignored;
+ * s_e >= 0 is the caller's responsibility) and rebuild the weights w_e = s_e exp(...). */
+int rw_graph_set_scale(rw_graph g, const void* scale, hipStream_t stream);
+
+int rw_grad_workspace_bytes(rw_graph g, size_t* bytes);
+
+/* Given the exact solution U (device C x N FP64) and the adjoint A = L_n^{-1} G (device C x N FP64, zero
+ * on seeds) of a loss gradient G = dl/dU, write (all device FP64):
+ *   dw (ndir x N): dl/dw_e = -sum_k (a_i^k - a_j^k)(u_i^k - u_j^k) for each present edge e = (i, j), 0 elsewhere;
+ *   ds (ndir x N): dl/ds_e = dl/dw_e exp(-beta f(J_i - J_j));
+ *   dJ (N): dl/dJ through every incident edge;   dbeta (1): dl/dbeta.
+ * Needs an FP64 graph.  Fixed-order reductions: the results are bitwise reproducible. */
+int rw_grad_edges(rw_graph g, const double* U, const double* A, int C, double* dw, double* dJ, double* dbeta,
+                  double* ds, void* work, size_t work_bytes, hipStream_t stream);
+
+int rw_spectral_workspace_bytes(rw_graph g, int m, int C, size_t* bytes);
+
+/* Truncated spectral approximation of the operator's pseudo-inverse applied to B (device C x N FP64):
+ * X = S Q' Lambda'^{-1} Q'^T S B with Q' = columns 1..m-1 of Q (device column-major N x m FP64, column
+ * 0 the null vector), S = D^{-1/2} (normalized graph) or I.  Used as the starting point of adjoint
+ * solves, reusing the precomputed eigenbasis. */
+int rw_spectral_apply(rw_graph g, const double* Q, const double* lambda, int m, const double* B, int C,
+                      double* X, void* work, size_t work_bytes, hipStream_t stream);
+
 /* ======================================================================================
  * Dense FP64 building blocks used by the steps above (exposed for testing and reuse)
  * ====================================================================================== */

@@ -102,6 +102,16 @@ _SIGS = {
                                  ct.c_void_p]),
     "rw_dense_lu_solve": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p]),
     "rw_cg_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_cg_solve_rhs": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int, ct.c_void_p, ct.c_double,
+                                   ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p,
+                                   ct.POINTER(rw_cg_info)]),
+    "rw_graph_set_scale": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "rw_grad_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_size_t)]),
+    "rw_grad_edges": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p,
+                                 ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p]),
+    "rw_spectral_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_spectral_apply": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int,
+                                     ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "rw_cg_solve": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int, ct.c_double, ct.c_int,
                                ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p,
                                ct.POINTER(rw_cg_info)]),
@@ -393,3 +403,102 @@ def dense_lu_solve(A: torch.Tensor, B: torch.Tensor):
     stat = torch.empty(1, dtype=torch.float64, device=A.device)
     _check(lib().rw_dense_lu_solve(_ptr(A), n, _ptr(X), nrhs, _ptr(stat), _stream(A.device)))
     return X, float(stat.item())
+
+
+# ---------------------------------------------------------------------------------------------
+# differentiation of the exact random walker
+# ---------------------------------------------------------------------------------------------
+def cg_solve_rhs(g: Graph, seed_node, seed_label, C: int, B: torch.Tensor, tol: float = 1e-12,
+                 max_iter: int = 100000, X0: Optional[torch.Tensor] = None, raise_on_noconv: bool = True):
+    """Solve L_n X_n = B_n (X zero on seeds).  B, X: (C, N) float64.  Returns (X, info)."""
+    nodes = np.ascontiguousarray(np.asarray(seed_node, dtype=np.int64))
+    labels = np.ascontiguousarray(np.asarray(seed_label, dtype=np.int32))
+    B = B.to(torch.float64).contiguous()
+    X = X0.to(torch.float64).contiguous().clone() if X0 is not None else torch.empty_like(B)
+    nb = ct.c_size_t()
+    _check(lib().rw_cg_workspace_bytes(g.handle, C, ct.byref(nb)))
+    work = _workspace(nb.value, g.device)
+    info = rw_cg_info()
+    st = lib().rw_cg_solve_rhs(g.handle, ct.c_void_p(nodes.ctypes.data), ct.c_void_p(labels.ctypes.data), nodes.size,
+                               C, _ptr(B), float(tol), int(max_iter), 1 if X0 is not None else 0, _ptr(X), _ptr(work),
+                               nb.value, _stream(g.device), ct.byref(info))
+    if st != RW_OK and not (st == RW_ENOCONV and not raise_on_noconv):
+        _check(st)
+    return X, {"iters": info.iters, "rel_residual": info.rel_residual, "status": st}
+
+
+def graph_set_scale(g: Graph, scale: torch.Tensor) -> None:
+    scale = scale.to(g.dtype).contiguous()
+    _check(lib().rw_graph_set_scale(g.handle, _ptr(scale), _stream(g.device)))
+
+
+def grad_edges(g: Graph, U: torch.Tensor, A: torch.Tensor):
+    """(dw (ndir, N), dJ (N,), dbeta (scalar tensor), ds (ndir, N)) for the exact solution U and adjoint A."""
+    C = U.shape[0]
+    nd = {(2, 4): 2, (2, 8): 4, (3, 6): 3}[(g.ndim, g.conn)]
+    dw = torch.empty((nd, g.N), dtype=torch.float64, device=g.device)
+    ds = torch.empty_like(dw)
+    dJ = torch.empty(g.N, dtype=torch.float64, device=g.device)
+    db = torch.empty((), dtype=torch.float64, device=g.device)
+    nb = ct.c_size_t()
+    _check(lib().rw_grad_workspace_bytes(g.handle, ct.byref(nb)))
+    work = _workspace(nb.value, g.device)
+    _check(lib().rw_grad_edges(g.handle, _ptr(U.contiguous()), _ptr(A.contiguous()), C, _ptr(dw), _ptr(dJ), _ptr(db),
+                               _ptr(ds), _ptr(work), nb.value, _stream(g.device)))
+    return dw, dJ, db, ds
+
+
+def spectral_apply(g: Graph, Q: torch.Tensor, lam: torch.Tensor, B: torch.Tensor) -> torch.Tensor:
+    """X = S Q' Lambda'^{-1} Q'^T S B (truncated pseudo-inverse through the eigenbasis)."""
+    m = Q.shape[0]
+    C = B.shape[0]
+    B = B.to(torch.float64).contiguous()
+    X = torch.empty_like(B)
+    nb = ct.c_size_t()
+    _check(lib().rw_spectral_workspace_bytes(g.handle, m, C, ct.byref(nb)))
+    work = _workspace(nb.value, g.device)
+    _check(lib().rw_spectral_apply(g.handle, _ptr(Q.contiguous()), _ptr(lam), m, _ptr(B), C, _ptr(X), _ptr(work),
+                                   nb.value, _stream(g.device)))
+    return X
+
+
+class RandomWalkerFn(torch.autograd.Function):
+    """U = exact random walker probabilities (C, N) as a function of the intensities J (N,), beta (scalar
+    tensor) and per-edge scales s (ndir, N).  Forward: FP64 CG started from the fast (eigenbasis) solution
+    when (Q, lam) are given.  Backward: the adjoint system L_n A = dl/dU by CG started from the spectral
+    pseudo-inverse through the same eigenbasis, then the edge-gradient kernel.  Only U is kept for the
+    backward pass (no CG iterates)."""
+
+    @staticmethod
+    def forward(ctx, J, beta, scale, dims, conn, seed_node, seed_label, C, Q=None, lam=None, tol=1e-12,
+                normalized=True):
+        g = Graph(J.detach().to(torch.float64), dims, conn, float(beta), dtype=torch.float64, normalized=normalized)
+        graph_set_scale(g, scale.detach())
+        U0 = None
+        if Q is not None:
+            U0, _ = solve_seeds(g, Q, lam, seed_node, seed_label, C)
+        U, info = cg_solve(g, seed_node, seed_label, C, tol=tol, U0=U0)
+        ctx.g = g
+        ctx.seeds = (seed_node, seed_label, C)
+        ctx.basis = (Q, lam)
+        ctx.tol = tol
+        ctx.cg_iters = info["iters"]
+        ctx.save_for_backward(U)
+        return U
+
+    @staticmethod
+    def backward(ctx, gU):
+        (U,) = ctx.saved_tensors
+        g = ctx.g
+        seed_node, seed_label, C = ctx.seeds
+        Q, lam = ctx.basis
+        X0 = spectral_apply(g, Q, lam, gU) if Q is not None and Q.dtype == torch.float64 else None
+        A, info = cg_solve_rhs(g, seed_node, seed_label, C, gU, tol=ctx.tol, X0=X0)
+        dw, dJ, db, ds = grad_edges(g, U, A)
+        return dJ, db, ds, None, None, None, None, None, None, None, None, None
+
+
+def random_walker(J, beta, scale, dims, conn, seed_node, seed_label, C, Q=None, lam=None, tol=1e-12,
+                  normalized=True):
+    """Differentiable exact random walker (see RandomWalkerFn)."""
+    return RandomWalkerFn.apply(J, beta, scale, dims, conn, seed_node, seed_label, C, Q, lam, tol, normalized)

@@ -58,9 +58,10 @@ __device__ __forceinline__ double nbr_sum(const GridDev& G, const double* wgt, i
   return acc;
 }
 
-// r = b - L_n x  (x zero on seeds), b_i = sum over seed neighbours j with label k of w_ij
+// r = b - L_n x  (x zero on seeds); b_i = B(k, i) when an explicit right-hand side is given, else
+// the seeded random walker's  b_i = sum over seed neighbours j with label k of w_ij  (= -B^T u_s)
 __global__ void k_cg_init(GridDev G, const double* wgt, const double* deg, const uint8_t* map, int C, int x0_given,
-                          double* U, double* r) {
+                          const double* B, double* U, double* r) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int k = blockIdx.y;
   if (i >= G.N) return;
@@ -70,7 +71,7 @@ __global__ void k_cg_init(GridDev G, const double* wgt, const double* deg, const
     return;
   }
   if (!x0_given) x[i] = 0.0;
-  double b = nbr_sum(G, wgt, i, [&](int64_t j) { return map[j] == k + 1 ? 1.0 : 0.0; });
+  double b = B ? B[(int64_t)k * G.N + i] : nbr_sum(G, wgt, i, [&](int64_t j) { return map[j] == k + 1 ? 1.0 : 0.0; });
   double Ax = 0.0;
   if (x0_given) {
     Ax = deg[i] * x[i] - nbr_sum(G, wgt, i, [&](int64_t j) { return map[j] ? 0.0 : x[j]; });
@@ -176,30 +177,17 @@ __global__ void k_cg_axpy(int64_t N, double* U, double* r, const double* p, cons
   r[t] -= a * q[t];
 }
 
-__global__ void k_cg_finish(int64_t N, const uint8_t* map, double* U) {
+// seed rows: one-hot (random walker) or zero (explicit right-hand side: the adjoint vanishes there)
+__global__ void k_cg_finish(int64_t N, const uint8_t* map, int onehot, double* U) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int k = blockIdx.y;
   if (i >= N) return;
-  if (map[i]) U[(int64_t)k * N + i] = (map[i] - 1 == k) ? 1.0 : 0.0;
+  if (map[i]) U[(int64_t)k * N + i] = (onehot && map[i] - 1 == k) ? 1.0 : 0.0;
 }
 
-}  // namespace rw
-
-using namespace rw;
-
-extern "C" {
-
-int rw_cg_workspace_bytes(rw_graph h, int C, size_t* bytes) {
-  RW_CHECK(h != nullptr && bytes != nullptr, RW_EINVAL, "null argument");
-  RW_CHECK(C >= 1 && C <= 255, RW_EINVAL, "C must be in [1, 255]");
-  // seeds are bounded by N
-  *bytes = cg_layout(&h->g, C, h->g.N, nullptr, nullptr);
-  return RW_OK;
-}
-
-int rw_cg_solve(rw_graph h, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, double tol,
-                int max_iter, int x0_given, double* U, void* work, size_t work_bytes, hipStream_t stream,
-                rw_cg_info* info) {
+static int cg_core(rw_graph h, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C,
+                   const double* B, double tol, int max_iter, int x0_given, double* U, void* work, size_t work_bytes,
+                   hipStream_t stream, rw_cg_info* info) {
   RW_CHECK(h != nullptr && U != nullptr && work != nullptr, RW_EINVAL, "null argument");
   const Graph* g = &h->g;
   RW_CHECK(g->dtype == RW_F64, RW_EINVAL, "the CG solver needs an FP64 graph");
@@ -239,7 +227,7 @@ int rw_cg_solve(rw_graph h, const int64_t* seed_node, const int32_t* seed_label,
   dim3 gridN(nblocks(N, 256), C);
   const int nbk = (int)std::min<int64_t>(kCgBlocks, nblocks(N, 256));
   dim3 gridR(nbk, C);
-  k_cg_init<<<gridN, 256, 0, stream>>>(G, wgt, g->degree, w.map, C, x0_given, U, w.r);
+  k_cg_init<<<gridN, 256, 0, stream>>>(G, wgt, g->degree, w.map, C, x0_given, B, U, w.r);
   RW_LAUNCH_CHECK();
   k_cg_precond<<<gridR, 256, 0, stream>>>(N, g->degree, w.map, w.r, w.z, w.partial, C);
   k_cg_scalars_rz<<<1, 256, 0, stream>>>(w.partial, nbk, C, w.sc, 1);
@@ -279,7 +267,7 @@ int rw_cg_solve(rw_graph h, const int64_t* seed_node, const int32_t* seed_label,
       done = converged(&worst);
     }
   }
-  k_cg_finish<<<gridN, 256, 0, stream>>>(N, w.map, U);
+  k_cg_finish<<<gridN, 256, 0, stream>>>(N, w.map, B ? 0 : 1, U);
   RW_LAUNCH_CHECK();
   RW_HIP(hipStreamSynchronize(stream));
   if (info) {
@@ -291,6 +279,32 @@ int rw_cg_solve(rw_graph h, const int64_t* seed_node, const int32_t* seed_label,
     return RW_ENOCONV;
   }
   return RW_OK;
+}
+
+}  // namespace rw
+
+using namespace rw;
+
+extern "C" {
+
+int rw_cg_workspace_bytes(rw_graph h, int C, size_t* bytes) {
+  RW_CHECK(h != nullptr && bytes != nullptr, RW_EINVAL, "null argument");
+  RW_CHECK(C >= 1 && C <= 255, RW_EINVAL, "C must be in [1, 255]");
+  *bytes = cg_layout(&h->g, C, h->g.N, nullptr, nullptr);
+  return RW_OK;
+}
+
+int rw_cg_solve(rw_graph h, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, double tol,
+                int max_iter, int x0_given, double* U, void* work, size_t work_bytes, hipStream_t stream,
+                rw_cg_info* info) {
+  return cg_core(h, seed_node, seed_label, S, C, nullptr, tol, max_iter, x0_given, U, work, work_bytes, stream, info);
+}
+
+int rw_cg_solve_rhs(rw_graph h, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, const double* B,
+                    double tol, int max_iter, int x0_given, double* X, void* work, size_t work_bytes,
+                    hipStream_t stream, rw_cg_info* info) {
+  RW_CHECK(B != nullptr, RW_EINVAL, "null right-hand side");
+  return cg_core(h, seed_node, seed_label, S, C, B, tol, max_iter, x0_given, X, work, work_bytes, stream, info);
 }
 
 }  // extern "C"

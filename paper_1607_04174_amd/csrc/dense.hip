@@ -84,7 +84,7 @@ int chol_upper_inverse(const double* L, double* Rinv, int n, hipStream_t s) {
 // ---------------------------------------------------------------------------------------------
 constexpr int kJacobiThreads = 1024;
 constexpr int kJacobiMaxSweeps = 30;
-constexpr size_t kLdsLimit = 160 * 1024 - 2048;   // dynamic LDS budget (static arrays use the rest)
+constexpr size_t kLdsLimit = 160 * 1024 - 64;   // dynamic LDS budget (the kernels' static LDS is 16 bytes)
 
 __device__ __forceinline__ int rr_player(int pos, int round, int n2) {
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n2 - 1);
@@ -140,7 +140,7 @@ static size_t syev_stride(int n, bool vectors, bool glb, int nrhs) {
 
 static size_t lds_bytes(int n, int nrhs) {
   int n2 = n + (n & 1), np = n2 / 2;
-  return (size_t)n2 * (n2 + 1) / 2 * 8 + (size_t)np * 16 + (size_t)np * 8 + (size_t)n2 * nrhs * 8 + 256;
+  return (size_t)n2 * (n2 + 1) / 2 * 8 + (size_t)np * 16 + (size_t)np * 8 + (size_t)n2 * nrhs * 8 + 16;
 }
 
 size_t syev_work_count(int n, int count, bool vectors, int nrhs) {
@@ -177,7 +177,7 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
     if (threadIdx.x == 0) rotated = 0;
     Store::sync();
     for (int round = 0; round < n2 - 1; ++round) {
-      for (int k = threadIdx.x; k < np; k += blockDim.x) {
+      for (int k = threadIdx.x; k < np; k += kJacobiThreads) {
         int p = rr_player(k, round, n2), q = rr_player(n2 - 1 - k, round, n2);
         if (p > q) { int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0;
@@ -205,59 +205,49 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
         }
       }
       Store::sync();
-      // off-diagonal 2 x 2 blocks of pairs k1 < k2 on a 32 x 32 thread grid: a thread's pairs k1
-      // (ta, ta + 32, ...) are read from LDS once per round; the pair k2 is shared by the 32 lanes of
-      // a half-wave.  Loads of up to four blocks are issued before their stores so that memory
-      // latency overlaps.
-      {
-        constexpr int KMAX = 16;                 // np <= 511
-        double c1v[KMAX], s1v[KMAX];
-        int p1v[KMAX], q1v[KMAX];
-        int nk1 = 0;
-        for (int k1 = ta; k1 < np && nk1 < KMAX; k1 += 32, ++nk1) {
-          c1v[nk1] = cs[k1];
-          s1v[nk1] = sn[k1];
-          p1v[nk1] = pq[2 * k1];
-          q1v[nk1] = pq[2 * k1 + 1];
-        }
-        for (int k2 = tb; k2 < np; k2 += 32) {
-          const double c2 = cs[k2], s2 = sn[k2];
-          const int p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
-          double bv[4][4];
-          int idx[4];
-          int cnt = 0;
-          auto flush = [&]() {
-            for (int u = 0; u < cnt; ++u) {
-              const int j = idx[u];
-              const double c1 = c1v[j], s1 = s1v[j];
-              const int p1 = p1v[j], q1 = q1v[j];
-              const double b00 = bv[u][0], b01 = bv[u][1], b10 = bv[u][2], b11 = bv[u][3];
-              const double r00 = c1 * b00 - s1 * b10, r01 = c1 * b01 - s1 * b11;   // rows: J1^T B
-              const double r10 = s1 * b00 + c1 * b10, r11 = s1 * b01 + c1 * b11;
-              S.st_sym(p1, p2, c2 * r00 - s2 * r01);                              // columns: (J1^T B) J2
-              if (q2 < n) S.st_sym(p1, q2, s2 * r00 + c2 * r01);
-              if (q1 < n) S.st_sym(q1, p2, c2 * r10 - s2 * r11);
-              if (q1 < n && q2 < n) S.st_sym(q1, q2, s2 * r10 + c2 * r11);
-            }
-            cnt = 0;
-          };
-          for (int j = 0; j < nk1; ++j) {
-            const int k1 = ta + 32 * j;
-            if (k1 >= k2) break;
-            if (s1v[j] == 0.0 && s2 == 0.0) continue;
-            const int p1 = p1v[j], q1 = q1v[j];
-            idx[cnt] = j;
-            bv[cnt][0] = S.ld(p1, p2);
-            bv[cnt][1] = q2 < n ? S.ld(p1, q2) : 0.0;
-            bv[cnt][2] = q1 < n ? S.ld(q1, p2) : 0.0;
-            bv[cnt][3] = (q1 < n && q2 < n) ? S.ld(q1, q2) : 0.0;
-            if (++cnt == 4) flush();
+      // off-diagonal 2 x 2 blocks of pairs k1 < k2 on a 32 x 32 thread grid (ta = k1 mod 32,
+      // tb = k2 mod 32).  Four blocks are loaded before any is stored so that memory latency
+      // overlaps; all per-block values stay in registers (constant indices after unrolling).
+      // Both stores keep a zero-padded dummy index (odd n) at zero, so loads need no bounds tests:
+      // every load is issued unconditionally (a block outside k1 < k2 reads pair k2's own entries and
+      // is not stored), and only the stores are predicated.
+      for (int k2 = tb; k2 < np; k2 += 32) {
+        const double c2 = cs[k2], s2 = sn[k2];
+        const int p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
+        for (int k1b = ta; k1b < k2; k1b += 128) {
+          double b0[4], b1[4], b2[4], b3[4], c1[4], s1[4];
+          int p1[4], q1[4];
+          bool v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int k1 = k1b + 32 * u;
+            const bool in = k1 < k2;
+            const int kk = in ? k1 : k2;
+            c1[u] = cs[kk];
+            s1[u] = sn[kk];
+            p1[u] = pq[2 * kk];
+            q1[u] = pq[2 * kk + 1];
+            v[u] = in && !(s1[u] == 0.0 && s2 == 0.0);
+            b0[u] = S.ld(p1[u], p2);
+            b1[u] = S.ld(p1[u], q2);
+            b2[u] = S.ld(q1[u], p2);
+            b3[u] = S.ld(q1[u], q2);
           }
-          flush();
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double r00 = c1[u] * b0[u] - s1[u] * b2[u], r01 = c1[u] * b1[u] - s1[u] * b3[u];  // J1^T B
+            const double r10 = s1[u] * b0[u] + c1[u] * b2[u], r11 = s1[u] * b1[u] + c1[u] * b3[u];
+            if (v[u]) {
+              S.st_sym(p1[u], p2, c2 * r00 - s2 * r01);                                            // (J1^T B) J2
+              S.st_sym(p1[u], q2, s2 * r00 + c2 * r01);
+              S.st_sym(q1[u], p2, c2 * r10 - s2 * r11);
+              S.st_sym(q1[u], q2, s2 * r10 + c2 * r11);
+            }
+          }
         }
       }
       if (rhs) {
-        for (int t = threadIdx.x; t < np * nrhs; t += blockDim.x) {
+        for (int t = threadIdx.x; t < np * nrhs; t += kJacobiThreads) {
           int k = t % np, r = t / np;
           double s = sn[k];
           if (s == 0.0) continue;
@@ -275,7 +265,7 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
     if (!any) { ++sweep; break; }
   }
   // eigenvalues ascending (stable by index); perm[i] = sorted position of index i
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  for (int i = threadIdx.x; i < n; i += kJacobiThreads) {
     double wi = S.ld(i, i);
     int rank = 0;
     for (int j = 0; j < n; ++j) {
@@ -302,15 +292,15 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(const double* As,
   int* pq = reinterpret_cast<int*>(sn + np);
   double* rhs = reinterpret_cast<double*>(pq + 2 * np);
   LdsStore S{a};
-  for (int64_t t = threadIdx.x; t < (int64_t)n2 * (n2 + 1) / 2; t += blockDim.x) a[t] = 0.0;
+  for (int64_t t = threadIdx.x; t < (int64_t)n2 * (n2 + 1) / 2; t += kJacobiThreads) a[t] = 0.0;
   __syncthreads();
-  for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += blockDim.x) {
+  for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += kJacobiThreads) {
     int i = (int)(t % n), j = (int)(t / n);
     if (i <= j) S.st_sym(i, j, 0.5 * (A[t] + A[j + (int64_t)i * n]));
   }
   double* R = Rs ? Rs + (int64_t)blockIdx.x * n * nrhs : nullptr;
   if (R)
-    for (int64_t t = threadIdx.x; t < (int64_t)n2 * nrhs; t += blockDim.x) {
+    for (int64_t t = threadIdx.x; t < (int64_t)n2 * nrhs; t += kJacobiThreads) {
       int i = (int)(t % n2), r = (int)(t / n2);
       rhs[t] = i < n ? R[i + (int64_t)r * n] : 0.0;
     }
@@ -318,7 +308,7 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(const double* As,
   jacobi_body(S, n, n2, R ? rhs : nullptr, nrhs, log, ws + (int64_t)blockIdx.x * n, perm, perm + n, cs, sn, pq);
   __syncthreads();
   if (R)
-    for (int64_t t = threadIdx.x; t < (int64_t)n * nrhs; t += blockDim.x) {
+    for (int64_t t = threadIdx.x; t < (int64_t)n * nrhs; t += kJacobiThreads) {
       int i = (int)(t % n), r = (int)(t / n);
       R[(int)perm[i] + (int64_t)r * n] = rhs[i + (int64_t)r * n2];
     }
@@ -336,13 +326,13 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_glb(const double* As,
   double* perm = wk + (size_t)n2 * n2 + (want_log ? syev_log_count(n) : 0);
   double* rhs = perm + n + 8;
   GlbStore S{a, n2};
-  for (int64_t t = threadIdx.x; t < (int64_t)n2 * n2; t += blockDim.x) {
+  for (int64_t t = threadIdx.x; t < (int64_t)n2 * n2; t += kJacobiThreads) {
     int i = (int)(t % n2), j = (int)(t / n2);
     a[t] = (i < n && j < n) ? 0.5 * (A[i + (int64_t)j * n] + A[j + (int64_t)i * n]) : 0.0;
   }
   double* R = Rs ? Rs + (int64_t)blockIdx.x * n * nrhs : nullptr;
   if (R)
-    for (int64_t t = threadIdx.x; t < (int64_t)n2 * nrhs; t += blockDim.x) {
+    for (int64_t t = threadIdx.x; t < (int64_t)n2 * nrhs; t += kJacobiThreads) {
       int i = (int)(t % n2), r = (int)(t / n2);
       rhs[t] = i < n ? R[i + (int64_t)r * n] : 0.0;
     }
@@ -350,7 +340,7 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_glb(const double* As,
   jacobi_body(S, n, n2, R ? rhs : nullptr, nrhs, log, ws + (int64_t)blockIdx.x * n, perm, perm + n, cs, sn, pq);
   __syncthreads();
   if (R)
-    for (int64_t t = threadIdx.x; t < (int64_t)n * nrhs; t += blockDim.x) {
+    for (int64_t t = threadIdx.x; t < (int64_t)n * nrhs; t += kJacobiThreads) {
       int i = (int)(t % n), r = (int)(t / n);
       R[(int)perm[i] + (int64_t)r * n] = rhs[i + (int64_t)r * n2];
     }
@@ -359,7 +349,7 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_glb(const double* As,
 // V from the logged rotations: V = J(1) J(2) ... applied to the identity; rows are independent, so
 // each workgroup replays every rotation on a slab of kReplayRows rows held in LDS, then writes the
 // columns in sorted order.
-constexpr int kReplayRows = 32;
+constexpr int kReplayRows = 8;     // rows of V per workgroup (more workgroups, less work each)
 constexpr int kReplayStage = 8;   // rounds of rotations staged in LDS per barrier pair
 
 __global__ __launch_bounds__(256) void k_jacobi_replay(int n, int rows_per_block, const double* work, int64_t stride,
@@ -376,7 +366,7 @@ __global__ __launch_bounds__(256) void k_jacobi_replay(int n, int rows_per_block
   const int ld = n2 + 1;
   double* stage = vs + rows_per_block * ld;        // kReplayStage x np x (c, s)
   int* spq = reinterpret_cast<int*>(stage + kReplayStage * np * 2);   // kReplayStage x np x (p, q)
-  for (int t = threadIdx.x; t < rows_per_block * ld; t += blockDim.x) {
+  for (int t = threadIdx.x; t < rows_per_block * ld; t += 256) {
     int r = t / ld, c = t - r * ld;
     vs[t] = (r < rows && c == r0 + r) ? 1.0 : 0.0;
   }
@@ -384,8 +374,8 @@ __global__ __launch_bounds__(256) void k_jacobi_replay(int n, int rows_per_block
   for (int g0 = 0; g0 < total_rounds; g0 += kReplayStage) {
     const int ng = min(kReplayStage, total_rounds - g0);
     lds_barrier();
-    for (int t = threadIdx.x; t < ng * np * 2; t += blockDim.x) stage[t] = log[(size_t)g0 * np * 2 + t];
-    for (int t = threadIdx.x; t < ng * np; t += blockDim.x) {
+    for (int t = threadIdx.x; t < ng * np * 2; t += 256) stage[t] = log[(size_t)g0 * np * 2 + t];
+    for (int t = threadIdx.x; t < ng * np; t += 256) {
       int gi = t / np, k = t - gi * np;
       int round = (g0 + gi) % (n2 - 1);
       int p = rr_player(k, round, n2), q = rr_player(n2 - 1 - k, round, n2);
@@ -396,8 +386,8 @@ __global__ __launch_bounds__(256) void k_jacobi_replay(int n, int rows_per_block
     for (int gi = 0; gi < ng; ++gi) {
       const double* L = stage + gi * np * 2;
       const int* PQ = spq + gi * np * 2;
-      for (int t = threadIdx.x; t < kReplayRows * np; t += blockDim.x) {
-        int r = t & (kReplayRows - 1), k = t >> 5;
+      for (int t = threadIdx.x; t < kReplayRows * np; t += 256) {
+        int r = t & (kReplayRows - 1), k = t >> 3;
         if (r >= rows) continue;
         double s = L[2 * k + 1];
         if (s == 0.0) continue;
@@ -413,7 +403,7 @@ __global__ __launch_bounds__(256) void k_jacobi_replay(int n, int rows_per_block
   }
   lds_barrier();
   double* V = Vs + (int64_t)b * n * n;
-  for (int t = threadIdx.x; t < rows * n; t += blockDim.x) {
+  for (int t = threadIdx.x; t < rows * n; t += 256) {
     int r = t % rows, col = t / rows;
     V[(r0 + r) + (int64_t)((int)perm[col]) * n] = vs[r * ld + col];
   }

@@ -15,7 +15,9 @@
 
 namespace rw {
 
-constexpr int kMaxCand = 16;   // candidate m values evaluated per probe of the choice of m
+// candidate m values evaluated per probe of the choice of m: all of [2, m_avail] at once when
+// m_avail <= 256 (one batched launch), else a k-ary search
+static inline int fit_cands(int ma) { return std::max(1, std::min(ma - 1, 256)); }
 
 struct SolveWork {
   uint8_t* map;       // N: 0 = not a seed, else label + 1
@@ -29,10 +31,10 @@ struct SolveWork {
   double* R;          // ma x C   (Q_s^T op_ss U_hat_s)
   double* Gq;         // ma x ma  (Q_s^T Q_s)
   double* Gb;         // ma x C   (Q_s^T U_hat_s)
-  double* fvals;      // kMaxCand x C
-  double* fitA;       // kMaxCand x ms x ms  (ms = min(S, ma))
-  double* fitR;       // kMaxCand x ms x C
-  double* fitW;       // kMaxCand x ms
+  double* fvals;      // ncand x C
+  double* fitA;       // ncand x ms x ms  (ms = min(S, ma))
+  double* fitR;       // ncand x ms x C
+  double* fitW;       // ncand x ms
   double* fitWork;    // Jacobi work
   double* K;          // ma x ma
   double* Y;          // ma x C
@@ -55,11 +57,12 @@ static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base,
   t.R = c.take<double>((size_t)ma * C);
   t.Gq = c.take<double>((size_t)ma * ma);
   t.Gb = c.take<double>((size_t)ma * C);
-  t.fvals = c.take<double>((size_t)kMaxCand * C);
-  t.fitA = c.take<double>((size_t)kMaxCand * ms * ms);
-  t.fitR = c.take<double>((size_t)kMaxCand * ms * C);
-  t.fitW = c.take<double>((size_t)kMaxCand * ms);
-  t.fitWork = c.take<double>(syev_work_count((int)ms, kMaxCand, false, C));
+  const int nc = fit_cands(ma);
+  t.fvals = c.take<double>((size_t)nc * C);
+  t.fitA = c.take<double>((size_t)nc * ms * ms);
+  t.fitR = c.take<double>((size_t)nc * ms * C);
+  t.fitW = c.take<double>((size_t)nc * ms);
+  t.fitWork = c.take<double>(syev_work_count((int)ms, nc, false, C));
   t.K = c.take<double>((size_t)ma * ma);
   t.Y = c.take<double>((size_t)ma * C);
   t.stat = c.take<double>(8);
@@ -437,9 +440,10 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
     const double rho = std::sqrt(rho2);
     // search: lo = largest m known to fail (1 = none), hi = smallest m known to pass (ma + 1 = none)
     int lo = 1, hi = ma + 1;
-    std::vector<double> fh((size_t)kMaxCand * C);
+    const int maxc = fit_cands(ma);
+    std::vector<double> fh((size_t)maxc * C);
     std::vector<int> cand;
-    // candidate list lives in the first kMaxCand ints of the K buffer (unused until the final solve)
+    // candidate list lives in the first maxc ints of the K buffer (unused until the final solve)
     int* cand_buf = reinterpret_cast<int*>(w.K);
     const int msmax = (int)std::min<int64_t>(S, ma);
     RW_CHECK(msmax <= 1022, RW_EINVAL, "choice of m supports min(S, m_avail) <= 1022");
@@ -447,7 +451,7 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
     while (hi - lo > 1) {
       cand.clear();
       int span = hi - lo - 1;
-      int nc = std::min(span, kMaxCand);
+      int nc = std::min(span, maxc);
       for (int q = 1; q <= nc; ++q) {
         int mm = lo + (int)(((int64_t)span * q + nc - 1) / nc);
         if (mm < 2) mm = 2;
