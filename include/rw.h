@@ -269,6 +269,26 @@ int rw_spectral_apply(rw_graph g, const double* Q, const double* lambda, int m, 
                       double* X, void* work, size_t work_bytes, hipStream_t stream);
 
 /* ======================================================================================
+ * Precision form: BF16 copies of the eigenbasis and matrix-core contractions with it
+ * ====================================================================================== */
+
+/* Convert a column-major rows x cols block between RW_F64 / RW_F32 / RW_BF16 (round to nearest even;
+ * device buffers, src != dst).  Used to make the BF16 copy of Q that rw_solve_seeds reads with
+ * q_dtype = RW_BF16: its reconstruction U = D^{-1/2} Q Y then runs on the matrix cores
+ * (v_mfma_f32_16x16x16bf16, FP32 accumulation; Y split into two BF16 parts) for C <= 8. */
+int rw_convert_block(const void* src, int src_dtype, void* dst, int dst_dtype, int64_t rows, int cols,
+                     hipStream_t stream);
+
+int rw_project_workspace_bytes(int64_t N, int m, int C, size_t* bytes);
+
+/* Projection onto the eigenbasis, P = Q^T X (the contraction behind eq. (16)'s Q_n^T P_n term):
+ * Q device column-major N x m of q_dtype (RW_BF16: matrix cores, FP32 accumulation, X split into two
+ * BF16 parts, C <= 8, m <= 256; RW_F32: FP64-accumulated VALU), X device C x N FP32, P device m x C
+ * FP64 (column-major).  Fixed-order reduction of the partial sums. */
+int rw_project_basis(const void* Q, int q_dtype, int64_t N, int m, const float* X, int C, double* P,
+                     void* work, size_t work_bytes, hipStream_t stream);
+
+/* ======================================================================================
  * Dense FP64 building blocks used by the steps above (exposed for testing and reuse)
  * ====================================================================================== */
 

@@ -102,6 +102,10 @@ _SIGS = {
                                  ct.c_void_p]),
     "rw_dense_lu_solve": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p]),
     "rw_cg_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_convert_block": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_int64, ct.c_int, ct.c_void_p]),
+    "rw_project_workspace_bytes": (ct.c_int, [ct.c_int64, ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_project_basis": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_int64, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p,
+                                    ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "rw_cg_solve_rhs": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int, ct.c_void_p, ct.c_double,
                                    ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p,
                                    ct.POINTER(rw_cg_info)]),
@@ -502,3 +506,32 @@ def random_walker(J, beta, scale, dims, conn, seed_node, seed_label, C, Q=None, 
                   normalized=True):
     """Differentiable exact random walker (see RandomWalkerFn)."""
     return RandomWalkerFn.apply(J, beta, scale, dims, conn, seed_node, seed_label, C, Q, lam, tol, normalized)
+
+
+# ---------------------------------------------------------------------------------------------
+# precision form
+# ---------------------------------------------------------------------------------------------
+def convert_block(X: torch.Tensor, dtype) -> torch.Tensor:
+    """Copy of a (cols, rows) block (column-major rows x cols) converted by the library (RNE)."""
+    X = X.contiguous()
+    out = torch.empty(X.shape, dtype=dtype, device=X.device)
+    cols = X.shape[0] if X.dim() > 1 else 1
+    rows = X.numel() // cols
+    _check(lib().rw_convert_block(_ptr(X), _TORCH_DT[X.dtype], _ptr(out), _TORCH_DT[dtype], rows, cols,
+                                  _stream(X.device)))
+    return out
+
+
+def project_basis(Q: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    """P = Q^T X for Q (m, N) (column-major N x m; float32 or bfloat16) and X (C, N) float32: (C, m) float64
+    tensor holding the column-major m x C result."""
+    m, N = Q.shape
+    C = X.shape[0]
+    X = X.to(torch.float32).contiguous()
+    P = torch.empty((C, m), dtype=torch.float64, device=Q.device)
+    nb = ct.c_size_t()
+    _check(lib().rw_project_workspace_bytes(N, m, C, ct.byref(nb)))
+    work = _workspace(nb.value, Q.device)
+    _check(lib().rw_project_basis(_ptr(Q.contiguous()), _TORCH_DT[Q.dtype], N, m, _ptr(X), C, _ptr(P), _ptr(work),
+                                  nb.value, _stream(Q.device)))
+    return P

@@ -1,0 +1,272 @@
+// BF16 tall-skinny contractions with the eigenbasis on the matrix cores (v_mfma_f32_16x16x16bf16),
+// FP32 accumulation:
+//   reconstruction  U = s * (Q Y)   (N x m times m x C; Sec. II-B eq. (16): the labels are linear
+//                                     combinations of the eigenvectors), seed rows one-hot;
+//   projection      P = Q^T X       (m x N times N x C).
+// Q is stored in BF16 (half the HBM bytes of FP32); the small operand (Y or X) is split into a
+// high and a low BF16 part that occupy separate MFMA output columns, so it keeps ~16 significant
+// bits and the only BF16 rounding that matters is Q's.  With C <= 8 labels the 16 output columns
+// hold both parts; the contraction stays HBM-bound (it reads Q once), so the matrix cores are
+// lightly used by construction.
+//
+// MFMA 16x16x16 operand layout (wave64): lane l holds A[l % 16][4 (l / 16) + v] and
+// B[4 (l / 16) + v][l % 16] for v = 0..3, and receives D[4 (l / 16) + v][l % 16].
+#include "rw_internal.h"
+
+namespace rw {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaNodes = 256;   // nodes per workgroup tile (4 waves x 64)
+
+__device__ __forceinline__ void split_bf16(float v, uint16_t* hi, uint16_t* lo) {
+  *hi = f32_to_bf16(v);
+  *lo = f32_to_bf16(v - bf16_to_f32(*hi));
+}
+
+// ---------------------------------------------------------------------------------------------
+// reconstruction
+// ---------------------------------------------------------------------------------------------
+template <typename TU>
+__global__ __launch_bounds__(256) void k_reconstruct_mfma(const uint16_t* __restrict__ Q, int64_t N, int m,
+                                                           const double* __restrict__ Y, int C,
+                                                           const uint8_t* __restrict__ map,
+                                                           const TU* __restrict__ dinv, int normalized,
+                                                           TU* __restrict__ U) {
+  extern __shared__ char smem[];
+  const int mpad = (m + 15) & ~15;
+  uint16_t* sBt = reinterpret_cast<uint16_t*>(smem);                    // [16 cols][mpad]
+  uint16_t* sQ = sBt + 16 * mpad;                                       // [256 nodes][16 k]
+  float* sD = reinterpret_cast<float*>(sQ + kMfmaNodes * 16);            // [256 nodes][17]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t node0 = (int64_t)blockIdx.x * kMfmaNodes;
+  // B operand: columns 0..C-1 high parts, C..2C-1 low parts, zero elsewhere
+  for (int t = tid; t < 16 * mpad; t += 256) {
+    int col = t / mpad, k = t - col * mpad;
+    uint16_t v = 0;
+    if (k < m) {
+      int c = col < C ? col : col - C;
+      if (col < 2 * C) {
+        uint16_t hi, lo;
+        split_bf16((float)Y[k + (int64_t)c * m], &hi, &lo);
+        v = col < C ? hi : lo;
+      }
+    }
+    sBt[t] = v;
+  }
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bool vec = (N & 3) == 0;
+  for (int k0 = 0; k0 < mpad; k0 += 16) {
+    __syncthreads();
+    // stage Q[k0 .. k0+16) x [node0, node0 + 256) transposed into sQ[node][k]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int idx = tid + 256 * r;        // 0..1023
+      const int col = idx >> 6, g = idx & 63;
+      const int64_t node = node0 + 4 * g;
+      const int k = k0 + col;
+      uint16_t v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+      if (k < m) {
+        const uint16_t* src = Q + (int64_t)k * N + node;
+        if (vec && node + 3 < N) {
+          const uint2 w = *reinterpret_cast<const uint2*>(src);
+          v0 = (uint16_t)(w.x & 0xffffu); v1 = (uint16_t)(w.x >> 16);
+          v2 = (uint16_t)(w.y & 0xffffu); v3 = (uint16_t)(w.y >> 16);
+        } else {
+          if (node < N) v0 = src[0];
+          if (node + 1 < N) v1 = src[1];
+          if (node + 2 < N) v2 = src[2];
+          if (node + 3 < N) v3 = src[3];
+        }
+      }
+      sQ[(4 * g + 0) * 16 + col] = v0;
+      sQ[(4 * g + 1) * 16 + col] = v1;
+      sQ[(4 * g + 2) * 16 + col] = v2;
+      sQ[(4 * g + 3) * 16 + col] = v3;
+    }
+    __syncthreads();
+    const bf16x4 b = *reinterpret_cast<const bf16x4*>(sBt + (lane & 15) * mpad + k0 + 4 * (lane >> 4));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int nl = 64 * wave + 16 * t + (lane & 15);
+      const bf16x4 a = *reinterpret_cast<const bf16x4*>(sQ + nl * 16 + 4 * (lane >> 4));
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+    }
+  }
+  // epilogue: combine high + low columns per node through LDS
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int nl = 64 * wave + 16 * t + 4 * (lane >> 4) + v;
+      sD[nl * 17 + (lane & 15)] = acc[t][v];
+    }
+  __syncthreads();
+  const int64_t i = node0 + tid;
+  if (i >= N) return;
+  const int ml = map[i];
+  const float sc = normalized ? (float)dinv[i] : 1.0f;
+  for (int c = 0; c < C; ++c) {
+    const float val = sD[tid * 17 + c] + sD[tid * 17 + c + C];
+    U[(int64_t)c * N + i] = ml ? (ml - 1 == c ? TU(1) : TU(0)) : TU(sc * val);
+  }
+}
+
+size_t reconstruct_mfma_lds(int m) {
+  const int mpad = (m + 15) & ~15;
+  return (size_t)16 * mpad * 2 + (size_t)kMfmaNodes * 16 * 2 + (size_t)kMfmaNodes * 17 * 4;
+}
+
+int reconstruct_mfma(const Graph* g, const void* Q, int m, const double* Y, int C, const uint8_t* map, void* U,
+                     hipStream_t s) {
+  RW_CHECK(C <= 8, RW_EINVAL, "the BF16 matrix-core reconstruction handles at most 8 labels");
+  const size_t sh = reconstruct_mfma_lds(m);
+  RW_CHECK(sh <= 64 * 1024, RW_EINVAL, "m = %d too large for the matrix-core reconstruction tile", m);
+  const unsigned grid = (unsigned)((g->N + kMfmaNodes - 1) / kMfmaNodes);
+  if (g->dtype == RW_F64)
+    k_reconstruct_mfma<double><<<grid, 256, sh, s>>>((const uint16_t*)Q, g->N, m, Y, C, map, (const double*)g->dinv,
+                                                     g->normalized, (double*)U);
+  else
+    k_reconstruct_mfma<float><<<grid, 256, sh, s>>>((const uint16_t*)Q, g->N, m, Y, C, map, (const float*)g->dinv,
+                                                    g->normalized, (float*)U);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// projection P = Q^T X: each workgroup accumulates a partial over its node range for every 16-row
+// chunk of Q^T, then the partials are summed in FP64 in a fixed order
+// ---------------------------------------------------------------------------------------------
+constexpr int kProjMaxChunks = 16;   // m <= 256
+
+__global__ __launch_bounds__(256) void k_project_mfma(const uint16_t* __restrict__ Q, int64_t N, int m,
+                                                      const float* __restrict__ X, int C, int64_t nodes_per_block,
+                                                      float* __restrict__ partial) {
+  __shared__ uint16_t sQ[16 * kMfmaNodes];   // [16 cols][256 nodes]
+  __shared__ float sR[4][16 * 16];           // per-wave results of one m-chunk
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int mchunks = (m + 15) >> 4;
+  const int64_t begin = (int64_t)blockIdx.x * nodes_per_block;
+  const int64_t end = std::min<int64_t>(N, begin + nodes_per_block);
+  f32x4 acc[kProjMaxChunks];
+#pragma unroll
+  for (int q = 0; q < kProjMaxChunks; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t n0 = begin; n0 < end; n0 += kMfmaNodes) {
+    // B fragments (X split) for this wave's 64 nodes: 4 k-steps of 16 nodes
+    bf16x4 b[4];
+    const int j = lane & 15;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int64_t nb = n0 + 64 * wave + 16 * st + 4 * (lane >> 4);
+      short e[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t node = nb + v;
+        uint16_t hv = 0;
+        if (node < end && j < 2 * C) {
+          uint16_t hi, lo;
+          split_bf16(X[(int64_t)(j < C ? j : j - C) * N + node], &hi, &lo);
+          hv = j < C ? hi : lo;
+        }
+        e[v] = (short)hv;
+      }
+      b[st] = bf16x4{e[0], e[1], e[2], e[3]};
+    }
+#pragma unroll
+    for (int q = 0; q < kProjMaxChunks; ++q) {
+      if (q >= mchunks) break;
+      __syncthreads();
+      for (int idx = tid; idx < 16 * kMfmaNodes; idx += 256) {
+        const int col = idx >> 8, nl = idx & 255;
+        const int k = 16 * q + col;
+        const int64_t node = n0 + nl;
+        sQ[idx] = (k < m && node < end) ? Q[(int64_t)k * N + node] : (uint16_t)0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int nl = 64 * wave + 16 * st + 4 * (lane >> 4);
+        const bf16x4 a = *reinterpret_cast<const bf16x4*>(sQ + (lane & 15) * kMfmaNodes + nl);
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[st], acc[q], 0, 0, 0);
+      }
+    }
+  }
+  // reduce the 4 waves and write this block's partial [m][16]
+  float* out = partial + (int64_t)blockIdx.x * mchunks * 256;
+#pragma unroll
+  for (int q = 0; q < kProjMaxChunks; ++q) {
+    if (q >= mchunks) break;
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sR[wave][(4 * (lane >> 4) + v) * 16 + (lane & 15)] = acc[q][v];
+    __syncthreads();
+    out[q * 256 + tid] = sR[0][tid] + sR[1][tid] + sR[2][tid] + sR[3][tid];
+  }
+}
+
+__global__ void k_project_final(const float* partial, int nblocks, int m, int C, double* P) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m * C) return;
+  const int i = t % m, c = t / m;
+  const int mchunks = (m + 15) >> 4;
+  const int q = i >> 4, r = i & 15;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    const float* p = partial + (int64_t)b * mchunks * 256 + q * 256 + r * 16;
+    s += (double)p[c] + (double)p[c + C];
+  }
+  P[i + (int64_t)c * m] = s;
+}
+
+static int proj_blocks(int64_t N) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (N + 1023) / 1024)); }
+
+size_t project_partial_count(int64_t N, int m) {
+  return (size_t)proj_blocks(N) * ((m + 15) / 16) * 256;
+}
+
+}  // namespace rw
+
+using namespace rw;
+
+extern "C" {
+
+int rw_convert_block(const void* src, int src_dtype, void* dst, int dst_dtype, int64_t rows, int cols,
+                     hipStream_t stream) {
+  RW_CHECK(src != nullptr && dst != nullptr, RW_EINVAL, "null argument");
+  RW_CHECK(src != dst, RW_EINVAL, "source and destination must differ");
+  RW_CHECK((src_dtype == RW_F64 || src_dtype == RW_F32 || src_dtype == RW_BF16) &&
+               (dst_dtype == RW_F64 || dst_dtype == RW_F32 || dst_dtype == RW_BF16), RW_EINVAL, "bad dtype");
+  RW_CHECK(rows >= 0 && cols >= 0, RW_EINVAL, "bad sizes");
+  return convert_block(src_dtype, src, rows, dst_dtype, dst, rows, rows, cols, stream);
+}
+
+int rw_project_workspace_bytes(int64_t N, int m, int C, size_t* bytes) {
+  RW_CHECK(bytes != nullptr && N >= 1 && m >= 1 && C >= 1, RW_EINVAL, "bad sizes");
+  *bytes = std::max(project_partial_count(N, m) * sizeof(float), gram_partial_count(N, m, C) * sizeof(double));
+  return RW_OK;
+}
+
+int rw_project_basis(const void* Q, int q_dtype, int64_t N, int m, const float* X, int C, double* P, void* work,
+                     size_t work_bytes, hipStream_t stream) {
+  RW_CHECK(Q != nullptr && X != nullptr && P != nullptr && work != nullptr, RW_EINVAL, "null argument");
+  RW_CHECK(N >= 1 && m >= 1 && C >= 1, RW_EINVAL, "bad sizes");
+  size_t need = 0;
+  RW_TRY(rw_project_workspace_bytes(N, m, C, &need));
+  RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "projection workspace too small: %zu < %zu", work_bytes, need);
+  if (q_dtype == RW_F32) return gram(RW_F32, Q, N, X, N, N, m, C, P, static_cast<double*>(work), stream);
+  RW_CHECK(q_dtype == RW_BF16, RW_EINVAL, "projection supports F32 (VALU) and BF16 (matrix cores) bases");
+  RW_CHECK(C <= 8 && m <= 16 * kProjMaxChunks, RW_EINVAL, "matrix-core projection needs C <= 8 and m <= 256");
+  const int nb = proj_blocks(N);
+  const int64_t per = ((N + nb - 1) / nb + kMfmaNodes - 1) / kMfmaNodes * kMfmaNodes;
+  float* partial = static_cast<float*>(work);
+  k_project_mfma<<<nb, 256, 0, stream>>>((const uint16_t*)Q, N, m, X, C, per, partial);
+  RW_LAUNCH_CHECK();
+  k_project_final<<<nblocks((int64_t)m * C, 256), 256, 0, stream>>>(partial, nb, m, C, P);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+}  // extern "C"

@@ -178,6 +178,10 @@ int fill_random(int dt, void* X, int64_t ld, int64_t rows, int cols, uint64_t se
 int project_out(int dt, void* X, int64_t ld, const void* v, int64_t rows, int cols, double* tmp,
                 double* partial, hipStream_t s);
 
+// ---- BF16 matrix-core contractions (mfma.hip) ----------------------------------------------------
+int reconstruct_mfma(const Graph* g, const void* Q, int m, const double* Y, int C, const uint8_t* map, void* U,
+                     hipStream_t s);
+
 // ---- small dense FP64 kernels, one workgroup per matrix (dense.hip) ------------------------------
 // In-place lower Cholesky of count matrices (n x n, ld n, stride n*n); info[b] = 0 or (k+1) of the
 // first non-positive pivot.

@@ -215,6 +215,7 @@ static int reconstruct_t(const Graph* g, const void* Q, int m, const double* Y, 
 
 static int reconstruct(const Graph* g, const void* Q, int qdt, int m, const double* Y, int C, const uint8_t* map,
                        void* U, hipStream_t s) {
+  if (qdt == RW_BF16 && C <= 8) return reconstruct_mfma(g, Q, m, Y, C, map, U, s);
   RW_CHECK((size_t)m * 8 * 8 <= 65536, RW_EINVAL, "m = %d too large for the reconstruction tile", m);
   if (g->dtype == RW_F64) {
     if (qdt == RW_F64) return reconstruct_t<double, double>(g, Q, m, Y, C, map, U, s);
