@@ -289,6 +289,58 @@ int rw_project_basis(const void* Q, int q_dtype, int64_t N, int m, const float* 
                      void* work, size_t work_bytes, hipStream_t stream);
 
 /* ======================================================================================
+ * Batching form: the online solve of Sec. II-B (gamma = 0, m fixed per image) for many images of
+ * uneven sizes at once, one interaction round per enqueue, capturable into a HIP graph
+ * ====================================================================================== */
+typedef struct rw_batch_s* rw_batch;
+
+typedef struct {
+  rw_graph g;            /* the image's graph (all images: one graph dtype) */
+  const void* Q;         /* device column-major N x m basis of q_dtype (column 0 the null vector) */
+  int32_t q_dtype;       /* RW_F64, RW_F32 or RW_BF16 (all images: one q_dtype) */
+  const double* lambda;  /* device FP64, m eigenvalues, lambda[0] = 0 */
+  int32_t m;             /* pairs used (no choice of m in the batched form), 2 <= m <= min(N, 1024) */
+  int64_t S_cap;         /* most distinct seeds this image will get in any round */
+  int32_t C_cap;         /* most labels in any round, 1..8 */
+  void* U;               /* device C_cap x N of the graph dtype; round output in the first C rows */
+} rw_batch_image;
+
+int rw_batch_workspace_bytes(const rw_batch_image* imgs, int n, size_t* bytes);
+
+/* Lay out the batch inside `work` (device, rw_batch_workspace_bytes; owned by the caller, kept alive
+ * until rw_batch_destroy), upload the per-image descriptors and choose the reconstruction's launch
+ * shape (threads per block x nodes per thread) by timing the candidates on this batch, unless the
+ * process already tuned the same batch shape (or the file named by RW_AUTOTUNE_CACHE lists it).
+ * The graphs, bases and outputs must stay alive and unmoved while the batch exists.  Synchronizes
+ * `stream`.  Errors: RW_EINVAL (1 <= n <= 65535, sizes, mixed dtypes), RW_EWORKSPACE, RW_EHIP. */
+int rw_batch_create(const rw_batch_image* imgs, int n, void* work, size_t work_bytes, hipStream_t stream,
+                    rw_batch* out);
+int rw_batch_destroy(rw_batch b);
+
+/* Launch shape in use and whether rw_batch_create timed it (tune_us: microseconds spent). */
+int rw_batch_info(rw_batch b, int* threads, int* nodes_per_thread, int* tuned_now, double* tune_us);
+
+/* Seeds of the next round (host arrays): image i has C[i] labels and the seeds
+ * seed_node[seed_off[i] .. seed_off[i+1]) with labels seed_label[...], under the same rules as
+ * rw_solve_seeds (validated here; nothing is changed on error).  The arrays are copied to the
+ * device on `stream`, which is then synchronized: work that still reads the previous round must be
+ * ordered before this call (same stream) or finished.  Errors: RW_EINVAL, RW_EHIP. */
+int rw_batch_set_seeds(rw_batch b, const int* C, const int64_t* seed_off, const int64_t* seed_node,
+                       const int32_t* seed_label, hipStream_t stream);
+
+/* Enqueue one round for every image on `stream` (no host synchronization, no allocation, no
+ * memset, no host-read sizes: launch shapes depend on the capacities only, so a stream capture of
+ * this call replays correctly for every later round of rw_batch_set_seeds).  Per image: seed map,
+ * gather of Q_s and B Q_n, the reduced system (Lambda - Q_s^T B Q_n) Y = Q_s^T op_ss U_hat_s (FP64,
+ * LU with partial pivoting), and U = D^{-1/2} Q Y on non-seeds, one-hot on seeds.  Errors: RW_EINVAL
+ * (no seeds set yet). */
+int rw_batch_enqueue(rw_batch b, hipStream_t stream);
+
+/* After a round has run: smallest LU pivot ratio over the images (synchronizes `stream`).
+ * Errors: RW_ESINGULAR when some image's reduced system was singular (its U is then not valid). */
+int rw_batch_status(rw_batch b, double* min_pivot, hipStream_t stream);
+
+/* ======================================================================================
  * Dense FP64 building blocks used by the steps above (exposed for testing and reuse)
  * ====================================================================================== */
 

@@ -67,6 +67,11 @@ class rw_solve_info(ct.Structure):
                 ("min_pivot", ct.c_double)]
 
 
+class rw_batch_image(ct.Structure):
+    _fields_ = [("g", ct.c_void_p), ("Q", ct.c_void_p), ("q_dtype", ct.c_int32), ("lambda_", ct.c_void_p),
+                ("m", ct.c_int32), ("S_cap", ct.c_int64), ("C_cap", ct.c_int32), ("U", ct.c_void_p)]
+
+
 class rw_cg_info(ct.Structure):
     _fields_ = [("iters", ct.c_int32), ("rel_residual", ct.c_double)]
 
@@ -116,6 +121,15 @@ _SIGS = {
     "rw_spectral_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]),
     "rw_spectral_apply": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int,
                                      ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p]),
+    "rw_batch_workspace_bytes": (ct.c_int, [ct.POINTER(rw_batch_image), ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_batch_create": (ct.c_int, [ct.POINTER(rw_batch_image), ct.c_int, ct.c_void_p, ct.c_size_t, ct.c_void_p,
+                                   ct.POINTER(ct.c_void_p)]),
+    "rw_batch_destroy": (ct.c_int, [ct.c_void_p]),
+    "rw_batch_info": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), ct.POINTER(ct.c_int),
+                                 ct.POINTER(ct.c_double)]),
+    "rw_batch_set_seeds": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "rw_batch_enqueue": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
+    "rw_batch_status": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_double), ct.c_void_p]),
     "rw_cg_solve": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int, ct.c_double, ct.c_int,
                                ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p,
                                ct.POINTER(rw_cg_info)]),
@@ -535,3 +549,108 @@ def project_basis(Q: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
     _check(lib().rw_project_basis(_ptr(Q.contiguous()), _TORCH_DT[Q.dtype], N, m, _ptr(X), C, _ptr(P), _ptr(work),
                                   nb.value, _stream(Q.device)))
     return P
+
+
+# ---------------------------------------------------------------------------------------------
+# batching form
+# ---------------------------------------------------------------------------------------------
+class BatchSolver:
+    """Online solves for many images at once (fixed m per image), one interaction round per run().
+
+    images: sequence of dicts {"graph": Graph, "Q": (m, N) tensor, "lam": (m,) float64 tensor,
+    "S_cap": int, "C_cap": int}; all graphs share one dtype and all bases one dtype.  U[i] is the
+    (C_cap, N_i) output of image i (first C rows valid after a round with C labels).  With
+    use_graph=True the first run() captures the enqueue into a torch.cuda.CUDAGraph (a HIP graph)
+    and later rounds replay it."""
+
+    def __init__(self, images, use_graph: bool = True):
+        self.images = list(images)
+        n = len(self.images)
+        if n == 0:
+            raise ValueError("empty batch")
+        self.device = self.images[0]["graph"].device
+        self.U = []
+        arr = (rw_batch_image * n)()
+        self._keep = []
+        for i, im in enumerate(self.images):
+            g, Q, lam = im["graph"], im["Q"].contiguous(), im["lam"].contiguous()
+            U = torch.zeros((int(im["C_cap"]), g.N), dtype=g.dtype, device=g.device)
+            self.U.append(U)
+            self._keep += [g, Q, lam]
+            arr[i].g = g.handle
+            arr[i].Q = Q.data_ptr()
+            arr[i].q_dtype = _TORCH_DT[Q.dtype]
+            arr[i].lambda_ = lam.data_ptr()
+            arr[i].m = int(im.get("m", Q.shape[0]))
+            arr[i].S_cap = int(im["S_cap"])
+            arr[i].C_cap = int(im["C_cap"])
+            arr[i].U = U.data_ptr()
+        self._arr = arr
+        nb = ct.c_size_t()
+        _check(lib().rw_batch_workspace_bytes(arr, n, ct.byref(nb)))
+        self.work = _workspace(nb.value, self.device)
+        h = ct.c_void_p()
+        _check(lib().rw_batch_create(arr, n, _ptr(self.work), nb.value, _stream(self.device), ct.byref(h)))
+        self.handle = h
+        self.use_graph = use_graph
+        self.graph = None
+        self._stream = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.rw_batch_destroy(h)
+            self.handle = None
+
+    def info(self):
+        th, npt, tuned = ct.c_int(), ct.c_int(), ct.c_int()
+        us = ct.c_double()
+        _check(lib().rw_batch_info(self.handle, ct.byref(th), ct.byref(npt), ct.byref(tuned), ct.byref(us)))
+        return {"threads": th.value, "nodes_per_thread": npt.value, "tuned_now": bool(tuned.value),
+                "tune_us": us.value}
+
+    def set_seeds(self, rounds):
+        """rounds: per image (C, seed_node, seed_label)."""
+        if len(rounds) != len(self.images):
+            raise ValueError("one (C, nodes, labels) per image")
+        Cs = np.array([int(r[0]) for r in rounds], dtype=np.int32)
+        nodes = [np.asarray(r[1], dtype=np.int64) for r in rounds]
+        labs = [np.asarray(r[2], dtype=np.int32) for r in rounds]
+        off = np.zeros(len(rounds) + 1, dtype=np.int64)
+        off[1:] = np.cumsum([a.size for a in nodes])
+        alln = np.ascontiguousarray(np.concatenate(nodes)) if nodes else np.zeros(0, np.int64)
+        alll = np.ascontiguousarray(np.concatenate(labs)) if labs else np.zeros(0, np.int32)
+        # on the stream that runs the rounds: the previous round is ordered before the upload
+        _check(lib().rw_batch_set_seeds(self.handle, ct.c_void_p(Cs.ctypes.data), ct.c_void_p(off.ctypes.data),
+                                        ct.c_void_p(alln.ctypes.data), ct.c_void_p(alll.ctypes.data),
+                                        _stream(self.device)))
+        self.C = Cs
+
+    def enqueue(self, stream=None):
+        st = (stream or torch.cuda.current_stream(self.device)).cuda_stream
+        _check(lib().rw_batch_enqueue(self.handle, ct.c_void_p(st)))
+
+    def run(self):
+        """Enqueue the round set by set_seeds (graph replay when use_graph)."""
+        if not self.use_graph:
+            self.enqueue()
+            return
+        if self.graph is None:
+            self._stream = torch.cuda.Stream(self.device)
+            self._stream.wait_stream(torch.cuda.current_stream(self.device))
+            with torch.cuda.stream(self._stream):
+                self.enqueue(self._stream)        # eager round (also warms up the launches)
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph, stream=self._stream):
+                self.enqueue(self._stream)
+            torch.cuda.current_stream(self.device).wait_stream(self._stream)
+        else:
+            self.graph.replay()
+
+    def status(self):
+        mp = ct.c_double()
+        _check(lib().rw_batch_status(self.handle, ct.byref(mp), _stream(self.device)))
+        return mp.value
+
+    def outputs(self):
+        return [U[: int(c)] for U, c in zip(self.U, self.C)]

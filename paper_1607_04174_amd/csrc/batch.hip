@@ -1,0 +1,538 @@
+// Batched online solves: many images (ragged sizes, different m, C and seed sets) in one enqueue of
+// device-only kernels, so that a caller can capture an interaction round into a HIP graph and replay
+// it.  Per round the host validates and uploads the seeds (rw_batch_set_seeds); rw_batch_enqueue
+// then launches, for all images at once: seed maps, the seed gather, the per-image reduced systems
+// (Q_s^T B Q_n and Q_s^T op_ss U_hat_s), one LU per image, and a persistent reconstruction kernel
+// that walks a global list of (image, node tile) work items.  Every launch reads its sizes from
+// device descriptors, so replays stay valid when the seeds, S or C change between rounds (up to the
+// capacities given at creation).  The reconstruction's launch shape (threads per block, nodes per
+// thread) is chosen at creation by timing the candidates on the batch itself (autotuner), with the
+// choice cached per batch shape for the process and, if RW_AUTOTUNE_CACHE names a file, on disk.
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <vector>
+
+#include "rw_internal.h"
+
+namespace rw {
+
+constexpr int kBatchMaxC = 8;
+
+struct BatchImg {
+  GridDev G;
+  int normalized;
+  int m;
+  int C;              // labels this round
+  int C_cap;
+  const void* coef;
+  const void* diag;
+  const double* degree;
+  const void* dinv;
+  const void* Q;
+  const double* lambda;
+  void* U;
+  uint8_t* map;
+  int64_t seed_off;   // first seed of this image in the round's arrays
+  int64_t S;          // seeds this round (after de-duplication)
+  int64_t S_cap;
+  double *Qs, *GB, *Hs, *Us, *T, *R, *K, *Y, *stat;
+};
+
+struct BatchTile {
+  int img;
+  int pad;
+  int64_t node0;
+};
+
+struct Variant {
+  int threads;
+  int npt;
+};
+
+struct rw_batch_impl {
+  std::vector<rw_batch_image> imgs;
+  int n = 0;
+  int gdt = RW_F32, qdt = RW_F32;
+  int64_t S_total_cap = 0;
+  int64_t max_N = 0;
+  int max_m = 0;
+  // device pointers inside the caller's workspace
+  BatchImg* d_desc = nullptr;
+  LuJob* d_jobs = nullptr;
+  int64_t* d_seed_node = nullptr;
+  int32_t* d_seed_label = nullptr;
+  int32_t* d_seed_img = nullptr;
+  BatchTile* d_tiles = nullptr;
+  int64_t* d_total = nullptr;   // seeds in the current round (device copy, read by the kernels)
+  int64_t tile_cap = 0;
+  // host mirrors
+  std::vector<BatchImg> desc;
+  Variant var{256, 1};
+  int64_t ntiles = 0;
+  int64_t total_seeds = 0;
+  bool tuned_now = false;
+  bool have_seeds = false;
+  double tune_us = 0.0;
+};
+
+static size_t batch_layout(const rw_batch_image* imgs, int n, void* base, rw_batch_impl* b) {
+  Carver c(base);
+  BatchImg* desc = c.take<BatchImg>(n);
+  LuJob* jobs = c.take<LuJob>(n);
+  int64_t S_tot = 0, tiles = 0;
+  for (int i = 0; i < n; ++i) {
+    S_tot += imgs[i].S_cap;
+    tiles += (imgs[i].g->g.N + 63) / 64;   // enough for the smallest tile (64 nodes)
+  }
+  int64_t* sn = c.take<int64_t>(std::max<int64_t>(S_tot, 1));
+  int32_t* sl = c.take<int32_t>(std::max<int64_t>(S_tot, 1));
+  int32_t* si = c.take<int32_t>(std::max<int64_t>(S_tot, 1));
+  BatchTile* tl = c.take<BatchTile>(std::max<int64_t>(tiles, 1));
+  int64_t* tot = c.take<int64_t>(1);
+  if (b) {
+    b->d_desc = desc; b->d_jobs = jobs; b->d_seed_node = sn; b->d_seed_label = sl; b->d_seed_img = si;
+    b->d_tiles = tl; b->d_total = tot; b->tile_cap = tiles; b->S_total_cap = S_tot;
+    b->desc.resize(n);
+  }
+  for (int i = 0; i < n; ++i) {
+    const rw_batch_image& im = imgs[i];
+    const int64_t N = im.g->g.N, S = im.S_cap, m = im.m, Cc = im.C_cap;
+    uint8_t* map = c.take<uint8_t>(N);
+    double* Qs = c.take<double>(S * m);
+    double* GB = c.take<double>(S * m);
+    double* Hs = c.take<double>(S * Cc);
+    double* Us = c.take<double>(S * Cc);
+    double* T = c.take<double>(m * m);
+    double* R = c.take<double>(m * Cc);
+    double* K = c.take<double>(m * m);
+    double* Y = c.take<double>(m * Cc);
+    double* st = c.take<double>(8);
+    if (b) {
+      BatchImg& d = b->desc[i];
+      const Graph* g = &im.g->g;
+      d.G = grid_of(g);
+      d.normalized = g->normalized;
+      d.m = im.m;
+      d.C = 0;
+      d.C_cap = im.C_cap;
+      d.coef = g->coef; d.diag = g->diag; d.degree = g->degree; d.dinv = g->dinv;
+      d.Q = im.Q; d.lambda = im.lambda; d.U = im.U; d.map = map;
+      d.seed_off = 0; d.S = 0; d.S_cap = S;
+      d.Qs = Qs; d.GB = GB; d.Hs = Hs; d.Us = Us; d.T = T; d.R = R; d.K = K; d.Y = Y; d.stat = st;
+    }
+  }
+  return c.used;
+}
+
+// ---------------------------------------------------------------------------------------------
+// kernels (all images at once; sizes from the device descriptors)
+// ---------------------------------------------------------------------------------------------
+__global__ void k_b_clear_maps(const BatchImg* D, int n) {
+  const BatchImg& d = D[blockIdx.y];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < d.G.N; i += (int64_t)gridDim.x * blockDim.x)
+    d.map[i] = 0;
+}
+
+__global__ void k_b_set_maps(const BatchImg* D, const int64_t* node, const int32_t* label, const int32_t* img,
+                             const int64_t* total) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= *total) return;
+  D[img[k]].map[node[k]] = (uint8_t)(label[k] + 1);
+}
+
+template <typename TQ, typename TG>
+__global__ void k_b_gather(const BatchImg* D, const int64_t* node, const int32_t* label, const int32_t* img,
+                           const int64_t* total) {
+  const int64_t gk = blockIdx.x;
+  if (gk >= *total) return;
+  const BatchImg& d = D[img[gk]];
+  const GridDev& G = d.G;
+  const int64_t k = gk - d.seed_off;      // index within the image
+  const int64_t S = d.S_cap;              // leading dimension of the per-image seed arrays
+  const int64_t i = node[gk];
+  const int64_t x = i % G.nx, y = (i / G.nx) % G.ny, z = i / (G.nx * G.ny);
+  const TQ* Q = static_cast<const TQ*>(d.Q);
+  const TG* coef = static_cast<const TG*>(d.coef);
+  int64_t nb[8];
+  double cf[8];
+  int cnt = 0;
+  for (int dd = 0; dd < G.ndir; ++dd) {
+    if (head_in(G, x, y, z, dd)) { nb[cnt] = i + G.off[dd]; cf[cnt] = (double)coef[dd * G.N + i]; ++cnt; }
+    if (tail_in(G, x, y, z, dd)) { nb[cnt] = i - G.off[dd]; cf[cnt] = (double)coef[dd * G.N + i - G.off[dd]]; ++cnt; }
+  }
+  for (int j = threadIdx.x; j < d.m; j += blockDim.x) {
+    const TQ* qc = Q + (int64_t)j * G.N;
+    d.Qs[k + (int64_t)j * S] = (double)Elem<TQ>::ld(qc, i);
+    double acc = 0.0;
+    for (int t = 0; t < cnt; ++t)
+      if (d.map[nb[t]] == 0) acc -= cf[t] * (double)Elem<TQ>::ld(qc, nb[t]);
+    d.GB[k + (int64_t)j * S] = acc;
+  }
+  for (int lab = threadIdx.x; lab < d.C; lab += blockDim.x) {
+    auto uhat = [&](int64_t nd, int ml) -> double {
+      if (ml - 1 != lab) return 0.0;
+      return d.normalized ? sqrt(d.degree[nd]) : 1.0;
+    };
+    const double own = uhat(i, d.map[i]);
+    double acc = (double)static_cast<const TG*>(d.diag)[i] * own;
+    for (int t = 0; t < cnt; ++t) {
+      const int ml = d.map[nb[t]];
+      if (ml != 0) acc -= cf[t] * uhat(nb[t], ml);
+    }
+    d.Hs[k + (int64_t)lab * S] = acc;
+    d.Us[k + (int64_t)lab * S] = own;
+  }
+}
+
+// T = Q_s^T GB and R = Q_s^T Hs per image (FP64, summed over the image's S seeds in order), then
+// K = diag(lambda) - T and the right-hand side Y = R.  One thread per output entry.
+__global__ void k_b_reduced(const BatchImg* D, LuJob* jobs) {
+  const BatchImg& d = D[blockIdx.y];
+  const int m = d.m, C = d.C;
+  const int64_t S = d.S, ld = d.S_cap;
+  const int64_t total = (int64_t)m * (m + C);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % m), j = (int)(t / m);
+    const double* a = d.Qs + (int64_t)i * ld;
+    const double* b = j < m ? d.GB + (int64_t)j * ld : d.Hs + (int64_t)(j - m) * ld;
+    double acc = 0.0;
+    for (int64_t s = 0; s < S; ++s) acc += a[s] * b[s];
+    if (j < m) d.K[i + (int64_t)j * m] = (i == j ? d.lambda[i] : 0.0) - acc;
+    else d.Y[i + (int64_t)(j - m) * m] = acc;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    LuJob jb;
+    jb.A = d.K; jb.B = d.Y; jb.stat = d.stat; jb.n = m; jb.nrhs = C;
+    jobs[blockIdx.y] = jb;
+  }
+}
+
+// persistent reconstruction over the (image, tile) list
+template <typename TQ, typename TU, int NPT>
+__global__ void k_b_reconstruct(const BatchImg* D, const BatchTile* tiles, int64_t ntiles) {
+  using CT = typename Elem<TQ>::C;
+  extern __shared__ char smem[];
+  CT* sY = reinterpret_cast<CT*>(smem);
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const BatchTile tl = tiles[t];
+    const BatchImg& d = D[tl.img];
+    const int m = d.m, C = d.C;
+    __syncthreads();
+    for (int q = threadIdx.x; q < m * kBatchMaxC; q += blockDim.x) {
+      const int j = q / kBatchMaxC, c = q % kBatchMaxC;
+      sY[q] = c < C ? (CT)d.Y[j + (int64_t)c * m] : CT(0);
+    }
+    __syncthreads();
+    const TQ* Q = static_cast<const TQ*>(d.Q);
+    const int64_t N = d.G.N;
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      const int64_t i = tl.node0 + threadIdx.x + (int64_t)r * blockDim.x;
+      if (i >= N) break;
+      CT acc[kBatchMaxC];
+#pragma unroll
+      for (int c = 0; c < kBatchMaxC; ++c) acc[c] = CT(0);
+      for (int j = 0; j < m; ++j) {
+        const CT q = Elem<TQ>::ld(Q, (int64_t)j * N + i);
+#pragma unroll
+        for (int c = 0; c < kBatchMaxC; ++c) acc[c] = fma(q, sY[j * kBatchMaxC + c], acc[c]);
+      }
+      const int ml = d.map[i];
+      const CT sc = d.normalized ? (CT) static_cast<const TU*>(d.dinv)[i] : CT(1);
+      TU* U = static_cast<TU*>(d.U);
+      for (int c = 0; c < C; ++c) U[(int64_t)c * N + i] = ml ? (ml - 1 == c ? TU(1) : TU(0)) : (TU)(sc * acc[c]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------------
+static const Variant kVariants[] = {{128, 1}, {256, 1}, {256, 2}, {256, 4}, {512, 1}, {512, 2}};
+
+static std::mutex g_tune_mu;
+static std::map<std::string, Variant> g_tune_cache;
+static bool g_tune_loaded = false;
+
+static void load_tune_cache() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("RW_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::ifstream f(path);
+  std::string key;
+  int th = 0, npt = 0;
+  while (f >> key >> th >> npt) g_tune_cache[key] = Variant{th, npt};
+}
+
+static void save_tune_cache() {
+  const char* path = std::getenv("RW_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::ofstream f(path);
+  for (auto& kv : g_tune_cache) f << kv.first << " " << kv.second.threads << " " << kv.second.npt << "\n";
+}
+
+static int build_tiles(rw_batch_impl* b, Variant v, hipStream_t s) {
+  std::vector<BatchTile> tl;
+  const int64_t span = (int64_t)v.threads * v.npt;
+  for (int i = 0; i < b->n; ++i) {
+    const int64_t N = b->imgs[i].g->g.N;
+    for (int64_t n0 = 0; n0 < N; n0 += span) tl.push_back(BatchTile{i, 0, n0});
+  }
+  RW_CHECK((int64_t)tl.size() <= b->tile_cap, RW_EINVAL, "tile list exceeds its capacity");
+  RW_HIP(hipMemcpyAsync(b->d_tiles, tl.data(), tl.size() * sizeof(BatchTile), hipMemcpyHostToDevice, s));
+  RW_HIP(hipStreamSynchronize(s));
+  b->ntiles = (int64_t)tl.size();
+  return RW_OK;
+}
+
+template <typename TQ, typename TU>
+static int launch_recon_t(const rw_batch_impl* b, Variant v, hipStream_t s) {
+  const size_t sh = (size_t)b->max_m * kBatchMaxC * sizeof(typename Elem<TQ>::C);
+  const unsigned grid = (unsigned)std::min<int64_t>(b->ntiles, 1024);
+  if (grid == 0) return RW_OK;
+  if (v.npt == 1) k_b_reconstruct<TQ, TU, 1><<<grid, v.threads, sh, s>>>(b->d_desc, b->d_tiles, b->ntiles);
+  else if (v.npt == 2) k_b_reconstruct<TQ, TU, 2><<<grid, v.threads, sh, s>>>(b->d_desc, b->d_tiles, b->ntiles);
+  else k_b_reconstruct<TQ, TU, 4><<<grid, v.threads, sh, s>>>(b->d_desc, b->d_tiles, b->ntiles);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+static int launch_recon(const rw_batch_impl* b, Variant v, hipStream_t s) {
+  if (b->gdt == RW_F64) {
+    if (b->qdt == RW_F64) return launch_recon_t<double, double>(b, v, s);
+    if (b->qdt == RW_F32) return launch_recon_t<float, double>(b, v, s);
+    return launch_recon_t<uint16_t, double>(b, v, s);
+  }
+  if (b->qdt == RW_F64) return launch_recon_t<double, float>(b, v, s);
+  if (b->qdt == RW_F32) return launch_recon_t<float, float>(b, v, s);
+  return launch_recon_t<uint16_t, float>(b, v, s);
+}
+
+static int autotune(rw_batch_impl* b, hipStream_t s) {
+  std::ostringstream key;
+  int64_t work = 0;
+  for (auto& im : b->imgs) work += im.g->g.N * (int64_t)im.m;
+  key << "batch_n" << b->n << "_Nm" << work << "_g" << b->gdt << "_q" << b->qdt;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache();
+    auto it = g_tune_cache.find(key.str());
+    if (it != g_tune_cache.end()) {
+      b->var = it->second;
+      return build_tiles(b, b->var, s);
+    }
+  }
+  // the descriptors hold C = 0 until the first seeds arrive, so the timed launches write nothing;
+  // their cost is the read of every image's basis, which is what the launch shape changes
+  hipEvent_t e0, e1;
+  RW_HIP(hipEventCreate(&e0));
+  RW_HIP(hipEventCreate(&e1));
+  double best = INFINITY;
+  Variant bestv = kVariants[0];
+  auto t0 = std::chrono::steady_clock::now();
+  for (const Variant& v : kVariants) {
+    RW_TRY(build_tiles(b, v, s));
+    RW_TRY(launch_recon(b, v, s));   // warm-up
+    RW_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < 3; ++r) RW_TRY(launch_recon(b, v, s));
+    RW_HIP(hipEventRecord(e1, s));
+    RW_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    RW_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) { best = ms; bestv = v; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->tune_us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  b->tuned_now = true;
+  b->var = bestv;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key.str()] = bestv;
+    save_tune_cache();
+  }
+  return build_tiles(b, b->var, s);
+}
+
+}  // namespace rw
+
+using namespace rw;
+
+struct rw_batch_s {
+  rw_batch_impl b;
+};
+
+extern "C" {
+
+int rw_batch_workspace_bytes(const rw_batch_image* imgs, int n, size_t* bytes) {
+  RW_CHECK(imgs != nullptr && n >= 1 && n <= 65535 && bytes != nullptr, RW_EINVAL, "bad argument");
+  for (int i = 0; i < n; ++i)
+    RW_CHECK(imgs[i].g != nullptr && imgs[i].m >= 2 && imgs[i].m <= 1024 && imgs[i].S_cap >= 1 && imgs[i].C_cap >= 1 &&
+                 imgs[i].C_cap <= kBatchMaxC, RW_EINVAL, "image %d: bad sizes", i);
+  *bytes = batch_layout(imgs, n, nullptr, nullptr);
+  return RW_OK;
+}
+
+int rw_batch_create(const rw_batch_image* imgs, int n, void* work, size_t work_bytes, hipStream_t stream,
+                    rw_batch* out) {
+  size_t need = 0;
+  RW_TRY(rw_batch_workspace_bytes(imgs, n, &need));
+  RW_CHECK(work != nullptr && out != nullptr, RW_EINVAL, "null argument");
+  RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "batch workspace too small: %zu < %zu", work_bytes, need);
+  const int gdt = imgs[0].g->g.dtype, qdt = imgs[0].q_dtype;
+  for (int i = 0; i < n; ++i) {
+    const rw_batch_image& im = imgs[i];
+    RW_CHECK(im.g->g.dtype == gdt && im.q_dtype == qdt, RW_EINVAL, "all images need the same graph and Q types");
+    RW_CHECK(im.Q != nullptr && im.lambda != nullptr && im.U != nullptr, RW_EINVAL, "image %d: null pointer", i);
+    RW_CHECK(im.m <= im.g->g.N, RW_EINVAL, "image %d: m > N", i);
+    RW_CHECK((size_t)im.m * kBatchMaxC * 8 <= 65536, RW_EINVAL, "image %d: m too large", i);
+  }
+  rw_batch h = new rw_batch_s();
+  rw_batch_impl* b = &h->b;
+  b->imgs.assign(imgs, imgs + n);
+  b->n = n;
+  b->gdt = gdt;
+  b->qdt = qdt;
+  for (int i = 0; i < n; ++i) {
+    b->max_N = std::max<int64_t>(b->max_N, imgs[i].g->g.N);
+    b->max_m = std::max(b->max_m, imgs[i].m);
+  }
+  batch_layout(imgs, n, work, b);
+  hipError_t e = hipMemcpyAsync(b->d_desc, b->desc.data(), n * sizeof(BatchImg), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    delete h;
+    set_error("batch descriptors: %s", hipGetErrorString(e));
+    return RW_EHIP;
+  }
+  int st = autotune(b, stream);
+  if (st != RW_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return RW_OK;
+}
+
+int rw_batch_destroy(rw_batch h) {
+  delete h;
+  return RW_OK;
+}
+
+int rw_batch_info(rw_batch h, int* threads, int* nodes_per_thread, int* tuned_now, double* tune_us) {
+  RW_CHECK(h != nullptr, RW_EINVAL, "null batch");
+  if (threads) *threads = h->b.var.threads;
+  if (nodes_per_thread) *nodes_per_thread = h->b.var.npt;
+  if (tuned_now) *tuned_now = h->b.tuned_now ? 1 : 0;
+  if (tune_us) *tune_us = h->b.tune_us;
+  return RW_OK;
+}
+
+int rw_batch_set_seeds(rw_batch h, const int* C, const int64_t* seed_off, const int64_t* seed_node,
+                       const int32_t* seed_label, hipStream_t stream) {
+  RW_CHECK(h != nullptr && C != nullptr && seed_off != nullptr && seed_node != nullptr && seed_label != nullptr,
+           RW_EINVAL, "null argument");
+  rw_batch_impl* b = &h->b;
+  std::vector<BatchImg> nd = b->desc;   // committed only when every image validates
+  std::vector<int64_t> nodes;
+  std::vector<int32_t> labels, imgid;
+  nodes.reserve(b->S_total_cap);
+  for (int i = 0; i < b->n; ++i) {
+    BatchImg& d = nd[i];
+    const int64_t N = d.G.N;
+    RW_CHECK(C[i] >= 1 && C[i] <= d.C_cap, RW_EINVAL, "image %d: C = %d exceeds its capacity %d", i, C[i], d.C_cap);
+    RW_CHECK(seed_off[i + 1] > seed_off[i], RW_EINVAL, "image %d: at least one seed is required", i);
+    std::vector<std::pair<int64_t, int32_t>> v;
+    for (int64_t k = seed_off[i]; k < seed_off[i + 1]; ++k) {
+      RW_CHECK(seed_node[k] >= 0 && seed_node[k] < N, RW_EINVAL, "image %d: seed node out of range", i);
+      RW_CHECK(seed_label[k] >= 0 && seed_label[k] < C[i], RW_EINVAL, "image %d: seed label out of range", i);
+      v.push_back({seed_node[k], seed_label[k]});
+    }
+    std::sort(v.begin(), v.end());
+    d.seed_off = (int64_t)nodes.size();
+    for (size_t k = 0; k < v.size(); ++k) {
+      if (k && v[k].first == v[k - 1].first) {
+        RW_CHECK(v[k].second == v[k - 1].second, RW_EINVAL, "image %d: node %lld seeded with two labels", i,
+                 (long long)v[k].first);
+        continue;
+      }
+      nodes.push_back(v[k].first);
+      labels.push_back(v[k].second);
+      imgid.push_back(i);
+    }
+    d.S = (int64_t)nodes.size() - d.seed_off;
+    RW_CHECK(d.S <= d.S_cap, RW_EINVAL, "image %d: %lld seeds exceed the capacity %lld", i, (long long)d.S,
+             (long long)d.S_cap);
+    RW_CHECK(d.S < N, RW_EINVAL, "image %d: every node is a seed", i);
+    d.C = C[i];
+  }
+  b->desc.swap(nd);
+  b->total_seeds = (int64_t)nodes.size();
+  b->have_seeds = true;
+  RW_HIP(hipMemcpyAsync(b->d_seed_node, nodes.data(), nodes.size() * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+  RW_HIP(hipMemcpyAsync(b->d_seed_label, labels.data(), labels.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  RW_HIP(hipMemcpyAsync(b->d_seed_img, imgid.data(), imgid.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  RW_HIP(hipMemcpyAsync(b->d_desc, b->desc.data(), b->n * sizeof(BatchImg), hipMemcpyHostToDevice, stream));
+  RW_HIP(hipMemcpyAsync(b->d_total, &b->total_seeds, sizeof(int64_t), hipMemcpyHostToDevice, stream));
+  RW_HIP(hipStreamSynchronize(stream));
+  return RW_OK;
+}
+
+int rw_batch_enqueue(rw_batch h, hipStream_t stream) {
+  RW_CHECK(h != nullptr, RW_EINVAL, "null batch");
+  rw_batch_impl* b = &h->b;
+  RW_CHECK(b->have_seeds, RW_EINVAL, "rw_batch_set_seeds must come before the first enqueue");
+  // Every launch shape below depends on the capacities only; this round's sizes are read on the
+  // device, so a captured graph of this call stays valid for every later round.
+  const int64_t cap = std::max<int64_t>(b->S_total_cap, 1);
+  k_b_clear_maps<<<dim3((unsigned)std::min<int64_t>(nblocks(b->max_N, 256), 1024), b->n), 256, 0, stream>>>(b->d_desc,
+                                                                                                             b->n);
+  RW_LAUNCH_CHECK();
+  k_b_set_maps<<<nblocks(cap, 256), 256, 0, stream>>>(b->d_desc, b->d_seed_node, b->d_seed_label, b->d_seed_img,
+                                                      b->d_total);
+  RW_LAUNCH_CHECK();
+#define RW_BGATHER(TQ, TG)                                                                                  \
+  k_b_gather<TQ, TG><<<(unsigned)cap, 256, 0, stream>>>(b->d_desc, b->d_seed_node, b->d_seed_label, b->d_seed_img, \
+                                                        b->d_total)
+  if (b->gdt == RW_F64) {
+    if (b->qdt == RW_F64) RW_BGATHER(double, double);
+    else if (b->qdt == RW_F32) RW_BGATHER(float, double);
+    else RW_BGATHER(uint16_t, double);
+  } else {
+    if (b->qdt == RW_F64) RW_BGATHER(double, float);
+    else if (b->qdt == RW_F32) RW_BGATHER(float, float);
+    else RW_BGATHER(uint16_t, float);
+  }
+#undef RW_BGATHER
+  RW_LAUNCH_CHECK();
+  const int64_t per_img = (int64_t)b->max_m * (b->max_m + kBatchMaxC);
+  k_b_reduced<<<dim3((unsigned)std::min<int64_t>(nblocks(per_img, 256), 256), b->n), 256, 0, stream>>>(b->d_desc,
+                                                                                                      b->d_jobs);
+  RW_LAUNCH_CHECK();
+  RW_TRY(lu_solve_batched(b->d_jobs, b->n, stream));
+  RW_TRY(launch_recon(b, b->var, stream));
+  return RW_OK;
+}
+
+int rw_batch_status(rw_batch h, double* min_pivot, hipStream_t stream) {
+  RW_CHECK(h != nullptr && min_pivot != nullptr, RW_EINVAL, "null argument");
+  rw_batch_impl* b = &h->b;
+  double worst = INFINITY;
+  for (int i = 0; i < b->n; ++i) {
+    double st = 0.0;
+    RW_HIP(hipMemcpyAsync(&st, b->desc[i].stat, sizeof(double), hipMemcpyDeviceToHost, stream));
+    RW_HIP(hipStreamSynchronize(stream));
+    worst = std::min(worst, st);
+  }
+  *min_pivot = worst;
+  RW_CHECK(worst > 0.0, RW_ESINGULAR, "a reduced seed system of the batch is singular");
+  return RW_OK;
+}
+
+}  // extern "C"

@@ -454,7 +454,7 @@ int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int
 // Pivot search by wave 0 (ties -> lowest row).  stat[0] = min |pivot| / max |a_ij|, or 0 when a
 // pivot falls below 1e-14 max |a_ij| (the solve is then abandoned).
 // ---------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_lu_solve(double* A, int n, double* B, int nrhs, double* stat) {
+__device__ void lu_body(double* A, int n, double* B, int nrhs, double* stat) {
   __shared__ double s_amax, s_piv, s_minpiv;
   __shared__ int s_prow, s_bad;
   if (threadIdx.x < 64) {
@@ -536,6 +536,24 @@ __global__ __launch_bounds__(1024) void k_lu_solve(double* A, int n, double* B, 
     __syncthreads();
   }
   if (threadIdx.x == 0) stat[0] = s_minpiv / amax;
+}
+
+__global__ __launch_bounds__(1024) void k_lu_solve(double* A, int n, double* B, int nrhs, double* stat) {
+  lu_body(A, n, B, nrhs, stat);
+}
+
+// one workgroup per job; jobs (and their sizes) are read from device memory, so a captured launch
+// stays valid when the jobs are rewritten between replays
+__global__ __launch_bounds__(1024) void k_lu_solve_batched(const LuJob* jobs, int count) {
+  const LuJob j = jobs[blockIdx.x];
+  if (j.n > 0) lu_body(j.A, j.n, j.B, j.nrhs, j.stat);
+}
+
+int lu_solve_batched(const LuJob* jobs, int count, hipStream_t s) {
+  if (count <= 0) return RW_OK;
+  k_lu_solve_batched<<<count, 1024, 0, s>>>(jobs, count);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
 }
 
 int lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s) {

@@ -197,6 +197,15 @@ size_t syev_work_count(int n, int count, bool vectors, int nrhs);
 // Solve A X = B by LU with partial pivoting (A: n x n, B: n x nrhs, both destroyed/overwritten;
 // X returned in B).  stat[0] = min |pivot| / max |a_ij| (0 if a pivot is below the threshold).
 int lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s);
+struct LuJob {
+  double* A;
+  double* B;
+  double* stat;
+  int n;
+  int nrhs;
+};
+// one LU solve per job (jobs in device memory)
+int lu_solve_batched(const LuJob* jobs, int count, hipStream_t s);
 
 }  // namespace rw
 

@@ -1,0 +1,154 @@
+"""GPU parity for the batching form: many images of uneven sizes, several interaction rounds, one
+enqueue per round (captured into a HIP graph and replayed), against the single-image solve on the same
+basis and against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1607_04174_amd as rw
+import rwsynth
+from oracle.fast_rw import fast_rw
+from oracle.graph import Graph as OGraph
+
+from gpu_common import banner, dev, need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+# uneven images: 2D 4-connected (the batched workload's graphs), one 8-connected, one 3D volume
+SHAPES = [((37, 29, 1), 4, 12), ((64, 48, 1), 4, 30), ((20, 90, 1), 4, 50), ((51, 51, 1), 8, 30),
+          ((12, 10, 9), 6, 20), ((129, 7, 1), 4, 8)]
+
+
+def _images(gdt, qdt, rounds=4, seed=0):
+    out = []
+    for k, (dims, conn, m) in enumerate(SHAPES):
+        w = rwsynth.Workload(f"b{k}", 500 + k, dims, conn, 90.0, m, 2, 10, 0.05, 4, "cycle", 0.0, "f64")
+        J, rid = rwsynth.phantom(w, seed)
+        g64 = rw.Graph(to_dev(J, torch.float64), w.dims, w.conn, w.beta, dtype=torch.float64)
+        Q, lam, _ = rw.precompute_eig(g64, m, tol=1e-10, max_iter=400)
+        g = g64 if gdt == torch.float64 else rw.Graph(to_dev(J, torch.float64), w.dims, w.conn, w.beta, dtype=gdt)
+        Qc = Q if qdt == torch.float64 else rw.convert_block(Q, qdt)
+        rnds = []
+        for r in range(rounds):
+            rnds.append(rwsynth.cfg4_round(w, rid, r, seed))
+        out.append(dict(w=w, J=J, graph=g, Q=Qc, lam=lam, rounds=rnds,
+                        S_cap=max(len(r[1]) for r in rnds), C_cap=4))
+    return out
+
+
+def _single(im, C, node, lab):
+    U, _ = rw.solve_seeds(im["graph"], im["Q"], im["lam"], node, lab, C)
+    return U
+
+
+def _tol(gdt, qdt):
+    if gdt == torch.float64 and qdt == torch.float64:
+        return 1e-10
+    return 1e-5 if qdt != torch.bfloat16 else 1e-2
+
+
+@pytest.mark.parametrize("gdt,qdt", [(torch.float64, torch.float64), (torch.float32, torch.float32),
+                                     (torch.float32, torch.bfloat16)], ids=["f64", "f32", "bf16"])
+def test_batch_rounds_match_single_image_solves(gdt, qdt):
+    need_gpu()
+    banner(f"batch eager {gdt} {qdt}")
+    ims = _images(gdt, qdt)
+    bs = rw.BatchSolver(ims, use_graph=False)
+    info = bs.info()
+    assert info["threads"] in (128, 256, 512) and info["nodes_per_thread"] in (1, 2, 4)
+    tol = _tol(gdt, qdt)
+    for r in range(len(ims[0]["rounds"])):
+        bs.set_seeds([im["rounds"][r] for im in ims])
+        bs.run()
+        assert bs.status() > 0
+        for i, (im, Ub) in enumerate(zip(ims, bs.outputs())):
+            C, node, lab = im["rounds"][r]
+            Us = _single(im, C, node, lab)
+            assert Ub.shape == Us.shape
+            err = (Ub.double() - Us.double()).abs().max().item()
+            # FP64: reductions in another order only; FP32/BF16: the single path's BF16 reconstruction runs on
+            # the matrix cores (Y rounded to two BF16 parts), the batched one on FP32 vector units
+            assert err <= tol, (r, i, err)
+            np.testing.assert_array_equal(Ub.double().cpu().numpy()[lab, node], 1.0)
+
+
+def test_batch_fp64_against_oracle():
+    need_gpu()
+    banner("batch oracle")
+    ims = _images(torch.float64, torch.float64, rounds=2)
+    bs = rw.BatchSolver(ims, use_graph=False)
+    for r in range(2):
+        bs.set_seeds([im["rounds"][r] for im in ims])
+        bs.run()
+        for i, (im, Ub) in enumerate(zip(ims, bs.outputs())):
+            C, node, lab = im["rounds"][r]
+            lam = im["lam"].cpu().numpy()
+            if np.min(np.abs(lam[1:])) < 1e-6:
+                continue        # the oracle's bordered system needs exact arithmetic there: covered by the solve tests
+            w = im["w"]
+            og = OGraph(im["J"], w.dims, w.conn, w.beta)
+            Uo = fast_rw(og, im["Q"].cpu().numpy().T, lam, node, lab, C)
+            err = np.abs(Ub.cpu().numpy().T - Uo).max()
+            assert err <= 1e-10 * max(1.0, np.abs(Uo).max()), (r, i, err)
+
+
+def test_batch_graph_replays_match_eager():
+    """Capture the round's enqueue into a HIP graph, replay it for rounds with other C and seed counts,
+    with eager work and synchronizations between the replays, and check every replay."""
+    need_gpu()
+    banner("batch graph replay")
+    ims = _images(torch.float32, torch.float32, rounds=5)
+    eager = rw.BatchSolver(ims, use_graph=False)
+    graphed = rw.BatchSolver(ims, use_graph=True)
+    for r in range(5):
+        rnd = [im["rounds"][r] for im in ims]
+        graphed.set_seeds(rnd)
+        graphed.run()
+        junk = torch.randn(1 << 20, device=dev()).sum()          # unrelated eager work between replays
+        torch.cuda.synchronize()
+        eager.set_seeds(rnd)
+        eager.run()
+        torch.cuda.synchronize()
+        assert graphed.status() > 0
+        for i, (Ug, Ue) in enumerate(zip(graphed.outputs(), eager.outputs())):
+            assert torch.equal(Ug, Ue), (r, i, (Ug - Ue).abs().max().item())
+        del junk
+    assert graphed.graph is not None
+
+
+def test_batch_rejects_bad_rounds_and_keeps_the_last_good_one():
+    need_gpu()
+    banner("batch validation")
+    ims = _images(torch.float64, torch.float64, rounds=1)
+    bs = rw.BatchSolver(ims, use_graph=False)
+    good = [im["rounds"][0] for im in ims]
+    bs.set_seeds(good)
+    bad = list(good)
+    C, node, lab = good[1]
+    bad[1] = (5, node, lab)                                           # C above the capacity (4)
+    with pytest.raises(rw.RWError):
+        bs.set_seeds(bad)
+    bad[1] = (C, np.concatenate([node, [node[0]]]), np.concatenate([lab, [(lab[0] + 1) % C]]))   # two labels
+    with pytest.raises(rw.RWError):
+        bs.set_seeds(bad)
+    bad[1] = (C, np.concatenate([node, [ims[1]["w"].N]]), np.concatenate([lab, [0]]))          # out of range
+    with pytest.raises(rw.RWError):
+        bs.set_seeds(bad)
+    extra = np.setdiff1d(np.arange(ims[1]["w"].N), node)[: ims[1]["S_cap"]]
+    bad[1] = (C, np.concatenate([node, extra]), np.concatenate([lab, np.zeros(extra.size, np.int32)]))
+    with pytest.raises(rw.RWError):                                   # more seeds than S_cap
+        bs.set_seeds(bad)
+    bs.run()                                                          # still the good round
+    for im, Ub in zip(ims, bs.outputs()):
+        C, node, lab = im["rounds"][0]
+        assert (Ub - _single(im, C, node, lab)).abs().max().item() <= 1e-10
+
+
+def test_batch_autotune_cache():
+    need_gpu()
+    ims = _images(torch.float32, torch.float32, rounds=1)
+    a = rw.BatchSolver(ims, use_graph=False)
+    b = rw.BatchSolver(ims, use_graph=False)
+    ia, ib = a.info(), b.info()
+    assert not ib["tuned_now"]
+    assert (ia["threads"], ia["nodes_per_thread"]) == (ib["threads"], ib["nodes_per_thread"])
