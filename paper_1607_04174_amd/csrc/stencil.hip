@@ -2,14 +2,23 @@
 // block, op = L_hat = I - D^{-1/2} W D^{-1/2} (zero rows where d = 0) or L = D - W (Sec. II-A, Sec. II-C).
 //
 // Per node the operator needs the diagonal and the coefficients of its 4/8/6 incident edges:
-// forward edges are stored at the node, backward ones at the neighbour (the edge's tail).  One
-// thread owns one node, loads its coefficients once and sweeps every column of the block, so the
-// coefficient planes are read once per launch while X and Y stream through.
+// forward edges are stored at the node, backward ones at the neighbour (the edge's tail).
+//
+// Main kernel (k_stencil_strip): each thread owns a strip of R nodes along y (2D) or z (3D) at one x,
+// holds their coefficients in registers, and walks its group of columns.  Per column it loads the
+// strip's centre values plus one row above and below once (register window, so the strip direction's
+// neighbours are not re-read), the x +- 1 values, and in 3D the y +- 1 values; the next column's
+// window is loaded before the current one is computed (two windows in flight).  Y is written with
+// non-temporal stores (it is not re-read by this launch).  The columns are split into G groups on
+// gridDim.y so that small grids still fill the chip; tiles are dealt to the 8 XCDs in contiguous
+// ranges (workgroup w runs on XCD w mod 8), so the rows a tile shares with its neighbours sit in the
+// same L2.  Byte offsets within a column are 32-bit; larger grids take the plain one-node-per-thread
+// kernel (k_stencil_wide).
 #include "rw_internal.h"
 
 namespace rw {
 
-template <typename T, int NDIR>
+template <typename T>
 struct StencilArgs {
   GridDev G;
   const T* X;
@@ -21,8 +30,166 @@ struct StencilArgs {
   typename Elem<T>::C alpha, beta, gamma;
 };
 
+struct StripMap {
+  int tiles_x;   // 64-wide tiles along x
+  int tiles_y;   // 3D: 4-row tiles along y
+  int ntiles;
+  int per_xcd;   // tiles per XCD (gridDim.x = 8 * per_xcd)
+  int cpg;       // columns per group (gridDim.y groups)
+};
+
+__device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+
+template <typename T, int NDIR, int R>
+__global__ __launch_bounds__(256) void k_stencil_strip(StencilArgs<T> a, StripMap tm) {
+  using C = typename Elem<T>::C;
+  constexpr bool D3 = NDIR == 3;
+  constexpr bool DIAG = NDIR == 4;
+  const int bid = blockIdx.x;
+  const int tile = (bid & 7) * tm.per_xcd + (bid >> 3);
+  if (tile >= tm.ntiles) return;
+  const int nx = (int)a.G.nx, ny = (int)a.G.ny, nz = (int)a.G.nz, N = (int)a.G.N;
+  const int tx = tile % tm.tiles_x;
+  const int t2 = tile / tm.tiles_x;
+  const int x = tx * 64 + threadIdx.x;
+  int y = 0, s0 = 0;     // 3D: y row and first z of the strip; 2D: first y of the strip
+  if constexpr (D3) {
+    y = (t2 % tm.tiles_y) * 4 + threadIdx.y;
+    s0 = (t2 / tm.tiles_y) * R;
+    if (x >= nx || y >= ny) return;
+  } else {
+    s0 = (t2 * 4 + threadIdx.y) * R;
+    if (x >= nx || s0 >= ny) return;
+  }
+  const int plane = nx * ny;
+  // window rows p = 0..R+1 are strip positions s0 - 1 .. s0 + R (clamped; their coefficients are 0)
+  uint32_t oc[R + 2], ol[R + 2], orr[R + 2];
+#pragma unroll
+  for (int p = 0; p < R + 2; ++p) {
+    const int row = D3 ? nx * y + plane * clampi(s0 + p - 1, nz) : nx * clampi(s0 + p - 1, ny);
+    oc[p] = (uint32_t)(x + row) * (uint32_t)sizeof(T);
+    ol[p] = (uint32_t)(clampi(x - 1, nx) + row) * (uint32_t)sizeof(T);
+    orr[p] = (uint32_t)(clampi(x + 1, nx) + row) * (uint32_t)sizeof(T);
+  }
+  uint32_t oyp[R], oym[R];
+  C c[R][2 * NDIR];
+  C dg[R];
+  bool ok[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    int yy, zz;
+    if constexpr (D3) {
+      yy = y;
+      zz = s0 + k;
+      ok[k] = zz < nz;
+      zz = clampi(zz, nz);
+      oyp[k] = (uint32_t)(x + nx * clampi(yy + 1, ny) + plane * zz) * (uint32_t)sizeof(T);
+      oym[k] = (uint32_t)(x + nx * clampi(yy - 1, ny) + plane * zz) * (uint32_t)sizeof(T);
+    } else {
+      yy = s0 + k;
+      zz = 0;
+      ok[k] = yy < ny;
+      yy = clampi(yy, ny);
+    }
+    const int i = x + nx * yy + plane * zz;
+    dg[k] = ok[k] ? (C)a.diag[i] : C(0);
+#pragma unroll
+    for (int d = 0; d < NDIR; ++d) {
+      const int hx = x + a.G.dx[d], hy = yy + a.G.dy[d], hz = zz + a.G.dz[d];
+      const bool f = ok[k] && hx >= 0 && hx < nx && hy >= 0 && hy < ny && hz >= 0 && hz < nz;
+      c[k][d] = f ? (C)a.coef[d * N + i] : C(0);
+      const int ux = x - a.G.dx[d], uy = yy - a.G.dy[d], uz = zz - a.G.dz[d];
+      const bool t = ok[k] && ux >= 0 && ux < nx && uy >= 0 && uy < ny && uz >= 0 && uz < nz;
+      c[k][NDIR + d] = t ? (C)a.coef[d * N + i - (int)a.G.off[d]] : C(0);
+    }
+  }
+  const int c0 = blockIdx.y * tm.cpg;
+  const int c1 = (int)min((int64_t)c0 + tm.cpg, a.b);
+  if (c0 >= c1) return;
+  const size_t cs = (size_t)N * sizeof(T);
+  struct Win {
+    C cen[R + 2], lf[R + 2], rt[R + 2];
+    C yp[R], ym[R];
+  };
+  auto ld = [](const char* p, uint32_t o) -> C { return (C)*reinterpret_cast<const T*>(p + o); };
+  auto load = [&](Win& w, const char* p) {
+#pragma unroll
+    for (int q = 0; q < R + 2; ++q) {
+      w.cen[q] = ld(p, oc[q]);
+      if (DIAG || (q >= 1 && q <= R)) {
+        w.lf[q] = ld(p, ol[q]);
+        w.rt[q] = ld(p, orr[q]);
+      } else {
+        w.lf[q] = C(0);
+        w.rt[q] = C(0);
+      }
+    }
+    if constexpr (D3) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        w.yp[k] = ld(p, oyp[k]);
+        w.ym[k] = ld(p, oym[k]);
+      }
+    }
+  };
+  const C al = a.alpha, be = a.beta, ga = a.gamma;
+  const bool useZ = a.Z != nullptr;
+  auto compute = [&](const Win& w, char* q, const char* zc) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int p = k + 1;
+      const C xi = w.cen[p];
+      C acc = dg[k] * xi;
+      // heads d = 0..NDIR-1, then tails (the edge order the graph defines)
+      if constexpr (NDIR == 2) {
+        acc -= c[k][0] * w.rt[p];
+        acc -= c[k][1] * w.cen[p + 1];
+        acc -= c[k][2] * w.lf[p];
+        acc -= c[k][3] * w.cen[p - 1];
+      } else if constexpr (NDIR == 4) {
+        acc -= c[k][0] * w.rt[p];
+        acc -= c[k][1] * w.cen[p + 1];
+        acc -= c[k][2] * w.rt[p + 1];
+        acc -= c[k][3] * w.rt[p - 1];
+        acc -= c[k][4] * w.lf[p];
+        acc -= c[k][5] * w.cen[p - 1];
+        acc -= c[k][6] * w.lf[p - 1];
+        acc -= c[k][7] * w.lf[p + 1];
+      } else {
+        acc -= c[k][0] * w.rt[p];
+        acc -= c[k][1] * w.yp[k];
+        acc -= c[k][2] * w.cen[p + 1];
+        acc -= c[k][3] * w.lf[p];
+        acc -= c[k][4] * w.ym[k];
+        acc -= c[k][5] * w.cen[p - 1];
+      }
+      C out = al * acc;
+      if (be != C(0)) out += be * xi;
+      if (useZ) out += ga * ld(zc, oc[p]);
+      if (ok[k]) __builtin_nontemporal_store((T)out, reinterpret_cast<T*>(q + oc[p]));
+    }
+  };
+  const char* xb = reinterpret_cast<const char*>(a.X) + (size_t)c0 * cs;
+  char* yb = reinterpret_cast<char*>(a.Y) + (size_t)c0 * cs;
+  const char* zb = useZ ? reinterpret_cast<const char*>(a.Z) + (size_t)c0 * cs : nullptr;
+  Win w0, w1;
+  load(w0, xb);
+  int col = c0;
+  for (; col + 2 <= c1; col += 2) {
+    load(w1, xb + cs);
+    compute(w0, yb, zb);
+    if (col + 2 < c1) load(w0, xb + 2 * cs);
+    compute(w1, yb + cs, useZ ? zb + cs : nullptr);
+    xb += 2 * cs;
+    yb += 2 * cs;
+    if (useZ) zb += 2 * cs;
+  }
+  if (col < c1) compute(w0, yb, zb);
+}
+
+// one node per thread, all columns, 64-bit indexing (grids whose columns exceed 32-bit byte offsets)
 template <typename T, int NDIR>
-__global__ __launch_bounds__(256) void k_stencil(StencilArgs<T, NDIR> a) {
+__global__ __launch_bounds__(256) void k_stencil_wide(StencilArgs<T> a) {
   using C = typename Elem<T>::C;
   const GridDev& G = a.G;
   const int64_t x = blockIdx.x * (int64_t)64 + threadIdx.x;
@@ -56,11 +223,35 @@ __global__ __launch_bounds__(256) void k_stencil(StencilArgs<T, NDIR> a) {
   }
 }
 
+// Strip length and column groups.  2D: R = 2; 3D: R = 4.  Groups: enough threads to cover the chip
+// about once (256 CUs x 1024 threads), at least 4 columns per group, at most 8 groups.
+template <int NDIR>
+static StripMap strip_map(const Graph* g, int R, int64_t b, dim3* grid) {
+  StripMap tm;
+  tm.tiles_x = (int)nblocks(g->nx, 64);
+  int64_t strips;
+  if (NDIR == 3) {
+    tm.tiles_y = (int)nblocks(g->ny, 4);
+    strips = (int64_t)tm.tiles_x * tm.tiles_y * nblocks(g->nz, R);
+    tm.ntiles = (int)strips;
+  } else {
+    tm.tiles_y = 0;
+    tm.ntiles = (int)((int64_t)tm.tiles_x * nblocks(nblocks(g->ny, R), 4));
+  }
+  const int64_t threads = (int64_t)tm.ntiles * 256;
+  int G = 1;
+  while (G < 8 && threads * G < (int64_t)256 * 1024 && (b + 2 * G - 1) / (2 * G) >= 4) G *= 2;
+  tm.cpg = (int)((b + G - 1) / G);
+  tm.per_xcd = (tm.ntiles + 7) / 8;
+  *grid = dim3((unsigned)(tm.per_xcd * 8), (unsigned)G);
+  return tm;
+}
+
 template <typename T, int NDIR>
 static int launch(const Graph* g, const void* X, void* Y, const void* Z, int64_t b, double alpha,
                   double beta, double gamma, hipStream_t s) {
   using C = typename Elem<T>::C;
-  StencilArgs<T, NDIR> a;
+  StencilArgs<T> a;
   a.G = grid_of(g);
   a.X = static_cast<const T*>(X);
   a.Y = static_cast<T*>(Y);
@@ -72,8 +263,21 @@ static int launch(const Graph* g, const void* X, void* Y, const void* Z, int64_t
   a.beta = (C)beta;
   a.gamma = (C)gamma;
   dim3 block(64, 4);
-  dim3 grid(nblocks(g->nx, 64), nblocks(g->ny * g->nz, 4));
-  k_stencil<T, NDIR><<<grid, block, 0, s>>>(a);
+  const bool narrow = (uint64_t)g->N * sizeof(T) <= 0xffffffffull && b < (int64_t)1 << 30;
+  if (narrow) {
+    dim3 grid;
+    if constexpr (NDIR == 3) {
+      StripMap tm = strip_map<NDIR>(g, 4, b, &grid);
+      k_stencil_strip<T, NDIR, 4><<<grid, block, 0, s>>>(a, tm);
+    } else {
+      StripMap tm = strip_map<NDIR>(g, 2, b, &grid);
+      k_stencil_strip<T, NDIR, 2><<<grid, block, 0, s>>>(a, tm);
+    }
+  } else {
+    RW_CHECK(g->ny * g->nz < (int64_t)4 * 65535, RW_EINVAL, "grid too tall for the stencil launch");
+    dim3 grid(nblocks(g->nx, 64), nblocks(g->ny * g->nz, 4));
+    k_stencil_wide<T, NDIR><<<grid, block, 0, s>>>(a);
+  }
   RW_LAUNCH_CHECK();
   return RW_OK;
 }
@@ -81,7 +285,6 @@ static int launch(const Graph* g, const void* X, void* Y, const void* Z, int64_t
 int stencil_apply(const Graph* g, const void* X, void* Y, const void* Z, int64_t b, double alpha,
                   double beta, double gamma, hipStream_t s) {
   if (b <= 0) return RW_OK;
-  RW_CHECK(g->ny * g->nz < (int64_t)4 * 65535, RW_EINVAL, "grid too tall for the stencil launch");
   if (g->dtype == RW_F64) {
     switch (g->ndir) {
       case 2: return launch<double, 2>(g, X, Y, Z, b, alpha, beta, gamma, s);
