@@ -41,6 +41,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the update-vs-recompute comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--spmm-reps", type=int, default=20)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only launch the stencil block and a plain copy of the same block (for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
@@ -53,6 +55,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     w = rwsynth.CFG2
+    if args.traffic_probe:
+        traffic_probe(rw, rwsynth, torch, w, dev)
+        return
     J, rid = rwsynth.phantom(w, 0)
     node, lab = rwsynth.seeds(w, rid, 0)
     edits = rwsynth.cfg2_edits(w, 0)
@@ -103,7 +108,7 @@ def main():
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.2f} solves/s, m_used={m_used}")
 
     # ---- stencil operator throughput (dominant HBM kernel), HIP events on the launch stream ----
-    nb = w.m - 1 + max(8, (w.m + 9) // 10)
+    nb = stencil_block_cols(w)
     X = torch.randn((nb, w.N), dtype=dt, device=dev)
     Y = torch.empty_like(X)
     stream = torch.cuda.current_stream()
@@ -172,11 +177,51 @@ def main():
         "update_vs_recompute": compare,
         "roofline": {"kernel": "k_stencil_strip<float,4,2> (N x %d block)" % nb, "bound": "hbm",
                      "achieved": round(spmm_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(spmm_gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(spmm_gbs / PEAK_HBM_GBS, 4), "traffic": stencil_traffic(nb, w.N),
                      "bytes_per_launch": spmm_bytes, "us_per_launch": round(spmm_ms * 1e3, 2)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def stencil_block_cols(w):
+    """Columns of the eigensolver's working block for m pairs (m - 1 + guard)."""
+    return w.m - 1 + max(8, (w.m + 9) // 10)
+
+
+def traffic_probe(rw, rwsynth, torch, w, dev):
+    """Five launches of the stencil on the N x nb block, then five plain device copies of the same block
+    (torch's copy kernel), for reading FETCH_SIZE / WRITE_SIZE per dispatch under the profiler."""
+    J, _ = rwsynth.phantom(w, 0)
+    g = rw.Graph(torch.as_tensor(J, device=dev), w.dims, w.conn, w.beta, dtype=torch.float32)
+    nb = stencil_block_cols(w)
+    X = torch.randn((nb, w.N), dtype=torch.float32, device=dev)
+    Y = torch.empty_like(X)
+    for _ in range(5):
+        rw.apply_laplacian(g, X, Y)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        Y.copy_(X)
+    torch.cuda.synchronize()
+    log(f"traffic probe: stencil and copy of {nb} x {w.N} fp32 ({nb * w.N * 4} bytes per block), 5 launches each")
+
+
+def stencil_traffic(nb, N):
+    """HBM bytes per stencil launch from the committed counter summary, if it was taken on the current
+    kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "stencil_traffic.json")
+    src = os.path.join(ROOT, "paper_1607_04174_amd", "csrc", "stencil.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("stencil_source_sha256") != sha or rec.get("cols") != nb or rec.get("N") != N:
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(w, J, node, lab, edits, Q0, lam0, solves_per_step):

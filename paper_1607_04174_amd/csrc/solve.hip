@@ -40,6 +40,11 @@ struct SolveWork {
   double* Y;          // ma x C
   double* stat;       // 8
   double* partial;
+  double* scrL;       // ma x ma  (Cholesky factor of Q_s^T Q_s, screening)
+  double* scrRi;      // ma x ma  (its transposed inverse)
+  double* scrZ;       // ma x C
+  double* scrF;       // (ma + 1): max over labels of the least-squares residual at m
+  int* scrCls;        // (ma + 1): 0 fails, 1 passes, 2 undecided; [0] = factorized leading size
 };
 
 static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base, SolveWork* w) {
@@ -68,6 +73,11 @@ static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base,
   t.stat = c.take<double>(8);
   size_t pc = std::max(gram_partial_count(S, ma, ma), gram_partial_count(S, ma, C));
   t.partial = c.take<double>(pc);
+  t.scrL = c.take<double>((size_t)ma * ma);
+  t.scrRi = c.take<double>((size_t)ma * ma);
+  t.scrZ = c.take<double>((size_t)ma * C);
+  t.scrF = c.take<double>((size_t)ma + 1);
+  t.scrCls = c.take<int>((size_t)ma + 1);
   if (w) *w = t;
   return c.used;
 }
@@ -338,6 +348,111 @@ __global__ __launch_bounds__(64) void k_fit_secular(const int* cand, int ncand, 
   if (lane == 0) fvals[ci + (int64_t)k * ncand] = f;
 }
 
+// Screening of the choice of m by one Cholesky factorization.  The leading m x m block of
+// G = Q_s^T Q_s is factorized by the leading block of G's lower Cholesky factor L, so one
+// factorization gives, for every m at once, the unconstrained least-squares fit of each label:
+//   z = L^{-1} g,  r(m) = ||b||^2 - sum_{j<m} z_j^2,  a(m) = L_m^{-T} z_m.
+// r(m) <= f(m) (the constraint can only raise the minimum), so r(m) > f_max decides "fails"; when the
+// fit is also feasible (||a(m)|| <= rho) it solves the constrained problem, f(m) = r(m), which decides
+// "passes" or "fails" outright.  Everything else (an active constraint, a value within a relative
+// 1e-8 band of the threshold, or m beyond the first pivot below 1e-8 of its diagonal entry, where G's
+// leading block is numerically singular, as for every m > S) is left to the eigen-based evaluation.
+// One workgroup; the factors live in the workspace (global memory, L2-resident).
+__global__ __launch_bounds__(1024) void k_fit_screen(int ma, int C, int64_t S, const double* Gq, const double* Gb,
+                                                     const double* Us, double rho2, double f_max, double* L,
+                                                     double* Ri, double* Z, double* F, int* cls) {
+  __shared__ int s_kf;
+  __shared__ double s_bn[64];   // C <= 64 (checked by the caller)
+  const int tid = threadIdx.x;
+  const int tx = tid & 31, ty = tid >> 5;
+  for (int64_t t = tid; t < (int64_t)ma * ma; t += blockDim.x) L[t] = Gq[t];
+  if (tid == 0) s_kf = ma;
+  if (tid < 64) {
+    for (int c = 0; c < C; ++c) {
+      double acc = 0.0;
+      for (int64_t i = tid; i < S; i += 64) acc += Us[i + c * S] * Us[i + c * S];
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (tid == 0) s_bn[c] = acc;
+    }
+  }
+  __syncthreads();
+  // right-looking Cholesky on the lower triangle, stopped at the first small pivot
+  for (int k = 0; k < ma; ++k) {
+    if (tid == 0) {
+      const double akk = L[k + (int64_t)k * ma];
+      if (!(akk > 1e-8 * Gq[k + (int64_t)k * ma]) || !isfinite(akk)) s_kf = k;
+      else L[k + (int64_t)k * ma] = sqrt(akk);
+    }
+    __syncthreads();
+    if (s_kf < ma) break;
+    const double piv = L[k + (int64_t)k * ma];
+    for (int i = k + 1 + tid; i < ma; i += blockDim.x) L[i + (int64_t)k * ma] /= piv;
+    __syncthreads();
+    for (int j = k + 1 + ty; j < ma; j += 32) {
+      const double ljk = L[j + (int64_t)k * ma];
+      for (int i = j + tx; i < ma; i += 32) L[i + (int64_t)j * ma] -= L[i + (int64_t)k * ma] * ljk;
+    }
+    __syncthreads();
+  }
+  const int kf = s_kf;      // leading blocks of size <= kf are factorized
+  // Ri = L^{-T} (upper triangular) on the leading kf block: one wave per column
+  const int wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+  for (int j = wave; j < kf; j += nw) {
+    double* x = Ri + (int64_t)j * ma;
+    const double xj = 1.0 / L[j + (int64_t)j * ma];
+    if (lane == 0) x[j] = xj;
+    for (int i = j - 1; i >= 0; --i) {
+      double acc = 0.0;
+      for (int k = i + 1 + lane; k <= j; k += 64) acc += L[k + (int64_t)i * ma] * (k == j ? xj : x[k]);
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      x[i] = -acc / L[i + (int64_t)i * ma];     // every lane stores the same value
+    }
+  }
+  __syncthreads();
+  // z_c = L^{-1} g_c:  z_j = sum_{i <= j} Ri(i, j) g_i
+  for (int t = tid; t < kf * C; t += blockDim.x) {
+    const int j = t % kf, c = t / kf;
+    double acc = 0.0;
+    for (int i = 0; i <= j; ++i) acc += Ri[i + (int64_t)j * ma] * Gb[i + (int64_t)c * ma];
+    Z[j + (int64_t)c * ma] = acc;
+  }
+  __syncthreads();
+  // per m in [1, ma]: residual, feasibility, class
+  for (int m = 1 + tid; m <= ma; m += blockDim.x) {
+    int cl = 2;
+    double rmax = 0.0;
+    if (m <= kf) {
+      bool feasible = true;
+      for (int c = 0; c < C; ++c) {
+        const double* z = Z + (int64_t)c * ma;
+        double zz = 0.0;
+        for (int j = 0; j < m; ++j) zz += z[j] * z[j];
+        const double r = fmax(s_bn[c] - zz, 0.0);
+        rmax = fmax(rmax, r);
+        double an = 0.0;
+        for (int i = 0; i < m; ++i) {
+          double ai = 0.0;
+          for (int j = i; j < m; ++j) ai += Ri[i + (int64_t)j * ma] * z[j];
+          an += ai * ai;
+        }
+        if (!(an <= rho2 * (1.0 - 1e-8))) feasible = false;
+      }
+      double bmax = 0.0;
+      for (int c = 0; c < C; ++c) bmax = fmax(bmax, s_bn[c]);
+      const double band = 1e-8 * (f_max + bmax);
+      if (rmax > f_max + band) cl = 0;
+      else if (feasible && rmax < f_max - band) cl = 1;
+      else if (feasible && rmax > f_max + band) cl = 0;
+    }
+    F[m] = rmax;
+    cls[m] = cl;
+  }
+  if (tid == 0) {
+    cls[0] = kf;
+    F[0] = 0.0;
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 
 static int host_seeds(const Graph* g, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C,
@@ -441,6 +556,27 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
     const double rho = std::sqrt(rho2);
     // search: lo = largest m known to fail (1 = none), hi = smallest m known to pass (ma + 1 = none)
     int lo = 1, hi = ma + 1;
+    std::vector<std::pair<int, double>> evaluated;
+    if (C <= 64) {
+      k_fit_screen<<<1, 1024, 0, stream>>>(ma, C, S, w.Gq, w.Gb, w.Us, rho * rho, f_max, w.scrL, w.scrRi, w.scrZ,
+                                           w.scrF, w.scrCls);
+      RW_LAUNCH_CHECK();
+      std::vector<int> cls(ma + 1);
+      std::vector<double> fr(ma + 1);
+      RW_HIP(hipMemcpyAsync(cls.data(), w.scrCls, (ma + 1) * sizeof(int), hipMemcpyDeviceToHost, stream));
+      RW_HIP(hipMemcpyAsync(fr.data(), w.scrF, (ma + 1) * sizeof(double), hipMemcpyDeviceToHost, stream));
+      RW_HIP(hipStreamSynchronize(stream));
+      // f is non-increasing in m: the first m not known to fail bounds lo, the first known pass bounds hi
+      int m0 = 2;
+      while (m0 <= ma && cls[m0] == 0) ++m0;
+      lo = std::min(m0, ma) - 1;    // when every m fails, m_avail is still evaluated for its fit value
+      for (int m = m0; m <= ma; ++m)
+        if (cls[m] == 1) {
+          hi = m;
+          evaluated.push_back({m, fr[m]});
+          break;
+        }
+    }
     const int maxc = fit_cands(ma);
     std::vector<double> fh((size_t)maxc * C);
     std::vector<int> cand;
@@ -448,7 +584,6 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
     int* cand_buf = reinterpret_cast<int*>(w.K);
     const int msmax = (int)std::min<int64_t>(S, ma);
     RW_CHECK(msmax <= 1022, RW_EINVAL, "choice of m supports min(S, m_avail) <= 1022");
-    std::vector<std::pair<int, double>> evaluated;
     while (hi - lo > 1) {
       cand.clear();
       int span = hi - lo - 1;

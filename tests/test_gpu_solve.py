@@ -95,11 +95,13 @@ def test_solve_rows_sum_to_one_and_seed_validation():
         assert ei.value.status == rw.RW_EINVAL
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_choice_of_m_matches_oracle(seed):
+@pytest.mark.parametrize("seed,per,m", [(0, 5, 48), (1, 5, 48), (2, 5, 48), (3, 30, 60), (4, 40, 70)])
+def test_choice_of_m_matches_oracle(seed, per, m):
+    """Few seeds (the chosen m exceeds S: decided by the per-candidate eigendecompositions) and many
+    seeds (the chosen m is below S: decided by the Cholesky screen)."""
     need_gpu()
-    banner(f"choice of m seed={seed}")
-    w = rwsynth.small("cm", (24, 22), 4, m=48, C=3, seeds_per_label=5, n_shapes=3, config_id=200 + seed)
+    banner(f"choice of m seed={seed} per={per} m={m}")
+    w = rwsynth.small("cm", (24, 22), 4, m=m, C=3, seeds_per_label=per, n_shapes=3, config_id=200 + seed)
     J, rid, node, lab = setup_case(w, seed)
     og = OGraph(J, w.dims, w.conn, w.beta)
     lam, Q = dense_eigpairs(og, w.m)
@@ -115,5 +117,8 @@ def test_choice_of_m_matches_oracle(seed):
         else:
             np.testing.assert_allclose(info["f_worst"], f.max(), rtol=1e-8, atol=1e-12)
         mu = info["m_used"]
-        Uo = fast_rw(og, Q, lam, node, lab, w.C, m=mu, exact=_needs_exact(lam[:mu]))
+        exact = _needs_exact(lam[:mu])
+        if exact and node.size > 40:
+            continue        # the rational oracle is too slow at this S; the solve itself is pinned above
+        Uo = fast_rw(og, Q, lam, node, lab, w.C, m=mu, exact=exact)
         assert np.abs(U.cpu().numpy().T - Uo).max() < 1e-10
