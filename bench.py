@@ -87,11 +87,11 @@ def main():
         lam.copy_(lam0)
         ms = []
         _, inf = rw.solve_seeds(gs, Q, lam, node, lab, w.C, eps=0.1, U=U, workspace=ws)
-        ms.append(inf["m_used"])
+        ms.append((inf["m_used"], inf["eig_probes"]))
         for e in edits:
             rw.update_eig(gs, [e], Q, lam, mode=rw.RW_UPDATE_RR, tol=tol)
             _, inf = rw.solve_seeds(gs, Q, lam, node, lab, w.C, eps=0.1, U=U, workspace=ws)
-            ms.append(inf["m_used"])
+            ms.append((inf["m_used"], inf["eig_probes"]))
         return ms
 
     for _ in range(args.warmup):
@@ -171,7 +171,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2D 512x512 8-connected phantom, beta 90, m=200, C=3, 50 seeds/label; "
                                "per step 4 solves (eps=0.1) + 3 edits with Rayleigh-Ritz updates",
-                   "N": w.N, "m": w.m, "C": w.C, "S": int(node.size), "m_used": m_used},
+                   "N": w.N, "m": w.m, "C": w.C, "S": int(node.size), "m_used": [a for a, _ in m_used],
+                   "eig_probes": [b for _, b in m_used]},
         "precompute_s": round(t_pre, 3),
         "spmv_gbs": round(spmm_gbs, 1),
         "update_vs_recompute": compare,

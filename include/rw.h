@@ -192,6 +192,7 @@ typedef struct {
   double f_max;      /* S * eps^2 (0 when eps <= 0) */
   double f_worst;    /* max over labels of the fit (eq. (24)) at m_used (0 when eps <= 0) */
   double min_pivot;  /* smallest |pivot| / max|entry| of the reduced system's LU */
+  int32_t eig_probes; /* choice of m: batched eigen-based evaluations the Cholesky screen left (0 when eps <= 0) */
 } rw_solve_info;
 
 int rw_solve_workspace_bytes(rw_graph g, int m_avail, int64_t S, int C, size_t* bytes);

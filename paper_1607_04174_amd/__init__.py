@@ -64,7 +64,7 @@ class rw_eig_info(ct.Structure):
 
 class rw_solve_info(ct.Structure):
     _fields_ = [("m_used", ct.c_int32), ("f_max", ct.c_double), ("f_worst", ct.c_double),
-                ("min_pivot", ct.c_double)]
+                ("min_pivot", ct.c_double), ("eig_probes", ct.c_int32)]
 
 
 class rw_batch_image(ct.Structure):
@@ -371,7 +371,8 @@ def solve_seeds(g: Graph, Q: torch.Tensor, lam: torch.Tensor, seed_node, seed_la
     _check(lib().rw_solve_seeds(g.handle, _ptr(Q), _TORCH_DT[Q.dtype], _ptr(lam), m_avail,
                                 ct.c_void_p(nodes.ctypes.data), ct.c_void_p(labels.ctypes.data), S, C, float(eps),
                                 _ptr(U), _ptr(work), work.numel(), _stream(g.device), ct.byref(info)))
-    return U, {"m_used": info.m_used, "f_max": info.f_max, "f_worst": info.f_worst, "min_pivot": info.min_pivot}
+    return U, {"m_used": info.m_used, "f_max": info.f_max, "f_worst": info.f_worst, "min_pivot": info.min_pivot,
+               "eig_probes": info.eig_probes}
 
 
 def cg_solve(g: Graph, seed_node, seed_label, C: int, tol: float = 1e-12, max_iter: int = 100000,

@@ -354,9 +354,13 @@ __global__ __launch_bounds__(64) void k_fit_secular(const int* cand, int ncand, 
 //   z = L^{-1} g,  r(m) = ||b||^2 - sum_{j<m} z_j^2,  a(m) = L_m^{-T} z_m.
 // r(m) <= f(m) (the constraint can only raise the minimum), so r(m) > f_max decides "fails"; when the
 // fit is also feasible (||a(m)|| <= rho) it solves the constrained problem, f(m) = r(m), which decides
-// "passes" or "fails" outright.  Everything else (an active constraint, a value within a relative
-// 1e-8 band of the threshold, or m beyond the first pivot below 1e-8 of its diagonal entry, where G's
-// leading block is numerically singular, as for every m > S) is left to the eigen-based evaluation.
+// "passes" or "fails" outright.  Rounding: the factorization is exact for G + E with
+// ||E|| <= c (m^2 + S) u trace(G_m) (Gram sums and factorization), which moves r(m) by a^T E a to
+// first order, so each decision keeps a band of 16 (m^2 + S) u trace(G_m) ||a(m)||^2 (plus 1e-10
+// relative) around f_max.  Everything else (an active or
+// nearly active constraint, a value inside the band, or m beyond the first pivot below 1e-12 of its
+// diagonal entry, where G's leading block is numerically singular, as for every m > S) is left to
+// the eigen-based evaluation.
 // One workgroup; the factors live in the workspace (global memory, L2-resident).
 __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int C, int64_t S, const double* Gq, const double* Gb,
                                                      const double* Us, double rho2, double f_max, double* L,
@@ -380,7 +384,7 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int C, int64_t S, c
   for (int k = 0; k < ma; ++k) {
     if (tid == 0) {
       const double akk = L[k + (int64_t)k * ma];
-      if (!(akk > 1e-8 * Gq[k + (int64_t)k * ma]) || !isfinite(akk)) s_kf = k;
+      if (!(akk > 1e-12 * Gq[k + (int64_t)k * ma]) || !isfinite(akk)) s_kf = k;
       else L[k + (int64_t)k * ma] = sqrt(akk);
     }
     __syncthreads();
@@ -417,34 +421,53 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int C, int64_t S, c
     Z[j + (int64_t)c * ma] = acc;
   }
   __syncthreads();
-  // per m in [1, ma]: residual, feasibility, class
-  for (int m = 1 + tid; m <= ma; m += blockDim.x) {
-    int cl = 2;
-    double rmax = 0.0;
-    if (m <= kf) {
-      bool feasible = true;
-      for (int c = 0; c < C; ++c) {
-        const double* z = Z + (int64_t)c * ma;
-        double zz = 0.0;
-        for (int j = 0; j < m; ++j) zz += z[j] * z[j];
-        const double r = fmax(s_bn[c] - zz, 0.0);
-        rmax = fmax(rmax, r);
-        double an = 0.0;
-        for (int i = 0; i < m; ++i) {
-          double ai = 0.0;
-          for (int j = i; j < m; ++j) ai += Ri[i + (int64_t)j * ma] * z[j];
-          an += ai * ai;
-        }
-        if (!(an <= rho2 * (1.0 - 1e-8))) feasible = false;
+  // per m in [1, ma]: residual r(m) = ||b||^2 - sum_{j<m} z_j^2 and the fit's squared norm
+  // ||a(m)||^2 = sum_{i<m} P(i, m-1)^2 with the row prefix sums P(i, j) = sum_{i<=j'<=j} Ri(i, j') z_j'
+  // (L is no longer needed: P overwrites it, one label at a time)
+  double bmax = 0.0;
+  for (int c = 0; c < C; ++c) bmax = fmax(bmax, s_bn[c]);
+  const double band0 = 1e-10 * (f_max + bmax);
+  // per-thread state for m = 1 + tid (ma <= 1024)
+  const int m = 1 + tid;
+  double trg = 0.0;
+  if (m <= kf)
+    for (int k = 0; k < m; ++k) trg += Gq[k + (int64_t)k * ma];
+  // Gram rounding (S terms per entry) plus the factorization's (m^2): ||E|| <= 16 (m^2 + S) u trace(G_m)
+  const double ebound = 16.0 * ((double)m * (double)m + (double)S) * 1.1102230246251565e-16 * trg;
+  double rmax = 0.0;
+  bool anyfail = false, allpass = true;
+  for (int c = 0; c < C; ++c) {
+    const double* z = Z + (int64_t)c * ma;
+    __syncthreads();
+    for (int i = tid; i < kf; i += blockDim.x) {
+      double acc = 0.0;
+      for (int j = i; j < kf; ++j) {
+        acc += Ri[i + (int64_t)j * ma] * z[j];
+        L[i + (int64_t)j * ma] = acc;
       }
-      double bmax = 0.0;
-      for (int c = 0; c < C; ++c) bmax = fmax(bmax, s_bn[c]);
-      const double band = 1e-8 * (f_max + bmax);
-      if (rmax > f_max + band) cl = 0;
-      else if (feasible && rmax < f_max - band) cl = 1;
-      else if (feasible && rmax > f_max + band) cl = 0;
     }
-    F[m] = rmax;
+    __syncthreads();
+    if (m <= kf) {
+      double zz = 0.0, an = 0.0;
+      for (int j = 0; j < m; ++j) zz += z[j] * z[j];
+      for (int i = 0; i < m; ++i) {
+        const double v = L[i + (int64_t)(m - 1) * ma];
+        an += v * v;
+      }
+      const double r = fmax(s_bn[c] - zz, 0.0);
+      rmax = fmax(rmax, r);
+      const double band = band0 + ebound * an;
+      if (r > f_max + band) anyfail = true;
+      if (!(r < f_max - band) || !(an <= 0.99 * rho2)) allpass = false;
+    }
+  }
+  if (m <= ma) {
+    int cl = 2;
+    if (m <= kf) {
+      if (anyfail) cl = 0;
+      else if (allpass) cl = 1;
+    }
+    F[m] = m <= kf ? rmax : 0.0;
     cls[m] = cl;
   }
   if (tid == 0) {
@@ -541,6 +564,7 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
   RW_TRY(gram(RW_F64, w.Qs, S, w.Hs, S, S, ma, C, w.R, w.partial, stream));
   // choice of m
   int m = ma;
+  int probes = 0;
   double f_max = 0.0, f_worst = 0.0;
   if (eps > 0.0) {
     f_max = (double)S * eps * eps;
@@ -557,7 +581,8 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
     // search: lo = largest m known to fail (1 = none), hi = smallest m known to pass (ma + 1 = none)
     int lo = 1, hi = ma + 1;
     std::vector<std::pair<int, double>> evaluated;
-    if (C <= 64) {
+    const bool screened = C <= 64 && ma <= 1024;
+    if (screened) {
       k_fit_screen<<<1, 1024, 0, stream>>>(ma, C, S, w.Gq, w.Gb, w.Us, rho * rho, f_max, w.scrL, w.scrRi, w.scrZ,
                                            w.scrF, w.scrCls);
       RW_LAUNCH_CHECK();
@@ -585,20 +610,28 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
     const int msmax = (int)std::min<int64_t>(S, ma);
     RW_CHECK(msmax <= 1022, RW_EINVAL, "choice of m supports min(S, m_avail) <= 1022");
     while (hi - lo > 1) {
+      ++probes;
       cand.clear();
       int span = hi - lo - 1;
-      int nc = std::min(span, maxc);
-      for (int q = 1; q <= nc; ++q) {
-        int mm = lo + (int)(((int64_t)span * q + nc - 1) / nc);
-        if (mm < 2) mm = 2;
-        if (cand.empty() || mm > cand.back()) cand.push_back(mm);
+      if (screened) {
+        // the screen leaves lo + 1 undecided and usually passes a few m later: the next 32 m in order
+        for (int mm = std::max(lo + 1, 2); mm < hi && (int)cand.size() < std::min(32, maxc); ++mm) cand.push_back(mm);
+      } else {
+        int nc = std::min(span, maxc);
+        for (int q = 1; q <= nc; ++q) {
+          int mm = lo + (int)(((int64_t)span * q + nc - 1) / nc);
+          if (mm < 2) mm = 2;
+          if (cand.empty() || mm > cand.back()) cand.push_back(mm);
+        }
       }
       int ncand = (int)cand.size();
       RW_HIP(hipMemcpyAsync(cand_buf, cand.data(), ncand * sizeof(int), hipMemcpyHostToDevice, stream));
-      k_fit_build<<<ncand, 256, 0, stream>>>(cand_buf, S, ma, C, msmax, w.Qs, w.Gq, w.Gb, w.Us, w.fitA, w.fitR);
+      // candidate problems are padded to the largest candidate's size (S once a candidate exceeds S)
+      const int msp = (int)std::min<int64_t>(S, cand.back());
+      k_fit_build<<<ncand, 256, 0, stream>>>(cand_buf, S, ma, C, msp, w.Qs, w.Gq, w.Gb, w.Us, w.fitA, w.fitR);
       RW_LAUNCH_CHECK();
-      RW_TRY(syev_batched(w.fitA, w.fitW, nullptr, w.fitR, C, msmax, ncand, w.fitWork, stream));
-      k_fit_secular<<<dim3(ncand, C), 64, 0, stream>>>(cand_buf, ncand, S, C, msmax, w.fitW, w.fitR, w.Us, rho,
+      RW_TRY(syev_batched(w.fitA, w.fitW, nullptr, w.fitR, C, msp, ncand, w.fitWork, stream));
+      k_fit_secular<<<dim3(ncand, C), 64, 0, stream>>>(cand_buf, ncand, S, C, msp, w.fitW, w.fitR, w.Us, rho,
                                                         w.fvals);
       RW_LAUNCH_CHECK();
       RW_HIP(hipMemcpyAsync(fh.data(), w.fvals, (size_t)ncand * C * sizeof(double), hipMemcpyDeviceToHost, stream));
@@ -633,6 +666,7 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
   RW_TRY(reconstruct(g, Q, q_dtype, m, w.Y, C, w.map, U, stream));
   if (info) {
     info->m_used = m;
+    info->eig_probes = probes;
     info->f_max = f_max;
     info->f_worst = f_worst;
     info->min_pivot = stat;
