@@ -43,6 +43,10 @@ def main():
     ap.add_argument("--spmm-reps", type=int, default=20)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch the stencil block and a plain copy of the same block (for HBM counters)")
+    ap.add_argument("--workload", default="interactive512",
+                    choices=["interactive512", "small64", "volume128", "batch64", "grad96"],
+                    help="interactive512 (default, the headline line); the others measure the remaining "
+                         "configurations and print their own line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
@@ -57,6 +61,10 @@ def main():
     w = rwsynth.CFG2
     if args.traffic_probe:
         traffic_probe(rw, rwsynth, torch, w, dev)
+        return
+    if args.workload != "interactive512":
+        line = MODES[args.workload](args, rw, rwsynth, torch, dev)
+        print(json.dumps(line), flush=True)
         return
     J, rid = rwsynth.phantom(w, 0)
     node, lab = rwsynth.seeds(w, rid, 0)
@@ -257,6 +265,301 @@ def cpu_baseline(w, J, node, lab, edits, Q0, lam0, solves_per_step):
                       "Rayleigh-Ritz update (beta edit) of the 512x512 workload, FP64, scaled to a step of "
                       f"{solves_per_step} solves + {n_upd} updates",
             "solve_s": round(t_solve, 3), "update_s": round(t_upd, 3)}
+
+
+# ---------------------------------------------------------------------------------------------
+# the other workloads (one JSON line each; the default run prints only the interactive512 line)
+# ---------------------------------------------------------------------------------------------
+def _sync_time(torch, fn, reps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out
+
+
+def _cores():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        return os.cpu_count()
+
+
+def _line(metric, value, unit, args, ms_per_step, dtype, config, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    out.update(extra)
+    return out
+
+
+def run_small64(args, rw, rwsynth, torch, dev):
+    """64 x 64, 4-connected, FP64: exact RW by CG and the eigenbasis solve (m = 50), both against the oracle."""
+    w = rwsynth.CFG1
+    J, rid = rwsynth.phantom(w, 0)
+    node, lab = rwsynth.seeds(w, rid, 0)
+    Jd = torch.as_tensor(J, device=dev)
+    g = rw.Graph(Jd, w.dims, w.conn, w.beta, dtype=torch.float64)
+    t_pre, (Q, lam, einfo) = _sync_time(torch, lambda: rw.precompute_eig(g, w.m, tol=1e-10, max_iter=400), 1)
+    ws = rw.SolveWorkspace()
+    for _ in range(args.warmup):
+        rw.cg_solve(g, node, lab, w.C, tol=1e-12)
+        rw.solve_seeds(g, Q, lam, node, lab, w.C, workspace=ws)
+    t_cg, (Ucg, cinfo) = _sync_time(torch, lambda: rw.cg_solve(g, node, lab, w.C, tol=1e-12), args.steps)
+    t_eig, (Ue, _) = _sync_time(torch, lambda: rw.solve_seeds(g, Q, lam, node, lab, w.C, workspace=ws), args.steps)
+    log(f"small64: CG {t_cg * 1e3:.2f} ms/solve ({cinfo['iters']} it), eigenbasis {t_eig * 1e3:.3f} ms/solve")
+    parity = None
+    cpu = None
+    if not args.no_cpu:
+        from oracle.exact_rw import exact_rw
+        from oracle.fast_rw import fast_rw
+        from oracle.graph import Graph as OGraph
+        og = OGraph(J, w.dims, w.conn, w.beta)
+        t0 = time.perf_counter()
+        Ud = exact_rw(og, node, lab, w.C, method="cg", tol=1e-12)
+        t_ocg = time.perf_counter() - t0
+        Qn, ln = Q.cpu().numpy().T, lam.cpu().numpy()
+        exact = bool(np.min(np.abs(ln[1:])) < 1e-6)
+        t0 = time.perf_counter()
+        Uf = fast_rw(og, Qn, ln, node, lab, w.C, exact=exact)
+        t_ofast = time.perf_counter() - t0
+        parity = {"cg_vs_oracle_maxabs": float(np.abs(Ucg.cpu().numpy().T - Ud).max()),
+                  "eig_vs_oracle_same_basis_maxabs": float(np.abs(Ue.cpu().numpy().T - Uf).max()),
+                  "eig_truncation_vs_exact_maxabs": float(np.abs(Ue.cpu().numpy().T - Ud).max())}
+        cpu = {"value": round(1.0 / t_ofast, 4), "unit": "RW solves/s", "cores": int(_cores()), "kind": "oracle",
+               "sample": "one eigenbasis solve (bordered system, FP64%s) of the 64x64 workload; the oracle's "
+                         "CG exact solve took %.3f s" % (", exact rational arithmetic" if exact else "", t_ocg)}
+    return _line("RW solves/s (eigenbasis, m = 50) and exact CG solves/s", round(1.0 / t_eig, 2), "RW solves/s",
+                 args, t_eig * 1e3, "f64",
+                 {"workload": "2D 64x64 4-connected phantom, beta 90, m=50, C=2, 20 seeds/label, FP64",
+                  "N": w.N, "m": w.m, "C": w.C, "S": int(node.size)},
+                 cg_solves_per_s=round(1.0 / t_cg, 2), cg_iters=cinfo["iters"], precompute_s=round(t_pre, 3),
+                 eig_max_residual=einfo["max_residual"], parity=parity, cpu_baseline=cpu)
+
+
+def _window_sines(torch, Qa, lama, Qb, lamb, delta):
+    """Per column i of Qa: sin of its angle to span{Qb_j : |lamb_j - lama_i| <= delta} (Davis-Kahan: at
+    most ||r_i|| / delta).  A window that reaches the last stored pair may need pairs beyond the cut;
+    those columns are flagged.  FP64 on the device (analysis only)."""
+    m = Qa.shape[0]
+    P = (Qb.double() @ Qa.double().T).cpu().numpy()     # (m, m): Qb^T Qa
+    la, lb = lama.double().cpu().numpy(), lamb.double().cpu().numpy()
+    sines = np.zeros(m)
+    crossing = np.zeros(m, dtype=bool)
+    for i in range(m):
+        sel = np.abs(lb - la[i]) <= delta
+        crossing[i] = la[i] + delta >= lb[-1]
+        sines[i] = np.sqrt(max(0.0, 1.0 - float((P[sel, i] ** 2).sum())))
+    return sines, crossing
+
+
+def run_volume128(args, rw, rwsynth, torch, dev):
+    """128^3, 6-connected, mixed precision: FP32 eigensolver and stencil, BF16 Q on the matrix cores, FP64
+    Gram / Cholesky-QR / Rayleigh-Ritz / seed system; errors against the FP64 path for every eigenpair and
+    every map; solve throughput with the BF16 basis."""
+    w = rwsynth.CFG3
+    J, rid = rwsynth.phantom(w, 0)
+    node, lab = rwsynth.seeds(w, rid, 0)
+    Jd = torch.as_tensor(J, device=dev)
+    g32 = rw.Graph(Jd, w.dims, w.conn, w.beta, dtype=torch.float32)
+    t32, (Q32, lam32, i32) = _sync_time(torch, lambda: rw.precompute_eig(g32, w.m, tol=1e-5, max_iter=400), 1)
+    log(f"volume128: FP32 precompute {t32:.2f}s it={i32['iters']} res={i32['max_residual']:.2e}")
+    g64 = rw.Graph(Jd, w.dims, w.conn, w.beta, dtype=torch.float64)
+    t64, (Q64, lam64, i64) = _sync_time(torch, lambda: rw.precompute_eig(g64, w.m, tol=1e-9, max_iter=600), 1)
+    log(f"volume128: FP64 precompute {t64:.2f}s it={i64['iters']} res={i64['max_residual']:.2e}")
+    dlam = (lam32 - lam64).abs().cpu().numpy()
+    sines, crossing = _window_sines(torch, Q32, lam32, Q64, lam64, delta=1e-3)
+    Qb = rw.convert_block(Q32, torch.bfloat16)
+    Q64b = rw.convert_block(Q64, torch.bfloat16)
+    ws = rw.SolveWorkspace()
+    ev = lam64.cpu().numpy()
+    gaps = np.diff(ev)
+    mcut = int(w.m // 2 + np.argmax(gaps[w.m // 2 - 1:]) + 1)      # largest gap in the upper half: a clean span
+    err = {}
+    for tag, mm in (("m", w.m), ("gap_cut", mcut)):
+        U64, _ = rw.solve_seeds(g64, Q64, lam64, node, lab, w.C, m_avail=mm, workspace=ws)
+        U32s, _ = rw.solve_seeds(g32, Q64.float(), lam64, node, lab, w.C, m_avail=mm, workspace=ws)
+        U16s, _ = rw.solve_seeds(g32, Q64b, lam64, node, lab, w.C, m_avail=mm, workspace=ws)
+        U32, _ = rw.solve_seeds(g32, Q32, lam32, node, lab, w.C, m_avail=mm, workspace=ws)
+        U16, _ = rw.solve_seeds(g32, Qb, lam32, node, lab, w.C, m_avail=mm, workspace=ws)
+        err[tag] = {"m": mm,
+                    "same_basis_fp32_maxabs": float((U32s.double() - U64).abs().max()),
+                    "same_basis_bf16_maxabs": float((U16s.double() - U64).abs().max()),
+                    "end_to_end_fp32_maxabs": float((U32.double() - U64).abs().max()),
+                    "end_to_end_bf16_maxabs": float((U16.double() - U64).abs().max()),
+                    "per_map_end_to_end_bf16_maxabs": [float((U16[c].double() - U64[c]).abs().max())
+                                                       for c in range(w.C)]}
+    ok = ~crossing
+    err["eig_abs_dlambda_max"] = float(dlam.max())
+    err["eig_abs_dlambda"] = [float(x) for x in dlam]
+    err["eig_sin_angle_max_inside"] = float(sines[ok].max()) if ok.any() else None
+    err["eig_pairs_window_crosses_cut"] = int(crossing.sum())
+    err["eig_sin_angle"] = [float(x) for x in sines]
+    U16 = torch.empty((w.C, w.N), dtype=torch.float32, device=dev)
+    U32 = torch.empty_like(U16)
+    log(f"volume128: errors vs FP64 path: {err['m']} {err['gap_cut']} dlambda {err['eig_abs_dlambda_max']:.2e} "
+        f"sin {err['eig_sin_angle_max_inside']} (crossing {err['eig_pairs_window_crosses_cut']})")
+    for _ in range(args.warmup):
+        rw.solve_seeds(g32, Qb, lam32, node, lab, w.C, U=U16, workspace=ws)
+    t16, _ = _sync_time(torch, lambda: rw.solve_seeds(g32, Qb, lam32, node, lab, w.C, U=U16, workspace=ws),
+                        args.steps)
+    t32s, _ = _sync_time(torch, lambda: rw.solve_seeds(g32, Q32, lam32, node, lab, w.C, U=U32, workspace=ws),
+                         args.steps)
+    # reconstruction kernel alone (matrix cores, BF16 Q): HIP events on the launch stream
+    stream = torch.cuda.current_stream()
+    reps = 10
+    e0 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    e1 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    for k in range(reps):
+        e0[k].record(stream)
+        rw.solve_seeds(g32, Qb, lam32, node, lab, w.C, U=U16, workspace=ws)
+        e1[k].record(stream)
+    torch.cuda.synchronize()
+    solve_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(e0, e1)]))
+    log(f"volume128: solve BF16 {t16 * 1e3:.2f} ms, FP32 {t32s * 1e3:.2f} ms")
+    return _line("RW solves/s (BF16 eigenbasis on the matrix cores) with errors against the FP64 path",
+                 round(1.0 / t16, 2), "RW solves/s", args, t16 * 1e3,
+                 "f32 stencil/blocks + bf16 Q (MFMA, f32 accumulation) + f64 Gram/RR/seed system",
+                 {"workload": "3D 128^3 6-connected phantom (8 ellipsoids, uniform intensities, sigma 0.03), "
+                              "beta 120, m=100, C=4, 200 seeds/label", "N": w.N, "m": w.m, "C": w.C,
+                  "S": int(node.size)},
+                 fp32_solves_per_s=round(1.0 / t32s, 2), gap_cut_m=mcut, precompute_fp32_s=round(t32, 2),
+                 precompute_fp64_s=round(t64, 2), fp32_max_residual=i32["max_residual"],
+                 fp64_max_residual=i64["max_residual"], errors=err, solve_event_ms=round(solve_ms, 3))
+
+
+def run_batch64(args, rw, rwsynth, torch, dev):
+    """64 uneven 2D images x 8 seed-set rounds; one HIP-graph replay per round."""
+    imgs = rwsynth.cfg4_images(64, 0)
+    rounds = 8
+    images, rid_of = [], []
+    t0 = time.perf_counter()
+    for i, w in enumerate(imgs):
+        J, rid = rwsynth.phantom(w, 0)
+        g = rw.Graph(torch.as_tensor(J, device=dev), w.dims, w.conn, w.beta, dtype=torch.float32)
+        Q, lam, _ = rw.precompute_eig(g, w.m, tol=1e-5, max_iter=400)
+        rnds = [rwsynth.cfg4_round(w, rid, r, 0) for r in range(rounds)]
+        images.append({"graph": g, "Q": Q, "lam": lam, "rounds": rnds, "C_cap": 4,
+                       "S_cap": max(len(x[1]) for x in rnds)})
+    torch.cuda.synchronize()
+    t_pre = time.perf_counter() - t0
+    elems = sum(im["graph"].N * im["Q"].shape[0] for im in images)
+    log(f"batch64: precompute of 64 bases {t_pre:.1f}s, sum N_i m_i = {elems:.3e}")
+    bs = rw.BatchSolver(images, use_graph=True)
+    info = bs.info()
+    # round r of the timed region uses interaction r mod 8; the seeds of each round are set (host
+    # validation + upload) inside the timed region, as an interactive session would
+    for r in range(args.warmup):
+        bs.set_seeds([im["rounds"][r % rounds] for im in images])
+        bs.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(args.steps * rounds):
+        bs.set_seeds([im["rounds"][r % rounds] for im in images])
+        bs.run()
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    per_round = T / (args.steps * rounds)
+    pivot = bs.status()
+    # one round's replay alone (seeds already resident): HIP events on the replay stream
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        bs.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    replay_ms = e0.elapsed_time(e1) / 5
+    qbytes = sum(im["graph"].N * im["Q"].shape[0] * 4 for im in images)
+    ubytes = sum(im["graph"].N * int(im["rounds"][0][0]) * 4 for im in images)
+    gbs = (qbytes + ubytes) / (replay_ms * 1e-3) / 1e9
+    log(f"batch64: {per_round * 1e3:.2f} ms/round incl. seed upload, replay {replay_ms:.2f} ms, "
+        f"{64 / per_round:.0f} image-interactions/s, tile {info}")
+    return _line("batched interactions/s (images x seed-set rounds per second)", round(64 / per_round, 1),
+                 "image-interactions/s", args, per_round * 1e3 * rounds,
+                 "f32 Q and U + f64 seed systems",
+                 {"workload": "64 2D phantoms, sides uniform in [128, 768], 4-connected, beta 90, m in {50, 100, "
+                              "200}, 8 seed-set rounds (C 2-4, 10-100 seeds/label), one HIP-graph replay per round",
+                  "images": 64, "rounds_per_step": rounds, "sum_N_m": int(elems)},
+                 ms_per_round=round(per_round * 1e3, 3), replay_ms=round(replay_ms, 3), precompute_s=round(t_pre, 1),
+                 autotune=info, min_pivot=pivot,
+                 roofline={"kernel": "k_b_reconstruct (whole round)", "bound": "hbm", "achieved": round(gbs, 1),
+                           "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                           "traffic": None, "bytes_per_launch": qbytes + ubytes,
+                           "note": "Q read + U write per round over the replay's duration (all kernels)"})
+
+
+def run_grad96(args, rw, rwsynth, torch, dev):
+    """96^3 exact RW (FP64 CG warm-started from the eigenbasis) forward + adjoint backward; central finite
+    differences on sampled entries."""
+    w = rwsynth.CFG5
+    J, rid = rwsynth.phantom(w, 0)
+    node, lab = rwsynth.seeds(w, rid, 0)
+    gt = rwsynth.label_map(rid, w.C)
+    Jd = torch.as_tensor(J, device=dev, dtype=torch.float64)
+    g = rw.Graph(Jd, w.dims, w.conn, w.beta, dtype=torch.float64)
+    t_pre, (Q, lam, _) = _sync_time(torch, lambda: rw.precompute_eig(g, w.m, tol=1e-8, max_iter=600), 1)
+    scale = torch.ones((3, w.N), dtype=torch.float64, device=dev)
+    mask = torch.ones(w.N, dtype=torch.bool, device=dev)
+    mask[torch.as_tensor(node, device=dev)] = False
+    y = torch.as_tensor(gt, device=dev, dtype=torch.long)
+
+    def loss_of(U):
+        p = U.gather(0, y[None, :])[0]
+        return -(torch.log(torch.clamp(p[mask], min=1e-12))).mean()
+
+    def fwd_bwd():
+        Jt = Jd.clone().requires_grad_(True)
+        bt = torch.tensor(w.beta, dtype=torch.float64, device=dev, requires_grad=True)
+        st = scale.clone().requires_grad_(True)
+        U = rw.random_walker(Jt, bt, st, w.dims, w.conn, node, lab, w.C, Q=Q, lam=lam, tol=1e-12)
+        L = loss_of(U)
+        L.backward()
+        return float(L), Jt.grad, bt.grad, st.grad
+
+    for _ in range(args.warmup):
+        fwd_bwd()
+    t_fb, (L0, dJ, db, ds) = _sync_time(torch, fwd_bwd, args.steps)
+
+    def fwd(J_=None, beta=w.beta, s=scale):
+        with torch.no_grad():
+            U = rw.random_walker(Jd if J_ is None else J_, torch.tensor(beta, dtype=torch.float64), s, w.dims,
+                                 w.conn, node, lab, w.C, Q=Q, lam=lam, tol=1e-13)
+            return float(loss_of(U))
+
+    t_f, _ = _sync_time(torch, fwd, 1)
+    h = 1e-6
+    rng = np.random.default_rng(5)
+    checks = []
+    for i in rng.choice(w.N, 3, replace=False):
+        Jp, Jm = Jd.clone(), Jd.clone()
+        Jp[int(i)] += h
+        Jm[int(i)] -= h
+        fd = (fwd(J_=Jp) - fwd(J_=Jm)) / (2 * h)
+        checks.append({"param": f"J[{int(i)}]", "fd": fd, "adjoint": float(dJ[int(i)])})
+    fd = (fwd(beta=w.beta + h) - fwd(beta=w.beta - h)) / (2 * h)
+    checks.append({"param": "beta", "fd": fd, "adjoint": float(db)})
+    for e in rng.choice(w.N - 20000, 2, replace=False):
+        sp, sm = scale.clone(), scale.clone()
+        sp[0, int(e)] += h
+        sm[0, int(e)] -= h
+        fd = (fwd(s=sp) - fwd(s=sm)) / (2 * h)
+        checks.append({"param": f"s[+x, {int(e)}]", "fd": fd, "adjoint": float(ds[0, int(e)])})
+    worst = max(abs(c["fd"] - c["adjoint"]) / max(1.0, abs(c["fd"])) for c in checks)
+    log(f"grad96: forward+backward {t_fb:.3f}s (forward alone {t_f:.3f}s), loss {L0:.6f}, FD worst rel {worst:.2e}")
+    return _line("forward + backward (exact RW, adjoint gradients w.r.t. J, beta and per-edge scales) per second",
+                 round(1.0 / t_fb, 3), "forward+backward/s", args, t_fb * 1e3, "f64",
+                 {"workload": "3D 96^3 6-connected phantom (5 ellipsoids, sigma 0.05), beta 120, m=80 (warm start), "
+                              "C=2, 100 seeds/label, cross-entropy vs the ground-truth mask", "N": w.N,
+                  "S": int(node.size)},
+                 forward_s=round(t_f, 4), precompute_s=round(t_pre, 2), loss=L0, fd_checks=checks,
+                 fd_worst_rel=worst)
+
+
+MODES = {"small64": run_small64, "volume128": run_volume128, "batch64": run_batch64, "grad96": run_grad96}
 
 
 if __name__ == "__main__":

@@ -61,6 +61,7 @@ struct rw_batch_impl {
   int64_t S_total_cap = 0;
   int64_t max_N = 0;
   int max_m = 0;
+  int max_C = 1;   // largest label capacity (reconstruction tile width 4 or 8)
   // device pointers inside the caller's workspace
   BatchImg* d_desc = nullptr;
   LuJob* d_jobs = nullptr;
@@ -212,9 +213,11 @@ __global__ void k_b_reduced(const BatchImg* D, LuJob* jobs) {
   }
 }
 
-// persistent reconstruction over the (image, tile) list
-template <typename TQ, typename TU, int NPT>
-__global__ void k_b_reconstruct(const BatchImg* D, const BatchTile* tiles, int64_t ntiles) {
+// persistent reconstruction over the (image, tile) list: U = D^{-1/2} Q Y on non-seeds, one-hot on
+// seeds.  Y (m x CB, zero-padded labels) is staged in LDS per tile; each thread owns NPT nodes and keeps
+// 4 * NPT loads of Q in flight (the j loop is unrolled by 4), so the pass over Q is bandwidth-bound.
+template <typename TQ, typename TU, int NPT, int CB>
+__global__ __launch_bounds__(512) void k_b_reconstruct(const BatchImg* D, const BatchTile* tiles, int64_t ntiles) {
   using CT = typename Elem<TQ>::C;
   extern __shared__ char smem[];
   CT* sY = reinterpret_cast<CT*>(smem);
@@ -223,29 +226,60 @@ __global__ void k_b_reconstruct(const BatchImg* D, const BatchTile* tiles, int64
     const BatchImg& d = D[tl.img];
     const int m = d.m, C = d.C;
     __syncthreads();
-    for (int q = threadIdx.x; q < m * kBatchMaxC; q += blockDim.x) {
-      const int j = q / kBatchMaxC, c = q % kBatchMaxC;
+    for (int q = threadIdx.x; q < m * CB; q += blockDim.x) {
+      const int j = q / CB, c = q % CB;
       sY[q] = c < C ? (CT)d.Y[j + (int64_t)c * m] : CT(0);
     }
     __syncthreads();
     const TQ* Q = static_cast<const TQ*>(d.Q);
     const int64_t N = d.G.N;
+    int64_t ii[NPT];
+    bool ok[NPT];
 #pragma unroll
     for (int r = 0; r < NPT; ++r) {
       const int64_t i = tl.node0 + threadIdx.x + (int64_t)r * blockDim.x;
-      if (i >= N) break;
-      CT acc[kBatchMaxC];
+      ok[r] = i < N;
+      ii[r] = ok[r] ? i : tl.node0;      // a valid node for the (discarded) loads of an idle slot
+    }
+    CT acc[NPT][CB];
 #pragma unroll
-      for (int c = 0; c < kBatchMaxC; ++c) acc[c] = CT(0);
-      for (int j = 0; j < m; ++j) {
-        const CT q = Elem<TQ>::ld(Q, (int64_t)j * N + i);
+    for (int r = 0; r < NPT; ++r)
 #pragma unroll
-        for (int c = 0; c < kBatchMaxC; ++c) acc[c] = fma(q, sY[j * kBatchMaxC + c], acc[c]);
+      for (int c = 0; c < CB; ++c) acc[r][c] = CT(0);
+    int j = 0;
+    for (; j + 4 <= m; j += 4) {
+      CT q[4][NPT];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) q[u][r] = Elem<TQ>::ld(Q, (int64_t)(j + u) * N + ii[r]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          const CT y = sY[(j + u) * CB + c];
+#pragma unroll
+          for (int r = 0; r < NPT; ++r) acc[r][c] = fma(q[u][r], y, acc[r][c]);
+        }
+    }
+    for (; j < m; ++j) {
+#pragma unroll
+      for (int r = 0; r < NPT; ++r) {
+        const CT q = Elem<TQ>::ld(Q, (int64_t)j * N + ii[r]);
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[r][c] = fma(q, sY[j * CB + c], acc[r][c]);
       }
+    }
+    TU* U = static_cast<TU*>(d.U);
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      if (!ok[r]) continue;
+      const int64_t i = ii[r];
       const int ml = d.map[i];
       const CT sc = d.normalized ? (CT) static_cast<const TU*>(d.dinv)[i] : CT(1);
-      TU* U = static_cast<TU*>(d.U);
-      for (int c = 0; c < C; ++c) U[(int64_t)c * N + i] = ml ? (ml - 1 == c ? TU(1) : TU(0)) : (TU)(sc * acc[c]);
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+        if (c < C) U[(int64_t)c * N + i] = ml ? (ml - 1 == c ? TU(1) : TU(0)) : (TU)(sc * acc[r][c]);
     }
   }
 }
@@ -291,16 +325,21 @@ static int build_tiles(rw_batch_impl* b, Variant v, hipStream_t s) {
   return RW_OK;
 }
 
-template <typename TQ, typename TU>
-static int launch_recon_t(const rw_batch_impl* b, Variant v, hipStream_t s) {
-  const size_t sh = (size_t)b->max_m * kBatchMaxC * sizeof(typename Elem<TQ>::C);
-  const unsigned grid = (unsigned)std::min<int64_t>(b->ntiles, 1024);
+template <typename TQ, typename TU, int CB>
+static int launch_recon_cb(const rw_batch_impl* b, Variant v, hipStream_t s) {
+  const size_t sh = (size_t)b->max_m * CB * sizeof(typename Elem<TQ>::C);
+  const unsigned grid = (unsigned)std::min<int64_t>(b->ntiles, 2048);
   if (grid == 0) return RW_OK;
-  if (v.npt == 1) k_b_reconstruct<TQ, TU, 1><<<grid, v.threads, sh, s>>>(b->d_desc, b->d_tiles, b->ntiles);
-  else if (v.npt == 2) k_b_reconstruct<TQ, TU, 2><<<grid, v.threads, sh, s>>>(b->d_desc, b->d_tiles, b->ntiles);
-  else k_b_reconstruct<TQ, TU, 4><<<grid, v.threads, sh, s>>>(b->d_desc, b->d_tiles, b->ntiles);
+  if (v.npt == 1) k_b_reconstruct<TQ, TU, 1, CB><<<grid, v.threads, sh, s>>>(b->d_desc, b->d_tiles, b->ntiles);
+  else if (v.npt == 2) k_b_reconstruct<TQ, TU, 2, CB><<<grid, v.threads, sh, s>>>(b->d_desc, b->d_tiles, b->ntiles);
+  else k_b_reconstruct<TQ, TU, 4, CB><<<grid, v.threads, sh, s>>>(b->d_desc, b->d_tiles, b->ntiles);
   RW_LAUNCH_CHECK();
   return RW_OK;
+}
+
+template <typename TQ, typename TU>
+static int launch_recon_t(const rw_batch_impl* b, Variant v, hipStream_t s) {
+  return b->max_C <= 4 ? launch_recon_cb<TQ, TU, 4>(b, v, s) : launch_recon_cb<TQ, TU, 8>(b, v, s);
 }
 
 static int launch_recon(const rw_batch_impl* b, Variant v, hipStream_t s) {
@@ -318,7 +357,7 @@ static int autotune(rw_batch_impl* b, hipStream_t s) {
   std::ostringstream key;
   int64_t work = 0;
   for (auto& im : b->imgs) work += im.g->g.N * (int64_t)im.m;
-  key << "batch_n" << b->n << "_Nm" << work << "_g" << b->gdt << "_q" << b->qdt;
+  key << "batch_n" << b->n << "_Nm" << work << "_g" << b->gdt << "_q" << b->qdt << "_c" << b->max_C;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_cache();
@@ -402,6 +441,7 @@ int rw_batch_create(const rw_batch_image* imgs, int n, void* work, size_t work_b
   for (int i = 0; i < n; ++i) {
     b->max_N = std::max<int64_t>(b->max_N, imgs[i].g->g.N);
     b->max_m = std::max(b->max_m, imgs[i].m);
+    b->max_C = std::max(b->max_C, imgs[i].C_cap);
   }
   batch_layout(imgs, n, work, b);
   hipError_t e = hipMemcpyAsync(b->d_desc, b->desc.data(), n * sizeof(BatchImg), hipMemcpyHostToDevice, stream);
