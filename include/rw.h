@@ -98,8 +98,17 @@ typedef struct {
   const void* ghat;     /* N: unit null vector */
   const double* degree; /* N: d in FP64 */
   const uint8_t* mask;  /* N: bit dir set iff the forward edge in direction dir is present */
+  const int64_t* comp;  /* N: component root (smallest node index) over edges with w >= 1e-30; valid after
+                           rw_graph_components (or any solve) since the last build or edit */
 } rw_graph_view;
 int rw_graph_get_view(rw_graph g, rw_graph_view* view);
+
+/* Connected components of the graph restricted to edges with w >= 1e-30, the topology on which the
+ * gamma = 0 systems of eq. (5) and of the eigenbasis solve are solvable: a component without a seed makes
+ * them singular, and rw_solve_seeds / rw_cg_solve / rw_cg_solve_rhs then fail with RW_EUNANCHORED.
+ * Computed on the device (hooking and pointer jumping) on first use after a build or edit and cached;
+ * n_components (host, may be null) receives their number.  Synchronizes `stream`. */
+int rw_graph_components(rw_graph g, int64_t* n_components, hipStream_t stream);
 
 /* Edits of the graph, applied in array order (Sec. III-B changes beta; the others are weight and
  * topology edits).  Edge ids must be valid and present (else RW_EINVAL, nothing applied).

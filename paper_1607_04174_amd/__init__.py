@@ -44,7 +44,7 @@ class rw_graph_view(ct.Structure):
     _fields_ = [("N", ct.c_int64), ("ndir", ct.c_int32), ("dtype", ct.c_int32), ("beta", ct.c_double),
                 ("J", ct.c_void_p), ("weight", ct.c_void_p), ("scale", ct.c_void_p), ("coef", ct.c_void_p),
                 ("diag", ct.c_void_p), ("dinv", ct.c_void_p), ("ghat", ct.c_void_p), ("degree", ct.c_void_p),
-                ("mask", ct.c_void_p)]
+                ("mask", ct.c_void_p), ("comp", ct.c_void_p)]
 
 
 class rw_edit(ct.Structure):
@@ -86,6 +86,7 @@ _SIGS = {
                                   ct.c_size_t, ct.c_void_p, ct.POINTER(ct.c_void_p)]),
     "rw_graph_destroy": (ct.c_int, [ct.c_void_p]),
     "rw_graph_get_view": (ct.c_int, [ct.c_void_p, ct.POINTER(rw_graph_view)]),
+    "rw_graph_components": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int64), ct.c_void_p]),
     "rw_edit_graph": (ct.c_int, [ct.c_void_p, ct.POINTER(rw_edit), ct.c_int, ct.c_void_p]),
     "rw_apply_laplacian": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p]),
     "rw_apply_laplacian_axpby": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64,
@@ -234,7 +235,14 @@ class Graph:
                 "weight": sl(v.weight, nd * N, tdt, es).view(nd, N), "scale": sl(v.scale, nd * N, tdt, es).view(nd, N),
                 "coef": sl(v.coef, nd * N, tdt, es).view(nd, N), "diag": sl(v.diag, N, tdt, es),
                 "dinv": sl(v.dinv, N, tdt, es), "ghat": sl(v.ghat, N, tdt, es),
-                "degree": sl(v.degree, N, torch.float64, 8), "mask": sl(v.mask, N, torch.uint8, 1)}
+                "degree": sl(v.degree, N, torch.float64, 8), "mask": sl(v.mask, N, torch.uint8, 1),
+                "comp": sl(v.comp, N, torch.int64, 8)}
+
+    def components(self):
+        """(number of components, (N,) int64 tensor of component roots) over edges with w >= 1e-30."""
+        nc = ct.c_int64()
+        _check(lib().rw_graph_components(self.handle, ct.byref(nc), _stream(self.device)))
+        return nc.value, self.view()["comp"]
 
 
 def build_graph(J, dims, conn, beta, dtype=torch.float32, weight_form="squared", normalized=True) -> Graph:

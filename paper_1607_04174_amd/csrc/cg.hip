@@ -14,6 +14,7 @@ constexpr int kCgCheckEvery = 8;   // iterations between host convergence checks
 
 struct CgWork {
   uint8_t* map;
+  uint8_t* anc;
   int64_t* seeds;
   int32_t* labels;
   double *r, *z, *p, *q;
@@ -25,6 +26,7 @@ static size_t cg_layout(const Graph* g, int C, int64_t S, void* base, CgWork* w)
   Carver c(base);
   CgWork t;
   t.map = c.take<uint8_t>(g->N);
+  t.anc = c.take<uint8_t>(g->N);
   t.seeds = c.take<int64_t>(std::max<int64_t>(S, 1));
   t.labels = c.take<int32_t>(std::max<int64_t>(S, 1));
   t.r = c.take<double>((size_t)C * g->N);
@@ -218,6 +220,7 @@ static int cg_core(rw_graph h, const int64_t* seed_node, const int32_t* seed_lab
   RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "cg workspace too small: %zu < %zu", work_bytes, need);
   RW_HIP(hipMemcpyAsync(w.seeds, nodes.data(), Sd * sizeof(int64_t), hipMemcpyHostToDevice, stream));
   RW_HIP(hipMemcpyAsync(w.labels, labels.data(), Sd * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  RW_TRY(check_anchored(&h->g, w.seeds, Sd, w.anc, stream));
   const int64_t N = g->N;
   const GridDev G = grid_of(g);
   const double* wgt = static_cast<const double*>(g->weight);

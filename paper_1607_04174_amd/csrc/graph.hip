@@ -167,10 +167,13 @@ size_t graph_layout(const rw_graph_desc& d, Graph* g, void* buf) {
   uint8_t* mask = c.take<uint8_t>(N);
   double* partial = c.take<double>(kReduceBlocks);
   double* sums = c.take<double>(8);
-  c.take<int64_t>(kEditStage);
+  int64_t* comp = c.take<int64_t>(N);
+  int* ccf = c.take<int>(64);
+  c.take<int64_t>(kEditStage);       // must stay the last block (edit_stage)
   if (g) {
     g->J = J; g->scale = scale; g->weight = weight; g->coef = coef; g->diag = diag; g->dinv = dinv;
     g->ghat = ghat; g->degree = degree; g->mask = mask; g->partial = partial; g->sums = sums;
+    g->comp = comp; g->cc_flag = ccf; g->cc_valid = false;
   }
   return c.used;
 }
@@ -204,7 +207,106 @@ static int rebuild_t(Graph* g, hipStream_t s) {
 }
 
 int graph_rebuild(Graph* g, hipStream_t s) {
+  g->cc_valid = false;
   return g->dtype == RW_F64 ? rebuild_t<double>(g, s) : rebuild_t<float>(g, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Connected components by hooking and pointer jumping.  comp[i] points towards a root (comp[r] = r)
+// and only ever decreases.  A round hooks, for every edge above the anchor weight whose endpoints have
+// different roots, the larger root under the smaller one (atomic minimum), then shortcuts every node to
+// its root.  Rounds repeat until one changes nothing; the root of each component is then its smallest
+// node index.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ int64_t cc_find(const int64_t* comp, int64_t x) {
+  int64_t r = comp[x];
+  while (r != x) {
+    x = r;
+    r = comp[x];
+  }
+  return x;
+}
+
+__global__ void k_cc_init(int64_t* comp, int64_t N) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N) comp[i] = i;
+}
+
+template <typename T>
+__global__ void k_cc_hook(GridDev G, const T* weight, const uint8_t* mask, int64_t* comp, int* changed) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= G.N) return;
+  const uint8_t mk = mask[i];
+  for (int d = 0; d < G.ndir; ++d) {
+    if (!((mk >> d) & 1)) continue;
+    if (!((double)weight[d * G.N + i] >= kAnchorWeight)) continue;
+    const int64_t a = cc_find(comp, i), b = cc_find(comp, i + G.off[d]);
+    if (a == b) continue;
+    const int64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    const unsigned long long old =
+        atomicMin(reinterpret_cast<unsigned long long*>(&comp[hi]), (unsigned long long)lo);
+    if ((int64_t)old > lo) *changed = 1;
+  }
+}
+
+__global__ void k_cc_jump(int64_t* comp, int64_t N) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N) comp[i] = cc_find(comp, i);
+}
+
+int graph_components(Graph* g, hipStream_t s) {
+  if (g->cc_valid) return RW_OK;
+  const GridDev G = grid_of(g);
+  k_cc_init<<<nblocks(g->N, 256), 256, 0, s>>>(g->comp, g->N);
+  RW_LAUNCH_CHECK();
+  for (int round = 0;; ++round) {
+    RW_CHECK(round < 4096, RW_ENOCONV, "connected components did not settle");
+    RW_HIP(hipMemsetAsync(g->cc_flag, 0, sizeof(int), s));
+    if (g->dtype == RW_F64)
+      k_cc_hook<double><<<nblocks(g->N, 256), 256, 0, s>>>(G, (const double*)g->weight, g->mask, g->comp, g->cc_flag);
+    else
+      k_cc_hook<float><<<nblocks(g->N, 256), 256, 0, s>>>(G, (const float*)g->weight, g->mask, g->comp, g->cc_flag);
+    RW_LAUNCH_CHECK();
+    k_cc_jump<<<nblocks(g->N, 256), 256, 0, s>>>(g->comp, g->N);
+    RW_LAUNCH_CHECK();
+    int changed = 0;
+    RW_HIP(hipMemcpyAsync(&changed, g->cc_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    RW_HIP(hipStreamSynchronize(s));
+    if (!changed) break;
+  }
+  g->cc_valid = true;
+  return RW_OK;
+}
+
+__global__ void k_cc_count(const int64_t* comp, int64_t N, unsigned long long* count) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N && comp[i] == i) atomicAdd(count, 1ull);
+}
+
+__global__ void k_anchor_mark(const int64_t* comp, const int64_t* seeds, int64_t S, uint8_t* flags) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < S) flags[comp[seeds[k]]] = 1;
+}
+
+__global__ void k_anchor_check(const int64_t* comp, const uint8_t* flags, int64_t N, int* bad) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N && !flags[comp[i]]) *bad = 1;
+}
+
+int check_anchored(Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, hipStream_t s) {
+  RW_TRY(graph_components(g, s));
+  RW_HIP(hipMemsetAsync(flags, 0, g->N, s));
+  RW_HIP(hipMemsetAsync(g->cc_flag + 1, 0, sizeof(int), s));
+  k_anchor_mark<<<nblocks(std::max<int64_t>(S, 1), 256), 256, 0, s>>>(g->comp, seeds, S, flags);
+  RW_LAUNCH_CHECK();
+  k_anchor_check<<<nblocks(g->N, 256), 256, 0, s>>>(g->comp, flags, g->N, g->cc_flag + 1);
+  RW_LAUNCH_CHECK();
+  int bad = 0;
+  RW_HIP(hipMemcpyAsync(&bad, g->cc_flag + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  RW_HIP(hipStreamSynchronize(s));
+  RW_CHECK(!bad, RW_EUNANCHORED,
+           "a connected component (edges with w >= 1e-30) holds no seed: the gamma = 0 system is singular");
+  return RW_OK;
 }
 
 static int validate_desc(const rw_graph_desc* d) {
@@ -290,7 +392,23 @@ int rw_graph_get_view(rw_graph h, rw_graph_view* v) {
   const Graph* g = &h->g;
   v->N = g->N; v->ndir = g->ndir; v->dtype = g->dtype; v->beta = g->beta;
   v->J = g->J; v->weight = g->weight; v->scale = g->scale; v->coef = g->coef; v->diag = g->diag;
-  v->dinv = g->dinv; v->ghat = g->ghat; v->degree = g->degree; v->mask = g->mask;
+  v->dinv = g->dinv; v->ghat = g->ghat; v->degree = g->degree; v->mask = g->mask; v->comp = g->comp;
+  return RW_OK;
+}
+
+int rw_graph_components(rw_graph h, int64_t* n_components, hipStream_t stream) {
+  RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
+  Graph* g = &h->g;
+  RW_TRY(graph_components(g, stream));
+  if (n_components) {
+    RW_HIP(hipMemsetAsync(g->cc_flag + 2, 0, 2 * sizeof(int), stream));
+    k_cc_count<<<nblocks(g->N, 256), 256, 0, stream>>>(g->comp, g->N, reinterpret_cast<unsigned long long*>(g->cc_flag + 2));
+    RW_LAUNCH_CHECK();
+    unsigned long long cnt = 0;
+    RW_HIP(hipMemcpyAsync(&cnt, g->cc_flag + 2, sizeof(cnt), hipMemcpyDeviceToHost, stream));
+    RW_HIP(hipStreamSynchronize(stream));
+    *n_components = (int64_t)cnt;
+  }
   return RW_OK;
 }
 

@@ -80,7 +80,13 @@ struct Graph {
   uint8_t* mask = nullptr;  // N
   double* partial = nullptr;  // reduction partials (kReduceBlocks)
   double* sums = nullptr;     // [0] = sum of degrees
+  int64_t* comp = nullptr;    // N: component root (the smallest node index) over edges with w >= kAnchorWeight
+  int* cc_flag = nullptr;     // device scratch for the component and anchoring kernels
+  bool cc_valid = false;      // comp matches the current weights
 };
+
+// edges below this weight do not connect nodes for the solvability check (they underflow in FP32)
+constexpr double kAnchorWeight = 1e-30;
 
 constexpr int kReduceBlocks = 1024;
 
@@ -143,6 +149,11 @@ template <> struct Elem<uint16_t> {
 
 size_t graph_layout(const rw_graph_desc& d, Graph* g, void* buf);  // returns bytes
 int graph_rebuild(Graph* g, hipStream_t s);   // weights -> degree, dinv, ghat, coef, diag
+// Connected components of the graph restricted to edges with w >= kAnchorWeight (computed on first use
+// after a build or edit, then cached), and the check that every component holds a seed: RW_EUNANCHORED
+// otherwise.  seeds: device array of S node ids; flags: device scratch of N bytes.
+int graph_components(Graph* g, hipStream_t s);
+int check_anchored(Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, hipStream_t s);
 
 // ---- stencil operator --------------------------------------------------------------------------
 // Y = alpha * op(X) + beta * X + gamma * Z   (column-major N x b, graph dtype)

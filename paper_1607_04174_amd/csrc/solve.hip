@@ -21,6 +21,7 @@ static inline int fit_cands(int ma) { return std::max(1, std::min(ma - 1, 256));
 
 struct SolveWork {
   uint8_t* map;       // N: 0 = not a seed, else label + 1
+  uint8_t* anc;       // N: anchoring check scratch
   int64_t* seeds;     // S
   int32_t* labels;    // S
   double* Qs;         // S x ma   (seed rows of Q)
@@ -52,6 +53,7 @@ static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base,
   int64_t ms = std::min<int64_t>(S, ma);
   SolveWork t;
   t.map = c.take<uint8_t>(g->N);
+  t.anc = c.take<uint8_t>(g->N);
   t.seeds = c.take<int64_t>(S);
   t.labels = c.take<int32_t>(S);
   t.Qs = c.take<double>(S * ma);
@@ -538,6 +540,7 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
   // seeds to the device; map of seeded nodes
   RW_HIP(hipMemcpyAsync(w.seeds, nodes.data(), S * sizeof(int64_t), hipMemcpyHostToDevice, stream));
   RW_HIP(hipMemcpyAsync(w.labels, labels.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  RW_TRY(check_anchored(&h->g, w.seeds, S, w.anc, stream));
   k_clear_map<<<nblocks(g->N, 256), 256, 0, stream>>>(w.map, g->N);
   RW_LAUNCH_CHECK();
   k_set_map<<<nblocks(S, 256), 256, 0, stream>>>(w.map, w.seeds, w.labels, S);

@@ -123,3 +123,50 @@ def test_invalid_graph_arguments():
         rw.Graph(J, (4, 3), 6, 1.0)          # 6-connectivity is 3D only
     with pytest.raises(rw.RWError):
         rw.Graph(J, (4, 3), 4, -1.0)         # beta < 0
+
+
+@pytest.mark.parametrize("dims,conn,dt", [((40, 31), 4, torch.float32), ((33, 29), 8, torch.float64),
+                                          ((14, 12, 11), 6, torch.float32)])
+def test_components_match_scipy(dims, conn, dt):
+    """Components over edges with w >= 1e-30 against scipy's connected components on the oracle's edge list:
+    the same partition (each node's root is its component's smallest node index)."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    need_gpu()
+    banner(f"components {dims} conn={conn}")
+    w = rwsynth.small("cc", dims, conn, n_shapes=4, beta=90.0)
+    J, rid, node, lab = setup_case(w)
+    J = J.copy()
+    J[rid == 1] += 12.0                    # shape 1 cut off: weights exp(-90 * 144) underflow to 0
+    gg = rw.Graph(to_dev(J, torch.float64), w.dims, w.conn, 90.0, dtype=dt)
+    og = OGraph(J, w.dims, w.conn, 90.0)
+    keep = og.w >= 1e-30
+    A = sp.coo_matrix((np.ones(keep.sum()), (og.tail[keep], og.head[keep])), shape=(og.N, og.N))
+    n_ref, labels = connected_components(A, directed=False)
+    n_gpu, comp = gg.components()
+    comp = comp.cpu().numpy()
+    assert n_gpu == n_ref
+    first = np.full(n_ref, og.N)
+    np.minimum.at(first, labels, np.arange(og.N))
+    np.testing.assert_array_equal(comp, first[labels])
+
+
+def test_unanchored_component_is_reported():
+    need_gpu()
+    w = rwsynth.small("ua", (20, 20), 4, n_shapes=1)
+    J = np.zeros(w.N)
+    box = np.zeros((20, 20), dtype=bool)
+    box[6:12, 7:13] = True
+    J[box.reshape(-1)] = 10.0                # exp(-90 * 100) = 0: the box is its own component
+    outside = np.flatnonzero(~box.reshape(-1))
+    inside = np.flatnonzero(box.reshape(-1))
+    node = np.array([outside[0], outside[-1]])
+    lab = np.array([0, 1], dtype=np.int32)
+    g = rw.Graph(to_dev(J, torch.float64), w.dims, w.conn, 90.0, dtype=torch.float64)
+    assert g.components()[0] == 2
+    Q, lam, _ = rw.precompute_eig(g, 8, tol=1e-9)
+    for call in (lambda n, l: rw.solve_seeds(g, Q, lam, n, l, 2), lambda n, l: rw.cg_solve(g, n, l, 2)):
+        with pytest.raises(rw.RWError) as ei:
+            call(node, lab)
+        assert ei.value.status == rw.RW_EUNANCHORED
+        call(np.append(node, inside[0]), np.append(lab, 0).astype(np.int32))   # anchored: no error
