@@ -24,10 +24,6 @@ static int64_t gram_chunks(int64_t rows, int bx, int by) {
   return std::max<int64_t>(1, c);
 }
 
-size_t gram_partial_count(int64_t rows, int bx, int by) {
-  return (size_t)gram_chunks(rows, bx, by) * bx * by;
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram(const T* X, int64_t ldx, const T* Y, int64_t ldy,
                                               int64_t rows, int bx, int by, int64_t chunk_rows,
@@ -80,6 +76,70 @@ __global__ __launch_bounds__(256) void k_gram(const T* X, int64_t ldx, const T* 
     }
 }
 
+// Large Gram tiles: 128 x 128 outputs per 256-thread block, 8 x 8 per thread (rows tx + 16 a, columns
+// ty + 16 b), 32-row slabs of X and Y staged in LDS as FP64: each LDS value feeds 8 FMAs.  With `sym`
+// (X^T Y known to be symmetric, e.g. X = Y) only tiles on or above the diagonal are computed and the
+// off-diagonal ones are written to both places.
+constexpr int kGB = 128;
+constexpr int kGBK = 32;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram_big(const T* X, int64_t ldx, const T* Y, int64_t ldy, int64_t rows,
+                                                  int bx, int by, int64_t chunk_rows, double* out, int64_t out_stride,
+                                                  int sym) {
+  if (sym && blockIdx.x > blockIdx.y) return;
+  __shared__ double sX[kGBK][kGB + 1];
+  __shared__ double sY[kGBK][kGB + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i0 = blockIdx.x * kGB, j0 = blockIdx.y * kGB;
+  const int64_t r_begin = blockIdx.z * chunk_rows;
+  const int64_t r_end = std::min<int64_t>(rows, r_begin + chunk_rows);
+  double acc[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
+  const int lr = threadIdx.x & 31;      // row within the slab
+  const int lc = threadIdx.x >> 5;      // 0..7: column group
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGBK) {
+    const int64_t row = r0 + lr;
+    const bool rin = row < r_end;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = lc + 8 * q;
+      const int ci = i0 + col, cj = j0 + col;
+      sX[lr][col] = (rin && ci < bx) ? (double)Elem<T>::ld(X, (int64_t)ci * ldx + row) : 0.0;
+      sY[lr][col] = (rin && cj < by) ? (double)Elem<T>::ld(Y, (int64_t)cj * ldy + row) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int k = 0; k < kGBK; ++k) {
+      double xv[8], yv[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) xv[a] = sX[k][tx + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) yv[b] = sY[k][ty + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[a][b] = fma(xv[a], yv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  double* o = out + blockIdx.z * out_stride;
+  const bool mirror = sym && blockIdx.x < blockIdx.y;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
+      if (i < bx && j < by) {
+        o[(int64_t)j * bx + i] = acc[a][b];
+        if (mirror) o[(int64_t)i * bx + j] = acc[a][b];
+      }
+    }
+}
+
 __global__ void k_sum_chunks(const double* partial, int64_t count, int64_t nchunks, double* G) {
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= count) return;
@@ -88,23 +148,50 @@ __global__ void k_sum_chunks(const double* partial, int64_t count, int64_t nchun
   G[k] = s;
 }
 
+static int64_t gram_big_chunks(int64_t rows, int bx, int by) {
+  // about 512 blocks, at least 2048 rows per chunk
+  int64_t tiles = (int64_t)((bx + kGB - 1) / kGB) * ((by + kGB - 1) / kGB);
+  int64_t want = std::max<int64_t>(1, 512 / std::max<int64_t>(1, tiles));
+  int64_t by_rows = std::max<int64_t>(1, rows / 2048);
+  return std::max<int64_t>(1, std::min<int64_t>(want, by_rows));
+}
+
+static bool gram_is_big(int bx, int by) { return bx >= 96 && by >= 96; }
+
+size_t gram_partial_count(int64_t rows, int bx, int by) {
+  int64_t nch = gram_is_big(bx, by) ? gram_big_chunks(rows, bx, by) : gram_chunks(rows, bx, by);
+  return (size_t)nch * bx * by;
+}
+
 int gram(int dt, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t rows, int bx, int by,
-         double* G, double* partial, hipStream_t s) {
+         double* G, double* partial, hipStream_t s, bool sym) {
   if (bx <= 0 || by <= 0) return RW_OK;
-  int64_t nch = gram_chunks(rows, bx, by);
+  const bool big = gram_is_big(bx, by);
+  const int tile = big ? kGB : kGT, slab = big ? kGBK : kGK;
+  int64_t nch = big ? gram_big_chunks(rows, bx, by) : gram_chunks(rows, bx, by);
   int64_t chunk_rows = (rows + nch - 1) / nch;
-  chunk_rows = (chunk_rows + kGK - 1) / kGK * kGK;
-  if (chunk_rows == 0) chunk_rows = kGK;
+  chunk_rows = (chunk_rows + slab - 1) / slab * slab;
+  if (chunk_rows == 0) chunk_rows = slab;
   nch = std::max<int64_t>(1, (rows + chunk_rows - 1) / chunk_rows);
-  dim3 grid((bx + kGT - 1) / kGT, (by + kGT - 1) / kGT, (unsigned)nch);
+  dim3 grid((bx + tile - 1) / tile, (by + tile - 1) / tile, (unsigned)nch);
   int64_t count = (int64_t)bx * by;
   double* dst = nch == 1 ? G : partial;
-  if (dt == RW_F64)
-    k_gram<double><<<grid, 256, 0, s>>>((const double*)X, ldx, (const double*)Y, ldy, rows, bx, by, chunk_rows, dst, count);
-  else if (dt == RW_F32)
-    k_gram<float><<<grid, 256, 0, s>>>((const float*)X, ldx, (const float*)Y, ldy, rows, bx, by, chunk_rows, dst, count);
-  else
-    k_gram<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)X, ldx, (const uint16_t*)Y, ldy, rows, bx, by, chunk_rows, dst, count);
+  const int sy = (sym && bx == by) ? 1 : 0;
+  if (big) {
+    if (dt == RW_F64)
+      k_gram_big<double><<<grid, 256, 0, s>>>((const double*)X, ldx, (const double*)Y, ldy, rows, bx, by, chunk_rows, dst, count, sy);
+    else if (dt == RW_F32)
+      k_gram_big<float><<<grid, 256, 0, s>>>((const float*)X, ldx, (const float*)Y, ldy, rows, bx, by, chunk_rows, dst, count, sy);
+    else
+      k_gram_big<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)X, ldx, (const uint16_t*)Y, ldy, rows, bx, by, chunk_rows, dst, count, sy);
+  } else {
+    if (dt == RW_F64)
+      k_gram<double><<<grid, 256, 0, s>>>((const double*)X, ldx, (const double*)Y, ldy, rows, bx, by, chunk_rows, dst, count);
+    else if (dt == RW_F32)
+      k_gram<float><<<grid, 256, 0, s>>>((const float*)X, ldx, (const float*)Y, ldy, rows, bx, by, chunk_rows, dst, count);
+    else
+      k_gram<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)X, ldx, (const uint16_t*)Y, ldy, rows, bx, by, chunk_rows, dst, count);
+  }
   RW_LAUNCH_CHECK();
   if (nch > 1) {
     k_sum_chunks<<<nblocks(count, 256), 256, 0, s>>>(partial, count, nch, G);

@@ -97,7 +97,7 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX) {
   const Graph* g = c.g;
   EigWork& w = c.w;
   const int64_t n2 = (int64_t)nb * nb;
-  RW_TRY(gram(c.dt, F, c.N, F, c.N, c.N, nb, nb, w.G, w.partial, c.s));
+  RW_TRY(gram(c.dt, F, c.N, F, c.N, c.N, nb, nb, w.G, w.partial, c.s, true));
   k_copy_d<<<nblocks(n2, 256), 256, 0, c.s>>>(w.G, w.G2, n2);
   RW_LAUNCH_CHECK();
   RW_TRY(chol_batched(w.G2, nb, 1, w.info, c.s));
@@ -113,7 +113,7 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX) {
   }
   RW_TRY(stencil_apply(g, F, LF, nullptr, nb, 1.0, 0.0, 0.0, c.s));
   c.spmm_cols += nb;
-  RW_TRY(gram(c.dt, F, c.N, LF, c.N, c.N, nb, nb, w.H, w.partial, c.s));
+  RW_TRY(gram(c.dt, F, c.N, LF, c.N, c.N, nb, nb, w.H, w.partial, c.s, true));
   RW_TRY(gemm_tn(RW_F64, w.H, nb, w.W, nb, w.T, nb, nb, nb, nb, 0.0, c.s));       // T = H W
   RW_TRY(gram(RW_F64, w.W, nb, w.T, nb, nb, nb, nb, w.Hp, w.partial, c.s));        // Hp = W^T H W
   k_symmetrize<<<nblocks((int64_t)nb * nb, 256), 256, 0, c.s>>>(w.Hp, nb);
@@ -343,7 +343,7 @@ int rw_update_eig(rw_graph h, const rw_edit* edits, int n_edits, int mode, const
       int src = 0;
       for (int pass = 0; pass < 2; ++pass) {
         int dst = pass == 0 ? 1 : 2;
-        RW_TRY(gram(c.dt, w.B[src], c.N, w.B[src], c.N, c.N, k, k, w.G, w.partial, stream));
+        RW_TRY(gram(c.dt, w.B[src], c.N, w.B[src], c.N, c.N, k, k, w.G, w.partial, stream, true));
         RW_TRY(chol_batched(w.G, k, 1, w.info, stream));
         int bad = 0;
         RW_HIP(hipMemcpyAsync(&bad, w.info, sizeof(int), hipMemcpyDeviceToHost, stream));

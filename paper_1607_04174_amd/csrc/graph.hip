@@ -212,24 +212,39 @@ int graph_rebuild(Graph* g, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Connected components by hooking and pointer jumping.  comp[i] points towards a root (comp[r] = r)
-// and only ever decreases.  A round hooks, for every edge above the anchor weight whose endpoints have
-// different roots, the larger root under the smaller one (atomic minimum), then shortcuts every node to
-// its root.  Rounds repeat until one changes nothing; the root of each component is then its smallest
-// node index.
+// Connected components by hooking and pointer jumping.  comp[i] points to a smaller node of the same
+// component, or to itself at a root.  A round hooks, for every edge above the anchor weight whose
+// endpoints have different roots, the larger root under the smaller one (atomic minimum), then
+// shortcuts every node to its root.  Rounds repeat until one finds no edge between different roots;
+// the root of each component is then its smallest node index.
 // ---------------------------------------------------------------------------------------------
-__device__ __forceinline__ int64_t cc_find(const int64_t* comp, int64_t x) {
-  int64_t r = comp[x];
-  while (r != x) {
-    x = r;
-    r = comp[x];
+// root of x with path halving (each visited node is re-pointed to its grandparent; pointers only move
+// towards smaller indices, so concurrent halving and hooking keep every chain ending at a root)
+__device__ __forceinline__ int64_t cc_find(int64_t* comp, int64_t x) {
+  int64_t p = comp[x];
+  while (p != x) {
+    const int64_t gp = comp[p];
+    if (gp != p) comp[x] = gp;
+    x = p;
+    p = gp;
   }
   return x;
 }
 
-__global__ void k_cc_init(int64_t* comp, int64_t N) {
+// start from the smallest index among each node and its anchored forward neighbours' tails, so the
+// first hooking round already sees short chains
+template <typename T>
+__global__ void k_cc_init(GridDev G, const T* weight, const uint8_t* mask, int64_t* comp) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < N) comp[i] = i;
+  if (i >= G.N) return;
+  int64_t c = i;
+  const int64_t x = i % G.nx, y = (i / G.nx) % G.ny, z = i / (G.nx * G.ny);
+  for (int d = 0; d < G.ndir; ++d) {
+    if (!tail_in(G, x, y, z, d)) continue;
+    const int64_t t = i - G.off[d];
+    if (((mask[t] >> d) & 1) && (double)weight[d * G.N + t] >= kAnchorWeight && t < c) c = t;
+  }
+  comp[i] = c;
 }
 
 template <typename T>
@@ -243,21 +258,34 @@ __global__ void k_cc_hook(GridDev G, const T* weight, const uint8_t* mask, int64
     const int64_t a = cc_find(comp, i), b = cc_find(comp, i + G.off[d]);
     if (a == b) continue;
     const int64_t lo = a < b ? a : b, hi = a < b ? b : a;
-    const unsigned long long old =
-        atomicMin(reinterpret_cast<unsigned long long*>(&comp[hi]), (unsigned long long)lo);
-    if ((int64_t)old > lo) *changed = 1;
+    atomicMin(reinterpret_cast<unsigned long long*>(&comp[hi]), (unsigned long long)lo);
+    // another round whenever an edge joined two roots: a concurrent hook may have re-pointed `hi` first,
+    // and only a later round sees the two trees again
+    *changed = 1;
   }
 }
 
+// full compression: every node to its root.  The walk is read-only (no halving), so the only store to
+// comp[i] is this thread's, and after the last round every entry is its root (the anchoring check and
+// the component count rely on that).
 __global__ void k_cc_jump(int64_t* comp, int64_t N) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < N) comp[i] = cc_find(comp, i);
+  if (i >= N) return;
+  int64_t x = i, p = comp[i];
+  while (p != x) {
+    x = p;
+    p = comp[x];
+  }
+  comp[i] = x;
 }
 
 int graph_components(Graph* g, hipStream_t s) {
   if (g->cc_valid) return RW_OK;
   const GridDev G = grid_of(g);
-  k_cc_init<<<nblocks(g->N, 256), 256, 0, s>>>(g->comp, g->N);
+  if (g->dtype == RW_F64)
+    k_cc_init<double><<<nblocks(g->N, 256), 256, 0, s>>>(G, (const double*)g->weight, g->mask, g->comp);
+  else
+    k_cc_init<float><<<nblocks(g->N, 256), 256, 0, s>>>(G, (const float*)g->weight, g->mask, g->comp);
   RW_LAUNCH_CHECK();
   for (int round = 0;; ++round) {
     RW_CHECK(round < 4096, RW_ENOCONV, "connected components did not settle");

@@ -165,8 +165,10 @@ int stencil_apply(const Graph* g, const void* X, void* Y, const void* Z, int64_t
 // Y (rows x by, ld ldy) of element type dt (RW_F64 / RW_F32 / RW_BF16).  Deterministic two-stage
 // reduction over row chunks through `partial` (gram_partial_count doubles).
 size_t gram_partial_count(int64_t rows, int bx, int by);
+// sym: the product is known to be symmetric (X = Y, or X^T M X with M symmetric); only the upper tiles
+// are computed and mirrored.
 int gram(int dt, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t rows, int bx, int by,
-         double* G, double* partial, hipStream_t s);
+         double* G, double* partial, hipStream_t s, bool sym = false);
 // Z (rows x n, ld ldz, type dt) = X (rows x k, ld ldx, type dt) * V (FP64, k x n, ld ldv)
 //   (+ beta * Z when beta != 0)
 int gemm_tn(int dt, const void* X, int64_t ldx, const double* V, int64_t ldv, void* Z, int64_t ldz,

@@ -362,44 +362,64 @@ __global__ __launch_bounds__(64) void k_fit_secular(const int* cand, int ncand, 
 // relative) around f_max.  Everything else (an active or
 // nearly active constraint, a value inside the band, or m beyond the first pivot below 1e-12 of its
 // diagonal entry, where G's leading block is numerically singular, as for every m > S) is left to
-// the eigen-based evaluation.
+// the eigen-based evaluation.  The factorization stops at the first m whose residual is at most f_max
+// for every label; larger m stay undecided (the search never needs them unless that m is undecided).
 // One workgroup; the factors live in the workspace (global memory, L2-resident).
 __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int C, int64_t S, const double* Gq, const double* Gb,
                                                      const double* Us, double rho2, double f_max, double* L,
                                                      double* Ri, double* Z, double* F, int* cls) {
   __shared__ int s_kf;
   __shared__ double s_bn[64];   // C <= 64 (checked by the caller)
+  __shared__ double s_r[64];    // running residual ||b||^2 - sum_{j<k} z_j^2 per label
+  __shared__ double s_col[1024];
   const int tid = threadIdx.x;
-  const int tx = tid & 31, ty = tid >> 5;
-  for (int64_t t = tid; t < (int64_t)ma * ma; t += blockDim.x) L[t] = Gq[t];
   if (tid == 0) s_kf = ma;
   if (tid < 64) {
     for (int c = 0; c < C; ++c) {
       double acc = 0.0;
       for (int64_t i = tid; i < S; i += 64) acc += Us[i + c * S] * Us[i + c * S];
       for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-      if (tid == 0) s_bn[c] = acc;
+      if (tid == 0) {
+        s_bn[c] = acc;
+        s_r[c] = acc;
+      }
     }
   }
   __syncthreads();
-  // right-looking Cholesky on the lower triangle, stopped at the first small pivot
+  // Left-looking Cholesky, one column per step, with z = L^{-1} g carried along: column k needs only the
+  // columns before it, so the factorization stops at the first small pivot (numerically singular
+  // leading block) or as soon as every label's running residual r(k+1) is at most f_max (no larger m
+  // is needed: the first m that can pass is at most k+1).
   for (int k = 0; k < ma; ++k) {
-    if (tid == 0) {
-      const double akk = L[k + (int64_t)k * ma];
-      if (!(akk > 1e-12 * Gq[k + (int64_t)k * ma]) || !isfinite(akk)) s_kf = k;
-      else L[k + (int64_t)k * ma] = sqrt(akk);
+    for (int i = k + tid; i < ma; i += blockDim.x) {
+      double acc = Gq[i + (int64_t)k * ma];
+      for (int j = 0; j < k; ++j) acc -= L[i + (int64_t)j * ma] * L[k + (int64_t)j * ma];
+      s_col[i] = acc;
     }
     __syncthreads();
-    if (s_kf < ma) break;
-    const double piv = L[k + (int64_t)k * ma];
-    for (int i = k + 1 + tid; i < ma; i += blockDim.x) L[i + (int64_t)k * ma] /= piv;
-    __syncthreads();
-    for (int j = k + 1 + ty; j < ma; j += 32) {
-      const double ljk = L[j + (int64_t)k * ma];
-      for (int i = j + tx; i < ma; i += 32) L[i + (int64_t)j * ma] -= L[i + (int64_t)k * ma] * ljk;
+    const double dkk = s_col[k];
+    if (!(dkk > 1e-12 * Gq[k + (int64_t)k * ma]) || !isfinite(dkk)) {   // uniform: every thread reads s_col[k]
+      if (tid == 0) s_kf = k;
+      break;
+    }
+    const double lkk = sqrt(dkk);
+    for (int i = k + tid; i < ma; i += blockDim.x) L[i + (int64_t)k * ma] = i == k ? lkk : s_col[i] / lkk;
+    if (tid < C) {
+      double acc = Gb[k + (int64_t)tid * ma];
+      for (int j = 0; j < k; ++j) acc -= L[k + (int64_t)j * ma] * Z[j + (int64_t)tid * ma];
+      const double z = acc / lkk;
+      Z[k + (int64_t)tid * ma] = z;
+      s_r[tid] -= z * z;
     }
     __syncthreads();
+    double worst = 0.0;
+    for (int c = 0; c < C; ++c) worst = fmax(worst, s_r[c]);
+    if (worst <= f_max) {          // uniform
+      if (tid == 0) s_kf = k + 1;
+      break;
+    }
   }
+  __syncthreads();
   const int kf = s_kf;      // leading blocks of size <= kf are factorized
   // Ri = L^{-T} (upper triangular) on the leading kf block: one wave per column
   const int wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
@@ -413,14 +433,6 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int C, int64_t S, c
       for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
       x[i] = -acc / L[i + (int64_t)i * ma];     // every lane stores the same value
     }
-  }
-  __syncthreads();
-  // z_c = L^{-1} g_c:  z_j = sum_{i <= j} Ri(i, j) g_i
-  for (int t = tid; t < kf * C; t += blockDim.x) {
-    const int j = t % kf, c = t / kf;
-    double acc = 0.0;
-    for (int i = 0; i <= j; ++i) acc += Ri[i + (int64_t)j * ma] * Gb[i + (int64_t)c * ma];
-    Z[j + (int64_t)c * ma] = acc;
   }
   __syncthreads();
   // per m in [1, ma]: residual r(m) = ||b||^2 - sum_{j<m} z_j^2 and the fit's squared norm
@@ -571,7 +583,7 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
   double f_max = 0.0, f_worst = 0.0;
   if (eps > 0.0) {
     f_max = (double)S * eps * eps;
-    RW_TRY(gram(RW_F64, w.Qs, S, w.Qs, S, S, ma, ma, w.Gq, w.partial, stream));
+    RW_TRY(gram(RW_F64, w.Qs, S, w.Qs, S, S, ma, ma, w.Gq, w.partial, stream, true));
     RW_TRY(gram(RW_F64, w.Qs, S, w.Us, S, S, ma, C, w.Gb, w.partial, stream));
     double rho2 = 0.0;
     if (g->normalized) {
