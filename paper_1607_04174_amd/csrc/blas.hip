@@ -411,10 +411,50 @@ __global__ void k_rank1_sub(T* X, int64_t ld, const T* v, const double* t, int64
   Elem<T>::st(X, idx, val);
 }
 
+// d_j = v^T X_j for one vector v (the 1 x cols Gram): block (j, chunk) reduces its rows in a fixed order
+// (strided per-thread sums, then a tree in LDS); FP64 accumulation.  HBM-bound: X is read once.
+template <typename T>
+__global__ __launch_bounds__(256) void k_vdot_cols(const T* v, const T* X, int64_t ld, int64_t rows,
+                                                   int64_t chunk_rows, int cols, double* out) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  const int64_t r0 = blockIdx.y * chunk_rows;
+  const int64_t r1 = std::min<int64_t>(rows, r0 + chunk_rows);
+  const T* xj = X + (int64_t)j * ld;
+  double acc = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256)
+    acc += (double)Elem<T>::ld(v, r) * (double)Elem<T>::ld(xj, r);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[(int64_t)blockIdx.y * cols + j] = red[0];
+}
+
+static int vdot_cols(int dt, const void* v, const void* X, int64_t ld, int64_t rows, int cols, double* d,
+                     double* partial, hipStream_t s) {
+  int64_t nch = gram_chunks(rows, 1, cols);        // the partial buffer holds nch x cols values
+  int64_t chunk_rows = (rows + nch - 1) / nch;
+  nch = (rows + chunk_rows - 1) / chunk_rows;
+  double* dst = nch == 1 ? d : partial;
+  dim3 grid(cols, (unsigned)nch);
+  if (dt == RW_F64) k_vdot_cols<double><<<grid, 256, 0, s>>>((const double*)v, (const double*)X, ld, rows, chunk_rows, cols, dst);
+  else if (dt == RW_F32) k_vdot_cols<float><<<grid, 256, 0, s>>>((const float*)v, (const float*)X, ld, rows, chunk_rows, cols, dst);
+  else k_vdot_cols<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)v, (const uint16_t*)X, ld, rows, chunk_rows, cols, dst);
+  RW_LAUNCH_CHECK();
+  if (nch > 1) {
+    k_sum_chunks<<<nblocks(cols, 256), 256, 0, s>>>(partial, cols, nch, d);
+    RW_LAUNCH_CHECK();
+  }
+  return RW_OK;
+}
+
 int project_out(int dt, void* X, int64_t ld, const void* v, int64_t rows, int cols, double* tmp, double* partial,
                 hipStream_t s) {
   if (cols <= 0) return RW_OK;
-  RW_TRY(gram(dt, v, rows, X, ld, rows, 1, cols, tmp, partial, s));
+  RW_TRY(vdot_cols(dt, v, X, ld, rows, cols, tmp, partial, s));
   dim3 grid(nblocks(rows, 256), cols);
   if (dt == RW_F64) k_rank1_sub<double><<<grid, 256, 0, s>>>((double*)X, ld, (const double*)v, tmp, rows, cols);
   else if (dt == RW_F32) k_rank1_sub<float><<<grid, 256, 0, s>>>((float*)X, ld, (const float*)v, tmp, rows, cols);

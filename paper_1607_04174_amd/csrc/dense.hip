@@ -211,37 +211,89 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
       // Both stores keep a zero-padded dummy index (odd n) at zero, so loads need no bounds tests:
       // every load is issued unconditionally (a block outside k1 < k2 reads pair k2's own entries and
       // is not stored), and only the stores are predicated.
-      for (int k2 = tb; k2 < np; k2 += 32) {
-        const double c2 = cs[k2], s2 = sn[k2];
-        const int p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
-        for (int k1b = ta; k1b < k2; k1b += 128) {
-          double b0[4], b1[4], b2[4], b3[4], c1[4], s1[4];
-          int p1[4], q1[4];
+      if constexpr (Store::kLdsOnly) {
+        // LDS variant (np <= 100): this thread's four k1 pairs are fixed for the round, so their
+        // rotations and packed row bases are loaded once; a packed index is then the larger index's
+        // base plus the smaller index
+        double c1[4], s1[4];
+        int p1[4], q1[4], bp1[4], bq1[4];
+        bool in1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k1 = ta + 32 * u;
+          in1[u] = k1 < np;
+          const int kk = in1[u] ? k1 : 0;
+          c1[u] = cs[kk];
+          s1[u] = sn[kk];
+          p1[u] = pq[2 * kk];
+          q1[u] = pq[2 * kk + 1];
+          bp1[u] = (p1[u] * (p1[u] + 1)) >> 1;
+          bq1[u] = (q1[u] * (q1[u] + 1)) >> 1;
+        }
+        for (int k2 = tb; k2 < np; k2 += 32) {
+          const double c2 = cs[k2], s2 = sn[k2];
+          const int p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
+          const int bp2 = (p2 * (p2 + 1)) >> 1, bq2 = (q2 * (q2 + 1)) >> 1;
+          double b0[4], b1[4], b2[4], b3[4];
+          int i0[4], i1[4], i2[4], i3[4];
           bool v[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            const int k1 = k1b + 32 * u;
-            const bool in = k1 < k2;
-            const int kk = in ? k1 : k2;
-            c1[u] = cs[kk];
-            s1[u] = sn[kk];
-            p1[u] = pq[2 * kk];
-            q1[u] = pq[2 * kk + 1];
-            v[u] = in && !(s1[u] == 0.0 && s2 == 0.0);
-            b0[u] = S.ld(p1[u], p2);
-            b1[u] = S.ld(p1[u], q2);
-            b2[u] = S.ld(q1[u], p2);
-            b3[u] = S.ld(q1[u], q2);
+            v[u] = in1[u] && ta + 32 * u < k2 && !(s1[u] == 0.0 && s2 == 0.0);
+            i0[u] = p1[u] < p2 ? bp2 + p1[u] : bp1[u] + p2;
+            i1[u] = p1[u] < q2 ? bq2 + p1[u] : bp1[u] + q2;
+            i2[u] = q1[u] < p2 ? bp2 + q1[u] : bq1[u] + p2;
+            i3[u] = q1[u] < q2 ? bq2 + q1[u] : bq1[u] + q2;
+            b0[u] = S.a[i0[u]];
+            b1[u] = S.a[i1[u]];
+            b2[u] = S.a[i2[u]];
+            b3[u] = S.a[i3[u]];
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const double r00 = c1[u] * b0[u] - s1[u] * b2[u], r01 = c1[u] * b1[u] - s1[u] * b3[u];  // J1^T B
             const double r10 = s1[u] * b0[u] + c1[u] * b2[u], r11 = s1[u] * b1[u] + c1[u] * b3[u];
             if (v[u]) {
-              S.st_sym(p1[u], p2, c2 * r00 - s2 * r01);                                            // (J1^T B) J2
-              S.st_sym(p1[u], q2, s2 * r00 + c2 * r01);
-              S.st_sym(q1[u], p2, c2 * r10 - s2 * r11);
-              S.st_sym(q1[u], q2, s2 * r10 + c2 * r11);
+              S.a[i0[u]] = c2 * r00 - s2 * r01;                                                       // (J1^T B) J2
+              S.a[i1[u]] = s2 * r00 + c2 * r01;
+              S.a[i2[u]] = c2 * r10 - s2 * r11;
+              S.a[i3[u]] = s2 * r10 + c2 * r11;
+            }
+          }
+        }
+      } else {
+        for (int k2 = tb; k2 < np; k2 += 32) {
+          const double c2 = cs[k2], s2 = sn[k2];
+          const int p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
+          for (int k1b = ta; k1b < k2; k1b += 128) {
+            double b0[4], b1[4], b2[4], b3[4], c1[4], s1[4];
+            int p1[4], q1[4];
+            bool v[4];
+  #pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int k1 = k1b + 32 * u;
+              const bool in = k1 < k2;
+              const int kk = in ? k1 : k2;
+              c1[u] = cs[kk];
+              s1[u] = sn[kk];
+              p1[u] = pq[2 * kk];
+              q1[u] = pq[2 * kk + 1];
+              v[u] = in && !(s1[u] == 0.0 && s2 == 0.0);
+              b0[u] = S.ld(p1[u], p2);
+              b1[u] = S.ld(p1[u], q2);
+              b2[u] = S.ld(q1[u], p2);
+              b3[u] = S.ld(q1[u], q2);
+            }
+  #pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const double r00 = c1[u] * b0[u] - s1[u] * b2[u], r01 = c1[u] * b1[u] - s1[u] * b3[u];  // J1^T B
+              const double r10 = s1[u] * b0[u] + c1[u] * b2[u], r11 = s1[u] * b1[u] + c1[u] * b3[u];
+              if (v[u]) {
+                S.st_sym(p1[u], p2, c2 * r00 - s2 * r01);                                            // (J1^T B) J2
+                S.st_sym(p1[u], q2, s2 * r00 + c2 * r01);
+                S.st_sym(q1[u], p2, c2 * r10 - s2 * r11);
+                S.st_sym(q1[u], q2, s2 * r10 + c2 * r11);
+              }
             }
           }
         }
