@@ -101,17 +101,30 @@ __global__ __launch_bounds__(256) void k_gram_big(const T* X, int64_t ldx, const
     for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
   const int lr = threadIdx.x & 31;      // row within the slab
   const int lc = threadIdx.x >> 5;      // 0..7: column group
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGBK) {
+  // the next slab's values are loaded into registers while the current one is multiplied
+  T px[16], py[16];
+  auto fetch = [&](int64_t r0) {
     const int64_t row = r0 + lr;
     const bool rin = row < r_end;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int col = lc + 8 * q;
       const int ci = i0 + col, cj = j0 + col;
-      sX[lr][col] = (rin && ci < bx) ? (double)Elem<T>::ld(X, (int64_t)ci * ldx + row) : 0.0;
-      sY[lr][col] = (rin && cj < by) ? (double)Elem<T>::ld(Y, (int64_t)cj * ldy + row) : 0.0;
+      px[q] = (rin && ci < bx) ? X[(int64_t)ci * ldx + row] : T(0);
+      py[q] = (rin && cj < by) ? Y[(int64_t)cj * ldy + row] : T(0);
+    }
+  };
+  if (r_begin < r_end) fetch(r_begin);
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGBK) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = lc + 8 * q;
+      sX[lr][col] = (double)Elem<T>::ld(px, q);
+      sY[lr][col] = (double)Elem<T>::ld(py, q);
     }
     __syncthreads();
+    if (r0 + kGBK < r_end) fetch(r0 + kGBK);
 #pragma unroll 2
     for (int k = 0; k < kGBK; ++k) {
       double xv[8], yv[8];
@@ -124,7 +137,6 @@ __global__ __launch_bounds__(256) void k_gram_big(const T* X, int64_t ldx, const
 #pragma unroll
         for (int b = 0; b < 8; ++b) acc[a][b] = fma(xv[a], yv[b], acc[a][b]);
     }
-    __syncthreads();
   }
   double* o = out + blockIdx.z * out_stride;
   const bool mirror = sym && blockIdx.x < blockIdx.y;

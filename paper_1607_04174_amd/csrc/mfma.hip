@@ -19,6 +19,7 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaNodes = 256;   // nodes per workgroup tile (4 waves x 64)
+constexpr int kSQ = 20;           // padded row of the staged Q tile (16 k values + 4)
 
 __device__ __forceinline__ void split_bf16(float v, uint16_t* hi, uint16_t* lo) {
   *hi = f32_to_bf16(v);
@@ -37,8 +38,8 @@ __global__ __launch_bounds__(256) void k_reconstruct_mfma(const uint16_t* __rest
   extern __shared__ char smem[];
   const int mpad = (m + 15) & ~15;
   uint16_t* sBt = reinterpret_cast<uint16_t*>(smem);                    // [16 cols][mpad]
-  uint16_t* sQ = sBt + 16 * mpad;                                       // [256 nodes][16 k]
-  float* sD = reinterpret_cast<float*>(sQ + kMfmaNodes * 16);            // [256 nodes][17]
+  uint16_t* sQ = sBt + 16 * mpad;                                       // [256 nodes][kSQ]
+  float* sD = reinterpret_cast<float*>(sQ + kMfmaNodes * kSQ);           // [256 nodes][17]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t node0 = (int64_t)blockIdx.x * kMfmaNodes;
   // B operand: columns 0..C-1 high parts, C..2C-1 low parts, zero elsewhere
@@ -59,40 +60,50 @@ __global__ __launch_bounds__(256) void k_reconstruct_mfma(const uint16_t* __rest
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   const bool vec = (N & 3) == 0;
-  for (int k0 = 0; k0 < mpad; k0 += 16) {
-    __syncthreads();
-    // stage Q[k0 .. k0+16) x [node0, node0 + 256) transposed into sQ[node][k]
+  // Q[k0 .. k0+16) x [node0, node0 + 256): thread (g, kq) reads rows k0 + 4 kq .. +3 at nodes
+  // node0 + 4 g .. +3 (four 8-byte loads, one step ahead of use), transposes the 4 x 4 block in
+  // registers and stores each node's four k values as one 8-byte word: sQ[node][k] with a padded row
+  // of kSQ elements (no bank conflicts between the 16 node rows a wave touches)
+  const int kq = tid & 3, g = tid >> 2;
+  const int64_t gnode = node0 + 4 * g;
+  uint2 pre[4];
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int idx = tid + 256 * r;        // 0..1023
-      const int col = idx >> 6, g = idx & 63;
-      const int64_t node = node0 + 4 * g;
-      const int k = k0 + col;
-      uint16_t v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+      const int k = k0 + 4 * kq + r;
+      uint2 w = make_uint2(0u, 0u);
       if (k < m) {
-        const uint16_t* src = Q + (int64_t)k * N + node;
-        if (vec && node + 3 < N) {
-          const uint2 w = *reinterpret_cast<const uint2*>(src);
-          v0 = (uint16_t)(w.x & 0xffffu); v1 = (uint16_t)(w.x >> 16);
-          v2 = (uint16_t)(w.y & 0xffffu); v3 = (uint16_t)(w.y >> 16);
+        const uint16_t* src = Q + (int64_t)k * N + gnode;
+        if (vec && gnode + 3 < N) {
+          w = *reinterpret_cast<const uint2*>(src);
         } else {
-          if (node < N) v0 = src[0];
-          if (node + 1 < N) v1 = src[1];
-          if (node + 2 < N) v2 = src[2];
-          if (node + 3 < N) v3 = src[3];
+          const uint32_t v0 = gnode < N ? src[0] : 0u, v1 = gnode + 1 < N ? src[1] : 0u;
+          const uint32_t v2 = gnode + 2 < N ? src[2] : 0u, v3 = gnode + 3 < N ? src[3] : 0u;
+          w = make_uint2(v0 | (v1 << 16), v2 | (v3 << 16));
         }
       }
-      sQ[(4 * g + 0) * 16 + col] = v0;
-      sQ[(4 * g + 1) * 16 + col] = v1;
-      sQ[(4 * g + 2) * 16 + col] = v2;
-      sQ[(4 * g + 3) * 16 + col] = v3;
+      pre[r] = w;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < mpad; k0 += 16) {
+    __syncthreads();
+    {
+      const uint32_t a0 = pre[0].x, a1 = pre[1].x, a2 = pre[2].x, a3 = pre[3].x;   // nodes 0, 1
+      const uint32_t b0 = pre[0].y, b1 = pre[1].y, b2 = pre[2].y, b3 = pre[3].y;   // nodes 2, 3
+      uint2* dst = reinterpret_cast<uint2*>(sQ + (4 * g) * kSQ + 4 * kq);
+      dst[0] = make_uint2((a0 & 0xffffu) | (a1 << 16), (a2 & 0xffffu) | (a3 << 16));
+      dst[kSQ / 4] = make_uint2((a0 >> 16) | (a1 & 0xffff0000u), (a2 >> 16) | (a3 & 0xffff0000u));
+      dst[2 * (kSQ / 4)] = make_uint2((b0 & 0xffffu) | (b1 << 16), (b2 & 0xffffu) | (b3 << 16));
+      dst[3 * (kSQ / 4)] = make_uint2((b0 >> 16) | (b1 & 0xffff0000u), (b2 >> 16) | (b3 & 0xffff0000u));
     }
     __syncthreads();
+    if (k0 + 16 < mpad) fetch(k0 + 16);
     const bf16x4 b = *reinterpret_cast<const bf16x4*>(sBt + (lane & 15) * mpad + k0 + 4 * (lane >> 4));
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int nl = 64 * wave + 16 * t + (lane & 15);
-      const bf16x4 a = *reinterpret_cast<const bf16x4*>(sQ + nl * 16 + 4 * (lane >> 4));
+      const bf16x4 a = *reinterpret_cast<const bf16x4*>(sQ + nl * kSQ + 4 * (lane >> 4));
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
     }
   }
@@ -117,7 +128,7 @@ __global__ __launch_bounds__(256) void k_reconstruct_mfma(const uint16_t* __rest
 
 size_t reconstruct_mfma_lds(int m) {
   const int mpad = (m + 15) & ~15;
-  return (size_t)16 * mpad * 2 + (size_t)kMfmaNodes * 16 * 2 + (size_t)kMfmaNodes * 17 * 4;
+  return (size_t)16 * mpad * 2 + (size_t)kMfmaNodes * kSQ * 2 + (size_t)kMfmaNodes * 17 * 4;
 }
 
 int reconstruct_mfma(const Graph* g, const void* Q, int m, const double* Y, int C, const uint8_t* map, void* U,
