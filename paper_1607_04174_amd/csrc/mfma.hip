@@ -156,9 +156,9 @@ constexpr int kProjMaxChunks = 16;   // m <= 256
 __global__ __launch_bounds__(256) void k_project_mfma(const uint16_t* __restrict__ Q, int64_t N, int m,
                                                       const float* __restrict__ X, int C, int64_t nodes_per_block,
                                                       float* __restrict__ partial) {
-  __shared__ uint16_t sQ[16 * kMfmaNodes];   // [16 cols][256 nodes]
   __shared__ float sR[4][16 * 16];           // per-wave results of one m-chunk
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool vec = (N & 3) == 0;
   const int mchunks = (m + 15) >> 4;
   const int64_t begin = (int64_t)blockIdx.x * nodes_per_block;
   const int64_t end = std::min<int64_t>(N, begin + nodes_per_block);
@@ -186,21 +186,27 @@ __global__ __launch_bounds__(256) void k_project_mfma(const uint16_t* __restrict
       }
       b[st] = bf16x4{e[0], e[1], e[2], e[3]};
     }
+    // A fragments straight from HBM: lane l takes four consecutive nodes of eigenvector 16 q + (l mod 16)
+    // (one 8-byte load when N is a multiple of 4), so Q needs no staging through LDS
 #pragma unroll
     for (int q = 0; q < kProjMaxChunks; ++q) {
       if (q >= mchunks) break;
-      __syncthreads();
-      for (int idx = tid; idx < 16 * kMfmaNodes; idx += 256) {
-        const int col = idx >> 8, nl = idx & 255;
-        const int k = 16 * q + col;
-        const int64_t node = n0 + nl;
-        sQ[idx] = (k < m && node < end) ? Q[(int64_t)k * N + node] : (uint16_t)0;
-      }
-      __syncthreads();
+      const int k = 16 * q + (lane & 15);
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
-        const int nl = 64 * wave + 16 * st + 4 * (lane >> 4);
-        const bf16x4 a = *reinterpret_cast<const bf16x4*>(sQ + (lane & 15) * kMfmaNodes + nl);
+        const int64_t nb = n0 + 64 * wave + 16 * st + 4 * (lane >> 4);
+        bf16x4 a = bf16x4{0, 0, 0, 0};
+        if (k < m) {
+          const uint16_t* src = Q + (int64_t)k * N + nb;
+          if (vec && nb + 3 < end) {
+            a = *reinterpret_cast<const bf16x4*>(src);
+          } else {
+            short e[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) e[v] = nb + v < end ? (short)src[v] : (short)0;
+            a = bf16x4{e[0], e[1], e[2], e[3]};
+          }
+        }
         acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[st], acc[q], 0, 0, 0);
       }
     }
