@@ -398,14 +398,16 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_glb(const double* As,
     }
 }
 
-// V from the logged rotations: V = J(1) J(2) ... applied to the identity; rows are independent, so
-// each workgroup replays every rotation on a slab of kReplayRows rows held in LDS, then writes the
-// columns in sorted order.
-constexpr int kReplayRows = 8;     // rows of V per workgroup (more workgroups, less work each)
-constexpr int kReplayStage = 8;   // rounds of rotations staged in LDS per barrier pair
+// V from the logged rotations: V = J(1) J(2) ... applied to the identity.  Rows are independent: each
+// wave owns kReplayRows rows of V in LDS and applies every round to them with its lanes spread over the
+// round's disjoint pairs, so successive rounds need no workgroup barrier (a wave's LDS accesses are
+// ordered); the workgroup synchronizes only to stage up to kReplayStage rounds of rotations into LDS.  At the
+// end the columns are written in sorted order.
+constexpr int kReplayRows = 1;     // rows of V per wave
+constexpr int kReplayStage = 16;   // rounds of rotations staged in LDS per barrier pair
 
-__global__ __launch_bounds__(256) void k_jacobi_replay(int n, int rows_per_block, const double* work, int64_t stride,
-                                                       int64_t log_off, double* Vs) {
+__global__ __launch_bounds__(256) void k_jacobi_replay(int n, int rows_per_block, int nstage, const double* work,
+                                                       int64_t stride, int64_t log_off, double* Vs) {
   extern __shared__ double vs[];
   const int n2 = n + (n & 1), np = n2 / 2;
   const int b = blockIdx.y;
@@ -416,15 +418,16 @@ __global__ __launch_bounds__(256) void k_jacobi_replay(int n, int rows_per_block
   const double* perm = log + syev_log_count(n);
   const int sweeps = (int)perm[n];
   const int ld = n2 + 1;
-  double* stage = vs + rows_per_block * ld;        // kReplayStage x np x (c, s)
-  int* spq = reinterpret_cast<int*>(stage + kReplayStage * np * 2);   // kReplayStage x np x (p, q)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* stage = vs + rows_per_block * ld;        // nstage x np x (c, s)
+  int* spq = reinterpret_cast<int*>(stage + nstage * np * 2);   // nstage x np x (p, q)
   for (int t = threadIdx.x; t < rows_per_block * ld; t += 256) {
     int r = t / ld, c = t - r * ld;
     vs[t] = (r < rows && c == r0 + r) ? 1.0 : 0.0;
   }
   const int total_rounds = sweeps * (n2 - 1);
-  for (int g0 = 0; g0 < total_rounds; g0 += kReplayStage) {
-    const int ng = min(kReplayStage, total_rounds - g0);
+  for (int g0 = 0; g0 < total_rounds; g0 += nstage) {
+    const int ng = min(nstage, total_rounds - g0);
     lds_barrier();
     for (int t = threadIdx.x; t < ng * np * 2; t += 256) stage[t] = log[(size_t)g0 * np * 2 + t];
     for (int t = threadIdx.x; t < ng * np; t += 256) {
@@ -438,19 +441,25 @@ __global__ __launch_bounds__(256) void k_jacobi_replay(int n, int rows_per_block
     for (int gi = 0; gi < ng; ++gi) {
       const double* L = stage + gi * np * 2;
       const int* PQ = spq + gi * np * 2;
-      for (int t = threadIdx.x; t < kReplayRows * np; t += 256) {
-        int r = t & (kReplayRows - 1), k = t >> 3;
-        if (r >= rows) continue;
-        double s = L[2 * k + 1];
+      for (int k = lane; k < np; k += 64) {
+        const double s = L[2 * k + 1];
         if (s == 0.0) continue;
-        double c = L[2 * k];
-        int p = PQ[2 * k], q = PQ[2 * k + 1];
-        double* v = vs + r * ld;
-        double vp = v[p], vq = v[q];
-        v[p] = c * vp - s * vq;
-        v[q] = s * vp + c * vq;
+        const double c = L[2 * k];
+        const int p = PQ[2 * k], q = PQ[2 * k + 1];
+#pragma unroll
+        for (int r = 0; r < kReplayRows; ++r) {
+          const int row = wave * kReplayRows + r;
+          if (row >= rows) break;
+          double* v = vs + row * ld;
+          const double vp = v[p], vq = v[q];
+          v[p] = c * vp - s * vq;
+          v[q] = s * vp + c * vq;
+        }
       }
-      lds_barrier();
+      // the next round may touch the same entries from other lanes of this wave
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
     }
   }
   lds_barrier();
@@ -484,9 +493,12 @@ int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int
   RW_LAUNCH_CHECK();
   if (vectors) {
     int n2 = n + (n & 1);
-    const size_t stage_bytes = (size_t)kReplayStage * (n2 / 2) * 2 * (sizeof(double) + sizeof(int));
-    int rpb = (int)std::min<size_t>(kReplayRows, (kLdsLimit - stage_bytes) / ((size_t)(n2 + 1) * sizeof(double)));
-    size_t sh = (size_t)rpb * (n2 + 1) * sizeof(double) + stage_bytes;
+    const int rpb = 4 * kReplayRows;     // four waves per workgroup
+    const size_t row_bytes = (size_t)rpb * (n2 + 1) * sizeof(double);
+    const size_t round_bytes = (size_t)(n2 / 2) * 2 * (sizeof(double) + sizeof(int));
+    RW_CHECK(row_bytes + round_bytes <= kLdsLimit, RW_EINVAL, "replay tile exceeds LDS");
+    const int nstage = (int)std::min<size_t>(kReplayStage, (kLdsLimit - row_bytes) / round_bytes);
+    size_t sh = row_bytes + (size_t)nstage * round_bytes;
     static bool attr2 = false;
     if (!attr2) {
       RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_replay),
@@ -495,7 +507,7 @@ int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int
     }
     dim3 grid((n + rpb - 1) / rpb, count);
     int64_t log_off = glb ? (int64_t)n2 * n2 : 0;
-    k_jacobi_replay<<<grid, 256, sh, s>>>(n, rpb, work, stride, log_off, V);
+    k_jacobi_replay<<<grid, 256, sh, s>>>(n, rpb, nstage, work, stride, log_off, V);
     RW_LAUNCH_CHECK();
   }
   return RW_OK;
