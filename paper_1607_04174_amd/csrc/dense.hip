@@ -3,6 +3,7 @@
 // stays L2-resident at these sizes); batched launches give each matrix its own workgroup.
 #include <cmath>
 
+#include "jacobi_layout.h"
 #include "rw_internal.h"
 
 namespace rw {
@@ -84,6 +85,7 @@ int chol_upper_inverse(const double* L, double* Rinv, int n, hipStream_t s) {
 // ---------------------------------------------------------------------------------------------
 constexpr int kJacobiThreads = 1024;
 constexpr int kJacobiMaxSweeps = 30;
+constexpr int kJacobiBlocksPerThread = 5;   // LDS variant: off-diagonal 2 x 2 blocks held per thread
 constexpr size_t kLdsLimit = 160 * 1024 - 64;   // dynamic LDS budget (the kernels' static LDS is 16 bytes)
 
 __device__ __forceinline__ int rr_player(int pos, int round, int n2) {
@@ -99,20 +101,7 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-struct LdsStore {   // packed upper triangle in LDS
-  static constexpr bool kLdsOnly = true;
-  __device__ static void sync() { lds_barrier(); }
-  double* a;
-  __device__ __forceinline__ int at(int i, int j) const {
-    int lo = i < j ? i : j, hi = i < j ? j : i;
-    return (hi * (hi + 1) >> 1) + lo;
-  }
-  __device__ __forceinline__ double ld(int i, int j) const { return a[at(i, j)]; }
-  __device__ __forceinline__ void st_sym(int i, int j, double v) const { a[at(i, j)] = v; }
-};
-
 struct GlbStore {   // full n2 x n2 column-major copy in global memory
-  static constexpr bool kLdsOnly = false;
   __device__ static void sync() { __syncthreads(); }
   double* a;
   int n2;
@@ -138,9 +127,12 @@ static size_t syev_stride(int n, bool vectors, bool glb, int nrhs) {
   return (s + 31) / 32 * 32;
 }
 
+// LDS variant: the position-layout matrix, the round's (c, s) pairs and the right-hand sides
+__host__ __device__ inline size_t lds_cs_offset(int n) { return (size_t)((JacLayout(n).words() + 1) & ~1); }   // in doubles
 static size_t lds_bytes(int n, int nrhs) {
-  int n2 = n + (n & 1), np = n2 / 2;
-  return (size_t)n2 * (n2 + 1) / 2 * 8 + (size_t)np * 16 + (size_t)np * 8 + (size_t)n2 * nrhs * 8 + 16;
+  const JacLayout P(n);
+  if ((int64_t)P.nto > (int64_t)kJacobiThreads * kJacobiBlocksPerThread || P.words() >= 32768) return SIZE_MAX;
+  return (lds_cs_offset(n) + 2 * (size_t)P.np + (size_t)P.n2 * nrhs) * sizeof(double);
 }
 
 size_t syev_work_count(int n, int count, bool vectors, int nrhs) {
@@ -208,60 +200,8 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
       // off-diagonal 2 x 2 blocks of pairs k1 < k2 on a 32 x 32 thread grid (ta = k1 mod 32,
       // tb = k2 mod 32).  Four blocks are loaded before any is stored so that memory latency
       // overlaps; all per-block values stay in registers (constant indices after unrolling).
-      // Both stores keep a zero-padded dummy index (odd n) at zero, so loads need no bounds tests:
-      // every load is issued unconditionally (a block outside k1 < k2 reads pair k2's own entries and
-      // is not stored), and only the stores are predicated.
-      if constexpr (Store::kLdsOnly) {
-        // LDS variant (np <= 100): this thread's four k1 pairs are fixed for the round, so their
-        // rotations and packed row bases are loaded once; a packed index is then the larger index's
-        // base plus the smaller index
-        double c1[4], s1[4];
-        int p1[4], q1[4], bp1[4], bq1[4];
-        bool in1[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k1 = ta + 32 * u;
-          in1[u] = k1 < np;
-          const int kk = in1[u] ? k1 : 0;
-          c1[u] = cs[kk];
-          s1[u] = sn[kk];
-          p1[u] = pq[2 * kk];
-          q1[u] = pq[2 * kk + 1];
-          bp1[u] = (p1[u] * (p1[u] + 1)) >> 1;
-          bq1[u] = (q1[u] * (q1[u] + 1)) >> 1;
-        }
-        for (int k2 = tb; k2 < np; k2 += 32) {
-          const double c2 = cs[k2], s2 = sn[k2];
-          const int p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
-          const int bp2 = (p2 * (p2 + 1)) >> 1, bq2 = (q2 * (q2 + 1)) >> 1;
-          double b0[4], b1[4], b2[4], b3[4];
-          int i0[4], i1[4], i2[4], i3[4];
-          bool v[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            v[u] = in1[u] && ta + 32 * u < k2 && !(s1[u] == 0.0 && s2 == 0.0);
-            i0[u] = p1[u] < p2 ? bp2 + p1[u] : bp1[u] + p2;
-            i1[u] = p1[u] < q2 ? bq2 + p1[u] : bp1[u] + q2;
-            i2[u] = q1[u] < p2 ? bp2 + q1[u] : bq1[u] + p2;
-            i3[u] = q1[u] < q2 ? bq2 + q1[u] : bq1[u] + q2;
-            b0[u] = S.a[i0[u]];
-            b1[u] = S.a[i1[u]];
-            b2[u] = S.a[i2[u]];
-            b3[u] = S.a[i3[u]];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const double r00 = c1[u] * b0[u] - s1[u] * b2[u], r01 = c1[u] * b1[u] - s1[u] * b3[u];  // J1^T B
-            const double r10 = s1[u] * b0[u] + c1[u] * b2[u], r11 = s1[u] * b1[u] + c1[u] * b3[u];
-            if (v[u]) {
-              S.a[i0[u]] = c2 * r00 - s2 * r01;                                                       // (J1^T B) J2
-              S.a[i1[u]] = s2 * r00 + c2 * r01;
-              S.a[i2[u]] = c2 * r10 - s2 * r11;
-              S.a[i3[u]] = s2 * r10 + c2 * r11;
-            }
-          }
-        }
-      } else {
+      // Both stores keep a zero-padded dummy index (odd n) at zero.
+      {
         for (int k2 = tb; k2 < np; k2 += 32) {
           const double c2 = cs[k2], s2 = sn[k2];
           const int p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
@@ -330,38 +270,203 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
   if (threadIdx.x == 0) sweeps_out[0] = (double)sweep;
 }
 
+// LDS variant (n <= 200): the matrix in the position layout (jacobi_layout.h).  A round is three
+// phases separated by workgroup barriers: (1) thread k computes pair k's rotation from its diagonal
+// block, (2) every thread rotates its off-diagonal blocks (a fixed set, held in registers) and the
+// right-hand sides, (3) every entry is written to its next-round position.  Lanes of a wave touch
+// consecutive blocks, so the LDS accesses are free of bank conflicts.  The rotation rule,
+// thresholds and log are those of the global-memory variant (index convention p < q); a sweep runs
+// only while some off-diagonal entry is above the thresholds, which is the same test as a sweep
+// without rotations, evaluated on the matrix at the sweep boundary.
 __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(const double* As, int n, double* ws, double* Rs, int nrhs,
                                                                 double* work, int64_t stride, int want_log) {
   extern __shared__ double smem[];
-  const int n2 = n + (n & 1), np = n2 / 2;
+  const JacLayout P(n);
+  const int n2 = P.n2, np = P.np, nto = P.nto;
   const double* A = As + (int64_t)blockIdx.x * n * n;
   double* wk = work + (int64_t)blockIdx.x * stride;
   double* log = want_log ? wk : nullptr;
   double* perm = wk + (want_log ? syev_log_count(n) : 0);
   double* a = smem;
-  double* cs = a + (size_t)n2 * (n2 + 1) / 2;
-  double* sn = cs + np;
-  int* pq = reinterpret_cast<int*>(sn + np);
-  double* rhs = reinterpret_cast<double*>(pq + 2 * np);
-  LdsStore S{a};
-  for (int64_t t = threadIdx.x; t < (int64_t)n2 * (n2 + 1) / 2; t += kJacobiThreads) a[t] = 0.0;
+  double* dg = a + 4 * nto;                                            // diagonal blocks: aa, ab, bb
+  double2* cs = reinterpret_cast<double2*>(smem + lds_cs_offset(n));  // (c, s) in slot convention
+  double* rhs = reinterpret_cast<double*>(cs + np);
+  __shared__ int big;
+  __shared__ double fro_s;
+  for (int t = threadIdx.x; t < P.words(); t += kJacobiThreads) a[t] = 0.0;
   __syncthreads();
+  // at a sweep boundary position x holds index x
   for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += kJacobiThreads) {
-    int i = (int)(t % n), j = (int)(t / n);
-    if (i <= j) S.st_sym(i, j, 0.5 * (A[t] + A[j + (int64_t)i * n]));
+    const int i = (int)(t % n), j = (int)(t / n);
+    if (i <= j) a[P.at(i, j)] = 0.5 * (A[t] + A[j + (int64_t)i * n]);
   }
   double* R = Rs ? Rs + (int64_t)blockIdx.x * n * nrhs : nullptr;
   if (R)
     for (int64_t t = threadIdx.x; t < (int64_t)n2 * nrhs; t += kJacobiThreads) {
-      int i = (int)(t % n2), r = (int)(t / n2);
+      const int i = (int)(t % n2), r = (int)(t / n2);
       rhs[t] = i < n ? R[i + (int64_t)r * n] : 0.0;
     }
   __syncthreads();
-  jacobi_body(S, n, n2, R ? rhs : nullptr, nrhs, log, ws + (int64_t)blockIdx.x * n, perm, perm + n, cs, sn, pq);
+  if (threadIdx.x < 64) {   // Frobenius norm, one wave, fixed order
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j)
+      for (int i = threadIdx.x; i < n; i += 64) {
+        const double v = a[P.at(i, j)];
+        acc += v * v;
+      }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (threadIdx.x == 0) fro_s = sqrt(acc);
+  }
+  // this thread's off-diagonal blocks and the flat indices their entries move to after a round
+  // (flat indices are below 2^15 at n <= 200, so two share a register)
+  int blk[kJacobiBlocksPerThread], kk[kJacobiBlocksPerThread], dst[kJacobiBlocksPerThread][2];
+#pragma unroll
+  for (int u = 0; u < kJacobiBlocksPerThread; ++u) {
+    const int L = threadIdx.x + u * kJacobiThreads;
+    blk[u] = -1;
+    kk[u] = 0;
+    dst[u][0] = dst[u][1] = 0;
+    if (L < nto) {
+      int k1, k2;
+      P.unfold(L, k1, k2);
+      blk[u] = P.block(k1, k2);
+      kk[u] = k1 | (k2 << 16);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        dst[u][e >> 1] |= P.at(P.next(P.pos(k1, e >> 1)), P.next(P.pos(k2, e & 1))) << (16 * (e & 1));
+    }
+  }
+  int ddst[2] = {0, 0};
+  if (threadIdx.x < np) {
+    const int k = threadIdx.x;
+    ddst[0] = P.at(P.next(P.pos(k, 0)), P.next(P.pos(k, 0))) | (P.at(P.next(P.pos(k, 0)), P.next(P.pos(k, 1))) << 16);
+    ddst[1] = P.at(P.next(P.pos(k, 1)), P.next(P.pos(k, 1)));
+  }
+  __syncthreads();
+  // thresholds: rounding noise regenerates off-diagonal entries of size ~eps |A|, so rotations below
+  // sqrt(n) eps relative to the diagonal, or eps |A|_F absolute, are skipped
+  const double abs_tiny = fro_s * 2.3e-16 + 1e-300;
+  const double rel_tol = 2.3e-16 * sqrt((double)n) * 2.0;
+  auto above = [&](double v, double d1, double d2) {
+    return fabs(v) > abs_tiny && fabs(v) > rel_tol * sqrt(fabs(d1) * fabs(d2));
+  };
+  int sweep = 0;
+  for (; sweep < kJacobiMaxSweeps; ++sweep) {
+    if (threadIdx.x == 0) big = 0;
+    lds_barrier();
+    int mine = 0;
+#pragma unroll
+    for (int u = 0; u < kJacobiBlocksPerThread; ++u)
+      if (blk[u] >= 0) {
+        const int k1 = kk[u] & 0xffff, k2 = kk[u] >> 16;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          mine |= above(a[e * nto + blk[u]], dg[(e >> 1) * 2 * np + k1], dg[(e & 1) * 2 * np + k2]);
+      }
+    if (threadIdx.x < np) {
+      const int k = threadIdx.x;
+      mine |= (n2 - 1 - k < n) && above(dg[np + k], dg[k], dg[2 * np + k]);
+    }
+    if (mine) big = 1;
+    lds_barrier();
+    if (!big) break;
+    for (int round = 0; round < n2 - 1; ++round) {
+      // (1) rotations from the diagonal blocks (index convention p < q for the thresholds and the log)
+      double daa = 0.0, dab = 0.0, dbb = 0.0;
+      if (threadIdx.x < np) {
+        const int k = threadIdx.x;
+        const int pa = rr_player(k, round, n2), pb = rr_player(n2 - 1 - k, round, n2);
+        daa = dg[k];
+        dab = dg[np + k];
+        dbb = dg[2 * np + k];
+        const bool low = pa < pb;   // the low position holds p
+        const double app = low ? daa : dbb, aqq = low ? dbb : daa, apq = dab;
+        double c = 1.0, s = 0.0;
+        if ((low ? pb : pa) < n && above(apq, app, aqq)) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          const double np_ = app - t * apq, nq_ = aqq + t * apq;
+          daa = low ? np_ : nq_;
+          dbb = low ? nq_ : np_;
+          dab = 0.0;
+        }
+        cs[k] = make_double2(c, low ? s : -s);   // with p and q exchanged the rotation's sine flips
+        if (log) {
+          double* L = log + ((size_t)(sweep * (n2 - 1) + round) * np + k) * 2;
+          L[0] = c;
+          L[1] = s;
+        }
+      }
+      lds_barrier();
+      // (2) J1^T B J2 for this thread's blocks; right-hand sides.  The empty asm statements mark the
+      // array stride and the packed destinations as changing every round, so that the compiler does
+      // not keep twenty precomputed addresses live across the loop (which would spill registers).
+      int nto_r = nto;
+      asm volatile("" : "+s"(nto_r));
+      double v[kJacobiBlocksPerThread][4];
+#pragma unroll
+      for (int u = 0; u < kJacobiBlocksPerThread; ++u)
+        if (blk[u] >= 0) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[u][e] = a[e * nto_r + blk[u]];
+          const double2 r1 = cs[kk[u] & 0xffff], r2 = cs[kk[u] >> 16];
+          if (!(r1.y == 0.0 && r2.y == 0.0)) {
+            const double c1 = r1.x, s1 = r1.y, c2 = r2.x, s2 = r2.y;
+            const double r00 = c1 * v[u][0] - s1 * v[u][2], r01 = c1 * v[u][1] - s1 * v[u][3];
+            const double r10 = s1 * v[u][0] + c1 * v[u][2], r11 = s1 * v[u][1] + c1 * v[u][3];
+            v[u][0] = c2 * r00 - s2 * r01;
+            v[u][1] = s2 * r00 + c2 * r01;
+            v[u][2] = c2 * r10 - s2 * r11;
+            v[u][3] = s2 * r10 + c2 * r11;
+          }
+        }
+      if (R) {
+        for (int t = threadIdx.x; t < np * nrhs; t += kJacobiThreads) {
+          const int k = t % np, r = t / np;
+          const double2 rot = cs[k];
+          if (rot.y == 0.0) continue;
+          const int x = rr_player(k, round, n2), y = rr_player(n2 - 1 - k, round, n2);
+          const double vx = rhs[x + r * n2], vy = rhs[y + r * n2];
+          rhs[x + r * n2] = rot.x * vx - rot.y * vy;
+          rhs[y + r * n2] = rot.y * vx + rot.x * vy;
+        }
+      }
+      lds_barrier();
+      // (3) move every entry to its next-round position
+#pragma unroll
+      for (int u = 0; u < kJacobiBlocksPerThread; ++u)
+        if (blk[u] >= 0) {
+          asm volatile("" : "+v"(dst[u][0]), "+v"(dst[u][1]));
+#pragma unroll
+          for (int e = 0; e < 4; ++e) a[(dst[u][e >> 1] >> (16 * (e & 1))) & 0xffff] = v[u][e];
+        }
+      if (threadIdx.x < np) {
+        a[ddst[0] & 0xffff] = daa;
+        a[ddst[0] >> 16] = dab;
+        a[ddst[1]] = dbb;
+      }
+      lds_barrier();
+    }
+  }
+  // eigenvalues ascending (stable by index); perm[i] = sorted position of index i
+  double* wout = ws + (int64_t)blockIdx.x * n;
+  for (int i = threadIdx.x; i < n; i += kJacobiThreads) {
+    const double wi = a[P.at(i, i)];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double wj = a[P.at(j, j)];
+      rank += (wj < wi) || (wj == wi && j < i);
+    }
+    wout[rank] = wi;
+    perm[i] = (double)rank;
+  }
+  if (threadIdx.x == 0) perm[n] = (double)sweep;
   __syncthreads();
   if (R)
     for (int64_t t = threadIdx.x; t < (int64_t)n * nrhs; t += kJacobiThreads) {
-      int i = (int)(t % n), r = (int)(t / n);
+      const int i = (int)(t % n), r = (int)(t / n);
       R[(int)perm[i] + (int64_t)r * n] = rhs[i + (int64_t)r * n2];
     }
 }
