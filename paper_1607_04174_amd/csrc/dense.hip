@@ -117,7 +117,7 @@ __host__ __device__ size_t syev_log_count(int n) {
   return (size_t)kJacobiMaxSweeps * (n2 - 1) * (n2 / 2) * 2;
 }
 
-// per-matrix work: [glb copy n2*n2][log][perm n][sweeps 8][rhs n2*nrhs (global variant)]
+// per-matrix work: [glb copy n2*n2][log: (c, s) per round and pair][perm n][sweeps 8][rhs n2*nrhs (global variant)]
 static size_t syev_stride(int n, bool vectors, bool glb, int nrhs) {
   int n2 = n + (n & 1);
   size_t s = glb ? (size_t)n2 * n2 : 0;
@@ -171,7 +171,8 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
     for (int round = 0; round < n2 - 1; ++round) {
       for (int k = threadIdx.x; k < np; k += kJacobiThreads) {
         int p = rr_player(k, round, n2), q = rr_player(n2 - 1 - k, round, n2);
-        if (p > q) { int t = p; p = q; q = t; }
+        const bool swapped = p > q;
+        if (swapped) { int t = p; p = q; q = t; }
         double c = 1.0, s = 0.0;
         if (q < n) {
           double apq = S.ld(p, q), app = S.ld(p, p), aqq = S.ld(q, q);
@@ -190,10 +191,10 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
         sn[k] = s;
         pq[2 * k] = p;
         pq[2 * k + 1] = q;
-        if (log) {
+        if (log) {   // sine of the rotation of (low position, high position)
           double* L = log + ((size_t)(sweep * (n2 - 1) + round) * np + k) * 2;
           L[0] = c;
-          L[1] = s;
+          L[1] = swapped ? -s : s;
         }
       }
       Store::sync();
@@ -274,8 +275,8 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
 // phases separated by workgroup barriers: (1) thread k computes pair k's rotation from its diagonal
 // block, (2) every thread rotates its off-diagonal blocks (a fixed set, held in registers) and the
 // right-hand sides, (3) every entry is written to its next-round position.  Lanes of a wave touch
-// consecutive blocks, so the LDS accesses are free of bank conflicts.  The rotation rule,
-// thresholds and log are those of the global-memory variant (index convention p < q); a sweep runs
+// consecutive blocks, so the LDS accesses are free of bank conflicts.  The rotation rule, thresholds
+// and log (c and the sine for the (low, high) position order) are those of the global-memory variant; a sweep runs
 // only while some off-diagonal entry is above the thresholds, which is the same test as a sweep
 // without rotations, evaluated on the matrix at the sweep boundary.
 __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(const double* As, int n, double* ws, double* Rs, int nrhs,
@@ -392,12 +393,9 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(const double* As,
           dbb = low ? nq_ : np_;
           dab = 0.0;
         }
-        cs[k] = make_double2(c, low ? s : -s);   // with p and q exchanged the rotation's sine flips
-        if (log) {
-          double* L = log + ((size_t)(sweep * (n2 - 1) + round) * np + k) * 2;
-          L[0] = c;
-          L[1] = s;
-        }
+        const double2 rot = make_double2(c, low ? s : -s);   // with p and q exchanged the sine flips
+        cs[k] = rot;
+        if (log) *reinterpret_cast<double2*>(log + ((size_t)(sweep * (n2 - 1) + round) * np + k) * 2) = rot;
       }
       lds_barrier();
       // (2) J1^T B J2 for this thread's blocks; right-hand sides.  The empty asm statements mark the
@@ -503,76 +501,104 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_glb(const double* As,
     }
 }
 
-// V from the logged rotations: V = J(1) J(2) ... applied to the identity.  Rows are independent: each
-// wave owns kReplayRows rows of V in LDS and applies every round to them with its lanes spread over the
-// round's disjoint pairs, so successive rounds need no workgroup barrier (a wave's LDS accesses are
-// ordered); the workgroup synchronizes only to stage up to kReplayStage rounds of rotations into LDS.  At the
-// end the columns are written in sorted order.
-constexpr int kReplayRows = 1;     // rows of V per wave
-constexpr int kReplayStage = 16;   // rounds of rotations staged in LDS per barrier pair
-
-__global__ __launch_bounds__(256) void k_jacobi_replay(int n, int rows_per_block, int nstage, const double* work,
-                                                       int64_t stride, int64_t log_off, double* Vs) {
-  extern __shared__ double vs[];
+// V from the logged rotations: V = J(1) J(2) ... applied to the identity.  Rows of V are independent
+// and are replayed in the position layout of jacobi_layout.h: lane l holds, for each of its PPL pairs
+// k = l PPL + j, the row's entries at the pair's low and high positions, so a rotation touches only the
+// lane's own registers, and the move to the next round's positions shifts low-slot entries down one pair
+// and high-slot entries up one pair (one cross-lane shuffle each).  One wave replays R rows; the logged
+// (c, s) of upcoming rounds are loaded D rounds ahead.  After whole sweeps position x holds index x, and
+// the columns are written in sorted order.
+template <int PPL, int R, int D>
+__global__ __launch_bounds__(64) void k_jacobi_replay(int n, const double* work, int64_t stride, int64_t log_off,
+                                                      double* Vs) {
   const int n2 = n + (n & 1), np = n2 / 2;
   const int b = blockIdx.y;
-  const int r0 = blockIdx.x * rows_per_block;
-  const int rows = min(rows_per_block, n - r0);
+  const int lane = threadIdx.x;
+  const int r0 = blockIdx.x * R;
   const double* wk = work + (int64_t)b * stride;
-  const double* log = wk + log_off;
-  const double* perm = log + syev_log_count(n);
-  const int sweeps = (int)perm[n];
-  const int ld = n2 + 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double* stage = vs + rows_per_block * ld;        // nstage x np x (c, s)
-  int* spq = reinterpret_cast<int*>(stage + nstage * np * 2);   // nstage x np x (p, q)
-  for (int t = threadIdx.x; t < rows_per_block * ld; t += 256) {
-    int r = t / ld, c = t - r * ld;
-    vs[t] = (r < rows && c == r0 + r) ? 1.0 : 0.0;
-  }
-  const int total_rounds = sweeps * (n2 - 1);
-  for (int g0 = 0; g0 < total_rounds; g0 += nstage) {
-    const int ng = min(nstage, total_rounds - g0);
-    lds_barrier();
-    for (int t = threadIdx.x; t < ng * np * 2; t += 256) stage[t] = log[(size_t)g0 * np * 2 + t];
-    for (int t = threadIdx.x; t < ng * np; t += 256) {
-      int gi = t / np, k = t - gi * np;
-      int round = (g0 + gi) % (n2 - 1);
-      int p = rr_player(k, round, n2), q = rr_player(n2 - 1 - k, round, n2);
-      spq[2 * t] = p < q ? p : q;
-      spq[2 * t + 1] = p < q ? q : p;
-    }
-    lds_barrier();
-    for (int gi = 0; gi < ng; ++gi) {
-      const double* L = stage + gi * np * 2;
-      const int* PQ = spq + gi * np * 2;
-      for (int k = lane; k < np; k += 64) {
-        const double s = L[2 * k + 1];
-        if (s == 0.0) continue;
-        const double c = L[2 * k];
-        const int p = PQ[2 * k], q = PQ[2 * k + 1];
+  const double2* log = reinterpret_cast<const double2*>(wk + log_off);
+  const double* perm = wk + log_off + syev_log_count(n);
+  const int total = (int)perm[n] * (n2 - 1);
+  double va[R][PPL], vb[R][PPL];
 #pragma unroll
-        for (int r = 0; r < kReplayRows; ++r) {
-          const int row = wave * kReplayRows + r;
-          if (row >= rows) break;
-          double* v = vs + row * ld;
-          const double vp = v[p], vq = v[q];
-          v[p] = c * vp - s * vq;
-          v[q] = s * vp + c * vq;
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      const int k = lane * PPL + j;
+      va[r][j] = (k < np && k == r0 + r) ? 1.0 : 0.0;
+      vb[r][j] = (k < np && n2 - 1 - k == r0 + r) ? 1.0 : 0.0;
+    }
+  auto fetch = [&](int g, double2 (&dst)[PPL]) {
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      const int k = lane * PPL + j;
+      dst[j] = (g < total && k < np) ? log[(size_t)g * np + k] : make_double2(1.0, 0.0);
+    }
+  };
+  double2 q[D][PPL];
+#pragma unroll
+  for (int d = 0; d < D; ++d) fetch(d, q[d]);
+  for (int g0 = 0; g0 < total; g0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int g = g0 + d;
+      if (g >= total) break;   // uniform across the wave
+      double2 rot[PPL];
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) rot[j] = q[d][j];
+      fetch(g + D, q[d]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          const double x = va[r][j], y = vb[r][j];
+          va[r][j] = rot[j].x * x - rot[j].y * y;
+          vb[r][j] = rot[j].y * x + rot[j].x * y;
+        }
+        if (np > 1) {
+          // low slot of pair k <- low slot of pair k+1; high slot of pair k <- high slot of pair k-1;
+          // pair 0 keeps its low entry and takes pair 1's; the last pair's low slot takes its high entry
+          const double from_next = __shfl_down(va[r][0], 1);
+          const double from_prev = __shfl_up(vb[r][PPL - 1], 1);
+          double na[PPL], nb[PPL];
+#pragma unroll
+          for (int j = 0; j < PPL; ++j) {
+            const int k = lane * PPL + j;
+            const double up = j + 1 < PPL ? va[r][j + 1] : from_next;
+            const double dn = j > 0 ? vb[r][j - 1] : from_prev;
+            na[j] = k == 0 ? va[r][j] : (k == np - 1 ? vb[r][j] : up);
+            nb[j] = k == 0 ? up : dn;
+          }
+#pragma unroll
+          for (int j = 0; j < PPL; ++j) {
+            va[r][j] = na[j];
+            vb[r][j] = nb[j];
+          }
         }
       }
-      // the next round may touch the same entries from other lanes of this wave
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
     }
   }
-  lds_barrier();
   double* V = Vs + (int64_t)b * n * n;
-  for (int t = threadIdx.x; t < rows * n; t += 256) {
-    int r = t % rows, col = t / rows;
-    V[(r0 + r) + (int64_t)((int)perm[col]) * n] = vs[r * ld + col];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int row = r0 + r;
+    if (row >= n) break;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      const int k = lane * PPL + j;
+      if (k >= np) continue;
+      if (k < n) V[row + (int64_t)((int)perm[k]) * n] = va[r][j];
+      const int x = n2 - 1 - k;
+      if (x < n) V[row + (int64_t)((int)perm[x]) * n] = vb[r][j];
+    }
   }
+}
+
+template <int PPL, int R, int D>
+static void launch_replay(int n, int count, const double* work, int64_t stride, int64_t log_off, double* V,
+                          hipStream_t s) {
+  dim3 grid((n + R - 1) / R, count);
+  k_jacobi_replay<PPL, R, D><<<grid, 64, 0, s>>>(n, work, stride, log_off, V);
 }
 
 int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int n, int count, double* work,
@@ -597,22 +623,12 @@ int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int
   }
   RW_LAUNCH_CHECK();
   if (vectors) {
-    int n2 = n + (n & 1);
-    const int rpb = 4 * kReplayRows;     // four waves per workgroup
-    const size_t row_bytes = (size_t)rpb * (n2 + 1) * sizeof(double);
-    const size_t round_bytes = (size_t)(n2 / 2) * 2 * (sizeof(double) + sizeof(int));
-    RW_CHECK(row_bytes + round_bytes <= kLdsLimit, RW_EINVAL, "replay tile exceeds LDS");
-    const int nstage = (int)std::min<size_t>(kReplayStage, (kLdsLimit - row_bytes) / round_bytes);
-    size_t sh = row_bytes + (size_t)nstage * round_bytes;
-    static bool attr2 = false;
-    if (!attr2) {
-      RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi_replay),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-      attr2 = true;
-    }
-    dim3 grid((n + rpb - 1) / rpb, count);
-    int64_t log_off = glb ? (int64_t)n2 * n2 : 0;
-    k_jacobi_replay<<<grid, 256, sh, s>>>(n, rpb, nstage, work, stride, log_off, V);
+    const int np = (n + (n & 1)) / 2;
+    const int64_t log_off = glb ? (int64_t)(n + (n & 1)) * (n + (n & 1)) : 0;
+    if (np <= 64) launch_replay<1, 2, 4>(n, count, work, stride, log_off, V, s);
+    else if (np <= 128) launch_replay<2, 2, 4>(n, count, work, stride, log_off, V, s);
+    else if (np <= 256) launch_replay<4, 1, 2>(n, count, work, stride, log_off, V, s);
+    else launch_replay<8, 1, 2>(n, count, work, stride, log_off, V, s);
     RW_LAUNCH_CHECK();
   }
   return RW_OK;
