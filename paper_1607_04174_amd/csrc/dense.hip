@@ -86,19 +86,9 @@ int chol_upper_inverse(const double* L, double* Rinv, int n, hipStream_t s) {
 constexpr int kJacobiThreads = 1024;
 constexpr int kJacobiMaxSweeps = 30;
 constexpr int kJacobiBlocksPerThread = 5;   // LDS variant: off-diagonal 2 x 2 blocks held per thread
-constexpr size_t kLdsLimit = 160 * 1024 - 64;   // dynamic LDS budget (the kernels' static LDS is 16 bytes)
 
 __device__ __forceinline__ int rr_player(int pos, int round, int n2) {
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n2 - 1);
-}
-
-// Workgroup barrier that orders only LDS traffic: it does not wait for outstanding global stores
-// (used where waves exchange data through LDS alone; global writes there are never read back
-// inside the kernel).
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 struct GlbStore {   // full n2 x n2 column-major copy in global memory

@@ -12,6 +12,18 @@
 
 namespace rw {
 
+// dynamic LDS budget of a workgroup (the kernels' static LDS stays below 64 bytes)
+constexpr size_t kLdsLimit = 160 * 1024 - 64;
+
+// Workgroup barrier that orders only LDS traffic: it does not wait for outstanding global stores
+// (used where waves exchange data through LDS alone; global writes there are never read back
+// inside the kernel).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---- error reporting ---------------------------------------------------------------------------
 void set_error(const char* fmt, ...);
 

@@ -41,9 +41,6 @@ struct SolveWork {
   double* Y;          // ma x C
   double* stat;       // 8
   double* partial;
-  double* scrL;       // ma x ma  (Cholesky factor of Q_s^T Q_s, screening)
-  double* scrRi;      // ma x ma  (its transposed inverse)
-  double* scrZ;       // ma x C
   double* scrF;       // (ma + 1): max over labels of the least-squares residual at m
   int* scrCls;        // (ma + 1): 0 fails, 1 passes, 2 undecided; [0] = factorized leading size
 };
@@ -75,9 +72,6 @@ static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base,
   t.stat = c.take<double>(8);
   size_t pc = std::max(gram_partial_count(S, ma, ma), gram_partial_count(S, ma, C));
   t.partial = c.take<double>(pc);
-  t.scrL = c.take<double>((size_t)ma * ma);
-  t.scrRi = c.take<double>((size_t)ma * ma);
-  t.scrZ = c.take<double>((size_t)ma * C);
   t.scrF = c.take<double>((size_t)ma + 1);
   t.scrCls = c.take<int>((size_t)ma + 1);
   if (w) *w = t;
@@ -364,82 +358,144 @@ __global__ __launch_bounds__(64) void k_fit_secular(const int* cand, int ncand, 
 // diagonal entry, where G's leading block is numerically singular, as for every m > S) is left to
 // the eigen-based evaluation.  The factorization stops at the first m whose residual is at most f_max
 // for every label; larger m stay undecided (the search never needs them unless that m is undecided).
-// One workgroup; the factors live in the workspace (global memory, L2-resident).
-__global__ __launch_bounds__(1024) void k_fit_screen(int ma, int C, int64_t S, const double* Gq, const double* Gb,
-                                                     const double* Us, double rho2, double f_max, double* L,
-                                                     double* Ri, double* Z, double* F, int* cls) {
+// One workgroup; everything lives in LDS, which bounds the factorized size to KM columns (m > KM stays
+// undecided).  The factorization is right-looking with unscaled columns (Schur complements
+// A(i,j) -= A(i,k) A(j,k) / A(k,k)), one barrier per column; the right-hand sides are updated alongside
+// (z_k = g_k / sqrt(A(k,k))), and the stopping test for k reads the residuals left by column k - 1.
+// Then Ri = L^{-T} column by column (one wave per column, back substitution in axpy form with the
+// solved entry broadcast from its lane), and per label the row prefix sums P.
+__device__ __forceinline__ int scr_lo(int i, int j, int KM) { return j * KM - ((j * (j - 1)) >> 1) + (i - j); }  // i >= j
+__device__ __forceinline__ int scr_up(int i, int j) { return ((j * (j + 1)) >> 1) + i; }                        // i <= j
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+constexpr int kScreenMaxKM = 192;   // three entries per lane in the inverse's back substitution
+
+static size_t screen_lds_bytes(int KM, int C) {
+  return ((size_t)KM * (KM + 1) + 2 * (size_t)KM * C + KM + 3 * (size_t)C) * sizeof(double);
+}
+
+static int screen_cols(int ma, int C) {
+  int KM = std::min(ma, kScreenMaxKM);
+  while (KM > 0 && screen_lds_bytes(KM, C) > kLdsLimit) --KM;
+  return KM;
+}
+
+__global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int64_t S, const double* Gq,
+                                                     const double* Gb, const double* Us, double rho2, double f_max,
+                                                     double* F, int* cls) {
+  extern __shared__ double sm[];
+  const int tri = KM * (KM + 1) / 2;
+  double* A = sm;              // packed lower (column-major): Schur complements, then L; later Ri (packed upper)
+  double* B = A + tri;         // packed upper: L^T, later the prefix sums P
+  double* G = B + tri;         // KM x C right-hand sides g = Q_s^T u, updated
+  double* Z = G + KM * C;      // KM x C, z = L^{-1} g
+  double* rd = Z + KM * C;     // 1 / L(k, k)
+  double* sr = rd + KM;        // 2 x C running residuals (alternating by column parity)
+  double* sbn = sr + 2 * C;    // ||b||^2 per label
   __shared__ int s_kf;
-  __shared__ double s_bn[64];   // C <= 64 (checked by the caller)
-  __shared__ double s_r[64];    // running residual ||b||^2 - sum_{j<k} z_j^2 per label
-  __shared__ double s_col[1024];
   const int tid = threadIdx.x;
-  if (tid == 0) s_kf = ma;
   if (tid < 64) {
     for (int c = 0; c < C; ++c) {
       double acc = 0.0;
       for (int64_t i = tid; i < S; i += 64) acc += Us[i + c * S] * Us[i + c * S];
       for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
       if (tid == 0) {
-        s_bn[c] = acc;
-        s_r[c] = acc;
+        sbn[c] = acc;
+        sr[c] = acc;
       }
     }
   }
+  for (int t = tid; t < KM * KM; t += blockDim.x) {
+    const int i = t % KM, j = t / KM;
+    if (i >= j) A[scr_lo(i, j, KM)] = Gq[i + (int64_t)j * ma];
+  }
+  for (int t = tid; t < KM * C; t += blockDim.x) G[t] = Gb[t % KM + (int64_t)(t / KM) * ma];
+  if (tid == 0) s_kf = KM;
   __syncthreads();
-  // Left-looking Cholesky, one column per step, with z = L^{-1} g carried along: column k needs only the
-  // columns before it, so the factorization stops at the first small pivot (numerically singular
-  // leading block) or as soon as every label's running residual r(k+1) is at most f_max (no larger m
-  // is needed: the first m that can pass is at most k+1).
-  for (int k = 0; k < ma; ++k) {
-    for (int i = k + tid; i < ma; i += blockDim.x) {
-      double acc = Gq[i + (int64_t)k * ma];
-      for (int j = 0; j < k; ++j) acc -= L[i + (int64_t)j * ma] * L[k + (int64_t)j * ma];
-      s_col[i] = acc;
+  // Cholesky with early stop: at the first small pivot (numerically singular leading block) or as soon as
+  // every label's residual r(k) is at most f_max (no larger m is needed: the first m that can pass is at
+  // most k)
+  const int tx = tid & 31, ty = tid >> 5;
+  for (int k = 0; k < KM; ++k) {
+    const double* srk = sr + (k & 1) * C;
+    if (k > 0) {
+      double worst = 0.0;
+      for (int c = 0; c < C; ++c) worst = fmax(worst, srk[c]);
+      if (worst <= f_max) {   // uniform
+        if (tid == 0) s_kf = k;
+        break;
+      }
     }
-    __syncthreads();
-    const double dkk = s_col[k];
-    if (!(dkk > 1e-12 * Gq[k + (int64_t)k * ma]) || !isfinite(dkk)) {   // uniform: every thread reads s_col[k]
+    const double dkk = A[scr_lo(k, k, KM)];
+    if (!(dkk > 1e-12 * Gq[k + (int64_t)k * ma]) || !isfinite(dkk)) {   // uniform
       if (tid == 0) s_kf = k;
       break;
     }
     const double lkk = sqrt(dkk);
-    for (int i = k + tid; i < ma; i += blockDim.x) L[i + (int64_t)k * ma] = i == k ? lkk : s_col[i] / lkk;
     if (tid < C) {
-      double acc = Gb[k + (int64_t)tid * ma];
-      for (int j = 0; j < k; ++j) acc -= L[k + (int64_t)j * ma] * Z[j + (int64_t)tid * ma];
-      const double z = acc / lkk;
-      Z[k + (int64_t)tid * ma] = z;
-      s_r[tid] -= z * z;
+      const double z = G[k + tid * KM] / lkk;
+      Z[k + tid * KM] = z;
+      sr[((k + 1) & 1) * C + tid] = srk[tid] - z * z;
     }
-    __syncthreads();
-    double worst = 0.0;
-    for (int c = 0; c < C; ++c) worst = fmax(worst, s_r[c]);
-    if (worst <= f_max) {          // uniform
-      if (tid == 0) s_kf = k + 1;
-      break;
+    if (tid == 0) rd[k] = 1.0 / lkk;
+    const double inv = 1.0 / dkk;
+    for (int j = k + 1 + ty; j < KM; j += 32) {
+      const double ajk = A[scr_lo(j, k, KM)] * inv;
+      for (int i = j + tx; i < KM; i += 32) A[scr_lo(i, j, KM)] -= A[scr_lo(i, k, KM)] * ajk;
     }
+    const int rows = KM - k - 1;
+    for (int t = tid; t < rows * C; t += blockDim.x) {
+      const int i = k + 1 + t % rows, c = t / rows;
+      G[i + c * KM] -= A[scr_lo(i, k, KM)] * (G[k + c * KM] * inv);
+    }
+    lds_barrier();
   }
   __syncthreads();
   const int kf = s_kf;      // leading blocks of size <= kf are factorized
-  // Ri = L^{-T} (upper triangular) on the leading kf block: one wave per column
+  // L^T (packed upper) from the scaled columns
+  for (int t = tid; t < kf * kf; t += blockDim.x) {
+    const int i = t % kf, j = t / kf;
+    if (i > j) B[scr_up(j, i)] = A[scr_lo(i, j, KM)] * rd[j];
+  }
+  __syncthreads();
+  // Ri = L^{-T} (packed upper, over A): column j solves L^T x = e_j; columns are spread over the waves
+  // in a zigzag so that long and short columns pair up
   const int wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
-  for (int j = wave; j < kf; j += nw) {
-    double* x = Ri + (int64_t)j * ma;
-    const double xj = 1.0 / L[j + (int64_t)j * ma];
-    if (lane == 0) x[j] = xj;
-    for (int i = j - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int k = i + 1 + lane; k <= j; k += 64) acc += L[k + (int64_t)i * ma] * (k == j ? xj : x[k]);
-      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-      x[i] = -acc / L[i + (int64_t)i * ma];     // every lane stores the same value
+  for (int g0 = 0; g0 < kf; g0 += nw) {
+    const int grp = g0 / nw;
+    const int j = (grp & 1) ? g0 + nw - 1 - wave : g0 + wave;
+    if (j >= kf) continue;
+    double bv[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) bv[r] = (lane + 64 * r == j) ? 1.0 : 0.0;
+    double xv[3] = {0.0, 0.0, 0.0};
+    for (int k = j; k >= 0; --k) {
+      const int rk = k >> 6;
+      const double bk = rk == 0 ? bv[0] : (rk == 1 ? bv[1] : bv[2]);
+      const double xk = readlane_d(bk, k & 63) * rd[k];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int i = lane + 64 * r;
+        if (i == k) xv[r] = xk;
+        if (i < k) bv[r] -= B[scr_up(i, k)] * xk;   // L(k, i) = L^T(i, k)
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int i = lane + 64 * r;
+      if (i <= j) A[scr_up(i, j)] = xv[r];
     }
   }
   __syncthreads();
   // per m in [1, ma]: residual r(m) = ||b||^2 - sum_{j<m} z_j^2 and the fit's squared norm
   // ||a(m)||^2 = sum_{i<m} P(i, m-1)^2 with the row prefix sums P(i, j) = sum_{i<=j'<=j} Ri(i, j') z_j'
-  // (L is no longer needed: P overwrites it, one label at a time)
   double bmax = 0.0;
-  for (int c = 0; c < C; ++c) bmax = fmax(bmax, s_bn[c]);
+  for (int c = 0; c < C; ++c) bmax = fmax(bmax, sbn[c]);
   const double band0 = 1e-10 * (f_max + bmax);
   // per-thread state for m = 1 + tid (ma <= 1024)
   const int m = 1 + tid;
@@ -451,13 +507,13 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int C, int64_t S, c
   double rmax = 0.0;
   bool anyfail = false, allpass = true;
   for (int c = 0; c < C; ++c) {
-    const double* z = Z + (int64_t)c * ma;
-    __syncthreads();
-    for (int i = tid; i < kf; i += blockDim.x) {
+    const double* z = Z + c * KM;
+    if (tid < kf) {
+      const int i = tid;
       double acc = 0.0;
       for (int j = i; j < kf; ++j) {
-        acc += Ri[i + (int64_t)j * ma] * z[j];
-        L[i + (int64_t)j * ma] = acc;
+        acc += A[scr_up(i, j)] * z[j];
+        B[scr_up(i, j)] = acc;
       }
     }
     __syncthreads();
@@ -465,15 +521,16 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int C, int64_t S, c
       double zz = 0.0, an = 0.0;
       for (int j = 0; j < m; ++j) zz += z[j] * z[j];
       for (int i = 0; i < m; ++i) {
-        const double v = L[i + (int64_t)(m - 1) * ma];
+        const double v = B[scr_up(i, m - 1)];
         an += v * v;
       }
-      const double r = fmax(s_bn[c] - zz, 0.0);
+      const double r = fmax(sbn[c] - zz, 0.0);
       rmax = fmax(rmax, r);
       const double band = band0 + ebound * an;
       if (r > f_max + band) anyfail = true;
       if (!(r < f_max - band) || !(an <= 0.99 * rho2)) allpass = false;
     }
+    __syncthreads();
   }
   if (m <= ma) {
     int cl = 2;
@@ -596,10 +653,17 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
     // search: lo = largest m known to fail (1 = none), hi = smallest m known to pass (ma + 1 = none)
     int lo = 1, hi = ma + 1;
     std::vector<std::pair<int, double>> evaluated;
-    const bool screened = C <= 64 && ma <= 1024;
+    const int KM = (C <= 64 && ma <= 1024) ? screen_cols(ma, C) : 0;   // one thread per m in the classification
+    const bool screened = KM >= 1;
     if (screened) {
-      k_fit_screen<<<1, 1024, 0, stream>>>(ma, C, S, w.Gq, w.Gb, w.Us, rho * rho, f_max, w.scrL, w.scrRi, w.scrZ,
-                                           w.scrF, w.scrCls);
+      static bool attr = false;
+      if (!attr) {
+        RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_fit_screen),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+        attr = true;
+      }
+      k_fit_screen<<<1, 1024, screen_lds_bytes(KM, C), stream>>>(ma, KM, C, S, w.Gq, w.Gb, w.Us, rho * rho, f_max,
+                                                                  w.scrF, w.scrCls);
       RW_LAUNCH_CHECK();
       std::vector<int> cls(ma + 1);
       std::vector<double> fr(ma + 1);
