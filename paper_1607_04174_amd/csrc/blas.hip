@@ -76,80 +76,100 @@ __global__ __launch_bounds__(256) void k_gram(const T* X, int64_t ldx, const T* 
     }
 }
 
-// Large Gram tiles: 128 x 128 outputs per 256-thread block, 8 x 8 per thread (rows tx + 16 a, columns
-// ty + 16 b), 32-row slabs of X and Y staged in LDS as FP64: each LDS value feeds 8 FMAs.  With `sym`
-// (X^T Y known to be symmetric, e.g. X = Y) only tiles on or above the diagonal are computed and the
-// off-diagonal ones are written to both places.
-constexpr int kGB = 128;
-constexpr int kGBK = 32;
+// Large Gram products on the FP64 matrix cores (v_mfma_f64_16x16x4f64: A(i,k) from lane i + 16k,
+// B(k,j) from lane j + 16k, D(4v + l/16, l%16) in register v of lane l).  One wave computes a 32 x 32 tile
+// of X^T Y over a chunk of rows.  The contraction order inside a 32-row step is free, so lane l takes
+// rows r0 + 8 (l/16) + s for MFMA step s: each lane reads 8 consecutive rows of its column, and the four
+// 16-lane groups together read 32 consecutive rows (whole cache lines).  Inputs are widened to FP64 in
+// registers (FP32 x FP32 products are exact in FP64).  With `sym` (X^T Y known to be symmetric) only
+// tiles on or above the diagonal are computed and off-diagonal ones are written to both places; a
+// diagonal tile of X^T X loads its operand once.
+typedef double gram_d4 __attribute__((ext_vector_type(4)));
+constexpr int kGM = 32;        // tile edge
+constexpr int kGMRows = 32;    // rows per step (8 MFMA steps)
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram_big(const T* X, int64_t ldx, const T* Y, int64_t ldy, int64_t rows,
-                                                  int bx, int by, int64_t chunk_rows, double* out, int64_t out_stride,
-                                                  int sym) {
-  if (sym && blockIdx.x > blockIdx.y) return;
-  __shared__ double sX[kGBK][kGB + 1];
-  __shared__ double sY[kGBK][kGB + 1];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int i0 = blockIdx.x * kGB, j0 = blockIdx.y * kGB;
-  const int64_t r_begin = blockIdx.z * chunk_rows;
+__device__ __forceinline__ void gram_load8(const T* col, int64_t r, int64_t r_end, bool ok, T (&v)[8]) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) v[s] = (ok && r + s < r_end) ? col[r + s] : T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_gram_mfma(const T* X, int64_t ldx, const T* Y, int64_t ldy, int64_t rows,
+                                                  int bx, int by, int64_t chunk_rows, int tiles_x, int sym,
+                                                  double* out, int64_t out_stride) {
+  int ti, tj;
+  const int t = blockIdx.x;
+  if (sym) {   // upper triangle of tiles, column by column
+    tj = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((tj + 1) * (tj + 2) / 2 <= t) ++tj;
+    while (tj * (tj + 1) / 2 > t) --tj;
+    ti = t - tj * (tj + 1) / 2;
+  } else {
+    ti = t % tiles_x;
+    tj = t / tiles_x;
+  }
+  const int i0 = ti * kGM, j0 = tj * kGM;
+  const int lane = threadIdx.x, c16 = lane & 15, kq = lane >> 4;
+  const int64_t r_begin = (int64_t)blockIdx.y * chunk_rows;
   const int64_t r_end = std::min<int64_t>(rows, r_begin + chunk_rows);
-  double acc[8][8];
+  const bool same = ti == tj && X == Y && ldx == ldy && i0 == j0;   // B operand equals A operand
+  const int ca0 = i0 + c16, ca1 = i0 + 16 + c16, cb0 = j0 + c16, cb1 = j0 + 16 + c16;
+  const bool oa0 = ca0 < bx, oa1 = ca1 < bx, ob0 = cb0 < by, ob1 = cb1 < by;
+  const T* pa0 = X + (int64_t)(oa0 ? ca0 : 0) * ldx;
+  const T* pa1 = X + (int64_t)(oa1 ? ca1 : 0) * ldx;
+  const T* pb0 = Y + (int64_t)(ob0 ? cb0 : 0) * ldy;
+  const T* pb1 = Y + (int64_t)(ob1 ? cb1 : 0) * ldy;
+  gram_d4 acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) acc[a][b] = 0.0;
-  const int lr = threadIdx.x & 31;      // row within the slab
-  const int lc = threadIdx.x >> 5;      // 0..7: column group
-  // the next slab's values are loaded into registers while the current one is multiplied
-  T px[16], py[16];
+    for (int b = 0; b < 2; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
+  T a0[8], a1[8], b0[8], b1[8];   // raw values of the next step (widened when used)
   auto fetch = [&](int64_t r0) {
-    const int64_t row = r0 + lr;
-    const bool rin = row < r_end;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = lc + 8 * q;
-      const int ci = i0 + col, cj = j0 + col;
-      px[q] = (rin && ci < bx) ? X[(int64_t)ci * ldx + row] : T(0);
-      py[q] = (rin && cj < by) ? Y[(int64_t)cj * ldy + row] : T(0);
+    const int64_t r = r0 + 8 * kq;
+    gram_load8(pa0, r, r_end, oa0, a0);
+    gram_load8(pa1, r, r_end, oa1, a1);
+    if (!same) {
+      gram_load8(pb0, r, r_end, ob0, b0);
+      gram_load8(pb1, r, r_end, ob1, b1);
     }
   };
   if (r_begin < r_end) fetch(r_begin);
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGBK) {
-    __syncthreads();
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGMRows) {
+    T ca[2][8], cb[2][8];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = lc + 8 * q;
-      sX[lr][col] = (double)Elem<T>::ld(px, q);
-      sY[lr][col] = (double)Elem<T>::ld(py, q);
+    for (int s = 0; s < 8; ++s) {
+      ca[0][s] = a0[s];
+      ca[1][s] = a1[s];
+      cb[0][s] = same ? a0[s] : b0[s];
+      cb[1][s] = same ? a1[s] : b1[s];
     }
-    __syncthreads();
-    if (r0 + kGBK < r_end) fetch(r0 + kGBK);
-#pragma unroll 2
-    for (int k = 0; k < kGBK; ++k) {
-      double xv[8], yv[8];
+    if (r0 + kGMRows < r_end) fetch(r0 + kGMRows);
 #pragma unroll
-      for (int a = 0; a < 8; ++a) xv[a] = sX[k][tx + 16 * a];
+    for (int s = 0; s < 8; ++s) {
+      const double xa[2] = {(double)Elem<T>::ld(ca[0], s), (double)Elem<T>::ld(ca[1], s)};
+      const double xb[2] = {(double)Elem<T>::ld(cb[0], s), (double)Elem<T>::ld(cb[1], s)};
 #pragma unroll
-      for (int b = 0; b < 8; ++b) yv[b] = sY[k][ty + 16 * b];
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int a = 0; a < 8; ++a)
-#pragma unroll
-        for (int b = 0; b < 8; ++b) acc[a][b] = fma(xv[a], yv[b], acc[a][b]);
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], xb[b], acc[a][b], 0, 0, 0);
     }
   }
-  double* o = out + blockIdx.z * out_stride;
-  const bool mirror = sym && blockIdx.x < blockIdx.y;
+  double* o = out + (int64_t)blockIdx.y * out_stride;
+  const bool mirror = sym && ti != tj;
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int i = i0 + tx + 16 * a, j = j0 + ty + 16 * b;
-      if (i < bx && j < by) {
-        o[(int64_t)j * bx + i] = acc[a][b];
-        if (mirror) o[(int64_t)i * bx + j] = acc[a][b];
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 16 * a + 4 * v + kq, j = j0 + 16 * b + c16;
+        if (i < bx && j < by) {
+          o[(int64_t)j * bx + i] = acc[a][b][v];
+          if (mirror) o[(int64_t)i * bx + j] = acc[a][b][v];
+        }
       }
-    }
 }
 
 __global__ void k_sum_chunks(const double* partial, int64_t count, int64_t nchunks, double* G) {
@@ -160,11 +180,17 @@ __global__ void k_sum_chunks(const double* partial, int64_t count, int64_t nchun
   G[k] = s;
 }
 
+static int gram_mfma_tiles(int bx, int by, bool sym) {
+  const int tx = (bx + kGM - 1) / kGM, ty = (by + kGM - 1) / kGM;
+  return sym ? tx * (tx + 1) / 2 : tx * ty;
+}
+
 static int64_t gram_big_chunks(int64_t rows, int bx, int by) {
-  // about 512 blocks, at least 2048 rows per chunk
-  int64_t tiles = (int64_t)((bx + kGB - 1) / kGB) * ((by + kGB - 1) / kGB);
-  int64_t want = std::max<int64_t>(1, 512 / std::max<int64_t>(1, tiles));
-  int64_t by_rows = std::max<int64_t>(1, rows / 2048);
+  // about 3072 waves (several per SIMD), at least 256 rows per chunk; sized for the non-symmetric tile
+  // count so that the partial buffer fits either case
+  const int64_t tiles = gram_mfma_tiles(bx, by, false);
+  const int64_t want = std::max<int64_t>(1, 3072 / std::max<int64_t>(1, tiles));
+  const int64_t by_rows = std::max<int64_t>(1, rows / 256);
   return std::max<int64_t>(1, std::min<int64_t>(want, by_rows));
 }
 
@@ -179,24 +205,26 @@ int gram(int dt, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t
          double* G, double* partial, hipStream_t s, bool sym) {
   if (bx <= 0 || by <= 0) return RW_OK;
   const bool big = gram_is_big(bx, by);
-  const int tile = big ? kGB : kGT, slab = big ? kGBK : kGK;
+  const int slab = big ? kGMRows : kGK;
   int64_t nch = big ? gram_big_chunks(rows, bx, by) : gram_chunks(rows, bx, by);
   int64_t chunk_rows = (rows + nch - 1) / nch;
   chunk_rows = (chunk_rows + slab - 1) / slab * slab;
   if (chunk_rows == 0) chunk_rows = slab;
   nch = std::max<int64_t>(1, (rows + chunk_rows - 1) / chunk_rows);
-  dim3 grid((bx + tile - 1) / tile, (by + tile - 1) / tile, (unsigned)nch);
   int64_t count = (int64_t)bx * by;
   double* dst = nch == 1 ? G : partial;
   const int sy = (sym && bx == by) ? 1 : 0;
   if (big) {
+    const int tiles_x = (bx + kGM - 1) / kGM;
+    dim3 grid((unsigned)gram_mfma_tiles(bx, by, sy != 0), (unsigned)nch);
     if (dt == RW_F64)
-      k_gram_big<double><<<grid, 256, 0, s>>>((const double*)X, ldx, (const double*)Y, ldy, rows, bx, by, chunk_rows, dst, count, sy);
+      k_gram_mfma<double><<<grid, 64, 0, s>>>((const double*)X, ldx, (const double*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, dst, count);
     else if (dt == RW_F32)
-      k_gram_big<float><<<grid, 256, 0, s>>>((const float*)X, ldx, (const float*)Y, ldy, rows, bx, by, chunk_rows, dst, count, sy);
+      k_gram_mfma<float><<<grid, 64, 0, s>>>((const float*)X, ldx, (const float*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, dst, count);
     else
-      k_gram_big<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)X, ldx, (const uint16_t*)Y, ldy, rows, bx, by, chunk_rows, dst, count, sy);
+      k_gram_mfma<uint16_t><<<grid, 64, 0, s>>>((const uint16_t*)X, ldx, (const uint16_t*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, dst, count);
   } else {
+    dim3 grid((bx + kGT - 1) / kGT, (by + kGT - 1) / kGT, (unsigned)nch);
     if (dt == RW_F64)
       k_gram<double><<<grid, 256, 0, s>>>((const double*)X, ldx, (const double*)Y, ldy, rows, bx, by, chunk_rows, dst, count);
     else if (dt == RW_F32)
