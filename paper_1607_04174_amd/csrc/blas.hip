@@ -305,9 +305,136 @@ __global__ __launch_bounds__(256) void k_gemm(const T* X, int64_t ldx, const dou
     }
 }
 
+// Z = X V (+ beta Z) for FP32 and BF16 X on the FP32 matrix cores (v_mfma_f32_16x16x4f32: A(i,k) from
+// lane i + 16k, B(k,j) from lane j + 16k, D(4 (l/16) + v, l%16) in register v of lane l), computed as
+// Z^T = V^T X^T so that a store writes 16 consecutive rows of a column per 16-lane group.  A workgroup
+// keeps an FP32 copy of a slab of V's columns (all k rows) in LDS and its eight waves walk 32-row tasks;
+// a wave accumulates all of the slab's 16-column blocks for its two 16-row blocks, with X fragments
+// loaded two steps ahead.  Same arithmetic as the vector kernel (V rounded to FP32, FP32 accumulation).
+typedef float gemm_f4 __attribute__((ext_vector_type(4)));
+constexpr int kGemmWaves = 8;
+constexpr int kGemmAhead = 2;
+
+template <typename T, int NCB>
+__global__ __launch_bounds__(64 * kGemmWaves) void k_gemm_mfma(const T* X, int64_t ldx, const double* V, int64_t ldv,
+                                                               T* Z, int64_t ldz, int64_t rows, int k, int n,
+                                                               double beta, int slab_w, int ld) {
+  extern __shared__ float sV[];   // [kpad][ld]: V(kk, c0 + c) rounded to FP32, zero beyond k
+  const int c0 = blockIdx.y * slab_w;
+  const int w = std::min(slab_w, n - c0);
+  const int nks = (k + 3) / 4;
+  for (int t = threadIdx.x; t < 4 * nks * w; t += blockDim.x) {
+    const int kk = t % (4 * nks), c = t / (4 * nks);
+    sV[kk * ld + c] = kk < k ? (float)V[(int64_t)(c0 + c) * ldv + kk] : 0.f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c16 = lane & 15, g = lane >> 4;
+  const int64_t tasks = (rows + 31) / 32;
+  for (int64_t task = (int64_t)blockIdx.x * kGemmWaves + wave; task < tasks; task += (int64_t)gridDim.x * kGemmWaves) {
+    const int64_t r0 = task * 32;
+    const int64_t ra = r0 + c16, rb = r0 + 16 + c16;
+    const bool oa = ra < rows, ob = rb < rows;
+    gemm_f4 acc[2][NCB];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[b][cb] = gemm_f4{0.f, 0.f, 0.f, 0.f};
+    float xa[kGemmAhead], xb[kGemmAhead];
+    auto fetch = [&](int s, float& va, float& vb) {
+      const int kk = 4 * s + g;
+      const bool ok = kk < k;
+      va = (ok && oa) ? (float)Elem<T>::ld(X, (int64_t)kk * ldx + ra) : 0.f;
+      vb = (ok && ob) ? (float)Elem<T>::ld(X, (int64_t)kk * ldx + rb) : 0.f;
+    };
+#pragma unroll
+    for (int d = 0; d < kGemmAhead; ++d) fetch(d, xa[d], xb[d]);
+    for (int s0 = 0; s0 < nks; s0 += kGemmAhead) {
+#pragma unroll
+      for (int d = 0; d < kGemmAhead; ++d) {
+        const int s = s0 + d;
+        if (s >= nks) break;
+        const float fa = xa[d], fb = xb[d];
+        fetch(s + kGemmAhead, xa[d], xb[d]);
+        const float* vrow = sV + (4 * s + g) * ld + c16;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const float av = 16 * cb + c16 < w ? vrow[16 * cb] : 0.f;
+          acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, fa, acc[0][cb], 0, 0, 0);
+          acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, fb, acc[1][cb], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int64_t row = b ? rb : ra;
+      if (!(b ? ob : oa)) continue;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = 16 * cb + 4 * g + v;
+          if (col >= w) continue;
+          const int64_t idx = (int64_t)(c0 + col) * ldz + row;
+          float out = acc[b][cb][v];
+          if (beta != 0.0) out += (float)beta * (float)Elem<T>::ld(Z, idx);
+          Elem<T>::st(Z, idx, out);
+        }
+    }
+  }
+}
+
+// widest slab of V's columns whose FP32 copy fits in LDS (all columns when they fit, else a multiple of
+// 16); 0 when not even 16 columns fit
+static int gemm_slab_width(int k, int n) {
+  const size_t kpad = (size_t)(k + 3) / 4 * 4;
+  const size_t cap = kLdsLimit / (kpad * sizeof(float));
+  if ((size_t)n <= cap && n <= 208) return n;
+  const int w = (int)std::min<size_t>(cap, 208) / 16 * 16;
+  return w;
+}
+
+template <typename T, int NCB>
+static void launch_gemm_mfma(const T* X, int64_t ldx, const double* V, int64_t ldv, T* Z, int64_t ldz, int64_t rows,
+                             int k, int n, double beta, int slab_w, hipStream_t s) {
+  const int ld = slab_w;
+  const int nslab = (n + slab_w - 1) / slab_w;
+  const size_t sh = (size_t)(k + 3) / 4 * 4 * ld * sizeof(float);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gemm_mfma<T, NCB>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+    attr = true;
+  }
+  const int64_t tasks = (rows + 31) / 32;
+  const int64_t per = std::max<int64_t>(1, 256 / nslab);
+  const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(per, (tasks + kGemmWaves - 1) / kGemmWaves));
+  k_gemm_mfma<T, NCB><<<dim3(gx, nslab), 64 * kGemmWaves, sh, s>>>(X, ldx, V, ldv, Z, ldz, rows, k, n, beta, slab_w, ld);
+}
+
+template <typename T>
+static bool gemm_mfma(const T* X, int64_t ldx, const double* V, int64_t ldv, T* Z, int64_t ldz, int64_t rows, int k,
+                      int n, double beta, hipStream_t s) {
+  const int sw = gemm_slab_width(k, n);
+  if (sw < 16 || rows < 1024 || n < 32 || k < 16) return false;
+  const int ncb = (sw + 15) / 16;
+  if (ncb <= 4) launch_gemm_mfma<T, 4>(X, ldx, V, ldv, Z, ldz, rows, k, n, beta, sw, s);
+  else if (ncb <= 8) launch_gemm_mfma<T, 8>(X, ldx, V, ldv, Z, ldz, rows, k, n, beta, sw, s);
+  else launch_gemm_mfma<T, 13>(X, ldx, V, ldv, Z, ldz, rows, k, n, beta, sw, s);
+  return true;
+}
+
 int gemm_tn(int dt, const void* X, int64_t ldx, const double* V, int64_t ldv, void* Z, int64_t ldz,
             int64_t rows, int k, int n, double beta, hipStream_t s) {
   if (rows <= 0 || n <= 0) return RW_OK;
+  if (dt == RW_F32 && gemm_mfma((const float*)X, ldx, V, ldv, (float*)Z, ldz, rows, k, n, beta, s)) {
+    RW_LAUNCH_CHECK();
+    return RW_OK;
+  }
+  if (dt == RW_BF16 && gemm_mfma((const uint16_t*)X, ldx, V, ldv, (uint16_t*)Z, ldz, rows, k, n, beta, s)) {
+    RW_LAUNCH_CHECK();
+    return RW_OK;
+  }
   dim3 grid((unsigned)((rows + kGT - 1) / kGT), (n + kGT - 1) / kGT);
   if (dt == RW_F64)
     k_gemm<double><<<grid, 256, 0, s>>>((const double*)X, ldx, V, ldv, (double*)Z, ldz, rows, k, n, beta);

@@ -39,6 +39,10 @@ EIG_CASES = [
     ("3d6_f64", rwsynth.small("e3", (9, 8, 7), 6, n_shapes=3), torch.float64, 1e-10, 16),
     ("2d8_f32", rwsynth.small("e4", (26, 24), 8, n_shapes=4), torch.float32, 1e-5, 30),
     ("3d6_f32", rwsynth.small("e5", (10, 9, 8), 6, n_shapes=3), torch.float32, 1e-5, 20),
+    # blocks wide enough for the matrix-core Gram (X^T X and the symmetric X^T op X) and, at m = 190, for
+    # the global-memory Jacobi variant of the Rayleigh-Ritz step
+    ("2d8_f64_m110", rwsynth.small("e6", (30, 28), 8, n_shapes=4), torch.float64, 1e-10, 110),
+    ("2d4_f32_m190", rwsynth.small("e7", (36, 34), 4, n_shapes=4), torch.float32, 1e-5, 190),
 ]
 
 
