@@ -88,15 +88,26 @@ typedef double gram_d4 __attribute__((ext_vector_type(4)));
 constexpr int kGM = 32;        // tile edge
 constexpr int kGMRows = 32;    // rows per step (8 MFMA steps)
 
+// 8 consecutive rows of one column; vector loads when the run is whole and aligned (vec: the leading
+// dimension is a multiple of 8 elements and the base 32-byte aligned, so col + r is aligned for r = 0 mod 8)
 template <typename T>
-__device__ __forceinline__ void gram_load8(const T* col, int64_t r, int64_t r_end, bool ok, T (&v)[8]) {
+__device__ __forceinline__ void gram_load8(const T* col, int64_t r, int64_t r_end, bool ok, bool vec, T (&v)[8]) {
+  if (ok && vec && r + 8 <= r_end) {
+    const uint4* p = reinterpret_cast<const uint4*>(col + r);
+    constexpr int nq = (int)(8 * sizeof(T) / sizeof(uint4));
+    uint4 q[nq];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) v[s] = (ok && r + s < r_end) ? col[r + s] : T(0);
+    for (int i = 0; i < nq; ++i) q[i] = p[i];
+    __builtin_memcpy(v, q, sizeof(q));
+  } else {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = (ok && r + s < r_end) ? col[r + s] : T(0);
+  }
 }
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_gram_mfma(const T* X, int64_t ldx, const T* Y, int64_t ldy, int64_t rows,
-                                                  int bx, int by, int64_t chunk_rows, int tiles_x, int sym,
+                                                  int bx, int by, int64_t chunk_rows, int tiles_x, int sym, int vec,
                                                   double* out, int64_t out_stride) {
   int ti, tj;
   const int t = blockIdx.x;
@@ -125,35 +136,40 @@ __global__ __launch_bounds__(64) void k_gram_mfma(const T* X, int64_t ldx, const
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = gram_d4{0.0, 0.0, 0.0, 0.0};
-  T a0[8], a1[8], b0[8], b1[8];   // raw values of the next step (widened when used)
-  auto fetch = [&](int64_t r0) {
+  // raw values of the next two steps (widened when used): loads run two steps ahead of the MFMAs
+  T q[2][4][8];
+  auto fetch = [&](int64_t r0, T (&d)[4][8]) {
     const int64_t r = r0 + 8 * kq;
-    gram_load8(pa0, r, r_end, oa0, a0);
-    gram_load8(pa1, r, r_end, oa1, a1);
+    gram_load8(pa0, r, r_end, oa0, vec, d[0]);
+    gram_load8(pa1, r, r_end, oa1, vec, d[1]);
     if (!same) {
-      gram_load8(pb0, r, r_end, ob0, b0);
-      gram_load8(pb1, r, r_end, ob1, b1);
+      gram_load8(pb0, r, r_end, ob0, vec, d[2]);
+      gram_load8(pb1, r, r_end, ob1, vec, d[3]);
     }
   };
-  if (r_begin < r_end) fetch(r_begin);
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += kGMRows) {
-    T ca[2][8], cb[2][8];
+  if (r_begin < r_end) fetch(r_begin, q[0]);
+  if (r_begin + kGMRows < r_end) fetch(r_begin + kGMRows, q[1]);
+  for (int64_t r00 = r_begin; r00 < r_end; r00 += 2 * kGMRows) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      ca[0][s] = a0[s];
-      ca[1][s] = a1[s];
-      cb[0][s] = same ? a0[s] : b0[s];
-      cb[1][s] = same ? a1[s] : b1[s];
-    }
-    if (r0 + kGMRows < r_end) fetch(r0 + kGMRows);
+    for (int h = 0; h < 2; ++h) {
+      const int64_t r0 = r00 + h * kGMRows;
+      if (r0 >= r_end) break;
+      T cur[4][8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const double xa[2] = {(double)Elem<T>::ld(ca[0], s), (double)Elem<T>::ld(ca[1], s)};
-      const double xb[2] = {(double)Elem<T>::ld(cb[0], s), (double)Elem<T>::ld(cb[1], s)};
+      for (int c = 0; c < 4; ++c)
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int e = 0; e < 8; ++e) cur[c][e] = (same && c >= 2) ? q[h][c - 2][e] : q[h][c][e];
+      if (r0 + 2 * kGMRows < r_end) fetch(r0 + 2 * kGMRows, q[h]);
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], xb[b], acc[a][b], 0, 0, 0);
+      for (int e = 0; e < 8; ++e) {
+        const double xa[2] = {(double)Elem<T>::ld(cur[0], e), (double)Elem<T>::ld(cur[1], e)};
+        const double xb[2] = {(double)Elem<T>::ld(cur[2], e), (double)Elem<T>::ld(cur[3], e)};
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], xb[b], acc[a][b], 0, 0, 0);
+      }
     }
   }
   double* o = out + (int64_t)blockIdx.y * out_stride;
@@ -185,11 +201,10 @@ static int gram_mfma_tiles(int bx, int by, bool sym) {
   return sym ? tx * (tx + 1) / 2 : tx * ty;
 }
 
-static int64_t gram_big_chunks(int64_t rows, int bx, int by) {
-  // about 3072 waves (several per SIMD), at least 256 rows per chunk; sized for the non-symmetric tile
-  // count so that the partial buffer fits either case
-  const int64_t tiles = gram_mfma_tiles(bx, by, false);
-  const int64_t want = std::max<int64_t>(1, 3072 / std::max<int64_t>(1, tiles));
+static int64_t gram_big_chunks(int64_t rows, int bx, int by, bool sym) {
+  // about 4096 waves (four per SIMD), at least 256 rows per chunk
+  const int64_t tiles = gram_mfma_tiles(bx, by, sym);
+  const int64_t want = std::max<int64_t>(1, 4096 / std::max<int64_t>(1, tiles));
   const int64_t by_rows = std::max<int64_t>(1, rows / 256);
   return std::max<int64_t>(1, std::min<int64_t>(want, by_rows));
 }
@@ -197,7 +212,8 @@ static int64_t gram_big_chunks(int64_t rows, int bx, int by) {
 static bool gram_is_big(int bx, int by) { return bx >= 96 && by >= 96; }
 
 size_t gram_partial_count(int64_t rows, int bx, int by) {
-  int64_t nch = gram_is_big(bx, by) ? gram_big_chunks(rows, bx, by) : gram_chunks(rows, bx, by);
+  // the symmetric case has the most chunks (fewer tiles)
+  int64_t nch = gram_is_big(bx, by) ? gram_big_chunks(rows, bx, by, bx == by) : gram_chunks(rows, bx, by);
   return (size_t)nch * bx * by;
 }
 
@@ -206,23 +222,25 @@ int gram(int dt, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t
   if (bx <= 0 || by <= 0) return RW_OK;
   const bool big = gram_is_big(bx, by);
   const int slab = big ? kGMRows : kGK;
-  int64_t nch = big ? gram_big_chunks(rows, bx, by) : gram_chunks(rows, bx, by);
+  const int sy = (sym && bx == by) ? 1 : 0;
+  int64_t nch = big ? gram_big_chunks(rows, bx, by, sy != 0) : gram_chunks(rows, bx, by);
   int64_t chunk_rows = (rows + nch - 1) / nch;
   chunk_rows = (chunk_rows + slab - 1) / slab * slab;
   if (chunk_rows == 0) chunk_rows = slab;
   nch = std::max<int64_t>(1, (rows + chunk_rows - 1) / chunk_rows);
   int64_t count = (int64_t)bx * by;
   double* dst = nch == 1 ? G : partial;
-  const int sy = (sym && bx == by) ? 1 : 0;
   if (big) {
     const int tiles_x = (bx + kGM - 1) / kGM;
     dim3 grid((unsigned)gram_mfma_tiles(bx, by, sy != 0), (unsigned)nch);
+    const size_t es = dtype_size(dt);
+    const int vec = (ldx % 8 == 0 && ldy % 8 == 0 && (uintptr_t)X % (8 * es) == 0 && (uintptr_t)Y % (8 * es) == 0) ? 1 : 0;
     if (dt == RW_F64)
-      k_gram_mfma<double><<<grid, 64, 0, s>>>((const double*)X, ldx, (const double*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, dst, count);
+      k_gram_mfma<double><<<grid, 64, 0, s>>>((const double*)X, ldx, (const double*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, vec, dst, count);
     else if (dt == RW_F32)
-      k_gram_mfma<float><<<grid, 64, 0, s>>>((const float*)X, ldx, (const float*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, dst, count);
+      k_gram_mfma<float><<<grid, 64, 0, s>>>((const float*)X, ldx, (const float*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, vec, dst, count);
     else
-      k_gram_mfma<uint16_t><<<grid, 64, 0, s>>>((const uint16_t*)X, ldx, (const uint16_t*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, dst, count);
+      k_gram_mfma<uint16_t><<<grid, 64, 0, s>>>((const uint16_t*)X, ldx, (const uint16_t*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, vec, dst, count);
   } else {
     dim3 grid((bx + kGT - 1) / kGT, (by + kGT - 1) / kGT, (unsigned)nch);
     if (dt == RW_F64)

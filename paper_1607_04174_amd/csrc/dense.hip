@@ -132,7 +132,7 @@ size_t syev_work_count(int n, int count, bool vectors, int nrhs) {
 
 template <class Store>
 __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, double* log, double* wout, double* permout,
-                            double* sweeps_out, double* cs, double* sn, int* pq) {
+                            double* sweeps_out, double* cs, double* sn, int* pq, double min_rel_tol) {
   const int np = n2 / 2;
   __shared__ int rotated;
   __shared__ double fro_s;
@@ -152,7 +152,7 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
   // sqrt(n) eps relative to the diagonal, or eps |A|_F absolute, are skipped; a sweep without
   // rotations ends the iteration
   const double abs_tiny = fro_s * 2.3e-16 + 1e-300;
-  const double rel_tol = 2.3e-16 * sqrt((double)n) * 2.0;
+  const double rel_tol = fmax(2.3e-16 * sqrt((double)n) * 2.0, min_rel_tol);
   const int ta = threadIdx.x & 31, tb = threadIdx.x >> 5;   // 32 x 32 thread grid over pair blocks
   int sweep = 0;
   for (; sweep < kJacobiMaxSweeps; ++sweep) {
@@ -270,7 +270,8 @@ __device__ void jacobi_body(Store S, int n, int n2, double* rhs, int nrhs, doubl
 // only while some off-diagonal entry is above the thresholds, which is the same test as a sweep
 // without rotations, evaluated on the matrix at the sweep boundary.
 __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(const double* As, int n, double* ws, double* Rs, int nrhs,
-                                                                double* work, int64_t stride, int want_log) {
+                                                                double* work, int64_t stride, int want_log,
+                                                                double min_rel_tol) {
   extern __shared__ double smem[];
   const JacLayout P(n);
   const int n2 = P.n2, np = P.np, nto = P.nto;
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(const double* As,
   // thresholds: rounding noise regenerates off-diagonal entries of size ~eps |A|, so rotations below
   // sqrt(n) eps relative to the diagonal, or eps |A|_F absolute, are skipped
   const double abs_tiny = fro_s * 2.3e-16 + 1e-300;
-  const double rel_tol = 2.3e-16 * sqrt((double)n) * 2.0;
+  const double rel_tol = fmax(2.3e-16 * sqrt((double)n) * 2.0, min_rel_tol);
   auto above = [&](double v, double d1, double d2) {
     return fabs(v) > abs_tiny && fabs(v) > rel_tol * sqrt(fabs(d1) * fabs(d2));
   };
@@ -460,7 +461,8 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(const double* As,
 }
 
 __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_glb(const double* As, int n, double* ws, double* Rs, int nrhs,
-                                                                double* work, int64_t stride, int want_log) {
+                                                                double* work, int64_t stride, int want_log,
+                                                                double min_rel_tol) {
   const int n2 = n + (n & 1), np = n2 / 2;
   __shared__ double cs[512], sn[512];
   __shared__ int pq[1024];
@@ -482,7 +484,8 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_glb(const double* As,
       rhs[t] = i < n ? R[i + (int64_t)r * n] : 0.0;
     }
   __syncthreads();
-  jacobi_body(S, n, n2, R ? rhs : nullptr, nrhs, log, ws + (int64_t)blockIdx.x * n, perm, perm + n, cs, sn, pq);
+  jacobi_body(S, n, n2, R ? rhs : nullptr, nrhs, log, ws + (int64_t)blockIdx.x * n, perm, perm + n, cs, sn, pq,
+              min_rel_tol);
   __syncthreads();
   if (R)
     for (int64_t t = threadIdx.x; t < (int64_t)n * nrhs; t += kJacobiThreads) {
@@ -592,7 +595,7 @@ static void launch_replay(int n, int count, const double* work, int64_t stride, 
 }
 
 int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int n, int count, double* work,
-                 hipStream_t s) {
+                 hipStream_t s, double min_rel_tol) {
   if (n <= 0 || count <= 0) return RW_OK;
   RW_CHECK(n <= 1022, RW_EINVAL, "Jacobi eigensolver limited to n <= 1022 (got %d)", n);
   const bool vectors = V != nullptr;
@@ -600,7 +603,7 @@ int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int
   const bool glb = lds_bytes(n, nr) > kLdsLimit;
   const int64_t stride = (int64_t)syev_stride(n, vectors, glb, nr);
   if (glb) {
-    k_jacobi_glb<<<count, kJacobiThreads, 0, s>>>(A, n, w, R, nr, work, stride, vectors ? 1 : 0);
+    k_jacobi_glb<<<count, kJacobiThreads, 0, s>>>(A, n, w, R, nr, work, stride, vectors ? 1 : 0, min_rel_tol);
   } else {
     size_t sh = lds_bytes(n, R ? nrhs : 0);
     static bool attr_set = false;
@@ -609,7 +612,8 @@ int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
       attr_set = true;
     }
-    k_jacobi_lds<<<count, kJacobiThreads, sh, s>>>(A, n, w, R, R ? nrhs : 0, work, stride, vectors ? 1 : 0);
+    k_jacobi_lds<<<count, kJacobiThreads, sh, s>>>(A, n, w, R, R ? nrhs : 0, work, stride, vectors ? 1 : 0,
+                                                   min_rel_tol);
   }
   RW_LAUNCH_CHECK();
   if (vectors) {

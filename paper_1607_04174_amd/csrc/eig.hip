@@ -118,7 +118,9 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX) {
   RW_TRY(gram(RW_F64, w.W, nb, w.T, nb, nb, nb, nb, w.Hp, w.partial, c.s));        // Hp = W^T H W
   k_symmetrize<<<nblocks((int64_t)nb * nb, 256), 256, 0, c.s>>>(w.Hp, nb);
   RW_LAUNCH_CHECK();
-  RW_TRY(syev_batched(w.Hp, w.theta, w.Z, nullptr, 0, nb, 1, w.syw, c.s));
+  // with an FP32 or BF16 basis the projected matrix carries errors near 1e-7 relative, so rotations
+  // below 1e-10 relative change nothing that the rotated basis can represent
+  RW_TRY(syev_batched(w.Hp, w.theta, w.Z, nullptr, 0, nb, 1, w.syw, c.s, c.dt == RW_F64 ? 0.0 : 1e-10));
   RW_TRY(gemm_tn(RW_F64, w.W, nb, w.Z, nb, w.WZ, nb, nb, nb, nb, 0.0, c.s));      // WZ = W Z
   RW_TRY(gemm_tn(c.dt, F, c.N, w.WZ, nb, X, c.N, c.N, nb, nb, 0.0, c.s));        // X = F W Z
   RW_TRY(gemm_tn(c.dt, LF, c.N, w.WZ, nb, LX, c.N, c.N, nb, nb, 0.0, c.s));      // op X

@@ -215,9 +215,11 @@ int chol_batched(double* A, int n, int count, int* info, hipStream_t s);
 int chol_upper_inverse(const double* L, double* Rinv, int n, hipStream_t s);
 // Symmetric eigendecomposition (parallel cyclic Jacobi) of count matrices A (n x n, stride n*n, read
 // only): w (ascending, stride n); V (n x n eigenvectors, or null); R (n x nrhs per matrix, or null)
-// is replaced by V^T R.  work: syev_work_count doubles.
+// is replaced by V^T R.  work: syev_work_count doubles.  min_rel_tol raises the relative rotation
+// threshold (|a_pq| against sqrt(|a_pp a_qq|)) above its FP64 default, for matrices whose entries carry
+// larger errors than FP64 rounding (0: the default).
 int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int n, int count, double* work,
-                 hipStream_t s);
+                 hipStream_t s, double min_rel_tol = 0.0);
 size_t syev_work_count(int n, int count, bool vectors, int nrhs);
 // Solve A X = B by LU with partial pivoting (A: n x n, B: n x nrhs, both destroyed/overwritten;
 // X returned in B).  stat[0] = min |pivot| / max |a_ij| (0 if a pivot is below the threshold).
