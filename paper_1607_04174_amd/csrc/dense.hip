@@ -72,6 +72,110 @@ int chol_upper_inverse(const double* L, double* Rinv, int n, hipStream_t s) {
   return RW_OK;
 }
 
+// Cholesky factor and its transposed inverse in one workgroup, in LDS (n <= 200): W = (L^T)^{-1}
+// (upper triangular, zero below) for A = L L^T.  The factorization is right-looking with unscaled
+// columns (Schur complements A(i,j) -= A(i,k) A(j,k) / A(k,k)), one barrier per column; then one wave
+// per column of W solves L^T x = e_j by back substitution in axpy form, the solved entry broadcast from
+// its lane.  info = k + 1 at the first pivot that is not positive and finite (W untouched), else 0.
+__device__ __forceinline__ int cw_lo(int i, int j, int n) { return j * n - ((j * (j - 1)) >> 1) + (i - j); }  // i >= j
+
+__device__ __forceinline__ double cw_readlane(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+constexpr int kCholInvMaxN = 200;   // packed factor plus n pivots within the LDS budget; 4 entries per lane
+
+__global__ __launch_bounds__(1024) void k_chol_inv_lds(const double* G, int n, double* W, int* info) {
+  extern __shared__ double sA[];   // packed lower factor (column-major), then 1 / L(k, k)
+  double* rd = sA + n * (n + 1) / 2;
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < n * n; t += blockDim.x) {
+    const int i = t % n, j = t / n;
+    if (i >= j) sA[cw_lo(i, j, n)] = G[t];
+  }
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  const int tx = tid & 31, ty = tid >> 5;
+  for (int k = 0; k < n; ++k) {
+    const double dkk = sA[cw_lo(k, k, n)];
+    if (!(dkk > 0.0) || !isfinite(dkk)) {   // uniform
+      if (tid == 0) s_bad = k + 1;
+      break;
+    }
+    if (tid == 0) rd[k] = 1.0 / sqrt(dkk);
+    const double inv = 1.0 / dkk;
+    for (int j = k + 1 + ty; j < n; j += 32) {
+      const double ajk = sA[cw_lo(j, k, n)] * inv;
+      for (int i = j + tx; i < n; i += 32) sA[cw_lo(i, j, n)] -= sA[cw_lo(i, k, n)] * ajk;
+    }
+    lds_barrier();
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) info[0] = s_bad;
+    return;
+  }
+  for (int t = tid; t < n * n; t += blockDim.x) {   // scale the columns: L(i, j) = A(i, j) / sqrt(A(j, j))
+    const int i = t % n, j = t / n;
+    if (i > j) sA[cw_lo(i, j, n)] *= rd[j];
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
+  for (int g0 = 0; g0 < n; g0 += nw) {
+    const int grp = g0 / nw;
+    const int j = (grp & 1) ? g0 + nw - 1 - wave : g0 + wave;   // zigzag: long and short columns pair up
+    if (j >= n) continue;
+    double bv[4], xv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      bv[r] = (lane + 64 * r == j) ? 1.0 : 0.0;
+      xv[r] = 0.0;
+    }
+    for (int k = j; k >= 0; --k) {
+      const int rk = k >> 6;
+      const double bk = rk == 0 ? bv[0] : (rk == 1 ? bv[1] : (rk == 2 ? bv[2] : bv[3]));
+      const double xk = cw_readlane(bk, k & 63) * rd[k];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = lane + 64 * r;
+        if (i == k) xv[r] = xk;
+        if (i < k) bv[r] -= sA[cw_lo(k, i, n)] * xk;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = lane + 64 * r;
+      if (i < n) W[i + (int64_t)j * n] = i <= j ? xv[r] : 0.0;
+    }
+  }
+  if (tid == 0) info[0] = 0;
+}
+
+int chol_inverse(double* G, double* W, int n, int* info, hipStream_t s) {
+  if (n <= 0) return RW_OK;
+  if (n > kCholInvMaxN) {
+    RW_TRY(chol_batched(G, n, 1, info, s));
+    int bad = 0;
+    RW_HIP(hipMemcpyAsync(&bad, info, sizeof(int), hipMemcpyDeviceToHost, s));
+    RW_HIP(hipStreamSynchronize(s));
+    if (bad == 0) RW_TRY(chol_upper_inverse(G, W, n, s));
+    return RW_OK;
+  }
+  static bool attr = false;
+  if (!attr) {
+    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_inv_lds),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+    attr = true;
+  }
+  const size_t sh = ((size_t)n * (n + 1) / 2 + n) * sizeof(double);
+  k_chol_inv_lds<<<1, 1024, sh, s>>>(G, n, W, info);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Symmetric eigendecomposition by the cyclic Jacobi method with the round-robin ("tournament")
 // ordering (Golub & Van Loan, Sec. 8.5): each round rotates n/2 disjoint index pairs at once.

@@ -58,6 +58,34 @@ __global__ void k_scale_cols(const double* V, const double* s, double* W, int n,
   W[t] = V[t] / sqrt(sj);
 }
 
+// E = G - I and max |E_ij| (one workgroup; the max does not depend on the reduction order)
+__global__ __launch_bounds__(1024) void k_offI_absmax(const double* G, int n, double* E, double* out) {
+  __shared__ double red[16];
+  double m = 0.0;
+  for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += blockDim.x) {
+    const int i = (int)(t % n), j = (int)(t / n);
+    const double e = G[t] - (i == j ? 1.0 : 0.0);
+    E[t] = e;
+    m = fmax(m, fabs(e));
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
+    out[0] = r;
+  }
+}
+
+// W = G^{-1/2} = I - E/2 + (3/8) E^2 + O(|E|^3) for G = I + E (E2 = E E)
+__global__ void k_series_w(const double* E, const double* E2, double* W, int n) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * n) return;
+  const int i = (int)(t % n), j = (int)(t / n);
+  W[t] = (i == j ? 1.0 : 0.0) - 0.5 * E[t] + 0.375 * E2[t];
+}
+
 __global__ void k_symmetrize(double* A, int n) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= (int64_t)n * n) return;
@@ -92,21 +120,37 @@ __global__ void k_copy_d(const double* a, double* b, int64_t n) {
 
 // One Rayleigh-Ritz step on the block F (nb columns).  Outputs X = F W Z, LX = op X, theta, res.
 // W makes F W orthonormal: W = R^{-1} from the Cholesky factor of G = F^T F (Cholesky QR), or, if
-// G is numerically singular, W = V s^{-1/2} from its eigendecomposition with small s floored.
-static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX) {
+// G is numerically singular, W = V s^{-1/2} from its eigendecomposition with small s floored.  With
+// `near_orth` (F already orthonormal up to storage rounding, as a stored eigenbasis is) and
+// max |G - I| < 1e-4, W = G^{-1/2} from its series I - E/2 + 3/8 E^2 (truncation below 1e-12).
+static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool near_orth = false) {
   const Graph* g = c.g;
   EigWork& w = c.w;
   const int64_t n2 = (int64_t)nb * nb;
   RW_TRY(gram(c.dt, F, c.N, F, c.N, c.N, nb, nb, w.G, w.partial, c.s, true));
-  k_copy_d<<<nblocks(n2, 256), 256, 0, c.s>>>(w.G, w.G2, n2);
-  RW_LAUNCH_CHECK();
-  RW_TRY(chol_batched(w.G2, nb, 1, w.info, c.s));
+  bool have_w = false;
+  if (near_orth) {
+    k_offI_absmax<<<1, 1024, 0, c.s>>>(w.G, nb, w.G2, w.tmp);
+    RW_LAUNCH_CHECK();
+    double e = 1.0;
+    RW_HIP(hipMemcpyAsync(&e, w.tmp, sizeof(double), hipMemcpyDeviceToHost, c.s));
+    RW_HIP(hipStreamSynchronize(c.s));
+    if (e < 1e-4) {
+      RW_TRY(gemm_tn(RW_F64, w.G2, nb, w.G2, nb, w.V, nb, nb, nb, nb, 0.0, c.s));   // E^2 (E symmetric)
+      k_series_w<<<nblocks(n2, 256), 256, 0, c.s>>>(w.G2, w.V, w.W, nb);
+      RW_LAUNCH_CHECK();
+      have_w = true;
+    }
+  }
   int bad = 0;
-  RW_HIP(hipMemcpyAsync(&bad, w.info, sizeof(int), hipMemcpyDeviceToHost, c.s));
-  RW_HIP(hipStreamSynchronize(c.s));
-  if (bad == 0) {
-    RW_TRY(chol_upper_inverse(w.G2, w.W, nb, c.s));
-  } else {
+  if (!have_w) {
+    k_copy_d<<<nblocks(n2, 256), 256, 0, c.s>>>(w.G, w.G2, n2);
+    RW_LAUNCH_CHECK();
+    RW_TRY(chol_inverse(w.G2, w.W, nb, w.info, c.s));
+    RW_HIP(hipMemcpyAsync(&bad, w.info, sizeof(int), hipMemcpyDeviceToHost, c.s));
+    RW_HIP(hipStreamSynchronize(c.s));
+  }
+  if (bad != 0) {
     RW_TRY(syev_batched(w.G, w.s, w.V, nullptr, 0, nb, 1, w.syw, c.s));
     k_scale_cols<<<nblocks(n2, 256), 256, 0, c.s>>>(w.V, w.s, w.W, nb, c.floor_rel);
     RW_LAUNCH_CHECK();
@@ -346,12 +390,11 @@ int rw_update_eig(rw_graph h, const rw_edit* edits, int n_edits, int mode, const
       for (int pass = 0; pass < 2; ++pass) {
         int dst = pass == 0 ? 1 : 2;
         RW_TRY(gram(c.dt, w.B[src], c.N, w.B[src], c.N, c.N, k, k, w.G, w.partial, stream, true));
-        RW_TRY(chol_batched(w.G, k, 1, w.info, stream));
+        RW_TRY(chol_inverse(w.G, w.W, k, w.info, stream));
         int bad = 0;
         RW_HIP(hipMemcpyAsync(&bad, w.info, sizeof(int), hipMemcpyDeviceToHost, stream));
         RW_HIP(hipStreamSynchronize(stream));
         RW_CHECK(bad == 0, RW_ESINGULAR, "stored eigenvectors are linearly dependent after the edit (pivot %d)", bad);
-        RW_TRY(chol_upper_inverse(w.G, w.W, k, stream));
         RW_TRY(gemm_tn(c.dt, w.B[src], c.N, w.W, k, w.B[dst], c.N, c.N, k, k, 0.0, stream));
         src = dst;
       }
@@ -361,7 +404,7 @@ int rw_update_eig(rw_graph h, const rw_edit* edits, int n_edits, int mode, const
       RW_TRY(col_dots(c.dt, w.B[ix], w.B[3], c.N, k, c.N, w.theta, w.partial, stream));
       RW_TRY(residual_norms(c.dt, w.B[3], w.B[ix], w.theta, c.N, k, c.N, w.res, w.partial, stream));
     } else {
-      RW_TRY(rr_step(c, k, w.B[0], w.B[1], w.B[2], w.B[3]));
+      RW_TRY(rr_step(c, k, w.B[0], w.B[1], w.B[2], w.B[3], true));
       ix = 2;
     }
     const int qdt = opts->q_dtype;

@@ -213,6 +213,9 @@ int reconstruct_mfma(const Graph* g, const void* Q, int m, const double* Y, int 
 int chol_batched(double* A, int n, int count, int* info, hipStream_t s);
 // Rinv = (L^T)^{-1} (upper triangular) for the lower factor L; n x n
 int chol_upper_inverse(const double* L, double* Rinv, int n, hipStream_t s);
+// W = (L^T)^{-1} for the Cholesky factor of G (n x n, lower triangle read; G may be overwritten);
+// info[0] = k + 1 at the first failed pivot (W then undefined), else 0.
+int chol_inverse(double* G, double* W, int n, int* info, hipStream_t s);
 // Symmetric eigendecomposition (parallel cyclic Jacobi) of count matrices A (n x n, stride n*n, read
 // only): w (ascending, stride n); V (n x n eigenvectors, or null); R (n x nrhs per matrix, or null)
 // is replaced by V^T R.  work: syev_work_count doubles.  min_rel_tol raises the relative rotation
