@@ -723,10 +723,12 @@ int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int
   if (vectors) {
     const int np = (n + (n & 1)) / 2;
     const int64_t log_off = glb ? (int64_t)(n + (n & 1)) * (n + (n & 1)) : 0;
-    if (np <= 64) launch_replay<1, 2, 4>(n, count, work, stride, log_off, V, s);
-    else if (np <= 128) launch_replay<2, 2, 4>(n, count, work, stride, log_off, V, s);
-    else if (np <= 256) launch_replay<4, 1, 2>(n, count, work, stride, log_off, V, s);
-    else launch_replay<8, 1, 2>(n, count, work, stride, log_off, V, s);
+    // the rotations are loaded 16 (or 8) rounds ahead: a round takes a few hundred cycles, a load from L2
+    // or HBM some thousands
+    if (np <= 64) launch_replay<1, 2, 16>(n, count, work, stride, log_off, V, s);
+    else if (np <= 128) launch_replay<2, 2, 16>(n, count, work, stride, log_off, V, s);
+    else if (np <= 256) launch_replay<4, 1, 8>(n, count, work, stride, log_off, V, s);
+    else launch_replay<8, 1, 8>(n, count, work, stride, log_off, V, s);
     RW_LAUNCH_CHECK();
   }
   return RW_OK;
@@ -839,9 +841,112 @@ int lu_solve_batched(const LuJob* jobs, int count, hipStream_t s) {
   return RW_OK;
 }
 
+// The same elimination with A and B in LDS (rows padded to an odd stride, so that a row read across
+// lanes is free of bank conflicts).  Rows are not exchanged: step k eliminates column k from every row not
+// yet chosen as a pivot row (a flag per row) using the chosen row p_k, so a column costs two barriers
+// (pivot search by one wave; elimination of A and B).  Back substitution runs over the pivot order.  Ties
+// in the pivot search go to the lowest row index, and the solution is written to B in natural order.
+__global__ __launch_bounds__(1024) void k_lu_solve_lds(const double* Ag, int n, double* Bg, int nrhs, double* stat) {
+  extern __shared__ double sm[];
+  const int ld = n | 1;
+  double* A = sm;                       // ld x n
+  double* B = A + (size_t)ld * n;       // ld x nrhs
+  int* prow = reinterpret_cast<int*>(B + (size_t)ld * nrhs);   // n: pivot row of step k
+  int* done = prow + n;                  // n: row already used as a pivot row
+  __shared__ double s_amax, s_minpiv;
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < n * n; t += blockDim.x) A[(t % n) + (t / n) * ld] = Ag[t];
+  for (int t = tid; t < n * nrhs; t += blockDim.x) B[(t % n) + (t / n) * ld] = Bg[t];
+  for (int t = tid; t < n; t += blockDim.x) done[t] = 0;
+  __syncthreads();
+  if (tid < 64) {
+    double m = 0.0;
+    for (int t = tid; t < n * n; t += 64) m = fmax(m, fabs(A[(t % n) + (t / n) * ld]));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if (tid == 0) { s_amax = m; s_minpiv = INFINITY; s_bad = 0; }
+  }
+  __syncthreads();
+  const double amax = s_amax;
+  for (int k = 0; k < n; ++k) {
+    if (tid < 64) {
+      double best = -1.0;
+      int brow = n;
+      for (int i = tid; i < n; i += 64) {
+        if (done[i]) continue;
+        const double v = fabs(A[i + k * ld]);
+        if (v > best || (v == best && i < brow)) { best = v; brow = i; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o);
+        const int orow = __shfl_xor(brow, o);
+        if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
+      }
+      if (tid == 0) {
+        prow[k] = brow;
+        done[brow] = 1;
+        if (!(best > 1e-14 * amax)) s_bad = 1;
+        s_minpiv = fmin(s_minpiv, best);
+      }
+    }
+    lds_barrier();
+    if (s_bad) break;
+    const int p = prow[k];
+    const double inv = 1.0 / A[p + k * ld];
+    // rows not yet chosen, columns k+1.. of A and all of B: x(i) -= (A(i,k) / A(p,k)) x(p)
+    const int cols = n - k - 1 + nrhs;
+    for (int t = tid; t < n * cols; t += blockDim.x) {
+      const int i = t % n, c = t / n;
+      if (done[i]) continue;
+      const double l = A[i + k * ld] * inv;
+      double* col = c < n - k - 1 ? A + (k + 1 + c) * ld : B + (c - (n - k - 1)) * ld;
+      col[i] -= l * col[p];
+    }
+    lds_barrier();
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) stat[0] = 0.0;
+    return;
+  }
+  // back substitution over the pivot order: x_k = b(p_k) / A(p_k, k); b(p_i) -= A(p_i, k) x_k for i < k
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = prow[k];
+    const double ukk = A[p + k * ld];
+    if (tid < nrhs) B[p + tid * ld] /= ukk;
+    lds_barrier();
+    for (int t = tid; t < k * nrhs; t += blockDim.x) {
+      const int i = t % k, r = t / k;
+      const int pi = prow[i];
+      B[pi + r * ld] -= A[pi + k * ld] * B[p + r * ld];
+    }
+    lds_barrier();
+  }
+  for (int t = tid; t < n * nrhs; t += blockDim.x) {
+    const int k = t % n, r = t / n;
+    Bg[k + (int64_t)r * n] = B[prow[k] + r * ld];
+  }
+  if (tid == 0) stat[0] = s_minpiv / amax;
+}
+
+static size_t lu_lds_bytes(int n, int nrhs) {
+  const size_t ld = (size_t)(n | 1);
+  return (ld * (n + nrhs)) * sizeof(double) + 2 * (size_t)n * sizeof(int);
+}
+
 int lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s) {
   if (n <= 0) return RW_OK;
-  k_lu_solve<<<1, 1024, 0, s>>>(A, n, B, nrhs, stat);
+  if (nrhs <= 1024 && lu_lds_bytes(n, nrhs) <= kLdsLimit) {
+    static bool attr = false;
+    if (!attr) {
+      RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_solve_lds),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+      attr = true;
+    }
+    k_lu_solve_lds<<<1, 1024, lu_lds_bytes(n, nrhs), s>>>(A, n, B, nrhs, stat);
+  } else {
+    k_lu_solve<<<1, 1024, 0, s>>>(A, n, B, nrhs, stat);
+  }
   RW_LAUNCH_CHECK();
   return RW_OK;
 }

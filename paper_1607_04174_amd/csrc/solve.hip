@@ -693,8 +693,10 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
       cand.clear();
       int span = hi - lo - 1;
       if (screened) {
-        // the screen leaves lo + 1 undecided and usually passes a few m later: the next 32 m in order
-        for (int mm = std::max(lo + 1, 2); mm < hi && (int)cand.size() < std::min(32, maxc); ++mm) cand.push_back(mm);
+        // the screen leaves lo + 1 undecided and usually passes a few m later: the next 8 m in order on the
+        // first probe (the batch's cost grows with its largest candidate), the next 32 on later ones
+        const int take = probes == 1 ? 8 : 32;
+        for (int mm = std::max(lo + 1, 2); mm < hi && (int)cand.size() < std::min(take, maxc); ++mm) cand.push_back(mm);
       } else {
         int nc = std::min(span, maxc);
         for (int q = 1; q <= nc; ++q) {
