@@ -585,17 +585,8 @@ int fill_random(int dt, void* X, int64_t ld, int64_t rows, int cols, uint64_t se
 // ---------------------------------------------------------------------------------------------
 // X -= v (v^T X) for a unit vector v
 // ---------------------------------------------------------------------------------------------
-template <typename T>
-__global__ void k_rank1_sub(T* X, int64_t ld, const T* v, const double* t, int64_t rows, int cols) {
-  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int c = blockIdx.y;
-  if (r >= rows) return;
-  using C = typename Elem<T>::C;
-  int64_t idx = (int64_t)c * ld + r;
-  C val = Elem<T>::ld(X, idx) - (C)t[c] * Elem<T>::ld(v, r);
-  Elem<T>::st(X, idx, val);
-}
-
+int project_out_to(int dt, const void* X, int64_t ldx, void* Y, int64_t ldy, const void* v, int64_t rows, int cols,
+                   double* tmp, double* partial, hipStream_t s);
 // d_j = v^T X_j for one vector v (the 1 x cols Gram): block (j, chunk) reduces its rows in a fixed order
 // (strided per-thread sums, then a tree in LDS); FP64 accumulation.  HBM-bound: X is read once.
 template <typename T>
@@ -638,12 +629,33 @@ static int vdot_cols(int dt, const void* v, const void* X, int64_t ld, int64_t r
 
 int project_out(int dt, void* X, int64_t ld, const void* v, int64_t rows, int cols, double* tmp, double* partial,
                 hipStream_t s) {
+  return project_out_to(dt, X, ld, X, ld, v, rows, cols, tmp, partial, s);
+}
+
+// Y = X - v (v^T X): the same two passes, reading X and writing Y (Y may be X)
+template <typename T>
+__global__ void k_rank1_sub_to(const T* X, int64_t ldx, T* Y, int64_t ldy, const T* v, const double* t, int64_t rows,
+                               int cols) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= rows) return;
+  using C = typename Elem<T>::C;
+  const C val = Elem<T>::ld(X, (int64_t)c * ldx + r) - (C)t[c] * Elem<T>::ld(v, r);
+  Elem<T>::st(Y, (int64_t)c * ldy + r, val);
+}
+
+int project_out_to(int dt, const void* X, int64_t ldx, void* Y, int64_t ldy, const void* v, int64_t rows, int cols,
+                   double* tmp, double* partial, hipStream_t s) {
   if (cols <= 0) return RW_OK;
-  RW_TRY(vdot_cols(dt, v, X, ld, rows, cols, tmp, partial, s));
+  RW_TRY(vdot_cols(dt, v, X, ldx, rows, cols, tmp, partial, s));
   dim3 grid(nblocks(rows, 256), cols);
-  if (dt == RW_F64) k_rank1_sub<double><<<grid, 256, 0, s>>>((double*)X, ld, (const double*)v, tmp, rows, cols);
-  else if (dt == RW_F32) k_rank1_sub<float><<<grid, 256, 0, s>>>((float*)X, ld, (const float*)v, tmp, rows, cols);
-  else k_rank1_sub<uint16_t><<<grid, 256, 0, s>>>((uint16_t*)X, ld, (const uint16_t*)v, tmp, rows, cols);
+  if (dt == RW_F64)
+    k_rank1_sub_to<double><<<grid, 256, 0, s>>>((const double*)X, ldx, (double*)Y, ldy, (const double*)v, tmp, rows, cols);
+  else if (dt == RW_F32)
+    k_rank1_sub_to<float><<<grid, 256, 0, s>>>((const float*)X, ldx, (float*)Y, ldy, (const float*)v, tmp, rows, cols);
+  else
+    k_rank1_sub_to<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)X, ldx, (uint16_t*)Y, ldy, (const uint16_t*)v, tmp,
+                                                   rows, cols);
   RW_LAUNCH_CHECK();
   return RW_OK;
 }

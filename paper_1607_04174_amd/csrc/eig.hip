@@ -375,14 +375,19 @@ int rw_update_eig(rw_graph h, const rw_edit* edits, int n_edits, int mode, const
   EigWork& w = c.w;
   const int k = m - 1;
   const size_t es = dtype_size(c.dt);
-  RW_TRY(copy_cols(opts->q_dtype, (const char*)Q + dtype_size(opts->q_dtype) * g->N, g->N, c.dt, w.B[0], g->N, g->N,
-                   k, stream));
+  // Rayleigh-Ritz on a basis stored in the graph's type reads Q's columns directly (the projection writes the
+  // block) and writes the rotated basis straight back into Q
+  const bool direct = mode == RW_UPDATE_RR && opts->q_dtype == c.dt;
+  char* Qv = (char*)Q + dtype_size(opts->q_dtype) * g->N;   // columns 1..m-1
+  if (!direct)
+    RW_TRY(copy_cols(opts->q_dtype, Qv, g->N, c.dt, w.B[0], g->N, g->N, k, stream));
   int st = RW_OK;
   if (mode == RW_UPDATE_RR_REFINE) {
     RW_TRY(fill_random(c.dt, w.B[0] + es * g->N * k, g->N, g->N, nb - k, opts->seed ^ 0x5eedull, stream));
     st = chfsi(c, m, nb, opts, Q, lambda, info);
   } else {
-    RW_TRY(project_out(c.dt, w.B[0], c.N, g->ghat, c.N, k, w.tmp, w.partial, stream));
+    if (direct) RW_TRY(project_out_to(c.dt, Qv, c.N, w.B[0], c.N, g->ghat, c.N, k, w.tmp, w.partial, stream));
+    else RW_TRY(project_out(c.dt, w.B[0], c.N, g->ghat, c.N, k, w.tmp, w.partial, stream));
     int ix = 0;
     if (mode == RW_UPDATE_DIAG_RQ) {
       // order-preserving orthonormalization (Cholesky QR, twice), then lambda_i = q_i^T op q_i
@@ -404,12 +409,12 @@ int rw_update_eig(rw_graph h, const rw_edit* edits, int n_edits, int mode, const
       RW_TRY(col_dots(c.dt, w.B[ix], w.B[3], c.N, k, c.N, w.theta, w.partial, stream));
       RW_TRY(residual_norms(c.dt, w.B[3], w.B[ix], w.theta, c.N, k, c.N, w.res, w.partial, stream));
     } else {
-      RW_TRY(rr_step(c, k, w.B[0], w.B[1], w.B[2], w.B[3], true));
+      RW_TRY(rr_step(c, k, w.B[0], w.B[1], direct ? Qv : w.B[2], w.B[3], true));
       ix = 2;
     }
     const int qdt = opts->q_dtype;
     RW_TRY(copy_cols(c.dt, g->ghat, c.N, qdt, Q, c.N, c.N, 1, stream));
-    RW_TRY(copy_cols(c.dt, w.B[ix], c.N, qdt, (char*)Q + dtype_size(qdt) * c.N, c.N, c.N, k, stream));
+    if (!direct) RW_TRY(copy_cols(c.dt, w.B[ix], c.N, qdt, Qv, c.N, c.N, k, stream));
     const double zero = 0.0;
     RW_HIP(hipMemcpyAsync(lambda, &zero, sizeof(double), hipMemcpyHostToDevice, stream));
     RW_HIP(hipMemcpyAsync(lambda + 1, w.theta, k * sizeof(double), hipMemcpyDeviceToDevice, stream));

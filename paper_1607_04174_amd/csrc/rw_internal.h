@@ -202,6 +202,9 @@ int fill_random(int dt, void* X, int64_t ld, int64_t rows, int cols, uint64_t se
 // X -= v (v^T X) for a unit vector v (rows), X column-major rows x cols
 int project_out(int dt, void* X, int64_t ld, const void* v, int64_t rows, int cols, double* tmp,
                 double* partial, hipStream_t s);
+// Y = X - v (v^T X), reading X and writing Y (Y may be X)
+int project_out_to(int dt, const void* X, int64_t ldx, void* Y, int64_t ldy, const void* v, int64_t rows, int cols,
+                   double* tmp, double* partial, hipStream_t s);
 
 // ---- BF16 matrix-core contractions (mfma.hip) ----------------------------------------------------
 int reconstruct_mfma(const Graph* g, const void* Q, int m, const double* Y, int C, const uint8_t* map, void* U,
