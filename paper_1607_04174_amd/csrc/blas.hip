@@ -328,10 +328,10 @@ __global__ __launch_bounds__(256) void k_gemm(const T* X, int64_t ldx, const dou
 // Z^T = V^T X^T so that a store writes 16 consecutive rows of a column per 16-lane group.  A workgroup
 // keeps an FP32 copy of a slab of V's columns (all k rows) in LDS and its eight waves walk 32-row tasks;
 // a wave accumulates all of the slab's 16-column blocks for its two 16-row blocks, with X fragments
-// loaded two steps ahead.  Same arithmetic as the vector kernel (V rounded to FP32, FP32 accumulation).
+// loaded four steps ahead.  Same arithmetic as the vector kernel (V rounded to FP32, FP32 accumulation).
 typedef float gemm_f4 __attribute__((ext_vector_type(4)));
 constexpr int kGemmWaves = 8;
-constexpr int kGemmAhead = 2;
+constexpr int kGemmAhead = 4;   // k-steps of X loaded ahead (a step is 26 MFMAs, an HBM load some microseconds)
 
 template <typename T, int NCB>
 __global__ __launch_bounds__(64 * kGemmWaves) void k_gemm_mfma(const T* X, int64_t ldx, const double* V, int64_t ldv,

@@ -846,6 +846,9 @@ int lu_solve_batched(const LuJob* jobs, int count, hipStream_t s) {
 // yet chosen as a pivot row (a flag per row) using the chosen row p_k, so a column costs two barriers
 // (pivot search by one wave; elimination of A and B).  Back substitution runs over the pivot order.  Ties
 // in the pivot search go to the lowest row index, and the solution is written to B in natural order.
+constexpr int kLuLdsMaxRows = 192;   // rows per lane in the elimination grid: 3 x 64
+constexpr int kLuWaveRhs = 8;        // back substitution in one wave up to this many right-hand sides
+
 __global__ __launch_bounds__(1024) void k_lu_solve_lds(const double* Ag, int n, double* Bg, int nrhs, double* stat) {
   extern __shared__ double sm[];
   const int ld = n | 1;
@@ -856,6 +859,7 @@ __global__ __launch_bounds__(1024) void k_lu_solve_lds(const double* Ag, int n, 
   __shared__ double s_amax, s_minpiv;
   __shared__ int s_bad;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   for (int t = tid; t < n * n; t += blockDim.x) A[(t % n) + (t / n) * ld] = Ag[t];
   for (int t = tid; t < n * nrhs; t += blockDim.x) B[(t % n) + (t / n) * ld] = Bg[t];
   for (int t = tid; t < n; t += blockDim.x) done[t] = 0;
@@ -869,38 +873,55 @@ __global__ __launch_bounds__(1024) void k_lu_solve_lds(const double* Ag, int n, 
   __syncthreads();
   const double amax = s_amax;
   for (int k = 0; k < n; ++k) {
-    if (tid < 64) {
+    if (wave == 0) {
+      // argmax of |A(i, k)| over rows not yet chosen; ties go to the lowest row index
       double best = -1.0;
       int brow = n;
-      for (int i = tid; i < n; i += 64) {
+      for (int i = lane; i < n; i += 64) {
         if (done[i]) continue;
         const double v = fabs(A[i + k * ld]);
-        if (v > best || (v == best && i < brow)) { best = v; brow = i; }
+        if (v > best) { best = v; brow = i; }   // rows visited in increasing order: first maximum kept
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o);
-        const int orow = __shfl_xor(brow, o);
-        if (ob > best || (ob == best && orow < brow)) { best = ob; brow = orow; }
+      double m = best;
+      for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+      const unsigned long long tie = __ballot(best == m);
+      int row;
+      if (__popcll(tie) == 1) {
+        row = __shfl(brow, __ffsll((long long)tie) - 1);
+      } else {
+        int r = best == m ? brow : n;
+        for (int o = 32; o > 0; o >>= 1) r = min(r, __shfl_xor(r, o));
+        row = r;
       }
-      if (tid == 0) {
-        prow[k] = brow;
-        done[brow] = 1;
-        if (!(best > 1e-14 * amax)) s_bad = 1;
-        s_minpiv = fmin(s_minpiv, best);
+      if (lane == 0) {
+        const bool ok = row < n && m > 1e-14 * amax;   // no candidate (NaN column) or a tiny pivot
+        prow[k] = ok ? row : 0;
+        if (ok) done[row] = 1;
+        else s_bad = 1;
+        s_minpiv = fmin(s_minpiv, m);
       }
     }
     lds_barrier();
     if (s_bad) break;
     const int p = prow[k];
     const double inv = 1.0 / A[p + k * ld];
-    // rows not yet chosen, columns k+1.. of A and all of B: x(i) -= (A(i,k) / A(p,k)) x(p)
+    // rows not yet chosen (lanes, up to three per lane), columns k+1.. of A and all of B (waves):
+    // x(i) -= (A(i,k) / A(p,k)) x(p)
+    double l[3];
+    bool act[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int i = lane + 64 * q;
+      act[q] = i < n && !done[i];
+      l[q] = act[q] ? A[i + k * ld] * inv : 0.0;
+    }
     const int cols = n - k - 1 + nrhs;
-    for (int t = tid; t < n * cols; t += blockDim.x) {
-      const int i = t % n, c = t / n;
-      if (done[i]) continue;
-      const double l = A[i + k * ld] * inv;
+    for (int c = wave; c < cols; c += 16) {
       double* col = c < n - k - 1 ? A + (k + 1 + c) * ld : B + (c - (n - k - 1)) * ld;
-      col[i] -= l * col[p];
+      const double xp = col[p];
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        if (act[q]) col[lane + 64 * q] -= l[q] * xp;
     }
     lds_barrier();
   }
@@ -910,17 +931,40 @@ __global__ __launch_bounds__(1024) void k_lu_solve_lds(const double* Ag, int n, 
     return;
   }
   // back substitution over the pivot order: x_k = b(p_k) / A(p_k, k); b(p_i) -= A(p_i, k) x_k for i < k
-  for (int k = n - 1; k >= 0; --k) {
-    const int p = prow[k];
-    const double ukk = A[p + k * ld];
-    if (tid < nrhs) B[p + tid * ld] /= ukk;
-    lds_barrier();
-    for (int t = tid; t < k * nrhs; t += blockDim.x) {
-      const int i = t % k, r = t / k;
-      const int pi = prow[i];
-      B[pi + r * ld] -= A[pi + k * ld] * B[p + r * ld];
+  if (nrhs <= kLuWaveRhs) {
+    // one wave, lanes over the pivot order positions i (up to three each): no barriers
+    if (wave == 0) {
+      int pr[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) pr[q] = lane + 64 * q < n ? prow[lane + 64 * q] : 0;
+      for (int k = n - 1; k >= 0; --k) {
+        const int p = prow[k];
+        const double rukk = 1.0 / A[p + k * ld];
+        for (int r = 0; r < nrhs; ++r) {
+          const double xk = B[p + r * ld] * rukk;   // b(p_k) is final: every later step has been applied
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            const int i = lane + 64 * q;
+            if (i < k) B[pr[q] + r * ld] -= A[pr[q] + k * ld] * xk;
+          }
+          if (lane == 0) B[p + r * ld] = xk;
+        }
+      }
     }
-    lds_barrier();
+    __syncthreads();
+  } else {
+    for (int k = n - 1; k >= 0; --k) {
+      const int p = prow[k];
+      const double ukk = A[p + k * ld];
+      for (int r = tid; r < nrhs; r += blockDim.x) B[p + r * ld] /= ukk;
+      lds_barrier();
+      for (int t = tid; t < k * nrhs; t += blockDim.x) {
+        const int i = t % k, r = t / k;
+        const int pi = prow[i];
+        B[pi + r * ld] -= A[pi + k * ld] * B[p + r * ld];
+      }
+      lds_barrier();
+    }
   }
   for (int t = tid; t < n * nrhs; t += blockDim.x) {
     const int k = t % n, r = t / n;
@@ -936,7 +980,7 @@ static size_t lu_lds_bytes(int n, int nrhs) {
 
 int lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s) {
   if (n <= 0) return RW_OK;
-  if (nrhs <= 1024 && lu_lds_bytes(n, nrhs) <= kLdsLimit) {
+  if (n <= kLuLdsMaxRows && lu_lds_bytes(n, nrhs) <= kLdsLimit) {
     static bool attr = false;
     if (!attr) {
       RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_solve_lds),

@@ -136,7 +136,7 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool ne
     RW_HIP(hipMemcpyAsync(&e, w.tmp, sizeof(double), hipMemcpyDeviceToHost, c.s));
     RW_HIP(hipStreamSynchronize(c.s));
     if (e < 1e-4) {
-      RW_TRY(gemm_tn(RW_F64, w.G2, nb, w.G2, nb, w.V, nb, nb, nb, nb, 0.0, c.s));   // E^2 (E symmetric)
+      RW_TRY(gram(RW_F64, w.G2, nb, w.G2, nb, nb, nb, nb, w.V, w.partial, c.s, true));   // E^2 = E^T E (E symmetric)
       k_series_w<<<nblocks(n2, 256), 256, 0, c.s>>>(w.G2, w.V, w.W, nb);
       RW_LAUNCH_CHECK();
       have_w = true;
@@ -158,14 +158,17 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool ne
   RW_TRY(stencil_apply(g, F, LF, nullptr, nb, 1.0, 0.0, 0.0, c.s));
   c.spmm_cols += nb;
   RW_TRY(gram(c.dt, F, c.N, LF, c.N, c.N, nb, nb, w.H, w.partial, c.s, true));
-  RW_TRY(gemm_tn(RW_F64, w.H, nb, w.W, nb, w.T, nb, nb, nb, nb, 0.0, c.s));       // T = H W
+  RW_TRY(gram(RW_F64, w.H, nb, w.W, nb, nb, nb, nb, w.T, w.partial, c.s));         // T = H^T W = H W
   RW_TRY(gram(RW_F64, w.W, nb, w.T, nb, nb, nb, nb, w.Hp, w.partial, c.s));        // Hp = W^T H W
   k_symmetrize<<<nblocks((int64_t)nb * nb, 256), 256, 0, c.s>>>(w.Hp, nb);
   RW_LAUNCH_CHECK();
   // with an FP32 or BF16 basis the projected matrix carries errors near 1e-7 relative, so rotations
   // below 1e-10 relative change nothing that the rotated basis can represent
   RW_TRY(syev_batched(w.Hp, w.theta, w.Z, nullptr, 0, nb, 1, w.syw, c.s, c.dt == RW_F64 ? 0.0 : 1e-10));
-  RW_TRY(gemm_tn(RW_F64, w.W, nb, w.Z, nb, w.WZ, nb, nb, nb, nb, 0.0, c.s));      // WZ = W Z
+  if (have_w)   // the series W is symmetric: W Z = W^T Z on the matrix cores
+    RW_TRY(gram(RW_F64, w.W, nb, w.Z, nb, nb, nb, nb, w.WZ, w.partial, c.s));
+  else
+    RW_TRY(gemm_tn(RW_F64, w.W, nb, w.Z, nb, w.WZ, nb, nb, nb, nb, 0.0, c.s));    // WZ = W Z
   RW_TRY(gemm_tn(c.dt, F, c.N, w.WZ, nb, X, c.N, c.N, nb, nb, 0.0, c.s));        // X = F W Z
   RW_TRY(gemm_tn(c.dt, LF, c.N, w.WZ, nb, LX, c.N, c.N, nb, nb, 0.0, c.s));      // op X
   RW_TRY(residual_norms(c.dt, LX, X, w.theta, c.N, nb, c.N, w.res, w.partial, c.s));
