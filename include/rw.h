@@ -362,6 +362,18 @@ int rw_dense_syev_workspace_bytes(int n, int count, size_t* bytes);
 int rw_dense_syev(const double* A, double* w, double* V, int n, int count, void* work, size_t work_bytes,
                   hipStream_t stream);
 
+/* Symmetric eigendecomposition of one matrix A (device, n x n column-major, read only; only the
+ * symmetric part is used) through its tridiagonal form: Householder reduction A = U T U^T (Golub & Van
+ * Loan Sec. 8.3.1), eigenvalues of T by bisection on Sturm counts (Sec. 8.4.1), eigenvectors of T by
+ * inverse iteration, V = U Z.  w (device, n, ascending) and V (device, n x n, eigenvectors as columns).
+ * 3 <= n <= 199.  Inverse iteration needs separated eigenvalues: when two are closer than 1e-6 of the
+ * largest Gershgorin row sum it returns RW_ENOCONV (w holds the eigenvalues; V is not reliable) and the
+ * Jacobi routine above should be used.  work: device buffer of rw_dense_syev_tridiag_workspace_bytes.
+ * Synchronizes `stream`.  Errors: RW_EINVAL, RW_EWORKSPACE, RW_ENOCONV. */
+int rw_dense_syev_tridiag_workspace_bytes(int n, size_t* bytes);
+int rw_dense_syev_tridiag(const double* A, double* w, double* V, int n, void* work, size_t work_bytes,
+                          hipStream_t stream);
+
 /* Solve A X = B by LU with partial pivoting (device, A n x n and B n x nrhs column-major, both
  * overwritten; X returned in B).  stat (device, 1 double) = min |pivot| / max |a_ij|, or 0 when a pivot
  * falls below 1e-14 max |a_ij| (B is then not a solution). */

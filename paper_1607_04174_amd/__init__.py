@@ -106,6 +106,9 @@ _SIGS = {
     "rw_dense_syev_workspace_bytes": (ct.c_int, [ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]),
     "rw_dense_syev": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_size_t,
                                  ct.c_void_p]),
+    "rw_dense_syev_tridiag_workspace_bytes": (ct.c_int, [ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_dense_syev_tridiag": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_size_t,
+                                         ct.c_void_p]),
     "rw_dense_lu_solve": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p]),
     "rw_cg_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_size_t)]),
     "rw_convert_block": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_int64, ct.c_int, ct.c_void_p]),
@@ -418,6 +421,21 @@ def dense_syev(A: torch.Tensor, vectors: bool = True):
     _check(lib().rw_dense_syev_workspace_bytes(n, count, ct.byref(nb)))
     work = _workspace(nb.value, A.device)
     _check(lib().rw_dense_syev(_ptr(A), _ptr(w), _ptr(V), n, count, _ptr(work), nb.value, _stream(A.device)))
+    return w, V
+
+
+def dense_syev_tridiag(A: torch.Tensor):
+    """Eigenpairs of one symmetric FP64 matrix A (n, n) (read as column-major) through its tridiagonal form
+    (3 <= n <= 199).  Returns (w (n,), V (n, n) with V[j] the j-th eigenvector).  Raises RWError with
+    RW_ENOCONV when eigenvalues are too close for inverse iteration."""
+    A = A.contiguous()
+    n = A.shape[0]
+    w = torch.empty(n, dtype=torch.float64, device=A.device)
+    V = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    nb = ct.c_size_t()
+    _check(lib().rw_dense_syev_tridiag_workspace_bytes(n, ct.byref(nb)))
+    work = _workspace(nb.value, A.device)
+    _check(lib().rw_dense_syev_tridiag(_ptr(A), _ptr(w), _ptr(V), n, _ptr(work), nb.value, _stream(A.device)))
     return w, V
 
 

@@ -38,7 +38,7 @@ static size_t eig_layout(const Graph* g, int nb, void* base, EigWork* w) {
   t.G = c.take<double>(n2); t.V = c.take<double>(n2); t.W = c.take<double>(n2); t.H = c.take<double>(n2);
   t.T = c.take<double>(n2); t.Hp = c.take<double>(n2); t.Z = c.take<double>(n2); t.WZ = c.take<double>(n2);
   t.G2 = c.take<double>(n2);
-  t.syw = c.take<double>(syev_work_count(nb, 1, true, 0));
+  t.syw = c.take<double>(std::max(syev_work_count(nb, 1, true, 0), tridiag_fits(nb) ? tridiag_work_count(nb) : 0));
   t.s = c.take<double>(nb); t.theta = c.take<double>(nb); t.res = c.take<double>(nb);
   t.tmp = c.take<double>(std::max(nb, 16));
   size_t pc = std::max({gram_partial_count(g->N, nb, nb), norm_partial_count(nb), gram_partial_count(g->N, 1, nb)});
@@ -162,9 +162,16 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool ne
   RW_TRY(gram(RW_F64, w.W, nb, w.T, nb, nb, nb, nb, w.Hp, w.partial, c.s));        // Hp = W^T H W
   k_symmetrize<<<nblocks((int64_t)nb * nb, 256), 256, 0, c.s>>>(w.Hp, nb);
   RW_LAUNCH_CHECK();
-  // with an FP32 or BF16 basis the projected matrix carries errors near 1e-7 relative, so rotations
-  // below 1e-10 relative change nothing that the rotated basis can represent
-  RW_TRY(syev_batched(w.Hp, w.theta, w.Z, nullptr, 0, nb, 1, w.syw, c.s, c.dt == RW_F64 ? 0.0 : 1e-10));
+  // with an FP32 or BF16 basis the projected matrix carries errors near 1e-7 relative: the tridiagonal
+  // solver (Householder, bisection, inverse iteration) serves when its eigenvalues are separated, else
+  // Jacobi, whose rotations below 1e-10 relative change nothing the rotated basis can represent
+  int est = RW_ENOCONV;
+  if (c.dt != RW_F64 && tridiag_fits(nb)) {
+    est = syev_tridiag(w.Hp, w.theta, w.Z, nb, w.syw, c.s);
+    if (est != RW_OK && est != RW_ENOCONV) return est;
+  }
+  if (est == RW_ENOCONV)
+    RW_TRY(syev_batched(w.Hp, w.theta, w.Z, nullptr, 0, nb, 1, w.syw, c.s, c.dt == RW_F64 ? 0.0 : 1e-10));
   if (have_w)   // the series W is symmetric: W Z = W^T Z on the matrix cores
     RW_TRY(gram(RW_F64, w.W, nb, w.Z, nb, nb, nb, nb, w.WZ, w.partial, c.s));
   else

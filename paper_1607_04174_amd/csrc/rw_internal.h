@@ -227,6 +227,11 @@ int chol_inverse(double* G, double* W, int n, int* info, hipStream_t s);
 int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int n, int count, double* work,
                  hipStream_t s, double min_rel_tol = 0.0);
 size_t syev_work_count(int n, int count, bool vectors, int nrhs);
+// Symmetric eigendecomposition of one matrix (3 <= n <= 199) through its tridiagonal form; returns
+// RW_ENOCONV without an error message when eigenvalues are too close for inverse iteration.
+bool tridiag_fits(int n);
+size_t tridiag_work_count(int n);
+int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hipStream_t s);
 // Solve A X = B by LU with partial pivoting (A: n x n, B: n x nrhs, both destroyed/overwritten;
 // X returned in B).  stat[0] = min |pivot| / max |a_ij| (0 if a pivot is below the threshold).
 int lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s);

@@ -1,0 +1,338 @@
+// Symmetric eigendecomposition through a tridiagonal form, for one matrix of order n <= 199:
+//   1. Householder reduction A = U T U^T (Golub & Van Loan Sec. 8.3.1) in one workgroup with the
+//      packed lower triangle in LDS: per column, one wave forms the reflector, 4 lanes per row form
+//      p = tau A22 v, every wave forms K = tau/2 p^T v, and all threads apply the rank-2 update
+//      A22 -= v w^T + w v^T with w = p - K v;
+//   2. eigenvalues of T by bisection on Sturm counts (Sec. 8.4.1), 64 points per step, one wave per
+//      eigenvalue (the interval shrinks 65-fold per step);
+//   3. eigenvectors of T by inverse iteration with the LDL^T factorization of T - lambda I (one lane
+//      per eigenvector, three solves);
+//   4. V = U Z, the reflectors applied to each eigenvector column (one wave per column).
+// Inverse iteration gives orthogonal vectors only when eigenvalues are separated: the driver reports
+// RW_ENOCONV when two eigenvalues are closer than 1e-6 |T|, and the caller then uses the Jacobi solver.
+// All arithmetic is FP64.
+#include <cmath>
+
+#include "rw_internal.h"
+
+namespace rw {
+
+__device__ __forceinline__ int tr_lo(int i, int j, int n) { return j * n - ((j * (j - 1)) >> 1) + (i - j); }  // i >= j
+
+static size_t tridiag_lds_bytes(int n) { return ((size_t)n * (n + 1) / 2 + 2 * (size_t)n) * sizeof(double); }
+
+bool tridiag_fits(int n) { return n >= 3 && n <= 256 && tridiag_lds_bytes(n) <= kLdsLimit; }   // n <= 199
+
+// work (doubles): reflectors n x n (reflector k in column k, entries 0..n-k-2, first entry 1), tau n, d n,
+// e n, lambda n, Z n x n (Z(j, i) = entry j of eigenvector i at j * n + i), LDL^T scratch 2 n x n, flag
+size_t tridiag_work_count(int n) { return (size_t)n * n * 4 + (size_t)n * 6 + 8; }
+
+struct TriBufs {
+  double *refl, *tau, *d, *e, *lam, *Z, *Lf, *Df, *flag;
+};
+
+static TriBufs tri_bufs(double* work, int n) {
+  TriBufs b;
+  const size_t nn = (size_t)n * n;
+  b.refl = work;
+  b.tau = b.refl + nn;
+  b.d = b.tau + n;
+  b.e = b.d + n;
+  b.lam = b.e + n;
+  b.Z = b.lam + n;
+  b.Lf = b.Z + nn;
+  b.Df = b.Lf + nn;
+  b.flag = b.Df + nn;
+  return b;
+}
+
+__device__ __forceinline__ double tr_wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// 1. Householder tridiagonalization (lower): reflector k maps A(k+1:n, k) to beta e1
+__global__ __launch_bounds__(1024) void k_tridiag(const double* A, int n, double* refl, double* tau, double* d,
+                                                  double* e) {
+  extern __shared__ double sA[];   // packed lower triangle, column-major
+  double* v = sA + n * (n + 1) / 2;
+  double* p = v + n;
+  __shared__ double s_tau[2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int t = tid; t < n * n; t += blockDim.x) {
+    const int i = t % n, j = t / n;
+    if (i >= j) sA[tr_lo(i, j, n)] = 0.5 * (A[t] + A[j + (int64_t)i * n]);
+  }
+  __syncthreads();
+  for (int k = 0; k < n - 2; ++k) {
+    const int m = n - k - 1;   // length of the column below the diagonal
+    if (wave == 0) {
+      double xs[4];
+      double ss = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = lane + 64 * q;
+        xs[q] = i < m ? sA[tr_lo(k + 1 + i, k, n)] : 0.0;
+        if (i >= 1) ss += xs[q] * xs[q];
+      }
+      ss = tr_wave_sum(ss);
+      const double x0 = __shfl(xs[0], 0);
+      double beta, tk, scale;
+      if (ss == 0.0) {   // already reduced: no reflection
+        tk = 0.0;
+        beta = x0;
+        scale = 0.0;
+      } else {
+        const double nrm = sqrt(x0 * x0 + ss);
+        beta = x0 >= 0.0 ? -nrm : nrm;
+        tk = (beta - x0) / beta;
+        scale = 1.0 / (x0 - beta);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = lane + 64 * q;
+        if (i < m) {
+          const double vi = i == 0 ? 1.0 : xs[q] * scale;
+          v[i] = vi;
+          refl[(int64_t)k * n + i] = vi;
+        }
+      }
+      if (lane == 0) {
+        s_tau[k & 1] = tk;
+        tau[k] = tk;
+        e[k] = beta;
+        d[k] = sA[tr_lo(k, k, n)];
+      }
+    }
+    lds_barrier();
+    const double tk = s_tau[k & 1];
+    if (tk == 0.0) continue;   // uniform
+    // p = tk A22 v, four lanes per row (A22 = A(k+1:n, k+1:n), symmetric, lower stored)
+    {
+      const int r = tid >> 2, sub = tid & 3;
+      double acc = 0.0;
+      if (r < m) {
+        for (int j = sub; j < m; j += 4) {
+          const double a = r >= j ? sA[tr_lo(k + 1 + r, k + 1 + j, n)] : sA[tr_lo(k + 1 + j, k + 1 + r, n)];
+          acc += a * v[j];
+        }
+      }
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      if (sub == 0 && r < m) p[r] = tk * acc;
+    }
+    lds_barrier();
+    // K = tk / 2 p^T v (every wave), then A22 -= v w^T + w v^T with w = p - K v
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = lane + 64 * q;
+      if (i < m) s += p[i] * v[i];
+    }
+    const double K = 0.5 * tk * tr_wave_sum(s);
+    const int tx = tid & 31, ty = tid >> 5;
+    for (int jj = ty; jj < m; jj += 32) {
+      const double vj = v[jj], wj = p[jj] - K * vj;
+      for (int ii = jj + tx; ii < m; ii += 32) {
+        const double vi = v[ii], wi = p[ii] - K * vi;
+        sA[tr_lo(k + 1 + ii, k + 1 + jj, n)] -= vi * wj + wi * vj;
+      }
+    }
+    lds_barrier();
+  }
+  __syncthreads();
+  if (tid == 0) {
+    d[n - 2] = sA[tr_lo(n - 2, n - 2, n)];
+    d[n - 1] = sA[tr_lo(n - 1, n - 1, n)];
+    e[n - 2] = sA[tr_lo(n - 1, n - 2, n)];
+    e[n - 1] = 0.0;
+    tau[n - 2] = 0.0;
+    tau[n - 1] = 0.0;
+  }
+}
+
+// Sturm count: the number of eigenvalues of T below sigma (the negative pivots of LDL^T of T - sigma I,
+// a pivot of magnitude below pivmin taken as -pivmin)
+__device__ __forceinline__ int tr_sturm(const double* d, const double* e2, int n, double sigma, double pivmin) {
+  double q = d[0] - sigma;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q < 0.0;
+  for (int j = 1; j < n; ++j) {
+    q = (d[j] - sigma) - e2[j - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// 2. eigenvalue idx = blockIdx.x (ascending) by 64-point bisection; flag[0] = 1 if two eigenvalues are
+// closer than 1e-6 |T| (checked by the wave of the larger one)
+__global__ __launch_bounds__(64) void k_tri_bisect(const double* dg, const double* eg, int n, double* lam,
+                                                   double* flag) {
+  __shared__ double d[256], e2[256];
+  const int idx = blockIdx.x, lane = threadIdx.x;
+  double lo = INFINITY, hi = -INFINITY, tn = 0.0, emax = 0.0;
+  for (int j = lane; j < n; j += 64) {
+    d[j] = dg[j];
+    const double el = j > 0 ? fabs(eg[j - 1]) : 0.0, er = j < n - 1 ? fabs(eg[j]) : 0.0;
+    if (j < n - 1) e2[j] = eg[j] * eg[j];
+    lo = fmin(lo, dg[j] - el - er);
+    hi = fmax(hi, dg[j] + el + er);
+    tn = fmax(tn, fabs(dg[j]) + el + er);
+    emax = fmax(emax, er * er);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o));
+    hi = fmax(hi, __shfl_xor(hi, o));
+    tn = fmax(tn, __shfl_xor(tn, o));
+    emax = fmax(emax, __shfl_xor(emax, o));
+  }
+  __syncthreads();
+  const double pivmin = 2.3e-308 * fmax(1.0, emax);
+  const double atol = 4.0 * 2.3e-16 * fmax(tn, 1e-300);
+  double a = lo - atol, b = hi + atol;   // count(a) <= idx < count(b)
+  for (int it = 0; it < 16 && b - a > atol; ++it) {   // a, b identical in every lane
+    const double sigma = a + (b - a) * (double)(lane + 1) / 65.0;
+    const int cnt = tr_sturm(d, e2, n, sigma, pivmin);
+    const unsigned long long le = __ballot(cnt <= idx);   // counts grow with sigma: lanes 0..L-1
+    const int L = __popcll(le);
+    const double na = L > 0 ? a + (b - a) * (double)L / 65.0 : a;
+    const double nb = L < 64 ? a + (b - a) * (double)(L + 1) / 65.0 : b;
+    a = na;
+    b = nb;
+  }
+  const double lam_i = 0.5 * (a + b);
+  if (lane == 0) lam[idx] = lam_i;
+  // separation from the next eigenvalue, measured from this wave's own side: the next eigenvalue lies
+  // above b - atol; a count at lam_i + 1e-6 |T| that exceeds idx + 1 means another eigenvalue is within
+  const double probe = lam_i + 1e-6 * tn;
+  const int c2 = lane == 0 ? tr_sturm(d, e2, n, probe, pivmin) : 0;
+  if (lane == 0 && idx + 1 < n && c2 > idx + 1) flag[0] = 1.0;
+}
+
+// 3. inverse iteration: eigenvector i = global thread index, three solves with LDL^T of T - lambda_i I
+// (pivots of magnitude below pivmin replaced by pivmin with their sign); Z(j, i) at j * n + i
+__global__ __launch_bounds__(64) void k_tri_invit(const double* d, const double* e, int n, const double* lam,
+                                                  double* Z, double* Lf, double* Df) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
+  double tn = 0.0;
+  for (int j = 0; j < n; ++j) tn = fmax(tn, fabs(d[j]) + (j > 0 ? fabs(e[j - 1]) : 0.0) + (j < n - 1 ? fabs(e[j]) : 0.0));
+  const double pivmin = 2.3e-16 * fmax(tn, 1e-300);
+  const double l = lam[i];
+  // factor: D_0 = d_0 - l, L_j = e_{j-1} / D_{j-1}, D_j = d_j - l - L_j e_{j-1}
+  double D = d[0] - l;
+  if (fabs(D) < pivmin) D = D < 0.0 ? -pivmin : pivmin;
+  Df[i] = D;
+  for (int j = 1; j < n; ++j) {
+    const double Lj = e[j - 1] / D;
+    D = (d[j] - l) - Lj * e[j - 1];
+    if (fabs(D) < pivmin) D = D < 0.0 ? -pivmin : pivmin;
+    Lf[(int64_t)j * n + i] = Lj;
+    Df[(int64_t)j * n + i] = D;
+  }
+  // start vector: deterministic, with no special structure
+  for (int j = 0; j < n; ++j) Z[(int64_t)j * n + i] = 1.0 + 0.5 * sin(0.7 * j + 1.3 * i + 0.1);
+  for (int it = 0; it < 3; ++it) {
+    // forward: y_j = b_j - L_j y_{j-1}; then z = y / D; backward: x_j = z_j - L_{j+1} x_{j+1}
+    double y = Z[i];
+    Z[i] = y;
+    for (int j = 1; j < n; ++j) {
+      y = Z[(int64_t)j * n + i] - Lf[(int64_t)j * n + i] * y;
+      Z[(int64_t)j * n + i] = y;
+    }
+    double x = Z[(int64_t)(n - 1) * n + i] / Df[(int64_t)(n - 1) * n + i];
+    Z[(int64_t)(n - 1) * n + i] = x;
+    double nrm = x * x;
+    for (int j = n - 2; j >= 0; --j) {
+      x = Z[(int64_t)j * n + i] / Df[(int64_t)j * n + i] - Lf[(int64_t)(j + 1) * n + i] * x;
+      Z[(int64_t)j * n + i] = x;
+      nrm += x * x;
+    }
+    const double inv = 1.0 / sqrt(nrm);
+    for (int j = 0; j < n; ++j) Z[(int64_t)j * n + i] *= inv;
+  }
+}
+
+// 4. V(:, col) = H_0 H_1 ... H_{n-3} z, z = eigenvector col of T; V column-major n x n
+__global__ __launch_bounds__(64) void k_tri_back(const double* refl, const double* tau, int n, const double* Z,
+                                                 double* V) {
+  const int col = blockIdx.x, lane = threadIdx.x;
+  double z[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = lane + 64 * q;
+    z[q] = r < n ? Z[(int64_t)r * n + col] : 0.0;
+  }
+  for (int k = n - 3; k >= 0; --k) {
+    const double tk = tau[k];
+    if (tk == 0.0) continue;
+    const double* vk = refl + (int64_t)k * n;
+    const int m = n - k - 1;
+    double vr[4];
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = lane + 64 * q - (k + 1);
+      vr[q] = (i >= 0 && i < m) ? vk[i] : 0.0;
+      s += vr[q] * z[q];
+    }
+    s = tr_wave_sum(s) * tk;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) z[q] -= s * vr[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = lane + 64 * q;
+    if (r < n) V[r + (int64_t)col * n] = z[q];
+  }
+}
+
+__global__ void k_tri_clear(double* flag) { flag[0] = 0.0; }
+
+int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hipStream_t s) {
+  RW_CHECK(tridiag_fits(n), RW_EINVAL, "tridiagonal eigensolver: n = %d out of range", n);
+  const TriBufs b = tri_bufs(work, n);
+  static bool attr = false;
+  if (!attr) {
+    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_tridiag), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kLdsLimit));
+    attr = true;
+  }
+  k_tri_clear<<<1, 1, 0, s>>>(b.flag);
+  k_tridiag<<<1, 1024, tridiag_lds_bytes(n), s>>>(A, n, b.refl, b.tau, b.d, b.e);
+  k_tri_bisect<<<n, 64, 0, s>>>(b.d, b.e, n, b.lam, b.flag);
+  k_tri_invit<<<(n + 63) / 64, 64, 0, s>>>(b.d, b.e, n, b.lam, b.Z, b.Lf, b.Df);
+  k_tri_back<<<n, 64, 0, s>>>(b.refl, b.tau, n, b.Z, V);
+  RW_LAUNCH_CHECK();
+  double flag = 0.0;
+  RW_HIP(hipMemcpyAsync(&flag, b.flag, sizeof(double), hipMemcpyDeviceToHost, s));
+  RW_HIP(hipMemcpyAsync(w, b.lam, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  RW_HIP(hipStreamSynchronize(s));
+  if (flag != 0.0) return RW_ENOCONV;   // clustered eigenvalues: the caller uses the Jacobi solver
+  return RW_OK;
+}
+
+}  // namespace rw
+
+using namespace rw;
+
+extern "C" {
+
+int rw_dense_syev_tridiag_workspace_bytes(int n, size_t* bytes) {
+  RW_CHECK(bytes != nullptr && tridiag_fits(n), RW_EINVAL, "bad size n = %d", n);
+  *bytes = tridiag_work_count(n) * sizeof(double);
+  return RW_OK;
+}
+
+int rw_dense_syev_tridiag(const double* A, double* w, double* V, int n, void* work, size_t work_bytes,
+                          hipStream_t stream) {
+  RW_CHECK(A != nullptr && w != nullptr && V != nullptr && work != nullptr, RW_EINVAL, "null argument");
+  RW_CHECK(tridiag_fits(n), RW_EINVAL, "tridiagonal eigensolver: n = %d out of range [3, 199]", n);
+  RW_CHECK(work_bytes >= tridiag_work_count(n) * sizeof(double), RW_EWORKSPACE, "workspace too small");
+  const int st = syev_tridiag(A, w, V, n, static_cast<double*>(work), stream);
+  if (st == RW_ENOCONV) set_error("tridiagonal eigensolver: clustered eigenvalues (use the Jacobi routine)");
+  return st;
+}
+
+}  // extern "C"

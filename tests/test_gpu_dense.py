@@ -36,6 +36,35 @@ def test_syev_matches_numpy(n, count):
         assert np.abs(Vb.T @ Vb - np.eye(n)).max() < 1e-12 * max(1, n / 50)
 
 
+@pytest.mark.parametrize("n", [3, 10, 64, 150, 199])
+def test_syev_tridiag_matches_numpy(n):
+    """Householder + bisection + inverse iteration on matrices with separated eigenvalues (a random
+    symmetric matrix, and a Rayleigh-Ritz-like one: a positive spectrum of width 1e-2 rotated by a random
+    orthogonal matrix), against numpy; a clustered spectrum is refused."""
+    need_gpu()
+    banner(f"syev tridiag n={n}")
+    rng = np.random.default_rng(100 + n)
+    X = rng.standard_normal((n, n))
+    Qm, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev_rr = np.sort(1.4e-3 + 1.1e-2 * rng.random(n))
+    for A in (X + X.T, (Qm * ev_rr) @ Qm.T):
+        A = 0.5 * (A + A.T)
+        ev = np.linalg.eigvalsh(A)
+        if np.min(np.diff(ev)) < 1e-6 * np.abs(ev).max() * 4:
+            continue                                   # the random draw happened to cluster: not this test
+        w, V = rw.dense_syev_tridiag(to_dev(A.T, torch.float64))
+        w, V = w.cpu().numpy(), V.cpu().numpy().T      # columns = eigenvectors
+        scale = np.abs(ev).max()
+        np.testing.assert_allclose(w, ev, atol=1e-13 * scale * max(1, n / 20))
+        assert np.abs(A @ V - V * w).max() < 1e-12 * scale * max(1, n / 20)
+        assert np.abs(V.T @ V - np.eye(n)).max() < 1e-11 * max(1, n / 50)
+    if n >= 10:
+        ev = np.concatenate([np.full(3, 0.5), np.linspace(1.0, 2.0, n - 3)])
+        A = (Qm * ev) @ Qm.T
+        with pytest.raises(rw.RWError):
+            rw.dense_syev_tridiag(to_dev(0.5 * (A + A.T).T, torch.float64))
+
+
 @pytest.mark.parametrize("n,nrhs", [(1, 1), (50, 3), (201, 4)])
 def test_lu_solve_matches_numpy(n, nrhs):
     need_gpu()
