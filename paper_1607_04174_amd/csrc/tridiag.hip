@@ -6,7 +6,7 @@
 //   2. eigenvalues of T by bisection on Sturm counts (Sec. 8.4.1), 64 points per step, one wave per
 //      eigenvalue (the interval shrinks 65-fold per step);
 //   3. eigenvectors of T by inverse iteration with the LDL^T factorization of T - lambda I (one lane
-//      per eigenvector, three solves);
+//      per eigenvector, three solves, in LDS);
 //   4. V = U Z, the reflectors applied to each eigenvector column (one wave per column).
 // Inverse iteration gives orthogonal vectors only when eigenvalues are separated: the driver reports
 // RW_ENOCONV when two eigenvalues are closer than 1e-6 |T|, and the caller then uses the Jacobi solver.
@@ -21,7 +21,10 @@ __device__ __forceinline__ int tr_lo(int i, int j, int n) { return j * n - ((j *
 
 static size_t tridiag_lds_bytes(int n) { return ((size_t)n * (n + 1) / 2 + 2 * (size_t)n) * sizeof(double); }
 
-bool tridiag_fits(int n) { return n >= 3 && n <= 256 && tridiag_lds_bytes(n) <= kLdsLimit; }   // n <= 199
+static size_t invit_lds_bytes(int n);
+bool tridiag_fits(int n) {   // n <= 199
+  return n >= 3 && n <= 256 && tridiag_lds_bytes(n) <= kLdsLimit && invit_lds_bytes(n) <= kLdsLimit;
+}
 
 // work (doubles): reflectors n x n (reflector k in column k, entries 0..n-k-2, first entry 1), tau n, d n,
 // e n, lambda n, Z n x n (Z(j, i) = entry j of eigenvector i at j * n + i), LDL^T scratch 2 n x n, flag
@@ -112,10 +115,18 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int n, double
       const int r = tid >> 2, sub = tid & 3;
       double acc = 0.0;
       if (r < m) {
-        for (int j = sub; j < m; j += 4) {
-          const double a = r >= j ? sA[tr_lo(k + 1 + r, k + 1 + j, n)] : sA[tr_lo(k + 1 + j, k + 1 + r, n)];
-          acc += a * v[j];
+        const int R = k + 1 + r;
+        int j = sub;
+        // j <= r: row R of the lower triangle, A(R, C) with C = k + 1 + j; the packed address advances by
+        // colstart(C + 4) - colstart(C) - 4 = 4 n - 4 C - 10
+        int C = k + 1 + j, addr = tr_lo(R, C, n);
+        for (; j <= r; j += 4, C += 4) {
+          acc += sA[addr] * v[j];
+          addr += 4 * n - 4 * C - 10;
         }
+        // j > r: column R, A(C, R), consecutive in C
+        addr = tr_lo(k + 1 + j, R, n);
+        for (; j < m; j += 4, addr += 4) acc += sA[addr] * v[j];
       }
       acc += __shfl_xor(acc, 1);
       acc += __shfl_xor(acc, 2);
@@ -133,9 +144,10 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int n, double
     const int tx = tid & 31, ty = tid >> 5;
     for (int jj = ty; jj < m; jj += 32) {
       const double vj = v[jj], wj = p[jj] - K * vj;
-      for (int ii = jj + tx; ii < m; ii += 32) {
+      int addr = tr_lo(k + 1 + jj + tx, k + 1 + jj, n);
+      for (int ii = jj + tx; ii < m; ii += 32, addr += 32) {
         const double vi = v[ii], wi = p[ii] - K * vi;
-        sA[tr_lo(k + 1 + ii, k + 1 + jj, n)] -= vi * wj + wi * vj;
+        sA[addr] -= vi * wj + wi * vj;
       }
     }
     lds_barrier();
@@ -211,47 +223,66 @@ __global__ __launch_bounds__(64) void k_tri_bisect(const double* dg, const doubl
 }
 
 // 3. inverse iteration: eigenvector i = global thread index, three solves with LDL^T of T - lambda_i I
-// (pivots of magnitude below pivmin replaced by pivmin with their sign); Z(j, i) at j * n + i
-__global__ __launch_bounds__(64) void k_tri_invit(const double* d, const double* e, int n, const double* lam,
-                                                  double* Z, double* Lf, double* Df) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  if (i >= n) return;
+// (pivots of magnitude below pivmin replaced by pivmin with their sign).  A workgroup of 32 threads keeps
+// T, its threads' factors (L_j and 1 / D_j) and iterates in LDS, entry j of thread t at j * 32 + t;
+// Z(j, i) is written at j * n + i.
+constexpr int kInvitThreads = 32;
+static size_t invit_lds_bytes(int n) { return ((size_t)n * (2 + 3 * kInvitThreads)) * sizeof(double); }
+
+__global__ __launch_bounds__(kInvitThreads) void k_tri_invit(const double* dg, const double* eg, int n,
+                                                             const double* lam, double* Z) {
+  extern __shared__ double sm[];
+  double* d = sm;
+  double* e = d + n;
+  double* Lf = e + n;
+  double* rD = Lf + (size_t)n * kInvitThreads;
+  double* z = rD + (size_t)n * kInvitThreads;
+  const int t = threadIdx.x, i = blockIdx.x * kInvitThreads + t;
   double tn = 0.0;
-  for (int j = 0; j < n; ++j) tn = fmax(tn, fabs(d[j]) + (j > 0 ? fabs(e[j - 1]) : 0.0) + (j < n - 1 ? fabs(e[j]) : 0.0));
+  for (int j = t; j < n; j += kInvitThreads) {
+    d[j] = dg[j];
+    e[j] = eg[j];
+    tn = fmax(tn, fabs(dg[j]) + (j > 0 ? fabs(eg[j - 1]) : 0.0) + (j < n - 1 ? fabs(eg[j]) : 0.0));
+  }
+  for (int o = kInvitThreads / 2; o > 0; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o, kInvitThreads));
+  __syncthreads();
+  if (i >= n) return;
   const double pivmin = 2.3e-16 * fmax(tn, 1e-300);
   const double l = lam[i];
   // factor: D_0 = d_0 - l, L_j = e_{j-1} / D_{j-1}, D_j = d_j - l - L_j e_{j-1}
   double D = d[0] - l;
   if (fabs(D) < pivmin) D = D < 0.0 ? -pivmin : pivmin;
-  Df[i] = D;
+  double r = 1.0 / D;
+  rD[t] = r;
   for (int j = 1; j < n; ++j) {
-    const double Lj = e[j - 1] / D;
+    const double Lj = e[j - 1] * r;
     D = (d[j] - l) - Lj * e[j - 1];
     if (fabs(D) < pivmin) D = D < 0.0 ? -pivmin : pivmin;
-    Lf[(int64_t)j * n + i] = Lj;
-    Df[(int64_t)j * n + i] = D;
+    r = 1.0 / D;
+    Lf[j * kInvitThreads + t] = Lj;
+    rD[j * kInvitThreads + t] = r;
   }
   // start vector: deterministic, with no special structure
-  for (int j = 0; j < n; ++j) Z[(int64_t)j * n + i] = 1.0 + 0.5 * sin(0.7 * j + 1.3 * i + 0.1);
+  for (int j = 0; j < n; ++j) z[j * kInvitThreads + t] = 1.0 + 0.5 * sin(0.7 * j + 1.3 * i + 0.1);
   for (int it = 0; it < 3; ++it) {
-    // forward: y_j = b_j - L_j y_{j-1}; then z = y / D; backward: x_j = z_j - L_{j+1} x_{j+1}
-    double y = Z[i];
-    Z[i] = y;
+    // forward: y_j = b_j - L_j y_{j-1}; then y / D; backward: x_j = y_j / D_j - L_{j+1} x_{j+1}
+    double y = z[t];
     for (int j = 1; j < n; ++j) {
-      y = Z[(int64_t)j * n + i] - Lf[(int64_t)j * n + i] * y;
-      Z[(int64_t)j * n + i] = y;
+      y = z[j * kInvitThreads + t] - Lf[j * kInvitThreads + t] * y;
+      z[j * kInvitThreads + t] = y;
     }
-    double x = Z[(int64_t)(n - 1) * n + i] / Df[(int64_t)(n - 1) * n + i];
-    Z[(int64_t)(n - 1) * n + i] = x;
+    double x = y * rD[(n - 1) * kInvitThreads + t];
+    z[(n - 1) * kInvitThreads + t] = x;
     double nrm = x * x;
     for (int j = n - 2; j >= 0; --j) {
-      x = Z[(int64_t)j * n + i] / Df[(int64_t)j * n + i] - Lf[(int64_t)(j + 1) * n + i] * x;
-      Z[(int64_t)j * n + i] = x;
+      x = z[j * kInvitThreads + t] * rD[j * kInvitThreads + t] - Lf[(j + 1) * kInvitThreads + t] * x;
+      z[j * kInvitThreads + t] = x;
       nrm += x * x;
     }
     const double inv = 1.0 / sqrt(nrm);
-    for (int j = 0; j < n; ++j) Z[(int64_t)j * n + i] *= inv;
+    for (int j = 0; j < n; ++j) z[j * kInvitThreads + t] *= inv;
   }
+  for (int j = 0; j < n; ++j) Z[(int64_t)j * n + i] = z[j * kInvitThreads + t];
 }
 
 // 4. V(:, col) = H_0 H_1 ... H_{n-3} z, z = eigenvector col of T; V column-major n x n
@@ -264,22 +295,33 @@ __global__ __launch_bounds__(64) void k_tri_back(const double* refl, const doubl
     const int r = lane + 64 * q;
     z[q] = r < n ? Z[(int64_t)r * n + col] : 0.0;
   }
-  for (int k = n - 3; k >= 0; --k) {
-    const double tk = tau[k];
-    if (tk == 0.0) continue;
+  // reflector k's entries for this lane's rows, loaded one step ahead
+  auto fetch = [&](int k, double (&vr)[4]) {
     const double* vk = refl + (int64_t)k * n;
     const int m = n - k - 1;
-    double vr[4];
-    double s = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = lane + 64 * q - (k + 1);
-      vr[q] = (i >= 0 && i < m) ? vk[i] : 0.0;
-      s += vr[q] * z[q];
+      vr[q] = (k >= 0 && i >= 0 && i < m) ? vk[i] : 0.0;
     }
-    s = tr_wave_sum(s) * tk;
+  };
+  double vr[4], vn[4];
+  double tk = n >= 3 ? tau[n - 3] : 0.0;
+  fetch(n - 3, vr);
+  for (int k = n - 3; k >= 0; --k) {
+    const double tnext = k > 0 ? tau[k - 1] : 0.0;
+    fetch(k - 1, vn);
+    if (tk != 0.0) {
+      double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) z[q] -= s * vr[q];
+      for (int q = 0; q < 4; ++q) s += vr[q] * z[q];
+      s = tr_wave_sum(s) * tk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) z[q] -= s * vr[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) vr[q] = vn[q];
+    tk = tnext;
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -297,12 +339,15 @@ int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hip
   if (!attr) {
     RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_tridiag), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)kLdsLimit));
+    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_tri_invit), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kLdsLimit));
     attr = true;
   }
   k_tri_clear<<<1, 1, 0, s>>>(b.flag);
   k_tridiag<<<1, 1024, tridiag_lds_bytes(n), s>>>(A, n, b.refl, b.tau, b.d, b.e);
   k_tri_bisect<<<n, 64, 0, s>>>(b.d, b.e, n, b.lam, b.flag);
-  k_tri_invit<<<(n + 63) / 64, 64, 0, s>>>(b.d, b.e, n, b.lam, b.Z, b.Lf, b.Df);
+  k_tri_invit<<<(n + kInvitThreads - 1) / kInvitThreads, kInvitThreads, invit_lds_bytes(n), s>>>(b.d, b.e, n, b.lam,
+                                                                                                b.Z);
   k_tri_back<<<n, 64, 0, s>>>(b.refl, b.tau, n, b.Z, V);
   RW_LAUNCH_CHECK();
   double flag = 0.0;
