@@ -175,7 +175,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (stencil, Q, U) + f64 (Gram, Rayleigh-Ritz, seed system)",
+        "dtype": "f32 (stencil, Q, U, Gram chunks) + f64 (Gram sums, Rayleigh-Ritz, seed system)",
         "data": "synthetic",
         "config": {"workload": "2D 512x512 8-connected phantom, beta 90, m=200, C=3, 50 seeds/label; "
                                "per step 4 solves (eps=0.1) + 3 edits with Rayleigh-Ritz updates",

@@ -1,6 +1,9 @@
 // Tall-skinny block kernels: Gram products X^T Y with FP64 accumulation (deterministic two-stage
-// reduction), block rotations X V, residual norms, conversions and the random start block.
+// reduction; FP32 accumulation within row chunks on request for nearly orthonormal FP32 blocks), block
+// rotations X V, residual norms, conversions and the random start block.
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "rw_internal.h"
 
@@ -188,6 +191,243 @@ __global__ __launch_bounds__(64) void k_gram_mfma(const T* X, int64_t ldx, const
       }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Symmetric Gram of tall FP32 blocks, G = X^T Y where X^T Y is symmetric (Y = X, or Y = op X for a
+// symmetric op), on the FP32 matrix cores.  One workgroup per chunk of rows: 32-row slabs of X and Y pass
+// through LDS (column-major with a 36-float column stride, double-buffered; the next slab waits in
+// registers while the current one is used), and the 16 waves share the 16 x 16 blocks of the upper block
+// triangle, grouped in 32 x 32 tiles whose fragments serve two blocks each.  Row 8 g + e of the slab is
+// the k index g of MFMA step e (A(i,k) and B(k,j) from lane i + 16 k or j + 16 k, D(4 (l/16) + v, l%16)
+// in register v of lane l).  A chunk (at most 2048 rows) accumulates in FP32, so its rounding error
+// stays near FP32's unit roundoff relative to the column norms; the chunk partials (FP32, upper
+// entries) are summed over chunks in FP64 and in chunk order.
+// ---------------------------------------------------------------------------------------------
+constexpr int kSGRows = 32;
+constexpr int kSGStride = 36;     // b128 reads of 8 lanes in one column group fall in distinct banks
+constexpr int kSGMaxN = 224;      // 7 tiles of 32
+constexpr int kSGWaves = 16;
+constexpr int kSGMaxTiles = 2;
+constexpr int kSGSlab = kSGMaxN * kSGStride;   // floats per matrix slab in LDS
+
+struct SymGramPlan {
+  unsigned char tile[28];              // (tj << 3) | ti, ti <= tj; wave w owns tile[first[w] .. first[w + 1])
+  unsigned char first[kSGWaves + 1];
+};
+
+typedef float sg_f4 __attribute__((ext_vector_type(4)));
+
+template <bool SAME>
+__global__ __launch_bounds__(64 * kSGWaves) void k_gram_sym_f32(const float* X, const float* Y, int64_t ld,
+                                                                int64_t rows, int nb, int64_t chunk_rows, int vec,
+                                                                SymGramPlan plan, float* partial) {
+  constexpr int NM = SAME ? 1 : 2;
+  extern __shared__ float sg[];   // [2 buffers][NM][kSGSlab]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c16 = lane & 15, g = lane >> 4;
+  const int64_t r_begin = (int64_t)blockIdx.x * chunk_rows;
+  const int64_t r_end = std::min<int64_t>(rows, r_begin + chunk_rows);
+  const int nslab = (int)((r_end - r_begin + kSGRows - 1) / kSGRows);
+  const int nq = ((nb + 15) & ~15) * (kSGRows / 4);   // float4 per matrix slab (columns padded to 16)
+  float4 pre[2][NM];
+  auto fetch = [&](int s) {
+    const int64_t r0 = r_begin + (int64_t)s * kSGRows;
+    const bool full = vec && r0 + kSGRows <= r_end;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = tid + 64 * kSGWaves * u;
+      const int col = q >> 3;
+      const int64_t row = r0 + 4 * (q & 7);
+#pragma unroll
+      for (int mt = 0; mt < NM; ++mt) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (q < nq && col < nb) {
+          const float* p = (mt == 0 ? X : Y) + (int64_t)col * ld + row;
+          if (full) {
+            v = *reinterpret_cast<const float4*>(p);
+          } else {
+            if (row + 0 < r_end) v.x = p[0];
+            if (row + 1 < r_end) v.y = p[1];
+            if (row + 2 < r_end) v.z = p[2];
+            if (row + 3 < r_end) v.w = p[3];
+          }
+        }
+        pre[u][mt] = v;
+      }
+    }
+  };
+  auto stash = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = tid + 64 * kSGWaves * u;
+      if (q < nq) {
+#pragma unroll
+        for (int mt = 0; mt < NM; ++mt)
+          *reinterpret_cast<float4*>(sg + (b * NM + mt) * kSGSlab + (q >> 3) * kSGStride + 4 * (q & 7)) = pre[u][mt];
+      }
+    }
+  };
+  const int t_first = plan.first[wave], cnt = plan.first[wave + 1] - t_first;
+  sg_f4 acc[kSGMaxTiles][2][2];
+#pragma unroll
+  for (int t = 0; t < kSGMaxTiles; ++t)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[t][a][b] = sg_f4{0.f, 0.f, 0.f, 0.f};
+  if (nslab > 0) {
+    fetch(0);
+    stash(0);
+    if (nslab > 1) fetch(1);
+  }
+  __syncthreads();
+  for (int s = 0; s < nslab; ++s) {
+    const float* sx = sg + (s & 1) * NM * kSGSlab;
+    const float* sy = SAME ? sx : sx + kSGSlab;
+#pragma unroll
+    for (int t = 0; t < kSGMaxTiles; ++t) {
+      if (t >= cnt) break;
+      const int code = plan.tile[t_first + t], ti = code & 7, tj = code >> 3;
+      const bool a1 = 32 * ti + 16 < nb, b1 = 32 * tj + 16 < nb, diag = ti == tj;
+      float fa[2][8], fb[2][8];
+      auto frag = [&](const float* base, int col, float (&f)[8]) {
+        const float4 lo = *reinterpret_cast<const float4*>(base + col * kSGStride + 8 * g);
+        const float4 hi = *reinterpret_cast<const float4*>(base + col * kSGStride + 8 * g + 4);
+        f[0] = lo.x; f[1] = lo.y; f[2] = lo.z; f[3] = lo.w;
+        f[4] = hi.x; f[5] = hi.y; f[6] = hi.z; f[7] = hi.w;
+      };
+      frag(sx, 32 * ti + c16, fa[0]);
+      frag(sx, 32 * ti + 16 + c16, fa[1]);   // beyond nb only when !a1: read but unused (inside the slab)
+      if (SAME && diag) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          fb[0][e] = fa[0][e];
+          fb[1][e] = fa[1][e];
+        }
+      } else {
+        frag(sy, 32 * tj + c16, fb[0]);
+        frag(sy, 32 * tj + 16 + c16, fb[1]);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        acc[t][0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[0][e], fb[0][e], acc[t][0][0], 0, 0, 0);
+        if (b1) acc[t][0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[0][e], fb[1][e], acc[t][0][1], 0, 0, 0);
+        if (a1 && !diag) acc[t][1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[1][e], fb[0][e], acc[t][1][0], 0, 0, 0);
+        if (a1 && b1) acc[t][1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[1][e], fb[1][e], acc[t][1][1], 0, 0, 0);
+      }
+    }
+    if (s + 1 < nslab) stash((s + 1) & 1);
+    __syncthreads();
+    if (s + 2 < nslab) fetch(s + 2);
+  }
+  float* o = partial + (int64_t)blockIdx.x * nb * nb;   // o[i nb + j], i <= j (16-block upper triangle)
+#pragma unroll
+  for (int t = 0; t < kSGMaxTiles; ++t) {
+    if (t >= cnt) break;
+    const int code = plan.tile[t_first + t], ti = code & 7, tj = code >> 3;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if (ti == tj && a == 1 && b == 0) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 32 * ti + 16 * a + 4 * g + v, j = 32 * tj + 16 * b + c16;
+          if (i < nb && j < nb) o[(int64_t)i * nb + j] = acc[t][a][b][v];
+        }
+      }
+  }
+}
+
+// G (nb x nb, symmetric) = sum over chunks of the upper entries, in chunk order, in FP64
+__global__ void k_sum_sym_f32(const float* partial, int64_t nch, int nb, double* G) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)nb * nb;
+  if (k >= nn) return;
+  const int i = (int)(k / nb), j = (int)(k % nb);
+  if (i > j) return;
+  double s = 0.0;
+#pragma unroll 8
+  for (int64_t c = 0; c < nch; ++c) s += (double)partial[c * nn + k];
+  G[(int64_t)j * nb + i] = s;
+  G[(int64_t)i * nb + j] = s;
+}
+
+// chunks: one per CU at least 512 rows each, at most 2048 rows each
+static int64_t sym_gram_chunks(int64_t rows) {
+  const int64_t a = std::min<int64_t>(256, (rows + 511) / 512), b = (rows + 2047) / 2048;
+  return std::max<int64_t>(1, std::max(a, b));
+}
+
+static bool sym_gram_fits(int64_t rows, int nb) { return nb >= 96 && nb <= kSGMaxN && rows >= 4096; }
+
+// tiles of the upper triangle to waves: largest first, each to the wave whose SIMD (wave % 4) and then
+// itself carry the least work (a tile's work is its number of 16 x 16 blocks)
+static bool sym_gram_plan(int nb, SymGramPlan* p) {
+  const int T = (nb + 31) / 32;
+  struct Tl { int code, cost; };
+  std::vector<Tl> tl;
+  for (int tj = 0; tj < T; ++tj)
+    for (int ti = 0; ti <= tj; ++ti) {
+      const int na = 32 * ti + 16 < nb ? 2 : 1, nbk = 32 * tj + 16 < nb ? 2 : 1;
+      int cost = na * nbk;
+      if (ti == tj && na == 2) cost -= 1;
+      tl.push_back({(tj << 3) | ti, cost});
+    }
+  std::stable_sort(tl.begin(), tl.end(), [](const Tl& x, const Tl& y) { return x.cost > y.cost; });
+  int load[kSGWaves] = {0}, simd[4] = {0};
+  std::vector<int> own[kSGWaves];
+  for (const Tl& t : tl) {
+    int best = 0;
+    for (int w = 1; w < kSGWaves; ++w) {
+      const int sw = simd[w & 3], sb = simd[best & 3];
+      if (sw < sb || (sw == sb && load[w] < load[best])) best = w;
+    }
+    own[best].push_back(t.code);
+    load[best] += t.cost;
+    simd[best & 3] += t.cost;
+  }
+  int pos = 0;
+  for (int w = 0; w < kSGWaves; ++w) {
+    if ((int)own[w].size() > kSGMaxTiles) return false;
+    p->first[w] = (unsigned char)pos;
+    for (int c : own[w]) p->tile[pos++] = (unsigned char)c;
+  }
+  p->first[kSGWaves] = (unsigned char)pos;
+  return true;
+}
+
+static bool gram_sym_f32(const float* X, int64_t ldx, const float* Y, int64_t ldy, int64_t rows, int nb, double* G,
+                         double* partial, hipStream_t s) {
+  if (ldx != ldy || !sym_gram_fits(rows, nb)) return false;
+  SymGramPlan plan;
+  if (!sym_gram_plan(nb, &plan)) return false;
+  const int64_t nch = sym_gram_chunks(rows);
+  const int64_t chunk_rows = ((rows + nch - 1) / nch + kSGRows - 1) / kSGRows * kSGRows;
+  const int64_t nblk = (rows + chunk_rows - 1) / chunk_rows;
+  const bool same = X == Y;
+  const int vec = (ldx % 4 == 0 && (uintptr_t)X % 16 == 0 && (uintptr_t)Y % 16 == 0) ? 1 : 0;
+  const size_t sh = (size_t)2 * (same ? 1 : 2) * kSGSlab * sizeof(float);
+  float* part = reinterpret_cast<float*>(partial);
+  if (same) {
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_sym_f32<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+      attr = true;
+    }
+    k_gram_sym_f32<true><<<(unsigned)nblk, 64 * kSGWaves, sh, s>>>(X, Y, ldx, rows, nb, chunk_rows, vec, plan, part);
+  } else {
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram_sym_f32<false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+      attr = true;
+    }
+    k_gram_sym_f32<false><<<(unsigned)nblk, 64 * kSGWaves, sh, s>>>(X, Y, ldx, rows, nb, chunk_rows, vec, plan, part);
+  }
+  k_sum_sym_f32<<<nblocks((int64_t)nb * nb, 256), 256, 0, s>>>(part, nblk, nb, G);
+  return true;
+}
+
 __global__ void k_sum_chunks(const double* partial, int64_t count, int64_t nchunks, double* G) {
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= count) return;
@@ -214,12 +454,20 @@ static bool gram_is_big(int bx, int by) { return bx >= 96 && by >= 96; }
 size_t gram_partial_count(int64_t rows, int bx, int by) {
   // the symmetric case has the most chunks (fewer tiles)
   int64_t nch = gram_is_big(bx, by) ? gram_big_chunks(rows, bx, by, bx == by) : gram_chunks(rows, bx, by);
-  return (size_t)nch * bx * by;
+  size_t c = (size_t)nch * bx * by;
+  if (bx == by && sym_gram_fits(rows, bx))   // FP32 partials of the symmetric FP32 kernel
+    c = std::max(c, ((size_t)sym_gram_chunks(rows) * bx * by + 1) / 2);
+  return c;
 }
 
 int gram(int dt, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t rows, int bx, int by,
-         double* G, double* partial, hipStream_t s, bool sym) {
+         double* G, double* partial, hipStream_t s, bool sym, bool acc32) {
   if (bx <= 0 || by <= 0) return RW_OK;
+  if (acc32 && dt == RW_F32 && sym && bx == by &&
+      gram_sym_f32((const float*)X, ldx, (const float*)Y, ldy, rows, bx, G, partial, s)) {
+    RW_LAUNCH_CHECK();
+    return RW_OK;
+  }
   const bool big = gram_is_big(bx, by);
   const int slab = big ? kGMRows : kGK;
   const int sy = (sym && bx == by) ? 1 : 0;

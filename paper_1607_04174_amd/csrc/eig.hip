@@ -127,7 +127,8 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool ne
   const Graph* g = c.g;
   EigWork& w = c.w;
   const int64_t n2 = (int64_t)nb * nb;
-  RW_TRY(gram(c.dt, F, c.N, F, c.N, c.N, nb, nb, w.G, w.partial, c.s, true));
+  // a nearly orthonormal block (the update path) allows FP32 accumulation over row chunks
+  RW_TRY(gram(c.dt, F, c.N, F, c.N, c.N, nb, nb, w.G, w.partial, c.s, true, near_orth));
   bool have_w = false;
   if (near_orth) {
     k_offI_absmax<<<1, 1024, 0, c.s>>>(w.G, nb, w.G2, w.tmp);
@@ -157,7 +158,7 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool ne
   }
   RW_TRY(stencil_apply(g, F, LF, nullptr, nb, 1.0, 0.0, 0.0, c.s));
   c.spmm_cols += nb;
-  RW_TRY(gram(c.dt, F, c.N, LF, c.N, c.N, nb, nb, w.H, w.partial, c.s, true));
+  RW_TRY(gram(c.dt, F, c.N, LF, c.N, c.N, nb, nb, w.H, w.partial, c.s, true, near_orth));
   RW_TRY(gram(RW_F64, w.H, nb, w.W, nb, nb, nb, nb, w.T, w.partial, c.s));         // T = H^T W = H W
   RW_TRY(gram(RW_F64, w.W, nb, w.T, nb, nb, nb, nb, w.Hp, w.partial, c.s));        // Hp = W^T H W
   k_symmetrize<<<nblocks((int64_t)nb * nb, 256), 256, 0, c.s>>>(w.Hp, nb);

@@ -178,9 +178,11 @@ int stencil_apply(const Graph* g, const void* X, void* Y, const void* Z, int64_t
 // reduction over row chunks through `partial` (gram_partial_count doubles).
 size_t gram_partial_count(int64_t rows, int bx, int by);
 // sym: the product is known to be symmetric (X = Y, or X^T M X with M symmetric); only the upper tiles
-// are computed and mirrored.
+// are computed and mirrored.  acc32 (FP32 blocks with sym only): chunks of rows may accumulate in FP32,
+// an error near FP32's unit roundoff times the column norms; for nearly orthonormal blocks only (an
+// ill-conditioned Gram needs the FP64 accumulation).
 int gram(int dt, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t rows, int bx, int by,
-         double* G, double* partial, hipStream_t s, bool sym = false);
+         double* G, double* partial, hipStream_t s, bool sym = false, bool acc32 = false);
 // Z (rows x n, ld ldz, type dt) = X (rows x k, ld ldx, type dt) * V (FP64, k x n, ld ldv)
 //   (+ beta * Z when beta != 0)
 int gemm_tn(int dt, const void* X, int64_t ldx, const double* V, int64_t ldv, void* Z, int64_t ldz,
