@@ -455,8 +455,9 @@ size_t gram_partial_count(int64_t rows, int bx, int by) {
   // the symmetric case has the most chunks (fewer tiles)
   int64_t nch = gram_is_big(bx, by) ? gram_big_chunks(rows, bx, by, bx == by) : gram_chunks(rows, bx, by);
   size_t c = (size_t)nch * bx * by;
-  if (bx == by && sym_gram_fits(rows, bx))   // FP32 partials of the symmetric FP32 kernel
-    c = std::max(c, ((size_t)sym_gram_chunks(rows) * bx * by + 1) / 2);
+  // FP32 partials of the symmetric FP32 kernel, for any width up to bx (callers may use fewer columns)
+  const int sb = std::min(bx, kSGMaxN);
+  if (bx == by && sym_gram_fits(rows, sb)) c = std::max(c, ((size_t)sym_gram_chunks(rows) * sb * sb + 1) / 2);
   return c;
 }
 
@@ -688,6 +689,12 @@ static bool gemm_mfma(const T* X, int64_t ldx, const double* V, int64_t ldv, T* 
   else if (ncb <= 8) launch_gemm_mfma<T, 8>(X, ldx, V, ldv, Z, ldz, rows, k, n, beta, sw, s);
   else launch_gemm_mfma<T, 13>(X, ldx, V, ldv, Z, ldz, rows, k, n, beta, sw, s);
   return true;
+}
+
+bool gemm_rowwise(int dt, int64_t rows, int k, int n) {
+  if (dt != RW_F32 && dt != RW_BF16) return false;
+  const int sw = gemm_slab_width(k, n);
+  return sw >= n && sw >= 16 && rows >= 1024 && n >= 32 && k >= 16;
 }
 
 int gemm_tn(int dt, const void* X, int64_t ldx, const double* V, int64_t ldv, void* Z, int64_t ldz,

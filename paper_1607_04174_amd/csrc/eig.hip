@@ -20,7 +20,7 @@ namespace rw {
 
 struct EigWork {
   char* B[4];
-  double *G, *G2, *V, *s, *W, *H, *T, *Hp, *Z, *WZ, *theta, *res, *syw, *tmp, *partial;
+  double *G, *G2, *V, *s, *W, *H, *T, *Hp, *Z, *WZ, *theta, *res, *cq, *syw, *tmp, *partial;
   int* info;
 };
 
@@ -39,7 +39,7 @@ static size_t eig_layout(const Graph* g, int nb, void* base, EigWork* w) {
   t.T = c.take<double>(n2); t.Hp = c.take<double>(n2); t.Z = c.take<double>(n2); t.WZ = c.take<double>(n2);
   t.G2 = c.take<double>(n2);
   t.syw = c.take<double>(std::max(syev_work_count(nb, 1, true, 0), tridiag_fits(nb) ? tridiag_work_count(nb) : 0));
-  t.s = c.take<double>(nb); t.theta = c.take<double>(nb); t.res = c.take<double>(nb);
+  t.s = c.take<double>(nb); t.theta = c.take<double>(nb); t.res = c.take<double>(nb); t.cq = c.take<double>(nb);
   t.tmp = c.take<double>(std::max(nb, 16));
   size_t pc = std::max({gram_partial_count(g->N, nb, nb), norm_partial_count(nb), gram_partial_count(g->N, 1, nb)});
   t.partial = c.take<double>(pc);
@@ -86,6 +86,32 @@ __global__ void k_series_w(const double* E, const double* E2, double* W, int n) 
   W[t] = (i == j ? 1.0 : 0.0) - 0.5 * E[t] + 0.375 * E2[t];
 }
 
+// Gram of the projected block F = Qv - g c^T (c = Qv^T g, g of unit norm) from Gq = Q^T Q of Q = [g, Qv]
+// ((nb + 1)^2): F^T F = Qv^T Qv - (2 - g^T g) c c^T; also returns c
+__global__ void k_gram_project(const double* Gq, int nb, double* G, double* cvec) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nb * nb) return;
+  const int i = (int)(t % nb), j = (int)(t / nb), n1 = nb + 1;
+  const double ci = Gq[i + 1], cj = Gq[j + 1];
+  G[t] = Gq[(int64_t)(j + 1) * n1 + i + 1] - (2.0 - Gq[0]) * ci * cj;
+  if (j == 0) cvec[i] = ci;
+}
+
+// rotation of the projected block through Q = [g, Qv]: F V = Q V' with V' ((nb + 1) x nb, ld nb + 1)
+// holding -(c^T V) in row 0 and V below
+__global__ void k_fold_rows(const double* V, const double* cvec, int nb, double* Vp) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)(nb + 1) * nb) return;
+  const int r = (int)(t % (nb + 1)), j = (int)(t / (nb + 1));
+  if (r == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < nb; ++i) acc += cvec[i] * V[(int64_t)j * nb + i];
+    Vp[t] = -acc;
+  } else {
+    Vp[t] = V[(int64_t)j * nb + r - 1];
+  }
+}
+
 __global__ void k_symmetrize(double* A, int n) {
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= (int64_t)n * n) return;
@@ -123,12 +149,23 @@ __global__ void k_copy_d(const double* a, double* b, int64_t n) {
 // G is numerically singular, W = V s^{-1/2} from its eigendecomposition with small s floored.  With
 // `near_orth` (F already orthonormal up to storage rounding, as a stored eigenbasis is) and
 // max |G - I| < 1e-4, W = G^{-1/2} from its series I - E/2 + 3/8 E^2 (truncation below 1e-12).
-static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool near_orth = false) {
+static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool near_orth = false,
+                   bool fold = false) {
   const Graph* g = c.g;
   EigWork& w = c.w;
   const int64_t n2 = (int64_t)nb * nb;
+  // with `fold`, the column before F holds the null vector g and the block is the projection F - g (g^T F):
+  // the projection enters through the Gram of [g, F] and the rotation's extra row, and op F serves for
+  // op of the projected block (op g = 0).  X may then be F itself (in-place rotation).
+  char* Q0 = F - dtype_size(c.dt) * c.N;
   // a nearly orthonormal block (the update path) allows FP32 accumulation over row chunks
-  RW_TRY(gram(c.dt, F, c.N, F, c.N, c.N, nb, nb, w.G, w.partial, c.s, true, near_orth));
+  if (fold) {
+    RW_TRY(gram(c.dt, Q0, c.N, Q0, c.N, c.N, nb + 1, nb + 1, w.Hp, w.partial, c.s, true, near_orth));
+    k_gram_project<<<nblocks(n2, 256), 256, 0, c.s>>>(w.Hp, nb, w.G, w.cq);
+    RW_LAUNCH_CHECK();
+  } else {
+    RW_TRY(gram(c.dt, F, c.N, F, c.N, c.N, nb, nb, w.G, w.partial, c.s, true, near_orth));
+  }
   bool have_w = false;
   if (near_orth) {
     k_offI_absmax<<<1, 1024, 0, c.s>>>(w.G, nb, w.G2, w.tmp);
@@ -177,7 +214,13 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool ne
     RW_TRY(gram(RW_F64, w.W, nb, w.Z, nb, nb, nb, nb, w.WZ, w.partial, c.s));
   else
     RW_TRY(gemm_tn(RW_F64, w.W, nb, w.Z, nb, w.WZ, nb, nb, nb, nb, 0.0, c.s));    // WZ = W Z
-  RW_TRY(gemm_tn(c.dt, F, c.N, w.WZ, nb, X, c.N, c.N, nb, nb, 0.0, c.s));        // X = F W Z
+  if (fold) {
+    k_fold_rows<<<nblocks((int64_t)(nb + 1) * nb, 256), 256, 0, c.s>>>(w.WZ, w.cq, nb, w.T);
+    RW_LAUNCH_CHECK();
+    RW_TRY(gemm_tn(c.dt, Q0, c.N, w.T, nb + 1, X, c.N, c.N, nb + 1, nb, 0.0, c.s));   // X = (F - g c^T) W Z
+  } else {
+    RW_TRY(gemm_tn(c.dt, F, c.N, w.WZ, nb, X, c.N, c.N, nb, nb, 0.0, c.s));        // X = F W Z
+  }
   RW_TRY(gemm_tn(c.dt, LF, c.N, w.WZ, nb, LX, c.N, c.N, nb, nb, 0.0, c.s));      // op X
   RW_TRY(residual_norms(c.dt, LX, X, w.theta, c.N, nb, c.N, w.res, w.partial, c.s));
   return RW_OK;
@@ -397,7 +440,12 @@ int rw_update_eig(rw_graph h, const rw_edit* edits, int n_edits, int mode, const
     RW_TRY(fill_random(c.dt, w.B[0] + es * g->N * k, g->N, g->N, nb - k, opts->seed ^ 0x5eedull, stream));
     st = chfsi(c, m, nb, opts, Q, lambda, info);
   } else {
-    if (direct) RW_TRY(project_out_to(c.dt, Qv, c.N, w.B[0], c.N, g->ghat, c.N, k, w.tmp, w.partial, stream));
+    // Rayleigh-Ritz in place on an FP32 basis: Q's column 0 takes the edited graph's null vector and the
+    // projection folds into the step (the rotation reads each row of [g, Qv] before writing it)
+    const bool fold = mode == RW_UPDATE_RR && direct && c.dt == RW_F32 && k + 1 <= nb &&
+                      gemm_rowwise(c.dt, c.N, k + 1, k);
+    if (fold) RW_TRY(copy_cols(c.dt, g->ghat, c.N, c.dt, Q, c.N, c.N, 1, stream));
+    else if (direct) RW_TRY(project_out_to(c.dt, Qv, c.N, w.B[0], c.N, g->ghat, c.N, k, w.tmp, w.partial, stream));
     else RW_TRY(project_out(c.dt, w.B[0], c.N, g->ghat, c.N, k, w.tmp, w.partial, stream));
     int ix = 0;
     if (mode == RW_UPDATE_DIAG_RQ) {
@@ -420,7 +468,7 @@ int rw_update_eig(rw_graph h, const rw_edit* edits, int n_edits, int mode, const
       RW_TRY(col_dots(c.dt, w.B[ix], w.B[3], c.N, k, c.N, w.theta, w.partial, stream));
       RW_TRY(residual_norms(c.dt, w.B[3], w.B[ix], w.theta, c.N, k, c.N, w.res, w.partial, stream));
     } else {
-      RW_TRY(rr_step(c, k, w.B[0], w.B[1], direct ? Qv : w.B[2], w.B[3], true));
+      RW_TRY(rr_step(c, k, fold ? Qv : w.B[0], w.B[1], direct ? Qv : w.B[2], w.B[3], true, fold));
       ix = 2;
     }
     const int qdt = opts->q_dtype;

@@ -187,6 +187,10 @@ int gram(int dt, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t
 //   (+ beta * Z when beta != 0)
 int gemm_tn(int dt, const void* X, int64_t ldx, const double* V, int64_t ldv, void* Z, int64_t ldz,
             int64_t rows, int k, int n, double beta, hipStream_t s);
+// true when gemm_tn with these sizes runs the single-slab matrix-core kernel, in which each 32-row task
+// reads all of its rows of X before it writes its rows of Z: Z may then share X's storage (same leading
+// dimension, shifted by whole columns), an in-place rotation
+bool gemm_rowwise(int dt, int64_t rows, int k, int n);
 // copy / convert a column-major block (rows x cols) between element types
 int convert_block(int dt_src, const void* src, int64_t lds, int dt_dst, void* dst, int64_t ldd,
                   int64_t rows, int cols, hipStream_t s);
