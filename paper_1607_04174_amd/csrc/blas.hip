@@ -691,6 +691,161 @@ static bool gemm_mfma(const T* X, int64_t ldx, const double* V, int64_t ldv, T* 
   return true;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Rotation of a block and of its operator image with the residual norms, in one pass (FP32 blocks):
+//   X = A0 V,  LX = A1' V,  res_j = ||LX_j - theta_j X_j||,
+// A1' = A1 shifted right by off1 columns (zero columns in front), so that V may carry extra leading rows
+// that act on A0 only.  Same arithmetic as k_gemm_mfma (V rounded to FP32 in LDS, FP32 accumulation);
+// a wave walks 16-row tasks and holds both outputs' accumulators, the residual terms (formed in FP64
+// from the stored FP32 values) accumulate per lane and column, then over the 16 lanes of a column
+// group, the waves of the workgroup and the workgroups, in a fixed order.  Each task reads its rows of
+// A0 before writing its rows of X, so X may share A0's storage (shifted by whole columns).
+// ---------------------------------------------------------------------------------------------
+constexpr int kRotAhead = 2;   // k-steps of the two inputs loaded ahead (two outputs' accumulators held)
+
+template <int NCB>
+__global__ __launch_bounds__(64 * kGemmWaves) void k_rotate_pair(const float* A0, const float* A1, int off1,
+                                                                 int64_t ld, const double* V, int64_t ldv,
+                                                                 const double* theta, float* X, float* LX,
+                                                                 int64_t rows, int k, int n, double* rpart) {
+  extern __shared__ float sV[];   // [kpad][n] V rounded to FP32 (zero beyond k), then theta (FP64)
+  const int nks = (k + 3) / 4;
+  for (int t = threadIdx.x; t < 4 * nks * n; t += blockDim.x) {
+    const int kk = t % (4 * nks), c = t / (4 * nks);
+    sV[kk * n + c] = kk < k ? (float)V[(int64_t)c * ldv + kk] : 0.f;
+  }
+  double* sTh = reinterpret_cast<double*>(sV + ((4 * nks * n + 1) & ~1));
+  for (int c = threadIdx.x; c < n; c += blockDim.x) sTh[c] = theta[c];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c16 = lane & 15, g = lane >> 4;
+  // a task's residual terms are summed over the 16 lanes of each column group at once; lane c16 keeps the
+  // sums of the column indices idx = 4 cb + v with idx % 16 == c16 (idx = 16 q + c16 in rps[q])
+  constexpr int NQ = (4 * NCB + 15) / 16;
+  float rps[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) rps[q] = 0.f;
+  const int64_t tasks = (rows + 15) / 16;
+  for (int64_t task = (int64_t)blockIdx.x * kGemmWaves + wave; task < tasks; task += (int64_t)gridDim.x * kGemmWaves) {
+    const int64_t r = task * 16 + c16;
+    const bool ok = r < rows;
+    gemm_f4 acc0[NCB], acc1[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      acc0[cb] = gemm_f4{0.f, 0.f, 0.f, 0.f};
+      acc1[cb] = gemm_f4{0.f, 0.f, 0.f, 0.f};
+    }
+    float x0[kRotAhead], x1[kRotAhead];
+    auto fetch = [&](int st, float& a, float& b) {
+      const int kk = 4 * st + g;
+      a = (ok && kk < k) ? A0[(int64_t)kk * ld + r] : 0.f;
+      b = (ok && kk < k && kk >= off1) ? A1[(int64_t)(kk - off1) * ld + r] : 0.f;
+    };
+#pragma unroll
+    for (int d = 0; d < kRotAhead; ++d) fetch(d, x0[d], x1[d]);
+    for (int s0 = 0; s0 < nks; s0 += kRotAhead) {
+#pragma unroll
+      for (int d = 0; d < kRotAhead; ++d) {
+        const int st = s0 + d;
+        if (st >= nks) break;
+        const float fa = x0[d], fb = x1[d];
+        fetch(st + kRotAhead, x0[d], x1[d]);
+        const float* vrow = sV + (4 * st + g) * n + c16;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const float av = 16 * cb + c16 < n ? vrow[16 * cb] : 0.f;
+          acc0[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, fa, acc0[cb], 0, 0, 0);
+          acc1[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, fb, acc1[cb], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = 16 * cb + 4 * g + v;
+        float e = 0.f;
+        if (ok && col < n) {
+          const float xv = acc0[cb][v], lv = acc1[cb][v];
+          X[(int64_t)col * ld + r] = xv;
+          LX[(int64_t)col * ld + r] = lv;
+          const double d = (double)lv - sTh[col] * (double)xv;
+          e = (float)(d * d);
+        }
+        e += __shfl_xor(e, 1);
+        e += __shfl_xor(e, 2);
+        e += __shfl_xor(e, 4);
+        e += __shfl_xor(e, 8);
+        const int idx = 4 * cb + v;
+        if ((idx & 15) == c16) rps[idx >> 4] += e;
+      }
+  }
+  // column sums over the waves (in order), then one value per workgroup
+  __syncthreads();   // V no longer read
+  double* red = reinterpret_cast<double*>(sV);   // [kGemmWaves][n]
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int idx = 16 * q + c16;
+    const int col = 16 * (idx >> 2) + 4 * g + (idx & 3);
+    if (idx < 4 * NCB && col < n) red[wave * n + col] = (double)rps[q];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    double t = 0.0;
+    for (int w = 0; w < kGemmWaves; ++w) t += red[w * n + c];
+    rpart[(int64_t)blockIdx.x * n + c] = t;
+  }
+}
+
+__global__ void k_rotate_res_final(const double* rpart, int nblk, int n, double* res) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double t = 0.0;
+  for (int b = 0; b < nblk; ++b) t += rpart[(int64_t)b * n + c];
+  res[c] = sqrt(t);
+}
+
+static size_t rotate_pair_lds(int k, int n) {
+  const size_t nks = (size_t)(k + 3) / 4;
+  return ((4 * nks * n + 1) & ~(size_t)1) * sizeof(float) + (size_t)n * sizeof(double);
+}
+
+bool rotate_pair_fits(int dt, int64_t rows, int k, int n) {
+  return dt == RW_F32 && rows >= 1024 && n >= 32 && n <= 208 && k >= 16 && rotate_pair_lds(k, n) <= kLdsLimit &&
+         (size_t)kGemmWaves * n * sizeof(double) <= rotate_pair_lds(k, n);
+}
+
+size_t rotate_pair_partial_count(int n) { return (size_t)256 * n; }
+
+template <int NCB>
+static void launch_rotate_pair(const float* A0, const float* A1, int off1, int64_t ld, const double* V, int64_t ldv,
+                               const double* theta, float* X, float* LX, int64_t rows, int k, int n, double* res,
+                               double* partial, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_rotate_pair<NCB>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+    attr = true;
+  }
+  const int64_t tasks = (rows + 15) / 16;
+  const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(256, (tasks + kGemmWaves - 1) / kGemmWaves));
+  k_rotate_pair<NCB><<<gx, 64 * kGemmWaves, rotate_pair_lds(k, n), s>>>(A0, A1, off1, ld, V, ldv, theta, X, LX, rows,
+                                                                        k, n, partial);
+  k_rotate_res_final<<<nblocks(n, 256), 256, 0, s>>>(partial, (int)gx, n, res);
+}
+
+int rotate_pair(const float* A0, const float* A1, int off1, int64_t ld, const double* V, int64_t ldv,
+                const double* theta, float* X, float* LX, int64_t rows, int k, int n, double* res, double* partial,
+                hipStream_t s) {
+  RW_CHECK(rotate_pair_fits(RW_F32, rows, k, n) && (off1 == 0 || off1 == 1), RW_EINVAL, "rotate_pair: bad shape");
+  const int ncb = (n + 15) / 16;
+  if (ncb <= 4) launch_rotate_pair<4>(A0, A1, off1, ld, V, ldv, theta, X, LX, rows, k, n, res, partial, s);
+  else if (ncb <= 8) launch_rotate_pair<8>(A0, A1, off1, ld, V, ldv, theta, X, LX, rows, k, n, res, partial, s);
+  else launch_rotate_pair<13>(A0, A1, off1, ld, V, ldv, theta, X, LX, rows, k, n, res, partial, s);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
 bool gemm_rowwise(int dt, int64_t rows, int k, int n) {
   if (dt != RW_F32 && dt != RW_BF16) return false;
   const int sw = gemm_slab_width(k, n);

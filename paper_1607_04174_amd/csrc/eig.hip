@@ -41,7 +41,8 @@ static size_t eig_layout(const Graph* g, int nb, void* base, EigWork* w) {
   t.syw = c.take<double>(std::max(syev_work_count(nb, 1, true, 0), tridiag_fits(nb) ? tridiag_work_count(nb) : 0));
   t.s = c.take<double>(nb); t.theta = c.take<double>(nb); t.res = c.take<double>(nb); t.cq = c.take<double>(nb);
   t.tmp = c.take<double>(std::max(nb, 16));
-  size_t pc = std::max({gram_partial_count(g->N, nb, nb), norm_partial_count(nb), gram_partial_count(g->N, 1, nb)});
+  size_t pc = std::max({gram_partial_count(g->N, nb, nb), norm_partial_count(nb), gram_partial_count(g->N, 1, nb),
+                       rotate_pair_partial_count(nb)});
   t.partial = c.take<double>(pc);
   t.info = c.take<int>(16);
   if (w) *w = t;
@@ -98,18 +99,19 @@ __global__ void k_gram_project(const double* Gq, int nb, double* G, double* cvec
 }
 
 // rotation of the projected block through Q = [g, Qv]: F V = Q V' with V' ((nb + 1) x nb, ld nb + 1)
-// holding -(c^T V) in row 0 and V below
-__global__ void k_fold_rows(const double* V, const double* cvec, int nb, double* Vp) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= (int64_t)(nb + 1) * nb) return;
-  const int r = (int)(t % (nb + 1)), j = (int)(t / (nb + 1));
-  if (r == 0) {
-    double acc = 0.0;
-    for (int i = 0; i < nb; ++i) acc += cvec[i] * V[(int64_t)j * nb + i];
-    Vp[t] = -acc;
-  } else {
-    Vp[t] = V[(int64_t)j * nb + r - 1];
+// holding -(c^T V) in row 0 and V below; one wave per column
+__global__ __launch_bounds__(64) void k_fold_rows(const double* V, const double* cvec, int nb, double* Vp) {
+  const int j = blockIdx.x, lane = threadIdx.x;
+  const double* vj = V + (int64_t)j * nb;
+  double* out = Vp + (int64_t)j * (nb + 1);
+  double acc = 0.0;
+  for (int i = lane; i < nb; i += 64) {
+    const double x = vj[i];
+    acc += cvec[i] * x;
+    out[i + 1] = x;
   }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) out[0] = -acc;
 }
 
 __global__ void k_symmetrize(double* A, int n) {
@@ -215,12 +217,17 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool ne
   else
     RW_TRY(gemm_tn(RW_F64, w.W, nb, w.Z, nb, w.WZ, nb, nb, nb, nb, 0.0, c.s));    // WZ = W Z
   if (fold) {
-    k_fold_rows<<<nblocks((int64_t)(nb + 1) * nb, 256), 256, 0, c.s>>>(w.WZ, w.cq, nb, w.T);
+    k_fold_rows<<<nb, 64, 0, c.s>>>(w.WZ, w.cq, nb, w.T);
     RW_LAUNCH_CHECK();
-    RW_TRY(gemm_tn(c.dt, Q0, c.N, w.T, nb + 1, X, c.N, c.N, nb + 1, nb, 0.0, c.s));   // X = (F - g c^T) W Z
-  } else {
-    RW_TRY(gemm_tn(c.dt, F, c.N, w.WZ, nb, X, c.N, c.N, nb, nb, 0.0, c.s));        // X = F W Z
   }
+  const double* Vr = fold ? w.T : w.WZ;   // the rotation, acting on [g, F] when folded
+  const int kr = fold ? nb + 1 : nb;
+  if (rotate_pair_fits(c.dt, c.N, kr, nb)) {   // X, op X and the residual norms in one pass
+    RW_TRY(rotate_pair((const float*)(fold ? Q0 : F), (const float*)LF, fold ? 1 : 0, c.N, Vr, kr, w.theta,
+                       (float*)X, (float*)LX, c.N, kr, nb, w.res, w.partial, c.s));
+    return RW_OK;
+  }
+  RW_TRY(gemm_tn(c.dt, fold ? Q0 : F, c.N, Vr, kr, X, c.N, c.N, kr, nb, 0.0, c.s));   // X = (F - g c^T) W Z
   RW_TRY(gemm_tn(c.dt, LF, c.N, w.WZ, nb, LX, c.N, c.N, nb, nb, 0.0, c.s));      // op X
   RW_TRY(residual_norms(c.dt, LX, X, w.theta, c.N, nb, c.N, w.res, w.partial, c.s));
   return RW_OK;

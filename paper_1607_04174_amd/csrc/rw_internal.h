@@ -191,6 +191,15 @@ int gemm_tn(int dt, const void* X, int64_t ldx, const double* V, int64_t ldv, vo
 // reads all of its rows of X before it writes its rows of Z: Z may then share X's storage (same leading
 // dimension, shifted by whole columns), an in-place rotation
 bool gemm_rowwise(int dt, int64_t rows, int k, int n);
+// X = A0 V, LX = A1' V and res_j = ||LX_j - theta_j X_j|| in one pass for FP32 blocks (rows x k inputs with
+// leading dimension ld, V FP64 k x n); A1' is A1 (k - off1 columns) behind off1 zero columns.  X may share
+// A0's storage shifted by whole columns.  rotate_pair_fits tells whether the shape is supported; `partial`
+// holds rotate_pair_partial_count(n) doubles.
+bool rotate_pair_fits(int dt, int64_t rows, int k, int n);
+size_t rotate_pair_partial_count(int n);
+int rotate_pair(const float* A0, const float* A1, int off1, int64_t ld, const double* V, int64_t ldv,
+                const double* theta, float* X, float* LX, int64_t rows, int k, int n, double* res, double* partial,
+                hipStream_t s);
 // copy / convert a column-major block (rows x cols) between element types
 int convert_block(int dt_src, const void* src, int64_t lds, int dt_dst, void* dst, int64_t ldd,
                   int64_t rows, int cols, hipStream_t s);
