@@ -108,10 +108,13 @@ __device__ __forceinline__ void gram_load8(const T* col, int64_t r, int64_t r_en
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(64) void k_gram_mfma(const T* X, int64_t ldx, const T* Y, int64_t ldy, int64_t rows,
-                                                  int bx, int by, int64_t chunk_rows, int tiles_x, int sym, int vec,
-                                                  double* out, int64_t out_stride) {
+// SPLIT waves per workgroup: wave w takes the w-th of SPLIT row ranges of the chunk, and the waves' tiles
+// are added in wave order through LDS (short reductions: fewer sequential steps per wave)
+template <typename T, int SPLIT>
+__global__ __launch_bounds__(64 * SPLIT) void k_gram_mfma(const T* X, int64_t ldx, const T* Y, int64_t ldy,
+                                                          int64_t rows, int bx, int by, int64_t chunk_rows,
+                                                          int tiles_x, int sym, int vec, double* out,
+                                                          int64_t out_stride) {
   int ti, tj;
   const int t = blockIdx.x;
   if (sym) {   // upper triangle of tiles, column by column
@@ -124,9 +127,12 @@ __global__ __launch_bounds__(64) void k_gram_mfma(const T* X, int64_t ldx, const
     tj = t / tiles_x;
   }
   const int i0 = ti * kGM, j0 = tj * kGM;
-  const int lane = threadIdx.x, c16 = lane & 15, kq = lane >> 4;
-  const int64_t r_begin = (int64_t)blockIdx.y * chunk_rows;
-  const int64_t r_end = std::min<int64_t>(rows, r_begin + chunk_rows);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c16 = lane & 15, kq = lane >> 4;
+  const int64_t sub_rows = (chunk_rows / SPLIT + kGMRows - 1) / kGMRows * kGMRows;
+  const int64_t c_begin = (int64_t)blockIdx.y * chunk_rows;
+  const int64_t c_end = std::min<int64_t>(rows, c_begin + chunk_rows);
+  const int64_t r_begin = std::min<int64_t>(c_end, c_begin + wave * sub_rows);
+  const int64_t r_end = wave == SPLIT - 1 ? c_end : std::min<int64_t>(c_end, r_begin + sub_rows);
   const bool same = ti == tj && X == Y && ldx == ldy && i0 == j0;   // B operand equals A operand
   const int ca0 = i0 + c16, ca1 = i0 + 16 + c16, cb0 = j0 + c16, cb1 = j0 + 16 + c16;
   const bool oa0 = ca0 < bx, oa1 = ca1 < bx, ob0 = cb0 < by, ob1 = cb1 < by;
@@ -174,6 +180,27 @@ __global__ __launch_bounds__(64) void k_gram_mfma(const T* X, int64_t ldx, const
             acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a], xb[b], acc[a][b], 0, 0, 0);
       }
     }
+  }
+  if (SPLIT > 1) {
+    __shared__ double red[SPLIT > 1 ? SPLIT - 1 : 1][16][64];
+    if (wave > 0) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) red[wave - 1][(a * 2 + b) * 4 + v][lane] = acc[a][b][v];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int w = 1; w < SPLIT; ++w)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[a][b][v] += red[w - 1][(a * 2 + b) * 4 + v][lane];
   }
   double* o = out + (int64_t)blockIdx.y * out_stride;
   const bool mirror = sym && ti != tj;
@@ -337,18 +364,28 @@ __global__ __launch_bounds__(64 * kSGWaves) void k_gram_sym_f32(const float* X, 
   }
 }
 
-// G (nb x nb, symmetric) = sum over chunks of the upper entries, in chunk order, in FP64
-__global__ void k_sum_sym_f32(const float* partial, int64_t nch, int nb, double* G) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// G (nb x nb, symmetric) = sum over chunks of the upper entries in FP64: a block covers 64 consecutive
+// entries, its four waves take every fourth chunk, and the four sums are added in wave order
+__global__ __launch_bounds__(256) void k_sum_sym_f32(const float* partial, int64_t nch, int nb, double* G) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t k = blockIdx.x * (int64_t)64 + lane;
   const int64_t nn = (int64_t)nb * nb;
-  if (k >= nn) return;
-  const int i = (int)(k / nb), j = (int)(k % nb);
-  if (i > j) return;
   double s = 0.0;
-#pragma unroll 8
-  for (int64_t c = 0; c < nch; ++c) s += (double)partial[c * nn + k];
-  G[(int64_t)j * nb + i] = s;
-  G[(int64_t)i * nb + j] = s;
+  if (k < nn) {
+#pragma unroll 4
+    for (int64_t c = wave; c < nch; c += 4) s += (double)partial[c * nn + k];
+  }
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && k < nn) {
+    const int i = (int)(k / nb), j = (int)(k % nb);
+    if (i <= j) {
+      const double t = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+      G[(int64_t)j * nb + i] = t;
+      G[(int64_t)i * nb + j] = t;
+    }
+  }
 }
 
 // chunks: one per CU at least 512 rows each, at most 2048 rows each
@@ -424,7 +461,7 @@ static bool gram_sym_f32(const float* X, int64_t ldx, const float* Y, int64_t ld
     }
     k_gram_sym_f32<false><<<(unsigned)nblk, 64 * kSGWaves, sh, s>>>(X, Y, ldx, rows, nb, chunk_rows, vec, plan, part);
   }
-  k_sum_sym_f32<<<nblocks((int64_t)nb * nb, 256), 256, 0, s>>>(part, nblk, nb, G);
+  k_sum_sym_f32<<<(unsigned)(((int64_t)nb * nb + 63) / 64), 256, 0, s>>>(part, nblk, nb, G);
   return true;
 }
 
@@ -484,12 +521,20 @@ int gram(int dt, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t
     dim3 grid((unsigned)gram_mfma_tiles(bx, by, sy != 0), (unsigned)nch);
     const size_t es = dtype_size(dt);
     const int vec = (ldx % 8 == 0 && ldy % 8 == 0 && (uintptr_t)X % (8 * es) == 0 && (uintptr_t)Y % (8 * es) == 0) ? 1 : 0;
-    if (dt == RW_F64)
-      k_gram_mfma<double><<<grid, 64, 0, s>>>((const double*)X, ldx, (const double*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, vec, dst, count);
-    else if (dt == RW_F32)
-      k_gram_mfma<float><<<grid, 64, 0, s>>>((const float*)X, ldx, (const float*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, vec, dst, count);
-    else
-      k_gram_mfma<uint16_t><<<grid, 64, 0, s>>>((const uint16_t*)X, ldx, (const uint16_t*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, vec, dst, count);
+    if (nch == 1 && rows <= 4096) {   // short products (the small dense matrices): four waves per tile
+      if (dt == RW_F64)
+        k_gram_mfma<double, 4><<<grid, 256, 0, s>>>((const double*)X, ldx, (const double*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, vec, dst, count);
+      else if (dt == RW_F32)
+        k_gram_mfma<float, 4><<<grid, 256, 0, s>>>((const float*)X, ldx, (const float*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, vec, dst, count);
+      else
+        k_gram_mfma<uint16_t, 4><<<grid, 256, 0, s>>>((const uint16_t*)X, ldx, (const uint16_t*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, vec, dst, count);
+    } else if (dt == RW_F64) {
+      k_gram_mfma<double, 1><<<grid, 64, 0, s>>>((const double*)X, ldx, (const double*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, vec, dst, count);
+    } else if (dt == RW_F32) {
+      k_gram_mfma<float, 1><<<grid, 64, 0, s>>>((const float*)X, ldx, (const float*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, vec, dst, count);
+    } else {
+      k_gram_mfma<uint16_t, 1><<<grid, 64, 0, s>>>((const uint16_t*)X, ldx, (const uint16_t*)Y, ldy, rows, bx, by, chunk_rows, tiles_x, sy, vec, dst, count);
+    }
   } else {
     dim3 grid((bx + kGT - 1) / kGT, (by + kGT - 1) / kGT, (unsigned)nch);
     if (dt == RW_F64)
@@ -696,11 +741,26 @@ static bool gemm_mfma(const T* X, int64_t ldx, const double* V, int64_t ldv, T* 
 //   X = A0 V,  LX = A1' V,  res_j = ||LX_j - theta_j X_j||,
 // A1' = A1 shifted right by off1 columns (zero columns in front), so that V may carry extra leading rows
 // that act on A0 only.  Same arithmetic as k_gemm_mfma (V rounded to FP32 in LDS, FP32 accumulation);
-// a wave walks 16-row tasks and holds both outputs' accumulators, the residual terms (formed in FP64
-// from the stored FP32 values) accumulate per lane and column, then over the 16 lanes of a column
-// group, the waves of the workgroup and the workgroups, in a fixed order.  Each task reads its rows of
+// a wave walks 16-row tasks and holds both outputs' accumulators.  The residual terms (FP32, from the
+// stored values; their rounding is that of the stored block) are summed per task over the 16 lanes of a
+// column group, then over the wave's tasks, the waves of the workgroup and the workgroups, in a fixed
+// order.  Each task reads its rows of
 // A0 before writing its rows of X, so X may share A0's storage (shifted by whole columns).
 // ---------------------------------------------------------------------------------------------
+// sum over the 16 lanes of a DPP row (quad swaps, half-row mirror, row mirror); every lane of the row
+// receives the same sum (each step adds two equal partial sums in swapped order)
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row16_sum(float x) {
+  x += dpp_f<0xB1>(x);    // quad_perm [1, 0, 3, 2]
+  x += dpp_f<0x4E>(x);    // quad_perm [2, 3, 0, 1]
+  x += dpp_f<0x141>(x);   // row_half_mirror
+  x += dpp_f<0x140>(x);   // row_mirror
+  return x;
+}
+
 constexpr int kRotAhead = 2;   // k-steps of the two inputs loaded ahead (two outputs' accumulators held)
 
 template <int NCB>
@@ -708,14 +768,14 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_rotate_pair(const float* A0
                                                                  int64_t ld, const double* V, int64_t ldv,
                                                                  const double* theta, float* X, float* LX,
                                                                  int64_t rows, int k, int n, double* rpart) {
-  extern __shared__ float sV[];   // [kpad][n] V rounded to FP32 (zero beyond k), then theta (FP64)
+  extern __shared__ float sV[];   // [kpad][n] V rounded to FP32 (zero beyond k), then theta
   const int nks = (k + 3) / 4;
   for (int t = threadIdx.x; t < 4 * nks * n; t += blockDim.x) {
     const int kk = t % (4 * nks), c = t / (4 * nks);
     sV[kk * n + c] = kk < k ? (float)V[(int64_t)c * ldv + kk] : 0.f;
   }
-  double* sTh = reinterpret_cast<double*>(sV + ((4 * nks * n + 1) & ~1));
-  for (int c = threadIdx.x; c < n; c += blockDim.x) sTh[c] = theta[c];
+  float* sTh = sV + 4 * nks * n;
+  for (int c = threadIdx.x; c < n; c += blockDim.x) sTh[c] = (float)theta[c];
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c16 = lane & 15, g = lane >> 4;
@@ -769,13 +829,10 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_rotate_pair(const float* A0
           const float xv = acc0[cb][v], lv = acc1[cb][v];
           X[(int64_t)col * ld + r] = xv;
           LX[(int64_t)col * ld + r] = lv;
-          const double d = (double)lv - sTh[col] * (double)xv;
-          e = (float)(d * d);
+          const float d = lv - sTh[col] * xv;
+          e = d * d;
         }
-        e += __shfl_xor(e, 1);
-        e += __shfl_xor(e, 2);
-        e += __shfl_xor(e, 4);
-        e += __shfl_xor(e, 8);
+        e = row16_sum(e);
         const int idx = 4 * cb + v;
         if ((idx & 15) == c16) rps[idx >> 4] += e;
       }
@@ -797,17 +854,18 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_rotate_pair(const float* A0
   }
 }
 
-__global__ void k_rotate_res_final(const double* rpart, int nblk, int n, double* res) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
+// one wave per column: lanes take every 64th workgroup's value, then a butterfly (fixed order)
+__global__ __launch_bounds__(64) void k_rotate_res_final(const double* rpart, int nblk, int n, double* res) {
+  const int c = blockIdx.x, lane = threadIdx.x;
   double t = 0.0;
-  for (int b = 0; b < nblk; ++b) t += rpart[(int64_t)b * n + c];
-  res[c] = sqrt(t);
+  for (int b = lane; b < nblk; b += 64) t += rpart[(int64_t)b * n + c];
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+  if (lane == 0) res[c] = sqrt(t);
 }
 
 static size_t rotate_pair_lds(int k, int n) {
   const size_t nks = (size_t)(k + 3) / 4;
-  return ((4 * nks * n + 1) & ~(size_t)1) * sizeof(float) + (size_t)n * sizeof(double);
+  return (4 * nks * n + n) * sizeof(float);
 }
 
 bool rotate_pair_fits(int dt, int64_t rows, int k, int n) {
@@ -831,7 +889,7 @@ static void launch_rotate_pair(const float* A0, const float* A1, int off1, int64
   const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(256, (tasks + kGemmWaves - 1) / kGemmWaves));
   k_rotate_pair<NCB><<<gx, 64 * kGemmWaves, rotate_pair_lds(k, n), s>>>(A0, A1, off1, ld, V, ldv, theta, X, LX, rows,
                                                                         k, n, partial);
-  k_rotate_res_final<<<nblocks(n, 256), 256, 0, s>>>(partial, (int)gx, n, res);
+  k_rotate_res_final<<<n, 64, 0, s>>>(partial, (int)gx, n, res);
 }
 
 int rotate_pair(const float* A0, const float* A1, int off1, int64_t ld, const double* V, int64_t ldv,
