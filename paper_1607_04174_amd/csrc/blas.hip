@@ -498,9 +498,29 @@ size_t gram_partial_count(int64_t rows, int bx, int by) {
   return c;
 }
 
+// FP64 Gram with few columns of Y over a short range of rows: one wave per column of X, lanes stride the
+// rows, a butterfly per product (fixed order)
+__global__ __launch_bounds__(64) void k_gram_skinny(const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                                                     int64_t rows, int bx, int by, double* G) {
+  const int i = blockIdx.x, lane = threadIdx.x;
+  const double* xi = X + (int64_t)i * ldx;
+  for (int j = 0; j < by; ++j) {
+    const double* yj = Y + (int64_t)j * ldy;
+    double acc = 0.0;
+    for (int64_t r = lane; r < rows; r += 64) acc += xi[r] * yj[r];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) G[(int64_t)j * bx + i] = acc;
+  }
+}
+
 int gram(int dt, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t rows, int bx, int by,
          double* G, double* partial, hipStream_t s, bool sym, bool acc32) {
   if (bx <= 0 || by <= 0) return RW_OK;
+  if (dt == RW_F64 && by <= 8 && bx > by && rows <= 8192) {
+    k_gram_skinny<<<bx, 64, 0, s>>>((const double*)X, ldx, (const double*)Y, ldy, rows, bx, by, G);
+    RW_LAUNCH_CHECK();
+    return RW_OK;
+  }
   if (acc32 && dt == RW_F32 && sym && bx == by &&
       gram_sym_f32((const float*)X, ldx, (const float*)Y, ldy, rows, bx, G, partial, s)) {
     RW_LAUNCH_CHECK();

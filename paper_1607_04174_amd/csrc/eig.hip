@@ -59,13 +59,25 @@ __global__ void k_scale_cols(const double* V, const double* s, double* W, int n,
   W[t] = V[t] / sqrt(sj);
 }
 
-// E = G - I and max |E_ij| (one workgroup; the max does not depend on the reduction order)
-__global__ __launch_bounds__(1024) void k_offI_absmax(const double* G, int n, double* E, double* out) {
+// E = G - I and max |E_ij| (one workgroup; the max does not depend on the reduction order).  With PROJ,
+// G is first formed as the projected Gram from Gq (as k_gram_project does, also writing G and c).
+template <bool PROJ>
+__global__ __launch_bounds__(1024) void k_offI_absmax(const double* Gin, int n, double* E, double* out,
+                                                      double* Gout = nullptr, double* cvec = nullptr) {
   __shared__ double red[16];
   double m = 0.0;
   for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += blockDim.x) {
     const int i = (int)(t % n), j = (int)(t / n);
-    const double e = G[t] - (i == j ? 1.0 : 0.0);
+    double gv;
+    if (PROJ) {
+      const double ci = Gin[i + 1], cj = Gin[j + 1];
+      gv = Gin[(int64_t)(j + 1) * (n + 1) + i + 1] - (2.0 - Gin[0]) * ci * cj;
+      Gout[t] = gv;
+      if (j == 0) cvec[i] = ci;
+    } else {
+      gv = Gin[t];
+    }
+    const double e = gv - (i == j ? 1.0 : 0.0);
     E[t] = e;
     m = fmax(m, fabs(e));
   }
@@ -163,14 +175,17 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool ne
   // a nearly orthonormal block (the update path) allows FP32 accumulation over row chunks
   if (fold) {
     RW_TRY(gram(c.dt, Q0, c.N, Q0, c.N, c.N, nb + 1, nb + 1, w.Hp, w.partial, c.s, true, near_orth));
-    k_gram_project<<<nblocks(n2, 256), 256, 0, c.s>>>(w.Hp, nb, w.G, w.cq);
-    RW_LAUNCH_CHECK();
+    if (!near_orth) {
+      k_gram_project<<<nblocks(n2, 256), 256, 0, c.s>>>(w.Hp, nb, w.G, w.cq);
+      RW_LAUNCH_CHECK();
+    }
   } else {
     RW_TRY(gram(c.dt, F, c.N, F, c.N, c.N, nb, nb, w.G, w.partial, c.s, true, near_orth));
   }
   bool have_w = false;
   if (near_orth) {
-    k_offI_absmax<<<1, 1024, 0, c.s>>>(w.G, nb, w.G2, w.tmp);
+    if (fold) k_offI_absmax<true><<<1, 1024, 0, c.s>>>(w.Hp, nb, w.G2, w.tmp, w.G, w.cq);
+    else k_offI_absmax<false><<<1, 1024, 0, c.s>>>(w.G, nb, w.G2, w.tmp);
     RW_LAUNCH_CHECK();
     double e = 1.0;
     RW_HIP(hipMemcpyAsync(&e, w.tmp, sizeof(double), hipMemcpyDeviceToHost, c.s));

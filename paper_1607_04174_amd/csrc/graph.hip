@@ -39,12 +39,15 @@ __global__ void k_graph_init(GridDev G, const void* Jsrc, int Jdt, double* J, T*
 }
 
 // w_e = s_e * exp(-beta * f(J_tail - J_head)), computed in FP64 and rounded once to T.
+// `flip` is set when an edge's weight crosses kAnchorWeight (the connectivity used by the solvability
+// check changes only then); it reads the previous weights, so on a first build it means nothing.
 template <typename T>
 __global__ void k_weights(GridDev G, const double* J, double beta, int form, const T* scale,
-                          const uint8_t* mask, T* weight) {
+                          const uint8_t* mask, T* weight, int* flip) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= G.N) return;
   uint8_t m = mask[i];
+  bool crossed = false;
   for (int d = 0; d < G.ndir; ++d) {
     double w = 0.0;
     if ((m >> d) & 1u) {
@@ -52,8 +55,11 @@ __global__ void k_weights(GridDev G, const double* J, double beta, int form, con
       double e = form == RW_WEIGHT_SQUARED ? diff * diff : fabs(diff);
       w = (double)scale[d * G.N + i] * exp(-beta * e);
     }
-    weight[d * G.N + i] = T(w);
+    const T old = weight[d * G.N + i], nw = T(w);
+    crossed |= ((double)old >= kAnchorWeight) != ((double)nw >= kAnchorWeight);
+    weight[d * G.N + i] = nw;
   }
+  if (crossed) *flip = 1;
 }
 
 // degree: forward edges stored at i, backward edges stored at the tail i - off[d]; fixed order.
@@ -193,7 +199,7 @@ static int rebuild_t(Graph* g, hipStream_t s) {
   GridDev G = grid_of(g);
   const int t = 256;
   k_weights<T><<<nblocks(g->N, t), t, 0, s>>>(G, g->J, g->beta, g->weight_form, (const T*)g->scale,
-                                                g->mask, (T*)g->weight);
+                                                g->mask, (T*)g->weight, g->cc_flag + 4);
   RW_LAUNCH_CHECK();
   int nb = (int)std::min<int64_t>(kReduceBlocks, nblocks(g->N, t));
   k_degree<T><<<nb, t, 0, s>>>(G, (const T*)g->weight, g->degree, g->partial);
@@ -207,6 +213,10 @@ static int rebuild_t(Graph* g, hipStream_t s) {
 }
 
 int graph_rebuild(Graph* g, hipStream_t s) {
+  if (g->cc_valid) {   // start watching for anchoring edges that appear or vanish
+    RW_HIP(hipMemsetAsync(g->cc_flag + 4, 0, sizeof(int), s));
+    g->cc_recheck = true;
+  }
   g->cc_valid = false;
   return g->dtype == RW_F64 ? rebuild_t<double>(g, s) : rebuild_t<float>(g, s);
 }
@@ -281,6 +291,16 @@ __global__ void k_cc_jump(int64_t* comp, int64_t N) {
 
 int graph_components(Graph* g, hipStream_t s) {
   if (g->cc_valid) return RW_OK;
+  if (g->cc_recheck) {   // the components of the last computation stand unless an edge crossed the threshold
+    g->cc_recheck = false;
+    int flip = 1;
+    RW_HIP(hipMemcpyAsync(&flip, g->cc_flag + 4, sizeof(int), hipMemcpyDeviceToHost, s));
+    RW_HIP(hipStreamSynchronize(s));
+    if (!flip) {
+      g->cc_valid = true;
+      return RW_OK;
+    }
+  }
   const GridDev G = grid_of(g);
   if (g->dtype == RW_F64)
     k_cc_init<double><<<nblocks(g->N, 256), 256, 0, s>>>(G, (const double*)g->weight, g->mask, g->comp);

@@ -95,6 +95,8 @@ struct Graph {
   int64_t* comp = nullptr;    // N: component root (the smallest node index) over edges with w >= kAnchorWeight
   int* cc_flag = nullptr;     // device scratch for the component and anchoring kernels
   bool cc_valid = false;      // comp matches the current weights
+  bool cc_recheck = false;    // comp matched the weights before the last rebuilds: still valid unless an edge
+                              // crossed kAnchorWeight since (device flag cc_flag[4], set by the weight kernel)
 };
 
 // edges below this weight do not connect nodes for the solvability check (they underflow in FP32)
