@@ -882,8 +882,7 @@ __global__ __launch_bounds__(1024) void k_lu_solve_lds(const double* Ag, int n, 
         const double v = fabs(A[i + k * ld]);
         if (v > best) { best = v; brow = i; }   // rows visited in increasing order: first maximum kept
       }
-      double m = best;
-      for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+      const double m = wave_max64(best);
       const unsigned long long tie = __ballot(best == m);
       int row;
       if (__popcll(tie) == 1) {

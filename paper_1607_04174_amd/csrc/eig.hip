@@ -59,14 +59,17 @@ __global__ void k_scale_cols(const double* V, const double* s, double* W, int n,
   W[t] = V[t] / sqrt(sj);
 }
 
-// E = G - I and max |E_ij| (one workgroup; the max does not depend on the reduction order).  With PROJ,
-// G is first formed as the projected Gram from Gq (as k_gram_project does, also writing G and c).
+// E = G - I and max |E_ij| (out[0] zeroed beforehand; blocks combine their maxima with an integer max on
+// the bit patterns, which orders non-negative doubles like their values, so the result does not depend on
+// the order).  With PROJ, G is first formed as the projected Gram from Gq (as k_gram_project does, also
+// writing G and c).
 template <bool PROJ>
-__global__ __launch_bounds__(1024) void k_offI_absmax(const double* Gin, int n, double* E, double* out,
-                                                      double* Gout = nullptr, double* cvec = nullptr) {
-  __shared__ double red[16];
+__global__ __launch_bounds__(256) void k_offI_absmax(const double* Gin, int n, double* E, double* out,
+                                                     double* Gout = nullptr, double* cvec = nullptr) {
+  __shared__ double red[4];
   double m = 0.0;
-  for (int64_t t = threadIdx.x; t < (int64_t)n * n; t += blockDim.x) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < (int64_t)n * n;
+       t += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(t % n), j = (int)(t / n);
     double gv;
     if (PROJ) {
@@ -87,7 +90,7 @@ __global__ __launch_bounds__(1024) void k_offI_absmax(const double* Gin, int n, 
   if (threadIdx.x == 0) {
     double r = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
-    out[0] = r;
+    atomicMax(reinterpret_cast<unsigned long long*>(out), (unsigned long long)__double_as_longlong(r));
   }
 }
 
@@ -184,8 +187,10 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool ne
   }
   bool have_w = false;
   if (near_orth) {
-    if (fold) k_offI_absmax<true><<<1, 1024, 0, c.s>>>(w.Hp, nb, w.G2, w.tmp, w.G, w.cq);
-    else k_offI_absmax<false><<<1, 1024, 0, c.s>>>(w.G, nb, w.G2, w.tmp);
+    RW_HIP(hipMemsetAsync(w.tmp, 0, sizeof(double), c.s));
+    const unsigned nbk = (unsigned)std::min<int64_t>(nblocks(n2, 256), 160);
+    if (fold) k_offI_absmax<true><<<nbk, 256, 0, c.s>>>(w.Hp, nb, w.G2, w.tmp, w.G, w.cq);
+    else k_offI_absmax<false><<<nbk, 256, 0, c.s>>>(w.G, nb, w.G2, w.tmp);
     RW_LAUNCH_CHECK();
     double e = 1.0;
     RW_HIP(hipMemcpyAsync(&e, w.tmp, sizeof(double), hipMemcpyDeviceToHost, c.s));

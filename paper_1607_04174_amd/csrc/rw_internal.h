@@ -18,6 +18,62 @@ constexpr size_t kLdsLimit = 160 * 1024 - 64;
 // Workgroup barrier that orders only LDS traffic: it does not wait for outstanding global stores
 // (used where waves exchange data through LDS alone; global writes there are never read back
 // inside the kernel).
+// Cross-lane sums and maxima by DPP (VALU data movement: no LDS round trip per step).  dpp_mov<CTRL>
+// moves a double across lanes by one DPP pattern; row16_* combine the 16 lanes of a DPP row (quad swaps,
+// half-row mirror, row mirror), each step combining two equal partials in swapped order so that every
+// lane of the row holds the same value; wave_* then combine the four rows in a fixed order through lane
+// reads, giving every lane the same result.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double quad_sum(double x) {   // the 4 lanes of a quad
+  x += dpp_mov<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x += dpp_mov<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  return x;
+}
+__device__ __forceinline__ double row16_sum(double x) {
+  x = quad_sum(x);
+  x += dpp_mov<0x141>(x);   // row_half_mirror
+  x += dpp_mov<0x140>(x);   // row_mirror
+  return x;
+}
+__device__ __forceinline__ double row16_max(double x) {
+  x = fmax(x, dpp_mov<0xB1>(x));
+  x = fmax(x, dpp_mov<0x4E>(x));
+  x = fmax(x, dpp_mov<0x141>(x));
+  x = fmax(x, dpp_mov<0x140>(x));
+  return x;
+}
+__device__ __forceinline__ double row16_min(double x) {
+  x = fmin(x, dpp_mov<0xB1>(x));
+  x = fmin(x, dpp_mov<0x4E>(x));
+  x = fmin(x, dpp_mov<0x141>(x));
+  x = fmin(x, dpp_mov<0x140>(x));
+  return x;
+}
+__device__ __forceinline__ double lane_read(double x, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double wave_sum64(double x) {
+  x = row16_sum(x);
+  return (lane_read(x, 0) + lane_read(x, 16)) + (lane_read(x, 32) + lane_read(x, 48));
+}
+__device__ __forceinline__ double wave_max64(double x) {
+  x = row16_max(x);
+  return fmax(fmax(lane_read(x, 0), lane_read(x, 16)), fmax(lane_read(x, 32), lane_read(x, 48)));
+}
+__device__ __forceinline__ double wave_min64(double x) {
+  x = row16_min(x);
+  return fmin(fmin(lane_read(x, 0), lane_read(x, 16)), fmin(lane_read(x, 32), lane_read(x, 48)));
+}
+
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();

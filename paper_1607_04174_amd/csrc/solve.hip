@@ -274,10 +274,7 @@ __global__ void k_fit_build(const int* cand, int64_t S, int ma, int C, int ms, c
   }
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum64(v); }
 
 // one wave per (candidate, label); lane-parallel sums reduced by butterflies, so all lanes agree
 __global__ __launch_bounds__(64) void k_fit_secular(const int* cand, int ncand, int64_t S, int C, int ms,
@@ -327,7 +324,7 @@ __global__ __launch_bounds__(64) void k_fit_secular(const int* cand, int ncand, 
       wm = fmax(wm, w[i]);
     }
     gn = wave_sum(gn);
-    for (int o = 32; o > 0; o >>= 1) wm = fmax(wm, __shfl_xor(wm, o));
+    wm = wave_max64(wm);
     double hi = small_m ? sqrt(gn) / rho : sqrt(fmax(wm, 1e-300) * gn) / rho;
     hi = fmax(hi, 1e-300);
     while (norm2(hi) > rho2) hi *= 2.0;
@@ -403,7 +400,7 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int6
     for (int c = 0; c < C; ++c) {
       double acc = 0.0;
       for (int64_t i = tid; i < S; i += 64) acc += Us[i + c * S] * Us[i + c * S];
-      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      acc = wave_sum64(acc);
       if (tid == 0) {
         sbn[c] = acc;
         sr[c] = acc;

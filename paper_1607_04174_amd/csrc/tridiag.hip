@@ -49,10 +49,8 @@ static TriBufs tri_bufs(double* work, int n) {
   return b;
 }
 
-__device__ __forceinline__ double tr_wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
+// sum over the 64 lanes of a wave, the same in every lane (DPP within rows, rows in a fixed order)
+__device__ __forceinline__ double tr_wave_sum(double v) { return wave_sum64(v); }
 
 // 1. Householder tridiagonalization (lower): reflector k maps A(k+1:n, k) to beta e1
 __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int n, double* refl, double* tau, double* d,
@@ -128,8 +126,7 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int n, double
         addr = tr_lo(k + 1 + j, R, n);
         for (; j < m; j += 4, addr += 4) acc += sA[addr] * v[j];
       }
-      acc += __shfl_xor(acc, 1);
-      acc += __shfl_xor(acc, 2);
+      acc = quad_sum(acc);   // the row's four lanes form one quad
       if (sub == 0 && r < m) p[r] = tk * acc;
     }
     lds_barrier();
@@ -193,12 +190,10 @@ __global__ __launch_bounds__(64) void k_tri_bisect(const double* dg, const doubl
     tn = fmax(tn, fabs(dg[j]) + el + er);
     emax = fmax(emax, er * er);
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, o));
-    hi = fmax(hi, __shfl_xor(hi, o));
-    tn = fmax(tn, __shfl_xor(tn, o));
-    emax = fmax(emax, __shfl_xor(emax, o));
-  }
+  lo = wave_min64(lo);
+  hi = wave_max64(hi);
+  tn = wave_max64(tn);
+  emax = wave_max64(emax);
   __syncthreads();
   const double pivmin = 2.3e-308 * fmax(1.0, emax);
   const double atol = 4.0 * 2.3e-16 * fmax(tn, 1e-300);
