@@ -305,6 +305,18 @@ size_t syev_work_count(int n, int count, bool vectors, int nrhs);
 bool tridiag_fits(int n);
 size_t tridiag_work_count(int n);
 int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hipStream_t s);
+// Batched eigenvalues and rotated right-hand sides through the tridiagonal form, for the candidate problems
+// of the choice of m: matrix b (order sizes[b] <= ld, leading dimension ld, ld^2 apart) has right-hand
+// sides R_b (ld x C, ld * C apart); on RW_OK, w_b holds its eigenvalues (zero beyond sizes[b]) and
+// R_b = V_b^T R_b (zero rows beyond sizes[b]).  RW_ENOCONV (clustered eigenvalues) leaves w and R as they
+// were.  work holds tridiag_rhs_work_count(max size, count, C) doubles.
+constexpr int kTriBatchMax = 32;
+struct TriSizes {
+  int n[kTriBatchMax];
+};
+size_t tridiag_rhs_work_count(int nmax, int count, int C);
+int syev_tridiag_rhs(const double* A, int ld, const int* sizes, int count, double* R, int C, double* w, double* work,
+                     size_t work_count, hipStream_t s);
 // Solve A X = B by LU with partial pivoting (A: n x n, B: n x nrhs, both destroyed/overwritten;
 // X returned in B).  stat[0] = min |pivot| / max |a_ij| (0 if a pivot is below the threshold).
 int lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s);

@@ -36,7 +36,8 @@ struct SolveWork {
   double* fitA;       // ncand x ms x ms  (ms = min(S, ma))
   double* fitR;       // ncand x ms x C
   double* fitW;       // ncand x ms
-  double* fitWork;    // Jacobi work
+  double* fitWork;    // eigensolver work (Jacobi, or the batched tridiagonal solver)
+  size_t fitWorkCount;
   double* K;          // ma x ma
   double* Y;          // ma x C
   double* stat;       // 8
@@ -66,7 +67,10 @@ static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base,
   t.fitA = c.take<double>((size_t)nc * ms * ms);
   t.fitR = c.take<double>((size_t)nc * ms * C);
   t.fitW = c.take<double>((size_t)nc * ms);
-  t.fitWork = c.take<double>(syev_work_count((int)ms, nc, false, C));
+  t.fitWorkCount = syev_work_count((int)ms, nc, false, C);
+  if (tridiag_fits((int)ms))
+    t.fitWorkCount = std::max(t.fitWorkCount, tridiag_rhs_work_count((int)ms, std::min(nc, kTriBatchMax), C));
+  t.fitWork = c.take<double>(t.fitWorkCount);
   t.K = c.take<double>((size_t)ma * ma);
   t.Y = c.take<double>((size_t)ma * C);
   t.stat = c.take<double>(8);
@@ -708,7 +712,22 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
       const int msp = (int)std::min<int64_t>(S, cand.back());
       k_fit_build<<<ncand, 256, 0, stream>>>(cand_buf, S, ma, C, msp, w.Qs, w.Gq, w.Gb, w.Us, w.fitA, w.fitR);
       RW_LAUNCH_CHECK();
-      RW_TRY(syev_batched(w.fitA, w.fitW, nullptr, w.fitR, C, msp, ncand, w.fitWork, stream));
+      // eigenvalues and rotated right-hand sides through the tridiagonal form (each candidate at its own
+      // order), the Jacobi solver when eigenvalues cluster or the batch does not fit
+      int est = RW_ENOCONV;
+      if (ncand <= kTriBatchMax && tridiag_fits(msp)) {
+        int sizes[kTriBatchMax];
+        bool ok = true;
+        for (int q = 0; q < ncand; ++q) {
+          sizes[q] = (int)std::min<int64_t>(S, cand[q]);
+          ok = ok && tridiag_fits(sizes[q]);
+        }
+        if (ok) {
+          est = syev_tridiag_rhs(w.fitA, msp, sizes, ncand, w.fitR, C, w.fitW, w.fitWork, w.fitWorkCount, stream);
+          if (est != RW_OK && est != RW_ENOCONV) return est;
+        }
+      }
+      if (est == RW_ENOCONV) RW_TRY(syev_batched(w.fitA, w.fitW, nullptr, w.fitR, C, msp, ncand, w.fitWork, stream));
       k_fit_secular<<<dim3(ncand, C), 64, 0, stream>>>(cand_buf, ncand, S, C, msp, w.fitW, w.fitR, w.Us, rho,
                                                         w.fvals);
       RW_LAUNCH_CHECK();

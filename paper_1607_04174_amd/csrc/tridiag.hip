@@ -53,8 +53,16 @@ static TriBufs tri_bufs(double* work, int n) {
 __device__ __forceinline__ double tr_wave_sum(double v) { return wave_sum64(v); }
 
 // 1. Householder tridiagonalization (lower): reflector k maps A(k+1:n, k) to beta e1
-__global__ __launch_bounds__(1024) void k_tridiag(const double* A, int n, double* refl, double* tau, double* d,
-                                                  double* e) {
+// Workgroup b reduces matrix b of a batch: order sz.n[b], leading dimension lda, matrices strideA apart;
+// its reflectors, tau, d and e sit nmax^2 or nmax entries apart per matrix.
+__global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int64_t strideA, TriSizes sz, int nmax,
+                                                  double* refl, double* tau, double* d, double* e) {
+  const int b = blockIdx.x, n = sz.n[b];
+  A += b * strideA;
+  refl += (int64_t)b * nmax * nmax;
+  tau += (int64_t)b * nmax;
+  d += (int64_t)b * nmax;
+  e += (int64_t)b * nmax;
   extern __shared__ double sA[];   // packed lower triangle, column-major
   double* v = sA + n * (n + 1) / 2;
   double* p = v + n;
@@ -62,7 +70,7 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int n, double
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int t = tid; t < n * n; t += blockDim.x) {
     const int i = t % n, j = t / n;
-    if (i >= j) sA[tr_lo(i, j, n)] = 0.5 * (A[t] + A[j + (int64_t)i * n]);
+    if (i >= j) sA[tr_lo(i, j, n)] = 0.5 * (A[i + (int64_t)j * lda] + A[j + (int64_t)i * lda]);
   }
   __syncthreads();
   for (int k = 0; k < n - 2; ++k) {
@@ -176,10 +184,14 @@ __device__ __forceinline__ int tr_sturm(const double* d, const double* e2, int n
 
 // 2. eigenvalue idx = blockIdx.x (ascending) by 64-point bisection; flag[0] = 1 if two eigenvalues are
 // closer than 1e-6 |T| (checked by the wave of the larger one)
-__global__ __launch_bounds__(64) void k_tri_bisect(const double* dg, const double* eg, int n, double* lam,
-                                                   double* flag) {
+__global__ __launch_bounds__(64) void k_tri_bisect(const double* dg, const double* eg, TriSizes sz, int nmax,
+                                                   double* lam, double* flag) {
   __shared__ double d[256], e2[256];
-  const int idx = blockIdx.x, lane = threadIdx.x;
+  const int idx = blockIdx.x, lane = threadIdx.x, n = sz.n[blockIdx.y];
+  if (idx >= n) return;   // the whole workgroup
+  dg += (int64_t)blockIdx.y * nmax;
+  eg += (int64_t)blockIdx.y * nmax;
+  lam += (int64_t)blockIdx.y * nmax;
   double lo = INFINITY, hi = -INFINITY, tn = 0.0, emax = 0.0;
   for (int j = lane; j < n; j += 64) {
     d[j] = dg[j];
@@ -224,8 +236,14 @@ __global__ __launch_bounds__(64) void k_tri_bisect(const double* dg, const doubl
 constexpr int kInvitThreads = 32;
 static size_t invit_lds_bytes(int n) { return ((size_t)n * (2 + 3 * kInvitThreads)) * sizeof(double); }
 
-__global__ __launch_bounds__(kInvitThreads) void k_tri_invit(const double* dg, const double* eg, int n,
-                                                             const double* lam, double* Z) {
+__global__ __launch_bounds__(kInvitThreads) void k_tri_invit(const double* dg, const double* eg, TriSizes sz,
+                                                             int nmax, const double* lam, double* Z) {
+  const int n = sz.n[blockIdx.y];
+  if ((int)blockIdx.x * kInvitThreads >= n) return;   // the whole workgroup
+  dg += (int64_t)blockIdx.y * nmax;
+  eg += (int64_t)blockIdx.y * nmax;
+  lam += (int64_t)blockIdx.y * nmax;
+  Z += (int64_t)blockIdx.y * nmax * nmax;
   extern __shared__ double sm[];
   double* d = sm;
   double* e = d + n;
@@ -327,22 +345,142 @@ __global__ __launch_bounds__(64) void k_tri_back(const double* refl, const doubl
 
 __global__ void k_tri_clear(double* flag) { flag[0] = 0.0; }
 
+// 5. (right-hand sides) h = U^T r = H_{n-3} ... H_1 H_0 r for right-hand side c = blockIdx.x of matrix
+// blockIdx.y (r: column c of R, ld ldr, matrices strideR apart; h: nmax x C per matrix), one wave each
+__global__ __launch_bounds__(64) void k_tri_rhs(const double* refl, const double* tau, TriSizes sz, int nmax,
+                                                const double* R, int ldr, int64_t strideR, int C, double* h) {
+  const int c = blockIdx.x, b = blockIdx.y, lane = threadIdx.x, n = sz.n[b];
+  refl += (int64_t)b * nmax * nmax;
+  tau += (int64_t)b * nmax;
+  const double* r = R + b * strideR + (int64_t)c * ldr;
+  double z[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = lane + 64 * q;
+    z[q] = i < n ? r[i] : 0.0;
+  }
+  auto fetch = [&](int k, double (&vr)[4]) {
+    const double* vk = refl + (int64_t)k * n;
+    const int m = n - k - 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = lane + 64 * q - (k + 1);
+      vr[q] = (k <= n - 3 && i >= 0 && i < m) ? vk[i] : 0.0;
+    }
+  };
+  double vr[4], vn[4];
+  double tk = tau[0];
+  fetch(0, vr);
+  for (int k = 0; k <= n - 3; ++k) {
+    const double tnext = k + 1 <= n - 3 ? tau[k + 1] : 0.0;
+    fetch(k + 1, vn);
+    if (tk != 0.0) {   // uniform
+      double t = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) t += vr[q] * z[q];
+      t = tr_wave_sum(t) * tk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) z[q] -= t * vr[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) vr[q] = vn[q];
+    tk = tnext;
+  }
+  double* hc = h + ((int64_t)b * C + c) * nmax;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = lane + 64 * q;
+    if (i < n) hc[i] = z[q];
+  }
+}
+
+// 6. (right-hand sides) w_i = lambda_i and R(i, c) = (Z^T h_c)_i for i < n, zero for n <= i < ldr; one wave
+// per (i, matrix).  Nothing is written when the cluster flag is set (the caller falls back with R intact).
+__global__ __launch_bounds__(64) void k_tri_rot(const double* Z, const double* lam, const double* h, TriSizes sz,
+                                                int nmax, int C, const double* flag, double* w, double* R, int ldr,
+                                                int64_t strideR) {
+  if (flag[0] != 0.0) return;
+  const int i = blockIdx.x, b = blockIdx.y, lane = threadIdx.x, n = sz.n[b];
+  double* rb = R + b * strideR;
+  if (i >= n) {
+    for (int c = lane; c < C; c += 64) rb[(int64_t)c * ldr + i] = 0.0;
+    if (lane == 0) w[(int64_t)b * ldr + i] = 0.0;
+    return;
+  }
+  const double* Zb = Z + (int64_t)b * nmax * nmax;   // Z(j, i) at j * n + i
+  for (int c = 0; c < C; ++c) {
+    const double* hc = h + ((int64_t)b * C + c) * nmax;
+    double t = 0.0;
+    for (int j = lane; j < n; j += 64) t += Zb[(int64_t)j * n + i] * hc[j];
+    t = tr_wave_sum(t);
+    if (lane == 0) rb[(int64_t)c * ldr + i] = t;
+  }
+  if (lane == 0) w[(int64_t)b * ldr + i] = lam[(int64_t)b * nmax + i];
+}
+
+static void tri_attrs() {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tridiag), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kLdsLimit);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tri_invit), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kLdsLimit);
+    attr = true;
+  }
+}
+
+size_t tridiag_rhs_work_count(int nmax, int count, int C) {
+  return (size_t)count * (2 * (size_t)nmax * nmax + (size_t)(4 + C) * nmax) + 8;
+}
+
+int syev_tridiag_rhs(const double* A, int ld, const int* sizes, int count, double* R, int C, double* w, double* work,
+                     size_t work_count, hipStream_t s) {
+  RW_CHECK(count >= 1 && count <= kTriBatchMax && C >= 1, RW_EINVAL, "batched tridiagonal solver: bad batch");
+  TriSizes sz;
+  int nmax = 0;
+  for (int b = 0; b < count; ++b) {
+    RW_CHECK(tridiag_fits(sizes[b]) && sizes[b] <= ld, RW_EINVAL, "batched tridiagonal solver: n = %d", sizes[b]);
+    sz.n[b] = sizes[b];
+    nmax = std::max(nmax, sizes[b]);
+  }
+  RW_CHECK(work_count >= tridiag_rhs_work_count(nmax, count, C), RW_EWORKSPACE, "batched tridiagonal solver: "
+           "workspace too small");
+  const size_t nn = (size_t)nmax * nmax;
+  double* refl = work;
+  double* Z = refl + count * nn;
+  double* tau = Z + count * nn;
+  double* d = tau + (size_t)count * nmax;
+  double* e = d + (size_t)count * nmax;
+  double* lam = e + (size_t)count * nmax;
+  double* h = lam + (size_t)count * nmax;
+  double* flag = h + (size_t)count * nmax * C;
+  tri_attrs();
+  const int64_t strideR = (int64_t)ld * C;
+  k_tri_clear<<<1, 1, 0, s>>>(flag);
+  k_tridiag<<<count, 1024, tridiag_lds_bytes(nmax), s>>>(A, ld, (int64_t)ld * ld, sz, nmax, refl, tau, d, e);
+  k_tri_rhs<<<dim3(C, count), 64, 0, s>>>(refl, tau, sz, nmax, R, ld, strideR, C, h);
+  k_tri_bisect<<<dim3(nmax, count), 64, 0, s>>>(d, e, sz, nmax, lam, flag);
+  k_tri_invit<<<dim3((nmax + kInvitThreads - 1) / kInvitThreads, count), kInvitThreads, invit_lds_bytes(nmax), s>>>(
+      d, e, sz, nmax, lam, Z);
+  k_tri_rot<<<dim3(ld, count), 64, 0, s>>>(Z, lam, h, sz, nmax, C, flag, w, R, ld, strideR);
+  RW_LAUNCH_CHECK();
+  double fl = 0.0;
+  RW_HIP(hipMemcpyAsync(&fl, flag, sizeof(double), hipMemcpyDeviceToHost, s));
+  RW_HIP(hipStreamSynchronize(s));
+  return fl != 0.0 ? RW_ENOCONV : RW_OK;
+}
+
 int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hipStream_t s) {
   RW_CHECK(tridiag_fits(n), RW_EINVAL, "tridiagonal eigensolver: n = %d out of range", n);
   const TriBufs b = tri_bufs(work, n);
-  static bool attr = false;
-  if (!attr) {
-    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_tridiag), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)kLdsLimit));
-    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_tri_invit), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)kLdsLimit));
-    attr = true;
-  }
+  tri_attrs();
+  TriSizes sz;
+  sz.n[0] = n;
   k_tri_clear<<<1, 1, 0, s>>>(b.flag);
-  k_tridiag<<<1, 1024, tridiag_lds_bytes(n), s>>>(A, n, b.refl, b.tau, b.d, b.e);
-  k_tri_bisect<<<n, 64, 0, s>>>(b.d, b.e, n, b.lam, b.flag);
-  k_tri_invit<<<(n + kInvitThreads - 1) / kInvitThreads, kInvitThreads, invit_lds_bytes(n), s>>>(b.d, b.e, n, b.lam,
-                                                                                                b.Z);
+  k_tridiag<<<1, 1024, tridiag_lds_bytes(n), s>>>(A, n, 0, sz, n, b.refl, b.tau, b.d, b.e);
+  k_tri_bisect<<<n, 64, 0, s>>>(b.d, b.e, sz, n, b.lam, b.flag);
+  k_tri_invit<<<(n + kInvitThreads - 1) / kInvitThreads, kInvitThreads, invit_lds_bytes(n), s>>>(b.d, b.e, sz, n,
+                                                                                                b.lam, b.Z);
   k_tri_back<<<n, 64, 0, s>>>(b.refl, b.tau, n, b.Z, V);
   RW_LAUNCH_CHECK();
   double flag = 0.0;
