@@ -374,6 +374,21 @@ int rw_dense_syev_tridiag_workspace_bytes(int n, size_t* bytes);
 int rw_dense_syev_tridiag(const double* A, double* w, double* V, int n, void* work, size_t work_bytes,
                           hipStream_t stream);
 
+/* Eigenvalues and rotated right-hand sides of a batch of symmetric matrices through their tridiagonal
+ * forms, the per-candidate eigenproblem of the choice of m (Sec. III-A1: one eigendecomposition per
+ * candidate serves the secular equations of all labels).  Matrix b (device, column-major, leading
+ * dimension ld, matrices ld*ld apart, read only) has order sizes[b] (host array, 3 <= sizes[b] <= min(ld,
+ * 199)); its right-hand sides R_b (device, ld x nrhs column-major, batches ld*nrhs apart) are replaced by
+ * V_b^T R_b and w_b (device, ld per matrix) receives the eigenvalues in ascending order; rows
+ * sizes[b] .. ld-1 of both are set to zero.  1 <= count <= 32.  When two eigenvalues of some matrix are
+ * closer than 1e-6 of its largest Gershgorin row sum the call returns RW_ENOCONV and leaves w and R
+ * unchanged (the Jacobi routine serves then).  work: device buffer of
+ * rw_dense_eig_rhs_batched_workspace_bytes(max size, count, nrhs).  Synchronizes `stream`.
+ * Errors: RW_EINVAL, RW_EWORKSPACE, RW_ENOCONV. */
+int rw_dense_eig_rhs_batched_workspace_bytes(int nmax, int count, int nrhs, size_t* bytes);
+int rw_dense_eig_rhs_batched(const double* A, int ld, const int* sizes, int count, double* R, int nrhs, double* w,
+                             void* work, size_t work_bytes, hipStream_t stream);
+
 /* Solve A X = B by LU with partial pivoting (device, A n x n and B n x nrhs column-major, both
  * overwritten; X returned in B).  stat (device, 1 double) = min |pivot| / max |a_ij|, or 0 when a pivot
  * falls below 1e-14 max |a_ij| (B is then not a solution). */

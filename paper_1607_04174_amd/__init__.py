@@ -107,6 +107,9 @@ _SIGS = {
     "rw_dense_syev": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_size_t,
                                  ct.c_void_p]),
     "rw_dense_syev_tridiag_workspace_bytes": (ct.c_int, [ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_dense_eig_rhs_batched_workspace_bytes": (ct.c_int, [ct.c_int, ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_dense_eig_rhs_batched": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int,
+                                            ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "rw_dense_syev_tridiag": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_size_t,
                                          ct.c_void_p]),
     "rw_dense_lu_solve": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p]),
@@ -437,6 +440,25 @@ def dense_syev_tridiag(A: torch.Tensor):
     work = _workspace(nb.value, A.device)
     _check(lib().rw_dense_syev_tridiag(_ptr(A), _ptr(w), _ptr(V), n, _ptr(work), nb.value, _stream(A.device)))
     return w, V
+
+
+def dense_eig_rhs_batched(A: torch.Tensor, sizes, R: torch.Tensor):
+    """Eigenvalues and rotated right-hand sides of a batch of symmetric FP64 matrices A (count, ld, ld),
+    each read column-major with order sizes[b], right-hand sides R (count, nrhs, ld) (column-major ld x nrhs
+    per matrix).  Returns (w (count, ld), R' (count, nrhs, ld)) with R'_b = V_b^T R_b and zero rows beyond
+    sizes[b].  Raises RWError with RW_ENOCONV when some matrix has clustered eigenvalues."""
+    A = A.contiguous()
+    count, ld = A.shape[0], A.shape[1]
+    nrhs = R.shape[1]
+    Rout = R.clone().contiguous()
+    w = torch.empty((count, ld), dtype=torch.float64, device=A.device)
+    sz = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32))
+    nb = ct.c_size_t()
+    _check(lib().rw_dense_eig_rhs_batched_workspace_bytes(int(sz.max()), count, nrhs, ct.byref(nb)))
+    work = _workspace(nb.value, A.device)
+    _check(lib().rw_dense_eig_rhs_batched(_ptr(A), ld, ct.c_void_p(sz.ctypes.data), count, _ptr(Rout), nrhs, _ptr(w),
+                                          _ptr(work), nb.value, _stream(A.device)))
+    return w, Rout
 
 
 def dense_lu_solve(A: torch.Tensor, B: torch.Tensor):

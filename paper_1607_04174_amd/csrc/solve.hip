@@ -377,7 +377,7 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 constexpr int kScreenMaxKM = 192;   // three entries per lane in the inverse's back substitution
 
 static size_t screen_lds_bytes(int KM, int C) {
-  return ((size_t)KM * (KM + 1) + 2 * (size_t)KM * C + KM + 3 * (size_t)C) * sizeof(double);
+  return ((size_t)KM * (KM + 1) + 2 * (size_t)KM * C + 2 * (size_t)KM + 3 * (size_t)C) * sizeof(double);
 }
 
 static int screen_cols(int ma, int C) {
@@ -391,13 +391,14 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int6
                                                      double* F, int* cls) {
   extern __shared__ double sm[];
   const int tri = KM * (KM + 1) / 2;
-  double* A = sm;              // packed lower (column-major): Schur complements, then L; later Ri (packed upper)
+  double* A = sm;              // packed lower (column-major): G_m, then L column by column; later Ri (packed upper)
   double* B = A + tri;         // packed upper: L^T, later the prefix sums P
   double* G = B + tri;         // KM x C right-hand sides g = Q_s^T u, updated
   double* Z = G + KM * C;      // KM x C, z = L^{-1} g
   double* rd = Z + KM * C;     // 1 / L(k, k)
   double* sr = rd + KM;        // 2 x C running residuals (alternating by column parity)
   double* sbn = sr + 2 * C;    // ||b||^2 per label
+  double* gd = sbn + C;        // diagonal of G_m (the pivot test and the error bound read it)
   __shared__ int s_kf;
   const int tid = threadIdx.x;
   if (tid < 64) {
@@ -416,12 +417,12 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int6
     if (i >= j) A[scr_lo(i, j, KM)] = Gq[i + (int64_t)j * ma];
   }
   for (int t = tid; t < KM * C; t += blockDim.x) G[t] = Gb[t % KM + (int64_t)(t / KM) * ma];
+  for (int t = tid; t < KM; t += blockDim.x) gd[t] = Gq[t + (int64_t)t * ma];
   if (tid == 0) s_kf = KM;
   __syncthreads();
-  // Cholesky with early stop: at the first small pivot (numerically singular leading block) or as soon as
-  // every label's residual r(k) is at most f_max (no larger m is needed: the first m that can pass is at
-  // most k)
-  const int tx = tid & 31, ty = tid >> 5;
+  // Cholesky with early stop, left-looking (column k of L is formed from the earlier columns only when its
+  // step comes): stop at the first small pivot (numerically singular leading block) or as soon as every
+  // label's residual r(k) is at most f_max (no larger m is needed: the first m that can pass is at most k)
   for (int k = 0; k < KM; ++k) {
     const double* srk = sr + (k & 1) * C;
     if (k > 0) {
@@ -432,36 +433,41 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int6
         break;
       }
     }
+    {   // Schur column c_i = A(i, k) - sum_{j<k} L(i, j) L(k, j), rows i >= k: one quad of lanes per row
+      const int r = tid >> 2, sub = tid & 3, i = k + r;
+      double acc = 0.0;
+      if (i < KM)
+        for (int j = sub; j < k; j += 4) acc += A[scr_lo(i, j, KM)] * A[scr_lo(k, j, KM)];
+      acc = quad_sum(acc);
+      if (sub == 0 && i < KM) A[scr_lo(i, k, KM)] -= acc;
+    }
+    lds_barrier();
     const double dkk = A[scr_lo(k, k, KM)];
-    if (!(dkk > 1e-12 * Gq[k + (int64_t)k * ma]) || !isfinite(dkk)) {   // uniform
+    if (!(dkk > 1e-12 * gd[k]) || !isfinite(dkk)) {   // uniform
       if (tid == 0) s_kf = k;
       break;
     }
-    const double lkk = sqrt(dkk);
+    const double lkk = sqrt(dkk), rk = 1.0 / lkk;
     if (tid < C) {
       const double z = G[k + tid * KM] / lkk;
       Z[k + tid * KM] = z;
       sr[((k + 1) & 1) * C + tid] = srk[tid] - z * z;
     }
-    if (tid == 0) rd[k] = 1.0 / lkk;
-    const double inv = 1.0 / dkk;
-    for (int j = k + 1 + ty; j < KM; j += 32) {
-      const double ajk = A[scr_lo(j, k, KM)] * inv;
-      for (int i = j + tx; i < KM; i += 32) A[scr_lo(i, j, KM)] -= A[scr_lo(i, k, KM)] * ajk;
-    }
-    const int rows = KM - k - 1;
-    for (int t = tid; t < rows * C; t += blockDim.x) {
-      const int i = k + 1 + t % rows, c = t / rows;
-      G[i + c * KM] -= A[scr_lo(i, k, KM)] * (G[k + c * KM] * inv);
+    if (tid == 0) rd[k] = rk;
+    // L(i, k) = c_i / L(k, k) below the diagonal, and the right-hand sides g_i -= L(i, k) z_k
+    for (int i = k + 1 + tid; i < KM; i += blockDim.x) {
+      const double l = A[scr_lo(i, k, KM)] * rk;
+      A[scr_lo(i, k, KM)] = l;
+      for (int c = 0; c < C; ++c) G[i + c * KM] -= l * (G[k + c * KM] * rk);
     }
     lds_barrier();
   }
   __syncthreads();
   const int kf = s_kf;      // leading blocks of size <= kf are factorized
-  // L^T (packed upper) from the scaled columns
+  // L^T (packed upper)
   for (int t = tid; t < kf * kf; t += blockDim.x) {
     const int i = t % kf, j = t / kf;
-    if (i > j) B[scr_up(j, i)] = A[scr_lo(i, j, KM)] * rd[j];
+    if (i > j) B[scr_up(j, i)] = A[scr_lo(i, j, KM)];
   }
   __syncthreads();
   // Ri = L^{-T} (packed upper, over A): column j solves L^T x = e_j; columns are spread over the waves
@@ -502,7 +508,7 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int6
   const int m = 1 + tid;
   double trg = 0.0;
   if (m <= kf)
-    for (int k = 0; k < m; ++k) trg += Gq[k + (int64_t)k * ma];
+    for (int k = 0; k < m; ++k) trg += gd[k];
   // Gram rounding (S terms per entry) plus the factorization's (m^2): ||E|| <= 16 (m^2 + S) u trace(G_m)
   const double ebound = 16.0 * ((double)m * (double)m + (double)S) * 1.1102230246251565e-16 * trg;
   double rmax = 0.0;

@@ -170,33 +170,49 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
 
 // Sturm count: the number of eigenvalues of T below sigma (the negative pivots of LDL^T of T - sigma I,
 // a pivot of magnitude below pivmin taken as -pivmin)
+// 1 / q from the hardware reciprocal and two Newton steps (relative error of a few units in the last place,
+// a perturbation of the same order as the rounding the count tolerates; |q| >= pivmin keeps it finite)
+__device__ __forceinline__ double tr_recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
+}
+
 __device__ __forceinline__ int tr_sturm(const double* d, const double* e2, int n, double sigma, double pivmin) {
   double q = d[0] - sigma;
   if (fabs(q) < pivmin) q = -pivmin;
   int cnt = q < 0.0;
   for (int j = 1; j < n; ++j) {
-    q = (d[j] - sigma) - e2[j - 1] / q;
+    q = (d[j] - sigma) - e2[j - 1] * tr_recip(q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
   return cnt;
 }
 
-// 2. eigenvalue idx = blockIdx.x (ascending) by 64-point bisection; flag[0] = 1 if two eigenvalues are
-// closer than 1e-6 |T| (checked by the wave of the larger one)
-__global__ __launch_bounds__(64) void k_tri_bisect(const double* dg, const double* eg, TriSizes sz, int nmax,
-                                                   double* lam, double* flag) {
+// 2. eigenvalue idx = blockIdx.x (ascending) by multisection: each pass evaluates Sturm counts at
+// kBisThreads interior points of [a, b] (one per thread) and keeps the subinterval where the count passes
+// idx (the interval shrinks (kBisThreads + 1)-fold per pass); flag[0] = 1 if two eigenvalues are closer
+// than 1e-6 |T| (checked by the workgroup of the smaller one)
+constexpr int kBisThreads = 256;
+__global__ __launch_bounds__(kBisThreads) void k_tri_bisect(const double* dg, const double* eg, TriSizes sz,
+                                                            int nmax, double* lam, double* flag) {
   __shared__ double d[256], e2[256];
-  const int idx = blockIdx.x, lane = threadIdx.x, n = sz.n[blockIdx.y];
+  __shared__ int s_cnt[2][kBisThreads / 64];
+  const int idx = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = sz.n[blockIdx.y];
   if (idx >= n) return;   // the whole workgroup
   dg += (int64_t)blockIdx.y * nmax;
   eg += (int64_t)blockIdx.y * nmax;
   lam += (int64_t)blockIdx.y * nmax;
+  // Gershgorin bounds, in every wave (identical results)
   double lo = INFINITY, hi = -INFINITY, tn = 0.0, emax = 0.0;
   for (int j = lane; j < n; j += 64) {
-    d[j] = dg[j];
     const double el = j > 0 ? fabs(eg[j - 1]) : 0.0, er = j < n - 1 ? fabs(eg[j]) : 0.0;
-    if (j < n - 1) e2[j] = eg[j] * eg[j];
+    if (wave == 0) {
+      d[j] = dg[j];
+      if (j < n - 1) e2[j] = eg[j] * eg[j];
+    }
     lo = fmin(lo, dg[j] - el - er);
     hi = fmax(hi, dg[j] + el + er);
     tn = fmax(tn, fabs(dg[j]) + el + er);
@@ -209,24 +225,30 @@ __global__ __launch_bounds__(64) void k_tri_bisect(const double* dg, const doubl
   __syncthreads();
   const double pivmin = 2.3e-308 * fmax(1.0, emax);
   const double atol = 4.0 * 2.3e-16 * fmax(tn, 1e-300);
-  double a = lo - atol, b = hi + atol;   // count(a) <= idx < count(b)
-  for (int it = 0; it < 16 && b - a > atol; ++it) {   // a, b identical in every lane
-    const double sigma = a + (b - a) * (double)(lane + 1) / 65.0;
+  constexpr double kParts = kBisThreads + 1;
+  double a = lo - atol, b = hi + atol;   // count(a) <= idx < count(b); a, b identical in every thread
+  for (int it = 0; it < 16 && b - a > atol; ++it) {
+    const double sigma = a + (b - a) * (double)(tid + 1) / kParts;
     const int cnt = tr_sturm(d, e2, n, sigma, pivmin);
-    const unsigned long long le = __ballot(cnt <= idx);   // counts grow with sigma: lanes 0..L-1
-    const int L = __popcll(le);
-    const double na = L > 0 ? a + (b - a) * (double)L / 65.0 : a;
-    const double nb = L < 64 ? a + (b - a) * (double)(L + 1) / 65.0 : b;
+    const unsigned long long le = __ballot(cnt <= idx);   // counts grow with sigma: threads 0..L-1
+    if (lane == 0) s_cnt[it & 1][wave] = __popcll(le);
+    __syncthreads();
+    int L = 0;
+#pragma unroll
+    for (int w = 0; w < kBisThreads / 64; ++w) L += s_cnt[it & 1][w];
+    const double na = L > 0 ? a + (b - a) * (double)L / kParts : a;
+    const double nb = L < kBisThreads ? a + (b - a) * (double)(L + 1) / kParts : b;
     a = na;
     b = nb;
   }
   const double lam_i = 0.5 * (a + b);
-  if (lane == 0) lam[idx] = lam_i;
-  // separation from the next eigenvalue, measured from this wave's own side: the next eigenvalue lies
+  if (tid == 0) lam[idx] = lam_i;
+  // separation from the next eigenvalue, measured from this workgroup's own side: the next eigenvalue lies
   // above b - atol; a count at lam_i + 1e-6 |T| that exceeds idx + 1 means another eigenvalue is within
-  const double probe = lam_i + 1e-6 * tn;
-  const int c2 = lane == 0 ? tr_sturm(d, e2, n, probe, pivmin) : 0;
-  if (lane == 0 && idx + 1 < n && c2 > idx + 1) flag[0] = 1.0;
+  if (tid == 0 && idx + 1 < n) {
+    const int c2 = tr_sturm(d, e2, n, lam_i + 1e-6 * tn, pivmin);
+    if (c2 > idx + 1) flag[0] = 1.0;
+  }
 }
 
 // 3. inverse iteration: eigenvector i = global thread index, three solves with LDL^T of T - lambda_i I
@@ -234,6 +256,7 @@ __global__ __launch_bounds__(64) void k_tri_bisect(const double* dg, const doubl
 // T, its threads' factors (L_j and 1 / D_j) and iterates in LDS, entry j of thread t at j * 32 + t;
 // Z(j, i) is written at j * n + i.
 constexpr int kInvitThreads = 32;
+constexpr int kInvB = 8;   // rows of a recurrence staged in registers at a time
 static size_t invit_lds_bytes(int n) { return ((size_t)n * (2 + 3 * kInvitThreads)) * sizeof(double); }
 
 __global__ __launch_bounds__(kInvitThreads) void k_tri_invit(const double* dg, const double* eg, TriSizes sz,
@@ -262,41 +285,105 @@ __global__ __launch_bounds__(kInvitThreads) void k_tri_invit(const double* dg, c
   if (i >= n) return;
   const double pivmin = 2.3e-16 * fmax(tn, 1e-300);
   const double l = lam[i];
+  // Each recurrence below runs over whole blocks of kInvB rows whose operands are loaded into registers
+  // first and whose results are stored after (a step then waits for arithmetic, not for an LDS round trip),
+  // and over the remaining rows one at a time.
   // factor: D_0 = d_0 - l, L_j = e_{j-1} / D_{j-1}, D_j = d_j - l - L_j e_{j-1}
   double D = d[0] - l;
   if (fabs(D) < pivmin) D = D < 0.0 ? -pivmin : pivmin;
   double r = 1.0 / D;
   rD[t] = r;
-  for (int j = 1; j < n; ++j) {
+  int j = 1;
+  for (; j + kInvB <= n; j += kInvB) {
+    double dv[kInvB], ev[kInvB], Lv[kInvB], rv[kInvB];
+#pragma unroll
+    for (int u = 0; u < kInvB; ++u) {
+      dv[u] = d[j + u];
+      ev[u] = e[j + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kInvB; ++u) {
+      const double Lj = ev[u] * r;
+      double Dj = (dv[u] - l) - Lj * ev[u];
+      if (fabs(Dj) < pivmin) Dj = Dj < 0.0 ? -pivmin : pivmin;
+      r = 1.0 / Dj;
+      Lv[u] = Lj;
+      rv[u] = r;
+    }
+#pragma unroll
+    for (int u = 0; u < kInvB; ++u) {
+      Lf[(j + u) * kInvitThreads + t] = Lv[u];
+      rD[(j + u) * kInvitThreads + t] = rv[u];
+    }
+  }
+  for (; j < n; ++j) {
     const double Lj = e[j - 1] * r;
-    D = (d[j] - l) - Lj * e[j - 1];
-    if (fabs(D) < pivmin) D = D < 0.0 ? -pivmin : pivmin;
-    r = 1.0 / D;
+    double Dj = (d[j] - l) - Lj * e[j - 1];
+    if (fabs(Dj) < pivmin) Dj = Dj < 0.0 ? -pivmin : pivmin;
+    r = 1.0 / Dj;
     Lf[j * kInvitThreads + t] = Lj;
     rD[j * kInvitThreads + t] = r;
   }
   // start vector: deterministic, with no special structure
-  for (int j = 0; j < n; ++j) z[j * kInvitThreads + t] = 1.0 + 0.5 * sin(0.7 * j + 1.3 * i + 0.1);
+  for (int jj = 0; jj < n; ++jj) z[jj * kInvitThreads + t] = 1.0 + 0.5 * sin(0.7 * jj + 1.3 * i + 0.1);
+  double inv = 1.0;   // the previous iteration's 1 / ||x||, applied as b is read
   for (int it = 0; it < 3; ++it) {
-    // forward: y_j = b_j - L_j y_{j-1}; then y / D; backward: x_j = y_j / D_j - L_{j+1} x_{j+1}
-    double y = z[t];
-    for (int j = 1; j < n; ++j) {
-      y = z[j * kInvitThreads + t] - Lf[j * kInvitThreads + t] * y;
+    // forward: y_j = b_j - L_j y_{j-1}
+    double y = z[t] * inv;
+    z[t] = y;
+    j = 1;
+    for (; j + kInvB <= n; j += kInvB) {
+      double zv[kInvB], lv[kInvB];
+#pragma unroll
+      for (int u = 0; u < kInvB; ++u) {
+        zv[u] = z[(j + u) * kInvitThreads + t] * inv;
+        lv[u] = Lf[(j + u) * kInvitThreads + t];
+      }
+#pragma unroll
+      for (int u = 0; u < kInvB; ++u) {
+        y = zv[u] - lv[u] * y;
+        zv[u] = y;
+      }
+#pragma unroll
+      for (int u = 0; u < kInvB; ++u) z[(j + u) * kInvitThreads + t] = zv[u];
+    }
+    for (; j < n; ++j) {
+      y = z[j * kInvitThreads + t] * inv - Lf[j * kInvitThreads + t] * y;
       z[j * kInvitThreads + t] = y;
     }
+    // backward: x_{n-1} = y_{n-1} / D_{n-1}, x_j = y_j / D_j - L_{j+1} x_{j+1}
     double x = y * rD[(n - 1) * kInvitThreads + t];
     z[(n - 1) * kInvitThreads + t] = x;
     double nrm = x * x;
-    for (int j = n - 2; j >= 0; --j) {
+    j = n - 2;
+    for (; j - kInvB + 1 >= 0; j -= kInvB) {
+      double zv[kInvB], rv[kInvB], lv[kInvB];
+#pragma unroll
+      for (int u = 0; u < kInvB; ++u) {
+        zv[u] = z[(j - u) * kInvitThreads + t];
+        rv[u] = rD[(j - u) * kInvitThreads + t];
+        lv[u] = Lf[(j - u + 1) * kInvitThreads + t];
+      }
+#pragma unroll
+      for (int u = 0; u < kInvB; ++u) {
+        x = zv[u] * rv[u] - lv[u] * x;
+        zv[u] = x;
+        nrm += x * x;
+      }
+#pragma unroll
+      for (int u = 0; u < kInvB; ++u) z[(j - u) * kInvitThreads + t] = zv[u];
+    }
+    for (; j >= 0; --j) {
       x = z[j * kInvitThreads + t] * rD[j * kInvitThreads + t] - Lf[(j + 1) * kInvitThreads + t] * x;
       z[j * kInvitThreads + t] = x;
       nrm += x * x;
     }
-    const double inv = 1.0 / sqrt(nrm);
-    for (int j = 0; j < n; ++j) z[j * kInvitThreads + t] *= inv;
+    inv = 1.0 / sqrt(nrm);
   }
-  for (int j = 0; j < n; ++j) Z[(int64_t)j * n + i] = z[j * kInvitThreads + t];
+  for (int jj = 0; jj < n; ++jj) Z[(int64_t)jj * n + i] = z[jj * kInvitThreads + t] * inv;
 }
+
+constexpr int kTriAhead = 4;   // reflectors loaded ahead by the back-transform and the right-hand-side pass
 
 // 4. V(:, col) = H_0 H_1 ... H_{n-3} z, z = eigenvector col of T; V column-major n x n
 __global__ __launch_bounds__(64) void k_tri_back(const double* refl, const double* tau, int n, const double* Z,
@@ -318,23 +405,30 @@ __global__ __launch_bounds__(64) void k_tri_back(const double* refl, const doubl
       vr[q] = (k >= 0 && i >= 0 && i < m) ? vk[i] : 0.0;
     }
   };
-  double vr[4], vn[4];
-  double tk = n >= 3 ? tau[n - 3] : 0.0;
-  fetch(n - 3, vr);
-  for (int k = n - 3; k >= 0; --k) {
-    const double tnext = k > 0 ? tau[k - 1] : 0.0;
-    fetch(k - 1, vn);
-    if (tk != 0.0) {
-      double s = 0.0;
+  // reflectors k, k-1, .., k-3 in flight (an L2 load takes longer than a step)
+  double vb[kTriAhead][4], tb[kTriAhead];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) s += vr[q] * z[q];
-      s = tr_wave_sum(s) * tk;
+  for (int u = 0; u < kTriAhead; ++u) {
+    fetch(n - 3 - u, vb[u]);
+    tb[u] = n - 3 - u >= 0 ? tau[n - 3 - u] : 0.0;
+  }
+  for (int k0 = n - 3; k0 >= 0; k0 -= kTriAhead) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) z[q] -= s * vr[q];
+    for (int u = 0; u < kTriAhead; ++u) {
+      const int k = k0 - u;
+      if (k < 0) break;
+      const double tk = tb[u];
+      if (tk != 0.0) {   // uniform
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s += vb[u][q] * z[q];
+        s = tr_wave_sum(s) * tk;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) z[q] -= s * vb[u][q];
+      }
+      fetch(k - kTriAhead, vb[u]);
+      tb[u] = k - kTriAhead >= 0 ? tau[k - kTriAhead] : 0.0;
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) vr[q] = vn[q];
-    tk = tnext;
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -368,23 +462,29 @@ __global__ __launch_bounds__(64) void k_tri_rhs(const double* refl, const double
       vr[q] = (k <= n - 3 && i >= 0 && i < m) ? vk[i] : 0.0;
     }
   };
-  double vr[4], vn[4];
-  double tk = tau[0];
-  fetch(0, vr);
-  for (int k = 0; k <= n - 3; ++k) {
-    const double tnext = k + 1 <= n - 3 ? tau[k + 1] : 0.0;
-    fetch(k + 1, vn);
-    if (tk != 0.0) {   // uniform
-      double t = 0.0;
+  double vb[kTriAhead][4], tb[kTriAhead];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) t += vr[q] * z[q];
-      t = tr_wave_sum(t) * tk;
+  for (int u = 0; u < kTriAhead; ++u) {
+    fetch(u, vb[u]);
+    tb[u] = u <= n - 3 ? tau[u] : 0.0;
+  }
+  for (int k0 = 0; k0 <= n - 3; k0 += kTriAhead) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) z[q] -= t * vr[q];
+    for (int u = 0; u < kTriAhead; ++u) {
+      const int k = k0 + u;
+      if (k > n - 3) break;
+      const double tk = tb[u];
+      if (tk != 0.0) {   // uniform
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t += vb[u][q] * z[q];
+        t = tr_wave_sum(t) * tk;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) z[q] -= t * vb[u][q];
+      }
+      fetch(k + kTriAhead, vb[u]);
+      tb[u] = k + kTriAhead <= n - 3 ? tau[k + kTriAhead] : 0.0;
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) vr[q] = vn[q];
-    tk = tnext;
   }
   double* hc = h + ((int64_t)b * C + c) * nmax;
 #pragma unroll
@@ -459,7 +559,7 @@ int syev_tridiag_rhs(const double* A, int ld, const int* sizes, int count, doubl
   k_tri_clear<<<1, 1, 0, s>>>(flag);
   k_tridiag<<<count, 1024, tridiag_lds_bytes(nmax), s>>>(A, ld, (int64_t)ld * ld, sz, nmax, refl, tau, d, e);
   k_tri_rhs<<<dim3(C, count), 64, 0, s>>>(refl, tau, sz, nmax, R, ld, strideR, C, h);
-  k_tri_bisect<<<dim3(nmax, count), 64, 0, s>>>(d, e, sz, nmax, lam, flag);
+  k_tri_bisect<<<dim3(nmax, count), kBisThreads, 0, s>>>(d, e, sz, nmax, lam, flag);
   k_tri_invit<<<dim3((nmax + kInvitThreads - 1) / kInvitThreads, count), kInvitThreads, invit_lds_bytes(nmax), s>>>(
       d, e, sz, nmax, lam, Z);
   k_tri_rot<<<dim3(ld, count), 64, 0, s>>>(Z, lam, h, sz, nmax, C, flag, w, R, ld, strideR);
@@ -478,7 +578,7 @@ int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hip
   sz.n[0] = n;
   k_tri_clear<<<1, 1, 0, s>>>(b.flag);
   k_tridiag<<<1, 1024, tridiag_lds_bytes(n), s>>>(A, n, 0, sz, n, b.refl, b.tau, b.d, b.e);
-  k_tri_bisect<<<n, 64, 0, s>>>(b.d, b.e, sz, n, b.lam, b.flag);
+  k_tri_bisect<<<n, kBisThreads, 0, s>>>(b.d, b.e, sz, n, b.lam, b.flag);
   k_tri_invit<<<(n + kInvitThreads - 1) / kInvitThreads, kInvitThreads, invit_lds_bytes(n), s>>>(b.d, b.e, sz, n,
                                                                                                 b.lam, b.Z);
   k_tri_back<<<n, 64, 0, s>>>(b.refl, b.tau, n, b.Z, V);
@@ -510,6 +610,23 @@ int rw_dense_syev_tridiag(const double* A, double* w, double* V, int n, void* wo
   RW_CHECK(work_bytes >= tridiag_work_count(n) * sizeof(double), RW_EWORKSPACE, "workspace too small");
   const int st = syev_tridiag(A, w, V, n, static_cast<double*>(work), stream);
   if (st == RW_ENOCONV) set_error("tridiagonal eigensolver: clustered eigenvalues (use the Jacobi routine)");
+  return st;
+}
+
+int rw_dense_eig_rhs_batched_workspace_bytes(int nmax, int count, int nrhs, size_t* bytes) {
+  RW_CHECK(bytes != nullptr && tridiag_fits(nmax) && count >= 1 && count <= kTriBatchMax && nrhs >= 1, RW_EINVAL,
+           "bad sizes (nmax = %d, count = %d, nrhs = %d)", nmax, count, nrhs);
+  *bytes = tridiag_rhs_work_count(nmax, count, nrhs) * sizeof(double);
+  return RW_OK;
+}
+
+int rw_dense_eig_rhs_batched(const double* A, int ld, const int* sizes, int count, double* R, int nrhs, double* w,
+                             void* work, size_t work_bytes, hipStream_t stream) {
+  RW_CHECK(A != nullptr && sizes != nullptr && R != nullptr && w != nullptr && work != nullptr, RW_EINVAL,
+           "null argument");
+  const int st = syev_tridiag_rhs(A, ld, sizes, count, R, nrhs, w, static_cast<double*>(work),
+                                  work_bytes / sizeof(double), stream);
+  if (st == RW_ENOCONV) set_error("batched tridiagonal solver: clustered eigenvalues (use the Jacobi routine)");
   return st;
 }
 

@@ -65,6 +65,44 @@ def test_syev_tridiag_matches_numpy(n):
             rw.dense_syev_tridiag(to_dev(0.5 * (A + A.T).T, torch.float64))
 
 
+def test_eig_rhs_batched_matches_numpy():
+    """The choice-of-m eigenproblem through the tridiagonal form: a batch of Gram matrices of different
+    orders inside one leading dimension (entries beyond each order hold garbage that must not be read),
+    against numpy: ascending eigenvalues, and V^T R compared through the sign-free products
+    (V^T R)_ic (V^T R)_id; rows beyond each order come back zero.  A clustered spectrum is refused."""
+    need_gpu()
+    banner("eig rhs batched")
+    rng = np.random.default_rng(31)
+    ld, nrhs = 90, 3
+    sizes = [88, 60, 90, 3, 45]
+    A = rng.standard_normal((len(sizes), ld, ld))            # garbage everywhere, then the leading blocks
+    R = rng.standard_normal((len(sizes), nrhs, ld))
+    for b, n in enumerate(sizes):
+        X = rng.standard_normal((150, n))
+        A[b, :n, :n] = (X.T @ X).T                           # column-major storage of a symmetric matrix
+    w, Rp = rw.dense_eig_rhs_batched(to_dev(A, torch.float64), sizes, to_dev(R, torch.float64))
+    w, Rp = w.cpu().numpy(), Rp.cpu().numpy()
+    for b, n in enumerate(sizes):
+        M = A[b, :n, :n].T
+        ev, V = np.linalg.eigh(M)
+        scale = np.abs(ev).max()
+        np.testing.assert_allclose(w[b, :n], ev, atol=1e-12 * scale)
+        assert np.all(w[b, n:] == 0.0) and np.all(Rp[b, :, n:] == 0.0)
+        ref = V.T @ R[b, :, :n].T                             # (n, nrhs)
+        got = Rp[b, :, :n].T
+        gap = np.min(np.diff(ev)) if n > 1 else scale
+        tol = 1e-12 * scale / gap * np.abs(R[b, :, :n]).max() ** 2 * n
+        for c in range(nrhs):
+            for d in range(nrhs):
+                np.testing.assert_allclose(got[:, c] * got[:, d], ref[:, c] * ref[:, d], atol=tol)
+    Qm, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    ev = np.concatenate([np.full(3, 0.5), np.linspace(1.0, 2.0, 37)])
+    C = np.zeros((1, ld, ld))
+    C[0, :40, :40] = ((Qm * ev) @ Qm.T).T
+    with pytest.raises(rw.RWError):
+        rw.dense_eig_rhs_batched(to_dev(C, torch.float64), [40], to_dev(R[:1], torch.float64))
+
+
 @pytest.mark.parametrize("n,nrhs", [(1, 1), (50, 3), (201, 4)])
 def test_lu_solve_matches_numpy(n, nrhs):
     need_gpu()
