@@ -294,13 +294,27 @@ __global__ __launch_bounds__(64) void k_fit_secular(const int* cand, int ncand, 
   for (int64_t i = lane; i < S; i += 64) bn += Us[i + (int64_t)k * S] * Us[i + (int64_t)k * S];
   const double bnorm2 = wave_sum(bn);
   const double rho2 = rho * rho;
+  // this lane's g_i^2 and w_i (i = lane + 64 q), held in registers across the bisection
+  constexpr int kQ = 16;   // ms <= 1024
+  const int nq = (ms + 63) / 64;
+  double g2v[kQ], wv[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int i = lane + 64 * q;
+    const bool in = q < nq && i < ms;
+    const double gi = in ? g[i] : 0.0;
+    g2v[q] = gi * gi;
+    wv[q] = in ? w[i] : 0.0;
+  }
   auto norm2 = [&](double mu) -> double {
     double acc = 0.0;
     int inf = 0;
-    for (int i = lane; i < ms; i += 64) {
-      double gi2 = g[i] * g[i];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      if (q >= nq) break;   // uniform
+      const double gi2 = g2v[q];
       if (gi2 == 0.0) continue;
-      double wi = fmax(w[i], 0.0), den = wi + mu;
+      const double wi = fmax(wv[q], 0.0), den = wi + mu;
       if (den <= 0.0) { inf = 1; continue; }
       acc += small_m ? gi2 / (den * den) : gi2 * wi / (den * den);
     }
@@ -310,10 +324,12 @@ __global__ __launch_bounds__(64) void k_fit_secular(const int* cand, int ncand, 
   };
   auto fval = [&](double mu) -> double {
     double acc = 0.0;
-    for (int i = lane; i < ms; i += 64) {
-      double gi2 = g[i] * g[i];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      if (q >= nq) break;   // uniform
+      const double gi2 = g2v[q];
       if (gi2 == 0.0) continue;
-      double wi = fmax(w[i], 0.0), den = wi + mu;
+      const double wi = fmax(wv[q], 0.0), den = wi + mu;
       if (small_m) acc += gi2 * (wi + 2.0 * mu) / (den * den);
       else acc += den > 0.0 ? gi2 * (mu / den) * (mu / den) : gi2;
     }
@@ -323,9 +339,14 @@ __global__ __launch_bounds__(64) void k_fit_secular(const int* cand, int ncand, 
   double mu = 0.0;
   if (!(norm2(0.0) <= rho2)) {
     double gn = 0.0, wm = 0.0;
-    for (int i = lane; i < ms; i += 64) {
-      gn += g[i] * g[i];
-      wm = fmax(wm, w[i]);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      if (q >= nq) break;   // uniform
+      const int i = lane + 64 * q;
+      if (i < ms) {
+        gn += g2v[q];
+        wm = fmax(wm, wv[q]);
+      }
     }
     gn = wave_sum(gn);
     wm = wave_max64(wm);
