@@ -257,6 +257,55 @@ __global__ void k_cc_init(GridDev G, const T* weight, const uint8_t* mask, int64
   comp[i] = c;
 }
 
+// 2D grids: the components within each 32 x 32 tile first, by min-label propagation over the tile's
+// anchoring edges in LDS (each step also jumps through the current label, which is a node of the same
+// component with an index no larger), until no label changes; then every node points to the smallest node
+// of its tile-local component.  The hooking rounds then only join tiles.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_cc_init_tile(GridDev G, const T* weight, const uint8_t* mask,
+                                                       int64_t* comp) {
+  __shared__ int lab[1024];
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5, me = threadIdx.x;
+  const int64_t x = (int64_t)blockIdx.x * 32 + lx, y = (int64_t)blockIdx.y * 32 + ly;
+  const bool in = x < G.nx && y < G.ny;
+  const int64_t i = y * G.nx + x;
+  // neighbours through anchoring edges inside the tile: slot 2 d forward, 2 d + 1 backward (the node itself
+  // when there is none, which changes nothing)
+  int nb[8];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    nb[2 * d] = me;
+    nb[2 * d + 1] = me;
+    if (!in || d >= G.ndir) continue;
+    if (((mask[i] >> d) & 1) && (double)weight[d * G.N + i] >= kAnchorWeight) {   // i -> i + off[d], stored at i
+      const int ax = lx + G.dx[d], ay = ly + G.dy[d];
+      if (ax >= 0 && ax < 32 && ay >= 0 && ay < 32 && head_in(G, x, y, 0, d)) nb[2 * d] = ay * 32 + ax;
+    }
+    if (tail_in(G, x, y, 0, d)) {   // i - off[d] -> i, stored at the tail
+      const int64_t t = i - G.off[d];
+      const int bx = lx - G.dx[d], by = ly - G.dy[d];
+      if (bx >= 0 && bx < 32 && by >= 0 && by < 32 && ((mask[t] >> d) & 1) &&
+          (double)weight[d * G.N + t] >= kAnchorWeight)
+        nb[2 * d + 1] = by * 32 + bx;
+    }
+  }
+  lab[me] = me;
+  __syncthreads();
+  for (;;) {
+    const int cur = lab[me];
+    int l = lab[cur];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) l = min(l, lab[nb[c]]);
+    const bool changed = l < cur;
+    if (changed) lab[me] = l;   // labels only decrease; a concurrent reader sees either value
+    if (!__syncthreads_or(changed)) break;
+  }
+  if (in) {
+    const int r = lab[me];
+    comp[i] = ((int64_t)blockIdx.y * 32 + (r >> 5)) * G.nx + (int64_t)blockIdx.x * 32 + (r & 31);
+  }
+}
+
 template <typename T>
 __global__ void k_cc_hook(GridDev G, const T* weight, const uint8_t* mask, int64_t* comp, int* changed) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -302,10 +351,17 @@ int graph_components(Graph* g, hipStream_t s) {
     }
   }
   const GridDev G = grid_of(g);
-  if (g->dtype == RW_F64)
+  if (g->nz == 1) {
+    const dim3 tiles((unsigned)((g->nx + 31) / 32), (unsigned)((g->ny + 31) / 32));
+    if (g->dtype == RW_F64)
+      k_cc_init_tile<double><<<tiles, 1024, 0, s>>>(G, (const double*)g->weight, g->mask, g->comp);
+    else
+      k_cc_init_tile<float><<<tiles, 1024, 0, s>>>(G, (const float*)g->weight, g->mask, g->comp);
+  } else if (g->dtype == RW_F64) {
     k_cc_init<double><<<nblocks(g->N, 256), 256, 0, s>>>(G, (const double*)g->weight, g->mask, g->comp);
-  else
+  } else {
     k_cc_init<float><<<nblocks(g->N, 256), 256, 0, s>>>(G, (const float*)g->weight, g->mask, g->comp);
+  }
   RW_LAUNCH_CHECK();
   for (int round = 0;; ++round) {
     RW_CHECK(round < 4096, RW_ENOCONV, "connected components did not settle");
