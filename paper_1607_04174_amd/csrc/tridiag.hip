@@ -73,69 +73,93 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
     if (i >= j) sA[tr_lo(i, j, n)] = 0.5 * (A[i + (int64_t)j * lda] + A[j + (int64_t)i * lda]);
   }
   __syncthreads();
-  for (int k = 0; k < n - 2; ++k) {
-    const int m = n - k - 1;   // length of the column below the diagonal
-    if (wave == 0) {
-      double xs[4];
-      double ss = 0.0;
+  // reflector k from column k below the diagonal (final once step k-1's update is done), by wave 0: v_k
+  // into vk, its entries to refl, tau, e, d, and tau for the workgroup in s_tau[k & 1]
+  auto reflector = [&](int k, double* vk) {
+    const int m = n - k - 1;
+    double xs[4];
+    double ss = 0.0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = lane + 64 * q;
-        xs[q] = i < m ? sA[tr_lo(k + 1 + i, k, n)] : 0.0;
-        if (i >= 1) ss += xs[q] * xs[q];
-      }
-      ss = tr_wave_sum(ss);
-      const double x0 = __shfl(xs[0], 0);
-      double beta, tk, scale;
-      if (ss == 0.0) {   // already reduced: no reflection
-        tk = 0.0;
-        beta = x0;
-        scale = 0.0;
-      } else {
-        const double nrm = sqrt(x0 * x0 + ss);
-        beta = x0 >= 0.0 ? -nrm : nrm;
-        tk = (beta - x0) / beta;
-        scale = 1.0 / (x0 - beta);
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int i = lane + 64 * q;
+      xs[q] = i < m ? sA[tr_lo(k + 1 + i, k, n)] : 0.0;
+      if (i >= 1) ss += xs[q] * xs[q];
+    }
+    ss = tr_wave_sum(ss);
+    const double x0 = __shfl(xs[0], 0);
+    double beta, tk, scale;
+    if (ss == 0.0) {   // already reduced: no reflection
+      tk = 0.0;
+      beta = x0;
+      scale = 0.0;
+    } else {
+      const double nrm = sqrt(x0 * x0 + ss);
+      beta = x0 >= 0.0 ? -nrm : nrm;
+      tk = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = lane + 64 * q;
-        if (i < m) {
-          const double vi = i == 0 ? 1.0 : xs[q] * scale;
-          v[i] = vi;
-          refl[(int64_t)k * n + i] = vi;
-        }
-      }
-      if (lane == 0) {
-        s_tau[k & 1] = tk;
-        tau[k] = tk;
-        e[k] = beta;
-        d[k] = sA[tr_lo(k, k, n)];
+    for (int q = 0; q < 4; ++q) {
+      const int i = lane + 64 * q;
+      if (i < m) {
+        const double vi = i == 0 ? 1.0 : xs[q] * scale;
+        vk[i] = vi;
+        refl[(int64_t)k * n + i] = vi;
       }
     }
-    lds_barrier();
+    if (lane == 0) {
+      s_tau[k & 1] = tk;
+      tau[k] = tk;
+      e[k] = beta;
+      d[k] = sA[tr_lo(k, k, n)];
+    }
+  };
+  // v_k lives in the packed slots of column k-1 below its diagonal (n - k entries, dead once reflector k-1
+  // is formed), v_0 in its own array: so reflector k+1 can be formed while step k still reads v_k
+  auto vbuf = [&](int k) -> double* { return k == 0 ? v : sA + tr_lo(k, k - 1, n); };
+  bool ahead = false;   // reflector k already formed during step k-1 (uniform)
+  for (int k = 0; k < n - 2; ++k) {
+    const int m = n - k - 1;   // length of the column below the diagonal
+    double* vk = vbuf(k);
+    if (!ahead) {
+      if (wave == 0) reflector(k, vk);
+      lds_barrier();
+    }
     const double tk = s_tau[k & 1];
+    ahead = false;
     if (tk == 0.0) continue;   // uniform
-    // p = tk A22 v, four lanes per row (A22 = A(k+1:n, k+1:n), symmetric, lower stored)
+    // p = tk A22 v (A22 = A(k+1:n, k+1:n), symmetric, lower stored): L lanes per row (one DPP quad, half
+    // row or row), more lanes as the block shrinks so that more waves share the rows
     {
-      const int r = tid >> 2, sub = tid & 3;
-      double acc = 0.0;
-      if (r < m) {
-        const int R = k + 1 + r;
-        int j = sub;
-        // j <= r: row R of the lower triangle, A(R, C) with C = k + 1 + j; the packed address advances by
-        // colstart(C + 4) - colstart(C) - 4 = 4 n - 4 C - 10
-        int C = k + 1 + j, addr = tr_lo(R, C, n);
-        for (; j <= r; j += 4, C += 4) {
-          acc += sA[addr] * v[j];
-          addr += 4 * n - 4 * C - 10;
+      const int LS = m > 128 ? 2 : (m > 64 ? 3 : 4), L = 1 << LS;
+      const int tri = (L * (L + 1)) >> 1;
+      for (int rb = 0; rb < m; rb += (int)(blockDim.x >> LS)) {   // uniform
+        const int r = rb + (tid >> LS), sub = tid & (L - 1);
+        double acc = 0.0;
+        if (r < m) {
+          const int R = k + 1 + r;
+          int j = sub;
+          // j <= r: row R of the lower triangle, A(R, C) with C = k + 1 + j; the packed address advances by
+          // colstart(C + L) - colstart(C) - L = L (n - C) - L (L + 1) / 2
+          int C = k + 1 + j, addr = tr_lo(R, C, n);
+          for (; j <= r; j += L, C += L) {
+            acc += sA[addr] * vk[j];
+            addr += L * (n - C) - tri;
+          }
+          // j > r: column R, A(C, R), consecutive in C
+          addr = tr_lo(k + 1 + j, R, n);
+          for (; j < m; j += L, addr += L) acc += sA[addr] * vk[j];
         }
-        // j > r: column R, A(C, R), consecutive in C
-        addr = tr_lo(k + 1 + j, R, n);
-        for (; j < m; j += 4, addr += 4) acc += sA[addr] * v[j];
+        if (LS == 2) {
+          acc = quad_sum(acc);
+        } else if (LS == 3) {
+          acc = quad_sum(acc);
+          acc += dpp_mov<0x141>(acc);   // row_half_mirror: the eight lanes of a half row
+        } else {
+          acc = row16_sum(acc);
+        }
+        if (sub == 0 && r < m) p[r] = tk * acc;
       }
-      acc = quad_sum(acc);   // the row's four lanes form one quad
-      if (sub == 0 && r < m) p[r] = tk * acc;
     }
     lds_barrier();
     // K = tk / 2 p^T v (every wave), then A22 -= v w^T + w v^T with w = p - K v
@@ -143,18 +167,25 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = lane + 64 * q;
-      if (i < m) s += p[i] * v[i];
+      if (i < m) s += p[i] * vk[i];
     }
     const double K = 0.5 * tk * tr_wave_sum(s);
     const int tx = tid & 31, ty = tid >> 5;
-    for (int jj = ty; jj < m; jj += 32) {
-      const double vj = v[jj], wj = p[jj] - K * vj;
+    auto update_col = [&](int jj) {
+      const double vj = vk[jj], wj = p[jj] - K * vj;
       int addr = tr_lo(k + 1 + jj + tx, k + 1 + jj, n);
       for (int ii = jj + tx; ii < m; ii += 32, addr += 32) {
-        const double vi = v[ii], wi = p[ii] - K * vi;
+        const double vi = vk[ii], wi = p[ii] - K * vi;
         sA[addr] -= vi * wj + wi * vj;
       }
-    }
+    };
+    if (ty < m) update_col(ty);
+    // look-ahead: column 0 of A22 (column k+1) was updated by lanes 0-31 of wave 0 just now, so wave 0
+    // forms reflector k+1 while the other waves finish the update
+    const bool la = k + 1 < n - 2;
+    if (la && wave == 0) reflector(k + 1, vbuf(k + 1));
+    for (int jj = ty + 32; jj < m; jj += 32) update_col(jj);
+    ahead = la;
     lds_barrier();
   }
   __syncthreads();
