@@ -210,11 +210,27 @@ __device__ __forceinline__ double tr_recip(double q) {
   return r;
 }
 
+// (the operands of eight steps are loaded before their chain, so that a step waits for arithmetic only)
 __device__ __forceinline__ int tr_sturm(const double* d, const double* e2, int n, double sigma, double pivmin) {
   double q = d[0] - sigma;
   if (fabs(q) < pivmin) q = -pivmin;
   int cnt = q < 0.0;
-  for (int j = 1; j < n; ++j) {
+  int j = 1;
+  for (; j + 8 <= n; j += 8) {
+    double dv[8], ev[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      dv[u] = d[j + u];
+      ev[u] = e2[j + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      q = (dv[u] - sigma) - ev[u] * tr_recip(q);
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+    }
+  }
+  for (; j < n; ++j) {
     q = (d[j] - sigma) - e2[j - 1] * tr_recip(q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
