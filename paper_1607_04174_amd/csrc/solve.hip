@@ -444,8 +444,19 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int6
   // Cholesky with early stop, left-looking (column k of L is formed from the earlier columns only when its
   // step comes): stop at the first small pivot (numerically singular leading block) or as soon as every
   // label's residual r(k) is at most f_max (no larger m is needed: the first m that can pass is at most k)
-  for (int k = 0; k < KM; ++k) {
-    const double* srk = sr + (k & 1) * C;
+  // Columns go in pairs (k, k+1): one pass forms both Schur columns from the same rows of L (the
+  // L(i, k) L(k+1, k) term of column k+1 is applied once column k is final), and the decisions for k+1
+  // are taken by every thread from values no thread changes in that phase, so a pair costs two barriers.
+  // sr holds the residuals before the pair (buffer (k / 2) & 1) and after it (the other buffer).
+  // L(k+1, k) is read by every thread in the pair's second phase, so it is stored after that phase's
+  // barrier (pend_k, pend_l: the same in every thread).
+  int pend_k = -1;
+  double pend_l = 0.0;
+  for (int k = 0; k < KM; k += 2) {
+    const double* srk = sr + ((k >> 1) & 1) * C;
+    double* srn = sr + (((k >> 1) + 1) & 1) * C;
+    if (pend_k >= 0 && tid == 0) A[scr_lo(pend_k + 1, pend_k, KM)] = pend_l;   // no reader until after the loop
+    pend_k = -1;
     if (k > 0) {
       double worst = 0.0;
       for (int c = 0; c < C; ++c) worst = fmax(worst, srk[c]);
@@ -454,13 +465,24 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int6
         break;
       }
     }
-    {   // Schur column c_i = A(i, k) - sum_{j<k} L(i, j) L(k, j), rows i >= k: one quad of lanes per row
+    const bool two = k + 1 < KM;
+    {   // Schur columns c_i = A(i, k) - sum_{j<k} L(i, j) L(k, j) (rows i >= k) and the same for k + 1
+        // without its j = k term (rows i >= k + 1): one quad of lanes per row
       const int r = tid >> 2, sub = tid & 3, i = k + r;
-      double acc = 0.0;
-      if (i < KM)
-        for (int j = sub; j < k; j += 4) acc += A[scr_lo(i, j, KM)] * A[scr_lo(k, j, KM)];
-      acc = quad_sum(acc);
-      if (sub == 0 && i < KM) A[scr_lo(i, k, KM)] -= acc;
+      double acc0 = 0.0, acc1 = 0.0;
+      if (i < KM) {
+        for (int j = sub; j < k; j += 4) {
+          const double lij = A[scr_lo(i, j, KM)];
+          acc0 += lij * A[scr_lo(k, j, KM)];
+          if (two) acc1 += lij * A[scr_lo(k + 1, j, KM)];
+        }
+      }
+      acc0 = quad_sum(acc0);
+      acc1 = quad_sum(acc1);
+      if (sub == 0 && i < KM) {
+        A[scr_lo(i, k, KM)] -= acc0;
+        if (two && i > k) A[scr_lo(i, k + 1, KM)] -= acc1;
+      }
     }
     lds_barrier();
     const double dkk = A[scr_lo(k, k, KM)];
@@ -469,20 +491,67 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int6
       break;
     }
     const double lkk = sqrt(dkk), rk = 1.0 / lkk;
-    if (tid < C) {
-      const double z = G[k + tid * KM] / lkk;
-      Z[k + tid * KM] = z;
-      sr[((k + 1) & 1) * C + tid] = srk[tid] - z * z;
-    }
+    if (tid < C) Z[k + tid * KM] = G[k + tid * KM] / lkk;
     if (tid == 0) rd[k] = rk;
-    // L(i, k) = c_i / L(k, k) below the diagonal, and the right-hand sides g_i -= L(i, k) z_k
-    for (int i = k + 1 + tid; i < KM; i += blockDim.x) {
-      const double l = A[scr_lo(i, k, KM)] * rk;
-      A[scr_lo(i, k, KM)] = l;
-      for (int c = 0; c < C; ++c) G[i + c * KM] -= l * (G[k + c * KM] * rk);
+    // column k + 1: stop before it when every residual after column k is small enough, or at a small pivot
+    bool stop1 = !two;
+    double Lk1 = 0.0, l1 = 1.0, r1 = 1.0;
+    if (two) {
+      double worst = 0.0;
+      for (int c = 0; c < C; ++c) {
+        const double z = G[k + c * KM] / lkk;
+        worst = fmax(worst, srk[c] - z * z);
+      }
+      Lk1 = A[scr_lo(k + 1, k, KM)] * rk;
+      const double dk1 = A[scr_lo(k + 1, k + 1, KM)] - Lk1 * Lk1;
+      stop1 = worst <= f_max || !(dk1 > 1e-12 * gd[k + 1]) || !isfinite(dk1);   // uniform
+      if (!stop1) {
+        l1 = sqrt(dk1);
+        r1 = 1.0 / l1;
+      }
+    }
+    if (stop1) {   // finish column k only
+      for (int i = k + 2 + tid; i < KM; i += blockDim.x) {
+        const double l = A[scr_lo(i, k, KM)] * rk;
+        A[scr_lo(i, k, KM)] = l;
+      }
+      if (two) {
+        pend_k = k;
+        pend_l = Lk1;
+      }
+      if (tid < C) {
+        const double z = G[k + tid * KM] / lkk;
+        srn[tid] = srk[tid] - z * z;
+      }
+      if (tid == 0) s_kf = two ? k + 1 : KM;
+      break;
+    }
+    // z_{k+1} from g_{k+1} after column k, and the residuals after the pair
+    if (tid < C) {
+      const double z0 = G[k + tid * KM] / lkk;
+      const double z1 = (G[k + 1 + tid * KM] - Lk1 * (G[k + tid * KM] * rk)) / l1;
+      Z[k + 1 + tid * KM] = z1;
+      srn[tid] = (srk[tid] - z0 * z0) - z1 * z1;
+    }
+    if (tid == 0) rd[k + 1] = r1;
+    pend_k = k;
+    pend_l = Lk1;
+    // rows below the pair: L(i, k), L(i, k+1) and the right-hand sides
+    for (int i = k + 2 + tid; i < KM; i += blockDim.x) {
+      const double l0 = A[scr_lo(i, k, KM)] * rk;
+      const double l1i = (A[scr_lo(i, k + 1, KM)] - l0 * Lk1) * r1;
+      A[scr_lo(i, k, KM)] = l0;
+      A[scr_lo(i, k + 1, KM)] = l1i;
+      for (int c = 0; c < C; ++c) {
+        const double gk = G[k + c * KM] * rk;
+        const double gk1 = (G[k + 1 + c * KM] - Lk1 * gk) * r1;
+        G[i + c * KM] -= l0 * gk + l1i * gk1;
+      }
     }
     lds_barrier();
   }
+  __syncthreads();
+  if (pend_k >= 0 && tid == 0) A[scr_lo(pend_k + 1, pend_k, KM)] = pend_l;
   __syncthreads();
   const int kf = s_kf;      // leading blocks of size <= kf are factorized
   // L^T (packed upper)
