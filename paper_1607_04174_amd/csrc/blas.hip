@@ -757,15 +757,15 @@ static bool gemm_mfma(const T* X, int64_t ldx, const double* V, int64_t ldv, T* 
 }
 
 // ---------------------------------------------------------------------------------------------
-// Rotation of a block and of its operator image with the residual norms, in one pass (FP32 blocks):
+// Rotation of a block with the residual norms of its operator image, in one pass (FP32 blocks):
 //   X = A0 V,  LX = A1' V,  res_j = ||LX_j - theta_j X_j||,
 // A1' = A1 shifted right by off1 columns (zero columns in front), so that V may carry extra leading rows
-// that act on A0 only.  Same arithmetic as k_gemm_mfma (V rounded to FP32 in LDS, FP32 accumulation);
-// a wave walks 16-row tasks and holds both outputs' accumulators.  The residual terms (FP32, from the
-// stored values; their rounding is that of the stored block) are summed per task over the 16 lanes of a
-// column group, then over the wave's tasks, the waves of the workgroup and the workgroups, in a fixed
-// order.  Each task reads its rows of
-// A0 before writing its rows of X, so X may share A0's storage (shifted by whole columns).
+// that act on A0 only.  LX is stored only when a buffer is given.  Same arithmetic as k_gemm_mfma (V
+// rounded to FP32 in LDS, FP32 accumulation); a wave walks 16-row tasks and holds both outputs'
+// accumulators.  The residual terms (FP32, from the unrounded accumulators, which are the stored values)
+// are summed per task over the 16 lanes of a column group, then over the wave's tasks, the waves of the
+// workgroup and the workgroups, in a fixed order.  Each task reads its rows of A0 before writing its rows
+// of X, so X may share A0's storage (shifted by whole columns).
 // ---------------------------------------------------------------------------------------------
 // sum over the 16 lanes of a DPP row (quad swaps, half-row mirror, row mirror); every lane of the row
 // receives the same sum (each step adds two equal partial sums in swapped order)
@@ -780,31 +780,51 @@ __device__ __forceinline__ float row16_sum(float x) {
   x += dpp_f<0x140>(x);   // row_mirror
   return x;
 }
+// four column sums over the 16 lanes of a DPP row at once (a reduce-scatter): lane i = 4 q + j of the row
+// returns the sum of e[t] with t = j for even q and t = 3 - j for odd q.  The two quad steps halve the set
+// of columns a lane keeps (it keeps the ones matching its t in bit 0, then in bit 1); the half-row and row
+// mirrors pair lanes i and 7 - i, then i and 15 - i, which hold the same t, so that all four lanes holding
+// a column end with the same sum.
+__device__ __forceinline__ float row16_sum4(const float e[4], int t) {
+  const bool b0 = t & 1, b1 = (t >> 1) & 1;
+  const float k0 = b0 ? e[1] : e[0], k1 = b0 ? e[3] : e[2];
+  const float s0 = b0 ? e[0] : e[1], s1 = b0 ? e[2] : e[3];
+  const float a0 = k0 + dpp_f<0xB1>(s0), a1 = k1 + dpp_f<0xB1>(s1);   // columns (t & 1) and (t & 1) + 2
+  float b = (b1 ? a1 : a0) + dpp_f<0x4E>(b1 ? a0 : a1);               // column t, over the quad
+  b += dpp_f<0x141>(b);
+  b += dpp_f<0x140>(b);
+  return b;
+}
 
 constexpr int kRotAhead = 2;   // k-steps of the two inputs loaded ahead (two outputs' accumulators held)
+
+// number of 16-column groups the rotation kernel is instantiated for (n columns)
+static inline int rot_ncb(int n) {
+  const int ncb = (n + 15) / 16;
+  return ncb <= 4 ? 4 : (ncb <= 8 ? 8 : 13);
+}
 
 template <int NCB>
 __global__ __launch_bounds__(64 * kGemmWaves) void k_rotate_pair(const float* A0, const float* A1, int off1,
                                                                  int64_t ld, const double* V, int64_t ldv,
                                                                  const double* theta, float* X, float* LX,
                                                                  int64_t rows, int k, int n, double* rpart) {
-  extern __shared__ float sV[];   // [kpad][n] V rounded to FP32 (zero beyond k), then theta
+  extern __shared__ float sV[];   // [kpad][n] V rounded to FP32 (zero beyond k), then theta (zero beyond n)
   const int nks = (k + 3) / 4;
   for (int t = threadIdx.x; t < 4 * nks * n; t += blockDim.x) {
     const int kk = t % (4 * nks), c = t / (4 * nks);
     sV[kk * n + c] = kk < k ? (float)V[(int64_t)c * ldv + kk] : 0.f;
   }
-  float* sTh = sV + 4 * nks * n;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) sTh[c] = (float)theta[c];
+  float* sTh = sV + 4 * nks * n;   // 16-byte aligned (4 nks n floats)
+  for (int c = threadIdx.x; c < 16 * NCB; c += blockDim.x) sTh[c] = c < n ? (float)theta[c] : 0.f;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c16 = lane & 15, g = lane >> 4;
-  // a task's residual terms are summed over the 16 lanes of each column group at once; lane c16 keeps the
-  // sums of the column indices idx = 4 cb + v with idx % 16 == c16 (idx = 16 q + c16 in rps[q])
-  constexpr int NQ = (4 * NCB + 15) / 16;
-  float rps[NQ];
+  // lane c16 keeps the residual sums of columns 16 cb + 4 g + t (see row16_sum4)
+  const int t = ((c16 >> 2) & 1) ? 3 - (c16 & 3) : (c16 & 3);
+  float rps[NCB];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) rps[q] = 0.f;
+  for (int cb = 0; cb < NCB; ++cb) rps[cb] = 0.f;
   const int64_t tasks = (rows + 15) / 16;
   for (int64_t task = (int64_t)blockIdx.x * kGemmWaves + wave; task < tasks; task += (int64_t)gridDim.x * kGemmWaves) {
     const int64_t r = task * 16 + c16;
@@ -839,38 +859,44 @@ __global__ __launch_bounds__(64 * kGemmWaves) void k_rotate_pair(const float* A0
         }
       }
     }
+    // the lane's output columns 16 cb + 4 g + v by a running offset (column steps of 1 and 13)
+    int64_t off = (int64_t)(4 * g) * ld + r;
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
+    for (int cb = 0; cb < NCB; ++cb) {
+      if (16 * cb >= n) break;   // uniform
+      const gemm_f4 th = *reinterpret_cast<const gemm_f4*>(sTh + 16 * cb + 4 * g);
+      float e[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int col = 16 * cb + 4 * g + v;
-        float e = 0.f;
+        e[v] = 0.f;
         if (ok && col < n) {
           const float xv = acc0[cb][v], lv = acc1[cb][v];
-          X[(int64_t)col * ld + r] = xv;
-          LX[(int64_t)col * ld + r] = lv;
-          const float d = lv - sTh[col] * xv;
-          e = d * d;
+          X[off] = xv;
+          if (LX) LX[off] = lv;
+          const float dv = lv - th[v] * xv;
+          e[v] = dv * dv;
         }
-        e = row16_sum(e);
-        const int idx = 4 * cb + v;
-        if ((idx & 15) == c16) rps[idx >> 4] += e;
+        off += v < 3 ? ld : 13 * ld;
       }
+      rps[cb] += row16_sum4(e, t);
+    }
   }
   // column sums over the waves (in order), then one value per workgroup
   __syncthreads();   // V no longer read
   double* red = reinterpret_cast<double*>(sV);   // [kGemmWaves][n]
+  if (c16 < 4) {   // quad 0: t = c16
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int idx = 16 * q + c16;
-    const int col = 16 * (idx >> 2) + 4 * g + (idx & 3);
-    if (idx < 4 * NCB && col < n) red[wave * n + col] = (double)rps[q];
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int col = 16 * cb + 4 * g + c16;
+      if (col < n) red[wave * n + col] = (double)rps[cb];
+    }
   }
   __syncthreads();
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    double t = 0.0;
-    for (int w = 0; w < kGemmWaves; ++w) t += red[w * n + c];
-    rpart[(int64_t)blockIdx.x * n + c] = t;
+    double s = 0.0;
+    for (int w = 0; w < kGemmWaves; ++w) s += red[w * n + c];
+    rpart[(int64_t)blockIdx.x * n + c] = s;
   }
 }
 
@@ -885,7 +911,7 @@ __global__ __launch_bounds__(64) void k_rotate_res_final(const double* rpart, in
 
 static size_t rotate_pair_lds(int k, int n) {
   const size_t nks = (size_t)(k + 3) / 4;
-  return (4 * nks * n + n) * sizeof(float);
+  return (4 * nks * n + 16 * (size_t)rot_ncb(n)) * sizeof(float);
 }
 
 bool rotate_pair_fits(int dt, int64_t rows, int k, int n) {
@@ -916,9 +942,9 @@ int rotate_pair(const float* A0, const float* A1, int off1, int64_t ld, const do
                 const double* theta, float* X, float* LX, int64_t rows, int k, int n, double* res, double* partial,
                 hipStream_t s) {
   RW_CHECK(rotate_pair_fits(RW_F32, rows, k, n) && (off1 == 0 || off1 == 1), RW_EINVAL, "rotate_pair: bad shape");
-  const int ncb = (n + 15) / 16;
-  if (ncb <= 4) launch_rotate_pair<4>(A0, A1, off1, ld, V, ldv, theta, X, LX, rows, k, n, res, partial, s);
-  else if (ncb <= 8) launch_rotate_pair<8>(A0, A1, off1, ld, V, ldv, theta, X, LX, rows, k, n, res, partial, s);
+  const int ncb = rot_ncb(n);
+  if (ncb == 4) launch_rotate_pair<4>(A0, A1, off1, ld, V, ldv, theta, X, LX, rows, k, n, res, partial, s);
+  else if (ncb == 8) launch_rotate_pair<8>(A0, A1, off1, ld, V, ldv, theta, X, LX, rows, k, n, res, partial, s);
   else launch_rotate_pair<13>(A0, A1, off1, ld, V, ldv, theta, X, LX, rows, k, n, res, partial, s);
   RW_LAUNCH_CHECK();
   return RW_OK;

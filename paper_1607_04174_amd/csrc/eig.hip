@@ -161,7 +161,8 @@ __global__ void k_copy_d(const double* a, double* b, int64_t n) {
   if (t < n) b[t] = a[t];
 }
 
-// One Rayleigh-Ritz step on the block F (nb columns).  Outputs X = F W Z, LX = op X, theta, res.
+// One Rayleigh-Ritz step on the block F (nb columns).  Outputs X = F W Z, theta and res (the residual
+// norms of X's columns); LX is scratch for op X, which no caller reads afterwards.
 // W makes F W orthonormal: W = R^{-1} from the Cholesky factor of G = F^T F (Cholesky QR), or, if
 // G is numerically singular, W = V s^{-1/2} from its eigendecomposition with small s floored.  With
 // `near_orth` (F already orthonormal up to storage rounding, as a stored eigenbasis is) and
@@ -185,6 +186,9 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool ne
   } else {
     RW_TRY(gram(c.dt, F, c.N, F, c.N, c.N, nb, nb, w.G, w.partial, c.s, true, near_orth));
   }
+  // W from the series is formed without waiting for max |G - I|: that value is read with the eigensolver's
+  // flag, and when it is too large for the series the projected matrix is formed again with Cholesky QR
+  const double* offI = nullptr;
   bool have_w = false;
   if (near_orth) {
     RW_HIP(hipMemsetAsync(w.tmp, 0, sizeof(double), c.s));
@@ -192,43 +196,56 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool ne
     if (fold) k_offI_absmax<true><<<nbk, 256, 0, c.s>>>(w.Hp, nb, w.G2, w.tmp, w.G, w.cq);
     else k_offI_absmax<false><<<nbk, 256, 0, c.s>>>(w.G, nb, w.G2, w.tmp);
     RW_LAUNCH_CHECK();
-    double e = 1.0;
-    RW_HIP(hipMemcpyAsync(&e, w.tmp, sizeof(double), hipMemcpyDeviceToHost, c.s));
-    RW_HIP(hipStreamSynchronize(c.s));
-    if (e < 1e-4) {
-      RW_TRY(gram(RW_F64, w.G2, nb, w.G2, nb, nb, nb, nb, w.V, w.partial, c.s, true));   // E^2 = E^T E (E symmetric)
-      k_series_w<<<nblocks(n2, 256), 256, 0, c.s>>>(w.G2, w.V, w.W, nb);
-      RW_LAUNCH_CHECK();
-      have_w = true;
-    }
+    RW_TRY(gram(RW_F64, w.G2, nb, w.G2, nb, nb, nb, nb, w.V, w.partial, c.s, true));   // E^2 = E^T E (E symmetric)
+    k_series_w<<<nblocks(n2, 256), 256, 0, c.s>>>(w.G2, w.V, w.W, nb);
+    RW_LAUNCH_CHECK();
+    offI = w.tmp;
+    have_w = true;
   }
-  int bad = 0;
-  if (!have_w) {
+  // W = R^{-1} of Cholesky QR, or from the eigendecomposition of G when that fails
+  auto cholesky_w = [&]() -> int {
     k_copy_d<<<nblocks(n2, 256), 256, 0, c.s>>>(w.G, w.G2, n2);
     RW_LAUNCH_CHECK();
     RW_TRY(chol_inverse(w.G2, w.W, nb, w.info, c.s));
+    int bad = 0;
     RW_HIP(hipMemcpyAsync(&bad, w.info, sizeof(int), hipMemcpyDeviceToHost, c.s));
     RW_HIP(hipStreamSynchronize(c.s));
-  }
-  if (bad != 0) {
-    RW_TRY(syev_batched(w.G, w.s, w.V, nullptr, 0, nb, 1, w.syw, c.s));
-    k_scale_cols<<<nblocks(n2, 256), 256, 0, c.s>>>(w.V, w.s, w.W, nb, c.floor_rel);
-    RW_LAUNCH_CHECK();
-  }
+    if (bad != 0) {
+      RW_TRY(syev_batched(w.G, w.s, w.V, nullptr, 0, nb, 1, w.syw, c.s));
+      k_scale_cols<<<nblocks(n2, 256), 256, 0, c.s>>>(w.V, w.s, w.W, nb, c.floor_rel);
+      RW_LAUNCH_CHECK();
+    }
+    return RW_OK;
+  };
+  if (!have_w) RW_TRY(cholesky_w());
   RW_TRY(stencil_apply(g, F, LF, nullptr, nb, 1.0, 0.0, 0.0, c.s));
   c.spmm_cols += nb;
   RW_TRY(gram(c.dt, F, c.N, LF, c.N, c.N, nb, nb, w.H, w.partial, c.s, true, near_orth));
-  RW_TRY(gram(RW_F64, w.H, nb, w.W, nb, nb, nb, nb, w.T, w.partial, c.s));         // T = H^T W = H W
-  RW_TRY(gram(RW_F64, w.W, nb, w.T, nb, nb, nb, nb, w.Hp, w.partial, c.s));        // Hp = W^T H W
-  k_symmetrize<<<nblocks((int64_t)nb * nb, 256), 256, 0, c.s>>>(w.Hp, nb);
-  RW_LAUNCH_CHECK();
   // with an FP32 or BF16 basis the projected matrix carries errors near 1e-7 relative: the tridiagonal
   // solver (Householder, bisection, inverse iteration) serves when its eigenvalues are separated, else
   // Jacobi, whose rotations below 1e-10 relative change nothing the rotated basis can represent
   int est = RW_ENOCONV;
-  if (c.dt != RW_F64 && tridiag_fits(nb)) {
-    est = syev_tridiag(w.Hp, w.theta, w.Z, nb, w.syw, c.s);
-    if (est != RW_OK && est != RW_ENOCONV) return est;
+  for (;;) {
+    RW_TRY(gram(RW_F64, w.H, nb, w.W, nb, nb, nb, nb, w.T, w.partial, c.s));         // T = H^T W = H W
+    RW_TRY(gram(RW_F64, w.W, nb, w.T, nb, nb, nb, nb, w.Hp, w.partial, c.s));        // Hp = W^T H W
+    k_symmetrize<<<nblocks((int64_t)nb * nb, 256), 256, 0, c.s>>>(w.Hp, nb);
+    RW_LAUNCH_CHECK();
+    est = RW_ENOCONV;
+    const double* tri_flag = nullptr;
+    if (c.dt != RW_F64 && tridiag_fits(nb)) {
+      est = syev_tridiag(w.Hp, w.theta, w.Z, nb, w.syw, c.s, offI != nullptr ? &tri_flag : nullptr);
+      if (est != RW_OK && est != RW_ENOCONV) return est;
+    }
+    if (offI == nullptr) break;
+    double e = 1.0, fl = 0.0;
+    RW_HIP(hipMemcpyAsync(&e, offI, sizeof(double), hipMemcpyDeviceToHost, c.s));
+    if (tri_flag != nullptr) RW_HIP(hipMemcpyAsync(&fl, tri_flag, sizeof(double), hipMemcpyDeviceToHost, c.s));
+    RW_HIP(hipStreamSynchronize(c.s));
+    if (tri_flag != nullptr && fl != 0.0) est = RW_ENOCONV;
+    offI = nullptr;
+    if (e < 1e-4) break;
+    have_w = false;   // the series does not apply: Cholesky QR, then the projected matrix again
+    RW_TRY(cholesky_w());
   }
   if (est == RW_ENOCONV)
     RW_TRY(syev_batched(w.Hp, w.theta, w.Z, nullptr, 0, nb, 1, w.syw, c.s, c.dt == RW_F64 ? 0.0 : 1e-10));
@@ -242,9 +259,9 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool ne
   }
   const double* Vr = fold ? w.T : w.WZ;   // the rotation, acting on [g, F] when folded
   const int kr = fold ? nb + 1 : nb;
-  if (rotate_pair_fits(c.dt, c.N, kr, nb)) {   // X, op X and the residual norms in one pass
+  if (rotate_pair_fits(c.dt, c.N, kr, nb)) {   // X and the residual norms in one pass (op X not stored)
     RW_TRY(rotate_pair((const float*)(fold ? Q0 : F), (const float*)LF, fold ? 1 : 0, c.N, Vr, kr, w.theta,
-                       (float*)X, (float*)LX, c.N, kr, nb, w.res, w.partial, c.s));
+                       (float*)X, nullptr, c.N, kr, nb, w.res, w.partial, c.s));
     return RW_OK;
   }
   RW_TRY(gemm_tn(c.dt, fold ? Q0 : F, c.N, Vr, kr, X, c.N, c.N, kr, nb, 0.0, c.s));   // X = (F - g c^T) W Z

@@ -363,8 +363,7 @@ int graph_components(Graph* g, hipStream_t s) {
     k_cc_init<float><<<nblocks(g->N, 256), 256, 0, s>>>(G, (const float*)g->weight, g->mask, g->comp);
   }
   RW_LAUNCH_CHECK();
-  for (int round = 0;; ++round) {
-    RW_CHECK(round < 4096, RW_ENOCONV, "connected components did not settle");
+  auto cc_round = [&]() -> int {   // hook and jump, cc_flag[0] set when a label changed
     RW_HIP(hipMemsetAsync(g->cc_flag, 0, sizeof(int), s));
     if (g->dtype == RW_F64)
       k_cc_hook<double><<<nblocks(g->N, 256), 256, 0, s>>>(G, (const double*)g->weight, g->mask, g->comp, g->cc_flag);
@@ -373,6 +372,14 @@ int graph_components(Graph* g, hipStream_t s) {
     RW_LAUNCH_CHECK();
     k_cc_jump<<<nblocks(g->N, 256), 256, 0, s>>>(g->comp, g->N);
     RW_LAUNCH_CHECK();
+    return RW_OK;
+  };
+  // the first round's flag is not read (a round without change leaves the labels as they are, so the next
+  // round reports no change either): labels are final after the first round that changes nothing
+  RW_TRY(cc_round());
+  for (int round = 1;; ++round) {
+    RW_CHECK(round < 4096, RW_ENOCONV, "connected components did not settle");
+    RW_TRY(cc_round());
     int changed = 0;
     RW_HIP(hipMemcpyAsync(&changed, g->cc_flag, sizeof(int), hipMemcpyDeviceToHost, s));
     RW_HIP(hipStreamSynchronize(s));
@@ -397,7 +404,7 @@ __global__ void k_anchor_check(const int64_t* comp, const uint8_t* flags, int64_
   if (i < N && !flags[comp[i]]) *bad = 1;
 }
 
-int check_anchored(Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, hipStream_t s) {
+int anchor_launch(Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, hipStream_t s, const int** bad_dev) {
   RW_TRY(graph_components(g, s));
   RW_HIP(hipMemsetAsync(flags, 0, g->N, s));
   RW_HIP(hipMemsetAsync(g->cc_flag + 1, 0, sizeof(int), s));
@@ -405,8 +412,15 @@ int check_anchored(Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, hi
   RW_LAUNCH_CHECK();
   k_anchor_check<<<nblocks(g->N, 256), 256, 0, s>>>(g->comp, flags, g->N, g->cc_flag + 1);
   RW_LAUNCH_CHECK();
+  *bad_dev = g->cc_flag + 1;
+  return RW_OK;
+}
+
+int check_anchored(Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, hipStream_t s) {
+  const int* bad_dev = nullptr;
+  RW_TRY(anchor_launch(g, seeds, S, flags, s, &bad_dev));
   int bad = 0;
-  RW_HIP(hipMemcpyAsync(&bad, g->cc_flag + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  RW_HIP(hipMemcpyAsync(&bad, bad_dev, sizeof(int), hipMemcpyDeviceToHost, s));
   RW_HIP(hipStreamSynchronize(s));
   RW_CHECK(!bad, RW_EUNANCHORED,
            "a connected component (edges with w >= 1e-30) holds no seed: the gamma = 0 system is singular");

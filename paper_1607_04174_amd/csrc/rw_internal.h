@@ -224,6 +224,9 @@ int graph_rebuild(Graph* g, hipStream_t s);   // weights -> degree, dinv, ghat, 
 // otherwise.  seeds: device array of S node ids; flags: device scratch of N bytes.
 int graph_components(Graph* g, hipStream_t s);
 int check_anchored(Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, hipStream_t s);
+// the same check queued on the stream without waiting: *bad_dev is the device int that is nonzero when some
+// component holds no seed, valid once the stream reaches this point (kept until the next components call)
+int anchor_launch(Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, hipStream_t s, const int** bad_dev);
 
 // ---- stencil operator --------------------------------------------------------------------------
 // Y = alpha * op(X) + beta * X + gamma * Z   (column-major N x b, graph dtype)
@@ -250,7 +253,8 @@ int gemm_tn(int dt, const void* X, int64_t ldx, const double* V, int64_t ldv, vo
 // dimension, shifted by whole columns), an in-place rotation
 bool gemm_rowwise(int dt, int64_t rows, int k, int n);
 // X = A0 V, LX = A1' V and res_j = ||LX_j - theta_j X_j|| in one pass for FP32 blocks (rows x k inputs with
-// leading dimension ld, V FP64 k x n); A1' is A1 (k - off1 columns) behind off1 zero columns.  X may share
+// leading dimension ld, V FP64 k x n); A1' is A1 (k - off1 columns) behind off1 zero columns.  LX may be
+// null (op X is then not stored, only its residual norms formed).  X may share
 // A0's storage shifted by whole columns.  rotate_pair_fits tells whether the shape is supported; `partial`
 // holds rotate_pair_partial_count(n) doubles.
 bool rotate_pair_fits(int dt, int64_t rows, int k, int n);
@@ -304,19 +308,23 @@ size_t syev_work_count(int n, int count, bool vectors, int nrhs);
 // RW_ENOCONV without an error message when eigenvalues are too close for inverse iteration.
 bool tridiag_fits(int n);
 size_t tridiag_work_count(int n);
-int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hipStream_t s);
+// With flag_dev, nothing waits: the call returns RW_OK and *flag_dev is the device double that is nonzero
+// where the result is RW_ENOCONV (then V is not valid).
+int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hipStream_t s,
+                 const double** flag_dev = nullptr);
 // Batched eigenvalues and rotated right-hand sides through the tridiagonal form, for the candidate problems
 // of the choice of m: matrix b (order sizes[b] <= ld, leading dimension ld, ld^2 apart) has right-hand
 // sides R_b (ld x C, ld * C apart); on RW_OK, w_b holds its eigenvalues (zero beyond sizes[b]) and
 // R_b = V_b^T R_b (zero rows beyond sizes[b]).  RW_ENOCONV (clustered eigenvalues) leaves w and R as they
-// were.  work holds tridiag_rhs_work_count(max size, count, C) doubles.
+// were.  work holds tridiag_rhs_work_count(max size, count, C) doubles.  With flag_dev, nothing waits: the
+// call returns RW_OK and *flag_dev is the device double that is nonzero where the result is RW_ENOCONV.
 constexpr int kTriBatchMax = 32;
 struct TriSizes {
   int n[kTriBatchMax];
 };
 size_t tridiag_rhs_work_count(int nmax, int count, int C);
 int syev_tridiag_rhs(const double* A, int ld, const int* sizes, int count, double* R, int C, double* w, double* work,
-                     size_t work_count, hipStream_t s);
+                     size_t work_count, hipStream_t s, const double** flag_dev = nullptr);
 // Solve A X = B by LU with partial pivoting (A: n x n, B: n x nrhs, both destroyed/overwritten;
 // X returned in B).  stat[0] = min |pivot| / max |a_ij| (0 if a pivot is below the threshold).
 int lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s);

@@ -280,10 +280,16 @@ __global__ void k_fit_build(const int* cand, int64_t S, int ma, int C, int ms, c
 
 __device__ __forceinline__ double wave_sum(double v) { return wave_sum64(v); }
 
+// rho of eq. (24): sqrt(1^T D 1) from the graph's device sum for the normalized operator, else sqrt(N)
+__device__ __forceinline__ double fit_rho(const double* sums, double n_nodes) {
+  return sqrt(sums != nullptr ? sums[0] : n_nodes);
+}
+
 // one wave per (candidate, label); lane-parallel sums reduced by butterflies, so all lanes agree
 __global__ __launch_bounds__(64) void k_fit_secular(const int* cand, int ncand, int64_t S, int C, int ms,
-                                                    const double* W, const double* R, const double* Us, double rho,
-                                                    double* fvals) {
+                                                    const double* W, const double* R, const double* Us,
+                                                    const double* sums, double n_nodes, double* fvals) {
+  const double rho = fit_rho(sums, n_nodes);
   const int ci = blockIdx.x, k = blockIdx.y;
   const int lane = threadIdx.x;
   const int m = cand[ci];
@@ -408,8 +414,9 @@ static int screen_cols(int ma, int C) {
 }
 
 __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int64_t S, const double* Gq,
-                                                     const double* Gb, const double* Us, double rho2, double f_max,
-                                                     double* F, int* cls) {
+                                                     const double* Gb, const double* Us, const double* sums,
+                                                     double n_nodes, double f_max, double* F, int* cls) {
+  const double rho = fit_rho(sums, n_nodes), rho2 = rho * rho;
   extern __shared__ double sm[];
   const int tri = KM * (KM + 1) / 2;
   double* A = sm;              // packed lower (column-major): G_m, then L column by column; later Ri (packed upper)
@@ -706,7 +713,9 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
   // seeds to the device; map of seeded nodes
   RW_HIP(hipMemcpyAsync(w.seeds, nodes.data(), S * sizeof(int64_t), hipMemcpyHostToDevice, stream));
   RW_HIP(hipMemcpyAsync(w.labels, labels.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-  RW_TRY(check_anchored(&h->g, w.seeds, S, w.anc, stream));
+  // the anchoring check runs on the device now and is read with the pivot test at the end
+  const int* unanchored = nullptr;
+  RW_TRY(anchor_launch(&h->g, w.seeds, S, w.anc, stream, &unanchored));
   k_clear_map<<<nblocks(g->N, 256), 256, 0, stream>>>(w.map, g->N);
   RW_LAUNCH_CHECK();
   k_set_map<<<nblocks(S, 256), 256, 0, stream>>>(w.map, w.seeds, w.labels, S);
@@ -739,14 +748,8 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
     f_max = (double)S * eps * eps;
     RW_TRY(gram(RW_F64, w.Qs, S, w.Qs, S, S, ma, ma, w.Gq, w.partial, stream, true));
     RW_TRY(gram(RW_F64, w.Qs, S, w.Us, S, S, ma, C, w.Gb, w.partial, stream));
-    double rho2 = 0.0;
-    if (g->normalized) {
-      RW_HIP(hipMemcpyAsync(&rho2, g->sums, sizeof(double), hipMemcpyDeviceToHost, stream));
-      RW_HIP(hipStreamSynchronize(stream));
-    } else {
-      rho2 = (double)g->N;
-    }
-    const double rho = std::sqrt(rho2);
+    // rho (eq. (24)) is formed on the device from the graph's degree sum
+    const double* rho_sums = g->normalized ? g->sums : nullptr;
     // search: lo = largest m known to fail (1 = none), hi = smallest m known to pass (ma + 1 = none)
     int lo = 1, hi = ma + 1;
     std::vector<std::pair<int, double>> evaluated;
@@ -759,8 +762,8 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
         attr = true;
       }
-      k_fit_screen<<<1, 1024, screen_lds_bytes(KM, C), stream>>>(ma, KM, C, S, w.Gq, w.Gb, w.Us, rho * rho, f_max,
-                                                                  w.scrF, w.scrCls);
+      k_fit_screen<<<1, 1024, screen_lds_bytes(KM, C), stream>>>(ma, KM, C, S, w.Gq, w.Gb, w.Us, rho_sums,
+                                                                  (double)g->N, f_max, w.scrF, w.scrCls);
       RW_LAUNCH_CHECK();
       std::vector<int> cls(ma + 1);
       std::vector<double> fr(ma + 1);
@@ -811,6 +814,7 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
       // eigenvalues and rotated right-hand sides through the tridiagonal form (each candidate at its own
       // order), the Jacobi solver when eigenvalues cluster or the batch does not fit
       int est = RW_ENOCONV;
+      const double* tri_flag = nullptr;   // the tridiagonal path's cluster flag, read with the fit values
       if (ncand <= kTriBatchMax && tridiag_fits(msp)) {
         int sizes[kTriBatchMax];
         bool ok = true;
@@ -819,16 +823,26 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
           ok = ok && tridiag_fits(sizes[q]);
         }
         if (ok) {
-          est = syev_tridiag_rhs(w.fitA, msp, sizes, ncand, w.fitR, C, w.fitW, w.fitWork, w.fitWorkCount, stream);
-          if (est != RW_OK && est != RW_ENOCONV) return est;
+          RW_TRY(syev_tridiag_rhs(w.fitA, msp, sizes, ncand, w.fitR, C, w.fitW, w.fitWork, w.fitWorkCount, stream,
+                                  &tri_flag));
+          est = RW_OK;
         }
       }
-      if (est == RW_ENOCONV) RW_TRY(syev_batched(w.fitA, w.fitW, nullptr, w.fitR, C, msp, ncand, w.fitWork, stream));
-      k_fit_secular<<<dim3(ncand, C), 64, 0, stream>>>(cand_buf, ncand, S, C, msp, w.fitW, w.fitR, w.Us, rho,
-                                                        w.fvals);
-      RW_LAUNCH_CHECK();
-      RW_HIP(hipMemcpyAsync(fh.data(), w.fvals, (size_t)ncand * C * sizeof(double), hipMemcpyDeviceToHost, stream));
-      RW_HIP(hipStreamSynchronize(stream));
+      // fit values (eq. (24)) from the eigenpairs; when the tridiagonal path flags clustered eigenvalues (it then
+      // leaves fitW and fitR as they were) they are discarded and formed again after the Jacobi solver
+      for (int pass = 0; pass < 2; ++pass) {
+        if (est == RW_ENOCONV)
+          RW_TRY(syev_batched(w.fitA, w.fitW, nullptr, w.fitR, C, msp, ncand, w.fitWork, stream));
+        k_fit_secular<<<dim3(ncand, C), 64, 0, stream>>>(cand_buf, ncand, S, C, msp, w.fitW, w.fitR, w.Us,
+                                                          rho_sums, (double)g->N, w.fvals);
+        RW_LAUNCH_CHECK();
+        double fl = 0.0;
+        RW_HIP(hipMemcpyAsync(fh.data(), w.fvals, (size_t)ncand * C * sizeof(double), hipMemcpyDeviceToHost, stream));
+        if (est == RW_OK) RW_HIP(hipMemcpyAsync(&fl, tri_flag, sizeof(double), hipMemcpyDeviceToHost, stream));
+        RW_HIP(hipStreamSynchronize(stream));
+        if (est == RW_ENOCONV || fl == 0.0) break;
+        est = RW_ENOCONV;
+      }
       int first_pass = -1;
       for (int q = 0; q < ncand; ++q) {
         double worst = 0.0;
@@ -852,11 +866,17 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
   k_build_reduced<<<nblocks((int64_t)m * std::max(m, C), 256), 256, 0, stream>>>(w.T, w.R, lambda, ma, m, C, w.K, w.Y);
   RW_LAUNCH_CHECK();
   RW_TRY(lu_solve(w.K, m, w.Y, C, w.stat, stream));
-  double stat = 0.0;
-  RW_HIP(hipMemcpyAsync(&stat, w.stat, sizeof(double), hipMemcpyDeviceToHost, stream));
-  RW_HIP(hipStreamSynchronize(stream));
-  RW_CHECK(stat > 0.0, RW_ESINGULAR, "reduced seed system is singular to working precision (m = %d)", m);
+  // the reconstruction is queued before the pivot test is read (one wait for both); U is not valid when
+  // the test fails
   RW_TRY(reconstruct(g, Q, q_dtype, m, w.Y, C, w.map, U, stream));
+  double stat = 0.0;
+  int bad = 0;
+  RW_HIP(hipMemcpyAsync(&stat, w.stat, sizeof(double), hipMemcpyDeviceToHost, stream));
+  RW_HIP(hipMemcpyAsync(&bad, unanchored, sizeof(int), hipMemcpyDeviceToHost, stream));
+  RW_HIP(hipStreamSynchronize(stream));
+  RW_CHECK(!bad, RW_EUNANCHORED,
+           "a connected component (edges with w >= 1e-30) holds no seed: the gamma = 0 system is singular");
+  RW_CHECK(stat > 0.0, RW_ESINGULAR, "reduced seed system is singular to working precision (m = %d)", m);
   if (info) {
     info->m_used = m;
     info->eig_probes = probes;

@@ -581,7 +581,7 @@ size_t tridiag_rhs_work_count(int nmax, int count, int C) {
 }
 
 int syev_tridiag_rhs(const double* A, int ld, const int* sizes, int count, double* R, int C, double* w, double* work,
-                     size_t work_count, hipStream_t s) {
+                     size_t work_count, hipStream_t s, const double** flag_dev) {
   RW_CHECK(count >= 1 && count <= kTriBatchMax && C >= 1, RW_EINVAL, "batched tridiagonal solver: bad batch");
   TriSizes sz;
   int nmax = 0;
@@ -611,13 +611,17 @@ int syev_tridiag_rhs(const double* A, int ld, const int* sizes, int count, doubl
       d, e, sz, nmax, lam, Z);
   k_tri_rot<<<dim3(ld, count), 64, 0, s>>>(Z, lam, h, sz, nmax, C, flag, w, R, ld, strideR);
   RW_LAUNCH_CHECK();
+  if (flag_dev != nullptr) {
+    *flag_dev = flag;
+    return RW_OK;
+  }
   double fl = 0.0;
   RW_HIP(hipMemcpyAsync(&fl, flag, sizeof(double), hipMemcpyDeviceToHost, s));
   RW_HIP(hipStreamSynchronize(s));
   return fl != 0.0 ? RW_ENOCONV : RW_OK;
 }
 
-int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hipStream_t s) {
+int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hipStream_t s, const double** flag_dev) {
   RW_CHECK(tridiag_fits(n), RW_EINVAL, "tridiagonal eigensolver: n = %d out of range", n);
   const TriBufs b = tri_bufs(work, n);
   tri_attrs();
@@ -630,6 +634,11 @@ int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hip
                                                                                                 b.lam, b.Z);
   k_tri_back<<<n, 64, 0, s>>>(b.refl, b.tau, n, b.Z, V);
   RW_LAUNCH_CHECK();
+  if (flag_dev != nullptr) {
+    *flag_dev = b.flag;
+    RW_HIP(hipMemcpyAsync(w, b.lam, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return RW_OK;
+  }
   double flag = 0.0;
   RW_HIP(hipMemcpyAsync(&flag, b.flag, sizeof(double), hipMemcpyDeviceToHost, s));
   RW_HIP(hipMemcpyAsync(w, b.lam, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
