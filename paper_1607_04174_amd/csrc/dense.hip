@@ -843,8 +843,8 @@ int lu_solve_batched(const LuJob* jobs, int count, hipStream_t s) {
 
 // The same elimination with A and B in LDS (rows padded to an odd stride, so that a row read across
 // lanes is free of bank conflicts).  Rows are not exchanged: step k eliminates column k from every row not
-// yet chosen as a pivot row (a flag per row) using the chosen row p_k, so a column costs two barriers
-// (pivot search by one wave; elimination of A and B).  Back substitution runs over the pivot order.  Ties
+// yet chosen as a pivot row (a flag per row) using the chosen row p_k; the pivot search of column k+1 runs in
+// one wave during step k, so a column costs one barrier.  Back substitution runs over the pivot order.  Ties
 // in the pivot search go to the lowest row index, and the solution is written to B in natural order.
 constexpr int kLuLdsMaxRows = 192;   // rows per lane in the elimination grid: 3 x 64
 constexpr int kLuWaveRhs = 8;        // back substitution in one wave up to this many right-hand sides
@@ -872,55 +872,72 @@ __global__ __launch_bounds__(1024) void k_lu_solve_lds(const double* Ag, int n, 
   }
   __syncthreads();
   const double amax = s_amax;
-  for (int k = 0; k < n; ++k) {
-    if (wave == 0) {
-      // argmax of |A(i, k)| over rows not yet chosen; ties go to the lowest row index
-      double best = -1.0;
-      int brow = n;
-      for (int i = lane; i < n; i += 64) {
-        if (done[i]) continue;
-        const double v = fabs(A[i + k * ld]);
-        if (v > best) { best = v; brow = i; }   // rows visited in increasing order: first maximum kept
-      }
-      const double m = wave_max64(best);
-      const unsigned long long tie = __ballot(best == m);
-      int row;
-      if (__popcll(tie) == 1) {
-        row = __shfl(brow, __ffsll((long long)tie) - 1);
-      } else {
-        int r = best == m ? brow : n;
-        for (int o = 32; o > 0; o >>= 1) r = min(r, __shfl_xor(r, o));
-        row = r;
-      }
-      if (lane == 0) {
-        const bool ok = row < n && m > 1e-14 * amax;   // no candidate (NaN column) or a tiny pivot
-        prow[k] = ok ? row : 0;
-        if (ok) done[row] = 1;
-        else s_bad = 1;
-        s_minpiv = fmin(s_minpiv, m);
-      }
+  // pivot of column k (one wave): argmax of |A(i, k)| over rows not yet chosen, ties to the lowest row index;
+  // prow[k], the smallest pivot so far, s_bad when no usable pivot is left
+  auto pivot = [&](int k) {
+    double best = -1.0;
+    int brow = n;
+    for (int i = lane; i < n; i += 64) {
+      if (done[i]) continue;
+      const double v = fabs(A[i + k * ld]);
+      if (v > best) { best = v; brow = i; }   // rows visited in increasing order: first maximum kept
     }
-    lds_barrier();
-    if (s_bad) break;
+    const double m = wave_max64(best);
+    const unsigned long long tie = __ballot(best == m);
+    int row;
+    if (__popcll(tie) == 1) {
+      row = __shfl(brow, __ffsll((long long)tie) - 1);
+    } else {
+      int r = best == m ? brow : n;
+      for (int o = 32; o > 0; o >>= 1) r = min(r, __shfl_xor(r, o));
+      row = r;
+    }
+    if (lane == 0) {
+      const bool ok = row < n && m > 1e-14 * amax;   // no candidate (NaN column) or a tiny pivot
+      prow[k] = ok ? row : 0;
+      if (!ok) s_bad = 1;
+      s_minpiv = fmin(s_minpiv, m);
+    }
+  };
+  if (wave == 0) pivot(0);
+  __syncthreads();
+  // step k eliminates column k with pivot row p = prow[k]: x(i) -= (A(i,k) / A(p,k)) x(p) on the rows not yet
+  // chosen.  Wave 0 updates column k+1 first and finds its pivot while the other waves update columns k+2..
+  // and B, so a step costs one barrier.
+  for (int k = 0; k < n; ++k) {
+    if (s_bad) break;   // uniform
     const int p = prow[k];
     const double inv = 1.0 / A[p + k * ld];
-    // rows not yet chosen (lanes, up to three per lane), columns k+1.. of A and all of B (waves):
-    // x(i) -= (A(i,k) / A(p,k)) x(p)
+    // rows of the lanes (up to three each); row p is not marked done yet (wave 0 marks it below, and the test
+    // i != p excludes it either way)
     double l[3];
     bool act[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const int i = lane + 64 * q;
-      act[q] = i < n && !done[i];
+      act[q] = i < n && i != p && !done[i];
       l[q] = act[q] ? A[i + k * ld] * inv : 0.0;
     }
-    const int cols = n - k - 1 + nrhs;
-    for (int c = wave; c < cols; c += 16) {
-      double* col = c < n - k - 1 ? A + (k + 1 + c) * ld : B + (c - (n - k - 1)) * ld;
-      const double xp = col[p];
+    if (wave == 0) {
+      if (lane == 0) done[p] = 1;
+      if (k + 1 < n) {
+        double* col = A + (k + 1) * ld;
+        const double xp = col[p];
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        if (act[q]) col[lane + 64 * q] -= l[q] * xp;
+        for (int q = 0; q < 3; ++q)
+          if (act[q]) col[lane + 64 * q] -= l[q] * xp;
+        pivot(k + 1);
+      }
+    } else {
+      const int na = n - k - 2 > 0 ? n - k - 2 : 0;   // columns k+2.. of A, then all of B
+      const int cols = na + nrhs;
+      for (int c = wave - 1; c < cols; c += 15) {
+        double* col = c < na ? A + (k + 2 + c) * ld : B + (c - na) * ld;
+        const double xp = col[p];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          if (act[q]) col[lane + 64 * q] -= l[q] * xp;
+      }
     }
     lds_barrier();
   }

@@ -237,10 +237,14 @@ static int rr_step(Ctx& c, int nb, char* F, char* LF, char* X, char* LX, bool ne
       if (est != RW_OK && est != RW_ENOCONV) return est;
     }
     if (offI == nullptr) break;
-    double e = 1.0, fl = 0.0;
-    RW_HIP(hipMemcpyAsync(&e, offI, sizeof(double), hipMemcpyDeviceToHost, c.s));
-    if (tri_flag != nullptr) RW_HIP(hipMemcpyAsync(&fl, tri_flag, sizeof(double), hipMemcpyDeviceToHost, c.s));
+    void* stage = nullptr;
+    RW_TRY(host_stage(2 * sizeof(double), &stage));
+    double* hs = static_cast<double*>(stage);
+    hs[1] = 0.0;
+    RW_HIP(hipMemcpyAsync(hs, offI, sizeof(double), hipMemcpyDeviceToHost, c.s));
+    if (tri_flag != nullptr) RW_HIP(hipMemcpyAsync(hs + 1, tri_flag, sizeof(double), hipMemcpyDeviceToHost, c.s));
     RW_HIP(hipStreamSynchronize(c.s));
+    const double e = hs[0], fl = hs[1];
     if (tri_flag != nullptr && fl != 0.0) est = RW_ENOCONV;
     offI = nullptr;
     if (e < 1e-4) break;
@@ -518,12 +522,13 @@ int rw_update_eig(rw_graph h, const rw_edit* edits, int n_edits, int mode, const
     const int qdt = opts->q_dtype;
     RW_TRY(copy_cols(c.dt, g->ghat, c.N, qdt, Q, c.N, c.N, 1, stream));
     if (!direct) RW_TRY(copy_cols(c.dt, w.B[ix], c.N, qdt, Qv, c.N, c.N, k, stream));
-    const double zero = 0.0;
-    RW_HIP(hipMemcpyAsync(lambda, &zero, sizeof(double), hipMemcpyHostToDevice, stream));
+    RW_HIP(hipMemsetAsync(lambda, 0, sizeof(double), stream));   // lambda[0] = +0.0
     RW_HIP(hipMemcpyAsync(lambda + 1, w.theta, k * sizeof(double), hipMemcpyDeviceToDevice, stream));
-    std::vector<double> rs(k);
-    RW_HIP(hipMemcpyAsync(rs.data(), w.res, k * sizeof(double), hipMemcpyDeviceToHost, stream));
+    void* stage = nullptr;
+    RW_TRY(host_stage(k * sizeof(double), &stage));
+    RW_HIP(hipMemcpyAsync(stage, w.res, k * sizeof(double), hipMemcpyDeviceToHost, stream));
     RW_HIP(hipStreamSynchronize(stream));
+    const std::vector<double> rs(static_cast<double*>(stage), static_cast<double*>(stage) + k);
     if (info) {
       info->iters = 0;
       info->spmm_columns = c.spmm_cols;

@@ -21,6 +21,22 @@ void set_error(const char* fmt, ...) {
   g_last_error = buf;
 }
 
+static thread_local void* g_stage = nullptr;
+static thread_local size_t g_stage_cap = 0;
+
+int host_stage(size_t bytes, void** p) {
+  if (g_stage_cap < bytes) {
+    if (g_stage != nullptr) RW_HIP(hipHostFree(g_stage));
+    g_stage = nullptr;
+    g_stage_cap = 0;
+    const size_t cap = std::max<size_t>(bytes, 65536);
+    RW_HIP(hipHostMalloc(&g_stage, cap, hipHostMallocDefault));
+    g_stage_cap = cap;
+  }
+  *p = g_stage;
+  return RW_OK;
+}
+
 static constexpr int64_t kEditStage = 65536;  // edge ids staged per chunk of an edit list
 
 template <typename T>

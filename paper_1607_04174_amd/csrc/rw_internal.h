@@ -82,6 +82,10 @@ __device__ __forceinline__ void lds_barrier() {
 
 // ---- error reporting ---------------------------------------------------------------------------
 void set_error(const char* fmt, ...);
+// Pinned host buffer of at least `bytes` for small device-to-host reads, one per host thread (grown on demand,
+// held until the process ends).  Reads into pageable memory wait for each copy in turn; reads into this buffer
+// are queued on the stream and waited for once.  The contents are the caller's until its next call.
+int host_stage(size_t bytes, void** p);
 
 #define RW_HIP(call)                                                                        \
   do {                                                                                      \

@@ -8,7 +8,9 @@
 //     (Lambda - Q_s^T B Q_n) Y = Q_s^T op_ss U_hat_s.
 // Its size is m, not S, and Lambda enters without inversion, so near-null eigenvalues need no
 // clamping.  The reconstruction U = D^{-1/2} Q Y is one tall-skinny pass over Q.
+#include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "rw_internal.h"
@@ -765,11 +767,15 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
       k_fit_screen<<<1, 1024, screen_lds_bytes(KM, C), stream>>>(ma, KM, C, S, w.Gq, w.Gb, w.Us, rho_sums,
                                                                   (double)g->N, f_max, w.scrF, w.scrCls);
       RW_LAUNCH_CHECK();
-      std::vector<int> cls(ma + 1);
-      std::vector<double> fr(ma + 1);
-      RW_HIP(hipMemcpyAsync(cls.data(), w.scrCls, (ma + 1) * sizeof(int), hipMemcpyDeviceToHost, stream));
-      RW_HIP(hipMemcpyAsync(fr.data(), w.scrF, (ma + 1) * sizeof(double), hipMemcpyDeviceToHost, stream));
+      void* stage = nullptr;
+      RW_TRY(host_stage((size_t)(ma + 1) * (sizeof(double) + sizeof(int)), &stage));
+      double* frs = static_cast<double*>(stage);
+      int* clss = reinterpret_cast<int*>(frs + ma + 1);
+      RW_HIP(hipMemcpyAsync(clss, w.scrCls, (ma + 1) * sizeof(int), hipMemcpyDeviceToHost, stream));
+      RW_HIP(hipMemcpyAsync(frs, w.scrF, (ma + 1) * sizeof(double), hipMemcpyDeviceToHost, stream));
       RW_HIP(hipStreamSynchronize(stream));
+      const std::vector<int> cls(clss, clss + ma + 1);
+      const std::vector<double> fr(frs, frs + ma + 1);
       // f is non-increasing in m: the first m not known to fail bounds lo, the first known pass bounds hi
       int m0 = 2;
       while (m0 <= ma && cls[m0] == 0) ++m0;
@@ -836,10 +842,16 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
         k_fit_secular<<<dim3(ncand, C), 64, 0, stream>>>(cand_buf, ncand, S, C, msp, w.fitW, w.fitR, w.Us,
                                                           rho_sums, (double)g->N, w.fvals);
         RW_LAUNCH_CHECK();
-        double fl = 0.0;
-        RW_HIP(hipMemcpyAsync(fh.data(), w.fvals, (size_t)ncand * C * sizeof(double), hipMemcpyDeviceToHost, stream));
-        if (est == RW_OK) RW_HIP(hipMemcpyAsync(&fl, tri_flag, sizeof(double), hipMemcpyDeviceToHost, stream));
+        void* stage = nullptr;
+        RW_TRY(host_stage(((size_t)ncand * C + 1) * sizeof(double), &stage));
+        double* hs = static_cast<double*>(stage);
+        hs[(size_t)ncand * C] = 0.0;
+        RW_HIP(hipMemcpyAsync(hs, w.fvals, (size_t)ncand * C * sizeof(double), hipMemcpyDeviceToHost, stream));
+        if (est == RW_OK)
+          RW_HIP(hipMemcpyAsync(hs + (size_t)ncand * C, tri_flag, sizeof(double), hipMemcpyDeviceToHost, stream));
         RW_HIP(hipStreamSynchronize(stream));
+        std::copy(hs, hs + (size_t)ncand * C, fh.begin());
+        const double fl = hs[(size_t)ncand * C];
         if (est == RW_ENOCONV || fl == 0.0) break;
         est = RW_ENOCONV;
       }
@@ -869,11 +881,15 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
   // the reconstruction is queued before the pivot test is read (one wait for both); U is not valid when
   // the test fails
   RW_TRY(reconstruct(g, Q, q_dtype, m, w.Y, C, w.map, U, stream));
-  double stat = 0.0;
-  int bad = 0;
-  RW_HIP(hipMemcpyAsync(&stat, w.stat, sizeof(double), hipMemcpyDeviceToHost, stream));
-  RW_HIP(hipMemcpyAsync(&bad, unanchored, sizeof(int), hipMemcpyDeviceToHost, stream));
+  void* stage = nullptr;
+  RW_TRY(host_stage(2 * sizeof(double), &stage));
+  double* hs = static_cast<double*>(stage);
+  RW_HIP(hipMemcpyAsync(hs, w.stat, sizeof(double), hipMemcpyDeviceToHost, stream));
+  RW_HIP(hipMemcpyAsync(hs + 1, unanchored, sizeof(int), hipMemcpyDeviceToHost, stream));
   RW_HIP(hipStreamSynchronize(stream));
+  const double stat = hs[0];
+  int bad = 0;
+  std::memcpy(&bad, hs + 1, sizeof(int));
   RW_CHECK(!bad, RW_EUNANCHORED,
            "a connected component (edges with w >= 1e-30) holds no seed: the gamma = 0 system is singular");
   RW_CHECK(stat > 0.0, RW_ESINGULAR, "reduced seed system is singular to working precision (m = %d)", m);
