@@ -220,7 +220,8 @@ int rw_solve_workspace_bytes(rw_graph g, int m_avail, int64_t S, int C, size_t* 
  * is solved (FP64 LU with partial pivoting); U_hat_n = Q_n Y, U = D^{-1/2} U_hat on non-seeds.
  * This system is algebraically the (S+1) x (S+1) bordered seed system of the paper's gamma = 0 case
  * with F_s eliminated.  The call synchronizes `stream`.
- * Errors: RW_EINVAL, RW_EWORKSPACE, RW_ESINGULAR (pivot < 1e-14 * max|entry|). */
+ * Errors: RW_EINVAL, RW_EWORKSPACE, RW_EUNANCHORED (a component of the anchoring graph holds no seed),
+ * RW_ESINGULAR (pivot < 1e-14 * max|entry|); U is not valid when the call fails. */
 int rw_solve_seeds(rw_graph g, const void* Q, int q_dtype, const double* lambda, int m_avail,
                    const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, double eps,
                    void* U, void* work, size_t work_bytes, hipStream_t stream, rw_solve_info* info);

@@ -325,19 +325,29 @@ __global__ __launch_bounds__(1024) void k_cc_init_tile(GridDev G, const T* weigh
 template <typename T>
 __global__ void k_cc_hook(GridDev G, const T* weight, const uint8_t* mask, int64_t* comp, int* changed) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= G.N) return;
-  const uint8_t mk = mask[i];
-  for (int d = 0; d < G.ndir; ++d) {
-    if (!((mk >> d) & 1)) continue;
-    if (!((double)weight[d * G.N + i] >= kAnchorWeight)) continue;
-    const int64_t a = cc_find(comp, i), b = cc_find(comp, i + G.off[d]);
-    if (a == b) continue;
-    const int64_t lo = a < b ? a : b, hi = a < b ? b : a;
-    atomicMin(reinterpret_cast<unsigned long long*>(&comp[hi]), (unsigned long long)lo);
-    // another round whenever an edge joined two roots: a concurrent hook may have re-pointed `hi` first,
-    // and only a later round sees the two trees again
-    *changed = 1;
+  const bool valid = i < G.N;
+  const uint8_t mk = valid ? mask[i] : 0;
+  const int lane = threadIdx.x & 63;
+  bool joined = false;
+  for (int d = 0; d < G.ndir; ++d) {   // uniform: every lane reaches the shuffles
+    int64_t lo = -1, hi = -1;
+    if (((mk >> d) & 1) && (double)weight[d * G.N + i] >= kAnchorWeight) {
+      const int64_t a = cc_find(comp, i), b = cc_find(comp, i + G.off[d]);
+      if (a != b) {
+        lo = a < b ? a : b;
+        hi = a < b ? b : a;
+      }
+    }
+    // neighbouring nodes across a tile boundary mostly join the same two roots: a lane whose previous lane
+    // performs the same hook leaves it to that lane (the minimum is idempotent)
+    const int64_t phi = __shfl_up(hi, 1), plo = __shfl_up(lo, 1);
+    if (hi >= 0 && !(lane > 0 && phi == hi && plo == lo))
+      atomicMin(reinterpret_cast<unsigned long long*>(&comp[hi]), (unsigned long long)lo);
+    joined = joined || hi >= 0;
   }
+  // another round whenever an edge joined two roots (a concurrent hook may have re-pointed `hi` first, and
+  // only a later round sees the two trees again); one store per wave, not one per join
+  if (__ballot(joined) != 0 && lane == 0) *changed = 1;
 }
 
 // full compression: every node to its root.  The walk is read-only (no halving), so the only store to
@@ -551,11 +561,14 @@ int rw_edit_graph(rw_graph h, const rw_edit* edits, int n_edits, hipStream_t str
   RW_CHECK(n_edits >= 0 && (n_edits == 0 || edits != nullptr), RW_EINVAL, "bad edit list");
   Graph* g = &h->g;
   if (n_edits == 0) return RW_OK;
-  // host-side validation against a copy of the presence mask, updated as the list is walked
-  std::vector<uint8_t> mask(g->N);
-  RW_HIP(hipMemcpyAsync(mask.data(), g->mask, g->N, hipMemcpyDeviceToHost, stream));
-  RW_HIP(hipStreamSynchronize(stream));
-  std::vector<uint8_t> mask0 = mask;
+  // host-side validation against a copy of the presence mask, updated as the list is walked (the graph keeps
+  // the host copy from its first edit on)
+  if (g->hmask.size() != (size_t)g->N) {
+    g->hmask.resize(g->N);
+    RW_HIP(hipMemcpyAsync(g->hmask.data(), g->mask, g->N, hipMemcpyDeviceToHost, stream));
+    RW_HIP(hipStreamSynchronize(stream));
+  }
+  std::vector<uint8_t> mask = g->hmask;
   for (int k = 0; k < n_edits; ++k) {
     const rw_edit& e = edits[k];
     switch (e.kind) {
@@ -621,9 +634,13 @@ int rw_edit_graph(rw_graph h, const rw_edit* edits, int n_edits, hipStream_t str
       }
     }
   }
-  if (mask != mask0) RW_HIP(hipMemcpyAsync(g->mask, mask.data(), g->N, hipMemcpyHostToDevice, stream));
+  const bool mask_changed = mask != g->hmask;
+  if (mask_changed) {
+    g->hmask.swap(mask);
+    RW_HIP(hipMemcpyAsync(g->mask, g->hmask.data(), g->N, hipMemcpyHostToDevice, stream));
+  }
   RW_TRY(graph_rebuild(g, stream));
-  RW_HIP(hipStreamSynchronize(stream));
+  if (mask_changed) RW_HIP(hipStreamSynchronize(stream));   // the host copy is the source of the upload
   return RW_OK;
 }
 

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/rw.h"
 
@@ -150,6 +151,7 @@ struct Graph {
   void* ghat = nullptr;     // N (dtype)
   double* degree = nullptr; // N
   uint8_t* mask = nullptr;  // N
+  std::vector<uint8_t> hmask;   // host copy of mask (empty until the first edit reads it; only edits change it)
   double* partial = nullptr;  // reduction partials (kReduceBlocks)
   double* sums = nullptr;     // [0] = sum of degrees
   int64_t* comp = nullptr;    // N: component root (the smallest node index) over edges with w >= kAnchorWeight

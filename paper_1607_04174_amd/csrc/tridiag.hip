@@ -1,10 +1,11 @@
 // Symmetric eigendecomposition through a tridiagonal form, for one matrix of order n <= 199:
 //   1. Householder reduction A = U T U^T (Golub & Van Loan Sec. 8.3.1) in one workgroup with the
-//      packed lower triangle in LDS: per column, one wave forms the reflector, 4 lanes per row form
-//      p = tau A22 v, every wave forms K = tau/2 p^T v, and all threads apply the rank-2 update
-//      A22 -= v w^T + w v^T with w = p - K v;
-//   2. eigenvalues of T by bisection on Sturm counts (Sec. 8.4.1), 64 points per step, one wave per
-//      eigenvalue (the interval shrinks 65-fold per step);
+//      packed lower triangle in LDS: per column, one wave forms the reflector (the next column's while
+//      the other waves finish the rank-2 update), 4 to 16 lanes per row form p = tau A22 v, every wave
+//      forms K = tau/2 p^T v, and all threads apply the rank-2 update A22 -= v w^T + w v^T with
+//      w = p - K v;
+//   2. eigenvalues of T by multisection on Sturm counts (Sec. 8.4.1), kBisThreads points per pass, one
+//      workgroup per eigenvalue (the interval shrinks kBisThreads + 1-fold per pass);
 //   3. eigenvectors of T by inverse iteration with the LDL^T factorization of T - lambda I (one lane
 //      per eigenvector, three solves, in LDS);
 //   4. V = U Z, the reflectors applied to each eigenvector column (one wave per column).
@@ -371,8 +372,20 @@ __global__ __launch_bounds__(kInvitThreads) void k_tri_invit(const double* dg, c
     Lf[j * kInvitThreads + t] = Lj;
     rD[j * kInvitThreads + t] = r;
   }
-  // start vector: deterministic, with no special structure
-  for (int jj = 0; jj < n; ++jj) z[jj * kInvitThreads + t] = 1.0 + 0.5 * sin(0.7 * jj + 1.3 * i + 0.1);
+  // start vector: deterministic, with no special structure: 1 + sin(0.7 j + 1.3 i + 0.1) / 2, the sines by
+  // the three-term recurrence s_{j+1} = 2 cos(0.7) s_j - s_{j-1} (n >= 3)
+  {
+    const double c2 = 2.0 * cos(0.7);
+    double s0 = sin(1.3 * i + 0.1), s1 = sin(0.7 + 1.3 * i + 0.1);
+    z[t] = 1.0 + 0.5 * s0;
+    z[kInvitThreads + t] = 1.0 + 0.5 * s1;
+    for (int jj = 2; jj < n; ++jj) {
+      const double s2 = c2 * s1 - s0;
+      z[jj * kInvitThreads + t] = 1.0 + 0.5 * s2;
+      s0 = s1;
+      s1 = s2;
+    }
+  }
   double inv = 1.0;   // the previous iteration's 1 / ||x||, applied as b is read
   for (int it = 0; it < 3; ++it) {
     // forward: y_j = b_j - L_j y_{j-1}
