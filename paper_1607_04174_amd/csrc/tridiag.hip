@@ -185,7 +185,9 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
     // forms reflector k+1 while the other waves finish the update
     const bool la = k + 1 < n - 2;
     if (la && wave == 0) reflector(k + 1, vbuf(k + 1));
-    for (int jj = ty + 32; jj < m; jj += 32) update_col(jj);
+    // the later columns in reverse order of ty, so that wave 0, which also formed the reflector, gets the
+    // shortest of each group of 32
+    for (int jj = (31 - ty) + 32; jj < m; jj += 32) update_col(jj);
     ahead = la;
     lds_barrier();
   }
@@ -331,15 +333,16 @@ __global__ __launch_bounds__(kInvitThreads) void k_tri_invit(const double* dg, c
   for (int o = kInvitThreads / 2; o > 0; o >>= 1) tn = fmax(tn, __shfl_xor(tn, o, kInvitThreads));
   __syncthreads();
   if (i >= n) return;
-  const double pivmin = 2.3e-16 * fmax(tn, 1e-300);
+  const double pivmin = 2.3e-16 * fmax(tn, 1e-290);   // a normal number (tr_recip)
   const double l = lam[i];
   // Each recurrence below runs over whole blocks of kInvB rows whose operands are loaded into registers
   // first and whose results are stored after (a step then waits for arithmetic, not for an LDS round trip),
   // and over the remaining rows one at a time.
   // factor: D_0 = d_0 - l, L_j = e_{j-1} / D_{j-1}, D_j = d_j - l - L_j e_{j-1}
+  // (the reciprocals by tr_recip: a few ulp, a perturbation of the factors the iteration does not notice)
   double D = d[0] - l;
   if (fabs(D) < pivmin) D = D < 0.0 ? -pivmin : pivmin;
-  double r = 1.0 / D;
+  double r = tr_recip(D);
   rD[t] = r;
   int j = 1;
   for (; j + kInvB <= n; j += kInvB) {
@@ -354,7 +357,7 @@ __global__ __launch_bounds__(kInvitThreads) void k_tri_invit(const double* dg, c
       const double Lj = ev[u] * r;
       double Dj = (dv[u] - l) - Lj * ev[u];
       if (fabs(Dj) < pivmin) Dj = Dj < 0.0 ? -pivmin : pivmin;
-      r = 1.0 / Dj;
+      r = tr_recip(Dj);
       Lv[u] = Lj;
       rv[u] = r;
     }
@@ -368,7 +371,7 @@ __global__ __launch_bounds__(kInvitThreads) void k_tri_invit(const double* dg, c
     const double Lj = e[j - 1] * r;
     double Dj = (d[j] - l) - Lj * e[j - 1];
     if (fabs(Dj) < pivmin) Dj = Dj < 0.0 ? -pivmin : pivmin;
-    r = 1.0 / Dj;
+    r = tr_recip(Dj);
     Lf[j * kInvitThreads + t] = Lj;
     rD[j * kInvitThreads + t] = r;
   }
