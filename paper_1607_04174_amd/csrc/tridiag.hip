@@ -446,7 +446,7 @@ __global__ __launch_bounds__(kInvitThreads) void k_tri_invit(const double* dg, c
   for (int jj = 0; jj < n; ++jj) Z[(int64_t)jj * n + i] = z[jj * kInvitThreads + t] * inv;
 }
 
-constexpr int kTriAhead = 4;   // reflectors loaded ahead by the back-transform and the right-hand-side pass
+constexpr int kTriAhead = 16;   // reflectors loaded ahead by the back-transform and the right-hand-side pass
 
 // 4. V(:, col) = H_0 H_1 ... H_{n-3} z, z = eigenvector col of T; V column-major n x n
 __global__ __launch_bounds__(64) void k_tri_back(const double* refl, const double* tau, int n, const double* Z,
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(64) void k_tri_back(const double* refl, const doubl
       vr[q] = (k >= 0 && i >= 0 && i < m) ? vk[i] : 0.0;
     }
   };
-  // reflectors k, k-1, .., k-3 in flight (an L2 load takes longer than a step)
+  // reflectors k, k-1, .., k-kTriAhead+1 in flight (written on another XCD, so most loads miss this L2)
   double vb[kTriAhead][4], tb[kTriAhead];
 #pragma unroll
   for (int u = 0; u < kTriAhead; ++u) {
