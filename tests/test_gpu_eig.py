@@ -107,6 +107,29 @@ def _edits(w, og):
             rwsynth.Edit("remove_edges", edge_ids=rem)]
 
 
+@pytest.mark.parametrize("dims,m", [((24, 22), 24), ((40, 36), 40)], ids=["small", "fold"])
+def test_update_rr_on_a_perturbed_basis(dims, m):
+    """Rayleigh-Ritz on a stored FP32 basis whose Gram is far from I (max |G - I| about 4e-3): the series for
+    G^{-1/2} does not apply, so the step forms the projected matrix again with Cholesky QR.  The result is
+    the Rayleigh-Ritz pairs of the same span (the second case takes the folded, in-place rotation)."""
+    need_gpu()
+    banner(f"update on a perturbed basis {dims}")
+    w = rwsynth.small("up", dims, 8, n_shapes=3)
+    dt, tol = torch.float32, 1e-5
+    gg, og, Q0, lam0, info = _gpu_eig(w, dt, tol, m)
+    Qp = Q0.copy()
+    Qp[:, 1:] *= 1.0 + 2e-3 * (1.0 + np.arange(1, m) / m)   # same span, columns 1.. longer by 0.2-0.4 %
+    edits = [rwsynth.Edit("set_beta", 150.0)]
+    og2 = og.copy()
+    og2.apply_edit(edits[0])
+    g2 = rw.Graph(to_dev(og.J, torch.float64), w.dims, w.conn, w.beta, dtype=dt)
+    Qd, lamd = to_dev(Qp.T, dt), to_dev(lam0, torch.float64)
+    rw.update_eig(g2, edits, Qd, lamd, mode=rw.RW_UPDATE_RR, tol=tol)
+    Qo, lo = rayleigh_ritz(og2, Qp.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(lamd.cpu().numpy(), lo, atol=2e-4)
+    assert principal_angle_sines(Qd.to(torch.float64).cpu().numpy().T, Qo).max() < 1e-3
+
+
 @pytest.mark.parametrize("name,w,dt,tol,m", UPD_CASES, ids=[c[0] for c in UPD_CASES])
 def test_update_modes_match_oracle(name, w, dt, tol, m):
     need_gpu()
