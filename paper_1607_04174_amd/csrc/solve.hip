@@ -715,7 +715,7 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
   // seeds to the device; map of seeded nodes
   RW_HIP(hipMemcpyAsync(w.seeds, nodes.data(), S * sizeof(int64_t), hipMemcpyHostToDevice, stream));
   RW_HIP(hipMemcpyAsync(w.labels, labels.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, stream));
-  // the anchoring check runs on the device now and is read with the pivot test at the end
+  // the anchoring check is queued here and read with the pivot test at the end
   const int* unanchored = nullptr;
   RW_TRY(anchor_launch(&h->g, w.seeds, S, w.anc, stream, &unanchored));
   k_clear_map<<<nblocks(g->N, 256), 256, 0, stream>>>(w.map, g->N);
