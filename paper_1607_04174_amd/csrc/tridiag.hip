@@ -57,8 +57,9 @@ __device__ __forceinline__ double tr_wave_sum(double v) { return wave_sum64(v); 
 // Workgroup b reduces matrix b of a batch: order sz.n[b], leading dimension lda, matrices strideA apart;
 // its reflectors, tau, d and e sit nmax^2 or nmax entries apart per matrix.
 __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int64_t strideA, TriSizes sz, int nmax,
-                                                  double* refl, double* tau, double* d, double* e) {
+                                                  double* refl, double* tau, double* d, double* e, double* flag) {
   const int b = blockIdx.x, n = sz.n[b];
+  if (b == 0 && threadIdx.x == 0) flag[0] = 0.0;   // the cluster flag of the bisection that follows
   A += b * strideA;
   refl += (int64_t)b * nmax * nmax;
   tau += (int64_t)b * nmax;
@@ -204,13 +205,21 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
 
 // Sturm count: the number of eigenvalues of T below sigma (the negative pivots of LDL^T of T - sigma I,
 // a pivot of magnitude below pivmin taken as -pivmin)
-// 1 / q from the hardware reciprocal and two Newton steps (relative error of a few units in the last place,
-// a perturbation of the same order as the rounding the count tolerates; |q| >= pivmin keeps it finite)
+// 1 / q from the hardware reciprocal and two Newton steps (a few units in the last place; |q| >= pivmin, a
+// normal number, keeps it finite)
 __device__ __forceinline__ double tr_recip(double q) {
   double r = __builtin_amdgcn_rcp(q);
   r = fma(r, fma(-q, r, 1.0), r);
   r = fma(r, fma(-q, r, 1.0), r);
   return r;
+}
+// the Sturm count's 1 / q with one Newton step (about 11 ulp, measured): the computed count is then the
+// exact count of T with each e^2 perturbed by some ten units in the last place, which moves an eigenvalue
+// by about 10 u |T| (a few times the multisection's stopping width 4 u |T|); each step's dependent chain
+// is two operations shorter than with two Newton steps
+__device__ __forceinline__ double tr_recip1(double q) {
+  const double r = __builtin_amdgcn_rcp(q);
+  return fma(r, fma(-q, r, 1.0), r);
 }
 
 // (the operands of eight steps are loaded before their chain, so that a step waits for arithmetic only)
@@ -228,13 +237,13 @@ __device__ __forceinline__ int tr_sturm(const double* d, const double* e2, int n
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      q = (dv[u] - sigma) - ev[u] * tr_recip(q);
+      q = (dv[u] - sigma) - ev[u] * tr_recip1(q);
       if (fabs(q) < pivmin) q = -pivmin;
       cnt += q < 0.0;
     }
   }
   for (; j < n; ++j) {
-    q = (d[j] - sigma) - e2[j - 1] * tr_recip(q);
+    q = (d[j] - sigma) - e2[j - 1] * tr_recip1(q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
@@ -500,7 +509,6 @@ __global__ __launch_bounds__(64) void k_tri_back(const double* refl, const doubl
   }
 }
 
-__global__ void k_tri_clear(double* flag) { flag[0] = 0.0; }
 
 // 5. (right-hand sides) h = U^T r = H_{n-3} ... H_1 H_0 r for right-hand side c = blockIdx.x of matrix
 // blockIdx.y (r: column c of R, ld ldr, matrices strideR apart; h: nmax x C per matrix), one wave each
@@ -619,8 +627,7 @@ int syev_tridiag_rhs(const double* A, int ld, const int* sizes, int count, doubl
   double* flag = h + (size_t)count * nmax * C;
   tri_attrs();
   const int64_t strideR = (int64_t)ld * C;
-  k_tri_clear<<<1, 1, 0, s>>>(flag);
-  k_tridiag<<<count, 1024, tridiag_lds_bytes(nmax), s>>>(A, ld, (int64_t)ld * ld, sz, nmax, refl, tau, d, e);
+  k_tridiag<<<count, 1024, tridiag_lds_bytes(nmax), s>>>(A, ld, (int64_t)ld * ld, sz, nmax, refl, tau, d, e, flag);
   k_tri_rhs<<<dim3(C, count), 64, 0, s>>>(refl, tau, sz, nmax, R, ld, strideR, C, h);
   k_tri_bisect<<<dim3(nmax, count), kBisThreads, 0, s>>>(d, e, sz, nmax, lam, flag);
   k_tri_invit<<<dim3((nmax + kInvitThreads - 1) / kInvitThreads, count), kInvitThreads, invit_lds_bytes(nmax), s>>>(
@@ -643,8 +650,7 @@ int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hip
   tri_attrs();
   TriSizes sz;
   sz.n[0] = n;
-  k_tri_clear<<<1, 1, 0, s>>>(b.flag);
-  k_tridiag<<<1, 1024, tridiag_lds_bytes(n), s>>>(A, n, 0, sz, n, b.refl, b.tau, b.d, b.e);
+  k_tridiag<<<1, 1024, tridiag_lds_bytes(n), s>>>(A, n, 0, sz, n, b.refl, b.tau, b.d, b.e, b.flag);
   k_tri_bisect<<<n, kBisThreads, 0, s>>>(b.d, b.e, sz, n, b.lam, b.flag);
   k_tri_invit<<<(n + kInvitThreads - 1) / kInvitThreads, kInvitThreads, invit_lds_bytes(n), s>>>(b.d, b.e, sz, n,
                                                                                                 b.lam, b.Z);
