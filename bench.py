@@ -49,8 +49,8 @@ def main():
                          "configurations and print their own line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in the design notes, not implemented)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (sharding across GPUs is "
+                                   "not implemented)"}))
         sys.exit(2)
 
     import torch
