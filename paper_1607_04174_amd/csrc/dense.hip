@@ -948,23 +948,44 @@ __global__ __launch_bounds__(1024) void k_lu_solve_lds(const double* Ag, int n, 
   }
   // back substitution over the pivot order: x_k = b(p_k) / A(p_k, k); b(p_i) -= A(p_i, k) x_k for i < k
   if (nrhs <= kLuWaveRhs) {
-    // one wave, lanes over the pivot order positions i (up to three each): no barriers
+    // one wave, lanes over the pivot order positions i (up to three each), the right-hand sides of a lane's
+    // rows held in registers: b(p_k) is read from the lane holding position k, so a step's chain is a lane
+    // read, a product and the lanes' updates, with no LDS round trip and no barriers
     if (wave == 0) {
       int pr[3];
+      double bv[3][kLuWaveRhs];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) pr[q] = lane + 64 * q < n ? prow[lane + 64 * q] : 0;
+      for (int q = 0; q < 3; ++q) {
+        const bool in = lane + 64 * q < n;
+        pr[q] = in ? prow[lane + 64 * q] : 0;
+#pragma unroll
+        for (int r = 0; r < kLuWaveRhs; ++r) bv[q][r] = (in && r < nrhs) ? B[pr[q] + r * ld] : 0.0;
+      }
       for (int k = n - 1; k >= 0; --k) {
-        const int p = prow[k];
+        const int p = prow[k], kq = k >> 6, kl = k & 63;   // position k: lane kl, slot kq
         const double rukk = 1.0 / A[p + k * ld];
-        for (int r = 0; r < nrhs; ++r) {
-          const double xk = B[p + r * ld] * rukk;   // b(p_k) is final: every later step has been applied
+        double a[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) a[q] = lane + 64 * q < k ? A[pr[q] + k * ld] : 0.0;
+#pragma unroll
+        for (int r = 0; r < kLuWaveRhs; ++r) {
+          if (r >= nrhs) break;   // uniform
+          // b(p_k) is final: every later step has been applied
+          const double bk = lane_read(kq == 0 ? bv[0][r] : (kq == 1 ? bv[1][r] : bv[2][r]), kl);
+          const double xk = bk * rukk;
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
-            const int i = lane + 64 * q;
-            if (i < k) B[pr[q] + r * ld] -= A[pr[q] + k * ld] * xk;
+            if (lane + 64 * q < k) bv[q][r] -= a[q] * xk;
+            if (q == kq && lane == kl) bv[q][r] = xk;
           }
-          if (lane == 0) B[p + r * ld] = xk;
         }
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        if (lane + 64 * q >= n) continue;
+#pragma unroll
+        for (int r = 0; r < kLuWaveRhs; ++r)
+          if (r < nrhs) B[pr[q] + r * ld] = bv[q][r];
       }
     }
     __syncthreads();
