@@ -86,6 +86,25 @@ def test_rr_full_basis_gives_new_eigenpairs():
     assert res.max() < 1e-12 and orth < 1e-12
 
 
+def test_rr_depends_only_on_the_span():
+    """Rayleigh-Ritz is a function of span([g_new, Q[:, 1:]]): a basis of the same span (columns 1..
+    mixed by an invertible upper-triangular matrix, so not orthonormal) gives the same pairs."""
+    w = rwsynth.small("t", (9, 8), 8, n_shapes=3)
+    J, _ = rwsynth.phantom(w)
+    g = Graph(J, (9, 8, 1), 8, beta=90.0)
+    lam, Q = dense_eigpairs(g, 14)
+    g2 = g.copy()
+    g2.set_beta(150.0)
+    rng = np.random.default_rng(11)
+    R = np.eye(13) + 0.3 * np.triu(rng.standard_normal((13, 13)))
+    Qm = Q.copy()
+    Qm[:, 1:] = Q[:, 1:] @ R
+    Q1, l1 = rayleigh_ritz(g2, Q)
+    Q2, l2 = rayleigh_ritz(g2, Qm)
+    np.testing.assert_allclose(l2, l1, atol=1e-12)
+    assert principal_angle_sines(Q2, Q1).max() < 1e-7   # the sine's floor: sqrt(1 - s^2) near s = 1
+
+
 def test_adjoint_matches_finite_differences():
     dims = (7, 6, 1)
     w = rwsynth.small("t", dims, 4, C=2, seeds_per_label=3, n_shapes=2)
