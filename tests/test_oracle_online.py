@@ -1,6 +1,7 @@
 """Pins of the oracle's online parts: the constrained least-squares fit that chooses m (KKT
-conditions, an independent constrained optimizer, monotonicity), the Rayleigh-quotient eigenvalue
-update (identity on an unchanged graph) and the adjoint gradients (central finite differences)."""
+conditions, an independent constrained optimizer, monotonicity), the eigenvector updates (identity on an
+unchanged graph, the exact pairs from a full basis, Rayleigh-Ritz a function of the span only) and the
+adjoint gradients (central finite differences)."""
 import numpy as np
 import pytest
 import scipy.optimize as so
