@@ -11,14 +11,13 @@ Readings:
   * stored sign of each eigenvector: its entry of largest magnitude is positive (lowest index on a
     tie).
 
-For small graphs the pairs come from a dense symmetric eigendecomposition (numpy.linalg.eigh); for
-mid-size graphs from scipy's shift-invert Lanczos (eigsh).  For any size, `certify` returns the
-residuals ||M q_i - lambda_i q_i|| and ||Q^T Q - I|| of a given basis.
+For small graphs the pairs come from a dense symmetric eigendecomposition (numpy.linalg.eigh).  For
+any size, `certify` returns the residuals ||M q_i - lambda_i q_i|| and ||Q^T Q - I|| of a given basis,
+and `principal_angle_sines` compares two spans.
 """
 from __future__ import annotations
 
 import numpy as np
-import scipy.sparse.linalg as spla
 
 
 def fix_signs(Q):
@@ -57,15 +56,6 @@ def full_spectrum(graph):
     return np.linalg.eigh(graph.M().toarray())[0]
 
 
-def eigsh_pairs(graph, m, sigma=-1e-3, tol=0.0):
-    """(lam, Q) from scipy shift-invert Lanczos around sigma; null vector inserted."""
-    M = graph.M().tocsc()
-    w, V = spla.eigsh(M, k=m, sigma=sigma, which="LM", tol=tol)
-    order = np.argsort(w)
-    Q, lam = insert_null(V[:, order], w[order], graph.ghat())
-    return lam, fix_signs(Q)
-
-
 def certify(graph, Q, lam):
     """Per-column residual norms ||M q_i - lam_i q_i|| and the orthonormality error ||Q^T Q - I||_max."""
     M = graph.M()
@@ -82,7 +72,14 @@ def rayleigh_quotients(graph, Q):
 
 
 def principal_angle_sines(Q1, Q2):
-    """Sines of the principal angles between span(Q1) and span(Q2) (both orthonormal columns)."""
-    s = np.linalg.svd(np.asarray(Q1).T @ np.asarray(Q2), compute_uv=False)
-    s = np.clip(s, 0.0, 1.0)
-    return np.sqrt(np.maximum(0.0, 1.0 - s * s))
+    """Sines of the min(k1, k2) principal angles between span(Q1) and span(Q2) (orthonormal columns):
+    the singular values of the part of the narrower basis outside the span of the wider one,
+    (I - Q1 Q1^T) Q2 with Q2 the narrower (Bjorck & Golub 1973).  Unlike sqrt(1 - cos^2) this keeps its
+    accuracy for small angles."""
+    Q1 = np.asarray(Q1, dtype=np.float64)
+    Q2 = np.asarray(Q2, dtype=np.float64)
+    if Q2.shape[1] > Q1.shape[1]:
+        Q1, Q2 = Q2, Q1
+    R = Q2 - Q1 @ (Q1.T @ Q2)
+    s = np.linalg.svd(R, compute_uv=False)
+    return np.clip(s, 0.0, 1.0)
