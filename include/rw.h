@@ -55,7 +55,8 @@ typedef struct {
   int32_t ndim;        /* 2 or 3 */
   int64_t dims[3];     /* nx, ny, nz; nz = 1 when ndim = 2; each >= 1, N >= 2 */
   int32_t conn;        /* 4 or 8 when ndim = 2; 6 when ndim = 3 */
-  int32_t dtype;       /* RW_F64 or RW_F32: type of the stored weights and of rw_apply_laplacian */
+  int32_t dtype;       /* RW_F64 or RW_F32: type of the operator's stored coefficients (coef, diag, dinv,
+                          ghat) and of rw_apply_laplacian; scales, weights and degrees are FP64 always */
   int32_t weight_form; /* RW_WEIGHT_SQUARED or RW_WEIGHT_ABS */
   int32_t normalized;  /* 1: the operator is L_hat = D^{-1/2} L D^{-1/2} (Sec. II-C); 0: L = D - W */
 } rw_graph_desc;
@@ -83,15 +84,17 @@ int rw_build_graph(const rw_graph_desc* desc, const void* J_dev, int J_dtype, do
 int rw_graph_destroy(rw_graph g);
 
 /* Device views of the graph's arrays (for tests and for callers that fuse their own work).
- * Arrays of `dtype` are the graph's dtype; planes are ndir x N, direction-major. */
+ * coef, diag, dinv and ghat are of the graph's dtype; J, weight, scale and degree are FP64 on every
+ * graph (an FP32 graph rounds only the operator's coefficients, once, from the FP64 values).  Planes
+ * are ndir x N, direction-major. */
 typedef struct {
   int64_t N;
   int32_t ndir;
   int32_t dtype;
   double beta;
   const double* J;      /* N, FP64 copy of the intensities */
-  const void* weight;   /* ndir x N: w_e = s_e * exp(...) (0 where absent / off-grid) */
-  const void* scale;    /* ndir x N: s_e (0 where absent / off-grid) */
+  const double* weight; /* ndir x N: w_e = s_e * exp(...) in FP64 (0 where absent / off-grid) */
+  const double* scale;  /* ndir x N: s_e in FP64 (0 where absent / off-grid) */
   const void* coef;     /* ndir x N: off-diagonal magnitude of the operator, w_e d_i^{-1/2} d_j^{-1/2} or w_e */
   const void* diag;     /* N: diagonal of the operator (1 or 0 for L_hat, d for L) */
   const void* dinv;     /* N: d^{-1/2} (0 where d = 0) */
@@ -215,13 +218,16 @@ int rw_solve_workspace_bytes(rw_graph g, int m_avail, int64_t S, int C, size_t* 
  *   eps      <= 0: use m = m_avail; > 0: m = the smallest m in [2, m_avail] whose fit of every
  *            label's seeds (eq. (24), rho = sqrt(1^T D 1) or sqrt(N)) is <= S * eps^2;
  *   U        device C x N of the graph's dtype; seed rows are one-hot, a label without seeds is 0.
- * Seeds are sorted ascending and the reduced (m x m) system
- *   (Lambda - Q_s^T B Q_n) Y = Q_s^T op_ss U_hat_s
- * is solved (FP64 LU with partial pivoting); U_hat_n = Q_n Y, U = D^{-1/2} U_hat on non-seeds.
- * This system is algebraically the (S+1) x (S+1) bordered seed system of the paper's gamma = 0 case
- * with F_s eliminated.  The call synchronizes `stream`.
- * Errors: RW_EINVAL, RW_EWORKSPACE, RW_EUNANCHORED (a component of the anchoring graph holds no seed),
- * RW_ESINGULAR (pivot < 1e-14 * max|entry|); U is not valid when the call fails. */
+ * Seeds are sorted ascending.  After m is chosen (the fit uses the stored columns), the basis is taken
+ * in FP64 as Q' = [g, (q_j - g c_j) / n_j], with g the graph's exact FP64 null vector, c_j = g^T q_j and
+ * n_j the norm (one pass over Q's first m columns), and the reduced (m x m) system
+ *   (Lambda - Q'_s^T B Q'_n) Y = Q'_s^T op_ss U_hat_s
+ * is formed from the FP64 weights and degrees and solved (FP64 LU with partial pivoting);
+ * U_hat_n = Q'_n Y, U = D^{-1/2} U_hat on non-seeds.  This system is algebraically the (S+1) x (S+1)
+ * bordered seed system of the paper's gamma = 0 case with F_s eliminated.  The call synchronizes `stream`.
+ * Errors: RW_EINVAL (also: a column of Q in the span of column 0), RW_EWORKSPACE, RW_EUNANCHORED (a
+ * component of the anchoring graph holds no seed), RW_ESINGULAR (pivot < 1e-14 * max|entry|); U is not
+ * valid when the call fails. */
 int rw_solve_seeds(rw_graph g, const void* Q, int q_dtype, const double* lambda, int m_avail,
                    const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, double eps,
                    void* U, void* work, size_t work_bytes, hipStream_t stream, rw_solve_info* info);
@@ -255,7 +261,7 @@ int rw_cg_solve_rhs(rw_graph g, const int64_t* seed_node, const int32_t* seed_la
  * Differentiation of the exact random walker (adjoint of Sec. II-A eq. (5), gamma = 0)
  * ====================================================================================== */
 
-/* Replace the per-edge scales s_e (device ndir x N, graph dtype; entries of absent edges are ignored;
+/* Replace the per-edge scales s_e (device ndir x N, FP64; entries of absent edges are ignored;
  * s_e >= 0 is the caller's responsibility) and rebuild the weights w_e = s_e exp(...). */
 int rw_graph_set_scale(rw_graph g, const void* scale, hipStream_t stream);
 
@@ -307,7 +313,9 @@ typedef struct rw_batch_s* rw_batch;
 
 typedef struct {
   rw_graph g;            /* the image's graph (all images: one graph dtype) */
-  const void* Q;         /* device column-major N x m basis of q_dtype (column 0 the null vector) */
+  const void* Q;         /* device column-major N x m basis of q_dtype (column 0 the null vector); with the
+                            graph, fixed for the batch's lifetime (rw_batch_create takes the constants
+                            of its FP64 form, as rw_solve_seeds does per call) */
   int32_t q_dtype;       /* RW_F64, RW_F32 or RW_BF16 (all images: one q_dtype) */
   const double* lambda;  /* device FP64, m eigenvalues, lambda[0] = 0 */
   int32_t m;             /* pairs used (no choice of m in the batched form), 2 <= m <= min(N, 1024) */

@@ -25,13 +25,20 @@ A node with d = 0 (no edges at all) gets U = 0.
 Exact mode.  R^T carries Lambda'^{-1}, so when the graph has weakly coupled regions (eigenvalues
 1e-9 .. 1e-17 above zero) the bordered system has entries of size 1/lambda and its FP64 solution
 loses up to all of its digits.  With exact=True the seed-side steps (B Q'_n, B R^T, the bordered
-solve and Y = Lambda'^{-1} Q'_s^T F_s) are carried out in exact rational arithmetic on the given FP64
-inputs (Python fractions), Y and c are rounded once to FP64, and only the final reconstruction
-Q'_n Y + g_n c^T runs in FP64.  This evaluates the same equations, in the same order, without
-rounding in the ill-conditioned part.
+solve and Y = Lambda'^{-1} Q'_s^T F_s) are carried out on the given FP64 inputs in 100-digit decimal
+arithmetic (each FP64 input converts exactly; a condition number up to 1e20 still leaves about 80
+correct digits, far below FP64's resolution), Y and c are rounded once to FP64, and only the final
+reconstruction Q'_n Y + g_n c^T runs in FP64.  exact="rational" carries out the same steps in exact
+rational arithmetic (Python fractions): no rounding at all, but its cost grows steeply with S; it
+pins the decimal evaluation.  Both evaluate the same equations, in the same order, without FP64
+rounding in the ill-conditioned part; the bordered solve is Gaussian elimination with partial
+pivoting (largest magnitude), which in exact arithmetic gives the exact solution whatever pivots it
+takes.
 """
 from __future__ import annotations
 
+import decimal
+from decimal import Decimal
 from fractions import Fraction
 
 import numpy as np
@@ -53,13 +60,14 @@ def _seed_blocks(graph, seed_node):
 
 
 def _exact_solve(A, b):
-    """Gaussian elimination with (first non-zero) pivoting over the rationals; A n x n, b n x k."""
+    """Gaussian elimination with partial pivoting (largest magnitude) in the entries' own arithmetic
+    (rationals or 100-digit decimals); A n x n, b n x k."""
     n = len(A)
     A = [row[:] for row in A]
     b = [row[:] for row in b]
     for k in range(n):
-        p = next((i for i in range(k, n) if A[i][k] != 0), None)
-        if p is None:
+        p = max(range(k, n), key=lambda i: abs(A[i][k]))
+        if A[p][k] == 0:
             raise np.linalg.LinAlgError("singular bordered system")
         A[k], A[p] = A[p], A[k]
         b[k], b[p] = b[p], b[k]
@@ -75,8 +83,8 @@ def _exact_solve(A, b):
             bi, bk = b[i], b[k]
             for j in range(len(bi)):
                 bi[j] -= f * bk[j]
-            Ai[k] = Fraction(0)
-    x = [[Fraction(0)] * len(b[0]) for _ in range(n)]
+            Ai[k] = A[k][k] * 0
+    x = [[b[0][0] * 0] * len(b[0]) for _ in range(n)]
     for k in range(n - 1, -1, -1):
         for j in range(len(b[0])):
             acc = b[k][j]
@@ -87,8 +95,8 @@ def _exact_solve(A, b):
     return x
 
 
-def _coeffs_exact(graph, Qp, lp, ghat, s, Ms, B, Uhat_s, C):
-    F = Fraction
+def _coeffs_exact(graph, Qp, lp, ghat, s, Ms, B, Uhat_s, C, number=Fraction):
+    F = number
     S, mp = s.size, Qp.shape[1]
     Bc = B.tocsr()
     Qs = [[F(float(v)) for v in row] for row in Qp[s]]
@@ -140,8 +148,14 @@ def fast_rw_coeffs(graph, Q, lam, seed_node, seed_label, C, m=None, exact=False)
     M, s, n, Ms, B = _seed_blocks(graph, seed_node)
     S = s.size
     Uhat_s = graph.hat_scale()[s][:, None] * one_hot(seed_label, C)
+    if exact == "rational":
+        Y, c = _coeffs_exact(graph, Qp, lp, ghat, s, Ms, B, Uhat_s, C, Fraction)
+        return Qp, Y, c
     if exact:
-        Y, c = _coeffs_exact(graph, Qp, lp, ghat, s, Ms, B, Uhat_s, C)
+        with decimal.localcontext() as ctx:
+            ctx.prec = 100
+            ctx.Emin, ctx.Emax = -999999, 999999
+            Y, c = _coeffs_exact(graph, Qp, lp, ghat, s, Ms, B, Uhat_s, C, Decimal)
         return Qp, Y, c
     Qs = Qp[s]                                       # Q'_s
     BQn = B @ Qp                                     # B Q'_n      (S x m')

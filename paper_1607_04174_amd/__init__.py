@@ -238,7 +238,8 @@ class Graph:
             return self.buf[off: off + count * esz].view(dt)
 
         return {"beta": v.beta, "J": sl(v.J, N, torch.float64, 8),
-                "weight": sl(v.weight, nd * N, tdt, es).view(nd, N), "scale": sl(v.scale, nd * N, tdt, es).view(nd, N),
+                "weight": sl(v.weight, nd * N, torch.float64, 8).view(nd, N),
+                "scale": sl(v.scale, nd * N, torch.float64, 8).view(nd, N),
                 "coef": sl(v.coef, nd * N, tdt, es).view(nd, N), "diag": sl(v.diag, N, tdt, es),
                 "dinv": sl(v.dinv, N, tdt, es), "ghat": sl(v.ghat, N, tdt, es),
                 "degree": sl(v.degree, N, torch.float64, 8), "mask": sl(v.mask, N, torch.uint8, 1),
@@ -495,7 +496,7 @@ def cg_solve_rhs(g: Graph, seed_node, seed_label, C: int, B: torch.Tensor, tol: 
 
 
 def graph_set_scale(g: Graph, scale: torch.Tensor) -> None:
-    scale = scale.to(g.dtype).contiguous()
+    scale = scale.to(torch.float64).contiguous()
     _check(lib().rw_graph_set_scale(g.handle, _ptr(scale), _stream(g.device)))
 
 

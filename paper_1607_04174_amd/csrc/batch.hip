@@ -8,6 +8,9 @@
 // capacities given at creation).  The reconstruction's launch shape (threads per block, nodes per
 // thread) is chosen at creation by timing the candidates on the batch itself (autotuner), with the
 // choice cached per batch shape for the process and, if RW_AUTOTUNE_CACHE names a file, on disk.
+// Each image's basis is taken in FP64 as the exact null vector plus the other columns made orthogonal to
+// it, as in the single-image solve; the constants of that correction (c_j, n_j) are computed once at
+// creation, so the graphs and bases must not change while the batch is used.
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -29,8 +32,9 @@ struct BatchImg {
   int m;
   int C;              // labels this round
   int C_cap;
-  const void* coef;
-  const void* diag;
+  const double* weight;   // FP64 edge weights (ndir x N)
+  const double* sums;     // [0] = 1^T D 1
+  const double* cn;       // 2 m: c_j, n_j of the FP64 basis
   const double* degree;
   const void* dinv;
   const void* Q;
@@ -70,6 +74,8 @@ struct rw_batch_impl {
   int32_t* d_seed_img = nullptr;
   BatchTile* d_tiles = nullptr;
   int64_t* d_total = nullptr;   // seeds in the current round (device copy, read by the kernels)
+  double* d_npart = nullptr;    // basis-constant partials (used at creation)
+  int* d_nbad = nullptr;        // per image: a basis column in the span of the null vector
   int64_t tile_cap = 0;
   // host mirrors
   std::vector<BatchImg> desc;
@@ -95,7 +101,13 @@ static size_t batch_layout(const rw_batch_image* imgs, int n, void* base, rw_bat
   int32_t* si = c.take<int32_t>(std::max<int64_t>(S_tot, 1));
   BatchTile* tl = c.take<BatchTile>(std::max<int64_t>(tiles, 1));
   int64_t* tot = c.take<int64_t>(1);
+  size_t npc = 1;
+  for (int i = 0; i < n; ++i) npc = std::max(npc, null_stats_partial_count(imgs[i].g->g.N, imgs[i].m));
+  double* npart = c.take<double>(npc);
+  int* nbad = c.take<int>((size_t)n);
   if (b) {
+    b->d_npart = npart;
+    b->d_nbad = nbad;
     b->d_desc = desc; b->d_jobs = jobs; b->d_seed_node = sn; b->d_seed_label = sl; b->d_seed_img = si;
     b->d_tiles = tl; b->d_total = tot; b->tile_cap = tiles; b->S_total_cap = S_tot;
     b->desc.resize(n);
@@ -113,6 +125,7 @@ static size_t batch_layout(const rw_batch_image* imgs, int n, void* base, rw_bat
     double* K = c.take<double>(m * m);
     double* Y = c.take<double>(m * Cc);
     double* st = c.take<double>(8);
+    double* cn = c.take<double>(2 * m);
     if (b) {
       BatchImg& d = b->desc[i];
       const Graph* g = &im.g->g;
@@ -121,7 +134,7 @@ static size_t batch_layout(const rw_batch_image* imgs, int n, void* base, rw_bat
       d.m = im.m;
       d.C = 0;
       d.C_cap = im.C_cap;
-      d.coef = g->coef; d.diag = g->diag; d.degree = g->degree; d.dinv = g->dinv;
+      d.weight = g->weight; d.sums = g->sums; d.cn = cn; d.degree = g->degree; d.dinv = g->dinv;
       d.Q = im.Q; d.lambda = im.lambda; d.U = im.U; d.map = map;
       d.seed_off = 0; d.S = 0; d.S_cap = S;
       d.Qs = Qs; d.GB = GB; d.Hs = Hs; d.Us = Us; d.T = T; d.R = R; d.K = K; d.Y = Y; d.stat = st;
@@ -146,48 +159,14 @@ __global__ void k_b_set_maps(const BatchImg* D, const int64_t* node, const int32
   D[img[k]].map[node[k]] = (uint8_t)(label[k] + 1);
 }
 
-template <typename TQ, typename TG>
+template <typename TQ>
 __global__ void k_b_gather(const BatchImg* D, const int64_t* node, const int32_t* label, const int32_t* img,
                            const int64_t* total) {
   const int64_t gk = blockIdx.x;
   if (gk >= *total) return;
   const BatchImg& d = D[img[gk]];
-  const GridDev& G = d.G;
-  const int64_t k = gk - d.seed_off;      // index within the image
-  const int64_t S = d.S_cap;              // leading dimension of the per-image seed arrays
-  const int64_t i = node[gk];
-  const int64_t x = i % G.nx, y = (i / G.nx) % G.ny, z = i / (G.nx * G.ny);
-  const TQ* Q = static_cast<const TQ*>(d.Q);
-  const TG* coef = static_cast<const TG*>(d.coef);
-  int64_t nb[8];
-  double cf[8];
-  int cnt = 0;
-  for (int dd = 0; dd < G.ndir; ++dd) {
-    if (head_in(G, x, y, z, dd)) { nb[cnt] = i + G.off[dd]; cf[cnt] = (double)coef[dd * G.N + i]; ++cnt; }
-    if (tail_in(G, x, y, z, dd)) { nb[cnt] = i - G.off[dd]; cf[cnt] = (double)coef[dd * G.N + i - G.off[dd]]; ++cnt; }
-  }
-  for (int j = threadIdx.x; j < d.m; j += blockDim.x) {
-    const TQ* qc = Q + (int64_t)j * G.N;
-    d.Qs[k + (int64_t)j * S] = (double)Elem<TQ>::ld(qc, i);
-    double acc = 0.0;
-    for (int t = 0; t < cnt; ++t)
-      if (d.map[nb[t]] == 0) acc -= cf[t] * (double)Elem<TQ>::ld(qc, nb[t]);
-    d.GB[k + (int64_t)j * S] = acc;
-  }
-  for (int lab = threadIdx.x; lab < d.C; lab += blockDim.x) {
-    auto uhat = [&](int64_t nd, int ml) -> double {
-      if (ml - 1 != lab) return 0.0;
-      return d.normalized ? sqrt(d.degree[nd]) : 1.0;
-    };
-    const double own = uhat(i, d.map[i]);
-    double acc = (double)static_cast<const TG*>(d.diag)[i] * own;
-    for (int t = 0; t < cnt; ++t) {
-      const int ml = d.map[nb[t]];
-      if (ml != 0) acc -= cf[t] * uhat(nb[t], ml);
-    }
-    d.Hs[k + (int64_t)lab * S] = acc;
-    d.Us[k + (int64_t)lab * S] = own;
-  }
+  gather_seed_row<TQ>(d.G, d.normalized, d.weight, d.degree, d.sums, static_cast<const TQ*>(d.Q), d.m, d.map, node[gk],
+                      d.C, d.cn, gk - d.seed_off, d.S_cap, d.Qs, d.GB, d.Hs, d.Us, nullptr, nullptr);
 }
 
 // T = Q_s^T GB and R = Q_s^T Hs per image (FP64, summed over the image's S seeds in order), then
@@ -213,9 +192,16 @@ __global__ void k_b_reduced(const BatchImg* D, LuJob* jobs) {
   }
 }
 
-// persistent reconstruction over the (image, tile) list: U = D^{-1/2} Q Y on non-seeds, one-hot on
-// seeds.  Y (m x CB, zero-padded labels) is staged in LDS per tile; each thread owns NPT nodes and keeps
-// 4 * NPT loads of Q in flight (the j loop is unrolled by 4), so the pass over Q is bandwidth-bound.
+// after the batched LU: the coefficients of the stored columns and the null vector's term per image
+__global__ __launch_bounds__(256) void k_b_coeffs(const BatchImg* D) {
+  const BatchImg& d = D[blockIdx.x];
+  solve_coeffs_block(d.Y, d.m, d.C, d.cn, ghat_scaled64(d.sums, d.normalized, d.G.N));
+}
+
+// persistent reconstruction over the (image, tile) list: U = D^{-1/2} sum_{j>=1} Q_j Y_j + kappa on non-seeds,
+// one-hot on seeds.  Y's rows 1..m-1 (x CB, zero-padded labels) and kappa (row 0) are staged in LDS per tile;
+// each thread owns NPT nodes and keeps 4 * NPT loads of Q in flight (the j loop is unrolled by 4), so the
+// pass over Q is bandwidth-bound.
 template <typename TQ, typename TU, int NPT, int CB>
 __global__ __launch_bounds__(512) void k_b_reconstruct(const BatchImg* D, const BatchTile* tiles, int64_t ntiles) {
   using CT = typename Elem<TQ>::C;
@@ -224,15 +210,18 @@ __global__ __launch_bounds__(512) void k_b_reconstruct(const BatchImg* D, const 
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const BatchTile tl = tiles[t];
     const BatchImg& d = D[tl.img];
-    const int m = d.m, C = d.C;
+    const int m = d.m - 1, C = d.C;   // columns 1 .. d.m - 1
+    CT* sK = sY + m * CB;
     __syncthreads();
-    for (int q = threadIdx.x; q < m * CB; q += blockDim.x) {
+    for (int q = threadIdx.x; q < d.m * CB; q += blockDim.x) {
       const int j = q / CB, c = q % CB;
-      sY[q] = c < C ? (CT)d.Y[j + (int64_t)c * m] : CT(0);
+      const CT v = c < C ? (CT)d.Y[j + (int64_t)c * d.m] : CT(0);
+      if (j == 0) sK[c] = v;
+      else sY[(j - 1) * CB + c] = v;
     }
     __syncthreads();
-    const TQ* Q = static_cast<const TQ*>(d.Q);
     const int64_t N = d.G.N;
+    const TQ* Q = static_cast<const TQ*>(d.Q) + N;
     int64_t ii[NPT];
     bool ok[NPT];
 #pragma unroll
@@ -277,9 +266,11 @@ __global__ __launch_bounds__(512) void k_b_reconstruct(const BatchImg* D, const 
       const int64_t i = ii[r];
       const int ml = d.map[i];
       const CT sc = d.normalized ? (CT) static_cast<const TU*>(d.dinv)[i] : CT(1);
+      const bool live = !d.normalized || sc > CT(0);
 #pragma unroll
       for (int c = 0; c < CB; ++c)
-        if (c < C) U[(int64_t)c * N + i] = ml ? (ml - 1 == c ? TU(1) : TU(0)) : (TU)(sc * acc[r][c]);
+        if (c < C)
+          U[(int64_t)c * N + i] = ml ? (ml - 1 == c ? TU(1) : TU(0)) : (TU)(sc * acc[r][c] + (live ? sK[c] : CT(0)));
     }
   }
 }
@@ -327,7 +318,7 @@ static int build_tiles(rw_batch_impl* b, Variant v, hipStream_t s) {
 
 template <typename TQ, typename TU, int CB>
 static int launch_recon_cb(const rw_batch_impl* b, Variant v, hipStream_t s) {
-  const size_t sh = (size_t)b->max_m * CB * sizeof(typename Elem<TQ>::C);
+  const size_t sh = (size_t)b->max_m * CB * sizeof(typename Elem<TQ>::C);   // (m - 1) rows + kappa
   const unsigned grid = (unsigned)std::min<int64_t>(b->ntiles, 2048);
   if (grid == 0) return RW_OK;
   if (v.npt == 1) k_b_reconstruct<TQ, TU, 1, CB><<<grid, v.threads, sh, s>>>(b->d_desc, b->d_tiles, b->ntiles);
@@ -451,7 +442,25 @@ int rw_batch_create(const rw_batch_image* imgs, int n, void* work, size_t work_b
     set_error("batch descriptors: %s", hipGetErrorString(e));
     return RW_EHIP;
   }
-  int st = autotune(b, stream);
+  // basis constants of every image (one pass over each basis), checked before the batch is handed out
+  int st = RW_OK;
+  std::vector<int> nbad((size_t)n, 0);
+  if (hipMemsetAsync(b->d_nbad, 0, n * sizeof(int), stream) != hipSuccess) st = RW_EHIP;
+  for (int i = 0; i < n && st == RW_OK; ++i)
+    st = null_stats(&imgs[i].g->g, imgs[i].Q, qdt, imgs[i].m, b->d_npart, const_cast<double*>(b->desc[i].cn),
+                    b->d_nbad + i, stream);
+  if (st == RW_OK && (hipMemcpyAsync(nbad.data(), b->d_nbad, n * sizeof(int), hipMemcpyDeviceToHost, stream) !=
+                          hipSuccess ||
+                      hipStreamSynchronize(stream) != hipSuccess)) {
+    set_error("batch basis constants: %s", hipGetErrorString(hipGetLastError()));
+    st = RW_EHIP;
+  }
+  for (int i = 0; i < n && st == RW_OK; ++i)
+    if (nbad[i]) {
+      set_error("image %d: basis column %d lies in the span of the null vector (column 0)", i, nbad[i]);
+      st = RW_EINVAL;
+    }
+  if (st == RW_OK) st = autotune(b, stream);
   if (st != RW_OK) {
     delete h;
     return st;
@@ -537,18 +546,12 @@ int rw_batch_enqueue(rw_batch h, hipStream_t stream) {
   k_b_set_maps<<<nblocks(cap, 256), 256, 0, stream>>>(b->d_desc, b->d_seed_node, b->d_seed_label, b->d_seed_img,
                                                       b->d_total);
   RW_LAUNCH_CHECK();
-#define RW_BGATHER(TQ, TG)                                                                                  \
-  k_b_gather<TQ, TG><<<(unsigned)cap, 256, 0, stream>>>(b->d_desc, b->d_seed_node, b->d_seed_label, b->d_seed_img, \
-                                                        b->d_total)
-  if (b->gdt == RW_F64) {
-    if (b->qdt == RW_F64) RW_BGATHER(double, double);
-    else if (b->qdt == RW_F32) RW_BGATHER(float, double);
-    else RW_BGATHER(uint16_t, double);
-  } else {
-    if (b->qdt == RW_F64) RW_BGATHER(double, float);
-    else if (b->qdt == RW_F32) RW_BGATHER(float, float);
-    else RW_BGATHER(uint16_t, float);
-  }
+#define RW_BGATHER(TQ)                                                                                  \
+  k_b_gather<TQ><<<(unsigned)cap, 256, 0, stream>>>(b->d_desc, b->d_seed_node, b->d_seed_label, b->d_seed_img, \
+                                                    b->d_total)
+  if (b->qdt == RW_F64) RW_BGATHER(double);
+  else if (b->qdt == RW_F32) RW_BGATHER(float);
+  else RW_BGATHER(uint16_t);
 #undef RW_BGATHER
   RW_LAUNCH_CHECK();
   const int64_t per_img = (int64_t)b->max_m * (b->max_m + kBatchMaxC);
@@ -556,6 +559,8 @@ int rw_batch_enqueue(rw_batch h, hipStream_t stream) {
                                                                                                       b->d_jobs);
   RW_LAUNCH_CHECK();
   RW_TRY(lu_solve_batched(b->d_jobs, b->n, stream));
+  k_b_coeffs<<<b->n, 256, 0, stream>>>(b->d_desc);
+  RW_LAUNCH_CHECK();
   RW_TRY(launch_recon(b, b->var, stream));
   return RW_OK;
 }

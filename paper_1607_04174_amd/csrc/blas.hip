@@ -486,11 +486,15 @@ static int64_t gram_big_chunks(int64_t rows, int bx, int by, bool sym) {
   return std::max<int64_t>(1, std::min<int64_t>(want, by_rows));
 }
 
-static bool gram_is_big(int bx, int by) { return bx >= 96 && by >= 96; }
+// the matrix-core kernel for wide products, and for short ones (the small dense systems: at most 4096 rows)
+// from 32 columns on, where the VALU kernel's 64 x 64 tiles leave most of the chip idle
+static bool gram_is_big(int64_t rows, int bx, int by) {
+  return (bx >= 96 && by >= 96) || (rows <= 4096 && bx >= 32 && by >= 32);
+}
 
 size_t gram_partial_count(int64_t rows, int bx, int by) {
   // the symmetric case has the most chunks (fewer tiles)
-  int64_t nch = gram_is_big(bx, by) ? gram_big_chunks(rows, bx, by, bx == by) : gram_chunks(rows, bx, by);
+  int64_t nch = gram_is_big(rows, bx, by) ? gram_big_chunks(rows, bx, by, bx == by) : gram_chunks(rows, bx, by);
   size_t c = (size_t)nch * bx * by;
   // FP32 partials of the symmetric FP32 kernel, for any width up to bx (callers may use fewer columns)
   const int sb = std::min(bx, kSGMaxN);
@@ -526,7 +530,7 @@ int gram(int dt, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t
     RW_LAUNCH_CHECK();
     return RW_OK;
   }
-  const bool big = gram_is_big(bx, by);
+  const bool big = gram_is_big(rows, bx, by);
   const int slab = big ? kGMRows : kGK;
   const int sy = (sym && bx == by) ? 1 : 0;
   int64_t nch = big ? gram_big_chunks(rows, bx, by, sy != 0) : gram_chunks(rows, bx, by);

@@ -79,12 +79,11 @@ __global__ void k_grad_J(GridDev G, int form, double beta, const double* J, cons
   dJ[i] = acc;
 }
 
-template <typename T>
-__global__ void k_set_scale(GridDev G, const T* in, const uint8_t* mask, T* scale) {
+__global__ void k_set_scale(GridDev G, const double* in, const uint8_t* mask, double* scale) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= G.N) return;
   const uint8_t m = mask[i];
-  for (int d = 0; d < G.ndir; ++d) scale[d * G.N + i] = ((m >> d) & 1u) ? in[d * G.N + i] : T(0);
+  for (int d = 0; d < G.ndir; ++d) scale[d * G.N + i] = ((m >> d) & 1u) ? in[d * G.N + i] : 0.0;
 }
 
 // Y(k, i) = s_i B(k, i) with s = d^{-1/2} (normalized) or 1
@@ -122,10 +121,7 @@ int rw_graph_set_scale(rw_graph h, const void* scale, hipStream_t stream) {
   RW_CHECK(h != nullptr && scale != nullptr, RW_EINVAL, "null argument");
   Graph* g = &h->g;
   GridDev G = grid_of(g);
-  if (g->dtype == RW_F64)
-    k_set_scale<double><<<nblocks(g->N, 256), 256, 0, stream>>>(G, (const double*)scale, g->mask, (double*)g->scale);
-  else
-    k_set_scale<float><<<nblocks(g->N, 256), 256, 0, stream>>>(G, (const float*)scale, g->mask, (float*)g->scale);
+  k_set_scale<<<nblocks(g->N, 256), 256, 0, stream>>>(G, (const double*)scale, g->mask, g->scale);
   RW_LAUNCH_CHECK();
   return graph_rebuild(g, stream);
 }

@@ -39,8 +39,7 @@ int host_stage(size_t bytes, void** p) {
 
 static constexpr int64_t kEditStage = 65536;  // edge ids staged per chunk of an edit list
 
-template <typename T>
-__global__ void k_graph_init(GridDev G, const void* Jsrc, int Jdt, double* J, T* scale, uint8_t* mask) {
+__global__ void k_graph_init(GridDev G, const void* Jsrc, int Jdt, double* J, double* scale, uint8_t* mask) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= G.N) return;
   J[i] = Jdt == RW_F64 ? static_cast<const double*>(Jsrc)[i] : (double)static_cast<const float*>(Jsrc)[i];
@@ -48,18 +47,19 @@ __global__ void k_graph_init(GridDev G, const void* Jsrc, int Jdt, double* J, T*
   uint8_t m = 0;
   for (int d = 0; d < G.ndir; ++d) {
     bool ok = head_in(G, x, y, z, d);
-    scale[d * G.N + i] = ok ? T(1) : T(0);
+    scale[d * G.N + i] = ok ? 1.0 : 0.0;
     if (ok) m |= uint8_t(1u << d);
   }
   mask[i] = m;
 }
 
-// w_e = s_e * exp(-beta * f(J_tail - J_head)), computed in FP64 and rounded once to T.
+// w_e = s_e * exp(-beta * f(J_tail - J_head)) in FP64.  Scales, weights and degrees are FP64 on every
+// graph; only the operator's coefficients (coef, diag, dinv, ghat) take the graph's type, so the seed
+// rows of the online solve can be formed from FP64 values on an FP32 graph.
 // `flip` is set when an edge's weight crosses kAnchorWeight (the connectivity used by the solvability
 // check changes only then); it reads the previous weights, so on a first build it means nothing.
-template <typename T>
-__global__ void k_weights(GridDev G, const double* J, double beta, int form, const T* scale,
-                          const uint8_t* mask, T* weight, int* flip) {
+__global__ void k_weights(GridDev G, const double* J, double beta, int form, const double* scale,
+                          const uint8_t* mask, double* weight, int* flip) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= G.N) return;
   uint8_t m = mask[i];
@@ -69,26 +69,25 @@ __global__ void k_weights(GridDev G, const double* J, double beta, int form, con
     if ((m >> d) & 1u) {
       double diff = J[i] - J[i + G.off[d]];
       double e = form == RW_WEIGHT_SQUARED ? diff * diff : fabs(diff);
-      w = (double)scale[d * G.N + i] * exp(-beta * e);
+      w = scale[d * G.N + i] * exp(-beta * e);
     }
-    const T old = weight[d * G.N + i], nw = T(w);
-    crossed |= ((double)old >= kAnchorWeight) != ((double)nw >= kAnchorWeight);
-    weight[d * G.N + i] = nw;
+    const double old = weight[d * G.N + i];
+    crossed |= (old >= kAnchorWeight) != (w >= kAnchorWeight);
+    weight[d * G.N + i] = w;
   }
   if (crossed) *flip = 1;
 }
 
 // degree: forward edges stored at i, backward edges stored at the tail i - off[d]; fixed order.
-template <typename T>
-__global__ void k_degree(GridDev G, const T* weight, double* degree, double* partial) {
+__global__ void k_degree(GridDev G, const double* weight, double* degree, double* partial) {
   double local = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.N;
        i += (int64_t)gridDim.x * blockDim.x) {
     int64_t x = i % G.nx, y = (i / G.nx) % G.ny, z = i / (G.nx * G.ny);
     double d = 0.0;
-    for (int k = 0; k < G.ndir; ++k) d += (double)weight[k * G.N + i];
+    for (int k = 0; k < G.ndir; ++k) d += weight[k * G.N + i];
     for (int k = 0; k < G.ndir; ++k)
-      if (tail_in(G, x, y, z, k)) d += (double)weight[k * G.N + i - G.off[k]];
+      if (tail_in(G, x, y, z, k)) d += weight[k * G.N + i - G.off[k]];
     degree[i] = d;
     local += d;
   }
@@ -118,7 +117,7 @@ __global__ void k_sum_partials(const double* partial, int n, double* out) {
 
 template <typename T>
 __global__ void k_finish(GridDev G, int normalized, const double* degree, const double* sums,
-                         const T* weight, const uint8_t* mask, T* dinv, T* ghat, T* diag, T* coef) {
+                         const double* weight, const uint8_t* mask, T* dinv, T* ghat, T* diag, T* coef) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= G.N) return;
   double d = degree[i];
@@ -135,7 +134,7 @@ __global__ void k_finish(GridDev G, int normalized, const double* degree, const 
   for (int k = 0; k < G.ndir; ++k) {
     double c = 0.0;
     if ((m >> k) & 1u) {
-      double w = (double)weight[k * G.N + i];
+      double w = weight[k * G.N + i];
       if (normalized) {
         double dh = degree[i + G.off[k]];
         double dhi = dh > 0.0 ? 1.0 / sqrt(dh) : 0.0;
@@ -148,9 +147,8 @@ __global__ void k_finish(GridDev G, int normalized, const double* degree, const 
   }
 }
 
-template <typename T>
 __global__ void k_scale_box(GridDev G, int64_t x0, int64_t y0, int64_t z0, int64_t x1, int64_t y1,
-                            int64_t z1, double v, const uint8_t* mask, T* scale) {
+                            int64_t z1, double v, const uint8_t* mask, double* scale) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= G.N) return;
   int64_t x = i % G.nx, y = (i / G.nx) % G.ny, z = i / (G.nx * G.ny);
@@ -160,17 +158,16 @@ __global__ void k_scale_box(GridDev G, int64_t x0, int64_t y0, int64_t z0, int64
     if (!((m >> d) & 1u)) continue;
     int64_t a = x + G.dx[d], b = y + G.dy[d], c = z + G.dz[d];
     if (a < x0 || a >= x1 || b < y0 || b >= y1 || c < z0 || c >= z1) continue;
-    scale[d * G.N + i] = T((double)scale[d * G.N + i] * v);
+    scale[d * G.N + i] *= v;
   }
 }
 
 // ids are distinct within one launch (checked on the host), so no two threads touch one slot.
-template <typename T>
-__global__ void k_edit_ids(const int64_t* ids, int64_t n, double v, int remove, T* scale) {
+__global__ void k_edit_ids(const int64_t* ids, int64_t n, double v, int remove, double* scale) {
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= n) return;
   int64_t e = ids[k];
-  scale[e] = remove ? T(0) : T((double)scale[e] * v);
+  scale[e] = remove ? 0.0 : scale[e] * v;
 }
 
 size_t graph_layout(const rw_graph_desc& d, Graph* g, void* buf) {
@@ -179,8 +176,8 @@ size_t graph_layout(const rw_graph_desc& d, Graph* g, void* buf) {
   size_t es = dtype_size(d.dtype);
   Carver c(buf);
   double* J = c.take<double>(N);
-  char* scale = c.take<char>(nd * N * es);
-  char* weight = c.take<char>(nd * N * es);
+  double* scale = c.take<double>(nd * N);
+  double* weight = c.take<double>(nd * N);
   char* coef = c.take<char>(nd * N * es);
   char* diag = c.take<char>(N * es);
   char* dinv = c.take<char>(N * es);
@@ -214,15 +211,15 @@ template <typename T>
 static int rebuild_t(Graph* g, hipStream_t s) {
   GridDev G = grid_of(g);
   const int t = 256;
-  k_weights<T><<<nblocks(g->N, t), t, 0, s>>>(G, g->J, g->beta, g->weight_form, (const T*)g->scale,
-                                                g->mask, (T*)g->weight, g->cc_flag + 4);
+  k_weights<<<nblocks(g->N, t), t, 0, s>>>(G, g->J, g->beta, g->weight_form, g->scale, g->mask, g->weight,
+                                             g->cc_flag + 4);
   RW_LAUNCH_CHECK();
   int nb = (int)std::min<int64_t>(kReduceBlocks, nblocks(g->N, t));
-  k_degree<T><<<nb, t, 0, s>>>(G, (const T*)g->weight, g->degree, g->partial);
+  k_degree<<<nb, t, 0, s>>>(G, g->weight, g->degree, g->partial);
   RW_LAUNCH_CHECK();
   k_sum_partials<<<1, 256, 0, s>>>(g->partial, nb, g->sums);
   RW_LAUNCH_CHECK();
-  k_finish<T><<<nblocks(g->N, t), t, 0, s>>>(G, g->normalized, g->degree, g->sums, (const T*)g->weight,
+  k_finish<T><<<nblocks(g->N, t), t, 0, s>>>(G, g->normalized, g->degree, g->sums, g->weight,
                                                g->mask, (T*)g->dinv, (T*)g->ghat, (T*)g->diag, (T*)g->coef);
   RW_LAUNCH_CHECK();
   return RW_OK;
@@ -259,8 +256,7 @@ __device__ __forceinline__ int64_t cc_find(int64_t* comp, int64_t x) {
 
 // start from the smallest index among each node and its anchored forward neighbours' tails, so the
 // first hooking round already sees short chains
-template <typename T>
-__global__ void k_cc_init(GridDev G, const T* weight, const uint8_t* mask, int64_t* comp) {
+__global__ void k_cc_init(GridDev G, const double* weight, const uint8_t* mask, int64_t* comp) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= G.N) return;
   int64_t c = i;
@@ -268,7 +264,7 @@ __global__ void k_cc_init(GridDev G, const T* weight, const uint8_t* mask, int64
   for (int d = 0; d < G.ndir; ++d) {
     if (!tail_in(G, x, y, z, d)) continue;
     const int64_t t = i - G.off[d];
-    if (((mask[t] >> d) & 1) && (double)weight[d * G.N + t] >= kAnchorWeight && t < c) c = t;
+    if (((mask[t] >> d) & 1) && weight[d * G.N + t] >= kAnchorWeight && t < c) c = t;
   }
   comp[i] = c;
 }
@@ -277,8 +273,7 @@ __global__ void k_cc_init(GridDev G, const T* weight, const uint8_t* mask, int64
 // anchoring edges in LDS (each step also jumps through the current label, which is a node of the same
 // component with an index no larger), until no label changes; then every node points to the smallest node
 // of its tile-local component.  The hooking rounds then only join tiles.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_cc_init_tile(GridDev G, const T* weight, const uint8_t* mask,
+__global__ __launch_bounds__(1024) void k_cc_init_tile(GridDev G, const double* weight, const uint8_t* mask,
                                                        int64_t* comp) {
   __shared__ int lab[1024];
   const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5, me = threadIdx.x;
@@ -293,7 +288,7 @@ __global__ __launch_bounds__(1024) void k_cc_init_tile(GridDev G, const T* weigh
     nb[2 * d] = me;
     nb[2 * d + 1] = me;
     if (!in || d >= G.ndir) continue;
-    if (((mask[i] >> d) & 1) && (double)weight[d * G.N + i] >= kAnchorWeight) {   // i -> i + off[d], stored at i
+    if (((mask[i] >> d) & 1) && weight[d * G.N + i] >= kAnchorWeight) {   // i -> i + off[d], stored at i
       const int ax = lx + G.dx[d], ay = ly + G.dy[d];
       if (ax >= 0 && ax < 32 && ay >= 0 && ay < 32 && head_in(G, x, y, 0, d)) nb[2 * d] = ay * 32 + ax;
     }
@@ -301,7 +296,7 @@ __global__ __launch_bounds__(1024) void k_cc_init_tile(GridDev G, const T* weigh
       const int64_t t = i - G.off[d];
       const int bx = lx - G.dx[d], by = ly - G.dy[d];
       if (bx >= 0 && bx < 32 && by >= 0 && by < 32 && ((mask[t] >> d) & 1) &&
-          (double)weight[d * G.N + t] >= kAnchorWeight)
+          weight[d * G.N + t] >= kAnchorWeight)
         nb[2 * d + 1] = by * 32 + bx;
     }
   }
@@ -322,8 +317,7 @@ __global__ __launch_bounds__(1024) void k_cc_init_tile(GridDev G, const T* weigh
   }
 }
 
-template <typename T>
-__global__ void k_cc_hook(GridDev G, const T* weight, const uint8_t* mask, int64_t* comp, int* changed) {
+__global__ void k_cc_hook(GridDev G, const double* weight, const uint8_t* mask, int64_t* comp, int* changed) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const bool valid = i < G.N;
   const uint8_t mk = valid ? mask[i] : 0;
@@ -331,7 +325,7 @@ __global__ void k_cc_hook(GridDev G, const T* weight, const uint8_t* mask, int64
   bool joined = false;
   for (int d = 0; d < G.ndir; ++d) {   // uniform: every lane reaches the shuffles
     int64_t lo = -1, hi = -1;
-    if (((mk >> d) & 1) && (double)weight[d * G.N + i] >= kAnchorWeight) {
+    if (((mk >> d) & 1) && weight[d * G.N + i] >= kAnchorWeight) {
       const int64_t a = cc_find(comp, i), b = cc_find(comp, i + G.off[d]);
       if (a != b) {
         lo = a < b ? a : b;
@@ -379,22 +373,14 @@ int graph_components(Graph* g, hipStream_t s) {
   const GridDev G = grid_of(g);
   if (g->nz == 1) {
     const dim3 tiles((unsigned)((g->nx + 31) / 32), (unsigned)((g->ny + 31) / 32));
-    if (g->dtype == RW_F64)
-      k_cc_init_tile<double><<<tiles, 1024, 0, s>>>(G, (const double*)g->weight, g->mask, g->comp);
-    else
-      k_cc_init_tile<float><<<tiles, 1024, 0, s>>>(G, (const float*)g->weight, g->mask, g->comp);
-  } else if (g->dtype == RW_F64) {
-    k_cc_init<double><<<nblocks(g->N, 256), 256, 0, s>>>(G, (const double*)g->weight, g->mask, g->comp);
+    k_cc_init_tile<<<tiles, 1024, 0, s>>>(G, g->weight, g->mask, g->comp);
   } else {
-    k_cc_init<float><<<nblocks(g->N, 256), 256, 0, s>>>(G, (const float*)g->weight, g->mask, g->comp);
+    k_cc_init<<<nblocks(g->N, 256), 256, 0, s>>>(G, g->weight, g->mask, g->comp);
   }
   RW_LAUNCH_CHECK();
   auto cc_round = [&]() -> int {   // hook and jump, cc_flag[0] set when a label changed
     RW_HIP(hipMemsetAsync(g->cc_flag, 0, sizeof(int), s));
-    if (g->dtype == RW_F64)
-      k_cc_hook<double><<<nblocks(g->N, 256), 256, 0, s>>>(G, (const double*)g->weight, g->mask, g->comp, g->cc_flag);
-    else
-      k_cc_hook<float><<<nblocks(g->N, 256), 256, 0, s>>>(G, (const float*)g->weight, g->mask, g->comp, g->cc_flag);
+    k_cc_hook<<<nblocks(g->N, 256), 256, 0, s>>>(G, g->weight, g->mask, g->comp, g->cc_flag);
     RW_LAUNCH_CHECK();
     k_cc_jump<<<nblocks(g->N, 256), 256, 0, s>>>(g->comp, g->N);
     RW_LAUNCH_CHECK();
@@ -514,10 +500,7 @@ int rw_build_graph(const rw_graph_desc* desc, const void* J_dev, int J_dtype, do
   }
   graph_layout(*desc, g, graph_buf);
   GridDev G = grid_of(g);
-  if (g->dtype == RW_F64)
-    k_graph_init<double><<<nblocks(g->N, 256), 256, 0, stream>>>(G, J_dev, J_dtype, g->J, (double*)g->scale, g->mask);
-  else
-    k_graph_init<float><<<nblocks(g->N, 256), 256, 0, stream>>>(G, J_dev, J_dtype, g->J, (float*)g->scale, g->mask);
+  k_graph_init<<<nblocks(g->N, 256), 256, 0, stream>>>(G, J_dev, J_dtype, g->J, g->scale, g->mask);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { delete h; set_error("graph init launch: %s", hipGetErrorString(e)); return RW_EHIP; }
   int st = graph_rebuild(g, stream);
@@ -612,22 +595,15 @@ int rw_edit_graph(rw_graph h, const rw_edit* edits, int n_edits, hipStream_t str
     if (e.kind == RW_EDIT_SET_BETA) {
       g->beta = e.value;
     } else if (e.kind == RW_EDIT_SCALE_BOX) {
-      if (g->dtype == RW_F64)
-        k_scale_box<double><<<nblocks(g->N, 256), 256, 0, stream>>>(G, e.box_lo[0], e.box_lo[1], e.box_lo[2], e.box_hi[0],
-                                                                      e.box_hi[1], e.box_hi[2], e.value, g->mask, (double*)g->scale);
-      else
-        k_scale_box<float><<<nblocks(g->N, 256), 256, 0, stream>>>(G, e.box_lo[0], e.box_lo[1], e.box_lo[2], e.box_hi[0],
-                                                                     e.box_hi[1], e.box_hi[2], e.value, g->mask, (float*)g->scale);
+      k_scale_box<<<nblocks(g->N, 256), 256, 0, stream>>>(G, e.box_lo[0], e.box_lo[1], e.box_lo[2], e.box_hi[0],
+                                                          e.box_hi[1], e.box_hi[2], e.value, g->mask, g->scale);
       RW_LAUNCH_CHECK();
     } else {
       int rem = e.kind == RW_EDIT_REMOVE_EDGES;
       for (int64_t j0 = 0; j0 < e.n; j0 += kEditStage) {
         int64_t cnt = std::min<int64_t>(kEditStage, e.n - j0);
         RW_HIP(hipMemcpyAsync(stage, e.edge_ids + j0, cnt * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-        if (g->dtype == RW_F64)
-          k_edit_ids<double><<<nblocks(cnt, 256), 256, 0, stream>>>(stage, cnt, e.value, rem, (double*)g->scale);
-        else
-          k_edit_ids<float><<<nblocks(cnt, 256), 256, 0, stream>>>(stage, cnt, e.value, rem, (float*)g->scale);
+        k_edit_ids<<<nblocks(cnt, 256), 256, 0, stream>>>(stage, cnt, e.value, rem, g->scale);
         RW_LAUNCH_CHECK();
         // the staging area is reused by the next chunk only after this kernel has read it
         RW_HIP(hipStreamSynchronize(stream));

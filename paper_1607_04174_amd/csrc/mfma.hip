@@ -36,6 +36,12 @@ __global__ __launch_bounds__(256) void k_reconstruct_mfma(const uint16_t* __rest
                                                            const TU* __restrict__ dinv, int normalized,
                                                            TU* __restrict__ U) {
   extern __shared__ char smem[];
+  // the product runs over Q's columns 1 .. m-1 against Y's rows 1 .. m-1; Y's row 0 is the null vector's
+  // per-label term, added in the epilogue
+  Q += N;
+  Y += 1;
+  const int ldy = m;
+  m -= 1;
   const int mpad = (m + 15) & ~15;
   uint16_t* sBt = reinterpret_cast<uint16_t*>(smem);                    // [16 cols][mpad]
   uint16_t* sQ = sBt + 16 * mpad;                                       // [256 nodes][kSQ]
@@ -50,7 +56,7 @@ __global__ __launch_bounds__(256) void k_reconstruct_mfma(const uint16_t* __rest
       int c = col < C ? col : col - C;
       if (col < 2 * C) {
         uint16_t hi, lo;
-        split_bf16((float)Y[k + (int64_t)c * m], &hi, &lo);
+        split_bf16((float)Y[k + (int64_t)c * ldy], &hi, &lo);
         v = col < C ? hi : lo;
       }
     }
@@ -120,14 +126,16 @@ __global__ __launch_bounds__(256) void k_reconstruct_mfma(const uint16_t* __rest
   if (i >= N) return;
   const int ml = map[i];
   const float sc = normalized ? (float)dinv[i] : 1.0f;
+  const bool live = !normalized || sc > 0.0f;
   for (int c = 0; c < C; ++c) {
     const float val = sD[tid * 17 + c] + sD[tid * 17 + c + C];
-    U[(int64_t)c * N + i] = ml ? (ml - 1 == c ? TU(1) : TU(0)) : TU(sc * val);
+    const float kap = live ? (float)Y[(int64_t)c * ldy - 1] : 0.0f;
+    U[(int64_t)c * N + i] = ml ? (ml - 1 == c ? TU(1) : TU(0)) : TU(sc * val + kap);
   }
 }
 
 size_t reconstruct_mfma_lds(int m) {
-  const int mpad = (m + 15) & ~15;
+  const int mpad = (m - 1 + 15) & ~15;   // columns 1 .. m-1
   return (size_t)16 * mpad * 2 + (size_t)kMfmaNodes * kSQ * 2 + (size_t)kMfmaNodes * 17 * 4;
 }
 

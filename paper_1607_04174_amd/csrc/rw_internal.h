@@ -143,8 +143,8 @@ struct Graph {
   int64_t off[4] = {0, 0, 0, 0};
   // device arrays inside the caller's graph buffer
   double* J = nullptr;      // N
-  void* scale = nullptr;    // ndir x N (dtype)
-  void* weight = nullptr;   // ndir x N (dtype)
+  double* scale = nullptr;  // ndir x N (FP64 on every graph)
+  double* weight = nullptr; // ndir x N (FP64 on every graph)
   void* coef = nullptr;     // ndir x N (dtype)
   void* diag = nullptr;     // N (dtype)
   void* dinv = nullptr;     // N (dtype)
@@ -290,8 +290,129 @@ int project_out_to(int dt, const void* X, int64_t ldx, void* Y, int64_t ldy, con
                    double* tmp, double* partial, hipStream_t s);
 
 // ---- BF16 matrix-core contractions (mfma.hip) ----------------------------------------------------
+// U = s_i sum_{j>=1} Q(i, j) Y(j, c) + kappa_c on non-seeds (s = d^{-1/2} or 1; kappa_c = Y(0, c), added
+// where s > 0 or the operator is L), one-hot on seeds; Y is m x C (ld m) in the form k_solve_coeffs leaves
 int reconstruct_mfma(const Graph* g, const void* Q, int m, const double* Y, int C, const uint8_t* map, void* U,
                      hipStream_t s);
+
+// ---- FP64 view of the operator and of a stored basis, for the online solve (solve.hip) ------------
+// Seed rows of the reduced system are formed from the FP64 weights and degrees (the graph's type only
+// rounds the stencil's coefficients), and the stored basis is taken as the exact FP64 null vector plus
+// the other columns made orthogonal to it in FP64:
+//   q'_0 = g,   q'_j = (q_j - g c_j) / n_j,   c_j = g^T q_j,   n_j = ||q_j - g c_j||   (j >= 1).
+// In a weakly coupled graph the reduced system has condition numbers near 1/u, and the rounding of an
+// FP32 coefficient or of a stored low-precision null vector would decide its solution.
+__device__ __forceinline__ double dinv64(const double* degree, int64_t x) {
+  const double d = degree[x];
+  return d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+}
+// unit null vector in FP64: D^{1/2} 1 / ||D^{1/2} 1|| (sums[0] = 1^T D 1) or 1 / sqrt(N)
+__device__ __forceinline__ double ghat64(const double* degree, const double* sums, int normalized, int64_t N,
+                                         int64_t x) {
+  return normalized ? sqrt(degree[x]) / sqrt(sums[0]) : 1.0 / sqrt((double)N);
+}
+// s_i g_i on a node with d_i > 0 (s = d^{-1/2} or 1): the same for every node
+__device__ __forceinline__ double ghat_scaled64(const double* sums, int normalized, int64_t N) {
+  return normalized ? 1.0 / sqrt(sums[0]) : 1.0 / sqrt((double)N);
+}
+// cn[j] = c_j and cn[m + j] = n_j for j in [1, m) (cn[0] = 0, cn[m] = 1) of the column-major N x m basis Q
+// (column 0 the null vector); *bad (device) is set when some n_j is not positive.  partial holds
+// null_stats_partial_count(N, m) doubles.
+size_t null_stats_partial_count(int64_t N, int m);
+int null_stats(const Graph* g, const void* Q, int qdt, int m, double* partial, double* cn, int* bad, hipStream_t s);
+// After the reduced solve (Y, m x C, ld m, the coefficients of the q'_j), in place and by one workgroup:
+// Y(j, c) /= n_j for j >= 1, then Y(0, c) = kappa_c = sg (Y(0, c) - sum_{j>=1} c_j Y(j, c)) with
+// sg = ghat_scaled64, so that U = s_i sum_{j>=1} q_j(i) Y(j, c) + kappa_c on nodes with s_i > 0.
+// The column sums run in order in one lane per label.
+__device__ __forceinline__ void solve_coeffs_block(double* Y, int m, int C, const double* cn, double sg) {
+  for (int64_t t = threadIdx.x; t < (int64_t)m * C; t += blockDim.x) {
+    const int j = (int)(t % m);
+    if (j > 0) Y[t] /= cn[m + j];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    double* y = Y + (int64_t)c * m;
+    double acc = y[0];
+    for (int j = 1; j < m; ++j) acc -= cn[j] * y[j];
+    y[0] = sg * acc;
+  }
+}
+// launch of solve_coeffs_block for one system (solve.hip)
+int solve_coeffs(double* Y, int m, int C, const double* cn, const Graph* g, hipStream_t s);
+
+// Seed row k (node i, leading dimension ld) of the reduced system's inputs, formed by one workgroup from
+// the FP64 weights and degrees: for j < m, Qs(k, j) = q'_j(i) and GB(k, j) = (B q'_j)(i) = -sum over the
+// non-seed neighbours t of coef(i, t) q'_j(t), with coef(i, t) = w_it d_i^{-1/2} d_t^{-1/2} (or w_it);
+// for c < C, Us(k, c) = U_hat(i, c) (d_i^{1/2} or 1 on the seed's label) and Hs(k, c) = (op_ss U_hat_s)(i, c).
+// With cn == nullptr the stored columns q_j are gathered as they are and g(i), (B g_n)(i) go to gs[k],
+// Bg[k] for a later correction (the choice of m fits the stored columns); otherwise the q'_j of cn.
+template <typename TQ>
+__device__ void gather_seed_row(const GridDev& G, int normalized, const double* weight, const double* degree,
+                                const double* sums, const TQ* Q, int m, const uint8_t* map, int64_t i, int C,
+                                const double* cn, int64_t k, int64_t ld, double* Qs, double* GB, double* Hs,
+                                double* Us, double* gs, double* Bg) {
+  const int64_t x = i % G.nx, y = (i / G.nx) % G.ny, z = i / (G.nx * G.ny);
+  const double di = normalized ? dinv64(degree, i) : 1.0;
+  int64_t nb[8];
+  double cf[8];
+  int cnt = 0;
+  for (int d = 0; d < G.ndir; ++d) {
+    if (head_in(G, x, y, z, d)) {
+      const int64_t t = i + G.off[d];
+      const double w = weight[d * G.N + i];
+      nb[cnt] = t;
+      cf[cnt++] = normalized ? w * di * dinv64(degree, t) : w;
+    }
+    if (tail_in(G, x, y, z, d)) {
+      const int64_t t = i - G.off[d];
+      const double w = weight[d * G.N + t];
+      nb[cnt] = t;
+      cf[cnt++] = normalized ? w * di * dinv64(degree, t) : w;
+    }
+  }
+  // g(i) and (B g_n)(i)
+  const double gi = ghat64(degree, sums, normalized, G.N, i);
+  double bg = 0.0;
+  for (int t = 0; t < cnt; ++t)
+    if (map[nb[t]] == 0) bg -= cf[t] * ghat64(degree, sums, normalized, G.N, nb[t]);
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    const TQ* qc = Q + (int64_t)j * G.N;
+    double qv = (double)Elem<TQ>::ld(qc, i);
+    double acc = 0.0;
+    for (int t = 0; t < cnt; ++t)
+      if (map[nb[t]] == 0) acc -= cf[t] * (double)Elem<TQ>::ld(qc, nb[t]);
+    if (cn != nullptr) {
+      if (j == 0) {
+        qv = gi;
+        acc = bg;
+      } else {
+        qv = (qv - gi * cn[j]) / cn[m + j];
+        acc = (acc - bg * cn[j]) / cn[m + j];
+      }
+    }
+    Qs[k + (int64_t)j * ld] = qv;
+    GB[k + (int64_t)j * ld] = acc;
+  }
+  if (cn == nullptr && threadIdx.x == 0) {
+    gs[k] = gi;
+    Bg[k] = bg;
+  }
+  const double diag = normalized ? (degree[i] > 0.0 ? 1.0 : 0.0) : degree[i];
+  for (int lab = threadIdx.x; lab < C; lab += blockDim.x) {
+    auto uhat = [&](int64_t node, int mlab) -> double {
+      if (mlab - 1 != lab) return 0.0;
+      return normalized ? sqrt(degree[node]) : 1.0;
+    };
+    const double own = uhat(i, map[i]);
+    double acc = diag * own;
+    for (int t = 0; t < cnt; ++t) {
+      const int ml = map[nb[t]];
+      if (ml != 0) acc -= cf[t] * uhat(nb[t], ml);
+    }
+    Hs[k + (int64_t)lab * ld] = acc;
+    Us[k + (int64_t)lab * ld] = own;
+  }
+}
 
 // ---- small dense FP64 kernels, one workgroup per matrix (dense.hip) ------------------------------
 // In-place lower Cholesky of count matrices (n x n, ld n, stride n*n); info[b] = 0 or (k+1) of the

@@ -8,6 +8,16 @@
 //     (Lambda - Q_s^T B Q_n) Y = Q_s^T op_ss U_hat_s.
 // Its size is m, not S, and Lambda enters without inversion, so near-null eigenvalues need no
 // clamping.  The reconstruction U = D^{-1/2} Q Y is one tall-skinny pass over Q.
+//
+// Precision.  A weakly coupled graph (two regions joined by weights near the FP64 underflow of the
+// exponent) has a second near-null pair, and the reduced matrix then has a condition number near 1/u:
+// its near-singular rows are formed by cancellation, and the rounding of an FP32 coefficient, or of an
+// FP32 null vector stored as Q's column 0, decides the solution there.  So the seed rows are formed from
+// the FP64 weights and degrees, and after m is chosen the basis is taken in FP64 as the exact null vector
+// g plus the stored columns made orthogonal to it (q'_j = (q_j - g c_j) / n_j, c_j = g^T q_j): one pass
+// over Q's first m columns gives the c_j and n_j, the seed rows are corrected in place, and the
+// reconstruction reads columns 1..m-1 with the null vector's term as a per-label constant (s_i g_i is the
+// same on every node with d_i > 0).  The choice of m fits the stored columns as they are.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -30,6 +40,11 @@ struct SolveWork {
   double* GB;         // S x ma   (B Q_n)
   double* Hs;         // S x C    (op_ss U_hat_s)
   double* Us;         // S x C    (U_hat_s)
+  double* gs;         // S        (g at the seeds, FP64)
+  double* Bg;         // S        (B g_n)
+  double* cn;         // 2 ma     (c_j, n_j of the FP64 basis)
+  double* npart;      // null_stats partials
+  int* nbad;          // set when some n_j is not positive
   double* T;          // ma x ma  (Q_s^T B Q_n)
   double* R;          // ma x C   (Q_s^T op_ss U_hat_s)
   double* Gq;         // ma x ma  (Q_s^T Q_s)
@@ -60,6 +75,11 @@ static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base,
   t.GB = c.take<double>(S * ma);
   t.Hs = c.take<double>(S * C);
   t.Us = c.take<double>(S * C);
+  t.gs = c.take<double>(S);
+  t.Bg = c.take<double>(S);
+  t.cn = c.take<double>(2 * (size_t)ma);
+  t.npart = c.take<double>(null_stats_partial_count(g->N, ma));
+  t.nbad = c.take<int>(4);
   t.T = c.take<double>((size_t)ma * ma);
   t.R = c.take<double>((size_t)ma * C);
   t.Gq = c.take<double>((size_t)ma * ma);
@@ -97,65 +117,177 @@ __global__ void k_set_map(uint8_t* map, const int64_t* seeds, const int32_t* lab
   if (k < S) map[seeds[k]] = (uint8_t)(labels[k] + 1);
 }
 
-// One block per seed.  Threads over columns j gather Q_s(i, j) and (B Q_n)(i, j) =
-// -sum over non-seed neighbours t of coef(i,t) Q(t, j); threads over labels form U_hat_s and
-// op_ss U_hat_s (diag U_hat_s(i) - sum over seed neighbours of coef U_hat_s(t)).
-template <typename TQ, typename TG>
+// One block per seed: the stored columns at the seed row, B Q_n, U_hat_s, op_ss U_hat_s, g and B g_n, from the
+// FP64 weights and degrees (gather_seed_row).
+template <typename TQ>
 __global__ void k_seed_gather(GridDev G, int normalized, const TQ* Q, int ma, const int64_t* seeds,
-                              const int32_t* labels, const uint8_t* map, const TG* coef, const TG* diag,
-                              const double* degree, int64_t S, int C, double* Qs, double* GB, double* Hs,
-                              double* Us) {
+                              const uint8_t* map, const double* weight, const double* degree, const double* sums,
+                              int64_t S, int C, double* Qs, double* GB, double* Hs, double* Us, double* gs, double* Bg) {
   const int64_t k = blockIdx.x;
-  const int64_t i = seeds[k];
-  const int64_t x = i % G.nx, y = (i / G.nx) % G.ny, z = i / (G.nx * G.ny);
-  int64_t nb[8];
-  double cf[8];
-  int cnt = 0;
-  for (int d = 0; d < G.ndir; ++d) {
-    if (head_in(G, x, y, z, d)) { nb[cnt] = i + G.off[d]; cf[cnt] = (double)coef[d * G.N + i]; ++cnt; }
-    if (tail_in(G, x, y, z, d)) { nb[cnt] = i - G.off[d]; cf[cnt] = (double)coef[d * G.N + i - G.off[d]]; ++cnt; }
-  }
-  for (int j = threadIdx.x; j < ma; j += blockDim.x) {
-    const TQ* qc = Q + (int64_t)j * G.N;
-    Qs[k + (int64_t)j * S] = (double)Elem<TQ>::ld(qc, i);
-    double acc = 0.0;
-    for (int t = 0; t < cnt; ++t)
-      if (map[nb[t]] == 0) acc -= cf[t] * (double)Elem<TQ>::ld(qc, nb[t]);
-    GB[k + (int64_t)j * S] = acc;
-  }
-  for (int lab = threadIdx.x; lab < C; lab += blockDim.x) {
-    auto uhat = [&](int64_t node, int mlab) -> double {
-      if (mlab - 1 != lab) return 0.0;
-      return normalized ? sqrt(degree[node]) : 1.0;
-    };
-    double own = uhat(i, map[i]);
-    double acc = (double)diag[i] * own;
-    for (int t = 0; t < cnt; ++t) {
-      int ml = map[nb[t]];
-      if (ml != 0) acc -= cf[t] * uhat(nb[t], ml);
-    }
-    Hs[k + (int64_t)lab * S] = acc;
-    Us[k + (int64_t)lab * S] = own;
-  }
+  gather_seed_row<TQ>(G, normalized, weight, degree, sums, Q, ma, map, seeds[k], C, nullptr, k, S, Qs, GB, Hs, Us, gs,
+                      Bg);
 }
 
-// K = diag(lambda) - T (leading m x m of the ma x ma T);  Yrhs = leading m rows of R
-__global__ void k_build_reduced(const double* T, const double* R, const double* lambda, int ma, int m, int C,
-                                double* K, double* Y) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < (int64_t)m * m) {
-    int i = (int)(t % m), j = (int)(t / m);
-    K[t] = (i == j ? lambda[i] : 0.0) - T[i + (int64_t)j * ma];
-  }
-  if (t < (int64_t)m * C) {
-    int i = (int)(t % m), c = (int)(t / m);
-    Y[t] = R[i + (int64_t)c * ma];
+// seed rows of the FP64 basis: column 0 becomes g, the others (q_j - g c_j) / n_j (in place, first m columns)
+__global__ void k_seed_correct(double* Qs, double* GB, const double* gs, const double* Bg, const double* cn, int64_t S,
+                               int m) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= S * m) return;
+  const int64_t k = t % S;
+  const int j = (int)(t / S);
+  if (j == 0) {
+    Qs[t] = gs[k];
+    GB[t] = Bg[k];
+  } else {
+    const double c = cn[j], n = cn[m + j];
+    Qs[t] = (Qs[t] - gs[k] * c) / n;
+    GB[t] = (GB[t] - Bg[k] * c) / n;
   }
 }
 
 // ---------------------------------------------------------------------------------------------
-// reconstruction: U(lab, i) = s_i * sum_j Q(i, j) Y(j, lab) on non-seeds (s = d^{-1/2} or 1),
-// one-hot on seeds.  Y lives in LDS; each thread owns one node and CB labels.
+// c_j = g^T q_j and ||q_j||^2 for j in [1, m): blocks over (2048-row chunk, 8 columns); each thread issues
+// all 64 loads of its eight rows x eight columns before any reduction, sums in FP64 (products of FP32 or
+// BF16 values are exact), then 16 wave sums by DPP and the four waves in order; per column, one wave sums
+// the chunk partials (fixed order, so the result does not depend on the launch).
+// ---------------------------------------------------------------------------------------------
+constexpr int kNsRowsPerThread = 8;
+constexpr int kNsRows = 256 * kNsRowsPerThread;
+constexpr int kNsCols = 8;
+
+size_t null_stats_partial_count(int64_t N, int m) {
+  return (size_t)2 * m * (size_t)((N + kNsRows - 1) / kNsRows);
+}
+
+template <typename TQ>
+__global__ __launch_bounds__(256) void k_null_stats(const TQ* Q, int64_t N, int m, const double* degree,
+                                                    int normalized, double* partial, int64_t nchunk) {
+  __shared__ double sh[4][2 * kNsCols];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t chunk = blockIdx.x;
+  const int j0 = 1 + (int)blockIdx.y * kNsCols;
+  const int ncol = min(kNsCols, m - j0);   // >= 1, uniform
+  const int64_t r0 = chunk * kNsRows + tid;
+  // clamped rows and columns keep every load unconditional (straight-line code, all loads in flight);
+  // rows past N carry weight 0, columns past m - 1 are read again and not stored
+  int64_t ic[kNsRowsPerThread];
+  double msk[kNsRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kNsRowsPerThread; ++q) {
+    const int64_t i = r0 + 256 * q;
+    ic[q] = i < N ? i : N - 1;
+    msk[q] = i < N ? 1.0 : 0.0;
+  }
+  double v[kNsCols][kNsRowsPerThread];
+#pragma unroll
+  for (int jj = 0; jj < kNsCols; ++jj) {
+    const TQ* qc = Q + (int64_t)(j0 + min(jj, ncol - 1)) * N;
+#pragma unroll
+    for (int q = 0; q < kNsRowsPerThread; ++q) v[jj][q] = (double)Elem<TQ>::ld(qc, ic[q]);
+  }
+  double sd[kNsRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kNsRowsPerThread; ++q) sd[q] = msk[q] * (normalized ? sqrt(degree[ic[q]]) : 1.0);
+#pragma unroll
+  for (int jj = 0; jj < kNsCols; ++jj) {
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int q = 0; q < kNsRowsPerThread; ++q) {
+      a += sd[q] * v[jj][q];
+      b += msk[q] * (v[jj][q] * v[jj][q]);
+    }
+    a = wave_sum64(a);
+    b = wave_sum64(b);
+    if (lane == 0) {
+      sh[wave][2 * jj] = a;
+      sh[wave][2 * jj + 1] = b;
+    }
+  }
+  __syncthreads();
+  if (tid < 2 * ncol) {
+    const int j = j0 + tid / 2;
+    const double t = (sh[0][tid] + sh[1][tid]) + (sh[2][tid] + sh[3][tid]);
+    partial[((int64_t)j * 2 + (tid & 1)) * nchunk + chunk] = t;
+  }
+}
+
+// one wave per column j >= 1 (block j - 1): lanes take the chunk partials in strides, then a wave sum
+__global__ __launch_bounds__(64) void k_null_finish(const double* partial, int64_t nchunk, int m, const double* sums,
+                                                    int normalized, int64_t N, double* cn, int* bad) {
+  const int j = 1 + blockIdx.x;
+  const int lane = threadIdx.x;
+  const double* pa = partial + (int64_t)j * 2 * nchunk;
+  const double* pb = pa + nchunk;
+  double a = 0.0, b = 0.0;
+  for (int64_t q = lane; q < nchunk; q += 64) {
+    a += pa[q];
+    b += pb[q];
+  }
+  a = wave_sum64(a);
+  b = wave_sum64(b);
+  if (lane == 0) {
+    // g = D^{1/2} 1 / sqrt(1^T D 1) (or 1 / sqrt(N)): c_j = (sum_i d_i^{1/2} q_ij) / sqrt(1^T D 1)
+    const double c = a / sqrt(normalized ? sums[0] : (double)N);
+    const double n2 = b - c * c;
+    cn[j] = c;
+    cn[m + j] = n2 > 0.0 ? sqrt(n2) : 1.0;
+    if (!(n2 > 0.0)) *bad = j;
+    if (j == 1) {
+      cn[0] = 0.0;
+      cn[m] = 1.0;
+    }
+  }
+}
+
+int null_stats(const Graph* g, const void* Q, int qdt, int m, double* partial, double* cn, int* bad, hipStream_t s) {
+  const int64_t nchunk = (g->N + kNsRows - 1) / kNsRows;
+  if (m > 1) {
+    const dim3 grid((unsigned)nchunk, (unsigned)((m - 1 + kNsCols - 1) / kNsCols));
+    if (qdt == RW_F64)
+      k_null_stats<double><<<grid, 256, 0, s>>>((const double*)Q, g->N, m, g->degree, g->normalized, partial, nchunk);
+    else if (qdt == RW_F32)
+      k_null_stats<float><<<grid, 256, 0, s>>>((const float*)Q, g->N, m, g->degree, g->normalized, partial, nchunk);
+    else
+      k_null_stats<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)Q, g->N, m, g->degree, g->normalized, partial,
+                                                   nchunk);
+    RW_LAUNCH_CHECK();
+  }
+  if (m > 1) {
+    k_null_finish<<<m - 1, 64, 0, s>>>(partial, nchunk, m, g->sums, g->normalized, g->N, cn, bad);
+    RW_LAUNCH_CHECK();
+  }
+  return RW_OK;
+}
+
+__global__ __launch_bounds__(256) void k_solve_coeffs(double* Y, int m, int C, const double* cn, const double* sums,
+                                                      int normalized, int64_t N) {
+  solve_coeffs_block(Y, m, C, cn, ghat_scaled64(sums, normalized, N));
+}
+
+int solve_coeffs(double* Y, int m, int C, const double* cn, const Graph* g, hipStream_t s) {
+  k_solve_coeffs<<<1, 256, 0, s>>>(Y, m, C, cn, g->sums, g->normalized, g->N);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+// K = diag(lambda) - T (leading m x m of T, leading dimension ld);  Yrhs = leading m rows of R
+__global__ void k_build_reduced(const double* T, const double* R, const double* lambda, int ld, int m, int C,
+                                double* K, double* Y) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t < (int64_t)m * m) {
+    int i = (int)(t % m), j = (int)(t / m);
+    K[t] = (i == j ? lambda[i] : 0.0) - T[i + (int64_t)j * ld];
+  }
+  if (t < (int64_t)m * C) {
+    int i = (int)(t % m), c = (int)(t / m);
+    Y[t] = R[i + (int64_t)c * ld];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// reconstruction: U(lab, i) = s_i * sum_{j>=1} Q(i, j) Y(j, lab) + kappa_lab on non-seeds (s = d^{-1/2} or 1;
+// kappa = Y(0, lab), the null vector's term, added where s_i > 0 or the operator is L), one-hot on seeds.
+// Y (rows 1..m-1) and kappa live in LDS; each thread owns one node and CB labels.
 // ---------------------------------------------------------------------------------------------
 template <typename TQ, typename TU, int CB>
 __global__ __launch_bounds__(256) void k_reconstruct(const TQ* Q, int64_t N, int m, const double* Y, int C,
@@ -163,24 +295,29 @@ __global__ __launch_bounds__(256) void k_reconstruct(const TQ* Q, int64_t N, int
                                                       TU* U) {
   using CT = typename Elem<TQ>::C;
   extern __shared__ char smem[];
-  CT* sY = reinterpret_cast<CT*>(smem);
+  CT* sY = reinterpret_cast<CT*>(smem);          // (m - 1) x CB
+  CT* sK = sY + (m - 1) * CB;                     // CB
   for (int t = threadIdx.x; t < m * CB; t += blockDim.x) {
     int j = t / CB, c = t % CB;
     int lab = lab0 + c;
-    sY[t] = lab < C ? (CT)Y[j + (int64_t)lab * m] : CT(0);
+    const CT v = lab < C ? (CT)Y[j + (int64_t)lab * m] : CT(0);
+    if (j == 0) sK[c] = v;
+    else sY[(j - 1) * CB + c] = v;
   }
   __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= N) return;
+  const TQ* Q1 = Q + N;   // columns 1 .. m-1
+  const int mq = m - 1;
   CT acc[CB];
 #pragma unroll
   for (int c = 0; c < CB; ++c) acc[c] = CT(0);
   int j = 0;
-  for (; j + 4 <= m; j += 4) {
-    CT q0 = Elem<TQ>::ld(Q, (int64_t)j * N + i);
-    CT q1 = Elem<TQ>::ld(Q, (int64_t)(j + 1) * N + i);
-    CT q2 = Elem<TQ>::ld(Q, (int64_t)(j + 2) * N + i);
-    CT q3 = Elem<TQ>::ld(Q, (int64_t)(j + 3) * N + i);
+  for (; j + 4 <= mq; j += 4) {
+    CT q0 = Elem<TQ>::ld(Q1, (int64_t)j * N + i);
+    CT q1 = Elem<TQ>::ld(Q1, (int64_t)(j + 1) * N + i);
+    CT q2 = Elem<TQ>::ld(Q1, (int64_t)(j + 2) * N + i);
+    CT q3 = Elem<TQ>::ld(Q1, (int64_t)(j + 3) * N + i);
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
       acc[c] = fma(q0, sY[(j + 0) * CB + c], acc[c]);
@@ -189,18 +326,19 @@ __global__ __launch_bounds__(256) void k_reconstruct(const TQ* Q, int64_t N, int
       acc[c] = fma(q3, sY[(j + 3) * CB + c], acc[c]);
     }
   }
-  for (; j < m; ++j) {
-    CT q = Elem<TQ>::ld(Q, (int64_t)j * N + i);
+  for (; j < mq; ++j) {
+    CT q = Elem<TQ>::ld(Q1, (int64_t)j * N + i);
 #pragma unroll
     for (int c = 0; c < CB; ++c) acc[c] = fma(q, sY[j * CB + c], acc[c]);
   }
   const int ml = map[i];
   const CT sc = normalized ? (CT)dinv[i] : CT(1);
+  const bool live = !normalized || sc > CT(0);
 #pragma unroll
   for (int c = 0; c < CB; ++c) {
     int lab = lab0 + c;
     if (lab >= C) break;
-    CT v = ml ? (ml - 1 == lab ? CT(1) : CT(0)) : sc * acc[c];
+    CT v = ml ? (ml - 1 == lab ? CT(1) : CT(0)) : sc * acc[c] + (live ? sK[c] : CT(0));
     U[(int64_t)lab * N + i] = (TU)v;
   }
 }
@@ -724,25 +862,16 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
   RW_LAUNCH_CHECK();
   const GridDev G = grid_of(g);
   const int ma = m_avail;
-#define RW_GATHER(TQ, TG)                                                                                     \
-  k_seed_gather<TQ, TG><<<(unsigned)S, 256, 0, stream>>>(G, g->normalized, (const TQ*)Q, ma, w.seeds, w.labels, \
-                                                         w.map, (const TG*)g->coef, (const TG*)g->diag, g->degree, S, \
-                                                         C, w.Qs, w.GB, w.Hs, w.Us)
-  if (g->dtype == RW_F64) {
-    if (q_dtype == RW_F64) RW_GATHER(double, double);
-    else if (q_dtype == RW_F32) RW_GATHER(float, double);
-    else RW_GATHER(uint16_t, double);
-  } else {
-    if (q_dtype == RW_F64) RW_GATHER(double, float);
-    else if (q_dtype == RW_F32) RW_GATHER(float, float);
-    else RW_GATHER(uint16_t, float);
-  }
+#define RW_GATHER(TQ)                                                                                     \
+  k_seed_gather<TQ><<<(unsigned)S, 256, 0, stream>>>(G, g->normalized, (const TQ*)Q, ma, w.seeds, w.map, g->weight, \
+                                                     g->degree, g->sums, S, C, w.Qs, w.GB, w.Hs, w.Us, w.gs, w.Bg)
+  if (q_dtype == RW_F64) RW_GATHER(double);
+  else if (q_dtype == RW_F32) RW_GATHER(float);
+  else RW_GATHER(uint16_t);
 #undef RW_GATHER
   RW_LAUNCH_CHECK();
-  // T = Q_s^T (B Q_n),  R = Q_s^T (op_ss U_hat_s)
-  RW_TRY(gram(RW_F64, w.Qs, S, w.GB, S, S, ma, ma, w.T, w.partial, stream));
-  RW_TRY(gram(RW_F64, w.Qs, S, w.Hs, S, S, ma, C, w.R, w.partial, stream));
-  // choice of m
+  RW_HIP(hipMemsetAsync(w.nbad, 0, sizeof(int), stream));
+  // choice of m (on the stored columns)
   int m = ma;
   int probes = 0;
   double f_max = 0.0, f_worst = 0.0;
@@ -874,10 +1003,18 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
     for (auto& e : evaluated)
       if (e.first == m) f_worst = e.second;
   }
+  // the FP64 basis of the first m columns: c_j, n_j by one pass over Q, then the seed rows in place
+  RW_TRY(null_stats(g, Q, q_dtype, m, w.npart, w.cn, w.nbad, stream));
+  k_seed_correct<<<nblocks(S * m, 256), 256, 0, stream>>>(w.Qs, w.GB, w.gs, w.Bg, w.cn, S, m);
+  RW_LAUNCH_CHECK();
+  // T = Q'_s^T (B Q'_n),  R = Q'_s^T (op_ss U_hat_s)  (m x m and m x C, leading dimension m)
+  RW_TRY(gram(RW_F64, w.Qs, S, w.GB, S, S, m, m, w.T, w.partial, stream));
+  RW_TRY(gram(RW_F64, w.Qs, S, w.Hs, S, S, m, C, w.R, w.partial, stream));
   // reduced system and solve
-  k_build_reduced<<<nblocks((int64_t)m * std::max(m, C), 256), 256, 0, stream>>>(w.T, w.R, lambda, ma, m, C, w.K, w.Y);
+  k_build_reduced<<<nblocks((int64_t)m * std::max(m, C), 256), 256, 0, stream>>>(w.T, w.R, lambda, m, m, C, w.K, w.Y);
   RW_LAUNCH_CHECK();
   RW_TRY(lu_solve(w.K, m, w.Y, C, w.stat, stream));
+  RW_TRY(solve_coeffs(w.Y, m, C, w.cn, g, stream));
   // the reconstruction is queued before the pivot test is read (one wait for both); U is not valid when
   // the test fails
   RW_TRY(reconstruct(g, Q, q_dtype, m, w.Y, C, w.map, U, stream));
@@ -886,12 +1023,15 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
   double* hs = static_cast<double*>(stage);
   RW_HIP(hipMemcpyAsync(hs, w.stat, sizeof(double), hipMemcpyDeviceToHost, stream));
   RW_HIP(hipMemcpyAsync(hs + 1, unanchored, sizeof(int), hipMemcpyDeviceToHost, stream));
+  RW_HIP(hipMemcpyAsync(reinterpret_cast<int*>(hs + 1) + 1, w.nbad, sizeof(int), hipMemcpyDeviceToHost, stream));
   RW_HIP(hipStreamSynchronize(stream));
   const double stat = hs[0];
-  int bad = 0;
+  int bad = 0, nbad = 0;
   std::memcpy(&bad, hs + 1, sizeof(int));
+  std::memcpy(&nbad, reinterpret_cast<int*>(hs + 1) + 1, sizeof(int));
   RW_CHECK(!bad, RW_EUNANCHORED,
            "a connected component (edges with w >= 1e-30) holds no seed: the gamma = 0 system is singular");
+  RW_CHECK(!nbad, RW_EINVAL, "basis column %d lies in the span of the null vector (column 0)", nbad);
   RW_CHECK(stat > 0.0, RW_ESINGULAR, "reduced seed system is singular to working precision (m = %d)", m);
   if (info) {
     info->m_used = m;

@@ -1,6 +1,11 @@
 """GPU parity for the batching form: many images of uneven sizes, several interaction rounds, one
 enqueue per round (captured into a HIP graph and replayed), against the single-image solve on the same
-basis and against the oracle."""
+basis and against the oracle.
+
+Five of the six images are weakly coupled: a region joined to the rest by weights near exp(-90 * 0.36),
+so a second eigenvalue sits at 1e-10 .. 1e-16 (the 129 x 7 strip: -1.3e-16) and the reduced seed system
+has a condition number up to 1e15.  Every image is compared with the oracle, which evaluates the paper's
+bordered system exactly (rational arithmetic) where the FP64 evaluation would lose the gate itself."""
 import numpy as np
 import pytest
 import torch
@@ -19,7 +24,15 @@ SHAPES = [((37, 29, 1), 4, 12), ((64, 48, 1), 4, 30), ((20, 90, 1), 4, 50), ((51
           ((12, 10, 9), 6, 20), ((129, 7, 1), 4, 8)]
 
 
-def _images(gdt, qdt, rounds=4, seed=0):
+def _small_round(w, rid, r, seed=0):
+    """A round with few seeds per label (the exact oracle's cost grows quickly with S): C in {2, 3}, 3..5
+    seeds per label, at least one in each connected component of each label's regions."""
+    C = 2 + (r % 2)
+    node, lab = rwsynth.seeds(w, rid, seed=seed, C=C, per_label=3 + (r % 3), stream_offset=50 + r)
+    return C, node, lab
+
+
+def _images(gdt, qdt, rounds=4, seed=0, small=False):
     out = []
     for k, (dims, conn, m) in enumerate(SHAPES):
         w = rwsynth.Workload(f"b{k}", 500 + k, dims, conn, 90.0, m, 2, 10, 0.05, 4, "cycle", 0.0, "f64")
@@ -30,7 +43,7 @@ def _images(gdt, qdt, rounds=4, seed=0):
         Qc = Q if qdt == torch.float64 else rw.convert_block(Q, qdt)
         rnds = []
         for r in range(rounds):
-            rnds.append(rwsynth.cfg4_round(w, rid, r, seed))
+            rnds.append(_small_round(w, rid, r, seed) if small else rwsynth.cfg4_round(w, rid, r, seed))
         out.append(dict(w=w, J=J, graph=g, Q=Qc, lam=lam, rounds=rnds,
                         S_cap=max(len(r[1]) for r in rnds), C_cap=4))
     return out
@@ -41,17 +54,13 @@ def _single(im, C, node, lab):
     return U
 
 
-def _cond_tol(tol, min_pivot):
-    """Two LU solves of the same reduced system with different elimination orders differ by rounding
-    amplified by its conditioning: relative pivot size p = min |pivot| / max |k_ij| gives kappa >~ 1/p,
-    and the forward error is bounded by a modest multiple of u kappa (u = 1.1e-16)."""
-    return max(tol, 1e-11 / max(min_pivot, 1e-300))
-
-
 def _tol(gdt, qdt):
+    """The FP64 gate; for FP32 and BF16 bases the method's gates (1e-4, 1e-2): the two paths sum the
+    reconstruction in FP32 with coefficients up to ~50 on the weakly coupled images, so their rounding
+    differs by up to ~1e-5 there."""
     if gdt == torch.float64 and qdt == torch.float64:
         return 1e-10
-    return 1e-5 if qdt != torch.bfloat16 else 1e-2
+    return 1e-4 if qdt != torch.bfloat16 else 1e-2
 
 
 @pytest.mark.parametrize("gdt,qdt", [(torch.float64, torch.float64), (torch.float32, torch.float32),
@@ -73,32 +82,38 @@ def test_batch_rounds_match_single_image_solves(gdt, qdt):
             Us, inf = rw.solve_seeds(im["graph"], im["Q"], im["lam"], node, lab, C)
             assert Ub.shape == Us.shape
             err = (Ub.double() - Us.double()).abs().max().item()
-            # FP64: reductions in another order only; FP32/BF16: the single path's BF16 reconstruction runs on
-            # the matrix cores (Y rounded to two BF16 parts), the batched one on FP32 vector units.  The two
-            # paths factor the reduced system with different LU kernels, so an ill-conditioned system widens
-            # the bound.
-            assert err <= _cond_tol(tol, inf["min_pivot"]), (r, i, err, inf["min_pivot"])
+            # FP64: reductions and the LU's elimination in another order only; FP32/BF16: the single path's
+            # BF16 reconstruction runs on the matrix cores (Y rounded to two BF16 parts), the batched one on
+            # FP32 vector units
+            assert err <= tol, (r, i, err, inf["min_pivot"])
             np.testing.assert_array_equal(Ub.double().cpu().numpy()[lab, node], 1.0)
 
 
-def test_batch_fp64_against_oracle():
+@pytest.mark.parametrize("gdt,qdt,tol", [(torch.float64, torch.float64, 1e-10), (torch.float32, torch.float32, 1e-4),
+                                         (torch.float32, torch.bfloat16, 1e-2)], ids=["f64", "f32", "bf16"])
+def test_batch_against_oracle(gdt, qdt, tol):
+    """Every image of two rounds against the oracle on the same (upcast) basis: 1e-10 relative for FP64,
+    1e-4 and 1e-2 max-abs for FP32 and BF16 bases."""
     need_gpu()
-    banner("batch oracle")
-    ims = _images(torch.float64, torch.float64, rounds=2)
+    banner(f"batch oracle {gdt} {qdt}")
+    ims = _images(gdt, qdt, rounds=2, small=True)
     bs = rw.BatchSolver(ims, use_graph=False)
     for r in range(2):
         bs.set_seeds([im["rounds"][r] for im in ims])
         bs.run()
+        assert bs.status() > 0
         for i, (im, Ub) in enumerate(zip(ims, bs.outputs())):
             C, node, lab = im["rounds"][r]
             lam = im["lam"].cpu().numpy()
-            if np.min(np.abs(lam[1:])) < 1e-6:
-                continue        # the oracle's bordered system needs exact arithmetic there: covered by the solve tests
             w = im["w"]
             og = OGraph(im["J"], w.dims, w.conn, w.beta)
-            Uo = fast_rw(og, im["Q"].cpu().numpy().T, lam, node, lab, C)
-            err = np.abs(Ub.cpu().numpy().T - Uo).max()
-            assert err <= 1e-10 * max(1.0, np.abs(Uo).max()), (r, i, err)
+            exact = bool(np.min(np.abs(lam[1:])) < 1e-6)
+            Uo = fast_rw(og, im["Q"].double().cpu().numpy().T, lam, node, lab, C, exact=exact)
+            err = np.abs(Ub.double().cpu().numpy().T - Uo).max()
+            bound = tol * max(1.0, np.abs(Uo).max()) if gdt == torch.float64 else tol
+            print(f"  round {r} image {i} {w.dims} m={w.m} S={node.size} lam1={lam[1]:.1e} exact={exact} "
+                  f"err={err:.2e}", flush=True)
+            assert err <= bound, (r, i, err)
 
 
 def test_batch_graph_replays_match_eager():

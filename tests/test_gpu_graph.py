@@ -37,17 +37,21 @@ def _weight_rtol(og):
 def _check_graph(gg, og, dt):
     v = gg.view()
     np.testing.assert_array_equal(v["mask"].cpu().numpy(), og.mask_bits())
+    # weights, scales and degrees are FP64 on every graph; only the operator's coefficients take its type
     w_ref = og.weights_by_dir()
-    w = v["weight"].cpu().numpy().astype(np.float64)
-    if dt == torch.float64:
-        assert np.all(np.abs(w - w_ref) <= _weight_rtol(og) * w_ref)
-    else:
-        # FP32 weight = the FP64 weight rounded once (1 ulp allowed for the exp difference)
-        np.testing.assert_allclose(w, w_ref.astype(np.float32).astype(np.float64), rtol=1.2e-7, atol=0)
+    w = v["weight"].cpu().numpy()
+    assert v["weight"].dtype == torch.float64 and v["scale"].dtype == torch.float64
+    assert np.all(np.abs(w - w_ref) <= _weight_rtol(og) * w_ref)
     d_ref = og.degree()
-    tol = 1e-14 if dt == torch.float64 else 1e-6
-    np.testing.assert_allclose(v["degree"].cpu().numpy(), d_ref, rtol=tol)
-    np.testing.assert_allclose(v["ghat"].cpu().numpy().astype(np.float64), og.ghat(), rtol=10 * tol, atol=1e-300)
+    np.testing.assert_allclose(v["degree"].cpu().numpy(), d_ref, rtol=1e-14)
+    # FP32 graph: coefficients and the null vector are the FP64 values rounded once (1 ulp, plus the FP64
+    # sides' own rounding differences); FP32 subnormals have an absolute spacing of 2^-149
+    tol, atol = (1e-13, 1e-300) if dt == torch.float64 else (1.2e-7, 2.0 ** -149)
+    np.testing.assert_allclose(v["ghat"].cpu().numpy().astype(np.float64), og.ghat(), rtol=tol, atol=atol)
+    dinv = og.dinv_sqrt()
+    c_ref = np.zeros_like(w_ref)
+    c_ref[og.dir, og.tail] = og.w * dinv[og.tail] * dinv[og.head]
+    np.testing.assert_allclose(v["coef"].cpu().numpy().astype(np.float64), c_ref, rtol=tol, atol=atol)
 
 
 @pytest.mark.parametrize("name,w,dt", CASES, ids=[c[0] for c in CASES])

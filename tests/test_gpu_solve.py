@@ -39,7 +39,7 @@ def _oracle_case(w):
 
 def _needs_exact(lam):
     """The oracle's FP64 bordered system divides by the non-null eigenvalues; below 1e-6 its own
-    rounding exceeds the FP64 gate, so the oracle solves that system exactly instead."""
+    rounding exceeds the FP64 gate, so the oracle evaluates that system in extended precision instead."""
     return np.min(np.abs(lam[1:])) < 1e-6
 
 
@@ -70,6 +70,37 @@ def test_solve_matches_oracle(name, w, gdt, qdt, tol, kind):
         U, _ = rw.solve_seeds(gg, to_dev(Qf.T, qdt), to_dev(lamf, torch.float64), node, lab, w.C)
         Ue = exact_rw(og, node, lab, w.C, method="direct")
         assert np.abs(U.cpu().numpy().T - Ue).max() < 1e-9
+
+
+# weakly coupled phantoms: a region joined to the rest by weights near exp(-90 * 0.36); the second eigenvalue
+# is 7e-14 (64 x 48) and -1.3e-16 (the 129 x 7 strip), and the reduced system's condition number ~1e15
+WEAK = [("strip129x7", rwsynth.Workload("b5", 505, (129, 7, 1), 4, 90.0, 8, 3, 5, 0.05, 4, "cycle", 0.0, "f64")),
+        ("img64x48", rwsynth.Workload("b1", 501, (64, 48, 1), 4, 90.0, 30, 3, 5, 0.05, 4, "cycle", 0.0, "f64"))]
+
+
+@pytest.mark.parametrize("name,w", WEAK, ids=[c[0] for c in WEAK])
+@pytest.mark.parametrize("gdt,qdt,tol", [(torch.float64, torch.float64, 1e-10), (torch.float32, torch.float32, 1e-4),
+                                         (torch.float32, torch.bfloat16, 1e-2)], ids=["f64", "f32", "bf16"])
+def test_solve_weakly_coupled_matches_exact_oracle(name, w, gdt, qdt, tol):
+    """The FP32 graph's coefficients and the stored low-precision null vector would decide the solution of
+    this system; the solve forms its seed rows from FP64 weights and takes the basis in FP64 around the exact
+    null vector, and matches the oracle's exact evaluation of the bordered system on the same basis."""
+    need_gpu()
+    banner(f"solve weakly coupled {name} {gdt} {qdt}")
+    J, rid = rwsynth.phantom(w, 0)
+    node, lab = rwsynth.seeds(w, rid, 0, per_label=5, stream_offset=3)
+    og = OGraph(J, w.dims, w.conn, w.beta)
+    lam, Q = dense_eigpairs(og, w.m)
+    assert np.min(np.abs(lam[1:])) < 1e-12
+    gg = rw.Graph(to_dev(J, torch.float64), w.dims, w.conn, w.beta, dtype=gdt)
+    Qd = to_dev(Q.T, qdt)
+    Qseen = Qd.to(torch.float64).cpu().numpy().T
+    U, info = rw.solve_seeds(gg, Qd, to_dev(lam, torch.float64), node, lab, w.C)
+    Uo = fast_rw(og, Qseen, lam, node, lab, w.C, exact=True)
+    err = np.abs(U.to(torch.float64).cpu().numpy().T - Uo).max()
+    print(f"  S={node.size} min_pivot={info['min_pivot']:.1e} err={err:.2e}", flush=True)
+    bound = tol * max(1.0, np.abs(Uo).max()) if gdt == torch.float64 else tol
+    assert err <= bound, err
 
 
 def test_solve_rows_sum_to_one_and_seed_validation():
@@ -117,8 +148,5 @@ def test_choice_of_m_matches_oracle(seed, per, m):
         else:
             np.testing.assert_allclose(info["f_worst"], f.max(), rtol=1e-8, atol=1e-12)
         mu = info["m_used"]
-        exact = _needs_exact(lam[:mu])
-        if exact and node.size > 40:
-            continue        # the rational oracle is too slow at this S; the solve itself is pinned above
-        Uo = fast_rw(og, Q, lam, node, lab, w.C, m=mu, exact=exact)
+        Uo = fast_rw(og, Q, lam, node, lab, w.C, m=mu, exact=_needs_exact(lam[:mu]))
         assert np.abs(U.cpu().numpy().T - Uo).max() < 1e-10

@@ -127,3 +127,21 @@ def test_exact_mode_agrees_and_survives_near_null_eigenvalues():
     assert lam[1] < 1e-9                              # weakly coupled region
     U = fast_rw(g, Q, lam, node, lab, 3, exact=True)
     np.testing.assert_allclose(U.sum(axis=1), 1.0, atol=1e-13)
+
+
+def test_decimal_exact_mode_equals_rational_mode():
+    """The exact mode's 100-digit decimal evaluation of the bordered system gives the same FP64 results as
+    the rational evaluation, on weakly coupled phantoms (second eigenvalue 7e-14 and -1.3e-16, condition
+    near 1e15) with FP64 and FP32-rounded bases."""
+    cases = [(rwsynth.Workload("b5", 505, (129, 7, 1), 4, 90.0, 8, 3, 5, 0.05, 4, "cycle", 0.0, "f64"), 3),
+             (rwsynth.Workload("b1", 501, (64, 48, 1), 4, 90.0, 30, 2, 5, 0.05, 4, "cycle", 0.0, "f64"), 2)]
+    for w, per in cases:
+        J, rid = rwsynth.phantom(w, 0)
+        node, lab = rwsynth.seeds(w, rid, 0, per_label=per, stream_offset=3)
+        g = Graph(J, w.dims, w.conn, w.beta)
+        lam, Q = dense_eigpairs(g, w.m)
+        assert np.min(np.abs(lam[1:])) < 1e-12
+        for Qx in (Q, Q.astype(np.float32).astype(np.float64)):
+            Ur = fast_rw(g, Qx, lam, node, lab, w.C, exact="rational")
+            Ud = fast_rw(g, Qx, lam, node, lab, w.C, exact=True)
+            np.testing.assert_allclose(Ud, Ur, rtol=0, atol=1e-15)
