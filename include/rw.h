@@ -232,6 +232,21 @@ int rw_solve_seeds(rw_graph g, const void* Q, int q_dtype, const double* lambda,
                    const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, double eps,
                    void* U, void* work, size_t work_bytes, hipStream_t stream, rw_solve_info* info);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): rw_solve_seeds with a fixed m (no choice of m; same kernels, same results as
+ * rw_solve_seeds with eps <= 0 and m_avail = m) that calls no hipMalloc, hipFree or other allocating
+ * routine.  Its workspace is a device array of the library (64 MiB, held by each GPU the library runs on
+ * until the process ends; the call takes its address on the current device) and its host staging is
+ * static.  Limits: at most 16384 seeds, and the workspace of rw_solve_workspace_bytes without the
+ * choice-of-m arrays (N bytes x 2 plus about 16 S m + 40 m^2 doubles) within 64 MiB; beyond them the call
+ * fails with RW_EWORKSPACE.  Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents (each call initializes what it reads); calls are serialized by a process-wide lock and each
+ * waits for its stream before it returns, also when it fails.  Arguments, outputs and errors as for
+ * rw_solve_seeds.  The call synchronizes `stream`. */
+int rw_solve_seeds_noalloc(rw_graph g, const void* Q, int q_dtype, const double* lambda, int m,
+                           const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, void* U,
+                           hipStream_t stream, rw_solve_info* info);
+
 /* ======================================================================================
  * Exact random walker by conjugate gradients (Sec. II-A eq. (5), gamma = 0)
  * ====================================================================================== */

@@ -103,6 +103,9 @@ _SIGS = {
     "rw_solve_seeds": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p,
                                   ct.c_void_p, ct.c_int64, ct.c_int, ct.c_double, ct.c_void_p, ct.c_void_p,
                                   ct.c_size_t, ct.c_void_p, ct.POINTER(rw_solve_info)]),
+    "rw_solve_seeds_noalloc": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p,
+                                          ct.c_void_p, ct.c_int64, ct.c_int, ct.c_void_p, ct.c_void_p,
+                                          ct.POINTER(rw_solve_info)]),
     "rw_dense_syev_workspace_bytes": (ct.c_int, [ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]),
     "rw_dense_syev": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_size_t,
                                  ct.c_void_p]),
@@ -388,6 +391,22 @@ def solve_seeds(g: Graph, Q: torch.Tensor, lam: torch.Tensor, seed_node, seed_la
                                 _ptr(U), _ptr(work), work.numel(), _stream(g.device), ct.byref(info)))
     return U, {"m_used": info.m_used, "f_max": info.f_max, "f_worst": info.f_worst, "min_pivot": info.min_pivot,
                "eig_probes": info.eig_probes}
+
+
+def solve_seeds_noalloc(g: Graph, Q: torch.Tensor, lam: torch.Tensor, seed_node, seed_label, C: int,
+                        m: Optional[int] = None, U: Optional[torch.Tensor] = None):
+    """solve_seeds with a fixed m through rw_solve_seeds_noalloc, whose workspace is the library's own device
+    array (the call allocates nothing; U is allocated here only when not given).  Returns (U, info dict)."""
+    m = Q.shape[0] if m is None else int(m)
+    nodes = np.ascontiguousarray(np.asarray(seed_node, dtype=np.int64))
+    labels = np.ascontiguousarray(np.asarray(seed_label, dtype=np.int32))
+    if U is None:
+        U = torch.empty((C, g.N), dtype=g.dtype, device=g.device)
+    info = rw_solve_info()
+    _check(lib().rw_solve_seeds_noalloc(g.handle, _ptr(Q), _TORCH_DT[Q.dtype], _ptr(lam), m,
+                                        ct.c_void_p(nodes.ctypes.data), ct.c_void_p(labels.ctypes.data), nodes.size,
+                                        C, _ptr(U), _stream(g.device), ct.byref(info)))
+    return U, {"m_used": info.m_used, "min_pivot": info.min_pivot}
 
 
 def cg_solve(g: Graph, seed_node, seed_label, C: int, tol: float = 1e-12, max_iter: int = 100000,

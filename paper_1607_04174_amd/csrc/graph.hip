@@ -10,15 +10,13 @@
 
 namespace rw {
 
-static thread_local std::string g_last_error;
+static thread_local char g_last_error[1024];   // fixed storage: reporting an error allocates nothing
 
 void set_error(const char* fmt, ...) {
-  char buf[1024];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
   va_end(ap);
-  g_last_error = buf;
 }
 
 static thread_local void* g_stage = nullptr;
@@ -460,7 +458,7 @@ using namespace rw;
 
 extern "C" {
 
-const char* rw_last_error(void) { return g_last_error.c_str(); }
+const char* rw_last_error(void) { return g_last_error; }
 int rw_version(void) { return 1; }
 
 int rw_graph_bytes(const rw_graph_desc* desc, size_t* bytes) {

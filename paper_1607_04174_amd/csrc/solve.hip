@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "rw_internal.h"
@@ -63,7 +64,8 @@ struct SolveWork {
   int* scrCls;        // (ma + 1): 0 fails, 1 passes, 2 undecided; [0] = factorized leading size
 };
 
-static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base, SolveWork* w) {
+// fit = false leaves out the choice-of-m arrays (solves with a fixed m)
+static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base, SolveWork* w, bool fit = true) {
   Carver c(base);
   int64_t ms = std::min<int64_t>(S, ma);
   SolveWork t;
@@ -84,13 +86,13 @@ static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base,
   t.R = c.take<double>((size_t)ma * C);
   t.Gq = c.take<double>((size_t)ma * ma);
   t.Gb = c.take<double>((size_t)ma * C);
-  const int nc = fit_cands(ma);
+  const int nc = fit ? fit_cands(ma) : 0;
   t.fvals = c.take<double>((size_t)nc * C);
   t.fitA = c.take<double>((size_t)nc * ms * ms);
   t.fitR = c.take<double>((size_t)nc * ms * C);
   t.fitW = c.take<double>((size_t)nc * ms);
-  t.fitWorkCount = syev_work_count((int)ms, nc, false, C);
-  if (tridiag_fits((int)ms))
+  t.fitWorkCount = fit ? syev_work_count((int)ms, nc, false, C) : 0;
+  if (fit && tridiag_fits((int)ms))
     t.fitWorkCount = std::max(t.fitWorkCount, tridiag_rhs_work_count((int)ms, std::min(nc, kTriBatchMax), C));
   t.fitWork = c.take<double>(t.fitWorkCount);
   t.K = c.take<double>((size_t)ma * ma);
@@ -793,12 +795,13 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int6
 
 // ---------------------------------------------------------------------------------------------
 
-static int host_seeds(const Graph* g, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C,
-                      std::vector<int64_t>* nodes, std::vector<int32_t>* labels) {
+// Validates, sorts and de-duplicates the seeds into caller buffers (v: S pairs of scratch; nodes, labels:
+// S entries); *S_out receives the number of distinct seeds.  Allocates nothing.
+static int host_seeds_into(const Graph* g, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C,
+                           std::pair<int64_t, int32_t>* v, int64_t* nodes, int32_t* labels, int64_t* S_out) {
   RW_CHECK(S >= 1, RW_EINVAL, "at least one seed is required");
   RW_CHECK(seed_node != nullptr && seed_label != nullptr, RW_EINVAL, "null seed arrays");
   RW_CHECK(C >= 1 && C <= 255, RW_EINVAL, "C must be in [1, 255] (got %d)", C);
-  std::vector<std::pair<int64_t, int32_t>> v((size_t)S);
   for (int64_t k = 0; k < S; ++k) {
     RW_CHECK(seed_node[k] >= 0 && seed_node[k] < g->N, RW_EINVAL, "seed %lld: node %lld out of range",
              (long long)k, (long long)seed_node[k]);
@@ -806,53 +809,31 @@ static int host_seeds(const Graph* g, const int64_t* seed_node, const int32_t* s
              (long long)k, seed_label[k]);
     v[k] = {seed_node[k], seed_label[k]};
   }
-  std::sort(v.begin(), v.end());
-  nodes->clear();
-  labels->clear();
-  for (size_t k = 0; k < v.size(); ++k) {
+  std::sort(v, v + S);
+  int64_t n = 0;
+  for (int64_t k = 0; k < S; ++k) {
     if (k > 0 && v[k].first == v[k - 1].first) {
       RW_CHECK(v[k].second == v[k - 1].second, RW_EINVAL, "node %lld seeded with labels %d and %d",
                (long long)v[k].first, v[k - 1].second, v[k].second);
       continue;
     }
-    nodes->push_back(v[k].first);
-    labels->push_back(v[k].second);
+    nodes[n] = v[k].first;
+    labels[n] = v[k].second;
+    ++n;
   }
+  *S_out = n;
   return RW_OK;
 }
 
-}  // namespace rw
-
-using namespace rw;
-
-extern "C" {
-
-int rw_solve_workspace_bytes(rw_graph h, int m_avail, int64_t S, int C, size_t* bytes) {
-  RW_CHECK(h != nullptr && bytes != nullptr, RW_EINVAL, "null argument");
-  RW_CHECK(m_avail >= 2 && S >= 1 && C >= 1, RW_EINVAL, "bad sizes");
-  *bytes = solve_layout(&h->g, m_avail, S, C, nullptr, nullptr);
-  return RW_OK;
-}
-
-int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda, int m_avail,
-                   const int64_t* seed_node, const int32_t* seed_label, int64_t S_in, int C, double eps, void* U,
-                   void* work, size_t work_bytes, hipStream_t stream, rw_solve_info* info) {
-  RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
+// The solve on sorted, distinct seeds (S of them; the workspace is laid out for S_cap >= S).  final_stage:
+// host memory for the three status words read at the end (pinned staging when null).
+static int solve_impl(rw_graph h, const void* Q, int q_dtype, const double* lambda, int m_avail, const int64_t* nodes,
+                      const int32_t* labels, int64_t S, int64_t S_cap, int C, double eps, void* U, const SolveWork& w,
+                      hipStream_t stream, rw_solve_info* info, void* final_stage) {
   const Graph* g = &h->g;
-  RW_CHECK(Q != nullptr && lambda != nullptr && U != nullptr && work != nullptr, RW_EINVAL, "null pointer argument");
-  RW_CHECK(q_dtype == RW_F64 || q_dtype == RW_F32 || q_dtype == RW_BF16, RW_EINVAL, "bad Q dtype");
-  RW_CHECK(m_avail >= 2 && m_avail <= g->N, RW_EINVAL, "m_avail = %d out of range", m_avail);
-  std::vector<int64_t> nodes;
-  std::vector<int32_t> labels;
-  RW_TRY(host_seeds(g, seed_node, seed_label, S_in, C, &nodes, &labels));
-  const int64_t S = (int64_t)nodes.size();
-  RW_CHECK(S < g->N, RW_EINVAL, "every node is a seed");
-  SolveWork w;
-  size_t need = solve_layout(g, m_avail, S_in, C, work, &w);  // sized for S_in >= S
-  RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "solve workspace too small: %zu < %zu", work_bytes, need);
   // seeds to the device; map of seeded nodes
-  RW_HIP(hipMemcpyAsync(w.seeds, nodes.data(), S * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-  RW_HIP(hipMemcpyAsync(w.labels, labels.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  RW_HIP(hipMemcpyAsync(w.seeds, nodes, S * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+  RW_HIP(hipMemcpyAsync(w.labels, labels, S * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   // the anchoring check is queued here and read with the pivot test at the end
   const int* unanchored = nullptr;
   RW_TRY(anchor_launch(&h->g, w.seeds, S, w.anc, stream, &unanchored));
@@ -1018,8 +999,8 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
   // the reconstruction is queued before the pivot test is read (one wait for both); U is not valid when
   // the test fails
   RW_TRY(reconstruct(g, Q, q_dtype, m, w.Y, C, w.map, U, stream));
-  void* stage = nullptr;
-  RW_TRY(host_stage(2 * sizeof(double), &stage));
+  void* stage = final_stage;
+  if (stage == nullptr) RW_TRY(host_stage(2 * sizeof(double), &stage));
   double* hs = static_cast<double*>(stage);
   RW_HIP(hipMemcpyAsync(hs, w.stat, sizeof(double), hipMemcpyDeviceToHost, stream));
   RW_HIP(hipMemcpyAsync(hs + 1, unanchored, sizeof(int), hipMemcpyDeviceToHost, stream));
@@ -1041,6 +1022,106 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
     info->min_pivot = stat;
   }
   return RW_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Allocation-free variant (fixed m): the workspace lives in `scratch`, a file-scope device array that each
+// GPU holds from module load to process end.  Host code never passes `scratch` itself (its name is a host
+// stand-in there): the first call on a device, with that device current, takes its device address with
+// hipGetSymbolAddress and keeps it per device.  The host side (seed sorting, status words) uses static
+// arrays.  A process-wide lock serializes calls, and each call waits for its stream before it returns
+// (also after a failure), so no two calls use the array at once.
+// ---------------------------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int64_t kNoAllocMaxSeeds = 16384;
+constexpr int kNoAllocMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_na_mu;
+static void* g_na_ptr[kNoAllocMaxDevices] = {};
+static std::pair<int64_t, int32_t> g_na_pairs[kNoAllocMaxSeeds];
+static int64_t g_na_nodes[kNoAllocMaxSeeds];
+static int32_t g_na_labels[kNoAllocMaxSeeds];
+static double g_na_stage[2];
+
+static int noalloc_scratch(void** ptr) {
+  int dev = -1;
+  RW_HIP(hipGetDevice(&dev));
+  RW_CHECK(dev >= 0 && dev < kNoAllocMaxDevices, RW_EINVAL, "device %d beyond the %d the library tracks", dev,
+           kNoAllocMaxDevices);
+  if (g_na_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    RW_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    RW_CHECK(p != nullptr, RW_EHIP, "no device address for the solve's scratch array");
+    g_na_ptr[dev] = p;
+  }
+  *ptr = g_na_ptr[dev];
+  return RW_OK;
+}
+
+}  // namespace rw
+
+using namespace rw;
+
+extern "C" {
+
+int rw_solve_seeds_noalloc(rw_graph h, const void* Q, int q_dtype, const double* lambda, int m,
+                           const int64_t* seed_node, const int32_t* seed_label, int64_t S_in, int C, void* U,
+                           hipStream_t stream, rw_solve_info* info) {
+  RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
+  const Graph* g = &h->g;
+  RW_CHECK(Q != nullptr && lambda != nullptr && U != nullptr, RW_EINVAL, "null pointer argument");
+  RW_CHECK(q_dtype == RW_F64 || q_dtype == RW_F32 || q_dtype == RW_BF16, RW_EINVAL, "bad Q dtype");
+  RW_CHECK(m >= 2 && m <= g->N, RW_EINVAL, "m = %d out of range", m);
+  RW_CHECK(S_in >= 1, RW_EINVAL, "at least one seed is required");
+  RW_CHECK(S_in <= kNoAllocMaxSeeds, RW_EWORKSPACE, "%lld seeds exceed the %lld of the allocation-free solve",
+           (long long)S_in, (long long)kNoAllocMaxSeeds);
+  const size_t need = solve_layout(g, m, S_in, C, nullptr, nullptr, false);
+  RW_CHECK(need <= kNoAllocScratchBytes, RW_EWORKSPACE,
+           "the solve needs %zu bytes of workspace, above the %zu of the allocation-free entry point", need,
+           kNoAllocScratchBytes);
+  std::lock_guard<std::mutex> lock(g_na_mu);
+  void* base = nullptr;
+  RW_TRY(noalloc_scratch(&base));
+  int64_t S = 0;
+  RW_TRY(host_seeds_into(g, seed_node, seed_label, S_in, C, g_na_pairs, g_na_nodes, g_na_labels, &S));
+  RW_CHECK(S < g->N, RW_EINVAL, "every node is a seed");
+  SolveWork w;
+  solve_layout(g, m, S_in, C, base, &w, false);
+  const int st = solve_impl(h, Q, q_dtype, lambda, m, g_na_nodes, g_na_labels, S, S_in, C, 0.0, U, w, stream, info,
+                            g_na_stage);
+  if (st != RW_OK) (void)hipStreamSynchronize(stream);   // nothing of a failed call still uses the array
+  return st;
+}
+
+int rw_solve_workspace_bytes(rw_graph h, int m_avail, int64_t S, int C, size_t* bytes) {
+  RW_CHECK(h != nullptr && bytes != nullptr, RW_EINVAL, "null argument");
+  RW_CHECK(m_avail >= 2 && S >= 1 && C >= 1, RW_EINVAL, "bad sizes");
+  *bytes = solve_layout(&h->g, m_avail, S, C, nullptr, nullptr);
+  return RW_OK;
+}
+
+int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda, int m_avail,
+                   const int64_t* seed_node, const int32_t* seed_label, int64_t S_in, int C, double eps, void* U,
+                   void* work, size_t work_bytes, hipStream_t stream, rw_solve_info* info) {
+  RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
+  const Graph* g = &h->g;
+  RW_CHECK(Q != nullptr && lambda != nullptr && U != nullptr && work != nullptr, RW_EINVAL, "null pointer argument");
+  RW_CHECK(q_dtype == RW_F64 || q_dtype == RW_F32 || q_dtype == RW_BF16, RW_EINVAL, "bad Q dtype");
+  RW_CHECK(m_avail >= 2 && m_avail <= g->N, RW_EINVAL, "m_avail = %d out of range", m_avail);
+  RW_CHECK(S_in >= 1, RW_EINVAL, "at least one seed is required");
+  std::vector<std::pair<int64_t, int32_t>> v((size_t)S_in);
+  std::vector<int64_t> nodes((size_t)S_in);
+  std::vector<int32_t> labels((size_t)S_in);
+  int64_t S = 0;
+  RW_TRY(host_seeds_into(g, seed_node, seed_label, S_in, C, v.data(), nodes.data(), labels.data(), &S));
+  RW_CHECK(S < g->N, RW_EINVAL, "every node is a seed");
+  SolveWork w;
+  size_t need = solve_layout(g, m_avail, S_in, C, work, &w);  // sized for S_in >= S
+  RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "solve workspace too small: %zu < %zu", work_bytes, need);
+  return solve_impl(h, Q, q_dtype, lambda, m_avail, nodes.data(), labels.data(), S, S_in, C, eps, U, w, stream, info,
+                    nullptr);
 }
 
 }  // extern "C"
