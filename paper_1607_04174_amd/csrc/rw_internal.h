@@ -431,9 +431,11 @@ int chol_inverse(double* G, double* W, int n, int* info, hipStream_t s);
 int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int n, int count, double* work,
                  hipStream_t s, double min_rel_tol = 0.0);
 size_t syev_work_count(int n, int count, bool vectors, int nrhs);
-// Symmetric eigendecomposition of one matrix (3 <= n <= 199) through its tridiagonal form; returns
+// Symmetric eigendecomposition of one matrix (3 <= n <= 256) through its tridiagonal form; returns
 // RW_ENOCONV without an error message when eigenvalues are too close for inverse iteration.
+// tridiag_batch_fits: the orders the batched solver takes (3 <= n <= 199, the reduction wholly in LDS).
 bool tridiag_fits(int n);
+bool tridiag_batch_fits(int n);
 size_t tridiag_work_count(int n);
 // With flag_dev, nothing waits: the call returns RW_OK and *flag_dev is the device double that is nonzero
 // where the result is RW_ENOCONV (then V is not valid).

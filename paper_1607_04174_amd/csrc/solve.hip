@@ -92,7 +92,7 @@ static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base,
   t.fitR = c.take<double>((size_t)nc * ms * C);
   t.fitW = c.take<double>((size_t)nc * ms);
   t.fitWorkCount = fit ? syev_work_count((int)ms, nc, false, C) : 0;
-  if (fit && tridiag_fits((int)ms))
+  if (fit && tridiag_batch_fits((int)ms))
     t.fitWorkCount = std::max(t.fitWorkCount, tridiag_rhs_work_count((int)ms, std::min(nc, kTriBatchMax), C));
   t.fitWork = c.take<double>(t.fitWorkCount);
   t.K = c.take<double>((size_t)ma * ma);
@@ -931,12 +931,12 @@ static int solve_impl(rw_graph h, const void* Q, int q_dtype, const double* lamb
       // order), the Jacobi solver when eigenvalues cluster or the batch does not fit
       int est = RW_ENOCONV;
       const double* tri_flag = nullptr;   // the tridiagonal path's cluster flag, read with the fit values
-      if (ncand <= kTriBatchMax && tridiag_fits(msp)) {
+      if (ncand <= kTriBatchMax && tridiag_batch_fits(msp)) {
         int sizes[kTriBatchMax];
         bool ok = true;
         for (int q = 0; q < ncand; ++q) {
           sizes[q] = (int)std::min<int64_t>(S, cand[q]);
-          ok = ok && tridiag_fits(sizes[q]);
+          ok = ok && tridiag_batch_fits(sizes[q]);
         }
         if (ok) {
           RW_TRY(syev_tridiag_rhs(w.fitA, msp, sizes, ncand, w.fitR, C, w.fitW, w.fitWork, w.fitWorkCount, stream,

@@ -1,9 +1,11 @@
-// Symmetric eigendecomposition through a tridiagonal form, for one matrix of order n <= 199:
+// Symmetric eigendecomposition through a tridiagonal form, for one matrix of order n <= 256 (batches of
+// matrices up to order 199):
 //   1. Householder reduction A = U T U^T (Golub & Van Loan Sec. 8.3.1) in one workgroup with the
 //      packed lower triangle in LDS: per column, one wave forms the reflector (the next column's while
 //      the other waves finish the rank-2 update), 4 to 16 lanes per row form p = tau A22 v, every wave
 //      forms K = tau/2 p^T v, and all threads apply the rank-2 update A22 -= v w^T + w v^T with
-//      w = p - K v;
+//      w = p - K v.  Above order 199 the packed triangle exceeds the LDS: the first n - 199 columns are
+//      reduced on a full copy in global memory (L2-resident) and the rest in LDS;
 //   2. eigenvalues of T by multisection on Sturm counts (Sec. 8.4.1), kBisThreads points per pass, one
 //      workgroup per eigenvalue (the interval shrinks kBisThreads + 1-fold per pass);
 //   3. eigenvectors of T by inverse iteration with the LDL^T factorization of T - lambda I (one lane
@@ -12,6 +14,7 @@
 // Inverse iteration gives orthogonal vectors only when eigenvalues are separated: the driver reports
 // RW_ENOCONV when two eigenvalues are closer than 1e-6 |T|, and the caller then uses the Jacobi solver.
 // All arithmetic is FP64.
+#include <algorithm>
 #include <cmath>
 
 #include "rw_internal.h"
@@ -21,11 +24,14 @@ namespace rw {
 __device__ __forceinline__ int tr_lo(int i, int j, int n) { return j * n - ((j * (j - 1)) >> 1) + (i - j); }  // i >= j
 
 static size_t tridiag_lds_bytes(int n) { return ((size_t)n * (n + 1) / 2 + 2 * (size_t)n) * sizeof(double); }
+constexpr int kTriLdsMax = 199;   // the largest order whose packed triangle (and two vectors) fit in LDS
 
-static size_t invit_lds_bytes(int n);
-bool tridiag_fits(int n) {   // n <= 199
-  return n >= 3 && n <= 256 && tridiag_lds_bytes(n) <= kLdsLimit && invit_lds_bytes(n) <= kLdsLimit;
+static size_t invit_lds_bytes(int n, int tpb);
+bool tridiag_batch_fits(int n) {   // n <= 199: the whole reduction in LDS
+  return n >= 3 && n <= kTriLdsMax && tridiag_lds_bytes(n) <= kLdsLimit && invit_lds_bytes(n, 32) <= kLdsLimit;
 }
+bool tridiag_fits(int n) { return n >= 3 && n <= 256; }
+static_assert((size_t)kTriLdsMax * (kTriLdsMax + 1) / 2 * 8 + 2 * kTriLdsMax * 8 <= kLdsLimit, "LDS");
 
 // work (doubles): reflectors n x n (reflector k in column k, entries 0..n-k-2, first entry 1), tau n, d n,
 // e n, lambda n, Z n x n (Z(j, i) = entry j of eigenvector i at j * n + i), LDL^T scratch 2 n x n, flag
@@ -56,8 +62,13 @@ __device__ __forceinline__ double tr_wave_sum(double v) { return wave_sum64(v); 
 // 1. Householder tridiagonalization (lower): reflector k maps A(k+1:n, k) to beta e1
 // Workgroup b reduces matrix b of a batch: order sz.n[b], leading dimension lda, matrices strideA apart;
 // its reflectors, tau, d and e sit nmax^2 or nmax entries apart per matrix.
+// Orders above kTriLdsMax (one matrix only): the first t0 = n - nl columns are reduced on a full symmetric
+// copy in global memory (Aw, n x n column-major, L2-resident: per step a thread-per-row matrix-vector
+// product and rank-2 update, coalesced along the columns), then the trailing triangle of order nl moves
+// to LDS and the reduction continues there with local indices.
 __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int64_t strideA, TriSizes sz, int nmax,
-                                                  double* refl, double* tau, double* d, double* e, double* flag) {
+                                                  double* refl, double* tau, double* d, double* e, double* flag,
+                                                  double* Aw, int t0) {
   const int b = blockIdx.x, n = sz.n[b];
   if (b == 0 && threadIdx.x == 0) flag[0] = 0.0;   // the cluster flag of the bisection that follows
   A += b * strideA;
@@ -65,26 +76,22 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
   tau += (int64_t)b * nmax;
   d += (int64_t)b * nmax;
   e += (int64_t)b * nmax;
-  extern __shared__ double sA[];   // packed lower triangle, column-major
-  double* v = sA + n * (n + 1) / 2;
-  double* p = v + n;
+  extern __shared__ double sA[];   // packed lower triangle of the trailing order nl, column-major
+  const int nl = n - t0;
+  double* v = sA + nl * (nl + 1) / 2;
+  double* p = v + nl;
   __shared__ double s_tau[2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int t = tid; t < n * n; t += blockDim.x) {
-    const int i = t % n, j = t / n;
-    if (i >= j) sA[tr_lo(i, j, n)] = 0.5 * (A[i + (int64_t)j * lda] + A[j + (int64_t)i * lda]);
-  }
-  __syncthreads();
-  // reflector k from column k below the diagonal (final once step k-1's update is done), by wave 0: v_k
-  // into vk, its entries to refl, tau, e, d, and tau for the workgroup in s_tau[k & 1]
-  auto reflector = [&](int k, double* vk) {
+  // reflector k from the column below the diagonal x[0 .. m) (m = n - k - 1), by wave 0: v_k into vk, its
+  // entries to refl, tau, e, and tau for the workgroup in s_tau[k & 1]; the diagonal entry dk to d
+  auto reflector = [&](int k, const double* x, int xstride, double dk, double* vk) {
     const int m = n - k - 1;
     double xs[4];
     double ss = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = lane + 64 * q;
-      xs[q] = i < m ? sA[tr_lo(k + 1 + i, k, n)] : 0.0;
+      xs[q] = i < m ? x[(int64_t)i * xstride] : 0.0;
       if (i >= 1) ss += xs[q] * xs[q];
     }
     ss = tr_wave_sum(ss);
@@ -113,24 +120,88 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
       s_tau[k & 1] = tk;
       tau[k] = tk;
       e[k] = beta;
-      d[k] = sA[tr_lo(k, k, n)];
+      d[k] = dk;
     }
   };
-  // v_k lives in the packed slots of column k-1 below its diagonal (n - k entries, dead once reflector k-1
-  // is formed), v_0 in its own array: so reflector k+1 can be formed while step k still reads v_k
-  auto vbuf = [&](int k) -> double* { return k == 0 ? v : sA + tr_lo(k, k - 1, n); };
-  bool ahead = false;   // reflector k already formed during step k-1 (uniform)
-  for (int k = 0; k < n - 2; ++k) {
+  if (t0 > 0) {
+    // ---- global phase: columns 0 .. t0-1 on the full copy Aw (ld n); vectors in the LDS region ----
+    double* gv = sA;            // two reflector vectors (256 each)
+    double* gp = sA + 512;      // p (256)
+    double* gred = sA + 768;    // matrix-vector partials, 4 x 256
+    for (int t = tid; t < n * n; t += blockDim.x) {
+      const int i = t % n, j = t / n;
+      Aw[t] = 0.5 * (A[i + (int64_t)j * lda] + A[j + (int64_t)i * lda]);
+    }
+    __syncthreads();
+    for (int k = 0; k < t0; ++k) {
+      const int m = n - k - 1;
+      double* vk = gv + 256 * (k & 1);
+      const double* col = Aw + (int64_t)k * n + (k + 1);   // A(k+1 .., k)
+      if (wave == 0) reflector(k, col, 1, Aw[(int64_t)k * n + k], vk);
+      __syncthreads();
+      const double tk = s_tau[k & 1];
+      if (tk == 0.0) continue;   // uniform
+      // p = tk A22 v: thread (r, g) sums the columns c = g, g + 4, .. of row r, then the four groups in order
+      const int r = tid & 255, g = tid >> 8;
+      double* A22 = Aw + (int64_t)(k + 1) * n + (k + 1);   // A22(r, c) at r + c n
+      if (r < m) {
+        double acc = 0.0;
+        for (int c = g; c < m; c += 4) acc += A22[r + (int64_t)c * n] * vk[c];
+        gred[g * 256 + r] = acc;
+      }
+      __syncthreads();
+      if (tid < m) gp[tid] = tk * ((gred[tid] + gred[256 + tid]) + (gred[512 + tid] + gred[768 + tid]));
+      __syncthreads();
+      // K = tk / 2 p^T v, then A22 -= v w^T + w v^T with w = p - K v (the full square: both triangles)
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = lane + 64 * q;
+        if (i < m) s += gp[i] * vk[i];
+      }
+      const double K = 0.5 * tk * tr_wave_sum(s);
+      if (r < m) {
+        const double vr = vk[r], wr = gp[r] - K * vr;
+        for (int c = g; c < m; c += 4) {
+          const double vc = vk[c], wc = gp[c] - K * vc;
+          A22[r + (int64_t)c * n] -= vr * wc + wr * vc;
+        }
+      }
+      __syncthreads();
+    }
+    // the trailing lower triangle (order nl) into LDS
+    for (int t = tid; t < nl * nl; t += blockDim.x) {
+      const int i = t % nl, j = t / nl;
+      if (i >= j) sA[tr_lo(i, j, nl)] = Aw[(t0 + i) + (int64_t)(t0 + j) * n];
+    }
+    __syncthreads();
+  } else {
+    for (int t = tid; t < n * n; t += blockDim.x) {
+      const int i = t % n, j = t / n;
+      if (i >= j) sA[tr_lo(i, j, n)] = 0.5 * (A[i + (int64_t)j * lda] + A[j + (int64_t)i * lda]);
+    }
+    __syncthreads();
+  }
+  // ---- LDS phase: local step kl = k - t0 on the packed triangle of order nl ----
+  // v_kl lives in the packed slots of local column kl-1 below its diagonal (nl - kl entries, dead once that
+  // reflector is formed), v_0 in its own array: so reflector kl+1 can be formed while step kl still reads v_kl
+  auto vbuf = [&](int kl) -> double* { return kl == 0 ? v : sA + tr_lo(kl, kl - 1, nl); };
+  auto reflector_lds = [&](int kl, double* vk) {
+    reflector(kl + t0, sA + tr_lo(kl + 1, kl, nl), 1, sA[tr_lo(kl, kl, nl)], vk);
+  };
+  bool ahead = false;   // reflector kl already formed during step kl-1 (uniform)
+  for (int kl = 0; kl < nl - 2; ++kl) {
+    const int k = kl + t0;
     const int m = n - k - 1;   // length of the column below the diagonal
-    double* vk = vbuf(k);
+    double* vk = vbuf(kl);
     if (!ahead) {
-      if (wave == 0) reflector(k, vk);
+      if (wave == 0) reflector_lds(kl, vk);
       lds_barrier();
     }
     const double tk = s_tau[k & 1];
     ahead = false;
     if (tk == 0.0) continue;   // uniform
-    // p = tk A22 v (A22 = A(k+1:n, k+1:n), symmetric, lower stored): L lanes per row (one DPP quad, half
+    // p = tk A22 v (A22 = A(kl+1:nl, kl+1:nl), symmetric, lower stored): L lanes per row (one DPP quad, half
     // row or row), more lanes as the block shrinks so that more waves share the rows
     {
       const int LS = m > 128 ? 2 : (m > 64 ? 3 : 4), L = 1 << LS;
@@ -139,17 +210,17 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
         const int r = rb + (tid >> LS), sub = tid & (L - 1);
         double acc = 0.0;
         if (r < m) {
-          const int R = k + 1 + r;
+          const int R = kl + 1 + r;
           int j = sub;
-          // j <= r: row R of the lower triangle, A(R, C) with C = k + 1 + j; the packed address advances by
-          // colstart(C + L) - colstart(C) - L = L (n - C) - L (L + 1) / 2
-          int C = k + 1 + j, addr = tr_lo(R, C, n);
+          // j <= r: row R of the lower triangle, A(R, C) with C = kl + 1 + j; the packed address advances by
+          // colstart(C + L) - colstart(C) - L = L (nl - C) - L (L + 1) / 2
+          int C = kl + 1 + j, addr = tr_lo(R, C, nl);
           for (; j <= r; j += L, C += L) {
             acc += sA[addr] * vk[j];
-            addr += L * (n - C) - tri;
+            addr += L * (nl - C) - tri;
           }
           // j > r: column R, A(C, R), consecutive in C
-          addr = tr_lo(k + 1 + j, R, n);
+          addr = tr_lo(kl + 1 + j, R, nl);
           for (; j < m; j += L, addr += L) acc += sA[addr] * vk[j];
         }
         if (LS == 2) {
@@ -175,17 +246,17 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
     const int tx = tid & 31, ty = tid >> 5;
     auto update_col = [&](int jj) {
       const double vj = vk[jj], wj = p[jj] - K * vj;
-      int addr = tr_lo(k + 1 + jj + tx, k + 1 + jj, n);
+      int addr = tr_lo(kl + 1 + jj + tx, kl + 1 + jj, nl);
       for (int ii = jj + tx; ii < m; ii += 32, addr += 32) {
         const double vi = vk[ii], wi = p[ii] - K * vi;
         sA[addr] -= vi * wj + wi * vj;
       }
     };
     if (ty < m) update_col(ty);
-    // look-ahead: column 0 of A22 (column k+1) was updated by lanes 0-31 of wave 0 just now, so wave 0
-    // forms reflector k+1 while the other waves finish the update
-    const bool la = k + 1 < n - 2;
-    if (la && wave == 0) reflector(k + 1, vbuf(k + 1));
+    // look-ahead: column 0 of A22 (local column kl+1) was updated by lanes 0-31 of wave 0 just now, so wave 0
+    // forms reflector kl+1 while the other waves finish the update
+    const bool la = kl + 1 < nl - 2;
+    if (la && wave == 0) reflector_lds(kl + 1, vbuf(kl + 1));
     // the later columns in reverse order of ty, so that wave 0, which also formed the reflector, gets the
     // shortest of each group of 32
     for (int jj = (31 - ty) + 32; jj < m; jj += 32) update_col(jj);
@@ -194,9 +265,9 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
   }
   __syncthreads();
   if (tid == 0) {
-    d[n - 2] = sA[tr_lo(n - 2, n - 2, n)];
-    d[n - 1] = sA[tr_lo(n - 1, n - 1, n)];
-    e[n - 2] = sA[tr_lo(n - 1, n - 2, n)];
+    d[n - 2] = sA[tr_lo(nl - 2, nl - 2, nl)];
+    d[n - 1] = sA[tr_lo(nl - 1, nl - 1, nl)];
+    e[n - 2] = sA[tr_lo(nl - 1, nl - 2, nl)];
     e[n - 1] = 0.0;
     tau[n - 2] = 0.0;
     tau[n - 1] = 0.0;
@@ -311,13 +382,14 @@ __global__ __launch_bounds__(kBisThreads) void k_tri_bisect(const double* dg, co
 }
 
 // 3. inverse iteration: eigenvector i = global thread index, three solves with LDL^T of T - lambda_i I
-// (pivots of magnitude below pivmin replaced by pivmin with their sign).  A workgroup of 32 threads keeps
-// T, its threads' factors (L_j and 1 / D_j) and iterates in LDS, entry j of thread t at j * 32 + t;
-// Z(j, i) is written at j * n + i.
-constexpr int kInvitThreads = 32;
+// (pivots of magnitude below pivmin replaced by pivmin with their sign).  A workgroup of kInvitThreads
+// threads (32, or 16 where 32 vectors do not fit in LDS) keeps T, its threads' factors (L_j and 1 / D_j)
+// and iterates in LDS, entry j of thread t at j * kInvitThreads + t; Z(j, i) is written at j * n + i.
 constexpr int kInvB = 8;   // rows of a recurrence staged in registers at a time
-static size_t invit_lds_bytes(int n) { return ((size_t)n * (2 + 3 * kInvitThreads)) * sizeof(double); }
+static size_t invit_lds_bytes(int n, int tpb) { return ((size_t)n * (2 + 3 * tpb)) * sizeof(double); }
+static int invit_threads(int n) { return invit_lds_bytes(n, 32) <= kLdsLimit ? 32 : 16; }
 
+template <int kInvitThreads>
 __global__ __launch_bounds__(kInvitThreads) void k_tri_invit(const double* dg, const double* eg, TriSizes sz,
                                                              int nmax, const double* lam, double* Z) {
   const int n = sz.n[blockIdx.y];
@@ -594,10 +666,20 @@ static void tri_attrs() {
   if (!attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tridiag), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)kLdsLimit);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tri_invit), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)kLdsLimit);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tri_invit<32>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tri_invit<16>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
     attr = true;
   }
+}
+
+static void launch_invit(const double* d, const double* e, const TriSizes& sz, int nmax, int count, const double* lam,
+                         double* Z, hipStream_t s) {
+  if (invit_threads(nmax) == 32)
+    k_tri_invit<32><<<dim3((nmax + 31) / 32, count), 32, invit_lds_bytes(nmax, 32), s>>>(d, e, sz, nmax, lam, Z);
+  else
+    k_tri_invit<16><<<dim3((nmax + 15) / 16, count), 16, invit_lds_bytes(nmax, 16), s>>>(d, e, sz, nmax, lam, Z);
 }
 
 size_t tridiag_rhs_work_count(int nmax, int count, int C) {
@@ -610,7 +692,8 @@ int syev_tridiag_rhs(const double* A, int ld, const int* sizes, int count, doubl
   TriSizes sz;
   int nmax = 0;
   for (int b = 0; b < count; ++b) {
-    RW_CHECK(tridiag_fits(sizes[b]) && sizes[b] <= ld, RW_EINVAL, "batched tridiagonal solver: n = %d", sizes[b]);
+    RW_CHECK(tridiag_batch_fits(sizes[b]) && sizes[b] <= ld, RW_EINVAL, "batched tridiagonal solver: n = %d",
+             sizes[b]);
     sz.n[b] = sizes[b];
     nmax = std::max(nmax, sizes[b]);
   }
@@ -627,11 +710,11 @@ int syev_tridiag_rhs(const double* A, int ld, const int* sizes, int count, doubl
   double* flag = h + (size_t)count * nmax * C;
   tri_attrs();
   const int64_t strideR = (int64_t)ld * C;
-  k_tridiag<<<count, 1024, tridiag_lds_bytes(nmax), s>>>(A, ld, (int64_t)ld * ld, sz, nmax, refl, tau, d, e, flag);
+  k_tridiag<<<count, 1024, tridiag_lds_bytes(nmax), s>>>(A, ld, (int64_t)ld * ld, sz, nmax, refl, tau, d, e, flag,
+                                                         nullptr, 0);
   k_tri_rhs<<<dim3(C, count), 64, 0, s>>>(refl, tau, sz, nmax, R, ld, strideR, C, h);
   k_tri_bisect<<<dim3(nmax, count), kBisThreads, 0, s>>>(d, e, sz, nmax, lam, flag);
-  k_tri_invit<<<dim3((nmax + kInvitThreads - 1) / kInvitThreads, count), kInvitThreads, invit_lds_bytes(nmax), s>>>(
-      d, e, sz, nmax, lam, Z);
+  launch_invit(d, e, sz, nmax, count, lam, Z, s);
   k_tri_rot<<<dim3(ld, count), 64, 0, s>>>(Z, lam, h, sz, nmax, C, flag, w, R, ld, strideR);
   RW_LAUNCH_CHECK();
   if (flag_dev != nullptr) {
@@ -650,10 +733,11 @@ int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hip
   tri_attrs();
   TriSizes sz;
   sz.n[0] = n;
-  k_tridiag<<<1, 1024, tridiag_lds_bytes(n), s>>>(A, n, 0, sz, n, b.refl, b.tau, b.d, b.e, b.flag);
+  // orders above kTriLdsMax: the first n - kTriLdsMax columns on a full copy in b.Lf (n x n, unused otherwise)
+  const int nl = std::min(n, kTriLdsMax);
+  k_tridiag<<<1, 1024, tridiag_lds_bytes(nl), s>>>(A, n, 0, sz, n, b.refl, b.tau, b.d, b.e, b.flag, b.Lf, n - nl);
   k_tri_bisect<<<n, kBisThreads, 0, s>>>(b.d, b.e, sz, n, b.lam, b.flag);
-  k_tri_invit<<<(n + kInvitThreads - 1) / kInvitThreads, kInvitThreads, invit_lds_bytes(n), s>>>(b.d, b.e, sz, n,
-                                                                                                b.lam, b.Z);
+  launch_invit(b.d, b.e, sz, n, 1, b.lam, b.Z, s);
   k_tri_back<<<n, 64, 0, s>>>(b.refl, b.tau, n, b.Z, V);
   RW_LAUNCH_CHECK();
   if (flag_dev != nullptr) {
@@ -684,7 +768,7 @@ int rw_dense_syev_tridiag_workspace_bytes(int n, size_t* bytes) {
 int rw_dense_syev_tridiag(const double* A, double* w, double* V, int n, void* work, size_t work_bytes,
                           hipStream_t stream) {
   RW_CHECK(A != nullptr && w != nullptr && V != nullptr && work != nullptr, RW_EINVAL, "null argument");
-  RW_CHECK(tridiag_fits(n), RW_EINVAL, "tridiagonal eigensolver: n = %d out of range [3, 199]", n);
+  RW_CHECK(tridiag_fits(n), RW_EINVAL, "tridiagonal eigensolver: n = %d out of range [3, 256]", n);
   RW_CHECK(work_bytes >= tridiag_work_count(n) * sizeof(double), RW_EWORKSPACE, "workspace too small");
   const int st = syev_tridiag(A, w, V, n, static_cast<double*>(work), stream);
   if (st == RW_ENOCONV) set_error("tridiagonal eigensolver: clustered eigenvalues (use the Jacobi routine)");
@@ -692,7 +776,7 @@ int rw_dense_syev_tridiag(const double* A, double* w, double* V, int n, void* wo
 }
 
 int rw_dense_eig_rhs_batched_workspace_bytes(int nmax, int count, int nrhs, size_t* bytes) {
-  RW_CHECK(bytes != nullptr && tridiag_fits(nmax) && count >= 1 && count <= kTriBatchMax && nrhs >= 1, RW_EINVAL,
+  RW_CHECK(bytes != nullptr && tridiag_batch_fits(nmax) && count >= 1 && count <= kTriBatchMax && nrhs >= 1, RW_EINVAL,
            "bad sizes (nmax = %d, count = %d, nrhs = %d)", nmax, count, nrhs);
   *bytes = tridiag_rhs_work_count(nmax, count, nrhs) * sizeof(double);
   return RW_OK;
