@@ -176,15 +176,8 @@ __global__ void k_b_reduced(const BatchImg* D, LuJob* jobs) {
   const int m = d.m, C = d.C;
   const int64_t S = d.S, ld = d.S_cap;
   const int64_t total = (int64_t)m * (m + C);
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(t % m), j = (int)(t / m);
-    const double* a = d.Qs + (int64_t)i * ld;
-    const double* b = j < m ? d.GB + (int64_t)j * ld : d.Hs + (int64_t)(j - m) * ld;
-    double acc = 0.0;
-    for (int64_t s = 0; s < S; ++s) acc += a[s] * b[s];
-    if (j < m) d.K[i + (int64_t)j * m] = (i == j ? d.lambda[i] : 0.0) - acc;
-    else d.Y[i + (int64_t)(j - m) * m] = acc;
-  }
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x)
+    reduced_entry(t, m, C, S, ld, d.Qs, d.GB, d.Hs, d.lambda, d.K, d.Y);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     LuJob jb;
     jb.A = d.K; jb.B = d.Y; jb.stat = d.stat; jb.n = m; jb.nrhs = C;

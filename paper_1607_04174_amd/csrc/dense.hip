@@ -827,20 +827,6 @@ __global__ __launch_bounds__(1024) void k_lu_solve(double* A, int n, double* B, 
   lu_body(A, n, B, nrhs, stat);
 }
 
-// one workgroup per job; jobs (and their sizes) are read from device memory, so a captured launch
-// stays valid when the jobs are rewritten between replays
-__global__ __launch_bounds__(1024) void k_lu_solve_batched(const LuJob* jobs, int count) {
-  const LuJob j = jobs[blockIdx.x];
-  if (j.n > 0) lu_body(j.A, j.n, j.B, j.nrhs, j.stat);
-}
-
-int lu_solve_batched(const LuJob* jobs, int count, hipStream_t s) {
-  if (count <= 0) return RW_OK;
-  k_lu_solve_batched<<<count, 1024, 0, s>>>(jobs, count);
-  RW_LAUNCH_CHECK();
-  return RW_OK;
-}
-
 // The same elimination with A and B in LDS (rows padded to an odd stride, so that a row read across
 // lanes is free of bank conflicts).  Rows are not exchanged: step k eliminates column k from every row not
 // yet chosen as a pivot row (a flag per row) using the chosen row p_k; the pivot search of column k+1 runs in
@@ -849,7 +835,7 @@ int lu_solve_batched(const LuJob* jobs, int count, hipStream_t s) {
 constexpr int kLuLdsMaxRows = 192;   // rows per lane in the elimination grid: 3 x 64
 constexpr int kLuWaveRhs = 8;        // back substitution in one wave up to this many right-hand sides
 
-__global__ __launch_bounds__(1024) void k_lu_solve_lds(const double* Ag, int n, double* Bg, int nrhs, double* stat) {
+__device__ void lu_lds_body(const double* Ag, int n, double* Bg, int nrhs, double* stat) {
   extern __shared__ double sm[];
   const int ld = n | 1;
   double* A = sm;                       // ld x n
@@ -1010,20 +996,53 @@ __global__ __launch_bounds__(1024) void k_lu_solve_lds(const double* Ag, int n, 
   if (tid == 0) stat[0] = s_minpiv / amax;
 }
 
-static size_t lu_lds_bytes(int n, int nrhs) {
+__host__ __device__ inline size_t lu_lds_bytes(int n, int nrhs) {
   const size_t ld = (size_t)(n | 1);
   return (ld * (n + nrhs)) * sizeof(double) + 2 * (size_t)n * sizeof(int);
+}
+// the LDS elimination serves a system when it fits; the single and the batched solves decide alike, so a
+// batched system is solved by the same code as the same system alone
+__host__ __device__ inline bool lu_lds_fits(int n, int nrhs) {
+  return n <= kLuLdsMaxRows && lu_lds_bytes(n, nrhs) <= kLdsLimit;
+}
+
+__global__ __launch_bounds__(1024) void k_lu_solve_lds(const double* Ag, int n, double* Bg, int nrhs, double* stat) {
+  lu_lds_body(Ag, n, Bg, nrhs, stat);
+}
+
+// one workgroup per job; jobs (and their sizes) are read from device memory, so a captured launch
+// stays valid when the jobs are rewritten between replays
+__global__ __launch_bounds__(1024) void k_lu_solve_batched(const LuJob* jobs, int count) {
+  const LuJob j = jobs[blockIdx.x];
+  if (j.n <= 0) return;
+  if (lu_lds_fits(j.n, j.nrhs)) lu_lds_body(j.A, j.n, j.B, j.nrhs, j.stat);
+  else lu_body(j.A, j.n, j.B, j.nrhs, j.stat);
+}
+
+static int lu_attrs() {
+  static bool attr = false;
+  if (!attr) {
+    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_solve_lds),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_solve_batched),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+    attr = true;
+  }
+  return RW_OK;
+}
+
+int lu_solve_batched(const LuJob* jobs, int count, hipStream_t s) {
+  if (count <= 0) return RW_OK;
+  RW_TRY(lu_attrs());
+  k_lu_solve_batched<<<count, 1024, kLdsLimit, s>>>(jobs, count);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
 }
 
 int lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s) {
   if (n <= 0) return RW_OK;
-  if (n <= kLuLdsMaxRows && lu_lds_bytes(n, nrhs) <= kLdsLimit) {
-    static bool attr = false;
-    if (!attr) {
-      RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_solve_lds),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
-      attr = true;
-    }
+  if (lu_lds_fits(n, nrhs)) {
+    RW_TRY(lu_attrs());
     k_lu_solve_lds<<<1, 1024, lu_lds_bytes(n, nrhs), s>>>(A, n, B, nrhs, stat);
   } else {
     k_lu_solve<<<1, 1024, 0, s>>>(A, n, B, nrhs, stat);

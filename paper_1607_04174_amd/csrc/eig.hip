@@ -4,12 +4,22 @@
 // Eigensolver: block Chebyshev-filtered subspace iteration with Rayleigh-Ritz.  The known null
 // vector (eigenvalue 0) is deflated analytically: the block lives in its orthogonal complement and
 // the null vector is written as column 0 of Q.  Each outer iteration applies a degree-d Chebyshev
-// polynomial of the operator that damps [a, b] (a = the largest Ritz value of the block,
-// b = 2 for L_hat, the Gershgorin bound 2 max d for L), i.e. d fused stencil passes over the block,
-// then one Rayleigh-Ritz step: G = F^T F and H = F^T op F in FP64, G = V s V^T, W = V s^{-1/2},
-// eig(W^T H W) = Z Theta Z^T, X = F W Z.  All dense work is FP64; the block itself is in the graph's
-// type.  On MI355X the cost is dominated by the HBM-bound stencil passes, which the polynomial
-// filter amortizes over one FP64 Gram / eigendecomposition per outer iteration.
+// polynomial of the operator that damps [a, b] (b = 2 for L_hat, the Gershgorin bound 2 max d for L),
+// i.e. d fused stencil passes over the block, then one Rayleigh-Ritz step: G = F^T F and H = F^T op F
+// in FP64, W with F W orthonormal, eig(W^T H W) = Z Theta Z^T, X = F W Z.  All dense work is FP64; the
+// block itself is in the graph's type.  On MI355X the cost is dominated by the HBM-bound stencil
+// passes, which the polynomial filter amortizes over one FP64 Gram / eigendecomposition per outer
+// iteration.
+//   * a: the block's largest Ritz value.  Next to a warm block (an update) the random guard columns hold
+//     it near 1 at first, and the low-degree filter on [a, b] turns them into the low-frequency directions
+//     the warm columns need; a tighter estimate of the top of the guard band leaves the guards random and
+//     gains only about 3x per 64 passes for the top wanted columns of the 512 x 512 workload (their gap to
+//     the band is 4e-4 of a spectrum of width 2), measured slower for every update.
+//   * soft locking: the leading wanted columns whose residuals are below tol / 4 are not filtered (they
+//     stay in the Rayleigh-Ritz step), so the filter's cost follows the unconverged columns.
+//   * degree: enough for the largest residual among the filtered wanted columns to fall to tol / 8 at
+//     the gain of the lowest filtered Ritz value, between 4 and 64 (at most the amplification of a cold
+//     start, 1e4 in FP32 and 1e8 in FP64).
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -316,8 +326,13 @@ static int chfsi(Ctx& c, int m, int nb, const rw_eig_opts* o, void* Q, double* l
     }
     if (nconv == k || it >= max_iter) break;
     ++it;
+    // soft locking: the leading wanted columns well below tol are left out of the filter
+    int nlock = 0;
+    while (nlock < k && rs[nlock] <= 0.25 * o->tol) ++nlock;
+    double res_act = 0.0;
+    for (int j = nlock; j < k; ++j) res_act = std::max(res_act, rs[j]);
     // filter bounds
-    double a = th[nb - 1], a0 = std::max(th[0], 0.0);
+    double a = th[nb - 1], a0 = std::max(th[nlock], 0.0);
     if (!(a < bup)) a = 0.5 * bup;
     if (!(a0 < a)) a0 = 0.0;
     const double e = 0.5 * (bup - a), cc = 0.5 * (bup + a);
@@ -325,9 +340,12 @@ static int chfsi(Ctx& c, int m, int nb, const rw_eig_opts* o, void* Q, double* l
     if (deg <= 0) {
       double t0 = (cc - a0) / e;
       double ac = t0 > 1.0 ? std::acosh(t0) : 1e-3;
-      deg = (int)std::ceil(std::acosh(amp_target) / ac);
+      const double amp = std::min(amp_target, std::max(16.0, 8.0 * res_act / o->tol));
+      deg = (int)std::ceil(std::acosh(amp) / ac);
       deg = std::min(64, std::max(4, deg));
     }
+    const int nfl = nb - nlock;                // filtered columns nlock .. nb-1
+    const size_t off = dtype_size(c.dt) * (size_t)c.N * nlock;
     // buffers: Y0 = X, Y1, Y2 free
     int b0 = ix, b1 = -1, b2 = -1;
     {
@@ -339,22 +357,25 @@ static int chfsi(Ctx& c, int m, int nb, const rw_eig_opts* o, void* Q, double* l
     }
     double sigma = e / (a0 - cc);
     const double tau = 2.0 / sigma;
+    const int bx = ix;   // the Ritz block X (the locked columns are taken from it)
     // Y1 = (op X - c X) sigma / e
-    RW_TRY(stencil_apply(g, w.B[b0], w.B[b1], nullptr, nb, sigma / e, -cc * sigma / e, 0.0, c.s));
-    c.spmm_cols += nb;
+    RW_TRY(stencil_apply(g, w.B[b0] + off, w.B[b1] + off, nullptr, nfl, sigma / e, -cc * sigma / e, 0.0, c.s));
+    c.spmm_cols += nfl;
     for (int i = 2; i <= deg; ++i) {
       double sn = 1.0 / (tau - sigma);
       // Y2 = (op Y1 - c Y1) 2 sn / e - sigma sn Y0
-      RW_TRY(stencil_apply(g, w.B[b1], w.B[b2], w.B[b0], nb, 2.0 * sn / e, -2.0 * cc * sn / e, -sigma * sn, c.s));
-      c.spmm_cols += nb;
+      RW_TRY(stencil_apply(g, w.B[b1] + off, w.B[b2] + off, w.B[b0] + off, nfl, 2.0 * sn / e, -2.0 * cc * sn / e,
+                           -sigma * sn, c.s));
+      c.spmm_cols += nfl;
       int t = b0;
       b0 = b1;
       b1 = b2;
       b2 = t;
       sigma = sn;
     }
-    // filtered block in b1; the other three are free
-    RW_TRY(project_out(c.dt, w.B[b1], c.N, g->ghat, c.N, nb, w.tmp, w.partial, c.s));
+    // filtered columns in b1; the locked ones join them unfiltered; the other three buffers are free
+    if (nlock > 0 && b1 != bx) RW_TRY(copy_cols(c.dt, w.B[bx], c.N, c.dt, w.B[b1], c.N, c.N, nlock, c.s));
+    RW_TRY(project_out(c.dt, w.B[b1] + off, c.N, g->ghat, c.N, nfl, w.tmp, w.partial, c.s));
     int fr[3], nf = 0;
     for (int q = 0; q < 4; ++q)
       if (q != b1) fr[nf++] = q;

@@ -340,6 +340,22 @@ __device__ __forceinline__ void solve_coeffs_block(double* Y, int m, int C, cons
 // launch of solve_coeffs_block for one system (solve.hip)
 int solve_coeffs(double* Y, int m, int C, const double* cn, const Graph* g, hipStream_t s);
 
+// Entry t of the reduced system from the seed rows (leading dimension ld, S seeds): for t < m m,
+// K(i, j) = lambda_i [i == j] - sum_s Qs(s, i) GB(s, j); for t < m C, Y(i, c) = sum_s Qs(s, i) Hs(s, c); the
+// seed sums run in order (the single and the batched solves form the system with this same code)
+__device__ __forceinline__ void reduced_entry(int64_t t, int m, int C, int64_t S, int64_t ld, const double* Qs,
+                                              const double* GB, const double* Hs, const double* lambda, double* K,
+                                              double* Y) {
+  if (t >= (int64_t)m * (m + C)) return;
+  const int i = (int)(t % m), j = (int)(t / m);
+  const double* a = Qs + (int64_t)i * ld;
+  const double* b = j < m ? GB + (int64_t)j * ld : Hs + (int64_t)(j - m) * ld;
+  double acc = 0.0;
+  for (int64_t q = 0; q < S; ++q) acc += a[q] * b[q];
+  if (j < m) K[i + (int64_t)j * m] = (i == j ? lambda[i] : 0.0) - acc;
+  else Y[i + (int64_t)(j - m) * m] = acc;
+}
+
 // Seed row k (node i, leading dimension ld) of the reduced system's inputs, formed by one workgroup from
 // the FP64 weights and degrees: for j < m, Qs(k, j) = q'_j(i) and GB(k, j) = (B q'_j)(i) = -sum over the
 // non-seed neighbours t of coef(i, t) q'_j(t), with coef(i, t) = w_it d_i^{-1/2} d_t^{-1/2} (or w_it);

@@ -46,8 +46,6 @@ struct SolveWork {
   double* cn;         // 2 ma     (c_j, n_j of the FP64 basis)
   double* npart;      // null_stats partials
   int* nbad;          // set when some n_j is not positive
-  double* T;          // ma x ma  (Q_s^T B Q_n)
-  double* R;          // ma x C   (Q_s^T op_ss U_hat_s)
   double* Gq;         // ma x ma  (Q_s^T Q_s)
   double* Gb;         // ma x C   (Q_s^T U_hat_s)
   double* fvals;      // ncand x C
@@ -82,8 +80,6 @@ static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base,
   t.cn = c.take<double>(2 * (size_t)ma);
   t.npart = c.take<double>(null_stats_partial_count(g->N, ma));
   t.nbad = c.take<int>(4);
-  t.T = c.take<double>((size_t)ma * ma);
-  t.R = c.take<double>((size_t)ma * C);
   t.Gq = c.take<double>((size_t)ma * ma);
   t.Gb = c.take<double>((size_t)ma * C);
   const int nc = fit ? fit_cands(ma) : 0;
@@ -272,19 +268,11 @@ int solve_coeffs(double* Y, int m, int C, const double* cn, const Graph* g, hipS
   return RW_OK;
 }
 
-// K = diag(lambda) - T (leading m x m of T, leading dimension ld);  Yrhs = leading m rows of R
-__global__ void k_build_reduced(const double* T, const double* R, const double* lambda, int ld, int m, int C,
-                                double* K, double* Y) {
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t < (int64_t)m * m) {
-    int i = (int)(t % m), j = (int)(t / m);
-    K[t] = (i == j ? lambda[i] : 0.0) - T[i + (int64_t)j * ld];
-  }
-  if (t < (int64_t)m * C) {
-    int i = (int)(t % m), c = (int)(t / m);
-    Y[t] = R[i + (int64_t)c * ld];
-  }
+__global__ void k_reduced(int m, int C, int64_t S, const double* Qs, const double* GB, const double* Hs,
+                          const double* lambda, double* K, double* Y) {
+  reduced_entry(blockIdx.x * (int64_t)blockDim.x + threadIdx.x, m, C, S, S, Qs, GB, Hs, lambda, K, Y);
 }
+
 
 // ---------------------------------------------------------------------------------------------
 // reconstruction: U(lab, i) = s_i * sum_{j>=1} Q(i, j) Y(j, lab) + kappa_lab on non-seeds (s = d^{-1/2} or 1;
@@ -988,11 +976,9 @@ static int solve_impl(rw_graph h, const void* Q, int q_dtype, const double* lamb
   RW_TRY(null_stats(g, Q, q_dtype, m, w.npart, w.cn, w.nbad, stream));
   k_seed_correct<<<nblocks(S * m, 256), 256, 0, stream>>>(w.Qs, w.GB, w.gs, w.Bg, w.cn, S, m);
   RW_LAUNCH_CHECK();
-  // T = Q'_s^T (B Q'_n),  R = Q'_s^T (op_ss U_hat_s)  (m x m and m x C, leading dimension m)
-  RW_TRY(gram(RW_F64, w.Qs, S, w.GB, S, S, m, m, w.T, w.partial, stream));
-  RW_TRY(gram(RW_F64, w.Qs, S, w.Hs, S, S, m, C, w.R, w.partial, stream));
-  // reduced system and solve
-  k_build_reduced<<<nblocks((int64_t)m * std::max(m, C), 256), 256, 0, stream>>>(w.T, w.R, lambda, m, m, C, w.K, w.Y);
+  // reduced system K = Lambda - Q'_s^T (B Q'_n), Y = Q'_s^T (op_ss U_hat_s), and its solve (the batched solve
+  // forms and solves each image's system with the same code)
+  k_reduced<<<nblocks((int64_t)m * (m + C), 256), 256, 0, stream>>>(m, C, S, w.Qs, w.GB, w.Hs, lambda, w.K, w.Y);
   RW_LAUNCH_CHECK();
   RW_TRY(lu_solve(w.K, m, w.Y, C, w.stat, stream));
   RW_TRY(solve_coeffs(w.Y, m, C, w.cn, g, stream));

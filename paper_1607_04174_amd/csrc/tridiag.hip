@@ -11,8 +11,11 @@
 //   3. eigenvectors of T by inverse iteration with the LDL^T factorization of T - lambda I (one lane
 //      per eigenvector, three solves, in LDS);
 //   4. V = U Z, the reflectors applied to each eigenvector column (one wave per column).
-// Inverse iteration gives orthogonal vectors only when eigenvalues are separated: the driver reports
-// RW_ENOCONV when two eigenvalues are closer than 1e-6 |T|, and the caller then uses the Jacobi solver.
+// Inverse iteration gives orthogonal vectors only when eigenvalues are separated: the vectors of a
+// cluster (successive eigenvalues closer than 1e-6 |T|) are computed again, in order, by inverse
+// iteration with Gram-Schmidt against the cluster's earlier vectors in every step (the approach of
+// LAPACK's dstein).  The driver reports RW_ENOCONV only for a cluster of more than kTriClusterMax vectors
+// or one whose vectors vanish under the orthogonalization; the caller then uses the Jacobi solver.
 // All arithmetic is FP64.
 #include <algorithm>
 #include <cmath>
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
                                                   double* refl, double* tau, double* d, double* e, double* flag,
                                                   double* Aw, int t0) {
   const int b = blockIdx.x, n = sz.n[b];
-  if (b == 0 && threadIdx.x == 0) flag[0] = 0.0;   // the cluster flag of the bisection that follows
+  if (b == 0 && threadIdx.x == 0) flag[0] = 0.0;   // the flag of the cluster pass that follows
   A += b * strideA;
   refl += (int64_t)b * nmax * nmax;
   tau += (int64_t)b * nmax;
@@ -323,8 +326,7 @@ __device__ __forceinline__ int tr_sturm(const double* d, const double* e2, int n
 
 // 2. eigenvalue idx = blockIdx.x (ascending) by multisection: each pass evaluates Sturm counts at
 // kBisThreads interior points of [a, b] (one per thread) and keeps the subinterval where the count passes
-// idx (the interval shrinks (kBisThreads + 1)-fold per pass); flag[0] = 1 if two eigenvalues are closer
-// than 1e-6 |T| (checked by the workgroup of the smaller one)
+// idx (the interval shrinks (kBisThreads + 1)-fold per pass)
 constexpr int kBisThreads = 256;
 __global__ __launch_bounds__(kBisThreads) void k_tri_bisect(const double* dg, const double* eg, TriSizes sz,
                                                             int nmax, double* lam, double* flag) {
@@ -373,12 +375,6 @@ __global__ __launch_bounds__(kBisThreads) void k_tri_bisect(const double* dg, co
   }
   const double lam_i = 0.5 * (a + b);
   if (tid == 0) lam[idx] = lam_i;
-  // separation from the next eigenvalue, measured from this workgroup's own side: the next eigenvalue lies
-  // above b - atol; a count at lam_i + 1e-6 |T| that exceeds idx + 1 means another eigenvalue is within
-  if (tid == 0 && idx + 1 < n) {
-    const int c2 = tr_sturm(d, e2, n, lam_i + 1e-6 * tn, pivmin);
-    if (c2 > idx + 1) flag[0] = 1.0;
-  }
 }
 
 // 3. inverse iteration: eigenvector i = global thread index, three solves with LDL^T of T - lambda_i I
@@ -527,6 +523,123 @@ __global__ __launch_bounds__(kInvitThreads) void k_tri_invit(const double* dg, c
   for (int jj = 0; jj < n; ++jj) Z[(int64_t)jj * n + i] = z[jj * kInvitThreads + t] * inv;
 }
 
+// 3b. clusters.  One wave per matrix walks the eigenvalues in order; for a cluster (successive
+// eigenvalues closer than kClusterRel |T|) the first vector is kept and each later one is computed again
+// from its own inverse-iteration vector: LDL^T of T - lambda I (lane 0), then three times Gram-Schmidt
+// against the cluster's earlier vectors (twice, all lanes), normalization and one solve, and a final
+// Gram-Schmidt and normalization.  The cluster's vectors are held in LDS (at most kTriClusterMax).
+// flag[0] = 1 for a longer cluster, or when a vector vanishes under the orthogonalization.
+constexpr double kClusterRel = 1e-6;
+constexpr int kTriClusterMax = 32;
+static size_t cluster_lds_bytes(int nmax) { return ((size_t)kTriClusterMax + 5) * nmax * sizeof(double); }
+
+__global__ __launch_bounds__(64) void k_tri_cluster(const double* dg, const double* eg, TriSizes sz, int nmax,
+                                                    const double* lam, double* Z, double* flag) {
+  const int b = blockIdx.x, n = sz.n[b], lane = threadIdx.x;
+  dg += (int64_t)b * nmax;
+  eg += (int64_t)b * nmax;
+  lam += (int64_t)b * nmax;
+  Z += (int64_t)b * nmax * nmax;   // Z(j, i) at j * n + i
+  extern __shared__ double sm[];
+  double* d = sm;
+  double* e = d + nmax;
+  double* Lf = e + nmax;
+  double* rD = Lf + nmax;
+  double* x = rD + nmax;
+  double* cl = x + nmax;   // cluster vectors, vector c at c * nmax
+  double tn = 0.0;
+  for (int j = lane; j < n; j += 64) {
+    d[j] = dg[j];
+    e[j] = eg[j];
+    tn = fmax(tn, fabs(dg[j]) + (j > 0 ? fabs(eg[j - 1]) : 0.0) + (j < n - 1 ? fabs(eg[j]) : 0.0));
+  }
+  tn = wave_max64(tn);
+  __syncthreads();
+  const double thr = kClusterRel * tn;
+  const double pivmin = 2.3e-16 * fmax(tn, 1e-290);
+  auto dot = [&](const double* u, const double* v) -> double {
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s += u[j] * v[j];
+    return wave_sum64(s);
+  };
+  int i = 1;
+  while (i < n) {   // uniform: every lane reads the same eigenvalues
+    if (!(lam[i] - lam[i - 1] < thr)) {
+      ++i;
+      continue;
+    }
+    const int c0 = i - 1;
+    int c1 = i;
+    while (c1 + 1 < n && lam[c1 + 1] - lam[c1] < thr) ++c1;
+    if (c1 - c0 + 1 > kTriClusterMax) {
+      if (lane == 0) flag[0] = 1.0;
+      return;
+    }
+    for (int j = lane; j < n; j += 64) cl[j] = Z[(int64_t)j * n + c0];
+    for (int v = c0 + 1; v <= c1; ++v) {
+      const int nv = v - c0;   // earlier vectors of the cluster in cl[0 .. nv)
+      for (int j = lane; j < n; j += 64) x[j] = Z[(int64_t)j * n + v];
+      const double l = lam[v];
+      if (lane == 0) {   // LDL^T of T - l I
+        double D = d[0] - l;
+        if (fabs(D) < pivmin) D = D < 0.0 ? -pivmin : pivmin;
+        double r = 1.0 / D;
+        rD[0] = r;
+        for (int j = 1; j < n; ++j) {
+          const double Lj = e[j - 1] * r;
+          double Dj = (d[j] - l) - Lj * e[j - 1];
+          if (fabs(Dj) < pivmin) Dj = Dj < 0.0 ? -pivmin : pivmin;
+          r = 1.0 / Dj;
+          Lf[j] = Lj;
+          rD[j] = r;
+        }
+      }
+      __syncthreads();
+      auto orth_normalize = [&]() -> double {
+        for (int pass = 0; pass < 2; ++pass)
+          for (int c = 0; c < nv; ++c) {
+            const double h = dot(cl + (int64_t)c * nmax, x);
+            for (int j = lane; j < n; j += 64) x[j] -= h * cl[(int64_t)c * nmax + j];
+            __syncthreads();
+          }
+        const double nrm = sqrt(dot(x, x));
+        const double s = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        for (int j = lane; j < n; j += 64) x[j] *= s;
+        __syncthreads();
+        return nrm;
+      };
+      double nrm = orth_normalize();
+      for (int it = 0; it < 3; ++it) {
+        if (lane == 0) {   // solve L D L^T y = x in place
+          double y = x[0];
+          for (int j = 1; j < n; ++j) {
+            y = x[j] - Lf[j] * y;
+            x[j] = y;
+          }
+          double xx = y * rD[n - 1];
+          x[n - 1] = xx;
+          for (int j = n - 2; j >= 0; --j) {
+            xx = x[j] * rD[j] - Lf[j + 1] * xx;
+            x[j] = xx;
+          }
+        }
+        __syncthreads();
+        nrm = orth_normalize();
+      }
+      if (!(nrm > 0.0) || !isfinite(nrm)) {
+        if (lane == 0) flag[0] = 1.0;
+        return;
+      }
+      for (int j = lane; j < n; j += 64) {
+        cl[(int64_t)nv * nmax + j] = x[j];
+        Z[(int64_t)j * n + v] = x[j];
+      }
+      __syncthreads();
+    }
+    i = c1 + 1;
+  }
+}
+
 constexpr int kTriAhead = 16;   // reflectors loaded ahead by the back-transform and the right-hand-side pass
 
 // 4. V(:, col) = H_0 H_1 ... H_{n-3} z, z = eigenvector col of T; V column-major n x n
@@ -670,6 +783,8 @@ static void tri_attrs() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tri_invit<16>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tri_cluster),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
     attr = true;
   }
 }
@@ -715,6 +830,7 @@ int syev_tridiag_rhs(const double* A, int ld, const int* sizes, int count, doubl
   k_tri_rhs<<<dim3(C, count), 64, 0, s>>>(refl, tau, sz, nmax, R, ld, strideR, C, h);
   k_tri_bisect<<<dim3(nmax, count), kBisThreads, 0, s>>>(d, e, sz, nmax, lam, flag);
   launch_invit(d, e, sz, nmax, count, lam, Z, s);
+  k_tri_cluster<<<count, 64, cluster_lds_bytes(nmax), s>>>(d, e, sz, nmax, lam, Z, flag);
   k_tri_rot<<<dim3(ld, count), 64, 0, s>>>(Z, lam, h, sz, nmax, C, flag, w, R, ld, strideR);
   RW_LAUNCH_CHECK();
   if (flag_dev != nullptr) {
@@ -738,6 +854,7 @@ int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hip
   k_tridiag<<<1, 1024, tridiag_lds_bytes(nl), s>>>(A, n, 0, sz, n, b.refl, b.tau, b.d, b.e, b.flag, b.Lf, n - nl);
   k_tri_bisect<<<n, kBisThreads, 0, s>>>(b.d, b.e, sz, n, b.lam, b.flag);
   launch_invit(b.d, b.e, sz, n, 1, b.lam, b.Z, s);
+  k_tri_cluster<<<1, 64, cluster_lds_bytes(n), s>>>(b.d, b.e, sz, n, b.lam, b.Z, b.flag);
   k_tri_back<<<n, 64, 0, s>>>(b.refl, b.tau, n, b.Z, V);
   RW_LAUNCH_CHECK();
   if (flag_dev != nullptr) {

@@ -40,7 +40,8 @@ def test_syev_matches_numpy(n, count):
 def test_syev_tridiag_matches_numpy(n):
     """Householder + bisection + inverse iteration on matrices with separated eigenvalues (a random
     symmetric matrix, and a Rayleigh-Ritz-like one: a positive spectrum of width 1e-2 rotated by a random
-    orthogonal matrix), against numpy; a clustered spectrum is refused."""
+    orthogonal matrix), against numpy; clustered spectra (equal eigenvalues, and gaps of 1e-9) give an
+    orthonormal basis of each cluster's subspace; a cluster of more than 32 is refused."""
     need_gpu()
     banner(f"syev tridiag n={n}")
     rng = np.random.default_rng(100 + n)
@@ -59,7 +60,17 @@ def test_syev_tridiag_matches_numpy(n):
         assert np.abs(A @ V - V * w).max() < 1e-12 * scale * max(1, n / 20)
         assert np.abs(V.T @ V - np.eye(n)).max() < 1e-11 * max(1, n / 50)
     if n >= 10:
-        ev = np.concatenate([np.full(3, 0.5), np.linspace(1.0, 2.0, n - 3)])
+        for ev in (np.concatenate([np.full(3, 0.5), np.linspace(1.0, 2.0, n - 3)]),
+                   np.concatenate([0.5 + 1e-9 * np.arange(4), np.linspace(1.0, 2.0, n - 4)])):
+            A = (Qm * ev) @ Qm.T
+            A = 0.5 * (A + A.T)
+            w, V = rw.dense_syev_tridiag(to_dev(A.T, torch.float64))
+            w, V = w.cpu().numpy(), V.cpu().numpy().T
+            np.testing.assert_allclose(w, np.sort(ev), atol=1e-13 * max(1, n / 20))
+            assert np.abs(A @ V - V * w).max() < 1e-12 * max(1, n / 20)
+            assert np.abs(V.T @ V - np.eye(n)).max() < 1e-11 * max(1, n / 50)
+    if n >= 40:
+        ev = np.concatenate([np.full(33, 0.5), np.linspace(1.0, 2.0, n - 33)])
         A = (Qm * ev) @ Qm.T
         with pytest.raises(rw.RWError):
             rw.dense_syev_tridiag(to_dev(0.5 * (A + A.T).T, torch.float64))
@@ -69,7 +80,8 @@ def test_eig_rhs_batched_matches_numpy():
     """The choice-of-m eigenproblem through the tridiagonal form: a batch of Gram matrices of different
     orders inside one leading dimension (entries beyond each order hold garbage that must not be read),
     against numpy: ascending eigenvalues, and V^T R compared through the sign-free products
-    (V^T R)_ic (V^T R)_id; rows beyond each order come back zero.  A clustered spectrum is refused."""
+    (V^T R)_ic (V^T R)_id; rows beyond each order come back zero.  A threefold eigenvalue is solved, more
+    than 32 equal ones are refused."""
     need_gpu()
     banner("eig rhs batched")
     rng = np.random.default_rng(31)
@@ -95,9 +107,24 @@ def test_eig_rhs_batched_matches_numpy():
         for c in range(nrhs):
             for d in range(nrhs):
                 np.testing.assert_allclose(got[:, c] * got[:, d], ref[:, c] * ref[:, d], atol=tol)
+    # a threefold eigenvalue: within the cluster the rotated rows depend on the basis chosen for its subspace,
+    # so their products are compared summed over the cluster (the secular equation uses only those sums)
     Qm, _ = np.linalg.qr(rng.standard_normal((40, 40)))
     ev = np.concatenate([np.full(3, 0.5), np.linspace(1.0, 2.0, 37)])
     C = np.zeros((1, ld, ld))
+    C[0, :40, :40] = ((Qm * ev) @ Qm.T).T
+    w, Rp = rw.dense_eig_rhs_batched(to_dev(C, torch.float64), [40], to_dev(R[:1], torch.float64))
+    w, Rp = w.cpu().numpy()[0], Rp.cpu().numpy()[0]
+    np.testing.assert_allclose(w[:40], np.sort(ev), atol=1e-13)
+    ref = Qm.T @ R[0, :, :40].T
+    ref = ref[np.argsort(ev, kind="stable")]
+    got = Rp[:, :40].T
+    for c in range(nrhs):
+        for d in range(nrhs):
+            np.testing.assert_allclose(got[3:, c] * got[3:, d], ref[3:, c] * ref[3:, d], atol=1e-11)
+            np.testing.assert_allclose((got[:3, c] * got[:3, d]).sum(), (ref[:3, c] * ref[:3, d]).sum(), atol=1e-11)
+    # more than 32 equal eigenvalues: refused (the caller uses the Jacobi solver)
+    ev = np.concatenate([np.full(33, 0.5), np.linspace(1.0, 2.0, 7)])
     C[0, :40, :40] = ((Qm * ev) @ Qm.T).T
     with pytest.raises(rw.RWError):
         rw.dense_eig_rhs_batched(to_dev(C, torch.float64), [40], to_dev(R[:1], torch.float64))
