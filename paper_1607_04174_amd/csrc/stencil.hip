@@ -4,7 +4,8 @@
 // Per node the operator needs the diagonal and the coefficients of its 4/8/6 incident edges:
 // forward edges are stored at the node, backward ones at the neighbour (the edge's tail).
 //
-// Main kernel (k_stencil_strip): each thread owns a strip of R nodes along y (2D) or z (3D) at one x,
+// Main kernel (k_stencil_strip): each thread owns a strip of R nodes along y (2D: 4 in FP32, 2 in FP64) or
+// z (3D: 4) at one x,
 // holds their coefficients in registers, and walks its group of columns.  Per column it loads the
 // strip's centre values plus one row above and below once (register window, so the strip direction's
 // neighbours are not re-read), the x +- 1 values, and in 3D the y +- 1 values; the next column's
@@ -40,7 +41,45 @@ struct StripMap {
 
 __device__ __forceinline__ int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
 
-template <typename T, int NDIR, int R>
+// Buffer loads and stores: a resource based at a column group's first column, the column's byte offset as
+// the scalar offset and the lane's 32-bit node offset as the vector offset, so no per-lane 64-bit address
+// is formed (or kept across the column loop); an offset past the resource reads 0.  Stores are non-temporal.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
+}
+template <typename T> struct Buf;
+template <> struct Buf<float> {
+  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+  }
+  static __device__ __forceinline__ void st(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, vo, so, 2);
+  }
+};
+template <> struct Buf<double> {
+  static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+  }
+  static __device__ __forceinline__ void st(double v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(
+                                              r, vo, so, 0)), v), r, vo, so, 2);
+  }
+};
+
+// ZT: the launch adds gamma Z (the fused Chebyshev step), with Z prefetched in the window like X.  alpha and
+// beta are folded into the per-thread coefficients (diagonal alpha d + beta, off-diagonals alpha c), so a node
+// costs the same multiply-adds in every mode; with alpha = 1 and beta = 0 the arithmetic is the plain operator's.
+// Neighbour offsets are the centre offset plus per-thread deltas (0 at a clamped boundary, whose coefficient is
+// 0).  BUF: buffer loads and stores (about 100 VGPRs for FP32); otherwise global loads and non-temporal stores
+// through 64-bit addresses (the compiler keeps one per load, about 180 VGPRs at R = 4).  Which is faster depends
+// on the mode (measured from HBM, each launch after a 1.25 GiB write and a 512 MiB read, MI355X):
+//   512 x 512 8-conn FP32, 219 columns, plain:  global R = 2 109 us, buffer R = 4 115 us, buffer R = 2 118 us;
+//                                       fused:  buffer R = 4 147 us, global R = 4 149 us, global R = 2 157 us;
+//   128^3 6-conn FP32, 110 columns, plain:      buffer R = 4 491 us, global R = 4 498 us, R = 2 530-545 us;
+//                                   fused:      buffer R = 4 638 us, global R = 4 695 us, R = 2 684-694 us;
+// all with two column groups (one or four were slower).  The 3D kernel runs at the same speed from HBM as from
+// the caches (about 0.48 of 8 TB/s): it is bound by its loads' issue, not by HBM.
+template <typename T, int NDIR, int R, bool ZT, bool BUF>
 __global__ __launch_bounds__(256) void k_stencil_strip(StencilArgs<T> a, StripMap tm) {
   using C = typename Elem<T>::C;
   constexpr bool D3 = NDIR == 3;
@@ -63,15 +102,20 @@ __global__ __launch_bounds__(256) void k_stencil_strip(StencilArgs<T> a, StripMa
   }
   const int plane = nx * ny;
   // window rows p = 0..R+1 are strip positions s0 - 1 .. s0 + R (clamped; their coefficients are 0)
-  uint32_t oc[R + 2], ol[R + 2], orr[R + 2];
+  uint32_t oc[R + 2];
 #pragma unroll
   for (int p = 0; p < R + 2; ++p) {
     const int row = D3 ? nx * y + plane * clampi(s0 + p - 1, nz) : nx * clampi(s0 + p - 1, ny);
     oc[p] = (uint32_t)(x + row) * (uint32_t)sizeof(T);
-    ol[p] = (uint32_t)(clampi(x - 1, nx) + row) * (uint32_t)sizeof(T);
-    orr[p] = (uint32_t)(clampi(x + 1, nx) + row) * (uint32_t)sizeof(T);
   }
-  uint32_t oyp[R], oym[R];
+  const uint32_t es = (uint32_t)sizeof(T);
+  const uint32_t dl = x > 0 ? es : 0u, dr = x + 1 < nx ? es : 0u;   // x - 1 = oc - dl, x + 1 = oc + dr
+  uint32_t dyp = 0, dym = 0;                                        // 3D: y +- 1
+  if constexpr (D3) {
+    dyp = y + 1 < ny ? (uint32_t)nx * es : 0u;
+    dym = y > 0 ? (uint32_t)nx * es : 0u;
+  }
+  const C al = a.alpha, be = a.beta, ga = a.gamma;
   C c[R][2 * NDIR];
   C dg[R];
   bool ok[R];
@@ -83,8 +127,6 @@ __global__ __launch_bounds__(256) void k_stencil_strip(StencilArgs<T> a, StripMa
       zz = s0 + k;
       ok[k] = zz < nz;
       zz = clampi(zz, nz);
-      oyp[k] = (uint32_t)(x + nx * clampi(yy + 1, ny) + plane * zz) * (uint32_t)sizeof(T);
-      oym[k] = (uint32_t)(x + nx * clampi(yy - 1, ny) + plane * zz) * (uint32_t)sizeof(T);
     } else {
       yy = s0 + k;
       zz = 0;
@@ -92,33 +134,48 @@ __global__ __launch_bounds__(256) void k_stencil_strip(StencilArgs<T> a, StripMa
       yy = clampi(yy, ny);
     }
     const int i = x + nx * yy + plane * zz;
-    dg[k] = ok[k] ? (C)a.diag[i] : C(0);
+    dg[k] = ok[k] ? al * (C)a.diag[i] + be : C(0);
 #pragma unroll
     for (int d = 0; d < NDIR; ++d) {
       const int hx = x + a.G.dx[d], hy = yy + a.G.dy[d], hz = zz + a.G.dz[d];
       const bool f = ok[k] && hx >= 0 && hx < nx && hy >= 0 && hy < ny && hz >= 0 && hz < nz;
-      c[k][d] = f ? (C)a.coef[d * N + i] : C(0);
+      c[k][d] = f ? al * (C)a.coef[d * N + i] : C(0);
       const int ux = x - a.G.dx[d], uy = yy - a.G.dy[d], uz = zz - a.G.dz[d];
       const bool t = ok[k] && ux >= 0 && ux < nx && uy >= 0 && uy < ny && uz >= 0 && uz < nz;
-      c[k][NDIR + d] = t ? (C)a.coef[d * N + i - (int)a.G.off[d]] : C(0);
+      c[k][NDIR + d] = t ? al * (C)a.coef[d * N + i - (int)a.G.off[d]] : C(0);
     }
   }
   const int c0 = blockIdx.y * tm.cpg;
   const int c1 = (int)min((int64_t)c0 + tm.cpg, a.b);
   if (c0 >= c1) return;
-  const size_t cs = (size_t)N * sizeof(T);
+  const size_t cs = (size_t)N * sizeof(T);   // the host keeps (cpg - 1) cs + cs below 2^32
+  const __amdgpu_buffer_rsrc_t rx = buf_rsrc(reinterpret_cast<const char*>(a.X) + (size_t)c0 * cs);
+  const __amdgpu_buffer_rsrc_t ry = buf_rsrc(reinterpret_cast<const char*>(a.Y) + (size_t)c0 * cs);
+  const __amdgpu_buffer_rsrc_t rz = buf_rsrc(ZT ? reinterpret_cast<const char*>(a.Z) + (size_t)c0 * cs
+                                                : reinterpret_cast<const char*>(a.X));
   struct Win {
     C cen[R + 2], lf[R + 2], rt[R + 2];
-    C yp[R], ym[R];
+    C yp[D3 ? R : 1], ym[D3 ? R : 1];
+    C z[ZT ? R : 1];
   };
-  auto ld = [](const char* p, uint32_t o) -> C { return (C)*reinterpret_cast<const T*>(p + o); };
-  auto load = [&](Win& w, const char* p) {
+  const char* xg = reinterpret_cast<const char*>(a.X) + (size_t)c0 * cs;
+  const char* zg = ZT ? reinterpret_cast<const char*>(a.Z) + (size_t)c0 * cs : xg;
+  char* yg = reinterpret_cast<char*>(a.Y) + (size_t)c0 * cs;
+  auto ldx = [&](uint32_t so, uint32_t o) -> C {
+    if constexpr (BUF) return (C)Buf<T>::ld(rx, o, so);
+    else return (C)*reinterpret_cast<const T*>(xg + so + o);
+  };
+  auto ldz = [&](uint32_t so, uint32_t o) -> C {
+    if constexpr (BUF) return (C)Buf<T>::ld(rz, o, so);
+    else return (C)*reinterpret_cast<const T*>(zg + so + o);
+  };
+  auto load = [&](Win& w, uint32_t so) {
 #pragma unroll
     for (int q = 0; q < R + 2; ++q) {
-      w.cen[q] = ld(p, oc[q]);
+      w.cen[q] = ldx(so, oc[q]);
       if (DIAG || (q >= 1 && q <= R)) {
-        w.lf[q] = ld(p, ol[q]);
-        w.rt[q] = ld(p, orr[q]);
+        w.lf[q] = ldx(so, oc[q] - dl);
+        w.rt[q] = ldx(so, oc[q] + dr);
       } else {
         w.lf[q] = C(0);
         w.rt[q] = C(0);
@@ -127,19 +184,20 @@ __global__ __launch_bounds__(256) void k_stencil_strip(StencilArgs<T> a, StripMa
     if constexpr (D3) {
 #pragma unroll
       for (int k = 0; k < R; ++k) {
-        w.yp[k] = ld(p, oyp[k]);
-        w.ym[k] = ld(p, oym[k]);
+        w.yp[k] = ldx(so, oc[k + 1] + dyp);
+        w.ym[k] = ldx(so, oc[k + 1] - dym);
       }
     }
+    if constexpr (ZT) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) w.z[k] = ldz(so, oc[k + 1]);
+    }
   };
-  const C al = a.alpha, be = a.beta, ga = a.gamma;
-  const bool useZ = a.Z != nullptr;
-  auto compute = [&](const Win& w, char* q, const char* zc) {
+  auto compute = [&](const Win& w, uint32_t so) {
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int p = k + 1;
-      const C xi = w.cen[p];
-      C acc = dg[k] * xi;
+      C acc = dg[k] * w.cen[p];
       // heads d = 0..NDIR-1, then tails (the edge order the graph defines)
       if constexpr (NDIR == 2) {
         acc -= c[k][0] * w.rt[p];
@@ -163,28 +221,26 @@ __global__ __launch_bounds__(256) void k_stencil_strip(StencilArgs<T> a, StripMa
         acc -= c[k][4] * w.ym[k];
         acc -= c[k][5] * w.cen[p - 1];
       }
-      C out = al * acc;
-      if (be != C(0)) out += be * xi;
-      if (useZ) out += ga * ld(zc, oc[p]);
-      if (ok[k]) __builtin_nontemporal_store((T)out, reinterpret_cast<T*>(q + oc[p]));
+      if constexpr (ZT) acc += ga * w.z[k];
+      if (ok[k]) {
+        if constexpr (BUF) Buf<T>::st((T)acc, ry, oc[p], so);
+        else __builtin_nontemporal_store((T)acc, reinterpret_cast<T*>(yg + so + oc[p]));
+      }
     }
   };
-  const char* xb = reinterpret_cast<const char*>(a.X) + (size_t)c0 * cs;
-  char* yb = reinterpret_cast<char*>(a.Y) + (size_t)c0 * cs;
-  const char* zb = useZ ? reinterpret_cast<const char*>(a.Z) + (size_t)c0 * cs : nullptr;
+  const uint32_t ucs = (uint32_t)cs;
+  uint32_t so = 0;
   Win w0, w1;
-  load(w0, xb);
+  load(w0, 0u);
   int col = c0;
   for (; col + 2 <= c1; col += 2) {
-    load(w1, xb + cs);
-    compute(w0, yb, zb);
-    if (col + 2 < c1) load(w0, xb + 2 * cs);
-    compute(w1, yb + cs, useZ ? zb + cs : nullptr);
-    xb += 2 * cs;
-    yb += 2 * cs;
-    if (useZ) zb += 2 * cs;
+    load(w1, so + ucs);
+    compute(w0, so);
+    if (col + 2 < c1) load(w0, so + 2 * ucs);
+    compute(w1, so + ucs);
+    so += 2 * ucs;
   }
-  if (col < c1) compute(w0, yb, zb);
+  if (col < c1) compute(w0, so);
 }
 
 // one node per thread, all columns, 64-bit indexing (grids whose columns exceed 32-bit byte offsets)
@@ -241,7 +297,14 @@ static StripMap strip_map(const Graph* g, int R, int64_t b, dim3* grid) {
   const int64_t threads = (int64_t)tm.ntiles * 256;
   int G = 1;
   while (G < 8 && threads * G < (int64_t)256 * 1024 && (b + 2 * G - 1) / (2 * G) >= 4) G *= 2;
+  if (threads >= 64 * 1024 && b >= 8) G = 2;   // large grids: two groups (measured best, see the kernel)
   tm.cpg = (int)((b + G - 1) / G);
+  // the buffer offsets of a column group, (cpg - 1) cs + node offsets, stay below 2^32
+  const uint64_t cs = (uint64_t)g->N * dtype_size(g->dtype);
+  while ((uint64_t)tm.cpg * cs >= ((uint64_t)1 << 32)) {
+    G *= 2;
+    tm.cpg = (int)((b + G - 1) / G);
+  }
   tm.per_xcd = (tm.ntiles + 7) / 8;
   *grid = dim3((unsigned)(tm.per_xcd * 8), (unsigned)G);
   return tm;
@@ -263,15 +326,21 @@ static int launch(const Graph* g, const void* X, void* Y, const void* Z, int64_t
   a.beta = (C)beta;
   a.gamma = (C)gamma;
   dim3 block(64, 4);
-  const bool narrow = (uint64_t)g->N * sizeof(T) <= 0xffffffffull && b < (int64_t)1 << 30;
+  const bool narrow = (uint64_t)g->N * sizeof(T) < ((uint64_t)1 << 31) && b < (int64_t)1 << 30;
   if (narrow) {
     dim3 grid;
-    if constexpr (NDIR == 3) {
+    const bool zt = a.Z != nullptr;
+    if constexpr (NDIR == 3) {                       // 3D: buffer loads, four nodes per thread along z
       StripMap tm = strip_map<NDIR>(g, 4, b, &grid);
-      k_stencil_strip<T, NDIR, 4><<<grid, block, 0, s>>>(a, tm);
-    } else {
+      if (zt) k_stencil_strip<T, NDIR, 4, true, true><<<grid, block, 0, s>>>(a, tm);
+      else k_stencil_strip<T, NDIR, 4, false, true><<<grid, block, 0, s>>>(a, tm);
+    } else if (zt && sizeof(T) == 4) {               // 2D fused FP32: buffer loads, four nodes per thread
+      StripMap tm = strip_map<NDIR>(g, 4, b, &grid);
+      k_stencil_strip<T, NDIR, 4, true, true><<<grid, block, 0, s>>>(a, tm);
+    } else {                                         // 2D plain, and FP64: global loads, two nodes per thread
       StripMap tm = strip_map<NDIR>(g, 2, b, &grid);
-      k_stencil_strip<T, NDIR, 2><<<grid, block, 0, s>>>(a, tm);
+      if (zt) k_stencil_strip<T, NDIR, 2, true, false><<<grid, block, 0, s>>>(a, tm);
+      else k_stencil_strip<T, NDIR, 2, false, false><<<grid, block, 0, s>>>(a, tm);
     }
   } else {
     RW_CHECK(g->ny * g->nz < (int64_t)4 * 65535, RW_EINVAL, "grid too tall for the stencil launch");
