@@ -39,6 +39,7 @@ extern "C" {
 #define RW_ESINGULAR (-4)    /* a small dense system has a pivot below its threshold */
 #define RW_EWORKSPACE (-5)   /* the buffer passed is smaller than the query returned */
 #define RW_EHIP (-6)         /* a HIP runtime call failed */
+#define RW_ECAPTURE (-7)     /* a synchronous call on a stream under HIP graph capture (nothing was enqueued) */
 
 /* ---- element types ---- */
 #define RW_F64 0
@@ -196,6 +197,39 @@ int rw_update_eig(rw_graph g, const rw_edit* edits, int n_edits, int mode, const
                   rw_eig_info* info);
 
 /* ======================================================================================
+ * Checkpoint of the offline phase (Sec. II-B: the eigenpairs are computed once, offline)
+ * ====================================================================================== */
+typedef struct {
+  char magic[8];          /* "RWEIGv1" */
+  int32_t version;        /* 1 */
+  int32_t ndim, conn, graph_dtype, weight_form, normalized;
+  int64_t dims[3];
+  double beta;            /* beta of the graph when saved */
+  int32_t m, q_dtype;     /* pairs stored, storage type of Q */
+  double tol;             /* residual tolerance the pairs were computed to (as given by the caller) */
+  uint64_t weight_hash;   /* 64-bit FNV-1a of the FP64 edge weights (ndir x N, 0 where absent) */
+  uint64_t q_bytes, lambda_bytes;
+  int32_t reserved[6];    /* zero */
+} rw_eig_header;
+
+/* Write the eigenpairs (Q: device, column-major N x m of q_dtype; lambda: device, m FP64) of graph g to
+ * the file `path` (created or truncated): the header above, then Q's bytes, then lambda's.  The weight
+ * hash ties the file to g's current operator.  Synchronizes `stream`.  Errors: RW_EINVAL (bad argument,
+ * the file cannot be written), RW_EHIP. */
+int rw_eig_save(rw_graph g, const char* path, const void* Q, int q_dtype, const double* lambda, int m,
+                double tol, hipStream_t stream);
+/* Read and validate a checkpoint's header (host only, no device work).  Errors: RW_EINVAL (cannot open,
+ * not a checkpoint, unsupported version, inconsistent sizes). */
+int rw_eig_read_header(const char* path, rw_eig_header* hdr);
+/* Load the first m (<= stored) pairs of a checkpoint into Q (device, N x m of q_dtype, which must equal the
+ * stored type) and lambda (device, m FP64), after checking that the file was written for this grid,
+ * connectivity and operator form and that the hash of g's current edge weights equals the stored one (a
+ * graph built with another beta, or edited since, is refused).  hdr (host, may be null) receives the
+ * header.  Synchronizes `stream`.  Errors: RW_EINVAL (any mismatch, truncated file), RW_EHIP. */
+int rw_eig_load(rw_graph g, const char* path, void* Q, int q_dtype, double* lambda, int m, hipStream_t stream,
+                rw_eig_header* hdr);
+
+/* ======================================================================================
  * Online random-walker solve in the eigenbasis (Sec. II-B eqs. (7)-(17), gamma = 0 case after
  * eq. (17); choice of m, Sec. III-A1 eq. (24))
  * ====================================================================================== */
@@ -231,6 +265,21 @@ int rw_solve_workspace_bytes(rw_graph g, int m_avail, int64_t S, int C, size_t* 
 int rw_solve_seeds(rw_graph g, const void* Q, int q_dtype, const double* lambda, int m_avail,
                    const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, double eps,
                    void* U, void* work, size_t work_bytes, hipStream_t stream, rw_solve_info* info);
+
+/* RW_ASYNC form of rw_solve_seeds, for streams under HIP graph capture and callers that must not wait:
+ * it only enqueues kernels (no host read, no wait, no memset) and reports through *status (device int32):
+ * RW_OK, or RW_EINVAL (a seed or label out of range, seeds not strictly ascending, a basis column in the
+ * null vector's span), RW_EUNANCHORED or RW_ESINGULAR as rw_solve_seeds would; U is valid only when it is
+ * RW_OK.  Differences from rw_solve_seeds: the seeds are device arrays (seed_node ascending and distinct,
+ * seed_label in [0, C)), m is fixed (no choice of m), and the graph's components must be current
+ * (rw_graph_components after the last build or edit; the call fails with RW_EINVAL otherwise).  work:
+ * at least rw_solve_workspace_bytes(g, m, S, C) bytes.  The same kernels as rw_solve_seeds with eps <= 0 and
+ * m_avail = m give the same results.  A captured graph of this call stays valid while the graph, Q, lambda,
+ * the buffers and S, C and m stay the same; the seed arrays' contents may change between replays.
+ * Errors returned by the call itself (nothing enqueued): RW_EINVAL, RW_EWORKSPACE. */
+int rw_solve_seeds_async(rw_graph g, const void* Q, int q_dtype, const double* lambda, int m,
+                         const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, void* U,
+                         void* work, size_t work_bytes, int32_t* status, hipStream_t stream);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses that
  * forbid allocation): rw_solve_seeds with a fixed m (no choice of m; same kernels, same results as

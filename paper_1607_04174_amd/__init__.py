@@ -18,9 +18,10 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librw.so")
 
-RW_OK, RW_EINVAL, RW_ENOCONV, RW_EUNANCHORED, RW_ESINGULAR, RW_EWORKSPACE, RW_EHIP = 0, -1, -2, -3, -4, -5, -6
+RW_OK, RW_EINVAL, RW_ENOCONV, RW_EUNANCHORED, RW_ESINGULAR, RW_EWORKSPACE, RW_EHIP, RW_ECAPTURE = \
+    0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "RW_OK", -1: "RW_EINVAL", -2: "RW_ENOCONV", -3: "RW_EUNANCHORED", -4: "RW_ESINGULAR",
-                -5: "RW_EWORKSPACE", -6: "RW_EHIP"}
+                -5: "RW_EWORKSPACE", -6: "RW_EHIP", -7: "RW_ECAPTURE"}
 RW_F64, RW_F32, RW_BF16 = 0, 1, 2
 RW_EDIT_SET_BETA, RW_EDIT_SCALE_EDGES, RW_EDIT_SCALE_BOX, RW_EDIT_REMOVE_EDGES = 0, 1, 2, 3
 RW_UPDATE_DIAG_RQ, RW_UPDATE_RR, RW_UPDATE_RR_REFINE = 0, 1, 2
@@ -55,6 +56,14 @@ class rw_edit(ct.Structure):
 class rw_eig_opts(ct.Structure):
     _fields_ = [("tol", ct.c_double), ("max_iter", ct.c_int32), ("degree", ct.c_int32), ("guard", ct.c_int32),
                 ("seed", ct.c_uint64), ("warm", ct.c_int32), ("q_dtype", ct.c_int32)]
+
+
+class rw_eig_header(ct.Structure):
+    _fields_ = [("magic", ct.c_char * 8), ("version", ct.c_int32), ("ndim", ct.c_int32), ("conn", ct.c_int32),
+                ("graph_dtype", ct.c_int32), ("weight_form", ct.c_int32), ("normalized", ct.c_int32),
+                ("dims", ct.c_int64 * 3), ("beta", ct.c_double), ("m", ct.c_int32), ("q_dtype", ct.c_int32),
+                ("tol", ct.c_double), ("weight_hash", ct.c_uint64), ("q_bytes", ct.c_uint64),
+                ("lambda_bytes", ct.c_uint64), ("reserved", ct.c_int32 * 6)]
 
 
 class rw_eig_info(ct.Structure):
@@ -106,6 +115,9 @@ _SIGS = {
     "rw_solve_seeds_noalloc": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p,
                                           ct.c_void_p, ct.c_int64, ct.c_int, ct.c_void_p, ct.c_void_p,
                                           ct.POINTER(rw_solve_info)]),
+    "rw_solve_seeds_async": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p,
+                                        ct.c_void_p, ct.c_int64, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t,
+                                        ct.c_void_p, ct.c_void_p]),
     "rw_dense_syev_workspace_bytes": (ct.c_int, [ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]),
     "rw_dense_syev": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_size_t,
                                  ct.c_void_p]),
@@ -116,6 +128,11 @@ _SIGS = {
     "rw_dense_syev_tridiag": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_size_t,
                                          ct.c_void_p]),
     "rw_dense_lu_solve": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p]),
+    "rw_eig_save": (ct.c_int, [ct.c_void_p, ct.c_char_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_double,
+                               ct.c_void_p]),
+    "rw_eig_read_header": (ct.c_int, [ct.c_char_p, ct.c_void_p]),
+    "rw_eig_load": (ct.c_int, [ct.c_void_p, ct.c_char_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p,
+                               ct.c_void_p]),
     "rw_cg_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_size_t)]),
     "rw_convert_block": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_int64, ct.c_int, ct.c_void_p]),
     "rw_project_workspace_bytes": (ct.c_int, [ct.c_int64, ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]),
@@ -393,6 +410,40 @@ def solve_seeds(g: Graph, Q: torch.Tensor, lam: torch.Tensor, seed_node, seed_la
                "eig_probes": info.eig_probes}
 
 
+def _header_dict(h: rw_eig_header) -> dict:
+    return {"version": h.version, "ndim": h.ndim, "conn": h.conn, "graph_dtype": h.graph_dtype,
+            "weight_form": h.weight_form, "normalized": h.normalized, "dims": tuple(h.dims), "beta": h.beta,
+            "m": h.m, "q_dtype": h.q_dtype, "tol": h.tol, "weight_hash": h.weight_hash}
+
+
+def eig_save(g: Graph, path: str, Q: torch.Tensor, lam: torch.Tensor, tol: float = 0.0) -> None:
+    """Write the eigenpairs (Q: (m, N) = column-major N x m, lam: (m,) float64) of graph g to `path`."""
+    Q = Q.contiguous()
+    lam = lam.to(torch.float64).contiguous()
+    _check(lib().rw_eig_save(g.handle, os.fsencode(path), _ptr(Q), _TORCH_DT[Q.dtype], _ptr(lam), Q.shape[0],
+                             float(tol), _stream(g.device)))
+
+
+def eig_read_header(path: str) -> dict:
+    """The header of a checkpoint (host only)."""
+    h = rw_eig_header()
+    _check(lib().rw_eig_read_header(os.fsencode(path), ct.byref(h)))
+    return _header_dict(h)
+
+
+def eig_load(g: Graph, path: str, m: Optional[int] = None):
+    """Load the first m pairs (all by default) of a checkpoint written for g's current operator.
+    Returns (Q (m, N), lam (m,), header dict)."""
+    hd = eig_read_header(path)
+    m = hd["m"] if m is None else int(m)
+    Q = torch.empty((m, g.N), dtype=_DT_TORCH[hd["q_dtype"]], device=g.device)
+    lam = torch.empty(m, dtype=torch.float64, device=g.device)
+    h = rw_eig_header()
+    _check(lib().rw_eig_load(g.handle, os.fsencode(path), _ptr(Q), hd["q_dtype"], _ptr(lam), m, _stream(g.device),
+                             ct.byref(h)))
+    return Q, lam, _header_dict(h)
+
+
 def solve_seeds_noalloc(g: Graph, Q: torch.Tensor, lam: torch.Tensor, seed_node, seed_label, C: int,
                         m: Optional[int] = None, U: Optional[torch.Tensor] = None):
     """solve_seeds with a fixed m through rw_solve_seeds_noalloc, whose workspace is the library's own device
@@ -407,6 +458,29 @@ def solve_seeds_noalloc(g: Graph, Q: torch.Tensor, lam: torch.Tensor, seed_node,
                                         ct.c_void_p(nodes.ctypes.data), ct.c_void_p(labels.ctypes.data), nodes.size,
                                         C, _ptr(U), _stream(g.device), ct.byref(info)))
     return U, {"m_used": info.m_used, "min_pivot": info.min_pivot}
+
+
+def solve_workspace_bytes(g: Graph, m: int, S: int, C: int) -> int:
+    nb = ct.c_size_t()
+    _check(lib().rw_solve_workspace_bytes(g.handle, int(m), max(int(S), 1), int(C), ct.byref(nb)))
+    return nb.value
+
+
+def solve_seeds_async(g: Graph, Q: torch.Tensor, lam: torch.Tensor, seed_node: torch.Tensor,
+                      seed_label: torch.Tensor, C: int, U: torch.Tensor, work: torch.Tensor, status: torch.Tensor,
+                      m: Optional[int] = None, stream=None) -> None:
+    """rw_solve_seeds_async: enqueue a fixed-m solve whose seeds (int64 nodes, ascending and distinct, and
+    int32 labels) are device tensors; nothing is read back and nothing waits, so the call can be captured
+    into a HIP graph.  status (a device int32 tensor) receives RW_OK or an RW_E* code when the work runs;
+    work is a byte tensor of at least solve_workspace_bytes(g, m, S, C)."""
+    m = Q.shape[0] if m is None else int(m)
+    assert seed_node.dtype == torch.int64 and seed_label.dtype == torch.int32 and status.dtype == torch.int32
+    assert seed_node.is_contiguous() and seed_label.is_contiguous() and U.is_contiguous() and work.is_contiguous()
+    assert seed_node.numel() == seed_label.numel() and U.dtype == g.dtype and tuple(U.shape) == (C, g.N)
+    s = _stream(g.device) if stream is None else ct.c_void_p(stream.cuda_stream)
+    _check(lib().rw_solve_seeds_async(g.handle, _ptr(Q), _TORCH_DT[Q.dtype], _ptr(lam), m, _ptr(seed_node),
+                                      _ptr(seed_label), seed_node.numel(), int(C), _ptr(U), _ptr(work),
+                                      work.numel() * work.element_size(), _ptr(status), s))
 
 
 def cg_solve(g: Graph, seed_node, seed_label, C: int, tol: float = 1e-12, max_iter: int = 100000,

@@ -404,6 +404,7 @@ int rw_batch_workspace_bytes(const rw_batch_image* imgs, int n, size_t* bytes) {
 
 int rw_batch_create(const rw_batch_image* imgs, int n, void* work, size_t work_bytes, hipStream_t stream,
                     rw_batch* out) {
+  RW_NOT_CAPTURING(stream);
   size_t need = 0;
   RW_TRY(rw_batch_workspace_bytes(imgs, n, &need));
   RW_CHECK(work != nullptr && out != nullptr, RW_EINVAL, "null argument");
@@ -478,6 +479,7 @@ int rw_batch_info(rw_batch h, int* threads, int* nodes_per_thread, int* tuned_no
 
 int rw_batch_set_seeds(rw_batch h, const int* C, const int64_t* seed_off, const int64_t* seed_node,
                        const int32_t* seed_label, hipStream_t stream) {
+  RW_NOT_CAPTURING(stream);
   RW_CHECK(h != nullptr && C != nullptr && seed_off != nullptr && seed_node != nullptr && seed_label != nullptr,
            RW_EINVAL, "null argument");
   rw_batch_impl* b = &h->b;
@@ -559,6 +561,7 @@ int rw_batch_enqueue(rw_batch h, hipStream_t stream) {
 }
 
 int rw_batch_status(rw_batch h, double* min_pivot, hipStream_t stream) {
+  RW_NOT_CAPTURING(stream);
   RW_CHECK(h != nullptr && min_pivot != nullptr, RW_EINVAL, "null argument");
   rw_batch_impl* b = &h->b;
   double worst = INFINITY;

@@ -300,12 +300,14 @@ int rw_cg_workspace_bytes(rw_graph h, int C, size_t* bytes) {
 int rw_cg_solve(rw_graph h, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, double tol,
                 int max_iter, int x0_given, double* U, void* work, size_t work_bytes, hipStream_t stream,
                 rw_cg_info* info) {
+  RW_NOT_CAPTURING(stream);
   return cg_core(h, seed_node, seed_label, S, C, nullptr, tol, max_iter, x0_given, U, work, work_bytes, stream, info);
 }
 
 int rw_cg_solve_rhs(rw_graph h, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, const double* B,
                     double tol, int max_iter, int x0_given, double* X, void* work, size_t work_bytes,
                     hipStream_t stream, rw_cg_info* info) {
+  RW_NOT_CAPTURING(stream);
   RW_CHECK(B != nullptr, RW_EINVAL, "null right-hand side");
   return cg_core(h, seed_node, seed_label, S, C, B, tol, max_iter, x0_given, X, work, work_bytes, stream, info);
 }

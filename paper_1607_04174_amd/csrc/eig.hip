@@ -448,6 +448,7 @@ int rw_eig_workspace_bytes(rw_graph h, int m, const rw_eig_opts* opts, size_t* b
 
 int rw_precompute_eig(rw_graph h, int m, const rw_eig_opts* opts, void* Q, double* lambda, void* work,
                       size_t work_bytes, hipStream_t stream, rw_eig_info* info) {
+  RW_NOT_CAPTURING(stream);
   auto t0 = std::chrono::steady_clock::now();
   RW_CHECK(h != nullptr && Q != nullptr && lambda != nullptr && work != nullptr, RW_EINVAL, "null argument");
   const Graph* g = &h->g;
@@ -480,6 +481,7 @@ int rw_update_workspace_bytes(rw_graph h, int m, const rw_eig_opts* opts, size_t
 
 int rw_update_eig(rw_graph h, const rw_edit* edits, int n_edits, int mode, const rw_eig_opts* opts, void* Q,
                   double* lambda, int m, void* work, size_t work_bytes, hipStream_t stream, rw_eig_info* info) {
+  RW_NOT_CAPTURING(stream);
   auto t0 = std::chrono::steady_clock::now();
   RW_CHECK(h != nullptr && Q != nullptr && lambda != nullptr && work != nullptr, RW_EINVAL, "null argument");
   RW_CHECK(mode >= RW_UPDATE_DIAG_RQ && mode <= RW_UPDATE_RR_REFINE, RW_EINVAL, "unknown update mode %d", mode);

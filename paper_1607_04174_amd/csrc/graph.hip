@@ -426,6 +426,39 @@ int anchor_launch(Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, hip
   return RW_OK;
 }
 
+__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_i32(int* p, int64_t n, int v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+int fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s) {
+  if (n <= 0) return RW_OK;
+  k_fill_u8<<<(unsigned)std::min<int64_t>(nblocks(n, 256), 4096), 256, 0, s>>>(p, n, v);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+int fill_i32(int* p, int64_t n, int v, hipStream_t s) {
+  if (n <= 0) return RW_OK;
+  k_fill_i32<<<(unsigned)std::min<int64_t>(nblocks(n, 256), 4096), 256, 0, s>>>(p, n, v);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+int anchor_launch_async(const Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, int* bad_dev, hipStream_t s) {
+  RW_CHECK(g->cc_valid, RW_EINVAL,
+           "the graph's components are not current: call rw_graph_components after the last build or edit");
+  RW_TRY(fill_u8(flags, g->N, 0, s));
+  RW_TRY(fill_i32(bad_dev, 1, 0, s));
+  k_anchor_mark<<<nblocks(std::max<int64_t>(S, 1), 256), 256, 0, s>>>(g->comp, seeds, S, flags);
+  RW_LAUNCH_CHECK();
+  k_anchor_check<<<nblocks(g->N, 256), 256, 0, s>>>(g->comp, flags, g->N, bad_dev);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
 int check_anchored(Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, hipStream_t s) {
   const int* bad_dev = nullptr;
   RW_TRY(anchor_launch(g, seeds, S, flags, s, &bad_dev));
@@ -522,6 +555,7 @@ int rw_graph_get_view(rw_graph h, rw_graph_view* v) {
 }
 
 int rw_graph_components(rw_graph h, int64_t* n_components, hipStream_t stream) {
+  RW_NOT_CAPTURING(stream);
   RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
   Graph* g = &h->g;
   RW_TRY(graph_components(g, stream));
@@ -538,6 +572,7 @@ int rw_graph_components(rw_graph h, int64_t* n_components, hipStream_t stream) {
 }
 
 int rw_edit_graph(rw_graph h, const rw_edit* edits, int n_edits, hipStream_t stream) {
+  RW_NOT_CAPTURING(stream);
   RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
   RW_CHECK(n_edits >= 0 && (n_edits == 0 || edits != nullptr), RW_EINVAL, "bad edit list");
   Graph* g = &h->g;

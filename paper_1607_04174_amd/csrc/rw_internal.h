@@ -113,6 +113,16 @@ int host_stage(size_t bytes, void** p);
 
 #define RW_LAUNCH_CHECK() RW_HIP(hipGetLastError())
 
+// Synchronous entry points wait for their stream or read device values on the host, which a stream under
+// HIP graph capture cannot do: they refuse such a stream up front (nothing is enqueued).
+#define RW_NOT_CAPTURING(stream)                                                                      \
+  do {                                                                                                 \
+    hipStreamCaptureStatus cs_ = hipStreamCaptureStatusNone;                                         \
+    RW_HIP(hipStreamIsCapturing((stream), &cs_));                                                      \
+    RW_CHECK(cs_ == hipStreamCaptureStatusNone, RW_ECAPTURE,                                         \
+             "%s waits for its stream; under HIP graph capture use the RW_ASYNC entry points", __func__); \
+  } while (0)
+
 // ---- workspace carving -------------------------------------------------------------------------
 // A bump allocator over a caller-owned device buffer; every block is 256-byte aligned.  With a null
 // base it only measures.
@@ -233,6 +243,12 @@ int check_anchored(Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, hi
 // the same check queued on the stream without waiting: *bad_dev is the device int that is nonzero when some
 // component holds no seed, valid once the stream reaches this point (kept until the next components call)
 int anchor_launch(Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, hipStream_t s, const int** bad_dev);
+// The anchoring check with kernels only (no memset, no host read; capturable): needs the components current
+// (g->cc_valid, e.g. after rw_graph_components); *bad_dev (device int) ends 1 when a component holds no seed.
+int anchor_launch_async(const Graph* g, const int64_t* seeds, int64_t S, uint8_t* flags, int* bad_dev, hipStream_t s);
+// fill kernels (capturable in place of hipMemsetAsync)
+int fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
+int fill_i32(int* p, int64_t n, int v, hipStream_t s);
 
 // ---- stencil operator --------------------------------------------------------------------------
 // Y = alpha * op(X) + beta * X + gamma * Z   (column-major N x b, graph dtype)

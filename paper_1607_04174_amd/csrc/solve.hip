@@ -1011,6 +1011,35 @@ static int solve_impl(rw_graph h, const void* Q, int q_dtype, const double* lamb
 }
 
 // ---------------------------------------------------------------------------------------------
+// Asynchronous variant (fixed m, seeds on the device): kernels only, no host read, no wait, no memset, so a
+// caller can capture it into a HIP graph.  The caller's seeds are copied into the workspace with any entry
+// out of range (node or label) replaced by 0, so no later kernel can index outside its arrays; such a
+// seed, or seeds not strictly ascending, set a flag.  The last kernel writes the status word.
+// ---------------------------------------------------------------------------------------------
+__global__ void k_sanitize_seeds(const int64_t* node, const int32_t* label, int64_t S, int64_t N, int C,
+                                 int64_t* node_out, int32_t* label_out, int* bad) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= S) return;
+  const int64_t v = node[k];
+  const int32_t l = label[k];
+  const bool ok = v >= 0 && v < N && l >= 0 && l < C && (k == 0 || node[k - 1] < v);
+  node_out[k] = (v >= 0 && v < N) ? v : 0;
+  label_out[k] = (l >= 0 && l < C) ? l : 0;
+  if (!ok) *bad = 1;
+}
+
+// status word: invalid seeds, then an unanchored component, then a basis column in the null vector's span,
+// then a singular reduced system, else RW_OK
+__global__ void k_solve_status(const int* flags, const double* stat, int32_t* status) {
+  int st = RW_OK;
+  if (flags[1]) st = RW_EINVAL;
+  else if (flags[2]) st = RW_EUNANCHORED;
+  else if (flags[0]) st = RW_EINVAL;
+  else if (!(stat[0] > 0.0)) st = RW_ESINGULAR;
+  *status = st;
+}
+
+// ---------------------------------------------------------------------------------------------
 // Allocation-free variant (fixed m): the workspace lives in `scratch`, a file-scope device array that each
 // GPU holds from module load to process end.  Host code never passes `scratch` itself (its name is a host
 // stand-in there): the first call on a device, with that device current, takes its device address with
@@ -1055,6 +1084,7 @@ extern "C" {
 int rw_solve_seeds_noalloc(rw_graph h, const void* Q, int q_dtype, const double* lambda, int m,
                            const int64_t* seed_node, const int32_t* seed_label, int64_t S_in, int C, void* U,
                            hipStream_t stream, rw_solve_info* info) {
+  RW_NOT_CAPTURING(stream);
   RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
   const Graph* g = &h->g;
   RW_CHECK(Q != nullptr && lambda != nullptr && U != nullptr, RW_EINVAL, "null pointer argument");
@@ -1081,6 +1111,55 @@ int rw_solve_seeds_noalloc(rw_graph h, const void* Q, int q_dtype, const double*
   return st;
 }
 
+int rw_solve_seeds_async(rw_graph h, const void* Q, int q_dtype, const double* lambda, int m,
+                         const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, void* U, void* work,
+                         size_t work_bytes, int32_t* status, hipStream_t stream) {
+  RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
+  const Graph* g = &h->g;
+  RW_CHECK(Q != nullptr && lambda != nullptr && U != nullptr && work != nullptr && status != nullptr &&
+               seed_node != nullptr && seed_label != nullptr,
+           RW_EINVAL, "null pointer argument");
+  RW_CHECK(q_dtype == RW_F64 || q_dtype == RW_F32 || q_dtype == RW_BF16, RW_EINVAL, "bad Q dtype");
+  RW_CHECK(m >= 2 && m <= g->N, RW_EINVAL, "m = %d out of range", m);
+  RW_CHECK(S >= 1 && S < g->N, RW_EINVAL, "S = %lld out of range", (long long)S);
+  RW_CHECK(C >= 1 && C <= 255, RW_EINVAL, "C must be in [1, 255] (got %d)", C);
+  RW_CHECK(g->cc_valid, RW_EINVAL,
+           "the graph's components are not current: call rw_graph_components after the last build or edit");
+  SolveWork w;
+  const size_t need = solve_layout(g, m, S, C, work, &w, false);
+  RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "solve workspace too small: %zu < %zu", work_bytes, need);
+  int* flags = w.nbad;   // [0] basis column in the null span, [1] invalid seeds, [2] unanchored
+  RW_TRY(fill_i32(flags, 3, 0, stream));
+  k_sanitize_seeds<<<nblocks(S, 256), 256, 0, stream>>>(seed_node, seed_label, S, g->N, C, w.seeds, w.labels,
+                                                        flags + 1);
+  RW_LAUNCH_CHECK();
+  RW_TRY(anchor_launch_async(g, w.seeds, S, w.anc, flags + 2, stream));
+  k_clear_map<<<nblocks(g->N, 256), 256, 0, stream>>>(w.map, g->N);
+  RW_LAUNCH_CHECK();
+  k_set_map<<<nblocks(S, 256), 256, 0, stream>>>(w.map, w.seeds, w.labels, S);
+  RW_LAUNCH_CHECK();
+  const GridDev G = grid_of(g);
+#define RW_GATHER(TQ)                                                                                    \
+  k_seed_gather<TQ><<<(unsigned)S, 256, 0, stream>>>(G, g->normalized, (const TQ*)Q, m, w.seeds, w.map, g->weight, \
+                                                     g->degree, g->sums, S, C, w.Qs, w.GB, w.Hs, w.Us, w.gs, w.Bg)
+  if (q_dtype == RW_F64) RW_GATHER(double);
+  else if (q_dtype == RW_F32) RW_GATHER(float);
+  else RW_GATHER(uint16_t);
+#undef RW_GATHER
+  RW_LAUNCH_CHECK();
+  RW_TRY(null_stats(g, Q, q_dtype, m, w.npart, w.cn, flags, stream));
+  k_seed_correct<<<nblocks(S * m, 256), 256, 0, stream>>>(w.Qs, w.GB, w.gs, w.Bg, w.cn, S, m);
+  RW_LAUNCH_CHECK();
+  k_reduced<<<nblocks((int64_t)m * (m + C), 256), 256, 0, stream>>>(m, C, S, w.Qs, w.GB, w.Hs, lambda, w.K, w.Y);
+  RW_LAUNCH_CHECK();
+  RW_TRY(lu_solve(w.K, m, w.Y, C, w.stat, stream));
+  RW_TRY(solve_coeffs(w.Y, m, C, w.cn, g, stream));
+  RW_TRY(reconstruct(g, Q, q_dtype, m, w.Y, C, w.map, U, stream));
+  k_solve_status<<<1, 1, 0, stream>>>(flags, w.stat, status);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
 int rw_solve_workspace_bytes(rw_graph h, int m_avail, int64_t S, int C, size_t* bytes) {
   RW_CHECK(h != nullptr && bytes != nullptr, RW_EINVAL, "null argument");
   RW_CHECK(m_avail >= 2 && S >= 1 && C >= 1, RW_EINVAL, "bad sizes");
@@ -1091,6 +1170,7 @@ int rw_solve_workspace_bytes(rw_graph h, int m_avail, int64_t S, int C, size_t* 
 int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda, int m_avail,
                    const int64_t* seed_node, const int32_t* seed_label, int64_t S_in, int C, double eps, void* U,
                    void* work, size_t work_bytes, hipStream_t stream, rw_solve_info* info) {
+  RW_NOT_CAPTURING(stream);
   RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
   const Graph* g = &h->g;
   RW_CHECK(Q != nullptr && lambda != nullptr && U != nullptr && work != nullptr, RW_EINVAL, "null pointer argument");

@@ -884,6 +884,7 @@ int rw_dense_syev_tridiag_workspace_bytes(int n, size_t* bytes) {
 
 int rw_dense_syev_tridiag(const double* A, double* w, double* V, int n, void* work, size_t work_bytes,
                           hipStream_t stream) {
+  RW_NOT_CAPTURING(stream);
   RW_CHECK(A != nullptr && w != nullptr && V != nullptr && work != nullptr, RW_EINVAL, "null argument");
   RW_CHECK(tridiag_fits(n), RW_EINVAL, "tridiagonal eigensolver: n = %d out of range [3, 256]", n);
   RW_CHECK(work_bytes >= tridiag_work_count(n) * sizeof(double), RW_EWORKSPACE, "workspace too small");
@@ -901,6 +902,7 @@ int rw_dense_eig_rhs_batched_workspace_bytes(int nmax, int count, int nrhs, size
 
 int rw_dense_eig_rhs_batched(const double* A, int ld, const int* sizes, int count, double* R, int nrhs, double* w,
                              void* work, size_t work_bytes, hipStream_t stream) {
+  RW_NOT_CAPTURING(stream);
   RW_CHECK(A != nullptr && sizes != nullptr && R != nullptr && w != nullptr && work != nullptr, RW_EINVAL,
            "null argument");
   const int st = syev_tridiag_rhs(A, ld, sizes, count, R, nrhs, w, static_cast<double*>(work),

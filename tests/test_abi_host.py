@@ -52,3 +52,30 @@ def test_host_validation_without_device():
     d.dims[2] = 2
     assert L.rw_graph_bytes(ct.byref(d), ct.byref(nb)) == rw.RW_EINVAL
     assert L.rw_version() >= 1
+
+
+def test_checkpoint_header_is_validated_on_the_host(tmp_path):
+    """rw_eig_read_header reads and checks a checkpoint's header without touching a device: a missing file,
+    a foreign file and inconsistent sizes are refused; a well-formed header comes back field by field."""
+    import paper_1607_04174_amd as rw
+    with pytest.raises(rw.RWError):
+        rw.eig_read_header(str(tmp_path / "missing.rweig"))
+    bad = tmp_path / "garbage.rweig"
+    bad.write_bytes(b"not a checkpoint" * 16)
+    with pytest.raises(rw.RWError):
+        rw.eig_read_header(str(bad))
+    h = rw.rw_eig_header()
+    assert ct.sizeof(h) == 128
+    h.magic = b"RWEIGv1"
+    h.version, h.ndim, h.conn, h.graph_dtype, h.weight_form, h.normalized = 1, 2, 4, 1, 0, 1
+    h.dims[0], h.dims[1], h.dims[2] = 7, 5, 1
+    h.beta, h.m, h.q_dtype, h.tol, h.weight_hash = 90.0, 3, 1, 1e-5, 12345
+    h.q_bytes, h.lambda_bytes = 35 * 3 * 4, 3 * 8
+    good = tmp_path / "good.rweig"
+    good.write_bytes(bytes(h) + bytes(35 * 3 * 4 + 3 * 8))
+    d = rw.eig_read_header(str(good))
+    assert (d["dims"], d["m"], d["q_dtype"], d["beta"], d["weight_hash"]) == ((7, 5, 1), 3, 1, 90.0, 12345)
+    h.q_bytes += 4                                    # sizes that do not match the grid
+    good.write_bytes(bytes(h))
+    with pytest.raises(rw.RWError):
+        rw.eig_read_header(str(good))
