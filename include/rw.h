@@ -45,6 +45,15 @@ extern "C" {
 #define RW_F64 0
 #define RW_F32 1
 #define RW_BF16 2
+/* BF16 pair form of an eigenbasis (rw_convert_block, rw_solve_seeds*, checkpoints): a column-major
+ * N x (RW_PAIR_COLS + m) BF16 block whose first RW_PAIR_COLS columns hold the rounding remainders
+ * bf16(q_j - bf16(q_j)) of columns j = 1 .. RW_PAIR_COLS (zero where j >= m) and whose last m columns are
+ * the plain BF16 copy bf16(q_j), j = 0 .. m-1.  Column j <= RW_PAIR_COLS is read as hi + lo (about 16
+ * significant bits); the others as BF16.  The low-index columns carry the largest coefficients of the
+ * online solve, so the remainder columns remove most of the BF16 rounding error of the maps for 8 extra
+ * columns of traffic.  The plain BF16 block starts at column RW_PAIR_COLS. */
+#define RW_BF16_PAIR 3
+#define RW_PAIR_COLS 8
 
 /* ---- edge-weight forms (Sec. II-A, eq. (2)) ---- */
 #define RW_WEIGHT_SQUARED 0  /* w = s_e * exp(-beta (J_i - J_j)^2) (default) */
@@ -212,7 +221,8 @@ typedef struct {
   int32_t reserved[6];    /* zero */
 } rw_eig_header;
 
-/* Write the eigenpairs (Q: device, column-major N x m of q_dtype; lambda: device, m FP64) of graph g to
+/* Write the eigenpairs (Q: device, column-major N x m of q_dtype, or the N x (RW_PAIR_COLS + m) pair form;
+ * lambda: device, m FP64) of graph g to
  * the file `path` (created or truncated): the header above, then Q's bytes, then lambda's.  The weight
  * hash ties the file to g's current operator.  Synchronizes `stream`.  Errors: RW_EINVAL (bad argument,
  * the file cannot be written), RW_EHIP. */
@@ -221,7 +231,8 @@ int rw_eig_save(rw_graph g, const char* path, const void* Q, int q_dtype, const 
 /* Read and validate a checkpoint's header (host only, no device work).  Errors: RW_EINVAL (cannot open,
  * not a checkpoint, unsupported version, inconsistent sizes). */
 int rw_eig_read_header(const char* path, rw_eig_header* hdr);
-/* Load the first m (<= stored) pairs of a checkpoint into Q (device, N x m of q_dtype, which must equal the
+/* Load the first m (<= stored) pairs of a checkpoint into Q (device, N x m of q_dtype, or the pair form's
+ * N x (RW_PAIR_COLS + m); q_dtype must equal the
  * stored type) and lambda (device, m FP64), after checking that the file was written for this grid,
  * connectivity and operator form and that the hash of g's current edge weights equals the stored one (a
  * graph built with another beta, or edited since, is refused).  hdr (host, may be null) receives the
@@ -244,7 +255,8 @@ typedef struct {
 int rw_solve_workspace_bytes(rw_graph g, int m_avail, int64_t S, int C, size_t* bytes);
 
 /* Label probabilities of the gamma = 0 random walker from the stored pairs (Q, lambda):
- *   Q        device, column-major N x (>= m_avail) of q_dtype (RW_F64, RW_F32 or RW_BF16) with
+ *   Q        device, column-major N x (>= m_avail) of q_dtype (RW_F64, RW_F32 or RW_BF16), or the
+ *            N x (RW_PAIR_COLS + (>= m_avail)) BF16 pair form (q_dtype RW_BF16_PAIR), with
  *            column 0 the graph's unit null vector and the other columns orthogonal to it (as
  *            rw_precompute_eig / rw_update_eig return them); lambda device FP64, lambda[0] = 0;
  *   seeds    host arrays seed_node[S] (0 <= node < N) and seed_label[S] (0 <= label < C); any order;
@@ -356,7 +368,9 @@ int rw_spectral_apply(rw_graph g, const double* Q, const double* lambda, int m, 
 /* Convert a column-major rows x cols block between RW_F64 / RW_F32 / RW_BF16 (round to nearest even;
  * device buffers, src != dst).  Used to make the BF16 copy of Q that rw_solve_seeds reads with
  * q_dtype = RW_BF16: its reconstruction U = D^{-1/2} Q Y then runs on the matrix cores
- * (v_mfma_f32_16x16x16bf16, FP32 accumulation; Y split into two BF16 parts) for C <= 8. */
+ * (v_mfma_f32_16x16x16bf16, FP32 accumulation; Y split into two BF16 parts) for C <= 8.
+ * dst_dtype = RW_BF16_PAIR (src RW_F64 or RW_F32) writes the pair form: dst holds
+ * rows x (RW_PAIR_COLS + cols) BF16 values. */
 int rw_convert_block(const void* src, int src_dtype, void* dst, int dst_dtype, int64_t rows, int cols,
                      hipStream_t stream);
 
@@ -380,7 +394,7 @@ typedef struct {
   const void* Q;         /* device column-major N x m basis of q_dtype (column 0 the null vector); with the
                             graph, fixed for the batch's lifetime (rw_batch_create takes the constants
                             of its FP64 form, as rw_solve_seeds does per call) */
-  int32_t q_dtype;       /* RW_F64, RW_F32 or RW_BF16 (all images: one q_dtype) */
+  int32_t q_dtype;       /* RW_F64, RW_F32 or RW_BF16 (all images: one q_dtype; not the pair form) */
   const double* lambda;  /* device FP64, m eigenvalues, lambda[0] = 0 */
   int32_t m;             /* pairs used (no choice of m in the batched form), 2 <= m <= min(N, 1024) */
   int64_t S_cap;         /* most distinct seeds this image will get in any round */

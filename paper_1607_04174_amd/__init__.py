@@ -22,7 +22,8 @@ RW_OK, RW_EINVAL, RW_ENOCONV, RW_EUNANCHORED, RW_ESINGULAR, RW_EWORKSPACE, RW_EH
     0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "RW_OK", -1: "RW_EINVAL", -2: "RW_ENOCONV", -3: "RW_EUNANCHORED", -4: "RW_ESINGULAR",
                 -5: "RW_EWORKSPACE", -6: "RW_EHIP", -7: "RW_ECAPTURE"}
-RW_F64, RW_F32, RW_BF16 = 0, 1, 2
+RW_F64, RW_F32, RW_BF16, RW_BF16_PAIR = 0, 1, 2, 3
+RW_PAIR_COLS = 8
 RW_EDIT_SET_BETA, RW_EDIT_SCALE_EDGES, RW_EDIT_SCALE_BOX, RW_EDIT_REMOVE_EDGES = 0, 1, 2, 3
 RW_UPDATE_DIAG_RQ, RW_UPDATE_RR, RW_UPDATE_RR_REFINE = 0, 1, 2
 
@@ -403,7 +404,7 @@ def solve_seeds(g: Graph, Q: torch.Tensor, lam: torch.Tensor, seed_node, seed_la
     _check(lib().rw_solve_workspace_bytes(g.handle, m_avail, max(S, 1), C, ct.byref(nb)))
     work = (workspace or SolveWorkspace()).get(nb.value, g.device)
     info = rw_solve_info()
-    _check(lib().rw_solve_seeds(g.handle, _ptr(Q), _TORCH_DT[Q.dtype], _ptr(lam), m_avail,
+    _check(lib().rw_solve_seeds(g.handle, *_qarg(Q), _ptr(lam), m_avail,
                                 ct.c_void_p(nodes.ctypes.data), ct.c_void_p(labels.ctypes.data), S, C, float(eps),
                                 _ptr(U), _ptr(work), work.numel(), _stream(g.device), ct.byref(info)))
     return U, {"m_used": info.m_used, "f_max": info.f_max, "f_worst": info.f_worst, "min_pivot": info.min_pivot,
@@ -417,11 +418,13 @@ def _header_dict(h: rw_eig_header) -> dict:
 
 
 def eig_save(g: Graph, path: str, Q: torch.Tensor, lam: torch.Tensor, tol: float = 0.0) -> None:
-    """Write the eigenpairs (Q: (m, N) = column-major N x m, lam: (m,) float64) of graph g to `path`."""
-    Q = Q.contiguous()
+    """Write the eigenpairs (Q: (m, N) = column-major N x m, or a PairBasis; lam: (m,) float64) of graph g
+    to `path`."""
+    if not isinstance(Q, PairBasis):
+        Q = Q.contiguous()
     lam = lam.to(torch.float64).contiguous()
-    _check(lib().rw_eig_save(g.handle, os.fsencode(path), _ptr(Q), _TORCH_DT[Q.dtype], _ptr(lam), Q.shape[0],
-                             float(tol), _stream(g.device)))
+    _check(lib().rw_eig_save(g.handle, os.fsencode(path), *_qarg(Q), _ptr(lam), Q.shape[0], float(tol),
+                             _stream(g.device)))
 
 
 def eig_read_header(path: str) -> dict:
@@ -433,14 +436,18 @@ def eig_read_header(path: str) -> dict:
 
 def eig_load(g: Graph, path: str, m: Optional[int] = None):
     """Load the first m pairs (all by default) of a checkpoint written for g's current operator.
-    Returns (Q (m, N), lam (m,), header dict)."""
+    Returns (Q (m, N) tensor, or a PairBasis for the pair form; lam (m,); header dict)."""
     hd = eig_read_header(path)
     m = hd["m"] if m is None else int(m)
-    Q = torch.empty((m, g.N), dtype=_DT_TORCH[hd["q_dtype"]], device=g.device)
+    pair = hd["q_dtype"] == RW_BF16_PAIR
+    if pair:
+        Q = PairBasis(torch.empty((RW_PAIR_COLS + m, g.N), dtype=torch.bfloat16, device=g.device))
+    else:
+        Q = torch.empty((m, g.N), dtype=_DT_TORCH[hd["q_dtype"]], device=g.device)
     lam = torch.empty(m, dtype=torch.float64, device=g.device)
     h = rw_eig_header()
-    _check(lib().rw_eig_load(g.handle, os.fsencode(path), _ptr(Q), hd["q_dtype"], _ptr(lam), m, _stream(g.device),
-                             ct.byref(h)))
+    _check(lib().rw_eig_load(g.handle, os.fsencode(path), _qarg(Q)[0], hd["q_dtype"], _ptr(lam), m,
+                             _stream(g.device), ct.byref(h)))
     return Q, lam, _header_dict(h)
 
 
@@ -454,7 +461,7 @@ def solve_seeds_noalloc(g: Graph, Q: torch.Tensor, lam: torch.Tensor, seed_node,
     if U is None:
         U = torch.empty((C, g.N), dtype=g.dtype, device=g.device)
     info = rw_solve_info()
-    _check(lib().rw_solve_seeds_noalloc(g.handle, _ptr(Q), _TORCH_DT[Q.dtype], _ptr(lam), m,
+    _check(lib().rw_solve_seeds_noalloc(g.handle, *_qarg(Q), _ptr(lam), m,
                                         ct.c_void_p(nodes.ctypes.data), ct.c_void_p(labels.ctypes.data), nodes.size,
                                         C, _ptr(U), _stream(g.device), ct.byref(info)))
     return U, {"m_used": info.m_used, "min_pivot": info.min_pivot}
@@ -478,7 +485,7 @@ def solve_seeds_async(g: Graph, Q: torch.Tensor, lam: torch.Tensor, seed_node: t
     assert seed_node.is_contiguous() and seed_label.is_contiguous() and U.is_contiguous() and work.is_contiguous()
     assert seed_node.numel() == seed_label.numel() and U.dtype == g.dtype and tuple(U.shape) == (C, g.N)
     s = _stream(g.device) if stream is None else ct.c_void_p(stream.cuda_stream)
-    _check(lib().rw_solve_seeds_async(g.handle, _ptr(Q), _TORCH_DT[Q.dtype], _ptr(lam), m, _ptr(seed_node),
+    _check(lib().rw_solve_seeds_async(g.handle, *_qarg(Q), _ptr(lam), m, _ptr(seed_node),
                                       _ptr(seed_label), seed_node.numel(), int(C), _ptr(U), _ptr(work),
                                       work.numel() * work.element_size(), _ptr(status), s))
 
@@ -668,6 +675,52 @@ def random_walker(J, beta, scale, dims, conn, seed_node, seed_label, C, Q=None, 
 # ---------------------------------------------------------------------------------------------
 # precision form
 # ---------------------------------------------------------------------------------------------
+class PairBasis:
+    """The BF16 pair form of an eigenbasis: `data` is a (RW_PAIR_COLS + m, N) bfloat16 tensor (column-major
+    N x (RW_PAIR_COLS + m)) holding the rounding remainders of columns 1 .. RW_PAIR_COLS, then the plain BF16
+    copy.  Accepted wherever a basis Q of shape (m, N) is."""
+
+    def __init__(self, data: torch.Tensor):
+        if data.dtype != torch.bfloat16 or data.dim() != 2 or data.shape[0] <= RW_PAIR_COLS:
+            raise ValueError("a pair form is a (RW_PAIR_COLS + m, N) bfloat16 tensor")
+        self.data = data.contiguous()
+
+    @property
+    def shape(self):
+        return (self.data.shape[0] - RW_PAIR_COLS, self.data.shape[1])
+
+    @property
+    def device(self):
+        return self.data.device
+
+    def plain(self) -> torch.Tensor:
+        """The plain BF16 block (m, N) (a view)."""
+        return self.data[RW_PAIR_COLS:]
+
+    def value(self) -> torch.Tensor:
+        """The basis the pair form represents, hi + lo, as float64 (m, N) (analysis and tests)."""
+        v = self.plain().double()
+        k = min(RW_PAIR_COLS, v.shape[0] - 1)
+        v[1:1 + k] += self.data[:k].double()
+        return v
+
+
+def _qarg(Q):
+    """(pointer, dtype code) of a basis argument: a tensor or a PairBasis."""
+    if isinstance(Q, PairBasis):
+        return _ptr(Q.data), RW_BF16_PAIR
+    return _ptr(Q), _TORCH_DT[Q.dtype]
+
+
+def to_pair(Q: torch.Tensor) -> PairBasis:
+    """The BF16 pair form of a float64 / float32 basis Q (m, N), made by the library."""
+    Q = Q.contiguous()
+    m, N = Q.shape
+    out = torch.empty((RW_PAIR_COLS + m, N), dtype=torch.bfloat16, device=Q.device)
+    _check(lib().rw_convert_block(_ptr(Q), _TORCH_DT[Q.dtype], _ptr(out), RW_BF16_PAIR, N, m, _stream(Q.device)))
+    return PairBasis(out)
+
+
 def convert_block(X: torch.Tensor, dtype) -> torch.Tensor:
     """Copy of a (cols, rows) block (column-major rows x cols) converted by the library (RNE)."""
     X = X.contiguous()

@@ -165,8 +165,8 @@ __global__ void k_b_gather(const BatchImg* D, const int64_t* node, const int32_t
   const int64_t gk = blockIdx.x;
   if (gk >= *total) return;
   const BatchImg& d = D[img[gk]];
-  gather_seed_row<TQ>(d.G, d.normalized, d.weight, d.degree, d.sums, static_cast<const TQ*>(d.Q), d.m, d.map, node[gk],
-                      d.C, d.cn, gk - d.seed_off, d.S_cap, d.Qs, d.GB, d.Hs, d.Us, nullptr, nullptr);
+  gather_seed_row<TQ>(d.G, d.normalized, d.weight, d.degree, d.sums, static_cast<const TQ*>(d.Q), nullptr, d.m, d.map,
+                      node[gk], d.C, d.cn, gk - d.seed_off, d.S_cap, d.Qs, d.GB, d.Hs, d.Us, nullptr, nullptr);
 }
 
 // T = Q_s^T GB and R = Q_s^T Hs per image (FP64, summed over the image's S seeds in order), then
@@ -410,6 +410,8 @@ int rw_batch_create(const rw_batch_image* imgs, int n, void* work, size_t work_b
   RW_CHECK(work != nullptr && out != nullptr, RW_EINVAL, "null argument");
   RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "batch workspace too small: %zu < %zu", work_bytes, need);
   const int gdt = imgs[0].g->g.dtype, qdt = imgs[0].q_dtype;
+  RW_CHECK(qdt == RW_F64 || qdt == RW_F32 || qdt == RW_BF16, RW_EINVAL,
+           "the batched solve takes RW_F64, RW_F32 or RW_BF16 bases (pass a pair form's plain block with RW_BF16)");
   for (int i = 0; i < n; ++i) {
     const rw_batch_image& im = imgs[i];
     RW_CHECK(im.g->g.dtype == gdt && im.q_dtype == qdt, RW_EINVAL, "all images need the same graph and Q types");

@@ -1014,6 +1014,32 @@ int convert_block(int dt_src, const void* src, int64_t lds, int dt_dst, void* ds
   return convert_from((const uint16_t*)src, lds, dt_dst, dst, ldd, rows, cols, s);
 }
 
+// pair form: thread (r, c) writes hi = bf16(q_c) to column kPairCols + c and, for 1 <= c <= kPairCols, the
+// remainder bf16(q_c - hi) (formed in the source precision) to column c - 1; column c = 0 also zeroes the
+// remainder columns of q_j with j >= cols
+template <typename S>
+__global__ void k_convert_pair(const S* src, int64_t rows, int cols, uint16_t* dst) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= rows || c >= cols) return;
+  const S v = src[(int64_t)c * rows + r];
+  const uint16_t hi = f32_to_bf16((float)v);
+  dst[(int64_t)(kPairCols + c) * rows + r] = hi;
+  if (c >= 1 && c <= kPairCols) dst[(int64_t)(c - 1) * rows + r] = f32_to_bf16((float)(v - (S)bf16_to_f32(hi)));
+  if (c == 0)
+    for (int j = cols > 1 ? cols : 1; j <= kPairCols; ++j) dst[(int64_t)(j - 1) * rows + r] = 0;
+}
+
+int convert_pair(int dt_src, const void* src, int64_t rows, uint16_t* dst, int cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return RW_OK;
+  RW_CHECK(cols <= 65535, RW_EINVAL, "too many columns to convert");
+  const dim3 grid(nblocks(rows, 256), cols);
+  if (dt_src == RW_F64) k_convert_pair<double><<<grid, 256, 0, s>>>((const double*)src, rows, cols, dst);
+  else k_convert_pair<float><<<grid, 256, 0, s>>>((const float*)src, rows, cols, dst);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
 // ---------------------------------------------------------------------------------------------
 // residual norms ||A_j - theta_j B_j|| in FP64, deterministic (per-column block partials)
 // ---------------------------------------------------------------------------------------------

@@ -1,6 +1,7 @@
 // Checkpoint of the offline phase (Sec. II-B: the eigenpairs are computed once, offline, and every online
 // solve and update starts from them).  A file holds a fixed header and the raw eigenpairs:
-//   rw_eig_header (128 bytes, little-endian) | Q (N x m column-major, q_dtype) | lambda (m FP64)
+//   rw_eig_header (128 bytes, little-endian) | Q (N x m column-major, q_dtype; N x (8 + m) BF16 for the
+//   pair form) | lambda (m FP64)
 // The header records the grid, the operator's form and a 64-bit FNV-1a hash of the FP64 edge weights
 // (ndir x N, 0 where an edge is absent), so a basis is loaded only into a graph whose operator it was
 // computed for.
@@ -40,11 +41,12 @@ static int read_header(FILE* f, const char* path, rw_eig_header* hdr) {
   RW_CHECK(std::memcmp(hdr->magic, kMagic, sizeof(kMagic)) == 0, RW_EINVAL, "%s: not an eigenpair checkpoint",
            path);
   RW_CHECK(hdr->version == 1, RW_EINVAL, "%s: checkpoint version %d is not supported", path, hdr->version);
-  RW_CHECK(hdr->m >= 1 && (hdr->q_dtype == RW_F64 || hdr->q_dtype == RW_F32 || hdr->q_dtype == RW_BF16) &&
+  RW_CHECK(hdr->m >= 1 && q_dtype_ok(hdr->q_dtype) &&
                hdr->dims[0] >= 1 && hdr->dims[1] >= 1 && hdr->dims[2] >= 1,
            RW_EINVAL, "%s: corrupt checkpoint header", path);
   const uint64_t N = (uint64_t)hdr->dims[0] * hdr->dims[1] * hdr->dims[2];
-  RW_CHECK(hdr->q_bytes == N * hdr->m * dtype_size(hdr->q_dtype) && hdr->lambda_bytes == (uint64_t)hdr->m * 8,
+  RW_CHECK(hdr->q_bytes == N * q_block_cols(hdr->q_dtype, hdr->m) * dtype_size(hdr->q_dtype) &&
+               hdr->lambda_bytes == (uint64_t)hdr->m * 8,
            RW_EINVAL, "%s: corrupt checkpoint header (sizes)", path);
   return RW_OK;
 }
@@ -66,7 +68,7 @@ int rw_eig_save(rw_graph h, const char* path, const void* Q, int q_dtype, const 
                 hipStream_t stream) {
   RW_NOT_CAPTURING(stream);
   RW_CHECK(h != nullptr && path != nullptr && Q != nullptr && lambda != nullptr, RW_EINVAL, "null argument");
-  RW_CHECK(q_dtype == RW_F64 || q_dtype == RW_F32 || q_dtype == RW_BF16, RW_EINVAL, "bad Q dtype");
+  RW_CHECK(q_dtype_ok(q_dtype), RW_EINVAL, "bad Q dtype");
   const Graph* g = &h->g;
   RW_CHECK(m >= 1 && m <= g->N, RW_EINVAL, "m = %d out of range", m);
   rw_eig_header hdr;
@@ -86,7 +88,7 @@ int rw_eig_save(rw_graph h, const char* path, const void* Q, int q_dtype, const 
   hdr.q_dtype = q_dtype;
   hdr.tol = tol;
   RW_TRY(weight_hash(g, stream, &hdr.weight_hash));
-  hdr.q_bytes = (uint64_t)g->N * m * dtype_size(q_dtype);
+  hdr.q_bytes = (uint64_t)g->N * q_block_cols(q_dtype, m) * dtype_size(q_dtype);
   hdr.lambda_bytes = (uint64_t)m * 8;
   FileCloser fc{fopen(path, "wb")};
   RW_CHECK(fc.f != nullptr, RW_EINVAL, "cannot open %s for writing", path);
@@ -137,9 +139,10 @@ int rw_eig_load(rw_graph h, const char* path, void* Q, int q_dtype, double* lamb
   RW_CHECK(hash == hdr.weight_hash, RW_EINVAL,
            "%s: computed for other edge weights (beta %.17g then; the graph was built or edited since)", path,
            hdr.beta);
-  // the first m columns are the first m * N values; lambda follows all hdr.m columns
+  // the first m pairs are a prefix of the stored block (the pair form's remainder columns come first);
+  // lambda follows the whole block
   const size_t es = dtype_size(q_dtype);
-  const uint64_t want = (uint64_t)g->N * m * es;
+  const uint64_t want = (uint64_t)g->N * q_block_cols(q_dtype, m) * es;
   const size_t chunk = size_t(64) << 20;
   std::vector<char> buf(std::min<size_t>(want, chunk));
   for (uint64_t off = 0; off < want; off += chunk) {

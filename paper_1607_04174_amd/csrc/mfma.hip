@@ -30,19 +30,23 @@ __device__ __forceinline__ void split_bf16(float v, uint16_t* hi, uint16_t* lo) 
 // reconstruction
 // ---------------------------------------------------------------------------------------------
 template <typename TU>
-__global__ __launch_bounds__(256) void k_reconstruct_mfma(const uint16_t* __restrict__ Q, int64_t N, int m,
-                                                           const double* __restrict__ Y, int C,
+__global__ __launch_bounds__(256) void k_reconstruct_mfma(const uint16_t* __restrict__ Q,
+                                                           const uint16_t* __restrict__ Qlo, int pm, int64_t N,
+                                                           int m, const double* __restrict__ Y, int C,
                                                            const uint8_t* __restrict__ map,
                                                            const TU* __restrict__ dinv, int normalized,
                                                            TU* __restrict__ U) {
   extern __shared__ char smem[];
   // the product runs over Q's columns 1 .. m-1 against Y's rows 1 .. m-1; Y's row 0 is the null vector's
-  // per-label term, added in the epilogue
+  // per-label term, added in the epilogue.  With the pair form's remainder columns (Qlo, pm of them) the
+  // contraction runs on over them, against Y's rows 1 .. pm again: k in [m-1, m-1+pm) reads Qlo column
+  // k - (m-1).
   Q += N;
   Y += 1;
   const int ldy = m;
   m -= 1;
-  const int mpad = (m + 15) & ~15;
+  const int kext = m + pm;
+  const int mpad = (kext + 15) & ~15;
   uint16_t* sBt = reinterpret_cast<uint16_t*>(smem);                    // [16 cols][mpad]
   uint16_t* sQ = sBt + 16 * mpad;                                       // [256 nodes][kSQ]
   float* sD = reinterpret_cast<float*>(sQ + kMfmaNodes * kSQ);           // [256 nodes][17]
@@ -52,11 +56,11 @@ __global__ __launch_bounds__(256) void k_reconstruct_mfma(const uint16_t* __rest
   for (int t = tid; t < 16 * mpad; t += 256) {
     int col = t / mpad, k = t - col * mpad;
     uint16_t v = 0;
-    if (k < m) {
+    if (k < kext) {
       int c = col < C ? col : col - C;
       if (col < 2 * C) {
         uint16_t hi, lo;
-        split_bf16((float)Y[k + (int64_t)c * ldy], &hi, &lo);
+        split_bf16((float)Y[(k < m ? k : k - m) + (int64_t)c * ldy], &hi, &lo);
         v = col < C ? hi : lo;
       }
     }
@@ -78,8 +82,8 @@ __global__ __launch_bounds__(256) void k_reconstruct_mfma(const uint16_t* __rest
     for (int r = 0; r < 4; ++r) {
       const int k = k0 + 4 * kq + r;
       uint2 w = make_uint2(0u, 0u);
-      if (k < m) {
-        const uint16_t* src = Q + (int64_t)k * N + gnode;
+      if (k < kext) {
+        const uint16_t* src = (k < m ? Q + (int64_t)k * N : Qlo + (int64_t)(k - m) * N) + gnode;
         if (vec && gnode + 3 < N) {
           w = *reinterpret_cast<const uint2*>(src);
         } else {
@@ -134,23 +138,24 @@ __global__ __launch_bounds__(256) void k_reconstruct_mfma(const uint16_t* __rest
   }
 }
 
-size_t reconstruct_mfma_lds(int m) {
-  const int mpad = (m - 1 + 15) & ~15;   // columns 1 .. m-1
+size_t reconstruct_mfma_lds(int m, int pm) {
+  const int mpad = (m - 1 + pm + 15) & ~15;   // columns 1 .. m-1, then pm remainder columns
   return (size_t)16 * mpad * 2 + (size_t)kMfmaNodes * kSQ * 2 + (size_t)kMfmaNodes * 17 * 4;
 }
 
-int reconstruct_mfma(const Graph* g, const void* Q, int m, const double* Y, int C, const uint8_t* map, void* U,
-                     hipStream_t s) {
+int reconstruct_mfma(const Graph* g, const void* Q, const uint16_t* Qlo, int m, const double* Y, int C,
+                     const uint8_t* map, void* U, hipStream_t s) {
   RW_CHECK(C <= 8, RW_EINVAL, "the BF16 matrix-core reconstruction handles at most 8 labels");
-  const size_t sh = reconstruct_mfma_lds(m);
+  const int pm = Qlo != nullptr ? std::min(kPairCols, m - 1) : 0;
+  const size_t sh = reconstruct_mfma_lds(m, pm);
   RW_CHECK(sh <= 64 * 1024, RW_EINVAL, "m = %d too large for the matrix-core reconstruction tile", m);
   const unsigned grid = (unsigned)((g->N + kMfmaNodes - 1) / kMfmaNodes);
   if (g->dtype == RW_F64)
-    k_reconstruct_mfma<double><<<grid, 256, sh, s>>>((const uint16_t*)Q, g->N, m, Y, C, map, (const double*)g->dinv,
-                                                     g->normalized, (double*)U);
+    k_reconstruct_mfma<double><<<grid, 256, sh, s>>>((const uint16_t*)Q, Qlo, pm, g->N, m, Y, C, map,
+                                                     (const double*)g->dinv, g->normalized, (double*)U);
   else
-    k_reconstruct_mfma<float><<<grid, 256, sh, s>>>((const uint16_t*)Q, g->N, m, Y, C, map, (const float*)g->dinv,
-                                                    g->normalized, (float*)U);
+    k_reconstruct_mfma<float><<<grid, 256, sh, s>>>((const uint16_t*)Q, Qlo, pm, g->N, m, Y, C, map,
+                                                    (const float*)g->dinv, g->normalized, (float*)U);
   RW_LAUNCH_CHECK();
   return RW_OK;
 }
@@ -262,9 +267,13 @@ int rw_convert_block(const void* src, int src_dtype, void* dst, int dst_dtype, i
                      hipStream_t stream) {
   RW_CHECK(src != nullptr && dst != nullptr, RW_EINVAL, "null argument");
   RW_CHECK(src != dst, RW_EINVAL, "source and destination must differ");
+  RW_CHECK(rows >= 0 && cols >= 0, RW_EINVAL, "bad sizes");
+  if (dst_dtype == RW_BF16_PAIR) {
+    RW_CHECK(src_dtype == RW_F64 || src_dtype == RW_F32, RW_EINVAL, "the pair form is made from an F64 or F32 block");
+    return convert_pair(src_dtype, src, rows, static_cast<uint16_t*>(dst), cols, stream);
+  }
   RW_CHECK((src_dtype == RW_F64 || src_dtype == RW_F32 || src_dtype == RW_BF16) &&
                (dst_dtype == RW_F64 || dst_dtype == RW_F32 || dst_dtype == RW_BF16), RW_EINVAL, "bad dtype");
-  RW_CHECK(rows >= 0 && cols >= 0, RW_EINVAL, "bad sizes");
   return convert_block(src_dtype, src, rows, dst_dtype, dst, rows, rows, cols, stream);
 }
 
@@ -282,7 +291,8 @@ int rw_project_basis(const void* Q, int q_dtype, int64_t N, int m, const float* 
   RW_TRY(rw_project_workspace_bytes(N, m, C, &need));
   RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "projection workspace too small: %zu < %zu", work_bytes, need);
   if (q_dtype == RW_F32) return gram(RW_F32, Q, N, X, N, N, m, C, P, static_cast<double*>(work), stream);
-  RW_CHECK(q_dtype == RW_BF16, RW_EINVAL, "projection supports F32 (VALU) and BF16 (matrix cores) bases");
+  RW_CHECK(q_dtype == RW_BF16, RW_EINVAL,
+           "projection supports F32 (VALU) and BF16 (matrix cores) bases (a pair form's plain block is BF16)");
   RW_CHECK(C <= 8 && m <= 16 * kProjMaxChunks, RW_EINVAL, "matrix-core projection needs C <= 8 and m <= 256");
   const int nb = proj_blocks(N);
   const int64_t per = ((N + nb - 1) / nb + kMfmaNodes - 1) / kMfmaNodes * kMfmaNodes;

@@ -139,6 +139,22 @@ struct Carver {
 };
 
 inline size_t dtype_size(int dt) { return dt == RW_F64 ? 8 : (dt == RW_F32 ? 4 : 2); }
+// eigenbasis storage: the plain types, or the BF16 pair form (remainder columns of q_1 .. q_kPairCols, then
+// the plain BF16 block)
+constexpr int kPairCols = RW_PAIR_COLS;
+inline bool q_dtype_ok(int dt) { return dt == RW_F64 || dt == RW_F32 || dt == RW_BF16 || dt == RW_BF16_PAIR; }
+inline int64_t q_block_cols(int dt, int64_t m) { return dt == RW_BF16_PAIR ? m + kPairCols : m; }
+// a basis as its plain block (element type dt) and, for the pair form, the remainder columns (else null)
+struct BasisView {
+  const void* hi;
+  const uint16_t* lo;
+  int dt;
+};
+inline BasisView basis_view(int64_t N, const void* Q, int qdt) {
+  if (qdt == RW_BF16_PAIR)
+    return {static_cast<const uint16_t*>(Q) + (int64_t)kPairCols * N, static_cast<const uint16_t*>(Q), RW_BF16};
+  return {Q, nullptr, qdt};
+}
 
 // ---- the graph handle --------------------------------------------------------------------------
 struct Graph {
@@ -287,6 +303,8 @@ int rotate_pair(const float* A0, const float* A1, int off1, int64_t ld, const do
 // copy / convert a column-major block (rows x cols) between element types
 int convert_block(int dt_src, const void* src, int64_t lds, int dt_dst, void* dst, int64_t ldd,
                   int64_t rows, int cols, hipStream_t s);
+// the BF16 pair form (rows x (kPairCols + cols)) of an F64 / F32 block
+int convert_pair(int dt_src, const void* src, int64_t rows, uint16_t* dst, int cols, hipStream_t s);
 // column norms (FP64 out) of R = A - B diag(theta) (theta may be null: plain norms of A)
 size_t norm_partial_count(int cols);
 int residual_norms(int dt, const void* A, const void* B, const double* theta, int64_t rows, int cols,
@@ -308,8 +326,8 @@ int project_out_to(int dt, const void* X, int64_t ldx, void* Y, int64_t ldy, con
 // ---- BF16 matrix-core contractions (mfma.hip) ----------------------------------------------------
 // U = s_i sum_{j>=1} Q(i, j) Y(j, c) + kappa_c on non-seeds (s = d^{-1/2} or 1; kappa_c = Y(0, c), added
 // where s > 0 or the operator is L), one-hot on seeds; Y is m x C (ld m) in the form k_solve_coeffs leaves
-int reconstruct_mfma(const Graph* g, const void* Q, int m, const double* Y, int C, const uint8_t* map, void* U,
-                     hipStream_t s);
+int reconstruct_mfma(const Graph* g, const void* Q, const uint16_t* Qlo, int m, const double* Y, int C,
+                     const uint8_t* map, void* U, hipStream_t s);
 
 // ---- FP64 view of the operator and of a stored basis, for the online solve (solve.hip) ------------
 // Seed rows of the reduced system are formed from the FP64 weights and degrees (the graph's type only
@@ -380,7 +398,8 @@ __device__ __forceinline__ void reduced_entry(int64_t t, int m, int C, int64_t S
 // Bg[k] for a later correction (the choice of m fits the stored columns); otherwise the q'_j of cn.
 template <typename TQ>
 __device__ void gather_seed_row(const GridDev& G, int normalized, const double* weight, const double* degree,
-                                const double* sums, const TQ* Q, int m, const uint8_t* map, int64_t i, int C,
+                                const double* sums, const TQ* Q, const TQ* Qlo, int m, const uint8_t* map,
+                                int64_t i, int C,
                                 const double* cn, int64_t k, int64_t ld, double* Qs, double* GB, double* Hs,
                                 double* Us, double* gs, double* Bg) {
   const int64_t x = i % G.nx, y = (i / G.nx) % G.ny, z = i / (G.nx * G.ny);
@@ -407,12 +426,20 @@ __device__ void gather_seed_row(const GridDev& G, int normalized, const double* 
   double bg = 0.0;
   for (int t = 0; t < cnt; ++t)
     if (map[nb[t]] == 0) bg -= cf[t] * ghat64(degree, sums, normalized, G.N, nb[t]);
+  // Qlo (the pair form's remainder columns, or null): column j in [1, kPairCols] is read as hi + lo, exact in
+  // FP64
   for (int j = threadIdx.x; j < m; j += blockDim.x) {
     const TQ* qc = Q + (int64_t)j * G.N;
+    const TQ* lc = (Qlo != nullptr && j >= 1 && j <= kPairCols) ? Qlo + (int64_t)(j - 1) * G.N : nullptr;
     double qv = (double)Elem<TQ>::ld(qc, i);
+    if (lc) qv += (double)Elem<TQ>::ld(lc, i);
     double acc = 0.0;
     for (int t = 0; t < cnt; ++t)
-      if (map[nb[t]] == 0) acc -= cf[t] * (double)Elem<TQ>::ld(qc, nb[t]);
+      if (map[nb[t]] == 0) {
+        double v = (double)Elem<TQ>::ld(qc, nb[t]);
+        if (lc) v += (double)Elem<TQ>::ld(lc, nb[t]);
+        acc -= cf[t] * v;
+      }
     if (cn != nullptr) {
       if (j == 0) {
         qv = gi;

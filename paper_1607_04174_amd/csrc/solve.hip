@@ -118,12 +118,12 @@ __global__ void k_set_map(uint8_t* map, const int64_t* seeds, const int32_t* lab
 // One block per seed: the stored columns at the seed row, B Q_n, U_hat_s, op_ss U_hat_s, g and B g_n, from the
 // FP64 weights and degrees (gather_seed_row).
 template <typename TQ>
-__global__ void k_seed_gather(GridDev G, int normalized, const TQ* Q, int ma, const int64_t* seeds,
+__global__ void k_seed_gather(GridDev G, int normalized, const TQ* Q, const TQ* Qlo, int ma, const int64_t* seeds,
                               const uint8_t* map, const double* weight, const double* degree, const double* sums,
                               int64_t S, int C, double* Qs, double* GB, double* Hs, double* Us, double* gs, double* Bg) {
   const int64_t k = blockIdx.x;
-  gather_seed_row<TQ>(G, normalized, weight, degree, sums, Q, ma, map, seeds[k], C, nullptr, k, S, Qs, GB, Hs, Us, gs,
-                      Bg);
+  gather_seed_row<TQ>(G, normalized, weight, degree, sums, Q, Qlo, ma, map, seeds[k], C, nullptr, k, S, Qs, GB, Hs,
+                      Us, gs, Bg);
 }
 
 // seed rows of the FP64 basis: column 0 becomes g, the others (q_j - g c_j) / n_j (in place, first m columns)
@@ -157,9 +157,13 @@ size_t null_stats_partial_count(int64_t N, int m) {
   return (size_t)2 * m * (size_t)((N + kNsRows - 1) / kNsRows);
 }
 
+static_assert(kNsCols == kPairCols, "the first column block holds exactly the pair form's remainder columns");
+
+// Qlo: the pair form's remainder columns (or null), added to columns 1 .. kPairCols (block row 0)
 template <typename TQ>
-__global__ __launch_bounds__(256) void k_null_stats(const TQ* Q, int64_t N, int m, const double* degree,
-                                                    int normalized, double* partial, int64_t nchunk) {
+__global__ __launch_bounds__(256) void k_null_stats(const TQ* Q, const TQ* Qlo, int64_t N, int m,
+                                                    const double* degree, int normalized, double* partial,
+                                                    int64_t nchunk) {
   __shared__ double sh[4][2 * kNsCols];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t chunk = blockIdx.x;
@@ -182,6 +186,14 @@ __global__ __launch_bounds__(256) void k_null_stats(const TQ* Q, int64_t N, int 
     const TQ* qc = Q + (int64_t)(j0 + min(jj, ncol - 1)) * N;
 #pragma unroll
     for (int q = 0; q < kNsRowsPerThread; ++q) v[jj][q] = (double)Elem<TQ>::ld(qc, ic[q]);
+  }
+  if (Qlo != nullptr && blockIdx.y == 0) {   // uniform per block
+#pragma unroll
+    for (int jj = 0; jj < kNsCols; ++jj) {
+      const TQ* lc = Qlo + (int64_t)min(jj, ncol - 1) * N;
+#pragma unroll
+      for (int q = 0; q < kNsRowsPerThread; ++q) v[jj][q] += (double)Elem<TQ>::ld(lc, ic[q]);
+    }
   }
   double sd[kNsRowsPerThread];
 #pragma unroll
@@ -239,15 +251,18 @@ __global__ __launch_bounds__(64) void k_null_finish(const double* partial, int64
 
 int null_stats(const Graph* g, const void* Q, int qdt, int m, double* partial, double* cn, int* bad, hipStream_t s) {
   const int64_t nchunk = (g->N + kNsRows - 1) / kNsRows;
+  const BasisView b = basis_view(g->N, Q, qdt);
   if (m > 1) {
     const dim3 grid((unsigned)nchunk, (unsigned)((m - 1 + kNsCols - 1) / kNsCols));
-    if (qdt == RW_F64)
-      k_null_stats<double><<<grid, 256, 0, s>>>((const double*)Q, g->N, m, g->degree, g->normalized, partial, nchunk);
-    else if (qdt == RW_F32)
-      k_null_stats<float><<<grid, 256, 0, s>>>((const float*)Q, g->N, m, g->degree, g->normalized, partial, nchunk);
+    if (b.dt == RW_F64)
+      k_null_stats<double><<<grid, 256, 0, s>>>((const double*)b.hi, nullptr, g->N, m, g->degree, g->normalized,
+                                                 partial, nchunk);
+    else if (b.dt == RW_F32)
+      k_null_stats<float><<<grid, 256, 0, s>>>((const float*)b.hi, nullptr, g->N, m, g->degree, g->normalized,
+                                                partial, nchunk);
     else
-      k_null_stats<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)Q, g->N, m, g->degree, g->normalized, partial,
-                                                   nchunk);
+      k_null_stats<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)b.hi, b.lo, g->N, m, g->degree, g->normalized,
+                                                   partial, nchunk);
     RW_LAUNCH_CHECK();
   }
   if (m > 1) {
@@ -279,10 +294,11 @@ __global__ void k_reduced(int m, int C, int64_t S, const double* Qs, const doubl
 // kappa = Y(0, lab), the null vector's term, added where s_i > 0 or the operator is L), one-hot on seeds.
 // Y (rows 1..m-1) and kappa live in LDS; each thread owns one node and CB labels.
 // ---------------------------------------------------------------------------------------------
+// Qlo (the pair form's remainder columns of q_1 .. q_pm, or null) adds its terms after the plain block's.
 template <typename TQ, typename TU, int CB>
-__global__ __launch_bounds__(256) void k_reconstruct(const TQ* Q, int64_t N, int m, const double* Y, int C,
-                                                      int lab0, const uint8_t* map, const TU* dinv, int normalized,
-                                                      TU* U) {
+__global__ __launch_bounds__(256) void k_reconstruct(const TQ* Q, const TQ* Qlo, int pm, int64_t N, int m,
+                                                      const double* Y, int C, int lab0, const uint8_t* map,
+                                                      const TU* dinv, int normalized, TU* U) {
   using CT = typename Elem<TQ>::C;
   extern __shared__ char smem[];
   CT* sY = reinterpret_cast<CT*>(smem);          // (m - 1) x CB
@@ -321,6 +337,12 @@ __global__ __launch_bounds__(256) void k_reconstruct(const TQ* Q, int64_t N, int
 #pragma unroll
     for (int c = 0; c < CB; ++c) acc[c] = fma(q, sY[j * CB + c], acc[c]);
   }
+  if (Qlo != nullptr)
+    for (int jl = 0; jl < pm; ++jl) {   // remainder of column jl + 1: Y row jl + 1 (sY row jl)
+      CT q = Elem<TQ>::ld(Qlo, (int64_t)jl * N + i);
+#pragma unroll
+      for (int c = 0; c < CB; ++c) acc[c] = fma(q, sY[jl * CB + c], acc[c]);
+    }
   const int ml = map[i];
   const CT sc = normalized ? (CT)dinv[i] : CT(1);
   const bool live = !normalized || sc > CT(0);
@@ -334,18 +356,20 @@ __global__ __launch_bounds__(256) void k_reconstruct(const TQ* Q, int64_t N, int
 }
 
 template <typename TQ, typename TU>
-static int reconstruct_t(const Graph* g, const void* Q, int m, const double* Y, int C, const uint8_t* map,
-                         void* U, hipStream_t s) {
+static int reconstruct_t(const Graph* g, const void* Q, const uint16_t* Qlo, int m, const double* Y, int C,
+                         const uint8_t* map, void* U, hipStream_t s) {
   using CT = typename Elem<TQ>::C;
+  const TQ* lo = reinterpret_cast<const TQ*>(Qlo);   // non-null only with TQ = uint16_t
+  const int pm = std::min(kPairCols, m - 1);
   for (int lab0 = 0; lab0 < C; lab0 += 8) {
     int rem = C - lab0;
     if (rem <= 4) {
       size_t sh = (size_t)m * 4 * sizeof(CT);
-      k_reconstruct<TQ, TU, 4><<<nblocks(g->N, 256), 256, sh, s>>>((const TQ*)Q, g->N, m, Y, C, lab0, map,
+      k_reconstruct<TQ, TU, 4><<<nblocks(g->N, 256), 256, sh, s>>>((const TQ*)Q, lo, pm, g->N, m, Y, C, lab0, map,
                                                                     (const TU*)g->dinv, g->normalized, (TU*)U);
     } else {
       size_t sh = (size_t)m * 8 * sizeof(CT);
-      k_reconstruct<TQ, TU, 8><<<nblocks(g->N, 256), 256, sh, s>>>((const TQ*)Q, g->N, m, Y, C, lab0, map,
+      k_reconstruct<TQ, TU, 8><<<nblocks(g->N, 256), 256, sh, s>>>((const TQ*)Q, lo, pm, g->N, m, Y, C, lab0, map,
                                                                     (const TU*)g->dinv, g->normalized, (TU*)U);
     }
     RW_LAUNCH_CHECK();
@@ -355,16 +379,17 @@ static int reconstruct_t(const Graph* g, const void* Q, int m, const double* Y, 
 
 static int reconstruct(const Graph* g, const void* Q, int qdt, int m, const double* Y, int C, const uint8_t* map,
                        void* U, hipStream_t s) {
-  if (qdt == RW_BF16 && C <= 8) return reconstruct_mfma(g, Q, m, Y, C, map, U, s);
+  const BasisView b = basis_view(g->N, Q, qdt);
+  if (b.dt == RW_BF16 && C <= 8) return reconstruct_mfma(g, b.hi, b.lo, m, Y, C, map, U, s);
   RW_CHECK((size_t)m * 8 * 8 <= 65536, RW_EINVAL, "m = %d too large for the reconstruction tile", m);
   if (g->dtype == RW_F64) {
-    if (qdt == RW_F64) return reconstruct_t<double, double>(g, Q, m, Y, C, map, U, s);
-    if (qdt == RW_F32) return reconstruct_t<float, double>(g, Q, m, Y, C, map, U, s);
-    return reconstruct_t<uint16_t, double>(g, Q, m, Y, C, map, U, s);
+    if (b.dt == RW_F64) return reconstruct_t<double, double>(g, b.hi, nullptr, m, Y, C, map, U, s);
+    if (b.dt == RW_F32) return reconstruct_t<float, double>(g, b.hi, nullptr, m, Y, C, map, U, s);
+    return reconstruct_t<uint16_t, double>(g, b.hi, b.lo, m, Y, C, map, U, s);
   }
-  if (qdt == RW_F64) return reconstruct_t<double, float>(g, Q, m, Y, C, map, U, s);
-  if (qdt == RW_F32) return reconstruct_t<float, float>(g, Q, m, Y, C, map, U, s);
-  return reconstruct_t<uint16_t, float>(g, Q, m, Y, C, map, U, s);
+  if (b.dt == RW_F64) return reconstruct_t<double, float>(g, b.hi, nullptr, m, Y, C, map, U, s);
+  if (b.dt == RW_F32) return reconstruct_t<float, float>(g, b.hi, nullptr, m, Y, C, map, U, s);
+  return reconstruct_t<uint16_t, float>(g, b.hi, b.lo, m, Y, C, map, U, s);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -783,6 +808,23 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int6
 
 // ---------------------------------------------------------------------------------------------
 
+// the seed rows of the first ma stored columns (hi + lo for the pair form), B Q_n, U_hat_s, op_ss U_hat_s
+static int seed_gather(const Graph* g, const void* Q, int qdt, int ma, const SolveWork& w, int64_t S, int C,
+                       hipStream_t s) {
+  const GridDev G = grid_of(g);
+  const BasisView b = basis_view(g->N, Q, qdt);
+#define RW_GATHER(TQ, LO)                                                                                   \
+  k_seed_gather<TQ><<<(unsigned)S, 256, 0, s>>>(G, g->normalized, (const TQ*)b.hi, LO, ma, w.seeds, w.map,       \
+                                                g->weight, g->degree, g->sums, S, C, w.Qs, w.GB, w.Hs, w.Us, w.gs, \
+                                                w.Bg)
+  if (b.dt == RW_F64) RW_GATHER(double, nullptr);
+  else if (b.dt == RW_F32) RW_GATHER(float, nullptr);
+  else RW_GATHER(uint16_t, b.lo);
+#undef RW_GATHER
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
 // Validates, sorts and de-duplicates the seeds into caller buffers (v: S pairs of scratch; nodes, labels:
 // S entries); *S_out receives the number of distinct seeds.  Allocates nothing.
 static int host_seeds_into(const Graph* g, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C,
@@ -829,16 +871,8 @@ static int solve_impl(rw_graph h, const void* Q, int q_dtype, const double* lamb
   RW_LAUNCH_CHECK();
   k_set_map<<<nblocks(S, 256), 256, 0, stream>>>(w.map, w.seeds, w.labels, S);
   RW_LAUNCH_CHECK();
-  const GridDev G = grid_of(g);
   const int ma = m_avail;
-#define RW_GATHER(TQ)                                                                                     \
-  k_seed_gather<TQ><<<(unsigned)S, 256, 0, stream>>>(G, g->normalized, (const TQ*)Q, ma, w.seeds, w.map, g->weight, \
-                                                     g->degree, g->sums, S, C, w.Qs, w.GB, w.Hs, w.Us, w.gs, w.Bg)
-  if (q_dtype == RW_F64) RW_GATHER(double);
-  else if (q_dtype == RW_F32) RW_GATHER(float);
-  else RW_GATHER(uint16_t);
-#undef RW_GATHER
-  RW_LAUNCH_CHECK();
+  RW_TRY(seed_gather(g, Q, q_dtype, ma, w, S, C, stream));
   RW_HIP(hipMemsetAsync(w.nbad, 0, sizeof(int), stream));
   // choice of m (on the stored columns)
   int m = ma;
@@ -1088,7 +1122,7 @@ int rw_solve_seeds_noalloc(rw_graph h, const void* Q, int q_dtype, const double*
   RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
   const Graph* g = &h->g;
   RW_CHECK(Q != nullptr && lambda != nullptr && U != nullptr, RW_EINVAL, "null pointer argument");
-  RW_CHECK(q_dtype == RW_F64 || q_dtype == RW_F32 || q_dtype == RW_BF16, RW_EINVAL, "bad Q dtype");
+  RW_CHECK(q_dtype_ok(q_dtype), RW_EINVAL, "bad Q dtype");
   RW_CHECK(m >= 2 && m <= g->N, RW_EINVAL, "m = %d out of range", m);
   RW_CHECK(S_in >= 1, RW_EINVAL, "at least one seed is required");
   RW_CHECK(S_in <= kNoAllocMaxSeeds, RW_EWORKSPACE, "%lld seeds exceed the %lld of the allocation-free solve",
@@ -1119,7 +1153,7 @@ int rw_solve_seeds_async(rw_graph h, const void* Q, int q_dtype, const double* l
   RW_CHECK(Q != nullptr && lambda != nullptr && U != nullptr && work != nullptr && status != nullptr &&
                seed_node != nullptr && seed_label != nullptr,
            RW_EINVAL, "null pointer argument");
-  RW_CHECK(q_dtype == RW_F64 || q_dtype == RW_F32 || q_dtype == RW_BF16, RW_EINVAL, "bad Q dtype");
+  RW_CHECK(q_dtype_ok(q_dtype), RW_EINVAL, "bad Q dtype");
   RW_CHECK(m >= 2 && m <= g->N, RW_EINVAL, "m = %d out of range", m);
   RW_CHECK(S >= 1 && S < g->N, RW_EINVAL, "S = %lld out of range", (long long)S);
   RW_CHECK(C >= 1 && C <= 255, RW_EINVAL, "C must be in [1, 255] (got %d)", C);
@@ -1138,15 +1172,7 @@ int rw_solve_seeds_async(rw_graph h, const void* Q, int q_dtype, const double* l
   RW_LAUNCH_CHECK();
   k_set_map<<<nblocks(S, 256), 256, 0, stream>>>(w.map, w.seeds, w.labels, S);
   RW_LAUNCH_CHECK();
-  const GridDev G = grid_of(g);
-#define RW_GATHER(TQ)                                                                                    \
-  k_seed_gather<TQ><<<(unsigned)S, 256, 0, stream>>>(G, g->normalized, (const TQ*)Q, m, w.seeds, w.map, g->weight, \
-                                                     g->degree, g->sums, S, C, w.Qs, w.GB, w.Hs, w.Us, w.gs, w.Bg)
-  if (q_dtype == RW_F64) RW_GATHER(double);
-  else if (q_dtype == RW_F32) RW_GATHER(float);
-  else RW_GATHER(uint16_t);
-#undef RW_GATHER
-  RW_LAUNCH_CHECK();
+  RW_TRY(seed_gather(g, Q, q_dtype, m, w, S, C, stream));
   RW_TRY(null_stats(g, Q, q_dtype, m, w.npart, w.cn, flags, stream));
   k_seed_correct<<<nblocks(S * m, 256), 256, 0, stream>>>(w.Qs, w.GB, w.gs, w.Bg, w.cn, S, m);
   RW_LAUNCH_CHECK();
@@ -1174,7 +1200,7 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
   RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
   const Graph* g = &h->g;
   RW_CHECK(Q != nullptr && lambda != nullptr && U != nullptr && work != nullptr, RW_EINVAL, "null pointer argument");
-  RW_CHECK(q_dtype == RW_F64 || q_dtype == RW_F32 || q_dtype == RW_BF16, RW_EINVAL, "bad Q dtype");
+  RW_CHECK(q_dtype_ok(q_dtype), RW_EINVAL, "bad Q dtype");
   RW_CHECK(m_avail >= 2 && m_avail <= g->N, RW_EINVAL, "m_avail = %d out of range", m_avail);
   RW_CHECK(S_in >= 1, RW_EINVAL, "at least one seed is required");
   std::vector<std::pair<int64_t, int32_t>> v((size_t)S_in);

@@ -64,3 +64,25 @@ def test_checkpoint_round_trip_and_refusals(dt, tmp_path):
     open(short, "wb").write(data[: len(data) - 16])
     with pytest.raises(rw.RWError):
         rw.eig_load(g, short)
+
+
+def test_checkpoint_pair_form(tmp_path):
+    """The pair form round-trips bit for bit, a prefix of it loads as the pair form of fewer pairs, and the
+    solve from the loaded pairs equals the solve from the original."""
+    need_gpu()
+    banner("checkpoint pair form")
+    w = rwsynth.small("ckp", (26, 24), 4, m=20, C=2, seeds_per_label=4, n_shapes=3)
+    J, rid, node, lab = setup_case(w)
+    g = rw.Graph(to_dev(J, torch.float64), w.dims, w.conn, w.beta, dtype=torch.float32)
+    Q, lam, _ = rw.precompute_eig(g, w.m, tol=1e-5, max_iter=400)
+    P = rw.to_pair(Q)
+    path = str(tmp_path / "pair.rweig")
+    rw.eig_save(g, path, P, lam)
+    assert rw.eig_read_header(path)["q_dtype"] == rw.RW_BF16_PAIR
+    P2, lam2, _ = rw.eig_load(g, path)
+    assert isinstance(P2, rw.PairBasis) and torch.equal(P2.data, P.data) and torch.equal(lam2, lam)
+    P3, lam3, _ = rw.eig_load(g, path, m=12)
+    assert torch.equal(P3.data, P.data[:rw.RW_PAIR_COLS + 12]) and torch.equal(lam3, lam[:12])
+    U1, _ = rw.solve_seeds(g, P, lam, node, lab, w.C)
+    U2, _ = rw.solve_seeds(g, P2, lam2, node, lab, w.C)
+    assert torch.equal(U1, U2)

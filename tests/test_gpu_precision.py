@@ -89,3 +89,41 @@ def test_mixed_precision_against_fp64_path():
     e16 = (Ub.double() - U64).abs().max().item()
     assert e32 <= 1e-4, e32
     assert e16 <= 1e-2, e16
+
+
+@pytest.mark.parametrize("dims,conn,C,m", [((30, 26), 8, 3, 45), ((12, 11, 9), 6, 4, 40), ((31, 29), 4, 10, 33),
+                                           ((20, 18), 4, 2, 6)])
+def test_pair_form_against_oracle_and_fp64_path(dims, conn, C, m):
+    """The BF16 pair form: its plain block equals rw_convert_block's BF16 copy and its remainder columns
+    hold q_j - hi_j to BF16 (zero beyond m - 1); the solve matches the oracle on the basis the pair
+    represents (hi + lo) at 1e-4, through the matrix cores (C <= 8) and the vector units (C = 10); against
+    the FP64 path its error is below the plain BF16 copy's."""
+    need_gpu()
+    banner(f"pair form {dims} conn={conn} C={C} m={m}")
+    w = rwsynth.small("pp", dims, conn, m=m, C=C, seeds_per_label=4, n_shapes=5)
+    J, rid, node, lab = setup_case(w)
+    g64 = rw.Graph(to_dev(J, torch.float64), w.dims, w.conn, w.beta, dtype=torch.float64)
+    Q, lam, _ = rw.precompute_eig(g64, m, tol=1e-10)
+    g32 = rw.Graph(to_dev(J, torch.float64), w.dims, w.conn, w.beta, dtype=torch.float32)
+    P = rw.to_pair(Q)
+    Qb = rw.convert_block(Q, torch.bfloat16)
+    assert torch.equal(P.plain(), Qb)
+    lo = P.data[:rw.RW_PAIR_COLS].double()
+    k = min(rw.RW_PAIR_COLS, m - 1)
+    ref_lo = (Q[1:1 + k] - Qb[1:1 + k].double()).float().to(torch.bfloat16).double()
+    assert torch.equal(lo[:k], ref_lo) and torch.all(lo[k:] == 0)
+    Qv = P.value()
+    assert (Qv[1:1 + k] - Q[1:1 + k]).abs().max().item() <= 2.0 ** -15 * Q[1:1 + k].abs().max().item()
+    Up, _ = rw.solve_seeds(g32, P, lam, node, lab, C)
+    og = OGraph(J, w.dims, w.conn, w.beta)
+    Uo = fast_rw(og, Qv.cpu().numpy().T, lam.cpu().numpy(), node, lab, C, exact=True)
+    err_o = np.abs(Up.cpu().numpy().T.astype(np.float64) - Uo).max()
+    U64, _ = rw.solve_seeds(g64, Q, lam, node, lab, C)
+    Ub, _ = rw.solve_seeds(g32, Qb, lam, node, lab, C)
+    e_pair = (Up.double() - U64).abs().max().item()
+    e_bf16 = (Ub.double() - U64).abs().max().item()
+    print(f"  vs oracle on the pair's basis {err_o:.2e}; vs FP64 path: pair {e_pair:.2e}, plain BF16 {e_bf16:.2e}",
+          flush=True)
+    assert err_o <= 1e-4, err_o
+    assert e_pair <= 1e-2 and e_pair <= e_bf16, (e_pair, e_bf16)
+    np.testing.assert_array_equal(Up.cpu().numpy().T[node, lab], 1.0)
