@@ -14,7 +14,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse.linalg as spla
 
-from .exact_rw import exact_rw, seed_split
+from .exact_rw import exact_rw, pcg, seed_split
 
 P_FLOOR = 1e-12
 
@@ -38,16 +38,25 @@ def ce_grad(U, gt, seed_node):
     return G
 
 
-def adjoint_grads(graph, seed_node, seed_label, C, G, U=None):
+def adjoint_grads(graph, seed_node, seed_label, C, G, U=None, method="direct", tol=1e-12):
     """(dl/dw [per edge, graph.edge_id order], dl/dJ [N], dl/dbeta, dl/ds [per edge]) for a loss
-    gradient G = dl/dU (N x C) at the exact forward solution."""
+    gradient G = dl/dU (N x C) at the exact forward solution.  The adjoint system L_n A_n = G_n is solved
+    by sparse LU (method "direct") or, on graphs too large to factor, by the Jacobi-preconditioned CG of
+    exact_rw (method "cg", relative residual tol per label)."""
     if U is None:
-        U = exact_rw(graph, seed_node, seed_label, C, method="direct")
+        U = exact_rw(graph, seed_node, seed_label, C, method=method, tol=tol)
     L = graph.L()
     s, n = seed_split(graph.N, seed_node)
-    lu = spla.splu(L[n][:, n].tocsc())
     A = np.zeros_like(U)
-    A[n] = lu.solve(np.ascontiguousarray(G[n]))
+    if method == "direct":
+        lu = spla.splu(L[n][:, n].tocsc())
+        A[n] = lu.solve(np.ascontiguousarray(G[n]))
+    elif method == "cg":
+        Ln = L[n][:, n].tocsr()
+        for k in range(C):
+            A[n, k] = pcg(Ln, np.ascontiguousarray(G[n, k]), tol=tol)[0]
+    else:
+        raise ValueError(method)
     t, h = graph.tail, graph.head
     dw = -np.sum((A[t] - A[h]) * (U[t] - U[h]), axis=1)
     w = graph.w

@@ -143,3 +143,22 @@ def test_adjoint_matches_finite_differences():
         fd = (L_at(scale=sp_) - L_at(scale=sm_)) / (2 * h)
         assert abs(fd - ds[e]) <= 1e-6 * max(1.0, abs(fd))
     assert np.isfinite(ce_loss(U, gt, node))
+
+
+@pytest.mark.parametrize("dims,conn", [((9, 8, 1), 8), ((6, 5, 4), 6)])
+def test_adjoint_cg_equals_direct(dims, conn):
+    """The adjoint by Jacobi-PCG (for graphs too large to factor) gives the gradients of the sparse-LU
+    adjoint, which the finite-difference pin above fixes."""
+    w = rwsynth.small("tc", dims, conn, C=3, seeds_per_label=3, n_shapes=3)
+    J, rid = rwsynth.phantom(w)
+    node, lab = rwsynth.seeds(w, rid)
+    gt = rwsynth.label_map(rid, 3)
+    g = Graph(J, dims, conn, beta=12.0)
+    U = exact_rw(g, node, lab, 3, method="direct")
+    G = ce_grad(U, gt, node)
+    ref = adjoint_grads(g, node, lab, 3, G, U)
+    Ucg = exact_rw(g, node, lab, 3, method="cg", tol=1e-13)
+    np.testing.assert_allclose(Ucg, U, atol=1e-11)
+    got = adjoint_grads(g, node, lab, 3, ce_grad(Ucg, gt, node), Ucg, method="cg", tol=1e-13)
+    for a, b in zip(got, ref):
+        np.testing.assert_allclose(a, b, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(b).max()))
