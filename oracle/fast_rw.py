@@ -198,10 +198,13 @@ def fast_rw(graph, Q, lam, seed_node, seed_label, C, m=None, rows=None, exact=Fa
 def fast_rw_prior(graph, Q, lam, seed_node, seed_label, C, gamma, prior, m=None):
     """gamma > 0 fast random walker, eqs. (15) and (17) as printed, in the variables of the
     operator graph.M() (with the normalized Laplacian this applies the prior in hat variables,
-    P_hat = D^{1/2} P, as the substitution of Sec. II-C prescribes)."""
+    P_hat = D^{1/2} P, as the substitution of Sec. II-C prescribes).  The stored basis is read as in the
+    gamma = 0 case: the analytic null vector g (the zero-eigenvalue eigenvector of Sec. II-B) takes the
+    place of the stored column closest to it, with eigenvalue 0, and the other columns are made
+    orthogonal to it (insert_null); E = Q (Lambda + gamma I)^{-1} Q^T then includes the null pair."""
     m = Q.shape[1] if m is None else m
-    Q = np.asarray(Q, dtype=np.float64)[:, :m]
-    lam = np.asarray(lam, dtype=np.float64)[:m]
+    Q, lam = insert_null(np.asarray(Q, dtype=np.float64)[:, :m], np.asarray(lam, dtype=np.float64)[:m],
+                         graph.ghat())
     M, s, n, Ms, B = _seed_blocks(graph, seed_node)
     hs = graph.hat_scale()
     Uhat_s = hs[s][:, None] * one_hot(seed_label, C)

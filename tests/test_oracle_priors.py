@@ -124,3 +124,20 @@ def test_fast_rw_prior_full_basis_normalized_is_the_degree_weighted_system():
     # and it is not the identity-weighted system of eq. (5) when the degrees are not all equal
     Ui = exact_rw(g, node, lab, 3, method="dense", gamma=gamma, prior=P)
     assert np.abs(Ui - U).max() > 1e-3
+
+
+def test_fast_rw_prior_reads_the_basis_around_the_exact_null_vector():
+    """The stored basis is read as in the gamma = 0 case: a perturbed stored null vector and null-vector
+    components in the other columns change nothing."""
+    w = rwsynth.small("ts", (9, 8), 4, C=2, seeds_per_label=3, n_shapes=2)
+    J, rid = rwsynth.phantom(w)
+    node, lab = rwsynth.seeds(w, rid)
+    g = Graph(J, (9, 8, 1), 4, beta=30.0)
+    lam, Q = dense_eigpairs(g, 20)
+    P = gaussian_priors(J, node, lab, 2)
+    U = fast_rw_prior(g, Q, lam, node, lab, 2, gamma=0.1, prior=P)
+    rng = np.random.default_rng(4)
+    Qm = Q.copy()
+    Qm[:, 0] += 1e-3 * rng.standard_normal(g.N)
+    Qm[:, 1:] += np.outer(g.ghat(), rng.uniform(-0.5, 0.5, 19))     # the stored null vector stays the closest
+    np.testing.assert_allclose(fast_rw_prior(g, Qm, lam, node, lab, 2, gamma=0.1, prior=P), U, atol=1e-12)
