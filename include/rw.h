@@ -278,6 +278,48 @@ int rw_solve_seeds(rw_graph g, const void* Q, int q_dtype, const double* lambda,
                    const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, double eps,
                    void* U, void* work, size_t work_bytes, hipStream_t stream, rw_solve_info* info);
 
+/* ---- gamma > 0: prior probabilities (Sec. II-A eq. (5); Sec. II-B eqs. (15), (17); Sec. III-A2 eq. (25)) ---- */
+
+int rw_solve_prior_workspace_bytes(rw_graph g, int m_avail, int64_t S, int C, size_t* bytes);
+
+/* Label probabilities of the random walker with priors P and weight gamma > 0 from the stored pairs:
+ * (L_n + gamma I) U_n = gamma P_n - B^T U_s in the variables of the graph's operator (under the normalized
+ * Laplacian the prior enters as P_hat = D^{1/2} P, so U solves (L_n + gamma D_n) U_n = gamma D_n P_n -
+ * B^T U_s).  With E = Q (Lambda + gamma I)^{-1} Q^T, eq. (17) for F_s and eq. (15) for U_n are evaluated in
+ * their m x m reduced form: with G = B Q'_n, Z = Q'_n^T P_hat_n and Lambda_g = Lambda + gamma I,
+ *   (Lambda_g - Q'_s^T G) V = Q'_s^T [op_ss U_hat_s + gamma (U_hat_s + G Lambda_g^{-1} Z)],
+ *   U_hat_n = Q'_n (V + gamma Lambda_g^{-1} Z),
+ * on the FP64 basis Q' of rw_solve_seeds (FP64 LU with partial pivoting).  No seed needs to reach every
+ * component (L_n + gamma I is definite).
+ *   Q, q_dtype, lambda, m_avail, seeds, C, U, work: as rw_solve_seeds (work: rw_solve_prior_workspace_bytes);
+ *   prior    device C x N (label k's map contiguous) of prior_dtype (RW_F64 or RW_F32), read-only;
+ *   gamma    > 0;
+ *   eps      <= 0: m = m_avail; > 0: m = the smallest m in [2, m_avail] with g_k(m) = ||p_k - Q_m Q_m^T p_k||^2
+ *            <= g_max = eps^2 n for the sampled labels k = 0, r^d, 2 r^d, ... (d the image dimension), with
+ *            p = P_hat and n = 1^T D 1 under the normalized Laplacian (p = P, n = N under L); g_k is taken
+ *            from one projection of P_hat on the stored columns (Q orthonormal: g_k(m) = ||p_k||^2 minus the
+ *            first m squared coefficients), m_avail when no m qualifies;
+ *   info     m_used, f_max = g_max, f_worst = max over the sampled labels of g_k(m_used) (0 when eps <= 0),
+ *            min_pivot.
+ * The call synchronizes `stream`.  Errors: RW_EINVAL, RW_EWORKSPACE, RW_ESINGULAR. */
+int rw_solve_seeds_prior(rw_graph g, const void* Q, int q_dtype, const double* lambda, int m_avail,
+                         const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, double gamma,
+                         const void* prior, int prior_dtype, double eps, int r, void* U, void* work,
+                         size_t work_bytes, hipStream_t stream, rw_solve_info* info);
+
+int rw_priors_workspace_bytes(int C, size_t* bytes);
+
+/* Prior probabilities from the seeds (Sec. IV-A): per label, a Gaussian fitted to the intensities J of its
+ * seeds (mean and maximum-likelihood variance, FP64, floored at 1e-6); prior(k, i) = that density at J_i
+ * normalized over the labels that have seeds (a softmax of the log-densities); a label without seeds gets 0.
+ * seed_node, seed_label: device arrays of S entries (any order); prior: device C x N of prior_dtype (RW_F64 or
+ * RW_F32); work: rw_priors_workspace_bytes(C); *status (device int32) receives RW_OK, or RW_EINVAL when a
+ * seed is out of range (such seeds are skipped).  Only enqueues kernels (capturable).  Errors of the call:
+ * RW_EINVAL, RW_EWORKSPACE. */
+int rw_priors_from_seeds(rw_graph g, const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C,
+                         void* prior, int prior_dtype, void* work, size_t work_bytes, int32_t* status,
+                         hipStream_t stream);
+
 /* RW_ASYNC form of rw_solve_seeds, for streams under HIP graph capture and callers that must not wait:
  * it only enqueues kernels (no host read, no wait, no memset) and reports through *status (device int32):
  * RW_OK, or RW_EINVAL (a seed or label out of range, seeds not strictly ascending, a basis column in the

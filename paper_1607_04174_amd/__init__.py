@@ -119,6 +119,15 @@ _SIGS = {
     "rw_solve_seeds_async": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p,
                                         ct.c_void_p, ct.c_int64, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t,
                                         ct.c_void_p, ct.c_void_p]),
+    "rw_solve_prior_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_int64, ct.c_int,
+                                                  ct.POINTER(ct.c_size_t)]),
+    "rw_solve_seeds_prior": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p,
+                                        ct.c_void_p, ct.c_int64, ct.c_int, ct.c_double, ct.c_void_p, ct.c_int,
+                                        ct.c_double, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p,
+                                        ct.POINTER(rw_solve_info)]),
+    "rw_priors_workspace_bytes": (ct.c_int, [ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_priors_from_seeds": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int, ct.c_void_p,
+                                        ct.c_int, ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p]),
     "rw_dense_syev_workspace_bytes": (ct.c_int, [ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]),
     "rw_dense_syev": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_size_t,
                                  ct.c_void_p]),
@@ -465,6 +474,46 @@ def solve_seeds_noalloc(g: Graph, Q: torch.Tensor, lam: torch.Tensor, seed_node,
                                         ct.c_void_p(nodes.ctypes.data), ct.c_void_p(labels.ctypes.data), nodes.size,
                                         C, _ptr(U), _stream(g.device), ct.byref(info)))
     return U, {"m_used": info.m_used, "min_pivot": info.min_pivot}
+
+
+def solve_seeds_prior(g: Graph, Q, lam: torch.Tensor, seed_node, seed_label, C: int, gamma: float,
+                      prior: torch.Tensor, eps: float = 0.0, r: int = 4, m_avail: Optional[int] = None,
+                      U: Optional[torch.Tensor] = None, workspace: Optional[SolveWorkspace] = None):
+    """Label probabilities (C, N) with priors (C, N) (float64 or float32) and weight gamma > 0; eps > 0 chooses m
+    from the priors (one label in every r^d).  Returns (U, info dict)."""
+    m_avail = Q.shape[0] if m_avail is None else int(m_avail)
+    nodes = np.ascontiguousarray(np.asarray(seed_node, dtype=np.int64))
+    labels = np.ascontiguousarray(np.asarray(seed_label, dtype=np.int32))
+    prior = prior.contiguous()
+    assert tuple(prior.shape) == (C, g.N) and prior.dtype in (torch.float64, torch.float32)
+    if U is None:
+        U = torch.empty((C, g.N), dtype=g.dtype, device=g.device)
+    nb = ct.c_size_t()
+    _check(lib().rw_solve_prior_workspace_bytes(g.handle, m_avail, max(nodes.size, 1), C, ct.byref(nb)))
+    work = (workspace or SolveWorkspace()).get(nb.value, g.device)
+    info = rw_solve_info()
+    _check(lib().rw_solve_seeds_prior(g.handle, *_qarg(Q), _ptr(lam), m_avail, ct.c_void_p(nodes.ctypes.data),
+                                      ct.c_void_p(labels.ctypes.data), nodes.size, C, float(gamma), _ptr(prior),
+                                      _TORCH_DT[prior.dtype], float(eps), int(r), _ptr(U), _ptr(work), work.numel(),
+                                      _stream(g.device), ct.byref(info)))
+    return U, {"m_used": info.m_used, "g_max": info.f_max, "g_worst": info.f_worst, "min_pivot": info.min_pivot}
+
+
+def priors_from_seeds(g: Graph, seed_node, seed_label, C: int, dtype=torch.float32) -> torch.Tensor:
+    """(C, N) Gaussian-fit priors from the seeds' intensities (rw_priors_from_seeds)."""
+    nodes = torch.as_tensor(np.asarray(seed_node, dtype=np.int64)).to(g.device)
+    labels = torch.as_tensor(np.asarray(seed_label, dtype=np.int32)).to(g.device)
+    out = torch.empty((C, g.N), dtype=dtype, device=g.device)
+    nb = ct.c_size_t()
+    _check(lib().rw_priors_workspace_bytes(C, ct.byref(nb)))
+    work = torch.empty(nb.value, dtype=torch.uint8, device=g.device)
+    status = torch.full((1,), 99, dtype=torch.int32, device=g.device)
+    _check(lib().rw_priors_from_seeds(g.handle, _ptr(nodes), _ptr(labels), nodes.numel(), C, _ptr(out),
+                                      _TORCH_DT[dtype], _ptr(work), work.numel(), _ptr(status), _stream(g.device)))
+    st = int(status.item())
+    if st != RW_OK:
+        raise RWError(st, "a seed is out of range")
+    return out
 
 
 def solve_workspace_bytes(g: Graph, m: int, S: int, C: int) -> int:

@@ -177,7 +177,7 @@ __global__ void k_b_reduced(const BatchImg* D, LuJob* jobs) {
   const int64_t S = d.S, ld = d.S_cap;
   const int64_t total = (int64_t)m * (m + C);
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x)
-    reduced_entry(t, m, C, S, ld, d.Qs, d.GB, d.Hs, d.lambda, d.K, d.Y);
+    reduced_entry(t, m, C, S, ld, d.Qs, d.GB, d.Hs, d.lambda, 0.0, d.K, d.Y);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     LuJob jb;
     jb.A = d.K; jb.B = d.Y; jb.stat = d.stat; jb.n = m; jb.nrhs = C;

@@ -237,7 +237,8 @@ __global__ __launch_bounds__(256) void k_project_mfma(const uint16_t* __restrict
   }
 }
 
-__global__ void k_project_final(const float* partial, int nblocks, int m, int C, double* P) {
+// P(i, c) (leading dimension ldp) = the sum of the block partials of row i, label c (both BF16 parts of X)
+__global__ void k_project_final(const float* partial, int nblocks, int m, int C, double* P, int ldp) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m * C) return;
   const int i = t % m, c = t / m;
@@ -248,13 +249,58 @@ __global__ void k_project_final(const float* partial, int nblocks, int m, int C,
     const float* p = partial + (int64_t)b * mchunks * 256 + q * 256 + r * 16;
     s += (double)p[c] + (double)p[c + C];
   }
-  P[i + (int64_t)c * m] = s;
+  P[i + (int64_t)c * ldp] = s;
+}
+
+__global__ void k_add_rows(const double* T, int rows, int C, double* P, int ldp) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * C) return;
+  const int i = t % rows, c = t / rows;
+  P[i + (int64_t)c * ldp] += T[t];
 }
 
 static int proj_blocks(int64_t N) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (N + 1023) / 1024)); }
 
 size_t project_partial_count(int64_t N, int m) {
   return (size_t)proj_blocks(N) * ((m + 15) / 16) * 256;
+}
+
+// BF16 Q^T X on the matrix cores in blocks of at most 256 columns and 8 labels
+static int project_bf16(const uint16_t* Q, int64_t N, int m, const float* X, int C, double* P, int ldp,
+                        float* partial, hipStream_t s) {
+  const int nb = proj_blocks(N);
+  const int64_t per = ((N + nb - 1) / nb + kMfmaNodes - 1) / kMfmaNodes * kMfmaNodes;
+  for (int c0 = 0; c0 < m; c0 += 16 * kProjMaxChunks)
+    for (int l0 = 0; l0 < C; l0 += 8) {
+      const int mc = std::min(16 * kProjMaxChunks, m - c0), cc = std::min(8, C - l0);
+      k_project_mfma<<<nb, 256, 0, s>>>(Q + (int64_t)c0 * N, N, mc, X + (int64_t)l0 * N, cc, per, partial);
+      RW_LAUNCH_CHECK();
+      k_project_final<<<nblocks((int64_t)mc * cc, 256), 256, 0, s>>>(partial, nb, mc, cc,
+                                                                       P + c0 + (int64_t)l0 * ldp, ldp);
+      RW_LAUNCH_CHECK();
+    }
+  return RW_OK;
+}
+
+size_t project_block_partial_bytes(int64_t N, int m, int C) {
+  return std::max(project_partial_count(N, std::min(m, 16 * kProjMaxChunks)) * sizeof(float),
+                  gram_partial_count(N, m, C) * sizeof(double));
+}
+
+int project_block(const void* Q, int qdt, int64_t N, int m, const void* X, int C, double* P, void* partial,
+                  double* tmp, hipStream_t s) {
+  if (qdt == RW_F64 || qdt == RW_F32)
+    return gram(qdt, Q, N, X, N, N, m, C, P, static_cast<double*>(partial), s);
+  const BasisView b = basis_view(N, Q, qdt);
+  RW_TRY(project_bf16(static_cast<const uint16_t*>(b.hi), N, m, static_cast<const float*>(X), C, P, m,
+                      static_cast<float*>(partial), s));
+  if (b.lo != nullptr && m > 1) {   // the remainder columns add to rows 1 .. pm
+    const int pm = std::min(kPairCols, m - 1);
+    RW_TRY(project_bf16(b.lo, N, pm, static_cast<const float*>(X), C, tmp, pm, static_cast<float*>(partial), s));
+    k_add_rows<<<nblocks((int64_t)pm * C, 256), 256, 0, s>>>(tmp, pm, C, P + 1, m);
+    RW_LAUNCH_CHECK();
+  }
+  return RW_OK;
 }
 
 }  // namespace rw
@@ -299,7 +345,7 @@ int rw_project_basis(const void* Q, int q_dtype, int64_t N, int m, const float* 
   float* partial = static_cast<float*>(work);
   k_project_mfma<<<nb, 256, 0, stream>>>((const uint16_t*)Q, N, m, X, C, per, partial);
   RW_LAUNCH_CHECK();
-  k_project_final<<<nblocks((int64_t)m * C, 256), 256, 0, stream>>>(partial, nb, m, C, P);
+  k_project_final<<<nblocks((int64_t)m * C, 256), 256, 0, stream>>>(partial, nb, m, C, P, m);
   RW_LAUNCH_CHECK();
   return RW_OK;
 }

@@ -305,6 +305,13 @@ int convert_block(int dt_src, const void* src, int64_t lds, int dt_dst, void* ds
                   int64_t rows, int cols, hipStream_t s);
 // the BF16 pair form (rows x (kPairCols + cols)) of an F64 / F32 block
 int convert_pair(int dt_src, const void* src, int64_t rows, uint16_t* dst, int cols, hipStream_t s);
+// P = Q^T X (m x C FP64, leading dimension m) for a basis of any storage type: X is F64 for an F64 basis, F32
+// otherwise (C x N label-major); F64 / F32 bases by FP64-accumulated VALU products, BF16 and the pair form on
+// the matrix cores (the pair form's remainder columns add to rows 1 .. 8).  partial: project_block_partial_bytes;
+// tmp: 8 C doubles (pair form only).
+size_t project_block_partial_bytes(int64_t N, int m, int C);
+int project_block(const void* Q, int qdt, int64_t N, int m, const void* X, int C, double* P, void* partial,
+                  double* tmp, hipStream_t s);
 // column norms (FP64 out) of R = A - B diag(theta) (theta may be null: plain norms of A)
 size_t norm_partial_count(int cols);
 int residual_norms(int dt, const void* A, const void* B, const double* theta, int64_t rows, int cols,
@@ -375,18 +382,18 @@ __device__ __forceinline__ void solve_coeffs_block(double* Y, int m, int C, cons
 int solve_coeffs(double* Y, int m, int C, const double* cn, const Graph* g, hipStream_t s);
 
 // Entry t of the reduced system from the seed rows (leading dimension ld, S seeds): for t < m m,
-// K(i, j) = lambda_i [i == j] - sum_s Qs(s, i) GB(s, j); for t < m C, Y(i, c) = sum_s Qs(s, i) Hs(s, c); the
-// seed sums run in order (the single and the batched solves form the system with this same code)
+// K(i, j) = (lambda_i + gamma) [i == j] - sum_s Qs(s, i) GB(s, j); for t < m C, Y(i, c) = sum_s Qs(s, i)
+// Hs(s, c); the seed sums run in order (the single and the batched solves form the system with this same code)
 __device__ __forceinline__ void reduced_entry(int64_t t, int m, int C, int64_t S, int64_t ld, const double* Qs,
-                                              const double* GB, const double* Hs, const double* lambda, double* K,
-                                              double* Y) {
+                                              const double* GB, const double* Hs, const double* lambda,
+                                              double gamma, double* K, double* Y) {
   if (t >= (int64_t)m * (m + C)) return;
   const int i = (int)(t % m), j = (int)(t / m);
   const double* a = Qs + (int64_t)i * ld;
   const double* b = j < m ? GB + (int64_t)j * ld : Hs + (int64_t)(j - m) * ld;
   double acc = 0.0;
   for (int64_t q = 0; q < S; ++q) acc += a[q] * b[q];
-  if (j < m) K[i + (int64_t)j * m] = (i == j ? lambda[i] : 0.0) - acc;
+  if (j < m) K[i + (int64_t)j * m] = (i == j ? lambda[i] + gamma : 0.0) - acc;
   else Y[i + (int64_t)(j - m) * m] = acc;
 }
 

@@ -284,8 +284,8 @@ int solve_coeffs(double* Y, int m, int C, const double* cn, const Graph* g, hipS
 }
 
 __global__ void k_reduced(int m, int C, int64_t S, const double* Qs, const double* GB, const double* Hs,
-                          const double* lambda, double* K, double* Y) {
-  reduced_entry(blockIdx.x * (int64_t)blockDim.x + threadIdx.x, m, C, S, S, Qs, GB, Hs, lambda, K, Y);
+                          const double* lambda, double gamma, double* K, double* Y) {
+  reduced_entry(blockIdx.x * (int64_t)blockDim.x + threadIdx.x, m, C, S, S, Qs, GB, Hs, lambda, gamma, K, Y);
 }
 
 
@@ -1012,7 +1012,8 @@ static int solve_impl(rw_graph h, const void* Q, int q_dtype, const double* lamb
   RW_LAUNCH_CHECK();
   // reduced system K = Lambda - Q'_s^T (B Q'_n), Y = Q'_s^T (op_ss U_hat_s), and its solve (the batched solve
   // forms and solves each image's system with the same code)
-  k_reduced<<<nblocks((int64_t)m * (m + C), 256), 256, 0, stream>>>(m, C, S, w.Qs, w.GB, w.Hs, lambda, w.K, w.Y);
+  k_reduced<<<nblocks((int64_t)m * (m + C), 256), 256, 0, stream>>>(m, C, S, w.Qs, w.GB, w.Hs, lambda, 0.0, w.K,
+                                                                     w.Y);
   RW_LAUNCH_CHECK();
   RW_TRY(lu_solve(w.K, m, w.Y, C, w.stat, stream));
   RW_TRY(solve_coeffs(w.Y, m, C, w.cn, g, stream));
@@ -1109,6 +1110,239 @@ static int noalloc_scratch(void** ptr) {
   return RW_OK;
 }
 
+
+// ---------------------------------------------------------------------------------------------
+// gamma > 0 with prior probabilities (Sec. II-B, eqs. (15) and (17)).  With Lambda_g = Lambda + gamma I,
+// G = B Q'_n (S x m), Z = Q'_n^T P_hat_n (m x C) and V = Lambda_g^{-1} Q'_s^T F_s, eq. (17) reduces, as the
+// gamma = 0 system does, to the m x m system
+//   (Lambda_g - Q'_s^T G) V = Q'_s^T [op_ss U_hat_s + gamma (U_hat_s + G Lambda_g^{-1} Z)]
+// and eq. (15) to U_hat_n = Q'_n Y with Y = V + gamma Lambda_g^{-1} Z.  P_hat = D^{1/2} P (P under L).
+// The choice of m from the priors (Sec. III-A2, eq. (25)) uses Z_hat = Q^T P_hat over all rows and the
+// stored columns: g_k(m) = ||p_hat_k||^2 - sum_{j<m} Z_hat(j, k)^2 (Q orthonormal), for k = 0, r^d, 2 r^d, ...
+// ---------------------------------------------------------------------------------------------
+struct PriorWork {
+  void* X;        // C x N (FP64 for an FP64 basis, else FP32): s_i P(k, i)
+  double* Zh;     // ma x C: Q^T X over all rows and the stored columns
+  double* Zp;     // m x C: Q'_n^T P_hat_n
+  double* gdot;   // C: g^T X (exact null vector)
+  double* xn2;    // C: ||X(k, :)||^2
+  double* Xs;     // S x C: s_i P(k, i) at the seeds, FP64
+  double* part;   // prep partials
+  void* ppart;    // projection partials
+  double* ptmp;   // kPairCols x C
+};
+
+static int prior_blocks(int64_t N) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (N + 2047) / 2048)); }
+
+static size_t prior_layout(const Graph* g, int ma, int64_t S, int C, void* base, SolveWork* w, PriorWork* pw) {
+  const size_t used = solve_layout(g, ma, S, C, base, w, false);
+  Carver c(base ? static_cast<char*>(base) + ((used + 255) & ~size_t(255)) : nullptr);
+  PriorWork t;
+  t.X = c.take<double>((size_t)C * g->N);
+  t.Zh = c.take<double>((size_t)ma * C);
+  t.Zp = c.take<double>((size_t)ma * C);
+  t.gdot = c.take<double>(C);
+  t.xn2 = c.take<double>(C);
+  t.Xs = c.take<double>((size_t)S * C);
+  t.part = c.take<double>((size_t)prior_blocks(g->N) * C * 2);
+  t.ppart = c.take<char>(project_block_partial_bytes(g->N, ma, C));
+  t.ptmp = c.take<double>((size_t)kPairCols * C);
+  if (pw) *pw = t;
+  return ((used + 255) & ~size_t(255)) + c.used;
+}
+
+// X(k, i) = s_i P(k, i); block b sums g_i X(k, i) and X(k, i)^2 over its node range (fixed order)
+template <typename TP, typename TX>
+__global__ __launch_bounds__(256) void k_prior_prep(const TP* P, int64_t N, int C, const double* degree,
+                                                    const double* sums, int normalized, TX* X, double* part) {
+  __shared__ double sh[4][2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t per = (N + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = blockIdx.x * per, i1 = min(N, i0 + per);
+  for (int k = 0; k < C; ++k) {
+    double a = 0.0, b = 0.0;
+    for (int64_t i = i0 + tid; i < i1; i += 256) {
+      const double sc = normalized ? sqrt(degree[i]) : 1.0;
+      const double x = sc * (double)P[(int64_t)k * N + i];
+      const TX xs = (TX)x;
+      X[(int64_t)k * N + i] = xs;
+      a += ghat64(degree, sums, normalized, N, i) * (double)xs;
+      b += (double)xs * (double)xs;
+    }
+    a = wave_sum64(a);
+    b = wave_sum64(b);
+    __syncthreads();
+    if (lane == 0) {
+      sh[wave][0] = a;
+      sh[wave][1] = b;
+    }
+    __syncthreads();
+    if (tid < 2)
+      part[((int64_t)blockIdx.x * C + k) * 2 + tid] = (sh[0][tid] + sh[1][tid]) + (sh[2][tid] + sh[3][tid]);
+  }
+}
+
+__global__ void k_prior_norms(const double* part, int nb, int C, double* gdot, double* xn2) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= C) return;
+  double a = 0.0, b = 0.0;
+  for (int q = 0; q < nb; ++q) {
+    a += part[((int64_t)q * C + k) * 2];
+    b += part[((int64_t)q * C + k) * 2 + 1];
+  }
+  gdot[k] = a;
+  xn2[k] = b;
+}
+
+// Xs(s, k) = s_i P(k, i) at seed s (node i), FP64
+template <typename TP>
+__global__ void k_prior_xs(const TP* P, int64_t N, int C, const int64_t* seeds, int64_t S, const double* degree,
+                           int normalized, double* Xs) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= S * C) return;
+  const int64_t s = t % S, k = t / S;
+  const int64_t i = seeds[s];
+  Xs[t] = (normalized ? sqrt(degree[i]) : 1.0) * (double)P[k * N + i];
+}
+
+// Zp(j, k) = q'_j^T X(k, :) over the non-seed rows: the full-row projection in the FP64 basis (q'_0 = g,
+// q'_j = (q_j - g c_j) / n_j) less the seed rows' part
+__global__ void k_prior_z(int m, int ma, int C, int64_t S, const double* Zh, const double* gdot, const double* cn,
+                          const double* Qs, const double* Xs, double* Zp) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)m * C) return;
+  const int j = (int)(t % m), k = (int)(t / m);
+  double z = j == 0 ? gdot[k] : (Zh[j + (int64_t)k * ma] - cn[j] * gdot[k]) / cn[m + j];
+  for (int64_t s = 0; s < S; ++s) z -= Qs[s + (int64_t)j * S] * Xs[s + (int64_t)k * S];
+  Zp[t] = z;
+}
+
+// Hs(s, k) += gamma (U_hat_s(s, k) + sum_j G(s, j) Zp(j, k) / (lambda_j + gamma))
+__global__ void k_prior_rhs(int m, int C, int64_t S, const double* GB, const double* Us, const double* lambda,
+                            double gamma, const double* Zp, double* Hs) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= S * C) return;
+  const int64_t s = t % S, k = t / S;
+  double acc = 0.0;
+  for (int j = 0; j < m; ++j) acc += GB[s + (int64_t)j * S] * Zp[j + k * m] / (lambda[j] + gamma);
+  Hs[t] += gamma * (Us[t] + acc);
+}
+
+// Y(j, k) += gamma Zp(j, k) / (lambda_j + gamma)
+__global__ void k_prior_finish(int m, int C, const double* lambda, double gamma, const double* Zp, double* Y) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)m * C) return;
+  const int j = (int)(t % m);
+  Y[t] += gamma * Zp[t] / (lambda[j] + gamma);
+}
+
+static int prior_solve_impl(rw_graph h, const void* Q, int q_dtype, const double* lambda, int ma,
+                            const int64_t* nodes, const int32_t* labels, int64_t S, int C, double gamma,
+                            const void* prior, int prior_dtype, double eps, int r, void* U, const SolveWork& w,
+                            const PriorWork& pw, hipStream_t stream, rw_solve_info* info) {
+  const Graph* g = &h->g;
+  RW_HIP(hipMemcpyAsync(w.seeds, nodes, S * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+  RW_HIP(hipMemcpyAsync(w.labels, labels, S * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  k_clear_map<<<nblocks(g->N, 256), 256, 0, stream>>>(w.map, g->N);
+  RW_LAUNCH_CHECK();
+  k_set_map<<<nblocks(S, 256), 256, 0, stream>>>(w.map, w.seeds, w.labels, S);
+  RW_LAUNCH_CHECK();
+  RW_TRY(seed_gather(g, Q, q_dtype, ma, w, S, C, stream));
+  RW_TRY(fill_i32(w.nbad, 1, 0, stream));
+  // X = s P, its projection on the stored columns, g^T X and ||X||^2
+  const bool x64 = q_dtype == RW_F64;
+  const int nb = prior_blocks(g->N);
+#define RW_PREP(TP, TX)                                                                                      \
+  k_prior_prep<TP, TX><<<nb, 256, 0, stream>>>(static_cast<const TP*>(prior), g->N, C, g->degree, g->sums,    \
+                                               g->normalized, static_cast<TX*>(pw.X), pw.part)
+  if (prior_dtype == RW_F64) {
+    if (x64) RW_PREP(double, double);
+    else RW_PREP(double, float);
+  } else {
+    if (x64) RW_PREP(float, double);
+    else RW_PREP(float, float);
+  }
+#undef RW_PREP
+  RW_LAUNCH_CHECK();
+  k_prior_norms<<<nblocks(C, 256), 256, 0, stream>>>(pw.part, nb, C, pw.gdot, pw.xn2);
+  RW_LAUNCH_CHECK();
+  RW_TRY(project_block(Q, q_dtype, g->N, ma, pw.X, C, pw.Zh, pw.ppart, pw.ptmp, stream));
+  // choice of m (eq. (25)) on the sampled labels
+  int m = ma;
+  double gmax = 0.0, gworst = 0.0;
+  if (eps > 0.0) {
+    int step = 1;
+    for (int q = 0; q < g->ndim; ++q) step *= r;
+    const int ns = (C + step - 1) / step;
+    void* stage = nullptr;
+    RW_TRY(host_stage(((size_t)ma * C + C + 1) * sizeof(double), &stage));
+    double* hz = static_cast<double*>(stage);
+    RW_HIP(hipMemcpyAsync(hz, pw.Zh, (size_t)ma * C * sizeof(double), hipMemcpyDeviceToHost, stream));
+    RW_HIP(hipMemcpyAsync(hz + (size_t)ma * C, pw.xn2, C * sizeof(double), hipMemcpyDeviceToHost, stream));
+    RW_HIP(hipMemcpyAsync(hz + (size_t)ma * C + C, g->sums, sizeof(double), hipMemcpyDeviceToHost, stream));
+    RW_HIP(hipStreamSynchronize(stream));
+    gmax = eps * eps * (g->normalized ? hz[(size_t)ma * C + C] : (double)g->N);
+    std::vector<double> gk((size_t)ns);
+    for (int q = 0; q < ns; ++q) gk[q] = hz[(size_t)ma * C + (size_t)q * step];
+    m = ma;
+    for (int mm = 1; mm <= ma; ++mm) {
+      double worst = 0.0;
+      for (int q = 0; q < ns; ++q) {
+        const double z = hz[(mm - 1) + (size_t)q * step * ma];
+        gk[q] -= z * z;
+        worst = std::max(worst, gk[q]);
+      }
+      gworst = worst;
+      if (mm >= 2 && worst <= gmax) {
+        m = mm;
+        break;
+      }
+    }
+  }
+  // the FP64 basis of the first m columns, the projection of P_hat_n on it, and the reduced system
+  RW_TRY(null_stats(g, Q, q_dtype, m, w.npart, w.cn, w.nbad, stream));
+  k_seed_correct<<<nblocks(S * m, 256), 256, 0, stream>>>(w.Qs, w.GB, w.gs, w.Bg, w.cn, S, m);
+  RW_LAUNCH_CHECK();
+  if (prior_dtype == RW_F64)
+    k_prior_xs<double><<<nblocks(S * C, 256), 256, 0, stream>>>(static_cast<const double*>(prior), g->N, C, w.seeds,
+                                                                S, g->degree, g->normalized, pw.Xs);
+  else
+    k_prior_xs<float><<<nblocks(S * C, 256), 256, 0, stream>>>(static_cast<const float*>(prior), g->N, C, w.seeds,
+                                                               S, g->degree, g->normalized, pw.Xs);
+  RW_LAUNCH_CHECK();
+  k_prior_z<<<nblocks((int64_t)m * C, 256), 256, 0, stream>>>(m, ma, C, S, pw.Zh, pw.gdot, w.cn, w.Qs, pw.Xs, pw.Zp);
+  RW_LAUNCH_CHECK();
+  k_prior_rhs<<<nblocks(S * C, 256), 256, 0, stream>>>(m, C, S, w.GB, w.Us, lambda, gamma, pw.Zp, w.Hs);
+  RW_LAUNCH_CHECK();
+  k_reduced<<<nblocks((int64_t)m * (m + C), 256), 256, 0, stream>>>(m, C, S, w.Qs, w.GB, w.Hs, lambda, gamma, w.K,
+                                                                     w.Y);
+  RW_LAUNCH_CHECK();
+  RW_TRY(lu_solve(w.K, m, w.Y, C, w.stat, stream));
+  k_prior_finish<<<nblocks((int64_t)m * C, 256), 256, 0, stream>>>(m, C, lambda, gamma, pw.Zp, w.Y);
+  RW_LAUNCH_CHECK();
+  RW_TRY(solve_coeffs(w.Y, m, C, w.cn, g, stream));
+  RW_TRY(reconstruct(g, Q, q_dtype, m, w.Y, C, w.map, U, stream));
+  void* stage = nullptr;
+  RW_TRY(host_stage(2 * sizeof(double), &stage));
+  double* hs = static_cast<double*>(stage);
+  RW_HIP(hipMemcpyAsync(hs, w.stat, sizeof(double), hipMemcpyDeviceToHost, stream));
+  RW_HIP(hipMemcpyAsync(hs + 1, w.nbad, sizeof(int), hipMemcpyDeviceToHost, stream));
+  RW_HIP(hipStreamSynchronize(stream));
+  const double stat = hs[0];
+  int nbad = 0;
+  std::memcpy(&nbad, hs + 1, sizeof(int));
+  RW_CHECK(!nbad, RW_EINVAL, "basis column %d lies in the span of the null vector (column 0)", nbad);
+  RW_CHECK(stat > 0.0, RW_ESINGULAR, "reduced seed system is singular to working precision (m = %d)", m);
+  if (info) {
+    info->m_used = m;
+    info->eig_probes = 0;
+    info->f_max = gmax;
+    info->f_worst = gworst;
+    info->min_pivot = stat;
+  }
+  return RW_OK;
+}
+
 }  // namespace rw
 
 using namespace rw;
@@ -1176,7 +1410,8 @@ int rw_solve_seeds_async(rw_graph h, const void* Q, int q_dtype, const double* l
   RW_TRY(null_stats(g, Q, q_dtype, m, w.npart, w.cn, flags, stream));
   k_seed_correct<<<nblocks(S * m, 256), 256, 0, stream>>>(w.Qs, w.GB, w.gs, w.Bg, w.cn, S, m);
   RW_LAUNCH_CHECK();
-  k_reduced<<<nblocks((int64_t)m * (m + C), 256), 256, 0, stream>>>(m, C, S, w.Qs, w.GB, w.Hs, lambda, w.K, w.Y);
+  k_reduced<<<nblocks((int64_t)m * (m + C), 256), 256, 0, stream>>>(m, C, S, w.Qs, w.GB, w.Hs, lambda, 0.0, w.K,
+                                                                     w.Y);
   RW_LAUNCH_CHECK();
   RW_TRY(lu_solve(w.K, m, w.Y, C, w.stat, stream));
   RW_TRY(solve_coeffs(w.Y, m, C, w.cn, g, stream));
@@ -1214,6 +1449,42 @@ int rw_solve_seeds(rw_graph h, const void* Q, int q_dtype, const double* lambda,
   RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "solve workspace too small: %zu < %zu", work_bytes, need);
   return solve_impl(h, Q, q_dtype, lambda, m_avail, nodes.data(), labels.data(), S, S_in, C, eps, U, w, stream, info,
                     nullptr);
+}
+
+int rw_solve_prior_workspace_bytes(rw_graph h, int m_avail, int64_t S, int C, size_t* bytes) {
+  RW_CHECK(h != nullptr && bytes != nullptr, RW_EINVAL, "null argument");
+  RW_CHECK(m_avail >= 2 && S >= 1 && C >= 1, RW_EINVAL, "bad sizes");
+  *bytes = prior_layout(&h->g, m_avail, S, C, nullptr, nullptr, nullptr);
+  return RW_OK;
+}
+
+int rw_solve_seeds_prior(rw_graph h, const void* Q, int q_dtype, const double* lambda, int m_avail,
+                         const int64_t* seed_node, const int32_t* seed_label, int64_t S_in, int C, double gamma,
+                         const void* prior, int prior_dtype, double eps, int r, void* U, void* work,
+                         size_t work_bytes, hipStream_t stream, rw_solve_info* info) {
+  RW_NOT_CAPTURING(stream);
+  RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
+  const Graph* g = &h->g;
+  RW_CHECK(Q != nullptr && lambda != nullptr && U != nullptr && work != nullptr && prior != nullptr, RW_EINVAL,
+           "null pointer argument");
+  RW_CHECK(q_dtype_ok(q_dtype), RW_EINVAL, "bad Q dtype");
+  RW_CHECK(prior_dtype == RW_F64 || prior_dtype == RW_F32, RW_EINVAL, "priors are F64 or F32");
+  RW_CHECK(gamma > 0.0 && std::isfinite(gamma), RW_EINVAL, "gamma must be positive (got %g)", gamma);
+  RW_CHECK(m_avail >= 2 && m_avail <= g->N, RW_EINVAL, "m_avail = %d out of range", m_avail);
+  RW_CHECK(eps <= 0.0 || (r >= 1 && r <= 64), RW_EINVAL, "label sampling step r = %d out of range", r);
+  RW_CHECK(S_in >= 1, RW_EINVAL, "at least one seed is required");
+  std::vector<std::pair<int64_t, int32_t>> v((size_t)S_in);
+  std::vector<int64_t> nodes((size_t)S_in);
+  std::vector<int32_t> labels((size_t)S_in);
+  int64_t S = 0;
+  RW_TRY(host_seeds_into(g, seed_node, seed_label, S_in, C, v.data(), nodes.data(), labels.data(), &S));
+  RW_CHECK(S < g->N, RW_EINVAL, "every node is a seed");
+  SolveWork w;
+  PriorWork pw;
+  const size_t need = prior_layout(g, m_avail, S_in, C, work, &w, &pw);
+  RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "prior solve workspace too small: %zu < %zu", work_bytes, need);
+  return prior_solve_impl(h, Q, q_dtype, lambda, m_avail, nodes.data(), labels.data(), S, C, gamma, prior,
+                          prior_dtype, eps, r, U, w, pw, stream, info);
 }
 
 }  // extern "C"
