@@ -44,7 +44,7 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch the stencil block and a plain copy of the same block (for HBM counters)")
     ap.add_argument("--workload", default="interactive512",
-                    choices=["interactive512", "small64", "volume128", "batch64", "grad96"],
+                    choices=["interactive512", "small64", "volume128", "batch64", "grad96", "prior512"],
                     help="interactive512 (default, the headline line); the others measure the remaining "
                          "configurations and print their own line")
     args = ap.parse_args()
@@ -630,7 +630,57 @@ def run_grad96(args, rw, rwsynth, torch, dev):
                  fd_worst_rel=worst)
 
 
-MODES = {"small64": run_small64, "volume128": run_volume128, "batch64": run_batch64, "grad96": run_grad96}
+def run_prior512(args, rw, rwsynth, torch, dev):
+    """512 x 512, 8-connected, FP32 graph and basis (m = 200), C = 3, 50 seeds per label: Gaussian-fit priors
+    from the seeds and the gamma > 0 solve with the choice of m from the priors (eps 0.1, r = 4)."""
+    w = rwsynth.CFG2
+    J, rid = rwsynth.phantom(w, 0)
+    node, lab = rwsynth.seeds(w, rid, 0)
+    Jd = torch.as_tensor(J, device=dev)
+    g = rw.Graph(Jd, w.dims, w.conn, w.beta, dtype=torch.float32)
+    t_pre, (Q, lam, einfo) = _sync_time(torch, lambda: rw.precompute_eig(g, w.m, tol=1e-5, max_iter=400), 1)
+    gamma, eps, r = 1e-3, 0.1, 4
+    ws = rw.SolveWorkspace()
+    U = torch.empty((w.C, w.N), dtype=torch.float32, device=dev)
+
+    def step():
+        P = rw.priors_from_seeds(g, node, lab, w.C, dtype=torch.float32)
+        return P, rw.solve_seeds_prior(g, Q, lam, node, lab, w.C, gamma, P, eps=eps, r=r, U=U, workspace=ws)[1]
+
+    for _ in range(args.warmup):
+        step()
+    t, (P, info) = _sync_time(torch, step, args.steps)
+    log(f"prior512: {t * 1e3:.2f} ms per priors + solve, m_used {info['m_used']}, g_worst/g_max "
+        f"{info['g_worst']:.3e}/{info['g_max']:.3e}")
+    parity = None
+    cpu = None
+    if not args.no_cpu:
+        from oracle.fast_rw import fast_rw_prior
+        from oracle.graph import Graph as OGraph
+        from oracle.priors import choose_m_prior, gaussian_priors
+        og = OGraph(J, w.dims, w.conn, w.beta)
+        Qn, ln = Q.double().cpu().numpy().T, lam.cpu().numpy()
+        t0 = time.perf_counter()
+        Po = gaussian_priors(J, node, lab, w.C)
+        m_o, _, _ = choose_m_prior(og, Qn, Po, eps=eps, r=r) if info["m_used"] < 20 else (None, None, None)
+        Uo = fast_rw_prior(og, Qn, ln, node, lab, w.C, gamma, Po, m=info["m_used"])
+        t_o = time.perf_counter() - t0
+        parity = {"priors_vs_oracle_maxabs": float(np.abs(P.double().cpu().numpy().T - Po).max()),
+                  "solve_vs_oracle_same_basis_maxabs": float(np.abs(U.double().cpu().numpy().T - Uo).max()),
+                  "m_oracle": m_o}
+        cpu = {"value": round(1.0 / t_o, 4), "unit": "solves/s", "cores": int(_cores()), "kind": "oracle",
+               "sample": "one priors + gamma > 0 solve of this workload at the GPU's m (dense FP64 numpy)"}
+    return _line("priors + gamma > 0 RW solves/s (choice of m from the priors)", round(1.0 / t, 2), "solves/s", args,
+                 t * 1e3, "f32 graph/basis + f64 seed system, projection and prior fit",
+                 {"workload": "2D 512x512 8-connected phantom, beta 90, FP32 basis m=200, C=3, 50 seeds/label, "
+                              "Gaussian priors, gamma 1e-3, eps 0.1, r 4", "N": w.N, "m": w.m, "C": w.C,
+                  "S": int(node.size)},
+                 m_used=info["m_used"], g_max=info["g_max"], g_worst=info["g_worst"], precompute_s=round(t_pre, 2),
+                 parity=parity, cpu_baseline=cpu)
+
+
+MODES = {"small64": run_small64, "volume128": run_volume128, "batch64": run_batch64, "grad96": run_grad96,
+         "prior512": run_prior512}
 
 
 if __name__ == "__main__":

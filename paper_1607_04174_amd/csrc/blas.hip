@@ -473,6 +473,89 @@ __global__ void k_sum_chunks(const double* partial, int64_t count, int64_t nchun
   G[k] = s;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Projection P = Q^T X of a tall basis (N x m, column-major) on a few label maps (X: C x N, label-major):
+// blocks over (2048-row chunk, 8 columns); each thread holds its 8 rows of up to 4 labels of X in registers
+// and accumulates the 8 x 4 products in FP64 (products of FP32 values are exact), then one DPP wave sum per
+// (column, label) and the four waves in order.  Q is read once; X once per 8 columns (from cache).  The chunk
+// partials are summed in a fixed order.
+// ---------------------------------------------------------------------------------------------
+constexpr int kPcRowsPerThread = 8;
+constexpr int kPcRows = 256 * kPcRowsPerThread;
+constexpr int kPcCols = 8;
+constexpr int kPcLabels = 4;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_project_cols(const T* Q, int64_t N, int m, const T* X, int C, int l0,
+                                                      double* partial) {
+  __shared__ double sh[4][kPcCols * kPcLabels];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t chunk = blockIdx.x;
+  const int j0 = (int)blockIdx.y * kPcCols;
+  const int ncol = min(kPcCols, m - j0), nl = min(kPcLabels, C - l0);
+  int64_t ic[kPcRowsPerThread];
+  double x[kPcRowsPerThread][kPcLabels];
+#pragma unroll
+  for (int q = 0; q < kPcRowsPerThread; ++q) {
+    const int64_t i = chunk * kPcRows + tid + 256 * q;
+    ic[q] = i < N ? i : N - 1;
+#pragma unroll
+    for (int k = 0; k < kPcLabels; ++k)
+      x[q][k] = (i < N && k < nl) ? (double)X[(int64_t)(l0 + k) * N + i] : 0.0;
+  }
+  double acc[kPcCols][kPcLabels];
+#pragma unroll
+  for (int jj = 0; jj < kPcCols; ++jj) {
+    const T* qc = Q + (int64_t)(j0 + min(jj, ncol - 1)) * N;
+    double v[kPcRowsPerThread];
+#pragma unroll
+    for (int q = 0; q < kPcRowsPerThread; ++q) v[q] = (double)qc[ic[q]];
+#pragma unroll
+    for (int k = 0; k < kPcLabels; ++k) {
+      double a = 0.0;
+#pragma unroll
+      for (int q = 0; q < kPcRowsPerThread; ++q) a += v[q] * x[q][k];
+      acc[jj][k] = a;
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < kPcCols; ++jj)
+#pragma unroll
+    for (int k = 0; k < kPcLabels; ++k) {
+      const double t = wave_sum64(acc[jj][k]);
+      if (lane == 0) sh[wave][jj * kPcLabels + k] = t;
+    }
+  __syncthreads();
+  if (tid < kPcCols * kPcLabels) {
+    const int jj = tid / kPcLabels, k = tid % kPcLabels;
+    if (jj < ncol && k < nl) {
+      const double t = (sh[0][tid] + sh[1][tid]) + (sh[2][tid] + sh[3][tid]);
+      partial[chunk * ((int64_t)m * C) + (j0 + jj) + (int64_t)(l0 + k) * m] = t;
+    }
+  }
+}
+
+size_t project_cols_partial_count(int64_t N, int m, int C) {
+  return (size_t)((N + kPcRows - 1) / kPcRows) * m * C;
+}
+
+int project_cols(int dt, const void* Q, int64_t N, int m, const void* X, int C, double* P, double* partial,
+                 hipStream_t s) {
+  if (m <= 0 || C <= 0) return RW_OK;
+  const int64_t nch = (N + kPcRows - 1) / kPcRows;
+  const dim3 grid((unsigned)nch, (unsigned)((m + kPcCols - 1) / kPcCols));
+  for (int l0 = 0; l0 < C; l0 += kPcLabels) {
+    if (dt == RW_F64)
+      k_project_cols<double><<<grid, 256, 0, s>>>((const double*)Q, N, m, (const double*)X, C, l0, partial);
+    else
+      k_project_cols<float><<<grid, 256, 0, s>>>((const float*)Q, N, m, (const float*)X, C, l0, partial);
+    RW_LAUNCH_CHECK();
+  }
+  k_sum_chunks<<<nblocks((int64_t)m * C, 256), 256, 0, s>>>(partial, (int64_t)m * C, nch, P);
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
 static int gram_mfma_tiles(int bx, int by, bool sym) {
   const int tx = (bx + kGM - 1) / kGM, ty = (by + kGM - 1) / kGM;
   return sym ? tx * (tx + 1) / 2 : tx * ty;

@@ -996,6 +996,210 @@ __device__ void lu_lds_body(const double* Ag, int n, double* Bg, int nrhs, doubl
   if (tid == 0) stat[0] = s_minpiv / amax;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Register-resident LU for n <= 32 R (R <= kLuRegMaxR), used where the LDS elimination below does not fit
+// (its trailing block no longer fits in LDS, n > 141 or so): the 1024 threads form a 32 x 32 grid and thread
+// (ti, tj) holds the elements (ti + 32 r, tj + 32 c) of A in registers; only B (n x nrhs), the step's
+// multipliers and pivot row, and the pivots live in LDS.  The elimination is that of lu_lds_body (same pivot
+// choice: largest magnitude over the rows not yet chosen, ties to the lowest row; the same products, so the
+// same bits); a step costs two barriers and a handful of LDS reads per thread instead of a sweep of the
+// trailing block through LDS.  The pivot of column k+1 is found by the 32 threads holding that column, in
+// one half-wave, right after their update.  Back substitution by the 32 threads holding column k.
+// Measured per step (one workgroup, n = 75 / 150): 2.4 / 3.2 us against 1.7 us for the LDS elimination and
+// 6.3 us for the global one; a workgroup barrier alone costs about 0.15 us and a dependent LDS read about
+// 0.07 us, so the step is latency-bound either way.  Beyond R = 6 the register tile spills.
+// ---------------------------------------------------------------------------------------------
+constexpr int kLuRegMaxR = 6;   // n <= 192
+
+__host__ __device__ inline size_t lu_reg_bytes(int n, int nrhs) {
+  return ((size_t)(n | 1) * nrhs + 3 * (size_t)n + 18) * sizeof(double) + (size_t)n * sizeof(int);
+}
+__host__ __device__ inline bool lu_reg_fits(int n, int nrhs) {
+  return n <= 32 * kLuRegMaxR && lu_reg_bytes(n, nrhs) <= kLdsLimit;
+}
+
+template <int R>
+__device__ void lu_reg_body(const double* Ag, int n, double* Bg, int nrhs, double* stat) {
+  extern __shared__ double sm[];
+  const int ld = n | 1;
+  double* B = sm;                              // ld x nrhs
+  double* colbuf = B + (size_t)ld * nrhs;      // n: multipliers of the step (0 on rows not eliminated)
+  double* rowbuf = colbuf + n;                 // n: the pivot row
+  double* diag = rowbuf + n;                   // n: u(p_k, k)
+  double* s_wmax = diag + n;                   // 16: per-wave maxima
+  double& s_minpiv = s_wmax[16];
+  int& s_bad = *reinterpret_cast<int*>(s_wmax + 17);
+  int* prow = reinterpret_cast<int*>(s_wmax + 18);   // n: pivot row of step k
+  // (the scalars live in the dynamic allocation: the batched kernel's static LDS stays within what its
+  // dynamic size leaves)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ti = lane & 31, tj = 2 * wave + (lane >> 5);
+  double a[R][R];
+  int rpos[R];   // the step at which row ti + 32 r became the pivot row, n before
+  // a[r][c] with a run-time c (or r), by unrolled selects: a run-time index into the register array would
+  // move it to scratch memory
+  auto col_of = [&](int r, int cs) {
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < R; ++c) v = c == cs ? a[r][c] : v;
+    return v;
+  };
+  double amax = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    rpos[r] = n;
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const int i = ti + 32 * r, j = tj + 32 * c;
+      a[r][c] = (i < n && j < n) ? Ag[i + (int64_t)j * n] : 0.0;
+      amax = fmax(amax, fabs(a[r][c]));
+    }
+  }
+  for (int t = tid; t < n * nrhs; t += blockDim.x) B[(t % n) + (t / n) * ld] = Bg[t];
+  amax = wave_max64(amax);
+  if (lane == 0) s_wmax[wave] = amax;
+  if (tid == 0) {
+    s_minpiv = INFINITY;
+    s_bad = 0;
+  }
+  __syncthreads();
+  amax = s_wmax[0];
+  for (int w = 1; w < 16; ++w) amax = fmax(amax, s_wmax[w]);
+  // pivot of column k by the half-wave holding it (tj == k mod 32): largest |a| over the rows not yet chosen,
+  // ties to the lowest row
+  auto pivot = [&](int k) {
+    const int cs = k >> 5;
+    double best = -1.0, val = 0.0;
+    int brow = n;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = ti + 32 * r;
+      const double v = col_of(r, cs);
+      if (i < n && rpos[r] == n && fabs(v) > best) {   // rows in increasing order: first maximum kept
+        best = fabs(v);
+        val = v;
+        brow = i;
+      }
+    }
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o), ov = __shfl_xor(val, o);
+      const int orow = __shfl_xor(brow, o);
+      if (ob > best || (ob == best && orow < brow)) {
+        best = ob;
+        val = ov;
+        brow = orow;
+      }
+    }
+    if (ti == 0) {
+      const bool ok = brow < n && best > 1e-14 * amax;
+      prow[k] = ok ? brow : 0;
+      diag[k] = ok ? val : 1.0;
+      if (!ok) s_bad = 1;
+      s_minpiv = fmin(s_minpiv, best);
+    }
+  };
+  if (tj == 0) pivot(0);
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (s_bad) break;   // uniform
+    const int p = prow[k];
+    const double inv = 1.0 / diag[k];
+    // the multipliers of column k and the pivot row
+    if (tj == (k & 31)) {
+      const int cs = k >> 5;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = ti + 32 * r;
+        if (i < n) colbuf[i] = (rpos[r] == n && i != p) ? col_of(r, cs) * inv : 0.0;
+      }
+    }
+    if (ti == (p & 31)) {
+      const int rs = p >> 5;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        const int j = tj + 32 * c;
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v = r == rs ? a[r][c] : v;
+        if (j > k && j < n) rowbuf[j] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (r == rs) rpos[r] = k;
+    }
+    lds_barrier();
+    // the update of the rows not yet chosen, then B, then the next pivot
+    double rb[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const int j = tj + 32 * c;
+      rb[c] = (j > k && j < n) ? rowbuf[j] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = ti + 32 * r;
+      if (i < n && rpos[r] == n) {
+        const double l = colbuf[i];
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+          const int j = tj + 32 * c;
+          if (j > k && j < n) a[r][c] -= l * rb[c];
+        }
+      }
+    }
+    for (int t = tid; t < n * nrhs; t += blockDim.x) {
+      const int i = t % n, q = t / n;
+      B[i + q * ld] -= colbuf[i] * B[p + q * ld];
+    }
+    if (k + 1 < n && tj == ((k + 1) & 31)) pivot(k + 1);
+    lds_barrier();
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) stat[0] = 0.0;
+    return;
+  }
+  // back substitution over the pivot order: x_k = b(p_k) / u(p_k, k); b(p_i) -= u(p_i, k) x_k for i < k
+  for (int k = n - 1; k >= 0; --k) {
+    if (tj == (k & 31)) {
+      const int p = prow[k], cs = k >> 5;
+      const double rukk = 1.0 / diag[k];
+      for (int q = 0; q < nrhs; ++q) {
+        const double xk = B[p + q * ld] * rukk;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = ti + 32 * r;
+          if (i < n && rpos[r] < k) B[i + q * ld] -= col_of(r, cs) * xk;
+        }
+        if (ti == 0) B[p + q * ld] = xk;
+      }
+    }
+    lds_barrier();
+  }
+  for (int t = tid; t < n * nrhs; t += blockDim.x) {
+    const int k = t % n, q = t / n;
+    Bg[k + (int64_t)q * n] = B[prow[k] + q * ld];
+  }
+  if (tid == 0) stat[0] = s_minpiv / amax;
+}
+
+__device__ void lu_reg_dispatch(const double* Ag, int n, double* Bg, int nrhs, double* stat) {
+  switch ((n + 31) >> 5) {
+    case 1: lu_reg_body<1>(Ag, n, Bg, nrhs, stat); break;
+    case 2: lu_reg_body<2>(Ag, n, Bg, nrhs, stat); break;
+    case 3: lu_reg_body<3>(Ag, n, Bg, nrhs, stat); break;
+    case 4: lu_reg_body<4>(Ag, n, Bg, nrhs, stat); break;
+    case 5: lu_reg_body<5>(Ag, n, Bg, nrhs, stat); break;
+    default: lu_reg_body<6>(Ag, n, Bg, nrhs, stat); break;
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(1024) void k_lu_reg(const double* Ag, int n, double* Bg, int nrhs, double* stat) {
+  lu_reg_body<R>(Ag, n, Bg, nrhs, stat);
+}
+
 __host__ __device__ inline size_t lu_lds_bytes(int n, int nrhs) {
   const size_t ld = (size_t)(n | 1);
   return (ld * (n + nrhs)) * sizeof(double) + 2 * (size_t)n * sizeof(int);
@@ -1016,6 +1220,7 @@ __global__ __launch_bounds__(1024) void k_lu_solve_batched(const LuJob* jobs, in
   const LuJob j = jobs[blockIdx.x];
   if (j.n <= 0) return;
   if (lu_lds_fits(j.n, j.nrhs)) lu_lds_body(j.A, j.n, j.B, j.nrhs, j.stat);
+  else if (lu_reg_fits(j.n, j.nrhs)) lu_reg_dispatch(j.A, j.n, j.B, j.nrhs, j.stat);
   else lu_body(j.A, j.n, j.B, j.nrhs, j.stat);
 }
 
@@ -1026,6 +1231,11 @@ static int lu_attrs() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
     RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_solve_batched),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+    const void* regs[] = {reinterpret_cast<const void*>(k_lu_reg<1>), reinterpret_cast<const void*>(k_lu_reg<2>),
+                          reinterpret_cast<const void*>(k_lu_reg<3>), reinterpret_cast<const void*>(k_lu_reg<4>),
+                          reinterpret_cast<const void*>(k_lu_reg<5>), reinterpret_cast<const void*>(k_lu_reg<6>)};
+    for (const void* f : regs)
+      RW_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
     attr = true;
   }
   return RW_OK;
@@ -1039,9 +1249,24 @@ int lu_solve_batched(const LuJob* jobs, int count, hipStream_t s) {
   return RW_OK;
 }
 
+template <int R>
+static void launch_lu_reg(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s) {
+  k_lu_reg<R><<<1, 1024, lu_reg_bytes(n, nrhs), s>>>(A, n, B, nrhs, stat);
+}
+
 int lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s) {
   if (n <= 0) return RW_OK;
-  if (lu_lds_fits(n, nrhs)) {
+  if (!lu_lds_fits(n, nrhs) && lu_reg_fits(n, nrhs)) {
+    RW_TRY(lu_attrs());
+    switch ((n + 31) >> 5) {
+      case 1: launch_lu_reg<1>(A, n, B, nrhs, stat, s); break;
+      case 2: launch_lu_reg<2>(A, n, B, nrhs, stat, s); break;
+      case 3: launch_lu_reg<3>(A, n, B, nrhs, stat, s); break;
+      case 4: launch_lu_reg<4>(A, n, B, nrhs, stat, s); break;
+      case 5: launch_lu_reg<5>(A, n, B, nrhs, stat, s); break;
+      default: launch_lu_reg<6>(A, n, B, nrhs, stat, s); break;
+    }
+  } else if (lu_lds_fits(n, nrhs)) {
     RW_TRY(lu_attrs());
     k_lu_solve_lds<<<1, 1024, lu_lds_bytes(n, nrhs), s>>>(A, n, B, nrhs, stat);
   } else {

@@ -284,13 +284,12 @@ static int project_bf16(const uint16_t* Q, int64_t N, int m, const float* X, int
 
 size_t project_block_partial_bytes(int64_t N, int m, int C) {
   return std::max(project_partial_count(N, std::min(m, 16 * kProjMaxChunks)) * sizeof(float),
-                  gram_partial_count(N, m, C) * sizeof(double));
+                  project_cols_partial_count(N, m, C) * sizeof(double));
 }
 
 int project_block(const void* Q, int qdt, int64_t N, int m, const void* X, int C, double* P, void* partial,
                   double* tmp, hipStream_t s) {
-  if (qdt == RW_F64 || qdt == RW_F32)
-    return gram(qdt, Q, N, X, N, N, m, C, P, static_cast<double*>(partial), s);
+  if (qdt == RW_F64 || qdt == RW_F32) return project_cols(qdt, Q, N, m, X, C, P, static_cast<double*>(partial), s);
   const BasisView b = basis_view(N, Q, qdt);
   RW_TRY(project_bf16(static_cast<const uint16_t*>(b.hi), N, m, static_cast<const float*>(X), C, P, m,
                       static_cast<float*>(partial), s));
@@ -325,7 +324,7 @@ int rw_convert_block(const void* src, int src_dtype, void* dst, int dst_dtype, i
 
 int rw_project_workspace_bytes(int64_t N, int m, int C, size_t* bytes) {
   RW_CHECK(bytes != nullptr && N >= 1 && m >= 1 && C >= 1, RW_EINVAL, "bad sizes");
-  *bytes = std::max(project_partial_count(N, m) * sizeof(float), gram_partial_count(N, m, C) * sizeof(double));
+  *bytes = std::max(project_partial_count(N, m) * sizeof(float), project_cols_partial_count(N, m, C) * sizeof(double));
   return RW_OK;
 }
 
@@ -336,7 +335,7 @@ int rw_project_basis(const void* Q, int q_dtype, int64_t N, int m, const float* 
   size_t need = 0;
   RW_TRY(rw_project_workspace_bytes(N, m, C, &need));
   RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "projection workspace too small: %zu < %zu", work_bytes, need);
-  if (q_dtype == RW_F32) return gram(RW_F32, Q, N, X, N, N, m, C, P, static_cast<double*>(work), stream);
+  if (q_dtype == RW_F32) return project_cols(RW_F32, Q, N, m, X, C, P, static_cast<double*>(work), stream);
   RW_CHECK(q_dtype == RW_BF16, RW_EINVAL,
            "projection supports F32 (VALU) and BF16 (matrix cores) bases (a pair form's plain block is BF16)");
   RW_CHECK(C <= 8 && m <= 16 * kProjMaxChunks, RW_EINVAL, "matrix-core projection needs C <= 8 and m <= 256");

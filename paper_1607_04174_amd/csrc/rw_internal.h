@@ -310,6 +310,10 @@ int convert_pair(int dt_src, const void* src, int64_t rows, uint16_t* dst, int c
 // the matrix cores (the pair form's remainder columns add to rows 1 .. 8).  partial: project_block_partial_bytes;
 // tmp: 8 C doubles (pair form only).
 size_t project_block_partial_bytes(int64_t N, int m, int C);
+// the VALU projection of F64 / F32 bases behind project_block (FP64 accumulation, fixed-order chunk sums)
+size_t project_cols_partial_count(int64_t N, int m, int C);
+int project_cols(int dt, const void* Q, int64_t N, int m, const void* X, int C, double* P, double* partial,
+                 hipStream_t s);
 int project_block(const void* Q, int qdt, int64_t N, int m, const void* X, int C, double* P, void* partial,
                   double* tmp, hipStream_t s);
 // column norms (FP64 out) of R = A - B diag(theta) (theta may be null: plain norms of A)
