@@ -60,7 +60,7 @@ def main():
     dev = torch.device("cuda", 0)
     w = rwsynth.CFG2
     if args.traffic_probe:
-        traffic_probe(rw, rwsynth, torch, w, dev)
+        traffic_probe(rw, rwsynth, torch, rwsynth.CFG3 if args.workload == "volume128" else w, dev)
         return
     if args.workload != "interactive512":
         line = MODES[args.workload](args, rw, rwsynth, torch, dev)
