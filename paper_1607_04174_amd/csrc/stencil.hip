@@ -79,7 +79,13 @@ template <> struct Buf<double> {
 //                                   fused:      buffer R = 4 638 us, global R = 4 695 us, R = 2 684-694 us;
 // all with two column groups (one or four were slower).  The 3D kernel runs at the same speed from HBM as from
 // the caches (about 0.48 of 8 TB/s): it is bound by its loads' issue, not by HBM.
-template <typename T, int NDIR, int R, bool ZT, bool BUF>
+// 2D tiles: WX waves side by side along x (64 WX columns) and 4 / WX strips along y.  For the 2D plain operator
+// (the eigensolver's residual and Rayleigh-Ritz products) tiles two waves wide with 8-row strips, buffer loads
+// and four column groups took 95 us against 110 us for the 64-wide tiles (copy of the same bytes: 81 us;
+// 8-wide strips of one-wave tiles, R = 4 or 16, or eight groups were slower; taking x +- 1 from neighbouring
+// lanes by DPP wave shifts instead of loads took 143 us).  AB: alpha and beta are folded into the coefficients
+// (off for the plain operator, which then uses them as stored; with the folding the same tiles took 114 us).
+template <typename T, int NDIR, int R, bool ZT, bool BUF, int WX = 1, bool AB = true>
 __global__ __launch_bounds__(256) void k_stencil_strip(StencilArgs<T> a, StripMap tm) {
   using C = typename Elem<T>::C;
   constexpr bool D3 = NDIR == 3;
@@ -90,14 +96,15 @@ __global__ __launch_bounds__(256) void k_stencil_strip(StencilArgs<T> a, StripMa
   const int nx = (int)a.G.nx, ny = (int)a.G.ny, nz = (int)a.G.nz, N = (int)a.G.N;
   const int tx = tile % tm.tiles_x;
   const int t2 = tile / tm.tiles_x;
-  const int x = tx * 64 + threadIdx.x;
+  static_assert(WX == 1 || !D3, "3D tiles are one wave wide");
+  const int x = (tx * WX + (int)threadIdx.y % WX) * 64 + threadIdx.x;
   int y = 0, s0 = 0;     // 3D: y row and first z of the strip; 2D: first y of the strip
   if constexpr (D3) {
     y = (t2 % tm.tiles_y) * 4 + threadIdx.y;
     s0 = (t2 / tm.tiles_y) * R;
     if (x >= nx || y >= ny) return;
   } else {
-    s0 = (t2 * 4 + threadIdx.y) * R;
+    s0 = (t2 * (4 / WX) + (int)threadIdx.y / WX) * R;
     if (x >= nx || s0 >= ny) return;
   }
   const int plane = nx * ny;
@@ -134,15 +141,15 @@ __global__ __launch_bounds__(256) void k_stencil_strip(StencilArgs<T> a, StripMa
       yy = clampi(yy, ny);
     }
     const int i = x + nx * yy + plane * zz;
-    dg[k] = ok[k] ? al * (C)a.diag[i] + be : C(0);
+    dg[k] = ok[k] ? (AB ? al * (C)a.diag[i] + be : (C)a.diag[i]) : C(0);
 #pragma unroll
     for (int d = 0; d < NDIR; ++d) {
       const int hx = x + a.G.dx[d], hy = yy + a.G.dy[d], hz = zz + a.G.dz[d];
       const bool f = ok[k] && hx >= 0 && hx < nx && hy >= 0 && hy < ny && hz >= 0 && hz < nz;
-      c[k][d] = f ? al * (C)a.coef[d * N + i] : C(0);
+      c[k][d] = f ? (AB ? al : C(1)) * (C)a.coef[d * N + i] : C(0);
       const int ux = x - a.G.dx[d], uy = yy - a.G.dy[d], uz = zz - a.G.dz[d];
       const bool t = ok[k] && ux >= 0 && ux < nx && uy >= 0 && uy < ny && uz >= 0 && uz < nz;
-      c[k][NDIR + d] = t ? al * (C)a.coef[d * N + i - (int)a.G.off[d]] : C(0);
+      c[k][NDIR + d] = t ? (AB ? al : C(1)) * (C)a.coef[d * N + i - (int)a.G.off[d]] : C(0);
     }
   }
   const int c0 = blockIdx.y * tm.cpg;
@@ -279,12 +286,13 @@ __global__ __launch_bounds__(256) void k_stencil_wide(StencilArgs<T> a) {
   }
 }
 
-// Strip length and column groups.  2D: R = 2; 3D: R = 4.  Groups: enough threads to cover the chip
-// about once (256 CUs x 1024 threads), at least 4 columns per group, at most 8 groups.
+// Strip length and column groups.  Groups: enough threads to cover the chip about once (256 CUs x 1024
+// threads), at least 4 columns per group, at most 8 groups; gforce > 0 fixes the number of groups (still
+// doubled while the 32-bit offsets need it).  WX: waves per tile along x (2D).
 template <int NDIR>
-static StripMap strip_map(const Graph* g, int R, int64_t b, dim3* grid) {
+static StripMap strip_map(const Graph* g, int R, int64_t b, dim3* grid, int WX = 1, int gforce = 0) {
   StripMap tm;
-  tm.tiles_x = (int)nblocks(g->nx, 64);
+  tm.tiles_x = (int)nblocks(g->nx, 64 * WX);
   int64_t strips;
   if (NDIR == 3) {
     tm.tiles_y = (int)nblocks(g->ny, 4);
@@ -292,12 +300,13 @@ static StripMap strip_map(const Graph* g, int R, int64_t b, dim3* grid) {
     tm.ntiles = (int)strips;
   } else {
     tm.tiles_y = 0;
-    tm.ntiles = (int)((int64_t)tm.tiles_x * nblocks(nblocks(g->ny, R), 4));
+    tm.ntiles = (int)((int64_t)tm.tiles_x * nblocks(nblocks(g->ny, R), 4 / WX));
   }
   const int64_t threads = (int64_t)tm.ntiles * 256;
   int G = 1;
   while (G < 8 && threads * G < (int64_t)256 * 1024 && (b + 2 * G - 1) / (2 * G) >= 4) G *= 2;
   if (threads >= 64 * 1024 && b >= 8) G = 2;   // large grids: two groups (measured best, see the kernel)
+  if (gforce > 0) G = (int)std::max<int64_t>(1, std::min<int64_t>(gforce, b));
   tm.cpg = (int)((b + G - 1) / G);
   // the buffer offsets of a column group, (cpg - 1) cs + node offsets, stay below 2^32
   const uint64_t cs = (uint64_t)g->N * dtype_size(g->dtype);
@@ -337,6 +346,10 @@ static int launch(const Graph* g, const void* X, void* Y, const void* Z, int64_t
     } else if (zt && sizeof(T) == 4) {               // 2D fused FP32: buffer loads, four nodes per thread
       StripMap tm = strip_map<NDIR>(g, 4, b, &grid);
       k_stencil_strip<T, NDIR, 4, true, true><<<grid, block, 0, s>>>(a, tm);
+    } else if (sizeof(T) == 4 && alpha == 1.0 && beta == 0.0) {
+      // 2D plain FP32: 128-column tiles of two 8-row strips, buffer loads, four column groups
+      StripMap tm = strip_map<NDIR>(g, 8, b, &grid, 2, 4);
+      k_stencil_strip<T, NDIR, 8, false, true, 2, false><<<grid, block, 0, s>>>(a, tm);
     } else {                                         // 2D plain, and FP64: global loads, two nodes per thread
       StripMap tm = strip_map<NDIR>(g, 2, b, &grid);
       if (zt) k_stencil_strip<T, NDIR, 2, true, false><<<grid, block, 0, s>>>(a, tm);
