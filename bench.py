@@ -40,6 +40,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-compare", action="store_true", help="skip the update-vs-recompute comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-eigsh", action="store_true",
+                    help="also time the oracle's eigsh recompute of the 512x512 basis (minutes of CPU time)")
     ap.add_argument("--spmm-reps", type=int, default=20)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch the stencil block and a plain copy of the same block (for HBM counters)")
@@ -215,6 +217,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(w, J, node, lab, edits, Q0, lam0, solves_per_step)
+        if args.cpu_eigsh:
+            cpu["recompute"] = cpu_recompute_eigsh(w, J, w.m)
 
     out = {
         "metric": "RW solves/s + eigvec-update vs recompute time at fixed error; SpMV HBM GB/s",
@@ -307,24 +311,53 @@ def cpu_baseline(w, J, node, lab, edits, Q0, lam0, solves_per_step):
         cores = os.cpu_count()
     Q = Q0.to(torch.float64).cpu().numpy().T
     lam = lam0.cpu().numpy()
-    og = OGraph(J, w.dims, w.conn, w.beta)
-    t0 = time.perf_counter()
-    m, _, _ = choose_m(og, Q, node, lab, w.C, eps=0.1)
-    fast_rw_coeffs(og, Q, lam, node, lab, w.C, m=m)
-    t_solve = time.perf_counter() - t0
-    og.apply_edit(edits[0])
-    t0 = time.perf_counter()
-    rayleigh_ritz(og, Q)
-    t_upd = time.perf_counter() - t0
     n_upd = solves_per_step - 1
+
+    def sample():
+        og = OGraph(J, w.dims, w.conn, w.beta)
+        t0 = time.perf_counter()
+        m, _, _ = choose_m(og, Q, node, lab, w.C, eps=0.1)
+        fast_rw_coeffs(og, Q, lam, node, lab, w.C, m=m)
+        t_solve = time.perf_counter() - t0
+        og.apply_edit(edits[0])
+        t0 = time.perf_counter()
+        rayleigh_ritz(og, Q)
+        return t_solve, time.perf_counter() - t0
+
+    t_solve, t_upd = sample()
     step_s = solves_per_step * t_solve + n_upd * t_upd
     log(f"cpu oracle: solve {t_solve:.2f}s, update {t_upd:.2f}s -> {solves_per_step / step_s:.4f} solves/s")
+    single = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            s1, u1 = sample()
+        single = {"value": round(solves_per_step / (solves_per_step * s1 + n_upd * u1), 5), "cores": 1,
+                  "solve_s": round(s1, 3), "update_s": round(u1, 3)}
+        log(f"cpu oracle, one thread: solve {s1:.2f}s, update {u1:.2f}s")
+    except ImportError:
+        pass
     return {"value": round(solves_per_step / step_s, 5), "unit": "RW solves/s", "cores": int(cores),
             "kind": "oracle",
             "sample": "one solve (choice of m by linear scan, bordered system, coefficients) and one "
                       "Rayleigh-Ritz update (beta edit) of the 512x512 workload, FP64, scaled to a step of "
                       f"{solves_per_step} solves + {n_upd} updates",
-            "solve_s": round(t_solve, 3), "update_s": round(t_upd, 3)}
+            "solve_s": round(t_solve, 3), "update_s": round(t_upd, 3), "single_thread": single}
+
+
+def cpu_recompute_eigsh(w, J, m, tol=1e-5):
+    """The oracle's recompute of the m smallest eigenpairs of the 512x512 operator by scipy's eigsh
+    (shift-invert about a point below the spectrum), for the update-vs-recompute comparison on the CPU."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    from oracle.graph import Graph as OGraph
+    og = OGraph(J, w.dims, w.conn, w.beta)
+    M = og.M().tocsc()
+    t0 = time.perf_counter()
+    vals, _ = spla.eigsh(M, k=m, sigma=-1e-3, which="LM", tol=tol)
+    t = time.perf_counter() - t0
+    log(f"cpu oracle eigsh: {m} pairs in {t:.1f}s")
+    return {"eigsh_recompute_s": round(t, 2), "pairs": m, "tol": tol, "lambda_max": float(vals.max())}
 
 
 # ---------------------------------------------------------------------------------------------
