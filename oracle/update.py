@@ -12,6 +12,12 @@ Readings:
     in their stored order (the process the paper uses after eq. (33)) before the quotients.
   * Rayleigh-Ritz (beyond the paper's diagonal update): the same basis, then the eigenpairs of the
     projected matrix H = Q'^T L_hat Q' rotate it.
+  * Bank of bases for several beta (the end of Sec. III-B: eigenvectors precomputed for several beta and
+    eq. (26) used to "interpolate" between them): for the requested operator, every bank basis gets its
+    diagonal update, and the basis whose quotients sum lowest is used with its lambda_hat.  Among
+    orthonormal bases of m columns the sum of the Rayleigh quotients is smallest for the eigenbasis of the
+    m smallest eigenvalues (Ky Fan), so the sum ranks the bases by how well they span the new low
+    spectrum.
 """
 from __future__ import annotations
 
@@ -51,3 +57,17 @@ def rayleigh_ritz(graph_new, Q):
     th, V = np.linalg.eigh(H)
     out = np.concatenate([Qn[:, :1], Qp @ V], axis=1)
     return fix_signs(out), np.concatenate([[0.0], th])
+
+
+def bank_select(graph_new, bank):
+    """Choose among the bases of a bank (a list of N x m arrays) for the operator of graph_new:
+    (index, Q_new, lambda_hat, traces) with traces[b] = sum of the diagonal quotients of basis b."""
+    best = None
+    traces = []
+    for b, Q in enumerate(bank):
+        Qn, lam = diag_rq(graph_new, Q)
+        t = float(lam.sum())
+        traces.append(t)
+        if best is None or t < best[3]:
+            best = (b, Qn, lam, t)
+    return best[0], best[1], best[2], np.array(traces)

@@ -12,7 +12,7 @@ from oracle.choose_m import choose_m, f_values, lsqi
 from oracle.eigen import certify, dense_eigpairs, principal_angle_sines
 from oracle.exact_rw import exact_rw
 from oracle.graph import Graph
-from oracle.update import diag_rq, rayleigh_ritz
+from oracle.update import bank_select, diag_rq, rayleigh_ritz
 
 
 @pytest.mark.parametrize("shape,rho", [((8, 3), 0.5), ((8, 3), 50.0), ((4, 7), 0.8), ((4, 7), 100.0),
@@ -162,3 +162,22 @@ def test_adjoint_cg_equals_direct(dims, conn):
     got = adjoint_grads(g, node, lab, 3, ce_grad(Ucg, gt, node), Ucg, method="cg", tol=1e-13)
     for a, b in zip(got, ref):
         np.testing.assert_allclose(a, b, rtol=1e-8, atol=1e-10 * max(1.0, np.abs(b).max()))
+
+
+def test_bank_select_prefers_the_current_eigenbasis():
+    """Ky Fan: among orthonormal bases of m columns the exact eigenbasis of the m smallest eigenvalues has the
+    smallest quotient sum, so a bank holding it (beside the bases of other beta) selects it, and its sum is the
+    sum of those eigenvalues."""
+    w = rwsynth.small("tb", (9, 8), 4, C=2, seeds_per_label=3, n_shapes=2)
+    J, rid = rwsynth.phantom(w)
+    bank, betas = [], (20.0, 40.0, 80.0)
+    for b in betas:
+        _, Q = dense_eigpairs(Graph(J, (9, 8, 1), 4, beta=b), 12)
+        bank.append(Q)
+    target = Graph(J, (9, 8, 1), 4, beta=40.0)
+    idx, Qn, lam, traces = bank_select(target, bank)
+    assert idx == 1
+    ev = np.linalg.eigvalsh(target.M().toarray())[:12]
+    np.testing.assert_allclose(traces[1], ev.sum(), rtol=1e-10, atol=1e-12)
+    assert traces[0] > traces[1] and traces[2] > traces[1]
+    np.testing.assert_allclose(lam, diag_rq(target, bank[1])[1], rtol=1e-14)
