@@ -46,7 +46,7 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch the stencil block and a plain copy of the same block (for HBM counters)")
     ap.add_argument("--workload", default="interactive512",
-                    choices=["interactive512", "small64", "volume128", "batch64", "grad96", "prior512"],
+                    choices=["interactive512", "small64", "volume128", "batch64", "grad96", "prior512", "bank512"],
                     help="interactive512 (default, the headline line); the others measure the remaining "
                          "configurations and print their own line")
     args = ap.parse_args()
@@ -712,8 +712,51 @@ def run_prior512(args, rw, rwsynth, torch, dev):
                  parity=parity, cpu_baseline=cpu)
 
 
+def run_bank512(args, rw, rwsynth, torch, dev):
+    """512 x 512, 8-connected, FP32, m = 200: bases precomputed for beta' in {45, 90, 180}; for beta = 150 the
+    bank selection (diagonal update of each basis, eq. (27); the smallest quotient sum) and a solve with the
+    chosen basis, against a solve with the basis computed for beta = 150 itself."""
+    w = rwsynth.CFG2
+    J, rid = rwsynth.phantom(w, 0)
+    node, lab = rwsynth.seeds(w, rid, 0)
+    Jd = torch.as_tensor(J, device=dev)
+    betas, beta = (45.0, 90.0, 180.0), 150.0
+    bank = []
+    t0 = time.perf_counter()
+    for b in betas:
+        gb = rw.Graph(Jd, w.dims, w.conn, b, dtype=torch.float32)
+        bank.append(rw.precompute_eig(gb, w.m, tol=1e-5, max_iter=400)[0].contiguous())
+    torch.cuda.synchronize()
+    t_bank = time.perf_counter() - t0
+    g = rw.Graph(Jd, w.dims, w.conn, beta, dtype=torch.float32)
+    ws = rw.SolveWorkspace()
+
+    def step():
+        idx, Q, lam, tr = rw.bank_select(g, bank)
+        U, info = rw.solve_seeds(g, Q, lam, node, lab, w.C, eps=0.1, workspace=ws)
+        return idx, tr, U, info
+
+    for _ in range(args.warmup):
+        step()
+    t, (idx, tr, U, info) = _sync_time(torch, step, args.steps)
+    t_sel, _ = _sync_time(torch, lambda: rw.bank_select(g, bank), args.steps)
+    Qx, lamx, _ = rw.precompute_eig(g, w.m, tol=1e-5, max_iter=400)
+    Ux, infox = rw.solve_seeds(g, Qx, lamx, node, lab, w.C, eps=0.1, workspace=ws)
+    agree = float((U.argmax(dim=0) == Ux.argmax(dim=0)).double().mean())
+    maxabs = float((U.double() - Ux.double()).abs().max())
+    log(f"bank512: chose beta' = {betas[idx]} (sums {[round(x, 4) for x in tr]}), selection {t_sel * 1e3:.2f} ms, "
+        f"selection + solve {t * 1e3:.2f} ms; labels agree with the beta = 150 basis on {agree:.4f} of the voxels")
+    return _line("bank selection + RW solves/s (beta changed online, bases precomputed for three other beta)",
+                 round(1.0 / t, 2), "solves/s", args, t * 1e3, "f32 graph/basis + f64 quotients and seed system",
+                 {"workload": "2D 512x512 8-connected phantom, FP32 bases m=200 for beta' 45/90/180, beta 150, "
+                              "C=3, 50 seeds/label, eps 0.1", "N": w.N, "m": w.m, "C": w.C, "S": int(node.size)},
+                 chosen_beta=betas[idx], quotient_sums=tr, selection_ms=round(t_sel * 1e3, 3),
+                 bank_precompute_s=round(t_bank, 2), m_used=info["m_used"],
+                 vs_exact_beta_basis={"label_agreement": agree, "maxabs": maxabs, "m_used": infox["m_used"]})
+
+
 MODES = {"small64": run_small64, "volume128": run_volume128, "batch64": run_batch64, "grad96": run_grad96,
-         "prior512": run_prior512}
+         "prior512": run_prior512, "bank512": run_bank512}
 
 
 if __name__ == "__main__":

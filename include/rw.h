@@ -205,6 +205,21 @@ int rw_update_eig(rw_graph g, const rw_edit* edits, int n_edits, int mode, const
                   void* Q, double* lambda, int m, void* work, size_t work_bytes, hipStream_t stream,
                   rw_eig_info* info);
 
+/* Bank of bases precomputed for several beta (Sec. III-B, last paragraph: eigenvectors for several beta, with
+ * the Rayleigh quotients of eq. (26) interpolating between them).  For g's current operator, every basis of the
+ * bank (nbank device pointers, each column-major N x m of opts->q_dtype, the graph's dtype) gets the diagonal
+ * update of rw_update_eig's RW_UPDATE_DIAG_RQ mode (eq. (27): null vector replaced, the other columns
+ * re-orthonormalized in order, lambda_hat_i = q_i^T op q_i), and the basis whose quotients sum lowest is
+ * written, updated, to Q_out (device, N x m, not a bank basis) with lambda_out (device, m FP64).  The smallest
+ * sum marks the basis closest to the current low spectrum: the eigenbasis of the m smallest eigenvalues has
+ * the smallest sum among orthonormal bases (Ky Fan).  The bank is read only.  *chosen (host) receives the
+ * index; traces (host, nbank, may be null) the sums.  work: rw_bank_workspace_bytes.  Synchronizes `stream`.
+ * Errors: RW_EINVAL, RW_EWORKSPACE, RW_ESINGULAR (a basis is linearly dependent). */
+int rw_bank_workspace_bytes(rw_graph g, int m, const rw_eig_opts* opts, size_t* bytes);
+int rw_bank_select(rw_graph g, const void* const* Q_bank, int nbank, const rw_eig_opts* opts, int m, void* Q_out,
+                   double* lambda_out, void* work, size_t work_bytes, hipStream_t stream, int* chosen,
+                   double* traces);
+
 /* ======================================================================================
  * Checkpoint of the offline phase (Sec. II-B: the eigenpairs are computed once, offline)
  * ====================================================================================== */

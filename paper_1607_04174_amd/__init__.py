@@ -128,6 +128,10 @@ _SIGS = {
     "rw_priors_workspace_bytes": (ct.c_int, [ct.c_int, ct.POINTER(ct.c_size_t)]),
     "rw_priors_from_seeds": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int, ct.c_void_p,
                                         ct.c_int, ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p]),
+    "rw_bank_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(rw_eig_opts), ct.POINTER(ct.c_size_t)]),
+    "rw_bank_select": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_void_p), ct.c_int, ct.POINTER(rw_eig_opts), ct.c_int,
+                                  ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p,
+                                  ct.POINTER(ct.c_int), ct.c_void_p]),
     "rw_dense_syev_workspace_bytes": (ct.c_int, [ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]),
     "rw_dense_syev": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_size_t,
                                  ct.c_void_p]),
@@ -382,6 +386,27 @@ def update_eig(g: Graph, edits, Q: torch.Tensor, lam: torch.Tensor, mode: int = 
         _check(st)
     return {"iters": info.iters, "n_converged": info.n_converged, "spmm_columns": info.spmm_columns,
             "max_residual": info.max_residual, "seconds": info.seconds, "status": st}
+
+
+def bank_select(g: Graph, bank, tol: float = 1e-5):
+    """Choose among bases (a list of (m, N) tensors of the graph's dtype) for g's current operator.
+    Returns (index, Q (m, N) updated copy, lambda_hat (m,), quotient sums per basis)."""
+    m = bank[0].shape[0]
+    dt = bank[0].dtype
+    for Q in bank:
+        assert Q.shape == bank[0].shape and Q.dtype == dt and Q.is_contiguous()
+    o = _eig_opts(tol, 1, 0, 0, 0, 1, dt)
+    nb = ct.c_size_t()
+    _check(lib().rw_bank_workspace_bytes(g.handle, m, ct.byref(o), ct.byref(nb)))
+    work = _workspace(nb.value, g.device)
+    ptrs = (ct.c_void_p * len(bank))(*[Q.data_ptr() for Q in bank])
+    Q_out = torch.empty_like(bank[0])
+    lam = torch.empty(m, dtype=torch.float64, device=g.device)
+    chosen = ct.c_int(-1)
+    traces = (ct.c_double * len(bank))()
+    _check(lib().rw_bank_select(g.handle, ptrs, len(bank), ct.byref(o), m, _ptr(Q_out), _ptr(lam), _ptr(work),
+                                nb.value, _stream(g.device), ct.byref(chosen), traces))
+    return chosen.value, Q_out, lam, list(traces)
 
 
 # ---------------------------------------------------------------------------------------------
