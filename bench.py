@@ -46,7 +46,8 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only launch the stencil block and a plain copy of the same block (for HBM counters)")
     ap.add_argument("--workload", default="interactive512",
-                    choices=["interactive512", "small64", "volume128", "batch64", "grad96", "prior512", "bank512"],
+                    choices=["interactive512", "small64", "volume128", "batch64", "grad96", "prior512", "bank512",
+                             "agg512"],
                     help="interactive512 (default, the headline line); the others measure the remaining "
                          "configurations and print their own line")
     args = ap.parse_args()
@@ -755,8 +756,73 @@ def run_bank512(args, rw, rwsynth, torch, dev):
                  vs_exact_beta_basis={"label_agreement": agree, "maxabs": maxabs, "m_used": infox["m_used"]})
 
 
+def run_agg512(args, rw, rwsynth, torch, dev):
+    """512 x 512, 8-connected, FP32 graph and basis (m = 200), C = 3, 50 seeds per label, aggregated into 2 x 2
+    blocks (N_bar = N / 4): the aggregated graph, the eq. (33) transfer of the basis with Gram-Schmidt and the
+    normalized-cut values, the seeds moved to their blocks, the solve on the blocks and the propagation back."""
+    w = rwsynth.CFG2
+    s = 2
+    J, rid = rwsynth.phantom(w, 0)
+    node, lab = rwsynth.seeds(w, rid, 0)
+    Jd = torch.as_tensor(J, device=dev)
+    g = rw.Graph(Jd, w.dims, w.conn, w.beta, dtype=torch.float32)
+    t_pre, (Q, lam, _) = _sync_time(torch, lambda: rw.precompute_eig(g, w.m, tol=1e-5, max_iter=400), 1)
+    Q = Q.contiguous()
+    ws = rw.SolveWorkspace()
+
+    def step():
+        c = rw.aggregate(g, s)
+        Qc, lamc = rw.aggregate_basis(g, c, s, Q)
+        cn, cl = rw.aggregate_seeds(g, s, node, lab)
+        Uc, info = rw.solve_seeds(c, Qc, lamc, cn, cl, w.C, eps=0.1, workspace=ws)
+        return c, Qc, lamc, Uc, rw.prolong(g, s, Uc), info
+
+    for _ in range(args.warmup):
+        step()
+    t, (c, Qc, lamc, Uc, U, info) = _sync_time(torch, step, args.steps)
+    t_tr, _ = _sync_time(torch, lambda: rw.aggregate_basis(g, c, s, Q), args.steps)
+    # the paper's baseline: a basis computed on the aggregated graph itself (not known before the aggregation)
+    Qd, lamd, _ = rw.precompute_eig(c, w.m, tol=1e-5, max_iter=400)
+    cn, cl = rw.aggregate_seeds(g, s, node, lab)
+    Ud, infod = rw.solve_seeds(c, Qd, lamd, cn, cl, w.C, eps=0.1, workspace=ws)
+    Uf, _ = rw.solve_seeds(g, Q, lam, node, lab, w.C, eps=0.1, workspace=ws)
+    lab_t, lab_d, lab_f = Uc.argmax(dim=0), Ud.argmax(dim=0), Uf.argmax(dim=0)
+    vs_direct = float((lab_t == lab_d).double().mean())
+    vs_full = float((U.argmax(dim=0) == lab_f).double().mean())
+    log(f"agg512: {t * 1e3:.2f} ms per aggregation + transfer + solve + propagation (transfer {t_tr * 1e3:.2f} ms), "
+        f"N_bar {c.N}, m_used {info['m_used']}; labels agree with the direct basis on {vs_direct:.4f} of the blocks, "
+        f"with the full-graph solve on {vs_full:.4f} of the voxels")
+    parity = None
+    cpu = None
+    if not args.no_cpu:
+        from oracle.aggregate import coarse_seeds, prolong, transfer_basis
+        from oracle.fast_rw import fast_rw
+        from oracle.graph import Graph as OGraph
+        og = OGraph(J, w.dims, w.conn, w.beta)
+        t0 = time.perf_counter()
+        co, Qo, lamo = transfer_basis(og, Q.double().cpu().numpy().T, s)
+        cno, clo = coarse_seeds(og, s, node, lab)
+        Uo = prolong(og, s, fast_rw(co, Qo, lamo, cno, clo, w.C, m=info["m_used"]))
+        t_o = time.perf_counter() - t0
+        wv = c.view()["weight"].double().cpu().numpy()
+        parity = {"weights_vs_oracle_maxrel": float(np.max(np.abs(wv[co.dir, co.tail] - co.w) / np.abs(co.w))),
+                  "basis_vs_oracle_maxabs": float(np.abs(Qc.double().cpu().numpy().T - Qo).max()),
+                  "lambda_vs_oracle_maxabs": float(np.abs(lamc.cpu().numpy() - lamo).max()),
+                  "probabilities_vs_oracle_maxabs": float(np.abs(U.double().cpu().numpy().T - Uo).max())}
+        cpu = {"value": round(1.0 / t_o, 4), "unit": "solves/s", "cores": int(_cores()), "kind": "oracle",
+               "sample": "one aggregation + transfer + coarse solve + propagation of this workload (dense FP64 numpy)"}
+    return _line("aggregated RW solves/s (eq. (33) transfer + solve on 2x2 blocks + propagation)", round(1.0 / t, 2),
+                 "solves/s", args, t * 1e3, "f32 graph/basis + f64 Gram-Schmidt, quotients and seed system",
+                 {"workload": "2D 512x512 8-connected phantom, beta 90, FP32 basis m=200, C=3, 50 seeds/label, "
+                              "2x2 blocks", "N": w.N, "N_bar": c.N, "m": w.m, "C": w.C, "S": int(node.size)},
+                 m_used=info["m_used"], transfer_ms=round(t_tr * 1e3, 3), precompute_s=round(t_pre, 2),
+                 vs_direct_basis={"label_agreement": vs_direct, "m_used": infod["m_used"]},
+                 vs_full_graph={"label_agreement": vs_full}, parity=parity, cpu_baseline=cpu)
+
+
 MODES = {"small64": run_small64, "volume128": run_volume128, "batch64": run_batch64, "grad96": run_grad96,
-         "prior512": run_prior512, "bank512": run_bank512}
+         "prior512": run_prior512, "bank512": run_bank512,
+         "agg512": run_agg512}
 
 
 if __name__ == "__main__":

@@ -220,6 +220,32 @@ int rw_bank_select(rw_graph g, const void* const* Q_bank, int nbank, const rw_ei
                    double* lambda_out, void* work, size_t work_bytes, hipStream_t stream, int* chosen,
                    double* traces);
 
+/* ---- vertex aggregation (Sec. III-C) over regular blocks of s x s (x s) voxels, the last ones clipped ---- */
+
+/* Description of the aggregated graph of g for blocks of s (the block grid, g's connectivity, dtype, weight form
+ * and operator form).  Host only.  Errors: RW_EINVAL (s < 1, fewer than two blocks). */
+int rw_aggregate_desc(rw_graph g, int s, rw_graph_desc* desc);
+int rw_aggregate_workspace_bytes(rw_graph g, int s, size_t* bytes);
+/* Build the aggregated graph in coarse_buf (rw_graph_bytes of rw_aggregate_desc): intensities 0 and per-edge
+ * scales equal to the summed FP64 weights of g's edges joining the two blocks, so its Laplacian is P^T L P for
+ * the 0/1 assignment matrix P.  The caller destroys it with rw_graph_destroy.  Synchronizes `stream`. */
+int rw_aggregate_graph(rw_graph g, int s, void* coarse_buf, size_t coarse_bytes, void* work, size_t work_bytes,
+                       hipStream_t stream, rw_graph* coarse);
+/* Eq. (33): Qc(y, j) = sum over the vertices x of block y of Delta(x) Q(x, j) / |y|, with Delta(x) twice the
+ * number of x's present edges whose other end lies in another block (the edges inside a block are consumed by
+ * it).  Q device column-major N x m (RW_F64 or RW_F32), Qc device N_bar x m of the same type.  Follow with
+ * rw_update_eig(coarse, NULL, 0, RW_UPDATE_DIAG_RQ, ...) for the Gram-Schmidt step and the normalized-cut values
+ * on the aggregated graph. */
+int rw_aggregate_basis(rw_graph g, int s, const void* Q, int q_dtype, int m, void* Qc, void* work,
+                       size_t work_bytes, hipStream_t stream);
+/* Seeds moved to their blocks (host arrays; out_* hold at least S entries): sorted, distinct.  Errors: RW_EINVAL
+ * (a node out of range, two labels in one block). */
+int rw_aggregate_seeds(rw_graph g, int s, const int64_t* seed_node, const int32_t* seed_label, int64_t S,
+                       int64_t* out_node, int32_t* out_label, int64_t* S_out);
+/* Propagation back to g (eq. (30) with eta(x, y) = 1 for x's block): U(c, x) = Uc(c, block of x); Uc device
+ * C x N_bar, U device C x N, g's dtype. */
+int rw_prolong(rw_graph g, int s, const void* Uc, int C, void* U, hipStream_t stream);
+
 /* ======================================================================================
  * Checkpoint of the offline phase (Sec. II-B: the eigenpairs are computed once, offline)
  * ====================================================================================== */

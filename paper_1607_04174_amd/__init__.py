@@ -132,6 +132,15 @@ _SIGS = {
     "rw_bank_select": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_void_p), ct.c_int, ct.POINTER(rw_eig_opts), ct.c_int,
                                   ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p,
                                   ct.POINTER(ct.c_int), ct.c_void_p]),
+    "rw_aggregate_desc": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(rw_graph_desc)]),
+    "rw_aggregate_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_aggregate_graph": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_size_t,
+                                      ct.c_void_p, ct.POINTER(ct.c_void_p)]),
+    "rw_aggregate_basis": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p,
+                                      ct.c_void_p, ct.c_size_t, ct.c_void_p]),
+    "rw_aggregate_seeds": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p,
+                                      ct.c_void_p, ct.POINTER(ct.c_int64)]),
+    "rw_prolong": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p]),
     "rw_dense_syev_workspace_bytes": (ct.c_int, [ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)]),
     "rw_dense_syev": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_size_t,
                                  ct.c_void_p]),
@@ -386,6 +395,63 @@ def update_eig(g: Graph, edits, Q: torch.Tensor, lam: torch.Tensor, mode: int = 
         _check(st)
     return {"iters": info.iters, "n_converged": info.n_converged, "spmm_columns": info.spmm_columns,
             "max_residual": info.max_residual, "seconds": info.seconds, "status": st}
+
+
+def aggregate(g: Graph, s: int) -> Graph:
+    """The graph of s x s (x s) blocks of g (rw_aggregate_graph): same connectivity, summed crossing weights."""
+    d = rw_graph_desc()
+    _check(lib().rw_aggregate_desc(g.handle, int(s), ct.byref(d)))
+    nb, nw = ct.c_size_t(), ct.c_size_t()
+    _check(lib().rw_graph_bytes(ct.byref(d), ct.byref(nb)))
+    _check(lib().rw_aggregate_workspace_bytes(g.handle, int(s), ct.byref(nw)))
+    c = Graph.__new__(Graph)
+    c.dims = tuple(int(d.dims[k]) for k in range(3))
+    c.ndim, c.N, c.conn, c.dtype, c.normalized, c.device = g.ndim, c.dims[0] * c.dims[1] * c.dims[2], g.conn, \
+        g.dtype, g.normalized, g.device
+    c._desc = d
+    c.buf = torch.empty(nb.value, dtype=torch.uint8, device=g.device)
+    c._work = torch.empty(nw.value, dtype=torch.uint8, device=g.device)
+    h = ct.c_void_p()
+    _check(lib().rw_aggregate_graph(g.handle, int(s), _ptr(c.buf), nb.value, _ptr(c._work), nw.value,
+                                    _stream(g.device), ct.byref(h)))
+    c.handle = h
+    return c
+
+
+def aggregate_basis(g: Graph, coarse: Graph, s: int, Q: torch.Tensor, lam_out: bool = True, tol: float = 1e-5):
+    """Eq. (33) transfer of Q (m, N) to the blocks, then the diagonal update on the aggregated graph
+    (Gram-Schmidt in order against its null vector, normalized-cut values).  Returns (Q_bar (m, N_bar), lambda)."""
+    m = Q.shape[0]
+    Q = Q.contiguous()
+    Qc = torch.empty((m, coarse.N), dtype=Q.dtype, device=Q.device)
+    nw = ct.c_size_t()
+    _check(lib().rw_aggregate_workspace_bytes(g.handle, int(s), ct.byref(nw)))
+    work = _workspace(nw.value, g.device)
+    _check(lib().rw_aggregate_basis(g.handle, int(s), _ptr(Q), _TORCH_DT[Q.dtype], m, _ptr(Qc), _ptr(work),
+                                    nw.value, _stream(g.device)))
+    lam = torch.empty(m, dtype=torch.float64, device=Q.device)
+    update_eig(coarse, [], Qc, lam, mode=RW_UPDATE_DIAG_RQ, tol=tol)
+    return Qc, lam
+
+
+def aggregate_seeds(g: Graph, s: int, seed_node, seed_label):
+    """Seeds moved to their blocks (sorted, distinct; conflicting labels in a block raise RWError)."""
+    nodes = np.ascontiguousarray(np.asarray(seed_node, dtype=np.int64))
+    labels = np.ascontiguousarray(np.asarray(seed_label, dtype=np.int32))
+    on = np.empty(max(1, nodes.size), np.int64)
+    ol = np.empty(max(1, nodes.size), np.int32)
+    n = ct.c_int64()
+    _check(lib().rw_aggregate_seeds(g.handle, int(s), ct.c_void_p(nodes.ctypes.data), ct.c_void_p(labels.ctypes.data),
+                                    nodes.size, ct.c_void_p(on.ctypes.data), ct.c_void_p(ol.ctypes.data), ct.byref(n)))
+    return on[:n.value].copy(), ol[:n.value].copy()
+
+
+def prolong(g: Graph, s: int, Uc: torch.Tensor) -> torch.Tensor:
+    """U_x = U_bar of x's block (Uc: (C, N_bar) of g's dtype) -> (C, N)."""
+    C = Uc.shape[0]
+    U = torch.empty((C, g.N), dtype=Uc.dtype, device=Uc.device)
+    _check(lib().rw_prolong(g.handle, int(s), _ptr(Uc.contiguous()), C, _ptr(U), _stream(g.device)))
+    return U
 
 
 def bank_select(g: Graph, bank, tol: float = 1e-5):
