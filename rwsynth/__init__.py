@@ -276,3 +276,79 @@ def cfg4_round(img: Workload, region_id: np.ndarray, rnd: int, seed: int = 0):
     per = int(rng.integers(10, 101))
     node, label = seeds(img, region_id, seed=seed, C=C, per_label=per, stream_offset=rnd + 1)
     return C, node, label
+
+
+# ----------------------------------------------------------------------------------------------
+# registration-style priors (displacement labels)
+# ----------------------------------------------------------------------------------------------
+# In registration the labels are displacement vectors on a regular grid (Sec. IV-A: 21 x 21 x 9 or
+# 31 x 31 x 13 of them) and the prior of label k at voxel x comes from comparing the patch around x
+# with the patch around x + v_k in the other image, normalized over the labels.  The image pairs are
+# not available; the stand-in keeps the structure such priors have: at each voxel a peak around the
+# best-matching displacement, that displacement varying smoothly over the volume, with per-voxel
+# jitter for the noise of the patch comparison.
+STREAM_DISPLACEMENT = 4
+
+CFG6_ID = 6
+CFG6 = Workload("3d96_6conn_rwir", CFG6_ID, (96, 96, 96), 6, 50.0, 200, 21 * 21 * 9, 0, 0.03, 8, "uniform",
+                0.0, "mixed")
+CFG6_EXTENT = (21, 21, 9)        # displacement labels per axis: C = 3969
+CFG6_GAMMA = 1.0
+CFG6_SIGMA = 0.7                 # width of a voxel's prior peak, in label spacings
+CFG6_JITTER = 0.5                # per-voxel jitter of the best displacement (voxels)
+
+
+def displacement_labels(extent) -> np.ndarray:
+    """C x 3 displacement vectors of the label grid (ex x ey x ez, centred at 0); label k = ix + ex*(iy +
+    ey*iz), as the node numbering."""
+    ex, ey, ez = (tuple(extent) + (1,) * 3)[:3]
+    k = np.arange(ex * ey * ez)
+    return np.stack([k % ex - ex // 2, (k // ex) % ey - ey // 2, k // (ex * ey) - ez // 2],
+                    axis=1).astype(np.float64)
+
+
+def displacement_field(dims, extent, config_id: int, seed: int = 0, n_bumps: int = 4,
+                       jitter: float = CFG6_JITTER) -> np.ndarray:
+    """N x 3 best-matching displacement per voxel: a sum of Gaussian bumps (centres uniform in the volume,
+    widths 15-35 % of the smallest side, amplitudes up to 0.8 of the label range per axis) plus Gaussian
+    jitter of standard deviation `jitter` per voxel and axis.  Axes without labels (extent 1) stay 0."""
+    nx, ny, nz = dims
+    ext = (tuple(extent) + (1,) * 3)[:3]
+    rng = rng_for(config_id, seed, STREAM_DISPLACEMENT)
+    i = np.arange(nx * ny * nz)
+    xyz = np.stack([i % nx, (i // nx) % ny, i // (nx * ny)], axis=1).astype(np.float64)
+    side = float(min(s for s in dims if s > 1))
+    field = np.zeros((i.size, 3))
+    for _ in range(n_bumps):
+        c = rng.uniform(0.0, 1.0, size=3) * np.array(dims, dtype=np.float64)
+        width = rng.uniform(0.15, 0.35) * side
+        amp = rng.uniform(-0.8, 0.8, size=3) * np.array([e // 2 for e in ext], dtype=np.float64)
+        r2 = (((xyz - c) * (np.array(dims) > 1)) ** 2).sum(axis=1)
+        field += np.exp(-0.5 * r2 / width ** 2)[:, None] * amp[None, :]
+    field += jitter * rng.standard_normal(field.shape) * (np.array(ext) > 1)[None, :]
+    return field
+
+
+def displacement_priors(field: np.ndarray, labels: np.ndarray, sigma: float = CFG6_SIGMA,
+                        rows=None) -> np.ndarray:
+    """N x C (or len(rows) x C) priors: at voxel x, p_k proportional to exp(-|v_k - d(x)|^2 / (2 sigma^2)),
+    normalized over the labels (the largest exponent subtracted first)."""
+    f = field if rows is None else field[np.asarray(rows)]
+    e = -((f[:, None, :] - labels[None, :, :]) ** 2).sum(axis=2) / (2.0 * sigma * sigma)
+    e -= e.max(axis=1, keepdims=True)
+    p = np.exp(e)
+    return p / p.sum(axis=1, keepdims=True)
+
+
+def displacement_priors_torch(field, labels, sigma: float = CFG6_SIGMA, dtype=None, chunk: int = 16384):
+    """The same priors computed with torch on the tensors' device, returned label-major (C, N) in `dtype`
+    (FP32 arithmetic, so equal to displacement_priors up to FP32 rounding)."""
+    import torch
+    N, C = field.shape[0], labels.shape[0]
+    out = torch.empty((C, N), dtype=dtype or torch.float32, device=field.device)
+    f32, l32 = field.float(), labels.float()
+    for a in range(0, N, chunk):
+        f = f32[a:a + chunk]
+        e = -((f[:, None, :] - l32[None, :, :]) ** 2).sum(dim=2) / (2.0 * sigma * sigma)
+        out[:, a:a + chunk] = torch.softmax(e, dim=1).t().to(out.dtype)
+    return out
