@@ -156,6 +156,15 @@ int rw_apply_laplacian(rw_graph g, const void* X, void* Y, int64_t b, hipStream_
 int rw_apply_laplacian_axpby(rw_graph g, const void* X, void* Y, const void* Z, int64_t b,
                              double alpha, double beta, double gamma, hipStream_t stream);
 
+/* rw_apply_laplacian for b >= 1 with its one operator kernel launched through hipExtLaunchKernel, so that
+ * `start` and `stop` (events the caller created with timing enabled on the stream's device) record that
+ * dispatch's own start and end: hipEventElapsedTime(start, stop) is the kernel's duration as a kernel
+ * trace reports it, without the stream's progress around the launch.  A measurement hook: the result is
+ * bit-identical to rw_apply_laplacian's.  RW_EINVAL for a null event or b < 1, RW_EHIP when the launch
+ * fails. */
+int rw_apply_laplacian_timed(rw_graph g, const void* X, void* Y, int64_t b, hipStream_t stream,
+                             hipEvent_t start, hipEvent_t stop);
+
 /* ======================================================================================
  * Offline eigenpairs (Sec. II-B eq. (6): the m smallest eigenpairs, null pair included)
  * ====================================================================================== */
@@ -347,6 +356,38 @@ int rw_solve_seeds_prior(rw_graph g, const void* Q, int q_dtype, const double* l
                          const int64_t* seed_node, const int32_t* seed_label, int64_t S, int C, double gamma,
                          const void* prior, int prior_dtype, double eps, int r, void* U, void* work,
                          size_t work_bytes, hipStream_t stream, rw_solve_info* info);
+
+/* Workspace of rw_solve_priors for these sizes (labels != 0 when the call asks for labels). */
+int rw_solve_priors_workspace_bytes(rw_graph g, int q_dtype, int m_avail, int C, int r, int labels,
+                                    size_t* bytes);
+
+/* The walker driven by priors alone, at registration label counts (thousands of displacement labels):
+ * eq. (5) of Sec. II-A with the seed set empty, (L + gamma I) U = gamma P on every vertex, in the variables of
+ * the graph's operator (under the normalized Laplacian (L_hat + gamma I) U_hat = gamma P_hat, i.e.
+ * (L + gamma D) U = gamma D P), approximated in the eigenbasis by eq. (15) of Sec. II-B with no seed rows:
+ *   U_hat = Q' (Lambda + gamma I)^{-1} gamma Q'^T P_hat,
+ * on the FP64 basis Q' of rw_solve_seeds (the exact null vector first, the other columns made orthogonal to it).
+ * Registration's result is, at each voxel, the label of largest probability (its displacement).
+ *   Q, q_dtype  device m_avail x N basis: RW_F64, RW_F32 or RW_BF16 (column 0 the null pair's); with RW_BF16
+ *            the projection and the labels run on the matrix cores (FP32 accumulation; m_avail <= 207);
+ *   lambda   device m_avail eigenvalues (FP64);
+ *   prior    device C x N (label k's map contiguous), RW_BF16 or RW_F32 with a BF16 basis, RW_F64 or RW_F32
+ *            otherwise; read-only;
+ *   gamma    > 0;
+ *   eps, r   eps <= 0: m = m_avail; > 0: the choice of m of rw_solve_seeds_prior (eq. (25) on the labels 0,
+ *            r^d, 2 r^d, ..., d the image dimension);
+ *   U        device C x N of the graph's dtype, or null: the probabilities;
+ *   label, prob  device N int32 and N of the graph's dtype, or both null: per voxel the smallest label of
+ *            largest probability and that probability (label 0, probability 0 on a vertex of degree 0);
+ *            with a BF16 basis evaluated by the fused reconstruction (U not formed), otherwise with the same
+ *            arithmetic as U;
+ *   work     rw_solve_priors_workspace_bytes(g, q_dtype, m_avail, C, r, label != null) bytes of device memory;
+ *   info     m_used, f_max = g_max and f_worst = the largest sampled g_k(m_used) (0 when eps <= 0).
+ * At least one of U and label must be asked for.  The call synchronizes `stream`.  Errors: RW_EINVAL (also: a
+ * basis column in the null vector's span), RW_EWORKSPACE, RW_ECAPTURE. */
+int rw_solve_priors(rw_graph g, const void* Q, int q_dtype, const double* lambda, int m_avail, const void* prior,
+                    int prior_dtype, int C, double gamma, double eps, int r, void* U, int32_t* label, void* prob,
+                    void* work, size_t work_bytes, hipStream_t stream, rw_solve_info* info);
 
 int rw_priors_workspace_bytes(int C, size_t* bytes);
 

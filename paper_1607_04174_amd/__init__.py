@@ -99,6 +99,8 @@ _SIGS = {
     "rw_graph_components": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int64), ct.c_void_p]),
     "rw_edit_graph": (ct.c_int, [ct.c_void_p, ct.POINTER(rw_edit), ct.c_int, ct.c_void_p]),
     "rw_apply_laplacian": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p]),
+    "rw_apply_laplacian_timed": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p,
+                                            ct.c_void_p, ct.c_void_p]),
     "rw_apply_laplacian_axpby": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64,
                                             ct.c_double, ct.c_double, ct.c_double, ct.c_void_p]),
     "rw_eig_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(rw_eig_opts), ct.POINTER(ct.c_size_t)]),
@@ -126,6 +128,11 @@ _SIGS = {
                                         ct.c_double, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p,
                                         ct.POINTER(rw_solve_info)]),
     "rw_priors_workspace_bytes": (ct.c_int, [ct.c_int, ct.POINTER(ct.c_size_t)]),
+    "rw_solve_priors_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
+                                                   ct.POINTER(ct.c_size_t)]),
+    "rw_solve_priors": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int,
+                                   ct.c_int, ct.c_double, ct.c_double, ct.c_int, ct.c_void_p, ct.c_void_p,
+                                   ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.POINTER(rw_solve_info)]),
     "rw_priors_from_seeds": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int, ct.c_void_p,
                                         ct.c_int, ct.c_void_p, ct.c_size_t, ct.c_void_p, ct.c_void_p]),
     "rw_bank_workspace_bytes": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(rw_eig_opts), ct.POINTER(ct.c_size_t)]),
@@ -333,6 +340,18 @@ def apply_laplacian(g: Graph, X: torch.Tensor, Y: Optional[torch.Tensor] = None)
     if Y is None:
         Y = torch.empty_like(X)
     _check(lib().rw_apply_laplacian(g.handle, _ptr(X), _ptr(Y), b, _stream(g.device)))
+    return Y
+
+
+def apply_laplacian_timed(g: Graph, X: torch.Tensor, Y: torch.Tensor, start, stop) -> torch.Tensor:
+    """apply_laplacian with the operator kernel's own start and end recorded into two torch.cuda.Event
+    objects (enable_timing=True); start.elapsed_time(stop) is then that dispatch's duration."""
+    b = X.numel() // g.N
+    for e in (start, stop):
+        if not e.cuda_event:                       # torch creates its events lazily, on the first record
+            e.record(torch.cuda.current_stream(g.device))
+    _check(lib().rw_apply_laplacian_timed(g.handle, _ptr(X), _ptr(Y), b, _stream(g.device),
+                                          ct.c_void_p(start.cuda_event), ct.c_void_p(stop.cuda_event)))
     return Y
 
 
@@ -588,6 +607,34 @@ def solve_seeds_prior(g: Graph, Q, lam: torch.Tensor, seed_node, seed_label, C: 
                                       _TORCH_DT[prior.dtype], float(eps), int(r), _ptr(U), _ptr(work), work.numel(),
                                       _stream(g.device), ct.byref(info)))
     return U, {"m_used": info.m_used, "g_max": info.f_max, "g_worst": info.f_worst, "min_pivot": info.min_pivot}
+
+
+def solve_priors(g: Graph, Q: torch.Tensor, lam: torch.Tensor, prior: torch.Tensor, gamma: float,
+                 eps: float = 0.0, r: int = 4, m_avail: Optional[int] = None, want_U: bool = True,
+                 want_labels: bool = False, U: Optional[torch.Tensor] = None,
+                 workspace: Optional[SolveWorkspace] = None):
+    """The walker driven by priors alone (no seeds), for label counts up to thousands: prior (C, N) of float64 /
+    float32 (FP64 or FP32 basis) or bfloat16 / float32 (BF16 basis).  Returns (U or None, labels or None,
+    prob or None, info dict); labels (N,) int32 are the smallest labels of largest probability per voxel."""
+    m_avail = Q.shape[0] if m_avail is None else int(m_avail)
+    prior = prior.contiguous()
+    C = prior.shape[0]
+    assert prior.shape[1] == g.N and Q.dtype in _TORCH_DT and prior.dtype in _TORCH_DT
+    if want_U and U is None:
+        U = torch.empty((C, g.N), dtype=g.dtype, device=g.device)
+    lab = torch.empty(g.N, dtype=torch.int32, device=g.device) if want_labels else None
+    prob = torch.empty(g.N, dtype=g.dtype, device=g.device) if want_labels else None
+    nb = ct.c_size_t()
+    _check(lib().rw_solve_priors_workspace_bytes(g.handle, _TORCH_DT[Q.dtype], m_avail, C, int(r),
+                                                 int(want_labels), ct.byref(nb)))
+    work = (workspace or SolveWorkspace()).get(nb.value, g.device)
+    info = rw_solve_info()
+    _check(lib().rw_solve_priors(g.handle, _ptr(Q.contiguous()), _TORCH_DT[Q.dtype], _ptr(lam), m_avail, _ptr(prior),
+                                 _TORCH_DT[prior.dtype], C, float(gamma), float(eps), int(r),
+                                 _ptr(U if want_U else None), _ptr(lab), _ptr(prob), _ptr(work), work.numel(),
+                                 _stream(g.device),
+                                 ct.byref(info)))
+    return (U if want_U else None), lab, prob, {"m_used": info.m_used, "g_max": info.f_max, "g_worst": info.f_worst}
 
 
 def priors_from_seeds(g: Graph, seed_node, seed_label, C: int, dtype=torch.float32) -> torch.Tensor:

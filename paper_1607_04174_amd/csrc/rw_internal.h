@@ -269,7 +269,8 @@ int fill_i32(int* p, int64_t n, int v, hipStream_t s);
 // ---- stencil operator --------------------------------------------------------------------------
 // Y = alpha * op(X) + beta * X + gamma * Z   (column-major N x b, graph dtype)
 int stencil_apply(const Graph* g, const void* X, void* Y, const void* Z, int64_t b, double alpha,
-                  double beta, double gamma, hipStream_t s);
+                  double beta, double gamma, hipStream_t s,
+                  hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // ---- tall-skinny dense kernels (blas.hip) -------------------------------------------------------
 // G (FP64, bx x by, column-major, ld = bx) = X^T Y for column-major X (rows x bx, ld ldx) and
@@ -365,6 +366,10 @@ __device__ __forceinline__ double ghat_scaled64(const double* sums, int normaliz
 // null_stats_partial_count(N, m) doubles.
 size_t null_stats_partial_count(int64_t N, int m);
 int null_stats(const Graph* g, const void* Q, int qdt, int m, double* partial, double* cn, int* bad, hipStream_t s);
+// U = s * sum_{j>=1} q_j Y_j + kappa (one-hot on the nodes map marks) for C labels of the solve's Y (m x C, after
+// solve_coeffs), U of the graph's dtype (solve.hip)
+int reconstruct_any(const Graph* g, const void* Q, int qdt, int m, const double* Y, int C, const uint8_t* map,
+                    void* U, hipStream_t s);
 // After the reduced solve (Y, m x C, ld m, the coefficients of the q'_j), in place and by one workgroup:
 // Y(j, c) /= n_j for j >= 1, then Y(0, c) = kappa_c = sg (Y(0, c) - sum_{j>=1} c_j Y(j, c)) with
 // sg = ghat_scaled64, so that U = s_i sum_{j>=1} q_j(i) Y(j, c) + kappa_c on nodes with s_i > 0.

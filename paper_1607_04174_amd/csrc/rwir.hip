@@ -1,0 +1,827 @@
+// The walker driven by priors alone, at registration label counts (thousands of displacement labels).
+// Sec. II-A eq. (5) with the seed set empty: (L + gamma I) U = gamma P on every vertex; under the normalized
+// Laplacian in hat variables (Sec. II-C), (L_hat + gamma I) U_hat = gamma P_hat with U_hat = D^{1/2} U and
+// P_hat = D^{1/2} P.  Sec. II-B eq. (15) with no seed rows gives U_hat = Q' (Lambda + gamma I)^{-1} gamma
+// Q'^T P_hat on the FP64 basis Q' = [g, (q_j - g c_j) / n_j] of the seeded solves (the null vector exact).
+// Sec. III-A2 eq. (25): m from g_k(m) on one label in every r^d.  The registration result is, per voxel,
+// the label of largest probability (its displacement) and that probability.
+//
+//   projection    Z_hat = Q^T P_hat over the stored columns, and g^T P_hat (one read of P).  On a BF16 basis
+//                 on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32 within a voxel chunk, FP64 over the
+//                 chunks), D^{1/2} folded into the staged Q tile so that the priors enter as stored, and g
+//                 as one more staged column;
+//   choice of m   ||p_hat_k||^2 on the sampled labels and the prefix sums of Z_hat (host);
+//   coefficients  Z' = Q'^T P_hat from Z_hat, g^T P_hat, c_j and n_j; Y = gamma (Lambda + gamma I)^{-1} Z',
+//                 rescaled so that U = s * sum_{j>=1} q_j Y_j + kappa (s = D^{-1/2});
+//   labels        the reconstruction fused with the arg max over the labels, U never written: on a BF16
+//                 basis the matrix cores over a voxel-major copy of the basis (one transposition per call)
+//                 with kappa folded in against a last column holding s^{-1} = d^{1/2}; otherwise one thread
+//                 per voxel;
+//   U             optionally, the seeded solves' reconstruction.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "rw_internal.h"
+
+namespace rw {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma_bf16(uint4 a, uint4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                 0, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  return (uint32_t)f32_to_bf16(lo) | ((uint32_t)f32_to_bf16(hi) << 16);
+}
+
+// ---------------------------------------------------------------------------------------------
+// per-voxel scales: sv = s_i = d_i^{1/2} (1 under L), sg = s_i g_i, inv = 1 / s_i (0 where d_i = 0)
+// ---------------------------------------------------------------------------------------------
+__global__ void k_rwir_scales(const double* degree, const double* sums, int normalized, int64_t N, float* sv,
+                              float* sg, float* inv) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double s = normalized ? sqrt(degree[i]) : 1.0;
+  sv[i] = (float)s;
+  sg[i] = (float)(s * ghat64(degree, sums, normalized, N, i));
+  inv[i] = s > 0.0 ? (float)(1.0 / s) : 0.0f;
+}
+
+// ---------------------------------------------------------------------------------------------
+// projection on the matrix cores (BF16 basis)
+// ---------------------------------------------------------------------------------------------
+// Workgroup: 4 waves, 256 labels (each wave 4 sub-tiles of 16), all KC = 16 NCT staged columns (the ma stored
+// columns, g, zeros), one chunk of voxels in stages of 64 (two K steps of 32).  The staged tile holds
+// s_i q_j(i) (and s_i g_i) in BF16, [column][voxel] with a padded row, double-buffered in LDS; the priors'
+// fragments come from HBM straight into registers, one stage ahead.  Output: FP32 partials per chunk,
+// part[(chunk C + label) KC + column].
+constexpr int kPjVox = 64;
+constexpr int kPjRow = kPjVox + 8;   // staged row in BF16 elements: conflict-free 16-byte fragment reads
+constexpr int kPjLab = 256;
+
+size_t rwir_proj_lds(int nct) { return (size_t)2 * nct * 16 * kPjRow * sizeof(uint16_t); }
+
+template <typename TP>
+__device__ __forceinline__ uint4 load_p8(const TP* row, int64_t v, int64_t vend, bool ok, bool vec);
+
+template <>
+__device__ __forceinline__ uint4 load_p8<uint16_t>(const uint16_t* row, int64_t v, int64_t vend, bool ok,
+                                                   bool vec) {
+  if (ok && vec && v + 8 <= vend) return *reinterpret_cast<const uint4*>(row + v);
+  uint16_t e[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) e[q] = (ok && v + q < vend) ? row[v + q] : (uint16_t)0;
+  return uint4{e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16), e[4] | ((uint32_t)e[5] << 16),
+               e[6] | ((uint32_t)e[7] << 16)};
+}
+
+template <>
+__device__ __forceinline__ uint4 load_p8<float>(const float* row, int64_t v, int64_t vend, bool ok, bool vec) {
+  float e[8];
+  if (ok && vec && v + 8 <= vend) {
+    const float4 a = *reinterpret_cast<const float4*>(row + v), b = *reinterpret_cast<const float4*>(row + v + 4);
+    e[0] = a.x; e[1] = a.y; e[2] = a.z; e[3] = a.w; e[4] = b.x; e[5] = b.y; e[6] = b.z; e[7] = b.w;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) e[q] = (ok && v + q < vend) ? row[v + q] : 0.0f;
+  }
+  return uint4{pack_bf16(e[0], e[1]), pack_bf16(e[2], e[3]), pack_bf16(e[4], e[5]), pack_bf16(e[6], e[7])};
+}
+
+template <typename TP, int NCT>
+__global__ __launch_bounds__(256) void k_rwir_proj(const uint16_t* __restrict__ Q, int ma, int64_t N,
+                                                   const TP* __restrict__ P, int C, const float* __restrict__ sv,
+                                                   const float* __restrict__ sg, int64_t chunk, int nlt,
+                                                   int64_t nwg, float* __restrict__ part) {
+  constexpr int KC = NCT * 16;
+  constexpr int PIECES = KC * (kPjVox / 8);            // 16-byte pieces of one staged tile
+  constexpr int PQ = (PIECES + 255) / 256;
+  extern __shared__ __align__(16) char smem[];
+  uint16_t* sQ = reinterpret_cast<uint16_t*>(smem);   // [2][KC][kPjRow]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // XCD-contiguous workgroups: the label tiles of one voxel chunk run on one XCD and share its L2
+  const int64_t per_xcd = (nwg + 7) / 8;
+  const int64_t L = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (L >= nwg) return;
+  const int64_t ck = L / nlt;
+  const int lt = (int)(L % nlt);
+  const int64_t vb = ck * chunk, ve = min(N, vb + chunk);
+  const int nst = (int)((ve - vb + kPjVox - 1) / kPjVox);
+  const int lrow = lane & 15, kg = lane >> 4;
+  const bool vecq = (N & 7) == 0;
+  const bool vecp = vecq;
+  const TP* prow[4];
+  bool pok[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t lab = (int64_t)lt * kPjLab + wave * 64 + t * 16 + lrow;
+    pok[t] = lab < C;
+    prow[t] = P + (pok[t] ? lab : 0) * N;
+  }
+  uint4 qreg[PQ];
+  auto load_stage = [&](int st) {
+    const int64_t v0 = vb + (int64_t)st * kPjVox;
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+      const int p = tid + 256 * q;
+      const int col = p >> 3;
+      const int64_t v = v0 + 8 * (p & 7);
+      if (p < PIECES && col < ma) {
+        const uint16_t* r = Q + (int64_t)col * N;
+        if (vecq && v + 8 <= ve) {
+          qreg[q] = *reinterpret_cast<const uint4*>(r + v);
+        } else {
+          uint16_t e[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) e[u] = v + u < ve ? r[v + u] : (uint16_t)0;
+          qreg[q] = uint4{e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16),
+                          e[4] | ((uint32_t)e[5] << 16), e[6] | ((uint32_t)e[7] << 16)};
+        }
+      } else {
+        qreg[q] = uint4{0u, 0u, 0u, 0u};
+      }
+    }
+  };
+  auto store_stage = [&](int st, int buf) {
+    const int64_t v0 = vb + (int64_t)st * kPjVox;
+    uint16_t* dst = sQ + buf * KC * kPjRow;
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+      const int p = tid + 256 * q;
+      if (p >= PIECES) break;
+      const int col = p >> 3, v8 = p & 7;
+      const int64_t v = v0 + 8 * v8;
+      float s[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[u] = v + u < ve ? (col == ma ? sg[v + u] : sv[v + u]) : 0.0f;
+      uint4 w;
+      if (col < ma) {
+        const uint32_t a[4] = {qreg[q].x, qreg[q].y, qreg[q].z, qreg[q].w};
+        uint32_t o[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          o[u] = pack_bf16(bf16_to_f32((uint16_t)(a[u] & 0xffffu)) * s[2 * u],
+                           bf16_to_f32((uint16_t)(a[u] >> 16)) * s[2 * u + 1]);
+        w = uint4{o[0], o[1], o[2], o[3]};
+      } else if (col == ma) {
+        w = uint4{pack_bf16(s[0], s[1]), pack_bf16(s[2], s[3]), pack_bf16(s[4], s[5]), pack_bf16(s[6], s[7])};
+      } else {
+        w = uint4{0u, 0u, 0u, 0u};
+      }
+      *reinterpret_cast<uint4*>(dst + col * kPjRow + 8 * v8) = w;
+    }
+  };
+  uint4 pa[4][2], pn[4][2];
+  auto load_p = [&](uint4 (&dst)[4][2], int st) {
+    const int64_t v0 = vb + (int64_t)st * kPjVox;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) dst[t][ks] = load_p8<TP>(prow[t], v0 + 32 * ks + 8 * kg, ve, pok[t], vecp);
+  };
+  f4 acc[4][NCT];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) acc[t][c] = f4{0.f, 0.f, 0.f, 0.f};
+  load_p(pa, 0);
+  load_stage(0);
+  store_stage(0, 0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    const bool more = st + 1 < nst;
+    if (more) {
+      load_p(pn, st + 1);
+      load_stage(st + 1);
+    }
+    const uint16_t* src = sQ + cur * KC * kPjRow;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) {
+        const uint4 b = *reinterpret_cast<const uint4*>(src + (c * 16 + lrow) * kPjRow + 32 * ks + 8 * kg);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t][c] = mfma_bf16(pa[t][ks], b, acc[t][c]);
+      }
+    }
+    if (more) {
+      store_stage(st + 1, cur ^ 1);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        pa[t][0] = pn[t][0];
+        pa[t][1] = pn[t][1];
+      }
+    }
+    __syncthreads();
+  }
+  // D[label 4 kg + v][column lrow] of each 16 x 16 tile
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t lab = (int64_t)lt * kPjLab + wave * 64 + t * 16 + 4 * kg + v;
+      if (lab >= C) continue;
+      float* dst = part + (ck * C + lab) * KC + lrow;
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) dst[c * 16] = acc[t][c][v];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// projection with FP64 accumulation (FP64 and FP32 bases): a 16-column x 16-label tile per workgroup and
+// voxel chunk, staged through LDS in steps of 64 voxels; the same partial layout (FP64)
+// ---------------------------------------------------------------------------------------------
+template <typename TQ, typename TP>
+__global__ __launch_bounds__(256) void k_rwir_proj_plain(const TQ* __restrict__ Q, int ma, int64_t N,
+                                                         const TP* __restrict__ P, int C,
+                                                         const double* __restrict__ degree,
+                                                         const double* __restrict__ sums, int normalized,
+                                                         int64_t chunk, int KC, double* __restrict__ part) {
+  __shared__ double sQ[16][65], sP[16][65];
+  const int tid = threadIdx.x, tj = tid >> 4, tk = tid & 15;
+  const int64_t ck = blockIdx.x;
+  const int j0 = blockIdx.y * 16;
+  const int64_t k0 = (int64_t)blockIdx.z * 16;
+  const int64_t vb = ck * chunk, ve = min(N, vb + chunk);
+  double acc = 0.0;
+  for (int64_t v0 = vb; v0 < ve; v0 += 64) {
+    // 16 rows x 64 voxels of each operand: thread (row tid / 16, voxels 4 (tid % 16) .. +3)
+    const int r = tid >> 4, c4 = 4 * (tid & 15);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t v = v0 + c4 + u;
+      const int j = j0 + r;
+      double q = 0.0, p = 0.0;
+      if (v < ve) {
+        const double s = normalized ? sqrt(degree[v]) : 1.0;
+        if (j < ma) q = s * (double)Elem<TQ>::ld(Q, (int64_t)j * N + v);
+        else if (j == ma) q = s * ghat64(degree, sums, normalized, N, v);
+        if (k0 + r < C) p = (double)Elem<TP>::ld(P, (k0 + r) * N + v);
+      }
+      sQ[r][c4 + u] = q;
+      sP[r][c4 + u] = p;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int u = 0; u < 64; ++u) acc = fma(sQ[tj][u], sP[tk][u], acc);
+    __syncthreads();
+  }
+  const int j = j0 + tj;
+  const int64_t k = k0 + tk;
+  if (j <= ma && k < C) part[(ck * C + k) * KC + j] = acc;
+}
+
+// Z_hat(j, k) (j < ma) and g^T P_hat (j = ma): the chunk partials summed in order, FP64
+template <typename TA>
+__global__ void k_rwir_reduce(const TA* part, int64_t nchunk, int C, int ma, int KC, double* Zh, double* gdot) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)C * (ma + 1)) return;
+  const int j = (int)(t % (ma + 1));
+  const int64_t k = t / (ma + 1);
+  double a = 0.0;
+  for (int64_t c = 0; c < nchunk; ++c) a += (double)part[(c * C + k) * KC + j];
+  if (j < ma) Zh[j + k * ma] = a;
+  else gdot[k] = a;
+}
+
+// ||p_hat_k||^2 for the sampled labels k = q step (one workgroup each, FP64), and their Z_hat columns beside
+// them for the host: stage[q ma + j] = Z_hat(j, k), stage[ns ma + q] = ||p_hat_k||^2
+template <typename TP>
+__global__ __launch_bounds__(256) void k_rwir_norms(const TP* P, int64_t N, int step, const double* degree,
+                                                    int normalized, const double* Zh, int ma, int ns,
+                                                    double* stage) {
+  __shared__ double sh[4];
+  const int q = blockIdx.x, tid = threadIdx.x;
+  const int64_t k = (int64_t)q * step;
+  double a = 0.0;
+  for (int64_t i = tid; i < N; i += 256) {
+    const double x = (normalized ? sqrt(degree[i]) : 1.0) * (double)Elem<TP>::ld(P, k * N + i);
+    a += x * x;
+  }
+  a = wave_sum64(a);
+  if ((tid & 63) == 0) sh[tid >> 6] = a;
+  __syncthreads();
+  if (tid == 0) stage[(int64_t)ns * ma + q] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  for (int j = tid; j < ma; j += 256) stage[(int64_t)q * ma + j] = Zh[j + k * ma];
+}
+
+// One thread per label: Z'(j) = g^T P_hat (j = 0) or (Z_hat(j) - c_j g^T P_hat) / n_j, Y(j) = gamma Z'(j) /
+// (lambda_j + gamma), then Y(j) /= n_j (j >= 1) and kappa = sg (Y(0) - sum_{j>=1} c_j Y(j)) in Y(0).  With Yt,
+// the labels' BF16 rows for the fused reconstruction: Yt[k KR + (j - 1)] = Y(j) for j in [1, m), Yt[k KR +
+// KR - 1] = kappa, zeros between; rows k in [C, Cpad) zero.
+__global__ void k_rwir_coeffs(const double* Zh, const double* gdot, int ma, int m, int C, int Cpad,
+                              const double* lambda, double gamma, const double* cn, const double* sums,
+                              int normalized, int64_t N, double* Y, uint16_t* Yt, int KR) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= Cpad) return;
+  if (k >= C) {
+    if (Yt)
+      for (int q = 0; q < KR; ++q) Yt[k * KR + q] = 0;
+    return;
+  }
+  const double gd = gdot[k];
+  const double* z = Zh + k * ma;
+  double* y = Y + k * m;
+  const double y0 = gamma * gd / (lambda[0] + gamma);
+  for (int j = 1; j < m; ++j) {
+    const double zp = (z[j] - cn[j] * gd) / cn[m + j];
+    y[j] = gamma * zp / (lambda[j] + gamma) / cn[m + j];
+  }
+  double acc = y0;
+  for (int j = 1; j < m; ++j) acc -= cn[j] * y[j];
+  y[0] = ghat_scaled64(sums, normalized, N) * acc;
+  if (Yt) {
+    uint16_t* r = Yt + k * KR;
+    for (int q = 0; q < KR - 1; ++q) r[q] = q + 1 < m ? f32_to_bf16((float)y[q + 1]) : (uint16_t)0;
+    r[KR - 1] = f32_to_bf16((float)y[0]);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// labels on the matrix cores (BF16 basis)
+// ---------------------------------------------------------------------------------------------
+// Voxel-major copy of the basis for the fused reconstruction: Qt[i KR + q] = q_{q+1}(i) for q < ma - 1,
+// Qt[i KR + KR - 1] = s_i (the column that carries kappa), zeros between.  64-voxel x 32-column tiles through
+// LDS (coalesced reads along voxels, 16-byte writes along columns).
+__global__ __launch_bounds__(256) void k_rwir_transpose(const uint16_t* __restrict__ Q, int ma, int64_t N,
+                                                        const float* __restrict__ sv, int KR,
+                                                        uint16_t* __restrict__ Qt) {
+  __shared__ uint16_t t[64][34];
+  const int tid = threadIdx.x;
+  const int64_t v0 = (int64_t)blockIdx.x * 64;
+  const int q0 = blockIdx.y * 32;
+  for (int e = tid; e < 64 * 32; e += 256) {
+    const int r = e >> 6, v = e & 63;   // column q0 + r, voxel v0 + v
+    const int q = q0 + r;
+    const int64_t i = v0 + v;
+    uint16_t x = 0;
+    if (i < N) {
+      if (q + 1 < ma) x = Q[(int64_t)(q + 1) * N + i];
+      else if (q == KR - 1) x = f32_to_bf16(sv[i]);
+    }
+    t[v][r] = x;
+  }
+  __syncthreads();
+  // each thread writes 8 columns (16 bytes) of one voxel: 64 voxels x 4 pieces
+  const int v = tid >> 2, p = tid & 3;
+  const int64_t i = v0 + v;
+  if (i < N) {
+    uint32_t w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = (uint32_t)t[v][8 * p + 2 * u] | ((uint32_t)t[v][8 * p + 2 * u + 1] << 16);
+    *reinterpret_cast<uint4*>(Qt + i * KR + q0 + 8 * p) = uint4{w[0], w[1], w[2], w[3]};
+  }
+}
+
+// Workgroup: 4 waves x 8 sub-tiles of 16 voxels.  A wave keeps its 128 voxels' basis fragments (KS K steps
+// of 32) in registers and runs over all labels in tiles of 16: D[label 4 kg + v][voxel lrow] = s_i U(label,
+// i), the larger value kept per lane (labels in increasing order, strict comparison), then the four lanes of
+// a voxel merged (larger value, or equal value and smaller label).  label[i] and prob[i] = s_i^{-1} D; a voxel
+// with d_i = 0 gets label 0 and probability 0.
+constexpr int kLbSub = 8;
+
+template <int KS, typename TU>
+__global__ __launch_bounds__(256) void k_rwir_label_mfma(const uint16_t* __restrict__ Qt, int64_t N,
+                                                         const uint16_t* __restrict__ Yt, int C,
+                                                         const float* __restrict__ inv, int32_t* __restrict__ label,
+                                                         TU* __restrict__ prob) {
+  constexpr int KR = 32 * KS;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lrow = lane & 15, kg = lane >> 4;
+  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * (16 * kLbSub);
+  if (base >= N) return;
+  uint4 b[kLbSub][KS];
+#pragma unroll
+  for (int u = 0; u < kLbSub; ++u) {
+    const int64_t i = base + 16 * u + lrow;
+    const int64_t ii = i < N ? i : N - 1;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) b[u][s] = *reinterpret_cast<const uint4*>(Qt + ii * KR + 32 * s + 8 * kg);
+  }
+  float best[kLbSub];
+  int bidx[kLbSub];
+#pragma unroll
+  for (int u = 0; u < kLbSub; ++u) {
+    best[u] = -INFINITY;
+    bidx[u] = 0;
+  }
+  const int ntile = (C + 15) >> 4;
+  uint4 a[KS], an[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) a[s] = *reinterpret_cast<const uint4*>(Yt + (int64_t)lrow * KR + 32 * s + 8 * kg);
+  for (int tl = 0; tl < ntile; ++tl) {
+    if (tl + 1 < ntile) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        an[s] = *reinterpret_cast<const uint4*>(Yt + ((int64_t)(tl + 1) * 16 + lrow) * KR + 32 * s + 8 * kg);
+    }
+    f4 acc[kLbSub];
+#pragma unroll
+    for (int u = 0; u < kLbSub; ++u) acc[u] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int u = 0; u < kLbSub; ++u) acc[u] = mfma_bf16(a[s], b[u][s], acc[u]);
+    const int l0 = tl * 16 + 4 * kg;
+#pragma unroll
+    for (int u = 0; u < kLbSub; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (l0 + v < C && acc[u][v] > best[u]) {
+          best[u] = acc[u][v];
+          bidx[u] = l0 + v;
+        }
+    if (tl + 1 < ntile) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) a[s] = an[s];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kLbSub; ++u) {
+#pragma unroll
+    for (int off = 16; off <= 32; off <<= 1) {
+      const float ov = __shfl_xor(best[u], off);
+      const int oi = __shfl_xor(bidx[u], off);
+      if (ov > best[u] || (ov == best[u] && oi < bidx[u])) {
+        best[u] = ov;
+        bidx[u] = oi;
+      }
+    }
+    const int64_t i = base + 16 * u + lrow;
+    if (kg == 0 && i < N) {
+      const float is = inv[i];
+      label[i] = is > 0.0f ? bidx[u] : 0;
+      prob[i] = (TU)(is > 0.0f ? best[u] * is : 0.0f);
+    }
+  }
+}
+
+// Labels with one thread per voxel (FP64 and FP32 bases): U(c, i) = s_i sum_{j>=1} q_j(i) Y(j, c) + kappa_c,
+// evaluated as the reconstruction does (same operations in the same order, labels 8 at a time), the first
+// label of largest U kept.
+template <typename TQ, typename TU>
+__global__ __launch_bounds__(256) void k_rwir_label_plain(const TQ* __restrict__ Q, int64_t N, int m,
+                                                          const double* __restrict__ Y, int C,
+                                                          const TU* __restrict__ dinv, int normalized,
+                                                          int32_t* __restrict__ label, TU* __restrict__ prob) {
+  using CT = typename Elem<TQ>::C;
+  constexpr int CB = 8;
+  extern __shared__ char smem[];
+  CT* sY = reinterpret_cast<CT*>(smem);   // (m - 1) x CB
+  CT* sK = sY + (m - 1) * CB;             // CB
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t ic = i < N ? i : N - 1;
+  const TQ* Q1 = Q + N;
+  const int mq = m - 1;
+  const CT sc = normalized ? (CT)dinv[ic] : CT(1);
+  const bool live = !normalized || sc > CT(0);
+  TU best = TU(0);
+  int bi = -1;
+  for (int lab0 = 0; lab0 < C; lab0 += CB) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < m * CB; t += blockDim.x) {
+      const int j = t / CB, c = t % CB;
+      const int lab = lab0 + c;
+      const CT v = lab < C ? (CT)Y[j + (int64_t)lab * m] : CT(0);
+      if (j == 0) sK[c] = v;
+      else sY[(j - 1) * CB + c] = v;
+    }
+    __syncthreads();
+    CT acc[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) acc[c] = CT(0);
+    int j = 0;
+    for (; j + 4 <= mq; j += 4) {
+      const CT q0 = Elem<TQ>::ld(Q1, (int64_t)j * N + ic);
+      const CT q1 = Elem<TQ>::ld(Q1, (int64_t)(j + 1) * N + ic);
+      const CT q2 = Elem<TQ>::ld(Q1, (int64_t)(j + 2) * N + ic);
+      const CT q3 = Elem<TQ>::ld(Q1, (int64_t)(j + 3) * N + ic);
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        acc[c] = fma(q0, sY[(j + 0) * CB + c], acc[c]);
+        acc[c] = fma(q1, sY[(j + 1) * CB + c], acc[c]);
+        acc[c] = fma(q2, sY[(j + 2) * CB + c], acc[c]);
+        acc[c] = fma(q3, sY[(j + 3) * CB + c], acc[c]);
+      }
+    }
+    for (; j < mq; ++j) {
+      const CT q = Elem<TQ>::ld(Q1, (int64_t)j * N + ic);
+#pragma unroll
+      for (int c = 0; c < CB; ++c) acc[c] = fma(q, sY[j * CB + c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int lab = lab0 + c;
+      if (lab >= C) break;
+      const TU u = (TU)(sc * acc[c] + (live ? sK[c] : CT(0)));
+      if (bi < 0 || u > best) {
+        best = u;
+        bi = lab;
+      }
+    }
+  }
+  if (i < N) {
+    label[i] = live ? bi : 0;
+    prob[i] = live ? best : TU(0);
+  }
+}
+
+__global__ void k_rwir_zero_map(uint8_t* map, int64_t N) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N) map[i] = 0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------------
+constexpr int64_t kPjChunks = 64;       // voxel chunks of the matrix-core projection
+constexpr int kPlainChunk = 16384;      // voxels per chunk of the FP64-accumulated projection
+
+struct RwirDims {
+  int ma, C, KC, KR, Cpad, ns, step;
+  int64_t nchunk, chunk, nlt;
+  bool mfma;
+};
+
+static RwirDims rwir_dims(const Graph* g, int qdt, int ma, int C, int r) {
+  RwirDims d;
+  d.ma = ma;
+  d.C = C;
+  d.mfma = qdt == RW_BF16;
+  // staged columns of the projection (the ma stored columns and g): the matrix-core kernel's width, else 16s
+  const int nct = (ma + 1 + 15) / 16;
+  d.KC = 16 * (d.mfma ? (nct <= 4 ? 4 : (nct <= 8 ? 8 : 13)) : nct);
+  d.KR = (ma + 31) / 32 * 32;          // columns 1 .. ma-1, zeros, kappa's column last
+  d.Cpad = (C + 15) / 16 * 16;
+  int step = 1;
+  for (int q = 0; q < g->ndim; ++q) step *= std::max(1, r);
+  d.step = step;
+  d.ns = (C + step - 1) / step;
+  if (d.mfma) {
+    d.nchunk = std::min<int64_t>(kPjChunks, (g->N + kPjVox - 1) / kPjVox);
+    d.chunk = ((g->N + d.nchunk - 1) / d.nchunk + kPjVox - 1) / kPjVox * kPjVox;
+    d.nchunk = (g->N + d.chunk - 1) / d.chunk;
+    d.nlt = (C + kPjLab - 1) / kPjLab;
+  } else {
+    d.chunk = kPlainChunk;
+    d.nchunk = (g->N + d.chunk - 1) / d.chunk;
+    d.nlt = 0;
+  }
+  return d;
+}
+
+struct RwirWork {
+  float *sv, *sg, *inv;
+  void* part;
+  double *Zh, *gdot, *Y, *cn, *npart, *stage;
+  int* nbad;
+  uint8_t* map;
+  uint16_t *Yt, *Qt;
+};
+
+static size_t rwir_layout(const Graph* g, const RwirDims& d, bool labels, void* base, RwirWork* w) {
+  Carver c(base);
+  RwirWork t;
+  t.sv = c.take<float>(g->N);
+  t.sg = c.take<float>(g->N);
+  t.inv = c.take<float>(g->N);
+  t.part = d.mfma ? (void*)c.take<float>((size_t)d.nchunk * d.C * d.KC)
+                  : (void*)c.take<double>((size_t)d.nchunk * d.C * d.KC);
+  t.Zh = c.take<double>((size_t)d.ma * d.C);
+  t.gdot = c.take<double>(d.C);
+  t.Y = c.take<double>((size_t)d.ma * d.C);
+  t.cn = c.take<double>(2 * (size_t)d.ma);
+  t.npart = c.take<double>(null_stats_partial_count(g->N, d.ma));
+  t.stage = c.take<double>((size_t)d.ns * d.ma + d.ns);
+  t.nbad = c.take<int>(1);
+  t.map = c.take<uint8_t>(g->N);
+  t.Yt = (d.mfma && labels) ? c.take<uint16_t>((size_t)d.Cpad * d.KR) : nullptr;
+  t.Qt = (d.mfma && labels) ? c.take<uint16_t>((size_t)g->N * d.KR) : nullptr;
+  if (w) *w = t;
+  return c.used + 256;
+}
+
+template <typename TP, int NCT>
+static int launch_proj(const Graph* g, const uint16_t* Q, const RwirDims& d, const void* P, const RwirWork& w,
+                       hipStream_t s) {
+  static bool attr = false;
+  const size_t lds = rwir_proj_lds(NCT);
+  if (!attr) {
+    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_rwir_proj<TP, NCT>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = true;
+  }
+  const int64_t nwg = d.nchunk * d.nlt;
+  const int64_t grid = (nwg + 7) / 8 * 8;
+  k_rwir_proj<TP, NCT><<<(unsigned)grid, 256, lds, s>>>(Q, d.ma, g->N, static_cast<const TP*>(P), d.C, w.sv, w.sg,
+                                                        d.chunk, (int)d.nlt, nwg, static_cast<float*>(w.part));
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+template <typename TP>
+static int proj_mfma(const Graph* g, const uint16_t* Q, const RwirDims& d, const void* P, const RwirWork& w,
+                     hipStream_t s) {
+  // d.KC is the kernel's width (the partial layout's stride)
+  if (d.KC == 64) return launch_proj<TP, 4>(g, Q, d, P, w, s);
+  if (d.KC == 128) return launch_proj<TP, 8>(g, Q, d, P, w, s);
+  return launch_proj<TP, 13>(g, Q, d, P, w, s);
+}
+
+template <int KS>
+static int label_mfma_t(const Graph* g, const RwirDims& d, const RwirWork& w, int32_t* label, void* prob,
+                        hipStream_t s) {
+  const unsigned nb = (unsigned)((g->N + 4 * 16 * kLbSub - 1) / (4 * 16 * kLbSub));
+  if (g->dtype == RW_F64)
+    k_rwir_label_mfma<KS, double><<<nb, 256, 0, s>>>(w.Qt, g->N, w.Yt, d.C, w.inv, label, static_cast<double*>(prob));
+  else
+    k_rwir_label_mfma<KS, float><<<nb, 256, 0, s>>>(w.Qt, g->N, w.Yt, d.C, w.inv, label, static_cast<float*>(prob));
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+template <typename TQ, typename TU>
+static int label_plain_t(const Graph* g, const void* Q, int m, const double* Y, int C, int32_t* label, void* prob,
+                         hipStream_t s) {
+  using CT = typename Elem<TQ>::C;
+  const size_t sh = (size_t)m * 8 * sizeof(CT);
+  k_rwir_label_plain<TQ, TU><<<nblocks(g->N, 256), 256, sh, s>>>(static_cast<const TQ*>(Q), g->N, m, Y, C,
+                                                                 static_cast<const TU*>(g->dinv), g->normalized,
+                                                                 label, static_cast<TU*>(prob));
+  RW_LAUNCH_CHECK();
+  return RW_OK;
+}
+
+}  // namespace rw
+
+using namespace rw;
+
+extern "C" {
+
+int rw_solve_priors_workspace_bytes(rw_graph h, int q_dtype, int m_avail, int C, int r, int labels, size_t* bytes) {
+  RW_CHECK(h != nullptr && bytes != nullptr, RW_EINVAL, "null argument");
+  RW_CHECK(q_dtype == RW_F64 || q_dtype == RW_F32 || q_dtype == RW_BF16, RW_EINVAL,
+           "the basis is RW_F64, RW_F32 or RW_BF16");
+  RW_CHECK(m_avail >= 2 && C >= 1, RW_EINVAL, "bad sizes (m_avail = %d, C = %d)", m_avail, C);
+  const RwirDims d = rwir_dims(&h->g, q_dtype, m_avail, C, r);
+  *bytes = rwir_layout(&h->g, d, labels != 0, nullptr, nullptr);
+  return RW_OK;
+}
+
+int rw_solve_priors(rw_graph h, const void* Q, int q_dtype, const double* lambda, int m_avail, const void* prior,
+                    int prior_dtype, int C, double gamma, double eps, int r, void* U, int32_t* label, void* prob,
+                    void* work, size_t work_bytes, hipStream_t stream, rw_solve_info* info) {
+  RW_CHECK(h != nullptr && Q != nullptr && lambda != nullptr && prior != nullptr && work != nullptr, RW_EINVAL,
+           "null argument");
+  RW_CHECK(q_dtype == RW_F64 || q_dtype == RW_F32 || q_dtype == RW_BF16, RW_EINVAL,
+           "the basis is RW_F64, RW_F32 or RW_BF16");
+  RW_CHECK(m_avail >= 2 && C >= 1, RW_EINVAL, "bad sizes (m_avail = %d, C = %d)", m_avail, C);
+  RW_CHECK(gamma > 0.0, RW_EINVAL, "gamma must be > 0");
+  RW_CHECK(U != nullptr || label != nullptr, RW_EINVAL, "nothing to compute: U and label are both null");
+  RW_CHECK((label == nullptr) == (prob == nullptr), RW_EINVAL, "label and prob go together");
+  RW_CHECK(eps <= 0.0 || r >= 1, RW_EINVAL, "r must be >= 1");
+  const Graph* g = &h->g;
+  const bool mf = q_dtype == RW_BF16;
+  RW_CHECK(mf ? (prior_dtype == RW_BF16 || prior_dtype == RW_F32)
+              : (prior_dtype == RW_F64 || prior_dtype == RW_F32),
+           RW_EINVAL, "priors: RW_BF16 or RW_F32 with a BF16 basis, RW_F64 or RW_F32 otherwise");
+  RW_CHECK(!mf || m_avail + 1 <= 13 * 16, RW_EINVAL, "a BF16 basis takes m_avail <= %d here (got %d)", 13 * 16 - 1,
+           m_avail);
+  RW_CHECK(!mf || (m_avail + 31) / 32 <= 8, RW_EINVAL, "m_avail too large for the label kernel");
+  RW_CHECK((int64_t)C * g->N < ((int64_t)1 << 62), RW_EINVAL, "C x N too large");
+  RW_NOT_CAPTURING(stream);
+  const RwirDims d = rwir_dims(g, q_dtype, m_avail, C, r);
+  RwirWork w;
+  const size_t need = rwir_layout(g, d, label != nullptr, nullptr, nullptr);
+  RW_CHECK(work_bytes >= need, RW_EWORKSPACE, "workspace too small: %zu < %zu", work_bytes, need);
+  rwir_layout(g, d, label != nullptr, work, &w);
+  k_rwir_scales<<<nblocks(g->N, 256), 256, 0, stream>>>(g->degree, g->sums, g->normalized, g->N, w.sv, w.sg, w.inv);
+  RW_LAUNCH_CHECK();
+  // projection
+  const int64_t nred = (int64_t)C * (m_avail + 1);
+  if (mf) {
+    const uint16_t* Qb = static_cast<const uint16_t*>(Q);
+    if (prior_dtype == RW_BF16) RW_TRY(proj_mfma<uint16_t>(g, Qb, d, prior, w, stream));
+    else RW_TRY(proj_mfma<float>(g, Qb, d, prior, w, stream));
+    k_rwir_reduce<float><<<nblocks(nred, 256), 256, 0, stream>>>(static_cast<const float*>(w.part), d.nchunk, C,
+                                                                  m_avail, d.KC, w.Zh, w.gdot);
+  } else {
+    const dim3 grid((unsigned)d.nchunk, (unsigned)((m_avail + 1 + 15) / 16), (unsigned)((C + 15) / 16));
+    RW_CHECK(grid.z <= 65535u, RW_EINVAL, "C too large for the FP64-accumulated projection");
+    double* pp = static_cast<double*>(w.part);
+#define RW_PP(TQ, TP)                                                                                           \
+  k_rwir_proj_plain<TQ, TP><<<grid, 256, 0, stream>>>(static_cast<const TQ*>(Q), m_avail, g->N,                 \
+                                                      static_cast<const TP*>(prior), C, g->degree, g->sums,     \
+                                                      g->normalized, d.chunk, d.KC, pp)
+    if (q_dtype == RW_F64) {
+      if (prior_dtype == RW_F64) RW_PP(double, double);
+      else RW_PP(double, float);
+    } else {
+      if (prior_dtype == RW_F64) RW_PP(float, double);
+      else RW_PP(float, float);
+    }
+#undef RW_PP
+    RW_LAUNCH_CHECK();
+    k_rwir_reduce<double><<<nblocks(nred, 256), 256, 0, stream>>>(pp, d.nchunk, C, m_avail, d.KC, w.Zh, w.gdot);
+  }
+  RW_LAUNCH_CHECK();
+  // choice of m (eq. (25)) on the sampled labels
+  int m = m_avail;
+  double gmax = 0.0, gworst = 0.0;
+  if (eps > 0.0) {
+    if (prior_dtype == RW_F64)
+      k_rwir_norms<double><<<d.ns, 256, 0, stream>>>(static_cast<const double*>(prior), g->N, d.step, g->degree,
+                                                     g->normalized, w.Zh, m_avail, d.ns, w.stage);
+    else if (prior_dtype == RW_F32)
+      k_rwir_norms<float><<<d.ns, 256, 0, stream>>>(static_cast<const float*>(prior), g->N, d.step, g->degree,
+                                                    g->normalized, w.Zh, m_avail, d.ns, w.stage);
+    else
+      k_rwir_norms<uint16_t><<<d.ns, 256, 0, stream>>>(static_cast<const uint16_t*>(prior), g->N, d.step,
+                                                       g->degree, g->normalized, w.Zh, m_avail, d.ns, w.stage);
+    RW_LAUNCH_CHECK();
+    const size_t nst = (size_t)d.ns * m_avail + d.ns;
+    void* stage = nullptr;
+    RW_TRY(host_stage((nst + 1) * sizeof(double), &stage));
+    double* hz = static_cast<double*>(stage);
+    RW_HIP(hipMemcpyAsync(hz, w.stage, nst * sizeof(double), hipMemcpyDeviceToHost, stream));
+    RW_HIP(hipMemcpyAsync(hz + nst, g->sums, sizeof(double), hipMemcpyDeviceToHost, stream));
+    RW_HIP(hipStreamSynchronize(stream));
+    gmax = eps * eps * (g->normalized ? hz[nst] : (double)g->N);
+    std::vector<double> gk(hz + (size_t)d.ns * m_avail, hz + nst);
+    for (int mm = 1; mm <= m_avail; ++mm) {
+      double worst = 0.0;
+      for (int q = 0; q < d.ns; ++q) {
+        const double z = hz[(size_t)q * m_avail + (mm - 1)];
+        gk[q] -= z * z;
+        worst = std::max(worst, gk[q]);
+      }
+      gworst = worst;
+      if (mm >= 2 && worst <= gmax) {
+        m = mm;
+        break;
+      }
+    }
+  }
+  // the FP64 basis of the first m columns and the coefficients
+  RW_TRY(fill_i32(w.nbad, 1, 0, stream));
+  RW_TRY(null_stats(g, Q, q_dtype, m, w.npart, w.cn, w.nbad, stream));
+  const bool fused = mf && label != nullptr;
+  k_rwir_coeffs<<<nblocks(d.Cpad, 256), 256, 0, stream>>>(w.Zh, w.gdot, m_avail, m, C, d.Cpad, lambda, gamma, w.cn,
+                                                          g->sums, g->normalized, g->N, w.Y,
+                                                          fused ? w.Yt : nullptr, d.KR);
+  RW_LAUNCH_CHECK();
+  if (U != nullptr) {
+    k_rwir_zero_map<<<nblocks(g->N, 256), 256, 0, stream>>>(w.map, g->N);
+    RW_LAUNCH_CHECK();
+    RW_TRY(reconstruct_any(g, Q, q_dtype, m, w.Y, C, w.map, U, stream));
+  }
+  if (label != nullptr) {
+    if (fused) {
+      const dim3 tg((unsigned)((g->N + 63) / 64), (unsigned)(d.KR / 32));
+      k_rwir_transpose<<<tg, 256, 0, stream>>>(static_cast<const uint16_t*>(Q), m, g->N, w.sv, d.KR, w.Qt);
+      RW_LAUNCH_CHECK();
+      switch (d.KR / 32) {
+        case 1: RW_TRY(label_mfma_t<1>(g, d, w, label, prob, stream)); break;
+        case 2: RW_TRY(label_mfma_t<2>(g, d, w, label, prob, stream)); break;
+        case 3: RW_TRY(label_mfma_t<3>(g, d, w, label, prob, stream)); break;
+        case 4: RW_TRY(label_mfma_t<4>(g, d, w, label, prob, stream)); break;
+        case 5: RW_TRY(label_mfma_t<5>(g, d, w, label, prob, stream)); break;
+        case 6: RW_TRY(label_mfma_t<6>(g, d, w, label, prob, stream)); break;
+        case 7: RW_TRY(label_mfma_t<7>(g, d, w, label, prob, stream)); break;
+        default: RW_TRY(label_mfma_t<8>(g, d, w, label, prob, stream)); break;
+      }
+    } else {
+      RW_CHECK((size_t)m * 8 * 8 <= 65536, RW_EINVAL, "m = %d too large for the label kernel", m);
+      if (g->dtype == RW_F64) {
+        if (q_dtype == RW_F64) RW_TRY((label_plain_t<double, double>(g, Q, m, w.Y, C, label, prob, stream)));
+        else RW_TRY((label_plain_t<float, double>(g, Q, m, w.Y, C, label, prob, stream)));
+      } else {
+        if (q_dtype == RW_F64) RW_TRY((label_plain_t<double, float>(g, Q, m, w.Y, C, label, prob, stream)));
+        else RW_TRY((label_plain_t<float, float>(g, Q, m, w.Y, C, label, prob, stream)));
+      }
+    }
+  }
+  void* stage = nullptr;
+  RW_TRY(host_stage(sizeof(int), &stage));
+  RW_HIP(hipMemcpyAsync(stage, w.nbad, sizeof(int), hipMemcpyDeviceToHost, stream));
+  RW_HIP(hipStreamSynchronize(stream));
+  int nbad = 0;
+  std::memcpy(&nbad, stage, sizeof(int));
+  RW_CHECK(!nbad, RW_EINVAL, "basis column %d lies in the span of the null vector (column 0)", nbad);
+  if (info) {
+    info->m_used = m;
+    info->eig_probes = 0;
+    info->f_max = gmax;
+    info->f_worst = gworst;
+    info->min_pivot = 1.0;
+  }
+  return RW_OK;
+}
+
+}  // extern "C"

@@ -392,6 +392,11 @@ static int reconstruct(const Graph* g, const void* Q, int qdt, int m, const doub
   return reconstruct_t<uint16_t, float>(g, b.hi, b.lo, m, Y, C, map, U, s);
 }
 
+int reconstruct_any(const Graph* g, const void* Q, int qdt, int m, const double* Y, int C, const uint8_t* map,
+                    void* U, hipStream_t s) {
+  return reconstruct(g, Q, qdt, m, Y, C, map, U, s);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Choice of m (Sec. III-A1): f_k(m) = min_{||a|| <= rho} ||Q_s[:, :m] a - b_k||^2.
 // Per candidate m, with ms = min(S, m): for m <= S the m x m normal matrix G = Q_s^T Q_s (leading
