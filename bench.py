@@ -47,7 +47,7 @@ def main():
                     help="only launch the stencil block and a plain copy of the same block (for HBM counters)")
     ap.add_argument("--workload", default="interactive512",
                     choices=["interactive512", "small64", "volume128", "batch64", "grad96", "prior512", "bank512",
-                             "agg512"],
+                             "agg512", "rwir96"],
                     help="interactive512 (default, the headline line); the others measure the remaining "
                          "configurations and print their own line")
     args = ap.parse_args()
@@ -143,39 +143,46 @@ def main():
             if flushed:
                 do_flush(k)
             ev0[k].record(stream)
-            fn()
+            fn(k)
             ev1[k].record(stream)
         torch.cuda.synchronize()
         return 1e3 * float(np.mean([a.elapsed_time(b) for a, b in zip(ev0, ev1)]))
 
     def stencil_us(cols, flushed):
+        """(dispatch us, bracketed us) per launch: the kernel's own start and end recorded by the launch
+        (the interval a kernel trace reports), and the stream events recorded before and after it."""
         X = torch.randn((cols, w.N), dtype=dt, device=dev)
         Y = torch.empty_like(X)
         for _ in range(3):
             rw.apply_laplacian(g, X, Y)
-        return event_us(lambda: rw.apply_laplacian(g, X, Y), flushed)
+        d0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.spmm_reps)]
+        d1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.spmm_reps)]
+        br = event_us(lambda k: rw.apply_laplacian_timed(g, X, Y, d0[k], d1[k]), flushed)
+        return 1e3 * float(np.mean([a.elapsed_time(b) for a, b in zip(d0, d1)])), br
 
     def copy_us():
         X = torch.randn((nb, w.N), dtype=dt, device=dev)
         Y = torch.empty_like(X)
         Y.copy_(X)
-        return event_us(lambda: Y.copy_(X), True)
+        return event_us(lambda k: Y.copy_(X), True)
 
     def stencil_bytes(cols):
         return w.N * (2 * es * cols + es * (ndir + 1))       # read X, write Y, coefficients + diagonal
 
-    spmm_us = stencil_us(nb, True)
-    spmm_us_warm = stencil_us(nb, False)
+    spmm_us, spmm_us_br = stencil_us(nb, True)
+    spmm_us_warm, _ = stencil_us(nb, False)
     step_cols = w.m - 1                                        # the update step's operator block
-    step_us = stencil_us(step_cols, True)
+    step_us, _ = stencil_us(step_cols, True)
     spmm_bytes = stencil_bytes(nb)
     cp_us = copy_us()
     spmm_gbs = spmm_bytes / (spmm_us * 1e-6) / 1e9
     spmm_gbs_warm = spmm_bytes / (spmm_us_warm * 1e-6) / 1e9
+    spmm_gbs_br = spmm_bytes / (spmm_us_br * 1e-6) / 1e9
     step_gbs = stencil_bytes(step_cols) / (step_us * 1e-6) / 1e9
     copy_gbs = 2 * es * nb * w.N / (cp_us * 1e-6) / 1e9
     del flush_w, flush_r
-    log(f"stencil N x {nb} fp32: {spmm_us:.1f} us/launch flushed ({spmm_gbs:.0f} GB/s), {spmm_us_warm:.1f} us "
+    log(f"stencil N x {nb} fp32: {spmm_us:.1f} us/launch flushed ({spmm_gbs:.0f} GB/s; {spmm_us_br:.1f} us between "
+        f"stream events around it), {spmm_us_warm:.1f} us "
         f"back to back ({spmm_gbs_warm:.0f} GB/s); N x {step_cols}: {step_us:.1f} us ({step_gbs:.0f} GB/s); "
         f"copy of the block {cp_us:.1f} us ({copy_gbs:.0f} GB/s)")
 
@@ -245,10 +252,14 @@ def main():
                      "achieved": round(spmm_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(spmm_gbs / PEAK_HBM_GBS, 4), "traffic": stencil_traffic(nb, w.N),
                      "bytes_per_launch": spmm_bytes, "us_per_launch": round(spmm_us, 2),
-                     "timing": "HIP events per launch; before each launch, outside the events, 1.25 GiB written "
+                     "timing": "HIP events recorded by each launch at the kernel's own start and end "
+                               "(hipExtLaunchKernel), on the launch stream; before each launch 1.25 GiB written "
                                "then 512 MiB of another buffer read",
+                     "stream_events": {"achieved": round(spmm_gbs_br, 1), "us_per_launch": round(spmm_us_br, 2),
+                                       "note": "events recorded on the stream before and after the launch"},
                      "copy_same_protocol": {"achieved": round(copy_gbs, 1), "us_per_launch": round(cp_us, 2),
-                                            "frac": round(copy_gbs / PEAK_HBM_GBS, 4)},
+                                            "frac": round(copy_gbs / PEAK_HBM_GBS, 4),
+                                            "note": "torch copy_ of the block between stream events"},
                      "unflushed": {"achieved": round(spmm_gbs_warm, 1), "us_per_launch": round(spmm_us_warm, 2)},
                      "in_step_shape": {"cols": step_cols, "achieved": round(step_gbs, 1),
                                        "us_per_launch": round(step_us, 2),
@@ -820,9 +831,88 @@ def run_agg512(args, rw, rwsynth, torch, dev):
                  vs_full_graph={"label_agreement": vs_full}, parity=parity, cpu_baseline=cpu)
 
 
+def run_rwir96(args, rw, rwsynth, torch, dev):
+    """96^3, 6-connected, beta 50, FP32 graph, BF16 basis (m = 200, precomputed in FP32), 21 x 21 x 9 = 3969
+    displacement labels with BF16 priors, gamma 1, no seeds: the projection of the priors, the coefficients and
+    the per-voxel labels fused with the reconstruction (U not formed)."""
+    w = rwsynth.CFG6
+    J, _ = rwsynth.phantom(w, 0)
+    Jd = torch.as_tensor(J, device=dev)
+    g = rw.Graph(Jd, w.dims, w.conn, w.beta, dtype=torch.float32)
+    t_pre, (Q, lam, einfo) = _sync_time(torch, lambda: rw.precompute_eig(g, w.m, tol=1e-5, max_iter=400), 1)
+    Qb = rw.convert_block(Q.contiguous(), torch.bfloat16)
+    labels = rwsynth.displacement_labels(rwsynth.CFG6_EXTENT)
+    field = rwsynth.displacement_field(w.dims, rwsynth.CFG6_EXTENT, rwsynth.CFG6_ID)
+    P = rwsynth.displacement_priors_torch(torch.as_tensor(field, device=dev), torch.as_tensor(labels, device=dev),
+                                          dtype=torch.bfloat16, chunk=2048)
+    C, N, gamma = labels.shape[0], w.N, rwsynth.CFG6_GAMMA
+    ws = rw.SolveWorkspace()
+
+    def step():
+        return rw.solve_priors(g, Qb, lam, P, gamma, want_U=False, want_labels=True, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    t, (_, lab, prob, info) = _sync_time(torch, step, args.steps)
+    _, (_, lab_e, _, info_e) = _sync_time(torch, lambda: rw.solve_priors(g, Qb, lam, P, gamma, eps=0.1, r=4,
+                                                                         want_U=False, want_labels=True,
+                                                                         workspace=ws), 1)
+    p_bytes = N * C * 2
+    KR = (w.m + 31) // 32 * 32
+    KC = 16 * 13
+    flops = 2.0 * N * C * (KC + KR)
+    log(f"rwir96: {t * 1e3:.2f} ms per solve (N {N}, C {C}, m {info['m_used']}); priors read at "
+        f"{p_bytes / t / 1e9:.0f} GB/s over the whole call; eps 0.1 chooses m = {info_e['m_used']}")
+    parity = None
+    cpu = None
+    if not args.no_cpu:
+        from oracle.graph import Graph as OGraph
+        from oracle.rwir import rwir_coefficients
+        og = OGraph(J, w.dims, w.conn, w.beta)
+        Qn = Qb.double().cpu().numpy().T
+        rng = np.random.default_rng(5)
+        rows = np.sort(rng.choice(N, size=2048, replace=False))
+        t0 = time.perf_counter()
+        # the oracle's projection streamed over voxel chunks of the same BF16 priors (C x N on the device)
+        from oracle.eigen import insert_null
+        Qi, li = insert_null(Qn, lam.cpu().numpy(), og.ghat())
+        hs = og.hat_scale()
+        Z = np.zeros((w.m, C))
+        for a in range(0, N, 32768):
+            b = min(N, a + 32768)
+            Pc = P[:, a:b].double().cpu().numpy().T
+            Z += Qi[a:b].T @ (hs[a:b, None] * Pc)
+        Y = (gamma / (li + gamma))[:, None] * Z
+        t_z = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        Ur = (Qi[rows] @ Y) / hs[rows, None]
+        t_r = time.perf_counter() - t1
+        top = Ur.max(axis=1)
+        lg = lab.cpu().numpy()[rows]
+        at = Ur[np.arange(rows.size), lg]
+        parity = {"sampled_voxels": int(rows.size),
+                  "label_value_gap_max": float((top - at).max()),
+                  "prob_vs_oracle_maxabs": float(np.abs(prob.double().cpu().numpy()[rows] - at).max()),
+                  "labels_equal_oracle_argmax": float(np.mean(np.argmax(Ur, axis=1) == lg))}
+        t_o = t_z + t_r * N / rows.size
+        cpu = {"value": round(1.0 / t_o, 5), "unit": "solves/s", "cores": int(_cores()), "kind": "oracle",
+               "sample": f"the oracle's full projection of the priors ({t_z:.1f} s, FP64 numpy) plus its labels on "
+                         f"{rows.size} voxels ({t_r:.2f} s), the latter scaled to all {N} voxels"}
+    return _line("RW solves/s driven by priors alone at registration label counts (labels per voxel)",
+                 round(1.0 / t, 2), "solves/s", args, t * 1e3,
+                 "bf16 basis and priors on the matrix cores (f32 accumulation) + f64 coefficients",
+                 {"workload": "3D 96^3 6-connected phantom, beta 50, BF16 basis m=200, 21x21x9 = 3969 displacement "
+                              "labels (BF16 priors), gamma 1, no seeds", "N": N, "m": w.m, "C": C},
+                 m_used=info["m_used"], m_chosen_eps_0_1=info_e["m_used"],
+                 effective={"prior_bytes_per_solve": p_bytes, "prior_gbs_whole_call": round(p_bytes / t / 1e9, 1),
+                            "mfma_flop_per_solve": flops,
+                            "mfma_tflops_whole_call": round(flops / t / 1e12, 1)},
+                 precompute_s=round(t_pre, 2), parity=parity, cpu_baseline=cpu)
+
+
 MODES = {"small64": run_small64, "volume128": run_volume128, "batch64": run_batch64, "grad96": run_grad96,
          "prior512": run_prior512, "bank512": run_bank512,
-         "agg512": run_agg512}
+         "agg512": run_agg512, "rwir96": run_rwir96}
 
 
 if __name__ == "__main__":

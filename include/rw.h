@@ -369,7 +369,7 @@ int rw_solve_priors_workspace_bytes(rw_graph g, int q_dtype, int m_avail, int C,
  * on the FP64 basis Q' of rw_solve_seeds (the exact null vector first, the other columns made orthogonal to it).
  * Registration's result is, at each voxel, the label of largest probability (its displacement).
  *   Q, q_dtype  device m_avail x N basis: RW_F64, RW_F32 or RW_BF16 (column 0 the null pair's); with RW_BF16
- *            the projection and the labels run on the matrix cores (FP32 accumulation; m_avail <= 207);
+ *            the projection and the labels run on the matrix cores (FP32 accumulation; m_avail <= 223);
  *   lambda   device m_avail eigenvalues (FP64);
  *   prior    device C x N (label k's map contiguous), RW_BF16 or RW_F32 with a BF16 basis, RW_F64 or RW_F32
  *            otherwise; read-only;

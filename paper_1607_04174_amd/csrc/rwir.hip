@@ -34,6 +34,9 @@ __device__ __forceinline__ f4 mfma_bf16(uint4 a, uint4 b, f4 c) {
                                                  0, 0, 0);
 }
 
+// kappa of the label rows past C in the fused reconstruction: far below any probability, so they never win
+constexpr float kPadKappa = -1e30f;
+
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
   return (uint32_t)f32_to_bf16(lo) | ((uint32_t)f32_to_bf16(hi) << 16);
 }
@@ -51,19 +54,63 @@ __global__ void k_rwir_scales(const double* degree, const double* sums, int norm
   inv[i] = s > 0.0 ? (float)(1.0 / s) : 0.0f;
 }
 
+// Qs[c Np + i] = BF16(s_i q_c(i)) for c < ma, BF16(s_i g_i) for c = ma, 0 for c in (ma, KC) and for i >= N;
+// one thread per 8 voxels of one column (16-byte stores)
+__global__ void k_rwir_scaled_basis(const uint16_t* __restrict__ Q, int ma, int64_t N, int64_t Np, int KC,
+                                    const float* __restrict__ sv, const float* __restrict__ sg,
+                                    uint16_t* __restrict__ Qs) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t per = Np / 8;
+  if (t >= per * KC) return;
+  const int c = (int)(t / per);
+  const int64_t v = 8 * (t % per);
+  float x[8];
+  if (c > ma) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = 0.0f;
+  } else if ((N & 7) == 0 && v + 8 <= N) {   // 16-byte rows: vector loads
+    const float4 s0 = *reinterpret_cast<const float4*>((c < ma ? sv : sg) + v);
+    const float4 s1 = *reinterpret_cast<const float4*>((c < ma ? sv : sg) + v + 4);
+    const float sc[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+    if (c < ma) {
+      const uint4 q = *reinterpret_cast<const uint4*>(Q + (int64_t)c * N + v);
+      const uint32_t a[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[2 * u] = bf16_to_f32((uint16_t)(a[u] & 0xffffu)) * sc[2 * u];
+        x[2 * u + 1] = bf16_to_f32((uint16_t)(a[u] >> 16)) * sc[2 * u + 1];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = sc[e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t i = v + e;
+      x[e] = i >= N ? 0.0f : (c < ma ? bf16_to_f32(Q[(int64_t)c * N + i]) * sv[i] : sg[i]);
+    }
+  }
+  *reinterpret_cast<uint4*>(Qs + (int64_t)c * Np + v) =
+      uint4{pack_bf16(x[0], x[1]), pack_bf16(x[2], x[3]), pack_bf16(x[4], x[5]), pack_bf16(x[6], x[7])};
+}
+
 // ---------------------------------------------------------------------------------------------
 // projection on the matrix cores (BF16 basis)
 // ---------------------------------------------------------------------------------------------
-// Workgroup: 4 waves, 256 labels (each wave 4 sub-tiles of 16), all KC = 16 NCT staged columns (the ma stored
-// columns, g, zeros), one chunk of voxels in stages of 64 (two K steps of 32).  The staged tile holds
-// s_i q_j(i) (and s_i g_i) in BF16, [column][voxel] with a padded row, double-buffered in LDS; the priors'
-// fragments come from HBM straight into registers, one stage ahead.  Output: FP32 partials per chunk,
+// Workgroup: 8 waves, 256 labels x KC = 32 NH columns of the scaled basis Qs (s_i q_j(i) for the ma stored
+// columns, s_i g_i, zeros: one pass per call, row stride Np), one chunk of voxels in stages of 64 (two K steps
+// of 32).  Wave w takes labels 64 (w % 4) .. +63 (4 sub-tiles of 16) against column half w / 4 (NH tiles of 16),
+// so that two waves share each SIMD.  The stage's Qs tile is copied to LDS ([column][voxel], padded row,
+// double-buffered); the priors' fragments come from HBM straight into registers, one stage ahead (the two
+// column halves read the same fragments; the second read hits the cache).  Output: FP32 partials per chunk,
 // part[(chunk C + label) KC + column].
 constexpr int kPjVox = 64;
 constexpr int kPjRow = kPjVox + 8;   // staged row in BF16 elements: conflict-free 16-byte fragment reads
 constexpr int kPjLab = 256;
+constexpr int kPjThreads = 512;
 
-size_t rwir_proj_lds(int nct) { return (size_t)2 * nct * 16 * kPjRow * sizeof(uint16_t); }
+size_t rwir_proj_lds(int kc) { return (size_t)2 * kc * kPjRow * sizeof(uint16_t); }
 
 template <typename TP>
 __device__ __forceinline__ uint4 load_p8(const TP* row, int64_t v, int64_t vend, bool ok, bool vec);
@@ -92,17 +139,17 @@ __device__ __forceinline__ uint4 load_p8<float>(const float* row, int64_t v, int
   return uint4{pack_bf16(e[0], e[1]), pack_bf16(e[2], e[3]), pack_bf16(e[4], e[5]), pack_bf16(e[6], e[7])};
 }
 
-template <typename TP, int NCT>
-__global__ __launch_bounds__(256) void k_rwir_proj(const uint16_t* __restrict__ Q, int ma, int64_t N,
-                                                   const TP* __restrict__ P, int C, const float* __restrict__ sv,
-                                                   const float* __restrict__ sg, int64_t chunk, int nlt,
-                                                   int64_t nwg, float* __restrict__ part) {
-  constexpr int KC = NCT * 16;
+template <typename TP, int NH>
+__global__ __launch_bounds__(kPjThreads) void k_rwir_proj(const uint16_t* __restrict__ Qs, int64_t Np, int64_t N,
+                                                          const TP* __restrict__ P, int C, int64_t chunk, int nlt,
+                                                          int64_t nwg, float* __restrict__ part) {
+  constexpr int KC = 32 * NH;
   constexpr int PIECES = KC * (kPjVox / 8);            // 16-byte pieces of one staged tile
-  constexpr int PQ = (PIECES + 255) / 256;
+  constexpr int PQ = (PIECES + kPjThreads - 1) / kPjThreads;
   extern __shared__ __align__(16) char smem[];
   uint16_t* sQ = reinterpret_cast<uint16_t*>(smem);   // [2][KC][kPjRow]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lg = wave & 3, c0 = (wave >> 2) * NH;      // label group, first column tile
   // XCD-contiguous workgroups: the label tiles of one voxel chunk run on one XCD and share its L2
   const int64_t per_xcd = (nwg + 7) / 8;
   const int64_t L = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
@@ -112,85 +159,89 @@ __global__ __launch_bounds__(256) void k_rwir_proj(const uint16_t* __restrict__ 
   const int64_t vb = ck * chunk, ve = min(N, vb + chunk);
   const int nst = (int)((ve - vb + kPjVox - 1) / kPjVox);
   const int lrow = lane & 15, kg = lane >> 4;
-  const bool vecq = (N & 7) == 0;
-  const bool vecp = vecq;
+  const bool vecp = (N & 7) == 0;
+  // rows past C read row C - 1 and are zeroed (no branch on the label)
   const TP* prow[4];
   bool pok[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int64_t lab = (int64_t)lt * kPjLab + wave * 64 + t * 16 + lrow;
+    const int64_t lab = (int64_t)lt * kPjLab + lg * 64 + t * 16 + lrow;
     pok[t] = lab < C;
-    prow[t] = P + (pok[t] ? lab : 0) * N;
+    prow[t] = P + (pok[t] ? lab : (int64_t)C - 1) * N;
   }
+  // a stage's tile: 16-byte pieces (column p / 8, voxels 8 (p % 8) .. +7).  A piece that starts inside the chunk
+  // ends inside it (chunk ends are multiples of 64) or, in the last chunk, inside Qs's zero padding past N.
   uint4 qreg[PQ];
   auto load_stage = [&](int st) {
     const int64_t v0 = vb + (int64_t)st * kPjVox;
 #pragma unroll
     for (int q = 0; q < PQ; ++q) {
-      const int p = tid + 256 * q;
-      const int col = p >> 3;
+      const int p = tid + kPjThreads * q;
       const int64_t v = v0 + 8 * (p & 7);
-      if (p < PIECES && col < ma) {
-        const uint16_t* r = Q + (int64_t)col * N;
-        if (vecq && v + 8 <= ve) {
-          qreg[q] = *reinterpret_cast<const uint4*>(r + v);
-        } else {
-          uint16_t e[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) e[u] = v + u < ve ? r[v + u] : (uint16_t)0;
-          qreg[q] = uint4{e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16),
-                          e[4] | ((uint32_t)e[5] << 16), e[6] | ((uint32_t)e[7] << 16)};
-        }
-      } else {
-        qreg[q] = uint4{0u, 0u, 0u, 0u};
-      }
+      const bool ok = p < PIECES && v < ve;
+      const uint4 x = *reinterpret_cast<const uint4*>(Qs + (ok ? (int64_t)(p >> 3) * Np + v : 0));
+      qreg[q] = ok ? x : uint4{0u, 0u, 0u, 0u};
     }
   };
-  auto store_stage = [&](int st, int buf) {
-    const int64_t v0 = vb + (int64_t)st * kPjVox;
+  auto store_stage = [&](int buf) {
     uint16_t* dst = sQ + buf * KC * kPjRow;
 #pragma unroll
     for (int q = 0; q < PQ; ++q) {
-      const int p = tid + 256 * q;
-      if (p >= PIECES) break;
-      const int col = p >> 3, v8 = p & 7;
-      const int64_t v = v0 + 8 * v8;
-      float s[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) s[u] = v + u < ve ? (col == ma ? sg[v + u] : sv[v + u]) : 0.0f;
-      uint4 w;
-      if (col < ma) {
-        const uint32_t a[4] = {qreg[q].x, qreg[q].y, qreg[q].z, qreg[q].w};
-        uint32_t o[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          o[u] = pack_bf16(bf16_to_f32((uint16_t)(a[u] & 0xffffu)) * s[2 * u],
-                           bf16_to_f32((uint16_t)(a[u] >> 16)) * s[2 * u + 1]);
-        w = uint4{o[0], o[1], o[2], o[3]};
-      } else if (col == ma) {
-        w = uint4{pack_bf16(s[0], s[1]), pack_bf16(s[2], s[3]), pack_bf16(s[4], s[5]), pack_bf16(s[6], s[7])};
-      } else {
-        w = uint4{0u, 0u, 0u, 0u};
-      }
-      *reinterpret_cast<uint4*>(dst + col * kPjRow + 8 * v8) = w;
+      const int p = tid + kPjThreads * q;
+      if (p < PIECES) *reinterpret_cast<uint4*>(dst + (p >> 3) * kPjRow + 8 * (p & 7)) = qreg[q];
     }
   };
   uint4 pa[4][2], pn[4][2];
+  // a full stage (64 voxels inside the chunk, rows 16-byte aligned) loads without checks; the chunk's last
+  // stage, or rows of any alignment, check every voxel
   auto load_p = [&](uint4 (&dst)[4][2], int st) {
     const int64_t v0 = vb + (int64_t)st * kPjVox;
+    if (vecp && v0 + kPjVox <= ve) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) dst[t][ks] = load_p8<TP>(prow[t], v0 + 32 * ks + 8 * kg, ve, pok[t], vecp);
+        for (int ks = 0; ks < 2; ++ks) {
+          const uint4 x = load_p8<TP>(prow[t], v0 + 32 * ks + 8 * kg, ve, true, true);
+          dst[t][ks] = pok[t] ? x : uint4{0u, 0u, 0u, 0u};
+        }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+          dst[t][ks] = load_p8<TP>(prow[t], v0 + 32 * ks + 8 * kg, ve, pok[t], vecp);
+    }
   };
-  f4 acc[4][NCT];
+  f4 acc[4][NH];
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int c = 0; c < NCT; ++c) acc[t][c] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < NH; ++c) acc[t][c] = f4{0.f, 0.f, 0.f, 0.f};
+  // one stage: 2 NH column fragments from LDS, each read one step before its 4 products
+  auto compute = [&](const uint4 (&pf)[4][2], int buf) {
+    const uint16_t* src = sQ + buf * KC * kPjRow + (c0 * 16 + lrow) * kPjRow + 8 * kg;
+    uint4 bn = *reinterpret_cast<const uint4*>(src);
+#pragma unroll
+    for (int q = 0; q < 2 * NH; ++q) {
+      const int ks = q / NH, c = q % NH;
+      const uint4 b = bn;
+      if (q + 1 < 2 * NH)
+        bn = *reinterpret_cast<const uint4*>(src + ((q + 1) % NH) * 16 * kPjRow + 32 * ((q + 1) / NH));
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t][c] = mfma_bf16(pf[t][ks], b, acc[t][c]);
+    }
+    // keep each fragment read one group of products ahead of its use (the scheduler would sink it)
+    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+#pragma unroll
+    for (int q = 0; q < 2 * NH - 2; ++q) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+  };
   load_p(pa, 0);
   load_stage(0);
-  store_stage(0, 0);
+  store_stage(0);
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
     const int cur = st & 1;
@@ -199,18 +250,9 @@ __global__ __launch_bounds__(256) void k_rwir_proj(const uint16_t* __restrict__ 
       load_p(pn, st + 1);
       load_stage(st + 1);
     }
-    const uint16_t* src = sQ + cur * KC * kPjRow;
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-#pragma unroll
-      for (int c = 0; c < NCT; ++c) {
-        const uint4 b = *reinterpret_cast<const uint4*>(src + (c * 16 + lrow) * kPjRow + 32 * ks + 8 * kg);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t][c] = mfma_bf16(pa[t][ks], b, acc[t][c]);
-      }
-    }
+    compute(pa, cur);
     if (more) {
-      store_stage(st + 1, cur ^ 1);
+      store_stage(cur ^ 1);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         pa[t][0] = pn[t][0];
@@ -224,11 +266,11 @@ __global__ __launch_bounds__(256) void k_rwir_proj(const uint16_t* __restrict__ 
   for (int t = 0; t < 4; ++t) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t lab = (int64_t)lt * kPjLab + wave * 64 + t * 16 + 4 * kg + v;
+      const int64_t lab = (int64_t)lt * kPjLab + lg * 64 + t * 16 + 4 * kg + v;
       if (lab >= C) continue;
-      float* dst = part + (ck * C + lab) * KC + lrow;
+      float* dst = part + (ck * C + lab) * KC + c0 * 16 + lrow;
 #pragma unroll
-      for (int c = 0; c < NCT; ++c) dst[c * 16] = acc[t][c][v];
+      for (int c = 0; c < NH; ++c) dst[c * 16] = acc[t][c][v];
     }
   }
 }
@@ -290,56 +332,76 @@ __global__ void k_rwir_reduce(const TA* part, int64_t nchunk, int C, int ma, int
   else gdot[k] = a;
 }
 
-// ||p_hat_k||^2 for the sampled labels k = q step (one workgroup each, FP64), and their Z_hat columns beside
-// them for the host: stage[q ma + j] = Z_hat(j, k), stage[ns ma + q] = ||p_hat_k||^2
+// ||p_hat_k||^2 for the sampled labels k = q step: workgroup (b, q) sums voxels b, b + kNormBlocks 256, ... of
+// label k (FP64) into part[q kNormBlocks + b]; k_rwir_norms_finish adds the partials in order and puts the
+// sampled labels' Z_hat columns beside them for the host: stage[q ma + j] = Z_hat(j, k), stage[ns ma + q] =
+// ||p_hat_k||^2
+constexpr int kNormBlocks = 64;
+
 template <typename TP>
 __global__ __launch_bounds__(256) void k_rwir_norms(const TP* P, int64_t N, int step, const double* degree,
-                                                    int normalized, const double* Zh, int ma, int ns,
-                                                    double* stage) {
+                                                    int normalized, double* part) {
   __shared__ double sh[4];
-  const int q = blockIdx.x, tid = threadIdx.x;
+  const int b = blockIdx.x, q = blockIdx.y, tid = threadIdx.x;
   const int64_t k = (int64_t)q * step;
   double a = 0.0;
-  for (int64_t i = tid; i < N; i += 256) {
+  for (int64_t i = (int64_t)b * 256 + tid; i < N; i += (int64_t)kNormBlocks * 256) {
     const double x = (normalized ? sqrt(degree[i]) : 1.0) * (double)Elem<TP>::ld(P, k * N + i);
     a += x * x;
   }
   a = wave_sum64(a);
   if ((tid & 63) == 0) sh[tid >> 6] = a;
   __syncthreads();
-  if (tid == 0) stage[(int64_t)ns * ma + q] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  if (tid == 0) part[(int64_t)q * kNormBlocks + b] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ __launch_bounds__(256) void k_rwir_norms_finish(const double* part, int step, const double* Zh, int ma,
+                                                           int ns, double* stage) {
+  const int q = blockIdx.x, tid = threadIdx.x;
+  const int64_t k = (int64_t)q * step;
+  if (tid == 0) {
+    double a = 0.0;
+    for (int b = 0; b < kNormBlocks; ++b) a += part[(int64_t)q * kNormBlocks + b];
+    stage[(int64_t)ns * ma + q] = a;
+  }
   for (int j = tid; j < ma; j += 256) stage[(int64_t)q * ma + j] = Zh[j + k * ma];
 }
 
-// One thread per label: Z'(j) = g^T P_hat (j = 0) or (Z_hat(j) - c_j g^T P_hat) / n_j, Y(j) = gamma Z'(j) /
-// (lambda_j + gamma), then Y(j) /= n_j (j >= 1) and kappa = sg (Y(0) - sum_{j>=1} c_j Y(j)) in Y(0).  With Yt,
-// the labels' BF16 rows for the fused reconstruction: Yt[k KR + (j - 1)] = Y(j) for j in [1, m), Yt[k KR +
-// KR - 1] = kappa, zeros between; rows k in [C, Cpad) zero.
-__global__ void k_rwir_coeffs(const double* Zh, const double* gdot, int ma, int m, int C, int Cpad,
-                              const double* lambda, double gamma, const double* cn, const double* sums,
-                              int normalized, int64_t N, double* Y, uint16_t* Yt, int KR) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// One wave per label: Z'(j) = g^T P_hat (j = 0) or (Z_hat(j) - c_j g^T P_hat) / n_j, Y(j) = gamma Z'(j) /
+// (lambda_j + gamma), then Y(j) /= n_j (j >= 1) and kappa = sg (Y(0) - sum_{j>=1} c_j Y(j)) in Y(0) (lanes take
+// j in strides, then a wave sum).  With Yt, the labels' BF16 rows for the fused reconstruction: Yt[k KR + (j -
+// 1)] = Y(j) for j in [1, m), Yt[k KR + KR - 1] = kappa, zeros between; rows k in [C, Cpad) zero but for
+// kPadKappa in the last column.
+__global__ __launch_bounds__(256) void k_rwir_coeffs(const double* Zh, const double* gdot, int ma, int m, int C,
+                                                     int Cpad, const double* lambda, double gamma, const double* cn,
+                                                     const double* sums, int normalized, int64_t N, double* Y,
+                                                     uint16_t* Yt, int KR) {
+  const int lane = threadIdx.x & 63;
+  const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (k >= Cpad) return;
   if (k >= C) {
     if (Yt)
-      for (int q = 0; q < KR; ++q) Yt[k * KR + q] = 0;
+      for (int q = lane; q < KR; q += 64) Yt[k * KR + q] = q == KR - 1 ? f32_to_bf16(kPadKappa) : (uint16_t)0;
     return;
   }
   const double gd = gdot[k];
   const double* z = Zh + k * ma;
   double* y = Y + k * m;
-  const double y0 = gamma * gd / (lambda[0] + gamma);
-  for (int j = 1; j < m; ++j) {
+  double part = 0.0;
+  for (int j = 1 + lane; j < m; j += 64) {
     const double zp = (z[j] - cn[j] * gd) / cn[m + j];
-    y[j] = gamma * zp / (lambda[j] + gamma) / cn[m + j];
+    const double yj = gamma * zp / (lambda[j] + gamma) / cn[m + j];
+    y[j] = yj;
+    part += cn[j] * yj;
+    if (Yt) Yt[k * KR + (j - 1)] = f32_to_bf16((float)yj);
   }
-  double acc = y0;
-  for (int j = 1; j < m; ++j) acc -= cn[j] * y[j];
-  y[0] = ghat_scaled64(sums, normalized, N) * acc;
-  if (Yt) {
-    uint16_t* r = Yt + k * KR;
-    for (int q = 0; q < KR - 1; ++q) r[q] = q + 1 < m ? f32_to_bf16((float)y[q + 1]) : (uint16_t)0;
-    r[KR - 1] = f32_to_bf16((float)y[0]);
+  part = wave_sum64(part);
+  if (Yt)
+    for (int q = m - 1 + lane; q < KR - 1; q += 64) Yt[k * KR + q] = 0;
+  if (lane == 0) {
+    const double kap = ghat_scaled64(sums, normalized, N) * (gamma * gd / (lambda[0] + gamma) - part);
+    y[0] = kap;
+    if (Yt) Yt[k * KR + KR - 1] = f32_to_bf16((float)kap);
   }
 }
 
@@ -356,16 +418,30 @@ __global__ __launch_bounds__(256) void k_rwir_transpose(const uint16_t* __restri
   const int tid = threadIdx.x;
   const int64_t v0 = (int64_t)blockIdx.x * 64;
   const int q0 = blockIdx.y * 32;
-  for (int e = tid; e < 64 * 32; e += 256) {
-    const int r = e >> 6, v = e & 63;   // column q0 + r, voxel v0 + v
+  {
+    // thread: column q0 + tid / 8, voxels v0 + 8 (tid % 8) .. +7
+    const int r = tid >> 3, v8 = 8 * (tid & 7);
     const int q = q0 + r;
-    const int64_t i = v0 + v;
-    uint16_t x = 0;
-    if (i < N) {
-      if (q + 1 < ma) x = Q[(int64_t)(q + 1) * N + i];
-      else if (q == KR - 1) x = f32_to_bf16(sv[i]);
+    const int64_t i = v0 + v8;
+    uint16_t x[8];
+    if (q + 1 < ma && (N & 7) == 0 && i + 8 <= N) {
+      const uint4 w = *reinterpret_cast<const uint4*>(Q + (int64_t)(q + 1) * N + i);
+      const uint32_t a[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[2 * u] = (uint16_t)(a[u] & 0xffffu);
+        x[2 * u + 1] = (uint16_t)(a[u] >> 16);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t ie = i + e;
+        x[e] = ie >= N ? (uint16_t)0
+                       : (q + 1 < ma ? Q[(int64_t)(q + 1) * N + ie] : (q == KR - 1 ? f32_to_bf16(sv[ie]) : (uint16_t)0));
+      }
     }
-    t[v][r] = x;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[v8 + e][r] = x[e];
   }
   __syncthreads();
   // each thread writes 8 columns (16 bytes) of one voxel: 64 voxels x 4 pieces
@@ -380,15 +456,17 @@ __global__ __launch_bounds__(256) void k_rwir_transpose(const uint16_t* __restri
 }
 
 // Workgroup: 4 waves x 8 sub-tiles of 16 voxels.  A wave keeps its 128 voxels' basis fragments (KS K steps
-// of 32) in registers and runs over all labels in tiles of 16: D[label 4 kg + v][voxel lrow] = s_i U(label,
-// i), the larger value kept per lane (labels in increasing order, strict comparison), then the four lanes of
-// a voxel merged (larger value, or equal value and smaller label).  label[i] and prob[i] = s_i^{-1} D; a voxel
-// with d_i = 0 gets label 0 and probability 0.
+// of 32) in registers and runs over the labels in tiles of 16, two at a time: D[label 4 kg + v][voxel lrow] =
+// s_i U(label, i); the label fragments of tile t + 2 load while tile t + 1's products run, and tile t's
+// comparisons follow tile t + 1's products (no register copies between tiles).  The larger value is kept per
+// lane (labels in increasing order, strict comparison), then the four lanes of a voxel merged (larger value,
+// or equal value and smaller label).  Rows of Yt past C carry -1e30 against the s column and never win.  label[i] and
+// prob[i] = s_i^{-1} D; a voxel with d_i = 0 gets label 0 and probability 0.
 constexpr int kLbSub = 8;
 
 template <int KS, typename TU>
 __global__ __launch_bounds__(256) void k_rwir_label_mfma(const uint16_t* __restrict__ Qt, int64_t N,
-                                                         const uint16_t* __restrict__ Yt, int C,
+                                                         const uint16_t* __restrict__ Yt, int Cpad,
                                                          const float* __restrict__ inv, int32_t* __restrict__ label,
                                                          TU* __restrict__ prob) {
   constexpr int KR = 32 * KS;
@@ -411,37 +489,48 @@ __global__ __launch_bounds__(256) void k_rwir_label_mfma(const uint16_t* __restr
     best[u] = -INFINITY;
     bidx[u] = 0;
   }
-  const int ntile = (C + 15) >> 4;
-  uint4 a[KS], an[KS];
+  const int ntile = Cpad >> 4;   // even
+  auto load_a = [&](uint4 (&a)[KS], int tl) {
 #pragma unroll
-  for (int s = 0; s < KS; ++s) a[s] = *reinterpret_cast<const uint4*>(Yt + (int64_t)lrow * KR + 32 * s + 8 * kg);
-  for (int tl = 0; tl < ntile; ++tl) {
-    if (tl + 1 < ntile) {
+    for (int s = 0; s < KS; ++s)
+      a[s] = *reinterpret_cast<const uint4*>(Yt + ((int64_t)tl * 16 + lrow) * KR + 32 * s + 8 * kg);
+  };
+  auto mma = [&](f4 (&c)[kLbSub], const uint4 (&a)[KS]) {
 #pragma unroll
-      for (int s = 0; s < KS; ++s)
-        an[s] = *reinterpret_cast<const uint4*>(Yt + ((int64_t)(tl + 1) * 16 + lrow) * KR + 32 * s + 8 * kg);
-    }
-    f4 acc[kLbSub];
-#pragma unroll
-    for (int u = 0; u < kLbSub; ++u) acc[u] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < kLbSub; ++u) c[u] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < KS; ++s)
 #pragma unroll
-      for (int u = 0; u < kLbSub; ++u) acc[u] = mfma_bf16(a[s], b[u][s], acc[u]);
-    const int l0 = tl * 16 + 4 * kg;
+      for (int u = 0; u < kLbSub; ++u) c[u] = mfma_bf16(a[s], b[u][s], c[u]);
+  };
+  auto pick = [&](const f4 (&c)[kLbSub], int l0) {
 #pragma unroll
     for (int u = 0; u < kLbSub; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        if (l0 + v < C && acc[u][v] > best[u]) {
-          best[u] = acc[u][v];
-          bidx[u] = l0 + v;
-        }
-    if (tl + 1 < ntile) {
-#pragma unroll
-      for (int s = 0; s < KS; ++s) a[s] = an[s];
-    }
+      for (int v = 0; v < 4; ++v) {
+        const float x = c[u][v];
+        const bool gt = x > best[u];
+        best[u] = gt ? x : best[u];
+        bidx[u] = gt ? l0 + v : bidx[u];
+      }
+  };
+  uint4 a0[KS], a1[KS];
+  f4 c0[kLbSub], c1[kLbSub];
+  load_a(a0, 0);
+  load_a(a1, 1);
+  mma(c0, a0);
+  int tl = 0;
+  for (; tl + 2 < ntile; tl += 2) {   // ntile is even: tl + 3 < ntile here
+    load_a(a0, tl + 2);
+    mma(c1, a1);
+    pick(c0, tl * 16 + 4 * kg);
+    load_a(a1, tl + 3);
+    mma(c0, a0);
+    pick(c1, (tl + 1) * 16 + 4 * kg);
   }
+  mma(c1, a1);
+  pick(c0, tl * 16 + 4 * kg);
+  pick(c1, (tl + 1) * 16 + 4 * kg);
 #pragma unroll
   for (int u = 0; u < kLbSub; ++u) {
 #pragma unroll
@@ -545,7 +634,7 @@ constexpr int kPlainChunk = 16384;      // voxels per chunk of the FP64-accumula
 
 struct RwirDims {
   int ma, C, KC, KR, Cpad, ns, step;
-  int64_t nchunk, chunk, nlt;
+  int64_t nchunk, chunk, nlt, Np;
   bool mfma;
 };
 
@@ -556,9 +645,10 @@ static RwirDims rwir_dims(const Graph* g, int qdt, int ma, int C, int r) {
   d.mfma = qdt == RW_BF16;
   // staged columns of the projection (the ma stored columns and g): the matrix-core kernel's width, else 16s
   const int nct = (ma + 1 + 15) / 16;
-  d.KC = 16 * (d.mfma ? (nct <= 4 ? 4 : (nct <= 8 ? 8 : 13)) : nct);
+  d.KC = 16 * (d.mfma ? (nct <= 4 ? 4 : (nct <= 8 ? 8 : 14)) : nct);
   d.KR = (ma + 31) / 32 * 32;          // columns 1 .. ma-1, zeros, kappa's column last
-  d.Cpad = (C + 15) / 16 * 16;
+  d.Cpad = (C + 31) / 32 * 32;   // label tiles of 16, taken in pairs
+  d.Np = (g->N + 7) / 8 * 8;
   int step = 1;
   for (int q = 0; q < g->ndim; ++q) step *= std::max(1, r);
   d.step = step;
@@ -579,10 +669,10 @@ static RwirDims rwir_dims(const Graph* g, int qdt, int ma, int C, int r) {
 struct RwirWork {
   float *sv, *sg, *inv;
   void* part;
-  double *Zh, *gdot, *Y, *cn, *npart, *stage;
+  double *Zh, *gdot, *Y, *cn, *npart, *stage, *npart2;
   int* nbad;
   uint8_t* map;
-  uint16_t *Yt, *Qt;
+  uint16_t *Yt, *Qt, *Qs;
 };
 
 static size_t rwir_layout(const Graph* g, const RwirDims& d, bool labels, void* base, RwirWork* w) {
@@ -599,28 +689,32 @@ static size_t rwir_layout(const Graph* g, const RwirDims& d, bool labels, void* 
   t.cn = c.take<double>(2 * (size_t)d.ma);
   t.npart = c.take<double>(null_stats_partial_count(g->N, d.ma));
   t.stage = c.take<double>((size_t)d.ns * d.ma + d.ns);
+  t.npart2 = c.take<double>((size_t)d.ns * kNormBlocks);
   t.nbad = c.take<int>(1);
   t.map = c.take<uint8_t>(g->N);
   t.Yt = (d.mfma && labels) ? c.take<uint16_t>((size_t)d.Cpad * d.KR) : nullptr;
   t.Qt = (d.mfma && labels) ? c.take<uint16_t>((size_t)g->N * d.KR) : nullptr;
+  t.Qs = d.mfma ? c.take<uint16_t>((size_t)d.KC * d.Np) : nullptr;
   if (w) *w = t;
   return c.used + 256;
 }
 
-template <typename TP, int NCT>
+template <typename TP, int NH>
 static int launch_proj(const Graph* g, const uint16_t* Q, const RwirDims& d, const void* P, const RwirWork& w,
                        hipStream_t s) {
   static bool attr = false;
-  const size_t lds = rwir_proj_lds(NCT);
+  const size_t lds = rwir_proj_lds(32 * NH);
   if (!attr) {
-    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_rwir_proj<TP, NCT>),
+    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_rwir_proj<TP, NH>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
   const int64_t nwg = d.nchunk * d.nlt;
   const int64_t grid = (nwg + 7) / 8 * 8;
-  k_rwir_proj<TP, NCT><<<(unsigned)grid, 256, lds, s>>>(Q, d.ma, g->N, static_cast<const TP*>(P), d.C, w.sv, w.sg,
-                                                        d.chunk, (int)d.nlt, nwg, static_cast<float*>(w.part));
+  k_rwir_scaled_basis<<<nblocks(d.Np / 8 * d.KC, 256), 256, 0, s>>>(Q, d.ma, g->N, d.Np, d.KC, w.sv, w.sg, w.Qs);
+  RW_LAUNCH_CHECK();
+  k_rwir_proj<TP, NH><<<(unsigned)grid, kPjThreads, lds, s>>>(w.Qs, d.Np, g->N, static_cast<const TP*>(P), d.C,
+                                                               d.chunk, (int)d.nlt, nwg, static_cast<float*>(w.part));
   RW_LAUNCH_CHECK();
   return RW_OK;
 }
@@ -629,9 +723,9 @@ template <typename TP>
 static int proj_mfma(const Graph* g, const uint16_t* Q, const RwirDims& d, const void* P, const RwirWork& w,
                      hipStream_t s) {
   // d.KC is the kernel's width (the partial layout's stride)
-  if (d.KC == 64) return launch_proj<TP, 4>(g, Q, d, P, w, s);
-  if (d.KC == 128) return launch_proj<TP, 8>(g, Q, d, P, w, s);
-  return launch_proj<TP, 13>(g, Q, d, P, w, s);
+  if (d.KC == 64) return launch_proj<TP, 2>(g, Q, d, P, w, s);
+  if (d.KC == 128) return launch_proj<TP, 4>(g, Q, d, P, w, s);
+  return launch_proj<TP, 7>(g, Q, d, P, w, s);
 }
 
 template <int KS>
@@ -639,9 +733,11 @@ static int label_mfma_t(const Graph* g, const RwirDims& d, const RwirWork& w, in
                         hipStream_t s) {
   const unsigned nb = (unsigned)((g->N + 4 * 16 * kLbSub - 1) / (4 * 16 * kLbSub));
   if (g->dtype == RW_F64)
-    k_rwir_label_mfma<KS, double><<<nb, 256, 0, s>>>(w.Qt, g->N, w.Yt, d.C, w.inv, label, static_cast<double*>(prob));
+    k_rwir_label_mfma<KS, double><<<nb, 256, 0, s>>>(w.Qt, g->N, w.Yt, d.Cpad, w.inv, label,
+                                                     static_cast<double*>(prob));
   else
-    k_rwir_label_mfma<KS, float><<<nb, 256, 0, s>>>(w.Qt, g->N, w.Yt, d.C, w.inv, label, static_cast<float*>(prob));
+    k_rwir_label_mfma<KS, float><<<nb, 256, 0, s>>>(w.Qt, g->N, w.Yt, d.Cpad, w.inv, label,
+                                                    static_cast<float*>(prob));
   RW_LAUNCH_CHECK();
   return RW_OK;
 }
@@ -691,7 +787,7 @@ int rw_solve_priors(rw_graph h, const void* Q, int q_dtype, const double* lambda
   RW_CHECK(mf ? (prior_dtype == RW_BF16 || prior_dtype == RW_F32)
               : (prior_dtype == RW_F64 || prior_dtype == RW_F32),
            RW_EINVAL, "priors: RW_BF16 or RW_F32 with a BF16 basis, RW_F64 or RW_F32 otherwise");
-  RW_CHECK(!mf || m_avail + 1 <= 13 * 16, RW_EINVAL, "a BF16 basis takes m_avail <= %d here (got %d)", 13 * 16 - 1,
+  RW_CHECK(!mf || m_avail + 1 <= 14 * 16, RW_EINVAL, "a BF16 basis takes m_avail <= %d here (got %d)", 14 * 16 - 1,
            m_avail);
   RW_CHECK(!mf || (m_avail + 31) / 32 <= 8, RW_EINVAL, "m_avail too large for the label kernel");
   RW_CHECK((int64_t)C * g->N < ((int64_t)1 << 62), RW_EINVAL, "C x N too large");
@@ -735,15 +831,18 @@ int rw_solve_priors(rw_graph h, const void* Q, int q_dtype, const double* lambda
   int m = m_avail;
   double gmax = 0.0, gworst = 0.0;
   if (eps > 0.0) {
+    const dim3 ng(kNormBlocks, (unsigned)d.ns);
     if (prior_dtype == RW_F64)
-      k_rwir_norms<double><<<d.ns, 256, 0, stream>>>(static_cast<const double*>(prior), g->N, d.step, g->degree,
-                                                     g->normalized, w.Zh, m_avail, d.ns, w.stage);
+      k_rwir_norms<double><<<ng, 256, 0, stream>>>(static_cast<const double*>(prior), g->N, d.step, g->degree,
+                                                   g->normalized, w.npart2);
     else if (prior_dtype == RW_F32)
-      k_rwir_norms<float><<<d.ns, 256, 0, stream>>>(static_cast<const float*>(prior), g->N, d.step, g->degree,
-                                                    g->normalized, w.Zh, m_avail, d.ns, w.stage);
+      k_rwir_norms<float><<<ng, 256, 0, stream>>>(static_cast<const float*>(prior), g->N, d.step, g->degree,
+                                                  g->normalized, w.npart2);
     else
-      k_rwir_norms<uint16_t><<<d.ns, 256, 0, stream>>>(static_cast<const uint16_t*>(prior), g->N, d.step,
-                                                       g->degree, g->normalized, w.Zh, m_avail, d.ns, w.stage);
+      k_rwir_norms<uint16_t><<<ng, 256, 0, stream>>>(static_cast<const uint16_t*>(prior), g->N, d.step, g->degree,
+                                                     g->normalized, w.npart2);
+    RW_LAUNCH_CHECK();
+    k_rwir_norms_finish<<<d.ns, 256, 0, stream>>>(w.npart2, d.step, w.Zh, m_avail, d.ns, w.stage);
     RW_LAUNCH_CHECK();
     const size_t nst = (size_t)d.ns * m_avail + d.ns;
     void* stage = nullptr;
@@ -772,7 +871,7 @@ int rw_solve_priors(rw_graph h, const void* Q, int q_dtype, const double* lambda
   RW_TRY(fill_i32(w.nbad, 1, 0, stream));
   RW_TRY(null_stats(g, Q, q_dtype, m, w.npart, w.cn, w.nbad, stream));
   const bool fused = mf && label != nullptr;
-  k_rwir_coeffs<<<nblocks(d.Cpad, 256), 256, 0, stream>>>(w.Zh, w.gdot, m_avail, m, C, d.Cpad, lambda, gamma, w.cn,
+  k_rwir_coeffs<<<nblocks(d.Cpad, 4), 256, 0, stream>>>(w.Zh, w.gdot, m_avail, m, C, d.Cpad, lambda, gamma, w.cn,
                                                           g->sums, g->normalized, g->N, w.Y,
                                                           fused ? w.Yt : nullptr, d.KR);
   RW_LAUNCH_CHECK();
