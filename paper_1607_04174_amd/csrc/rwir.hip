@@ -139,7 +139,7 @@ __device__ __forceinline__ uint4 load_p8<float>(const float* row, int64_t v, int
   return uint4{pack_bf16(e[0], e[1]), pack_bf16(e[2], e[3]), pack_bf16(e[4], e[5]), pack_bf16(e[6], e[7])};
 }
 
-template <typename TP, int NH>
+template <typename TP, int NH, bool VEC>
 __global__ __launch_bounds__(kPjThreads) void k_rwir_proj(const uint16_t* __restrict__ Qs, int64_t Np, int64_t N,
                                                           const TP* __restrict__ P, int C, int64_t chunk, int nlt,
                                                           int64_t nwg, float* __restrict__ part) {
@@ -158,8 +158,10 @@ __global__ __launch_bounds__(kPjThreads) void k_rwir_proj(const uint16_t* __rest
   const int lt = (int)(L % nlt);
   const int64_t vb = ck * chunk, ve = min(N, vb + chunk);
   const int nst = (int)((ve - vb + kPjVox - 1) / kPjVox);
+  // VEC (16-byte rows): the full stages run without checks and the chunk's partial last stage, if any, after
+  // them with checks; otherwise every stage checks
+  const int nfull = VEC ? (int)((ve - vb) / kPjVox) : 0;
   const int lrow = lane & 15, kg = lane >> 4;
-  const bool vecp = (N & 7) == 0;
   // rows past C read row C - 1 and are zeroed (no branch on the label)
   const TP* prow[4];
   bool pok[4];
@@ -171,15 +173,16 @@ __global__ __launch_bounds__(kPjThreads) void k_rwir_proj(const uint16_t* __rest
   }
   // a stage's tile: 16-byte pieces (column p / 8, voxels 8 (p % 8) .. +7).  A piece that starts inside the chunk
   // ends inside it (chunk ends are multiples of 64) or, in the last chunk, inside Qs's zero padding past N.
+  // Threads past the tile's pieces load its last piece again and do not store it.
   uint4 qreg[PQ];
-  auto load_stage = [&](int st) {
+  auto load_stage = [&](int st, bool full) {
     const int64_t v0 = vb + (int64_t)st * kPjVox;
 #pragma unroll
     for (int q = 0; q < PQ; ++q) {
-      const int p = tid + kPjThreads * q;
+      const int p = min(tid + kPjThreads * q, PIECES - 1);
       const int64_t v = v0 + 8 * (p & 7);
-      const bool ok = p < PIECES && v < ve;
-      const uint4 x = *reinterpret_cast<const uint4*>(Qs + (ok ? (int64_t)(p >> 3) * Np + v : 0));
+      const bool ok = full || v < ve;
+      const uint4 x = *reinterpret_cast<const uint4*>(Qs + (int64_t)(p >> 3) * Np + (ok ? v : 0));
       qreg[q] = ok ? x : uint4{0u, 0u, 0u, 0u};
     }
   };
@@ -188,29 +191,23 @@ __global__ __launch_bounds__(kPjThreads) void k_rwir_proj(const uint16_t* __rest
 #pragma unroll
     for (int q = 0; q < PQ; ++q) {
       const int p = tid + kPjThreads * q;
-      if (p < PIECES) *reinterpret_cast<uint4*>(dst + (p >> 3) * kPjRow + 8 * (p & 7)) = qreg[q];
+      if (PQ * kPjThreads == PIECES || p < PIECES) *reinterpret_cast<uint4*>(dst + (p >> 3) * kPjRow + 8 * (p & 7)) = qreg[q];
     }
   };
   uint4 pa[4][2], pn[4][2];
-  // a full stage (64 voxels inside the chunk, rows 16-byte aligned) loads without checks; the chunk's last
-  // stage, or rows of any alignment, check every voxel
-  auto load_p = [&](uint4 (&dst)[4][2], int st) {
+  auto load_p = [&](uint4 (&dst)[4][2], int st, bool full) {
     const int64_t v0 = vb + (int64_t)st * kPjVox;
-    if (vecp && v0 + kPjVox <= ve) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
+      for (int ks = 0; ks < 2; ++ks) {
+        if (full) {
           const uint4 x = load_p8<TP>(prow[t], v0 + 32 * ks + 8 * kg, ve, true, true);
           dst[t][ks] = pok[t] ? x : uint4{0u, 0u, 0u, 0u};
+        } else {
+          dst[t][ks] = load_p8<TP>(prow[t], v0 + 32 * ks + 8 * kg, ve, pok[t], VEC);
         }
-    } else {
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
-          dst[t][ks] = load_p8<TP>(prow[t], v0 + 32 * ks + 8 * kg, ve, pok[t], vecp);
-    }
+      }
   };
   f4 acc[4][NH];
 #pragma unroll
@@ -218,7 +215,9 @@ __global__ __launch_bounds__(kPjThreads) void k_rwir_proj(const uint16_t* __rest
 #pragma unroll
     for (int c = 0; c < NH; ++c) acc[t][c] = f4{0.f, 0.f, 0.f, 0.f};
   // one stage: 2 NH column fragments from LDS, each read one step before its 4 products
-  auto compute = [&](const uint4 (&pf)[4][2], int buf) {
+  auto compute = [&](const uint4 (&pf)[4][2], int buf, bool loads_first) {
+    // the next stage's global loads (issued before this call) go ahead of the products
+    if (loads_first) __builtin_amdgcn_sched_group_barrier(0x020, 8 + PQ, 0);
     const uint16_t* src = sQ + buf * KC * kPjRow + (c0 * 16 + lrow) * kPjRow + 8 * kg;
     uint4 bn = *reinterpret_cast<const uint4*>(src);
 #pragma unroll
@@ -239,20 +238,35 @@ __global__ __launch_bounds__(kPjThreads) void k_rwir_proj(const uint16_t* __rest
     }
     __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
   };
-  load_p(pa, 0);
-  load_stage(0);
+  // stage st computes from (pa, buffer st % 2) while stage st + 1's data arrive in (pn, registers)
+  const bool full0 = 0 < nfull;
+  load_p(pa, 0, full0);
+  load_stage(0, full0);
   store_stage(0);
   __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int cur = st & 1;
+  int st = 0;
+  for (; st + 1 < nfull; ++st) {   // the next stage is full too: no checks
+    load_p(pn, st + 1, true);
+    load_stage(st + 1, true);
+    compute(pa, st & 1, true);
+    store_stage((st & 1) ^ 1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      pa[t][0] = pn[t][0];
+      pa[t][1] = pn[t][1];
+    }
+    __syncthreads();
+  }
+  for (; st < nst; ++st) {         // the remaining stages (a partial one, or all without VEC)
     const bool more = st + 1 < nst;
     if (more) {
-      load_p(pn, st + 1);
-      load_stage(st + 1);
+      const bool fn = st + 1 < nfull;
+      load_p(pn, st + 1, fn);
+      load_stage(st + 1, fn);
     }
-    compute(pa, cur);
+    compute(pa, st & 1, false);
     if (more) {
-      store_stage(cur ^ 1);
+      store_stage((st & 1) ^ 1);
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         pa[t][0] = pn[t][0];
@@ -699,13 +713,13 @@ static size_t rwir_layout(const Graph* g, const RwirDims& d, bool labels, void* 
   return c.used + 256;
 }
 
-template <typename TP, int NH>
+template <typename TP, int NH, bool VEC>
 static int launch_proj(const Graph* g, const uint16_t* Q, const RwirDims& d, const void* P, const RwirWork& w,
                        hipStream_t s) {
   static bool attr = false;
   const size_t lds = rwir_proj_lds(32 * NH);
   if (!attr) {
-    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_rwir_proj<TP, NH>),
+    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_rwir_proj<TP, NH, VEC>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr = true;
   }
@@ -713,7 +727,7 @@ static int launch_proj(const Graph* g, const uint16_t* Q, const RwirDims& d, con
   const int64_t grid = (nwg + 7) / 8 * 8;
   k_rwir_scaled_basis<<<nblocks(d.Np / 8 * d.KC, 256), 256, 0, s>>>(Q, d.ma, g->N, d.Np, d.KC, w.sv, w.sg, w.Qs);
   RW_LAUNCH_CHECK();
-  k_rwir_proj<TP, NH><<<(unsigned)grid, kPjThreads, lds, s>>>(w.Qs, d.Np, g->N, static_cast<const TP*>(P), d.C,
+  k_rwir_proj<TP, NH, VEC><<<(unsigned)grid, kPjThreads, lds, s>>>(w.Qs, d.Np, g->N, static_cast<const TP*>(P), d.C,
                                                                d.chunk, (int)d.nlt, nwg, static_cast<float*>(w.part));
   RW_LAUNCH_CHECK();
   return RW_OK;
@@ -723,9 +737,10 @@ template <typename TP>
 static int proj_mfma(const Graph* g, const uint16_t* Q, const RwirDims& d, const void* P, const RwirWork& w,
                      hipStream_t s) {
   // d.KC is the kernel's width (the partial layout's stride)
-  if (d.KC == 64) return launch_proj<TP, 2>(g, Q, d, P, w, s);
-  if (d.KC == 128) return launch_proj<TP, 4>(g, Q, d, P, w, s);
-  return launch_proj<TP, 7>(g, Q, d, P, w, s);
+  const bool vec = (g->N & 7) == 0;
+  if (d.KC == 64) return vec ? launch_proj<TP, 2, true>(g, Q, d, P, w, s) : launch_proj<TP, 2, false>(g, Q, d, P, w, s);
+  if (d.KC == 128) return vec ? launch_proj<TP, 4, true>(g, Q, d, P, w, s) : launch_proj<TP, 4, false>(g, Q, d, P, w, s);
+  return vec ? launch_proj<TP, 7, true>(g, Q, d, P, w, s) : launch_proj<TP, 7, false>(g, Q, d, P, w, s);
 }
 
 template <int KS>
