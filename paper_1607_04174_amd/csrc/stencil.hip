@@ -15,6 +15,8 @@
 // ranges (workgroup w runs on XCD w mod 8), so the rows a tile shares with its neighbours sit in the
 // same L2.  Byte offsets within a column are 32-bit; larger grids take the plain one-node-per-thread
 // kernel (k_stencil_wide).
+#include <hip/hip_ext.h>
+
 #include "rw_internal.h"
 
 namespace rw {
@@ -319,9 +321,22 @@ static StripMap strip_map(const Graph* g, int R, int64_t b, dim3* grid, int WX =
   return tm;
 }
 
+// a kernel launch; with events, through hipExtLaunchKernel so that they record this dispatch's own start
+// and end (the interval a kernel trace reports), not the stream's progress around it
+template <typename... A>
+static hipError_t launch_k(void (*kernel)(A...), dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0,
+                           hipEvent_t e1, A... args) {
+  if (e0 == nullptr && e1 == nullptr) {
+    kernel<<<grid, block, 0, s>>>(args...);
+    return hipGetLastError();
+  }
+  void* argv[] = {static_cast<void*>(&args)...};
+  return hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, argv, 0, s, e0, e1, 0);
+}
+
 template <typename T, int NDIR>
 static int launch(const Graph* g, const void* X, void* Y, const void* Z, int64_t b, double alpha,
-                  double beta, double gamma, hipStream_t s) {
+                  double beta, double gamma, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using C = typename Elem<T>::C;
   StencilArgs<T> a;
   a.G = grid_of(g);
@@ -335,49 +350,50 @@ static int launch(const Graph* g, const void* X, void* Y, const void* Z, int64_t
   a.beta = (C)beta;
   a.gamma = (C)gamma;
   dim3 block(64, 4);
+  hipError_t st = hipSuccess;
   const bool narrow = (uint64_t)g->N * sizeof(T) < ((uint64_t)1 << 31) && b < (int64_t)1 << 30;
   if (narrow) {
     dim3 grid;
     const bool zt = a.Z != nullptr;
     if constexpr (NDIR == 3) {                       // 3D: buffer loads, four nodes per thread along z
       StripMap tm = strip_map<NDIR>(g, 4, b, &grid);
-      if (zt) k_stencil_strip<T, NDIR, 4, true, true><<<grid, block, 0, s>>>(a, tm);
-      else k_stencil_strip<T, NDIR, 4, false, true><<<grid, block, 0, s>>>(a, tm);
+      if (zt) st = launch_k(k_stencil_strip<T, NDIR, 4, true, true>, grid, block, s, e0, e1, a, tm);
+      else st = launch_k(k_stencil_strip<T, NDIR, 4, false, true>, grid, block, s, e0, e1, a, tm);
     } else if (zt && sizeof(T) == 4) {               // 2D fused FP32: buffer loads, four nodes per thread
       StripMap tm = strip_map<NDIR>(g, 4, b, &grid);
-      k_stencil_strip<T, NDIR, 4, true, true><<<grid, block, 0, s>>>(a, tm);
+      st = launch_k(k_stencil_strip<T, NDIR, 4, true, true>, grid, block, s, e0, e1, a, tm);
     } else if (sizeof(T) == 4 && alpha == 1.0 && beta == 0.0) {
       // 2D plain FP32: 128-column tiles of two 8-row strips, buffer loads, four column groups
       StripMap tm = strip_map<NDIR>(g, 8, b, &grid, 2, 4);
-      k_stencil_strip<T, NDIR, 8, false, true, 2, false><<<grid, block, 0, s>>>(a, tm);
+      st = launch_k(k_stencil_strip<T, NDIR, 8, false, true, 2, false>, grid, block, s, e0, e1, a, tm);
     } else {                                         // 2D plain, and FP64: global loads, two nodes per thread
       StripMap tm = strip_map<NDIR>(g, 2, b, &grid);
-      if (zt) k_stencil_strip<T, NDIR, 2, true, false><<<grid, block, 0, s>>>(a, tm);
-      else k_stencil_strip<T, NDIR, 2, false, false><<<grid, block, 0, s>>>(a, tm);
+      if (zt) st = launch_k(k_stencil_strip<T, NDIR, 2, true, false>, grid, block, s, e0, e1, a, tm);
+      else st = launch_k(k_stencil_strip<T, NDIR, 2, false, false>, grid, block, s, e0, e1, a, tm);
     }
   } else {
     RW_CHECK(g->ny * g->nz < (int64_t)4 * 65535, RW_EINVAL, "grid too tall for the stencil launch");
     dim3 grid(nblocks(g->nx, 64), nblocks(g->ny * g->nz, 4));
-    k_stencil_wide<T, NDIR><<<grid, block, 0, s>>>(a);
+    st = launch_k(k_stencil_wide<T, NDIR>, grid, block, s, e0, e1, a);
   }
-  RW_LAUNCH_CHECK();
+  RW_CHECK(st == hipSuccess, RW_EHIP, "stencil launch: %s", hipGetErrorString(st));
   return RW_OK;
 }
 
 int stencil_apply(const Graph* g, const void* X, void* Y, const void* Z, int64_t b, double alpha,
-                  double beta, double gamma, hipStream_t s) {
+                  double beta, double gamma, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (b <= 0) return RW_OK;
   if (g->dtype == RW_F64) {
     switch (g->ndir) {
-      case 2: return launch<double, 2>(g, X, Y, Z, b, alpha, beta, gamma, s);
-      case 3: return launch<double, 3>(g, X, Y, Z, b, alpha, beta, gamma, s);
-      default: return launch<double, 4>(g, X, Y, Z, b, alpha, beta, gamma, s);
+      case 2: return launch<double, 2>(g, X, Y, Z, b, alpha, beta, gamma, s, e0, e1);
+      case 3: return launch<double, 3>(g, X, Y, Z, b, alpha, beta, gamma, s, e0, e1);
+      default: return launch<double, 4>(g, X, Y, Z, b, alpha, beta, gamma, s, e0, e1);
     }
   }
   switch (g->ndir) {
-    case 2: return launch<float, 2>(g, X, Y, Z, b, alpha, beta, gamma, s);
-    case 3: return launch<float, 3>(g, X, Y, Z, b, alpha, beta, gamma, s);
-    default: return launch<float, 4>(g, X, Y, Z, b, alpha, beta, gamma, s);
+    case 2: return launch<float, 2>(g, X, Y, Z, b, alpha, beta, gamma, s, e0, e1);
+    case 3: return launch<float, 3>(g, X, Y, Z, b, alpha, beta, gamma, s, e0, e1);
+    default: return launch<float, 4>(g, X, Y, Z, b, alpha, beta, gamma, s, e0, e1);
   }
 }
 
@@ -403,6 +419,16 @@ int rw_apply_laplacian_axpby(rw_graph h, const void* X, void* Y, const void* Z, 
   RW_CHECK(X != Y || b == 0, RW_EINVAL, "X and Y must be distinct");
   RW_CHECK(gamma == 0.0 || Z != nullptr, RW_EINVAL, "Z required when gamma != 0");
   return stencil_apply(&h->g, X, Y, Z, b, alpha, beta, gamma, stream);
+}
+
+int rw_apply_laplacian_timed(rw_graph h, const void* X, void* Y, int64_t b, hipStream_t stream,
+                             hipEvent_t start, hipEvent_t stop) {
+  RW_CHECK(h != nullptr, RW_EINVAL, "null graph");
+  RW_CHECK(b >= 1, RW_EINVAL, "b must be >= 1");
+  RW_CHECK(X != nullptr && Y != nullptr, RW_EINVAL, "null X or Y");
+  RW_CHECK(X != Y, RW_EINVAL, "X and Y must be distinct");
+  RW_CHECK(start != nullptr && stop != nullptr, RW_EINVAL, "null event");
+  return stencil_apply(&h->g, X, Y, nullptr, b, 1.0, 0.0, 0.0, stream, start, stop);
 }
 
 }  // extern "C"

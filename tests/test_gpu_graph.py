@@ -91,6 +91,15 @@ def test_stencil_matches_oracle(name, w, dt, normalized):
     ref = 0.7 * (M @ Xr.T).T - 0.3 * Xr + 1.9 * Zr
     err = np.linalg.norm(Yd.cpu().numpy() - ref) / np.linalg.norm(ref)
     assert err < (1e-13 if dt == torch.float64 else 2e-6), err
+    # the timed launch: bit-identical to the plain one, with the dispatch's own interval in the events
+    X = to_dev(rng.standard_normal((37, og.N)), dt)
+    Yp = rw.apply_laplacian(gg, X)
+    Yt = torch.empty_like(X)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rw.apply_laplacian_timed(gg, X, Yt, e0, e1)
+    torch.cuda.synchronize()
+    assert torch.equal(Yp, Yt)
+    assert e0.elapsed_time(e1) > 0.0
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
