@@ -248,7 +248,7 @@ def main():
         "precompute_s": round(t_pre, 3),
         "spmv_gbs": round(spmm_gbs, 1),
         "update_vs_recompute": compare,
-        "roofline": {"kernel": "k_stencil_strip<float,4,8,plain,buffer,WX=2> (N x %d block)" % nb, "bound": "hbm",
+        "roofline": {"kernel": "k_stencil_strip<float,4,8,plain,buffer,WX=2,PF=2> (N x %d block)" % nb, "bound": "hbm",
                      "achieved": round(spmm_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(spmm_gbs / PEAK_HBM_GBS, 4), "traffic": stencil_traffic(nb, w.N),
                      "bytes_per_launch": spmm_bytes, "us_per_launch": round(spmm_us, 2),

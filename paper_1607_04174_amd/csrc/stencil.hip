@@ -87,7 +87,10 @@ template <> struct Buf<double> {
 // 8-wide strips of one-wave tiles, R = 4 or 16, or eight groups were slower; taking x +- 1 from neighbouring
 // lanes by DPP wave shifts instead of loads took 143 us).  AB: alpha and beta are folded into the coefficients
 // (off for the plain operator, which then uses them as stored; with the folding the same tiles took 114 us).
-template <typename T, int NDIR, int R, bool ZT, bool BUF, int WX = 1, bool AB = true>
+// PF: columns in flight ahead of the one computed (1 or 2).  For the 2D plain tiles, two took 97-98 us against
+// 100-103 us for one (eight column groups: 105-110 us; R = 4 with eight groups: 100-101 us); back to back
+// 77 us either way, so the remaining distance to the copy is the latency of the first loads from HBM.
+template <typename T, int NDIR, int R, bool ZT, bool BUF, int WX = 1, bool AB = true, int PF = 1>
 __global__ __launch_bounds__(256) void k_stencil_strip(StencilArgs<T> a, StripMap tm) {
   using C = typename Elem<T>::C;
   constexpr bool D3 = NDIR == 3;
@@ -239,17 +242,34 @@ __global__ __launch_bounds__(256) void k_stencil_strip(StencilArgs<T> a, StripMa
   };
   const uint32_t ucs = (uint32_t)cs;
   uint32_t so = 0;
-  Win w0, w1;
-  load(w0, 0u);
   int col = c0;
-  for (; col + 2 <= c1; col += 2) {
-    load(w1, so + ucs);
-    compute(w0, so);
-    if (col + 2 < c1) load(w0, so + 2 * ucs);
-    compute(w1, so + ucs);
-    so += 2 * ucs;
+  if constexpr (PF == 1) {   // one column in flight ahead of the one computed
+    Win w0, w1;
+    load(w0, 0u);
+    for (; col + 2 <= c1; col += 2) {
+      load(w1, so + ucs);
+      compute(w0, so);
+      if (col + 2 < c1) load(w0, so + 2 * ucs);
+      compute(w1, so + ucs);
+      so += 2 * ucs;
+    }
+    if (col < c1) compute(w0, so);
+  } else {                   // two columns in flight: three windows in rotation
+    Win w0, w1, w2;
+    load(w0, 0u);
+    if (col + 1 < c1) load(w1, ucs);
+    for (; col + 3 <= c1; col += 3) {
+      load(w2, so + 2 * ucs);
+      compute(w0, so);
+      if (col + 3 < c1) load(w0, so + 3 * ucs);
+      compute(w1, so + ucs);
+      if (col + 4 < c1) load(w1, so + 4 * ucs);
+      compute(w2, so + 2 * ucs);
+      so += 3 * ucs;
+    }
+    if (col < c1) compute(w0, so);
+    if (col + 1 < c1) compute(w1, so + ucs);
   }
-  if (col < c1) compute(w0, so);
 }
 
 // one node per thread, all columns, 64-bit indexing (grids whose columns exceed 32-bit byte offsets)
@@ -363,9 +383,10 @@ static int launch(const Graph* g, const void* X, void* Y, const void* Z, int64_t
       StripMap tm = strip_map<NDIR>(g, 4, b, &grid);
       st = launch_k(k_stencil_strip<T, NDIR, 4, true, true>, grid, block, s, e0, e1, a, tm);
     } else if (sizeof(T) == 4 && alpha == 1.0 && beta == 0.0) {
-      // 2D plain FP32: 128-column tiles of two 8-row strips, buffer loads, four column groups
+      // 2D plain FP32: 128-column tiles of two 8-row strips, buffer loads, four column groups, two columns
+      // in flight
       StripMap tm = strip_map<NDIR>(g, 8, b, &grid, 2, 4);
-      st = launch_k(k_stencil_strip<T, NDIR, 8, false, true, 2, false>, grid, block, s, e0, e1, a, tm);
+      st = launch_k(k_stencil_strip<T, NDIR, 8, false, true, 2, false, 2>, grid, block, s, e0, e1, a, tm);
     } else {                                         // 2D plain, and FP64: global loads, two nodes per thread
       StripMap tm = strip_map<NDIR>(g, 2, b, &grid);
       if (zt) st = launch_k(k_stencil_strip<T, NDIR, 2, true, false>, grid, block, s, e0, e1, a, tm);
