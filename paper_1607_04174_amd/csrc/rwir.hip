@@ -469,25 +469,31 @@ __global__ __launch_bounds__(256) void k_rwir_transpose(const uint16_t* __restri
   }
 }
 
-// Workgroup: 4 waves x 8 sub-tiles of 16 voxels.  A wave keeps its 128 voxels' basis fragments (KS K steps
-// of 32) in registers and runs over the labels in tiles of 16, two at a time: D[label 4 kg + v][voxel lrow] =
-// s_i U(label, i); the label fragments of tile t + 2 load while tile t + 1's products run, and tile t's
-// comparisons follow tile t + 1's products (no register copies between tiles).  The larger value is kept per
-// lane (labels in increasing order, strict comparison), then the four lanes of a voxel merged (larger value,
-// or equal value and smaller label).  Rows of Yt past C carry -1e30 against the s column and never win.  label[i] and
-// prob[i] = s_i^{-1} D; a voxel with d_i = 0 gets label 0 and probability 0.
-constexpr int kLbSub = 8;
+// Workgroup: 8 waves (two per SIMD, so that one wave's comparisons run beside the other's products) x 4
+// sub-tiles of 16 voxels.  A wave keeps its 64 voxels' basis fragments (KS K steps of 32) in registers; the
+// label rows go through LDS two tiles of 16 at a time (double-buffered, rows padded by 8 elements for
+// conflict-free 16-byte reads, one barrier per pair), and every wave runs over all labels:
+// D[label 4 kg + v][voxel lrow] = s_i U(label, i).  The larger value is kept per lane (labels in increasing
+// order, strict comparison), then the four lanes of a voxel merged (larger value, or equal value and smaller
+// label).  Rows of Yt past C carry -1e30 against the s column and never win.  label[i] and prob[i] =
+// s_i^{-1} D; a voxel with d_i = 0 gets label 0 and probability 0.
+constexpr int kLbSub = 4;
+constexpr int kLbWaves = 8;
+constexpr int kLbVox = kLbWaves * 16 * kLbSub;   // voxels per workgroup
 
 template <int KS, typename TU>
-__global__ __launch_bounds__(256) void k_rwir_label_mfma(const uint16_t* __restrict__ Qt, int64_t N,
-                                                         const uint16_t* __restrict__ Yt, int Cpad,
-                                                         const float* __restrict__ inv, int32_t* __restrict__ label,
-                                                         TU* __restrict__ prob) {
+__global__ __launch_bounds__(64 * kLbWaves) void k_rwir_label_mfma(const uint16_t* __restrict__ Qt, int64_t N,
+                                                                   const uint16_t* __restrict__ Yt, int Cpad,
+                                                                   const float* __restrict__ inv,
+                                                                   int32_t* __restrict__ label,
+                                                                   TU* __restrict__ prob) {
   constexpr int KR = 32 * KS;
+  constexpr int ROW = KR + 8;                      // LDS row of a label (BF16 elements)
+  constexpr int PIECES = 32 * KR / 8;              // 16-byte pieces of two label tiles
+  __shared__ __align__(16) uint16_t sY[2][32 * ROW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lrow = lane & 15, kg = lane >> 4;
-  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * (16 * kLbSub);
-  if (base >= N) return;
+  const int64_t base = (int64_t)blockIdx.x * kLbVox + wave * (16 * kLbSub);
   uint4 b[kLbSub][KS];
 #pragma unroll
   for (int u = 0; u < kLbSub; ++u) {
@@ -503,48 +509,57 @@ __global__ __launch_bounds__(256) void k_rwir_label_mfma(const uint16_t* __restr
     best[u] = -INFINITY;
     bidx[u] = 0;
   }
-  const int ntile = Cpad >> 4;   // even
-  auto load_a = [&](uint4 (&a)[KS], int tl) {
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
-      a[s] = *reinterpret_cast<const uint4*>(Yt + ((int64_t)tl * 16 + lrow) * KR + 32 * s + 8 * kg);
+  const int npair = Cpad >> 5;
+  // a pair's rows: piece p = row p / (KR / 8), 8 elements at 8 (p % (KR / 8)), thread t takes pieces t and
+  // t + 512 (at most 1024 pieces); threads past the pieces repeat the last one and do not store it
+  static_assert(PIECES <= 2 * 64 * kLbWaves, "two staged pieces per thread");
+  uint4 st0, st1;
+  auto piece = [&](int pr, int p) {
+    const int q = min(p, PIECES - 1);
+    return *reinterpret_cast<const uint4*>(Yt + ((int64_t)pr * 32 + q / (KR / 8)) * KR + 8 * (q % (KR / 8)));
   };
-  auto mma = [&](f4 (&c)[kLbSub], const uint4 (&a)[KS]) {
-#pragma unroll
-    for (int u = 0; u < kLbSub; ++u) c[u] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
-#pragma unroll
-      for (int u = 0; u < kLbSub; ++u) c[u] = mfma_bf16(a[s], b[u][s], c[u]);
+  auto load_pair = [&](int pr) {
+    st0 = piece(pr, tid);
+    st1 = piece(pr, tid + 64 * kLbWaves);
   };
-  auto pick = [&](const f4 (&c)[kLbSub], int l0) {
-#pragma unroll
-    for (int u = 0; u < kLbSub; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float x = c[u][v];
-        const bool gt = x > best[u];
-        best[u] = gt ? x : best[u];
-        bidx[u] = gt ? l0 + v : bidx[u];
-      }
+  auto store_pair = [&](int buf) {
+    const int p0 = tid, p1 = tid + 64 * kLbWaves;
+    if (p0 < PIECES) *reinterpret_cast<uint4*>(&sY[buf][(p0 / (KR / 8)) * ROW + 8 * (p0 % (KR / 8))]) = st0;
+    if (p1 < PIECES) *reinterpret_cast<uint4*>(&sY[buf][(p1 / (KR / 8)) * ROW + 8 * (p1 % (KR / 8))]) = st1;
   };
-  uint4 a0[KS], a1[KS];
-  f4 c0[kLbSub], c1[kLbSub];
-  load_a(a0, 0);
-  load_a(a1, 1);
-  mma(c0, a0);
-  int tl = 0;
-  for (; tl + 2 < ntile; tl += 2) {   // ntile is even: tl + 3 < ntile here
-    load_a(a0, tl + 2);
-    mma(c1, a1);
-    pick(c0, tl * 16 + 4 * kg);
-    load_a(a1, tl + 3);
-    mma(c0, a0);
-    pick(c1, (tl + 1) * 16 + 4 * kg);
+  load_pair(0);
+  store_pair(0);
+  __syncthreads();
+  for (int pr = 0; pr < npair; ++pr) {
+    const int buf = pr & 1;
+    if (pr + 1 < npair) load_pair(pr + 1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint4 a[KS];
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        a[s] = *reinterpret_cast<const uint4*>(&sY[buf][(16 * h + lrow) * ROW + 32 * s + 8 * kg]);
+      f4 c[kLbSub];
+#pragma unroll
+      for (int u = 0; u < kLbSub; ++u) c[u] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int u = 0; u < kLbSub; ++u) c[u] = mfma_bf16(a[s], b[u][s], c[u]);
+      const int l0 = pr * 32 + 16 * h + 4 * kg;
+#pragma unroll
+      for (int u = 0; u < kLbSub; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float x = c[u][v];
+          const bool gt = x > best[u];
+          best[u] = gt ? x : best[u];
+          bidx[u] = gt ? l0 + v : bidx[u];
+        }
+    }
+    if (pr + 1 < npair) store_pair(buf ^ 1);
+    __syncthreads();
   }
-  mma(c1, a1);
-  pick(c0, tl * 16 + 4 * kg);
-  pick(c1, (tl + 1) * 16 + 4 * kg);
 #pragma unroll
   for (int u = 0; u < kLbSub; ++u) {
 #pragma unroll
@@ -746,13 +761,13 @@ static int proj_mfma(const Graph* g, const uint16_t* Q, const RwirDims& d, const
 template <int KS>
 static int label_mfma_t(const Graph* g, const RwirDims& d, const RwirWork& w, int32_t* label, void* prob,
                         hipStream_t s) {
-  const unsigned nb = (unsigned)((g->N + 4 * 16 * kLbSub - 1) / (4 * 16 * kLbSub));
+  const unsigned nb = (unsigned)((g->N + kLbVox - 1) / kLbVox);
   if (g->dtype == RW_F64)
-    k_rwir_label_mfma<KS, double><<<nb, 256, 0, s>>>(w.Qt, g->N, w.Yt, d.Cpad, w.inv, label,
-                                                     static_cast<double*>(prob));
+    k_rwir_label_mfma<KS, double><<<nb, 64 * kLbWaves, 0, s>>>(w.Qt, g->N, w.Yt, d.Cpad, w.inv, label,
+                                                               static_cast<double*>(prob));
   else
-    k_rwir_label_mfma<KS, float><<<nb, 256, 0, s>>>(w.Qt, g->N, w.Yt, d.Cpad, w.inv, label,
-                                                    static_cast<float*>(prob));
+    k_rwir_label_mfma<KS, float><<<nb, 64 * kLbWaves, 0, s>>>(w.Qt, g->N, w.Yt, d.Cpad, w.inv, label,
+                                                              static_cast<float*>(prob));
   RW_LAUNCH_CHECK();
   return RW_OK;
 }
