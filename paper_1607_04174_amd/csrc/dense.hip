@@ -1200,6 +1200,208 @@ __global__ __launch_bounds__(1024) void k_lu_reg(const double* Ag, int n, double
   lu_reg_body<R>(Ag, n, Bg, nrhs, stat);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Register-column LU for 192 < n <= 208, beyond the register tile: column c belongs to wave c % 16, which keeps
+// rows 0..127 of it in registers (lane l: rows l and l + 64); rows 128.. of every column live in LDS (lane l:
+// rows 128 + l and 192 + l).  The elimination is that of lu_lds_body (no row exchanges; pivot: largest magnitude
+// over the rows not yet chosen, ties to the lowest row; the same products).  In step k the owner of column k+1
+// updates that column first, copies its register rows to an LDS vector (two, alternating by step) and finds
+// its pivot, while the other waves update the columns they own with the multipliers of column k from the
+// previous vector and the pivot row's entries read across lanes; one barrier per step.  Back substitution by
+// the owner of each column in turn, over the pivot order.
+// ---------------------------------------------------------------------------------------------
+constexpr int kLuColRegRows = 128;   // rows held in registers (two per lane)
+constexpr int kLuColMaxN = 208;      // 13 columns per wave (more spill at 1024 threads)
+constexpr int kLuColMinN = 193;      // below, the register tile serves
+
+__host__ __device__ inline size_t lu_col_bytes(int n, int nrhs) {
+  const size_t ldl = (size_t)((n - kLuColRegRows) | 1);
+  return (ldl * n + (size_t)(n | 1) * nrhs + 2 * kLuColRegRows + 18) * sizeof(double) +
+         (3 * (size_t)n + 1) * sizeof(int);
+}
+__host__ __device__ inline bool lu_col_fits(int n, int nrhs) {
+  return n >= kLuColMinN && n <= kLuColMaxN && lu_col_bytes(n, nrhs) <= kLdsLimit;
+}
+
+template <int NC>
+__device__ void lu_col_body(const double* Ag, int n, double* Bg, int nrhs, double* stat) {
+  constexpr int RR = kLuColRegRows;
+  extern __shared__ double sm[];
+  const int nl = n - RR, ldl = nl | 1, ldb = n | 1;
+  double* AL = sm;                              // ldl x n: rows RR.. of every column
+  double* B = AL + (size_t)ldl * n;             // ldb x nrhs
+  double* nx = B + (size_t)ldb * nrhs;          // 2 x RR: register rows of the step's pivot column
+  double* sc = nx + 2 * RR;                     // [0] max |A|, [1] smallest pivot, [2..17] wave maxima
+  int* prow = reinterpret_cast<int*>(sc + 18);  // n: pivot row of step k
+  int* done = prow + n;                         // n: row already a pivot row
+  int* pos = done + n;                          // n: position of a row in the pivot order
+  int* bad = pos + n;                           // 1
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double a[NC][2];   // a[j][q] = A(lane + 64 q, wave + 16 j)
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int c = wave + 16 * j;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) a[j][q] = c < n ? Ag[(lane + 64 * q) + (int64_t)c * n] : 0.0;
+  }
+  double m = 0.0;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) m = fmax(m, fmax(fabs(a[j][0]), fabs(a[j][1])));
+  for (int t = tid; t < nl * n; t += blockDim.x) {
+    const double x = Ag[RR + (t % nl) + (int64_t)(t / nl) * n];
+    AL[(t % nl) + (t / nl) * ldl] = x;
+    m = fmax(m, fabs(x));
+  }
+  for (int t = tid; t < n * nrhs; t += blockDim.x) B[(t % n) + (t / n) * ldb] = Bg[t];
+  for (int t = tid; t < n; t += blockDim.x) done[t] = 0;
+  m = wave_max64(m);
+  if (lane == 0) sc[2 + wave] = m;
+  __syncthreads();
+  if (tid == 0) {
+    double mm = 0.0;
+    for (int w = 0; w < 16; ++w) mm = fmax(mm, sc[2 + w]);
+    sc[0] = mm;
+    sc[1] = INFINITY;
+    *bad = 0;
+  }
+  __syncthreads();
+  const double amax = sc[0];
+  // this lane's LDS rows: RR + lane + 64 s, s < 2, present when below n
+  const bool lr0 = lane < nl, lr1 = lane + 64 < nl;
+  // pivot of column c (held in col by the calling wave, after its update): its register rows to nx[c & 1], then
+  // the largest magnitude over the rows not yet chosen (a lane's rows in increasing order: first maximum kept;
+  // ties across lanes to the lowest row)
+  auto pivot = [&](int c, const double (&col)[2]) __attribute__((always_inline)) {
+    double best = -1.0;
+    int brow = n;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int i = lane + 64 * q;
+      nx[(c & 1) * RR + i] = col[q];
+      if (!done[i]) {
+        const double v = fabs(col[q]);
+        if (v > best) { best = v; brow = i; }
+      }
+    }
+    if (lr0 && !done[RR + lane]) {
+      const double v = fabs(AL[lane + c * ldl]);
+      if (v > best) { best = v; brow = RR + lane; }
+    }
+    if (lr1 && !done[RR + 64 + lane]) {
+      const double v = fabs(AL[lane + 64 + c * ldl]);
+      if (v > best) { best = v; brow = RR + 64 + lane; }
+    }
+    const double mx = wave_max64(best);
+    const unsigned long long tie = __ballot(best == mx);
+    int row;
+    if (__popcll(tie) == 1) {
+      row = __shfl(brow, __ffsll((long long)tie) - 1);
+    } else {
+      int r = best == mx ? brow : n;
+      for (int o = 32; o > 0; o >>= 1) r = min(r, __shfl_xor(r, o));
+      row = r;
+    }
+    if (lane == 0) {
+      const bool ok = row < n && mx > 1e-14 * amax;
+      prow[c] = ok ? row : 0;
+      if (!ok) *bad = 1;
+      sc[1] = fmin(sc[1], mx);
+    }
+  };
+  if (wave == 0) pivot(0, a[0]);
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (*bad) break;   // uniform
+    const int p = prow[k];
+    const double* ck = nx + (k & 1) * RR;
+    const double inv = 1.0 / (p < RR ? ck[p] : AL[(p - RR) + k * ldl]);
+    // multipliers of this lane's rows: registers (lane, lane + 64), LDS (RR + lane, RR + 64 + lane)
+    const bool act0 = lane != p && !done[lane], act1 = lane + 64 != p && !done[lane + 64];
+    const bool act2 = lr0 && RR + lane != p && !done[RR + lane];
+    const bool act3 = lr1 && RR + 64 + lane != p && !done[RR + 64 + lane];
+    const double l0 = act0 ? ck[lane] * inv : 0.0, l1 = act1 ? ck[lane + 64] * inv : 0.0;
+    const double l2 = act2 ? AL[lane + k * ldl] * inv : 0.0, l3 = act3 ? AL[lane + 64 + k * ldl] * inv : 0.0;
+    const bool pr = p < RR;
+    const int pl = p & 63;
+    auto update = [&](double (&col)[2], int c) __attribute__((always_inline)) {
+      const double xp = pr ? __shfl(p < 64 ? col[0] : col[1], pl) : AL[(p - RR) + c * ldl];
+      if (act0) col[0] -= l0 * xp;
+      if (act1) col[1] -= l1 * xp;
+      if (act2) AL[lane + c * ldl] -= l2 * xp;
+      if (act3) AL[lane + 64 + c * ldl] -= l3 * xp;
+    };
+    const int k1 = k + 1;
+    if (k1 < n && wave == (k1 & 15)) {   // the next pivot column first, then its pivot
+      if (lane == 0) done[p] = 1;
+#pragma unroll
+      for (int j = 0; j < NC; ++j)
+        if (j == (k1 >> 4)) {
+          update(a[j], k1);
+          pivot(k1, a[j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int c = wave + 16 * j;
+      if (c > k1 && c < n) update(a[j], c);
+    }
+    for (int r = wave; r < nrhs; r += 16) {
+      double* col = B + r * ldb;
+      const double xp = col[p];
+      if (act0) col[lane] -= l0 * xp;
+      if (act1) col[lane + 64] -= l1 * xp;
+      if (act2) col[RR + lane] -= l2 * xp;
+      if (act3) col[RR + 64 + lane] -= l3 * xp;
+    }
+    __syncthreads();
+  }
+  if (*bad) {
+    if (tid == 0) stat[0] = 0.0;
+    return;
+  }
+  for (int t = tid; t < n; t += blockDim.x) pos[prow[t]] = t;
+  __syncthreads();
+  // back substitution over the pivot order: x_k = b(p_k) / A(p_k, k); b(p_i) -= A(p_i, k) x_k for i < k, by the
+  // owner of column k
+  for (int k = n - 1; k >= 0; --k) {
+    if (wave == (k & 15)) {
+      const int p = prow[k], pl = p & 63;
+      const bool up0 = pos[lane] < k, up1 = pos[lane + 64] < k;
+      const bool up2 = lr0 && pos[RR + lane] < k, up3 = lr1 && pos[RR + 64 + lane] < k;
+      const double a2 = up2 ? AL[lane + k * ldl] : 0.0, a3 = up3 ? AL[lane + 64 + k * ldl] : 0.0;
+#pragma unroll
+      for (int j = 0; j < NC; ++j)
+        if (j == (k >> 4)) {
+          const double u = p < RR ? __shfl(p < 64 ? a[j][0] : a[j][1], pl) : AL[(p - RR) + k * ldl];
+          const double ru = 1.0 / u;
+          for (int r = 0; r < nrhs; ++r) {
+            double* col = B + r * ldb;
+            const double xk = col[p] * ru;
+            if (up0) col[lane] -= a[j][0] * xk;
+            if (up1) col[lane + 64] -= a[j][1] * xk;
+            if (up2) col[RR + lane] -= a2 * xk;
+            if (up3) col[RR + 64 + lane] -= a3 * xk;
+            if (lane == 0) col[p] = xk;
+          }
+        }
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < n * nrhs; t += blockDim.x) {
+    const int k = t % n, r = t / n;
+    Bg[k + (int64_t)r * n] = B[prow[k] + r * ldb];
+  }
+  if (tid == 0) stat[0] = sc[1] / amax;
+}
+
+__device__ void lu_col_dispatch(const double* Ag, int n, double* Bg, int nrhs, double* stat) {
+  lu_col_body<(kLuColMaxN + 15) / 16>(Ag, n, Bg, nrhs, stat);
+}
+
+__global__ __launch_bounds__(1024) void k_lu_col(const double* Ag, int n, double* Bg, int nrhs, double* stat) {
+  lu_col_dispatch(Ag, n, Bg, nrhs, stat);
+}
+
 __host__ __device__ inline size_t lu_lds_bytes(int n, int nrhs) {
   const size_t ld = (size_t)(n | 1);
   return (ld * (n + nrhs)) * sizeof(double) + 2 * (size_t)n * sizeof(int);
@@ -1221,6 +1423,7 @@ __global__ __launch_bounds__(1024) void k_lu_solve_batched(const LuJob* jobs, in
   if (j.n <= 0) return;
   if (lu_lds_fits(j.n, j.nrhs)) lu_lds_body(j.A, j.n, j.B, j.nrhs, j.stat);
   else if (lu_reg_fits(j.n, j.nrhs)) lu_reg_dispatch(j.A, j.n, j.B, j.nrhs, j.stat);
+  else if (lu_col_fits(j.n, j.nrhs)) lu_col_dispatch(j.A, j.n, j.B, j.nrhs, j.stat);
   else lu_body(j.A, j.n, j.B, j.nrhs, j.stat);
 }
 
@@ -1236,6 +1439,8 @@ static int lu_attrs() {
                           reinterpret_cast<const void*>(k_lu_reg<5>), reinterpret_cast<const void*>(k_lu_reg<6>)};
     for (const void* f : regs)
       RW_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_lu_col), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kLdsLimit));
     attr = true;
   }
   return RW_OK;
@@ -1269,6 +1474,9 @@ int lu_solve(double* A, int n, double* B, int nrhs, double* stat, hipStream_t s)
   } else if (lu_lds_fits(n, nrhs)) {
     RW_TRY(lu_attrs());
     k_lu_solve_lds<<<1, 1024, lu_lds_bytes(n, nrhs), s>>>(A, n, B, nrhs, stat);
+  } else if (lu_col_fits(n, nrhs)) {
+    RW_TRY(lu_attrs());
+    k_lu_col<<<1, 1024, lu_col_bytes(n, nrhs), s>>>(A, n, B, nrhs, stat);
   } else {
     k_lu_solve<<<1, 1024, 0, s>>>(A, n, B, nrhs, stat);
   }

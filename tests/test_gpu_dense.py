@@ -130,8 +130,8 @@ def test_eig_rhs_batched_matches_numpy():
         rw.dense_eig_rhs_batched(to_dev(C, torch.float64), [40], to_dev(R[:1], torch.float64))
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (2, 1), (50, 3), (64, 9), (129, 2), (150, 3), (192, 4), (201, 4),
-                                    (75, 260)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (2, 1), (50, 3), (64, 9), (129, 2), (150, 3), (192, 4), (193, 1),
+                                    (201, 4), (200, 20), (208, 8), (209, 2), (75, 260)])
 def test_lu_solve_matches_numpy(n, nrhs):
     need_gpu()
     rng = np.random.default_rng(n)
