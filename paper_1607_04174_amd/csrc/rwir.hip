@@ -104,7 +104,10 @@ __global__ void k_rwir_scaled_basis(const uint16_t* __restrict__ Q, int ma, int6
 // so that two waves share each SIMD.  The stage's Qs tile is copied to LDS ([column][voxel], padded row,
 // double-buffered); the priors' fragments come from HBM straight into registers, one stage ahead (the two
 // column halves read the same fragments; the second read hits the cache).  Output: FP32 partials per chunk,
-// part[(chunk C + label) KC + column].
+// part[(chunk C + label) KC + column].  Measured at 96^3 x 3969 labels: 2.8 ms, 2.5 TB/s of priors.  Each label
+// row contributes 128 contiguous bytes per stage, so HBM serves many short scattered pieces; four waves with
+// all 224 columns each and two stages of priors in flight (three register sets) took 3.75 ms with the same
+// partials, so the depth of prefetch is not what limits it.
 constexpr int kPjVox = 64;
 constexpr int kPjRow = kPjVox + 8;   // staged row in BF16 elements: conflict-free 16-byte fragment reads
 constexpr int kPjLab = 256;
