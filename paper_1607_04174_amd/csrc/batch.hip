@@ -170,14 +170,16 @@ __global__ void k_b_gather(const BatchImg* D, const int64_t* node, const int32_t
 }
 
 // T = Q_s^T GB and R = Q_s^T Hs per image (FP64, summed over the image's S seeds in order), then
-// K = diag(lambda) - T and the right-hand side Y = R.  One thread per output entry.
-__global__ void k_b_reduced(const BatchImg* D, LuJob* jobs) {
+// K = diag(lambda) - T and the right-hand side Y = R.  32 x 32 tiles of the output per workgroup (the single
+// solve's code): workgroup x runs over the tiles of image y.
+__global__ __launch_bounds__(256) void k_b_reduced(const BatchImg* D, LuJob* jobs) {
+  __shared__ double sA[kRedTile * 33], sB[kRedTile * 33];
   const BatchImg& d = D[blockIdx.y];
   const int m = d.m, C = d.C;
   const int64_t S = d.S, ld = d.S_cap;
-  const int64_t total = (int64_t)m * (m + C);
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x)
-    reduced_entry(t, m, C, S, ld, d.Qs, d.GB, d.Hs, d.lambda, 0.0, d.K, d.Y);
+  const int tr = (m + kRedTile - 1) / kRedTile, tc = (m + C + kRedTile - 1) / kRedTile;
+  for (int t = blockIdx.x; t < tr * tc; t += gridDim.x)
+    reduced_tile(t % tr, t / tr, m, C, S, ld, d.Qs, d.GB, d.Hs, d.lambda, 0.0, d.K, d.Y, sA, sB);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     LuJob jb;
     jb.A = d.K; jb.B = d.Y; jb.stat = d.stat; jb.n = m; jb.nrhs = C;
@@ -551,9 +553,9 @@ int rw_batch_enqueue(rw_batch h, hipStream_t stream) {
   else RW_BGATHER(uint16_t);
 #undef RW_BGATHER
   RW_LAUNCH_CHECK();
-  const int64_t per_img = (int64_t)b->max_m * (b->max_m + kBatchMaxC);
-  k_b_reduced<<<dim3((unsigned)std::min<int64_t>(nblocks(per_img, 256), 256), b->n), 256, 0, stream>>>(b->d_desc,
-                                                                                                      b->d_jobs);
+  const int64_t per_img = (int64_t)((b->max_m + kRedTile - 1) / kRedTile) *
+                          ((b->max_m + kBatchMaxC + kRedTile - 1) / kRedTile);   // tiles of the largest image
+  k_b_reduced<<<dim3((unsigned)per_img, b->n), 256, 0, stream>>>(b->d_desc, b->d_jobs);
   RW_LAUNCH_CHECK();
   RW_TRY(lu_solve_batched(b->d_jobs, b->n, stream));
   k_b_coeffs<<<b->n, 256, 0, stream>>>(b->d_desc);

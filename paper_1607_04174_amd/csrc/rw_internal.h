@@ -390,20 +390,51 @@ __device__ __forceinline__ void solve_coeffs_block(double* Y, int m, int C, cons
 // launch of solve_coeffs_block for one system (solve.hip)
 int solve_coeffs(double* Y, int m, int C, const double* cn, const Graph* g, hipStream_t s);
 
-// Entry t of the reduced system from the seed rows (leading dimension ld, S seeds): for t < m m,
-// K(i, j) = (lambda_i + gamma) [i == j] - sum_s Qs(s, i) GB(s, j); for t < m C, Y(i, c) = sum_s Qs(s, i)
-// Hs(s, c); the seed sums run in order (the single and the batched solves form the system with this same code)
-__device__ __forceinline__ void reduced_entry(int64_t t, int m, int C, int64_t S, int64_t ld, const double* Qs,
-                                              const double* GB, const double* Hs, const double* lambda,
-                                              double gamma, double* K, double* Y) {
-  if (t >= (int64_t)m * (m + C)) return;
-  const int i = (int)(t % m), j = (int)(t / m);
-  const double* a = Qs + (int64_t)i * ld;
-  const double* b = j < m ? GB + (int64_t)j * ld : Hs + (int64_t)(j - m) * ld;
-  double acc = 0.0;
-  for (int64_t q = 0; q < S; ++q) acc += a[q] * b[q];
-  if (j < m) K[i + (int64_t)j * m] = (i == j ? lambda[i] + gamma : 0.0) - acc;
-  else Y[i + (int64_t)(j - m) * m] = acc;
+
+// The reduced system from the seed rows (leading dimension ld, S seeds): K(i, j) = (lambda_i + gamma) [i == j]
+// - sum_s Qs(s, i) GB(s, j) for j < m, Y(i, c) = sum_s Qs(s, i) Hs(s, c) for c < C; each entry sums its S
+// products in seed order (the single and the batched solves form the system with this same code).  A 32 x 32
+// tile of the m x (m + C) output per 256-thread workgroup (tile (bx, by): rows 32 bx.., columns 32 by..;
+// thread (ty, tx) the entries (32 bx + ty + 16 a, 32 by + tx + 16 b)), the seed rows staged in LDS 32 at a time.
+// sA, sB: 32 x 33 doubles each in LDS.
+constexpr int kRedTile = 32;
+__device__ __forceinline__ void reduced_tile(int bx, int by, int m, int C, int64_t S, int64_t ld, const double* Qs,
+                                             const double* GB, const double* Hs, const double* lambda,
+                                             double gamma, double* K, double* Y, double* sA, double* sB) {
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int i0 = kRedTile * bx, j0 = kRedTile * by;
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  for (int64_t s0 = 0; s0 < S; s0 += kRedTile) {
+    // columns of the tile: 32 seeds each, consecutive threads on consecutive seeds
+    for (int e = tid; e < kRedTile * kRedTile; e += 256) {
+      const int q = e & 31, c = e >> 5;
+      const int64_t s = s0 + q;
+      const int i = i0 + c, j = j0 + c;
+      sA[q * 33 + c] = (s < S && i < m) ? Qs[s + (int64_t)i * ld] : 0.0;
+      const double* bc = j < m ? GB + (int64_t)j * ld : Hs + (int64_t)(j - m) * ld;
+      sB[q * 33 + c] = (s < S && j < m + C) ? bc[s] : 0.0;
+    }
+    __syncthreads();
+    const int nq = (int)(S - s0 < kRedTile ? S - s0 : kRedTile);
+    for (int q = 0; q < nq; ++q) {
+      const double a0 = sA[q * 33 + ty], a1 = sA[q * 33 + ty + 16];
+      const double b0 = sB[q * 33 + tx], b1 = sB[q * 33 + tx + 16];
+      acc[0][0] += a0 * b0;
+      acc[0][1] += a0 * b1;
+      acc[1][0] += a1 * b0;
+      acc[1][1] += a1 * b1;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int i = i0 + ty + 16 * a, j = j0 + tx + 16 * b;
+      if (i >= m || j >= m + C) continue;
+      if (j < m) K[i + (int64_t)j * m] = (i == j ? lambda[i] + gamma : 0.0) - acc[a][b];
+      else Y[i + (int64_t)(j - m) * m] = acc[a][b];
+    }
 }
 
 // Seed row k (node i, leading dimension ld) of the reduced system's inputs, formed by one workgroup from

@@ -283,9 +283,15 @@ int solve_coeffs(double* Y, int m, int C, const double* cn, const Graph* g, hipS
   return RW_OK;
 }
 
-__global__ void k_reduced(int m, int C, int64_t S, const double* Qs, const double* GB, const double* Hs,
-                          const double* lambda, double gamma, double* K, double* Y) {
-  reduced_entry(blockIdx.x * (int64_t)blockDim.x + threadIdx.x, m, C, S, S, Qs, GB, Hs, lambda, gamma, K, Y);
+__global__ __launch_bounds__(256) void k_reduced(int m, int C, int64_t S, const double* Qs, const double* GB,
+                                                 const double* Hs, const double* lambda, double gamma, double* K,
+                                                 double* Y) {
+  __shared__ double sA[kRedTile * 33], sB[kRedTile * 33];
+  reduced_tile(blockIdx.x, blockIdx.y, m, C, S, S, Qs, GB, Hs, lambda, gamma, K, Y, sA, sB);
+}
+
+static dim3 reduced_grid(int m, int C) {
+  return dim3((unsigned)((m + kRedTile - 1) / kRedTile), (unsigned)((m + C + kRedTile - 1) / kRedTile));
 }
 
 
@@ -1017,7 +1023,7 @@ static int solve_impl(rw_graph h, const void* Q, int q_dtype, const double* lamb
   RW_LAUNCH_CHECK();
   // reduced system K = Lambda - Q'_s^T (B Q'_n), Y = Q'_s^T (op_ss U_hat_s), and its solve (the batched solve
   // forms and solves each image's system with the same code)
-  k_reduced<<<nblocks((int64_t)m * (m + C), 256), 256, 0, stream>>>(m, C, S, w.Qs, w.GB, w.Hs, lambda, 0.0, w.K,
+  k_reduced<<<reduced_grid(m, C), 256, 0, stream>>>(m, C, S, w.Qs, w.GB, w.Hs, lambda, 0.0, w.K,
                                                                      w.Y);
   RW_LAUNCH_CHECK();
   RW_TRY(lu_solve(w.K, m, w.Y, C, w.stat, stream));
@@ -1319,7 +1325,7 @@ static int prior_solve_impl(rw_graph h, const void* Q, int q_dtype, const double
   RW_LAUNCH_CHECK();
   k_prior_rhs<<<nblocks(S * C, 256), 256, 0, stream>>>(m, C, S, w.GB, w.Us, lambda, gamma, pw.Zp, w.Hs);
   RW_LAUNCH_CHECK();
-  k_reduced<<<nblocks((int64_t)m * (m + C), 256), 256, 0, stream>>>(m, C, S, w.Qs, w.GB, w.Hs, lambda, gamma, w.K,
+  k_reduced<<<reduced_grid(m, C), 256, 0, stream>>>(m, C, S, w.Qs, w.GB, w.Hs, lambda, gamma, w.K,
                                                                      w.Y);
   RW_LAUNCH_CHECK();
   RW_TRY(lu_solve(w.K, m, w.Y, C, w.stat, stream));
@@ -1415,7 +1421,7 @@ int rw_solve_seeds_async(rw_graph h, const void* Q, int q_dtype, const double* l
   RW_TRY(null_stats(g, Q, q_dtype, m, w.npart, w.cn, flags, stream));
   k_seed_correct<<<nblocks(S * m, 256), 256, 0, stream>>>(w.Qs, w.GB, w.gs, w.Bg, w.cn, S, m);
   RW_LAUNCH_CHECK();
-  k_reduced<<<nblocks((int64_t)m * (m + C), 256), 256, 0, stream>>>(m, C, S, w.Qs, w.GB, w.Hs, lambda, 0.0, w.K,
+  k_reduced<<<reduced_grid(m, C), 256, 0, stream>>>(m, C, S, w.Qs, w.GB, w.Hs, lambda, 0.0, w.K,
                                                                      w.Y);
   RW_LAUNCH_CHECK();
   RW_TRY(lu_solve(w.K, m, w.Y, C, w.stat, stream));
