@@ -19,6 +19,7 @@
 // All arithmetic is FP64.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "rw_internal.h"
 
@@ -275,6 +276,218 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
     tau[n - 2] = 0.0;
     tau[n - 1] = 0.0;
   }
+}
+
+// 1'. The same reduction with the matrix in registers, for orders up to kTriRegMax: 512 threads, thread
+// (lane, wave) holds A(i, j) for the rows i = lane + 64 s (s < RS) and the columns j = wave + 8 t (t < CS),
+// both triangles, so that no step reads or writes the matrix in LDS.  Per column k:
+//   * the wave that holds column k (wave k mod 8) forms reflector k from its registers, one step ahead:
+//     during the update of step k-1, right after updating that column, while the other waves update theirs;
+//     v (zero at i <= k and i >= n, 1 at k+1) goes to LDS (two buffers, by the parity of k);
+//   * barrier; each thread sums A(i, j) v_j over its columns for each of its rows (v_j from a copy of v held
+//     one entry per lane, read out by lane reads); the row partials of the eight waves go to LDS;
+//   * barrier; 256 threads add a row's eight partials in a fixed order: p = tau A22 v (zero at i <= k);
+//   * barrier; every wave forms K = tau/2 p^T v and w = p - K v, and each thread applies
+//     A -= v w^T + w v^T to its elements.  Elements in finished rows or columns see v = w = 0 there and keep
+//     their values; columns wholly at or left of k and row blocks wholly at or above k are skipped.
+// Outputs as k_tridiag: reflector k in refl[k n ..], tau, d and e.
+constexpr int kTriRegMax = 200;
+constexpr int kTriRegThreads = 512;
+static size_t tridiag_reg_lds_bytes() { return (size_t)(2 * 256 + 256 + 8 * 256) * sizeof(double); }
+
+// f(integral_constant<int, I>) for I = B .. E-1, in order
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+template <int RS, int CS>
+__global__ __launch_bounds__(kTriRegThreads) void k_tridiag_reg(const double* A, int lda, int64_t strideA,
+                                                                TriSizes sz, int nmax, double* refl, double* tau,
+                                                                double* d, double* e, double* flag) {
+  static_assert(RS >= 1 && RS <= 4 && 8 * CS <= 64 * RS, "layout");
+  const int b = blockIdx.x, n = sz.n[b];
+  if (b == 0 && threadIdx.x == 0) flag[0] = 0.0;   // the flag of the cluster pass that follows
+  A += b * strideA;
+  refl += (int64_t)b * nmax * nmax;
+  tau += (int64_t)b * nmax;
+  d += (int64_t)b * nmax;
+  e += (int64_t)b * nmax;
+  extern __shared__ double sT[];
+  __shared__ double s_tau[2];
+  // the wave index as a uniform value, so that the slot tests below are scalar branches
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double a[RS][CS];
+  // 0.5 (A + A^T), straight from memory (A(i, j) with consecutive rows across lanes; A(j, i) one row per lane,
+  // from L2: the matrix was just written)
+#pragma unroll
+  for (int s = 0; s < RS; ++s)
+#pragma unroll
+    for (int t = 0; t < CS; ++t) {
+      const int i = lane + 64 * s, j = wave + 8 * t;
+      a[s][t] = (i < n && j < n) ? 0.5 * (A[i + (int64_t)j * lda] + A[j + (int64_t)i * lda]) : 0.0;
+    }
+  double* sv = sT;             // v of the step, two buffers of 256
+  double* sp = sT + 512;       // p (256)
+  double* sPr = sT + 768;      // row partials, 8 x 256
+  // reflector k from x = column k (rows lane + 64 s), by the wave holding it: v to sv[k & 1], tau to s_tau[k & 1]
+  auto reflector = [&](int k, const double (&x)[RS]) {
+    double ss = 0.0, xk = x[0], xk1 = x[0];
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int i = lane + 64 * s;
+      if (i >= k + 2 && i < n) ss += x[s] * x[s];
+      if (s == (k >> 6)) xk = x[s];
+      if (s == ((k + 1) >> 6)) xk1 = x[s];
+    }
+    ss = wave_sum64(ss);
+    const double dk = lane_read(xk, k & 63), x0 = lane_read(xk1, (k + 1) & 63);
+    double beta, tkv, scale;
+    if (ss == 0.0) {   // already reduced: no reflection
+      tkv = 0.0;
+      beta = x0;
+      scale = 0.0;
+    } else {
+      const double nrm = sqrt(x0 * x0 + ss);
+      beta = x0 >= 0.0 ? -nrm : nrm;
+      tkv = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    double* vb = sv + 256 * (k & 1);
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int i = lane + 64 * s;
+      const double vi = i == k + 1 ? 1.0 : (i > k + 1 && i < n ? x[s] * scale : 0.0);
+      vb[i] = vi;
+      if (i > k && i < n) refl[(int64_t)k * n + (i - k - 1)] = vi;
+    }
+    if (lane == 0) {
+      s_tau[k & 1] = tkv;
+      tau[k] = tkv;
+      e[k] = beta;
+      d[k] = dk;
+    }
+  };
+  // step k = 8 T + w (w = k mod 8, a runtime value; T, the first row slot below k (SLO) and the slot of column
+  // k+1 (T1 = T, or T + 1 when w = 7) fixed at compile time, so that no register is chosen at run time).  The
+  // products run over all column slots from T on, with no tests: v and p are zero at the columns j <= k and
+  // j >= n and at the rows i <= k, so those elements take exact zero updates (also when tau = 0, which makes
+  // p and w zero)
+  auto step = [&](int k, int w, auto Tc, auto SLOc, auto T1c) {
+    constexpr int T = decltype(Tc)::value, SLO = decltype(SLOc)::value, T1 = decltype(T1c)::value;
+    const double* vb = sv + 256 * (k & 1);
+    const double tk = s_tau[k & 1];
+    // p partials: r_s = sum over this thread's columns of A(i, j) v_j
+    const double vcol = lane < CS ? vb[wave + 8 * lane] : 0.0;
+    double r[RS];
+#pragma unroll
+    for (int s = SLO; s < RS; ++s) r[s] = 0.0;
+    static_for<T, CS>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
+      const double vj = lane_read(vcol, t);
+#pragma unroll
+      for (int s = SLO; s < RS; ++s) r[s] = fma(a[s][t], vj, r[s]);
+    });
+#pragma unroll
+    for (int s = SLO; s < RS; ++s) sPr[wave * 256 + lane + 64 * s] = r[s];
+    lds_barrier();
+    if (tid < 64 * RS) {
+      const int i = tid;
+      double p = 0.0;
+      if (i > k && i < n) {
+        const double* q = sPr + i;
+        p = tk * (((q[0] + q[256]) + (q[512] + q[768])) + ((q[1024] + q[1280]) + (q[1536] + q[1792])));
+      }
+      sp[i] = p;
+    }
+    lds_barrier();
+    // -v and -w at this thread's rows (held negated, so that the update is two plain FMAs)
+    double nv[RS], nw[RS], dot = 0.0;
+#pragma unroll
+    for (int s = SLO; s < RS; ++s) {
+      nv[s] = -vb[lane + 64 * s];
+      nw[s] = -sp[lane + 64 * s];
+      dot = fma(nw[s], nv[s], dot);
+    }
+    const double K = 0.5 * tk * wave_sum64(dot);
+#pragma unroll
+    for (int s = SLO; s < RS; ++s) nw[s] = fma(-K, nv[s], nw[s]);
+    const double wcol = lane < CS ? fma(-K, vcol, sp[wave + 8 * lane]) : 0.0;
+    // A -= v w^T + w v^T on this thread's elements, as two rounded FMAs per element
+    auto updated = [&](int s, double aij, double vj, double wj) { return fma(nw[s], vj, fma(nv[s], wj, aij)); };
+    static_for<T, CS>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
+      const double vj = lane_read(vcol, t), wj = lane_read(wcol, t);
+#pragma unroll
+      for (int s = SLO; s < RS; ++s) a[s][t] = updated(s, a[s][t], vj, wj);
+    });
+    if constexpr (T1 < CS) {
+      if (k + 1 < n - 2 && wave == ((w + 1) & 7)) {   // reflector k+1 from the updated column k+1
+        double x[RS];
+#pragma unroll
+        for (int s = 0; s < RS; ++s) x[s] = a[s][T1];
+        reflector(k + 1, x);
+      }
+    }
+    if (k == n - 3) {   // the last 2 x 2 block: columns n-2 and n-1, in slot T or T+1
+      static_for<T, (T + 2 < CS ? T + 2 : CS)>([&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+#pragma unroll
+        for (int s = SLO; s < RS; ++s) {
+          const int i = lane + 64 * s, j = wave + 8 * t;
+          if (i == j && i >= n - 2 && i < n) d[i] = a[s][t];
+          if (i == n - 1 && j == n - 2) e[n - 2] = a[s][t];
+        }
+      });
+    }
+  };
+  if (wave == 0) {
+    double x[RS];
+#pragma unroll
+    for (int s = 0; s < RS; ++s) x[s] = a[s][0];
+    reflector(0, x);
+  }
+  // steps 8T .. 8T+6 in a loop, step 8T+7 (whose column k+1 sits in slot T+1) after it
+  static_for<0, CS>([&](auto Tc) {
+    constexpr int T = decltype(Tc)::value;
+    using TT = std::integral_constant<int, T>;
+    for (int w = 0; w < 7; ++w) {
+      const int k = 8 * T + w;
+      if (k >= n - 2) break;   // uniform
+      lds_barrier();           // v_k and tau_k
+      step(k, w, TT{}, std::integral_constant<int, T / 8>{}, TT{});
+    }
+    const int k = 8 * T + 7;
+    if (k < n - 2) {
+      lds_barrier();
+      step(k, 7, TT{}, std::integral_constant<int, (8 * T + 8) / 64>{}, std::integral_constant<int, T + 1>{});
+    }
+  });
+  if (tid == 0) {
+    e[n - 1] = 0.0;
+    tau[n - 2] = 0.0;
+    tau[n - 1] = 0.0;
+  }
+}
+
+// launch k_tridiag_reg for matrices of order up to nmax (at most kTriRegMax)
+static void launch_tridiag_reg(const double* A, int lda, int64_t strideA, const TriSizes& sz, int nmax, int count,
+                               double* refl, double* tau, double* d, double* e, double* flag, hipStream_t s) {
+  const size_t lds = tridiag_reg_lds_bytes();
+#define RW_TRI_REG(RS, CS)                                                                                     \
+  k_tridiag_reg<RS, CS><<<count, kTriRegThreads, lds, s>>>(A, lda, strideA, sz, nmax, refl, tau, d, e, flag)
+  if (nmax <= 64)
+    RW_TRI_REG(1, 8);
+  else if (nmax <= 128)
+    RW_TRI_REG(2, 16);
+  else if (nmax <= 192)
+    RW_TRI_REG(3, 24);
+  else
+    RW_TRI_REG(4, 25);
+#undef RW_TRI_REG
 }
 
 // Sturm count: the number of eigenvalues of T below sigma (the negative pivots of LDL^T of T - sigma I,
@@ -785,6 +998,12 @@ static void tri_attrs() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_tri_cluster),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+    const void* reg[] = {reinterpret_cast<const void*>(k_tridiag_reg<1, 8>),
+                         reinterpret_cast<const void*>(k_tridiag_reg<2, 16>),
+                         reinterpret_cast<const void*>(k_tridiag_reg<3, 24>),
+                         reinterpret_cast<const void*>(k_tridiag_reg<4, 25>)};
+    for (const void* f : reg)
+      (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tridiag_reg_lds_bytes());
     attr = true;
   }
 }
@@ -825,8 +1044,7 @@ int syev_tridiag_rhs(const double* A, int ld, const int* sizes, int count, doubl
   double* flag = h + (size_t)count * nmax * C;
   tri_attrs();
   const int64_t strideR = (int64_t)ld * C;
-  k_tridiag<<<count, 1024, tridiag_lds_bytes(nmax), s>>>(A, ld, (int64_t)ld * ld, sz, nmax, refl, tau, d, e, flag,
-                                                         nullptr, 0);
+  launch_tridiag_reg(A, ld, (int64_t)ld * ld, sz, nmax, count, refl, tau, d, e, flag, s);
   k_tri_rhs<<<dim3(C, count), 64, 0, s>>>(refl, tau, sz, nmax, R, ld, strideR, C, h);
   k_tri_bisect<<<dim3(nmax, count), kBisThreads, 0, s>>>(d, e, sz, nmax, lam, flag);
   launch_invit(d, e, sz, nmax, count, lam, Z, s);
@@ -849,9 +1067,14 @@ int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hip
   tri_attrs();
   TriSizes sz;
   sz.n[0] = n;
-  // orders above kTriLdsMax: the first n - kTriLdsMax columns on a full copy in b.Lf (n x n, unused otherwise)
-  const int nl = std::min(n, kTriLdsMax);
-  k_tridiag<<<1, 1024, tridiag_lds_bytes(nl), s>>>(A, n, 0, sz, n, b.refl, b.tau, b.d, b.e, b.flag, b.Lf, n - nl);
+  // orders up to kTriRegMax: the matrix in registers; above: the first n - kTriLdsMax columns on a full copy in
+  // b.Lf (n x n, unused otherwise), the rest packed in LDS
+  if (n <= kTriRegMax) {
+    launch_tridiag_reg(A, n, 0, sz, n, 1, b.refl, b.tau, b.d, b.e, b.flag, s);
+  } else {
+    const int nl = std::min(n, kTriLdsMax);
+    k_tridiag<<<1, 1024, tridiag_lds_bytes(nl), s>>>(A, n, 0, sz, n, b.refl, b.tau, b.d, b.e, b.flag, b.Lf, n - nl);
+  }
   k_tri_bisect<<<n, kBisThreads, 0, s>>>(b.d, b.e, sz, n, b.lam, b.flag);
   launch_invit(b.d, b.e, sz, n, 1, b.lam, b.Z, s);
   k_tri_cluster<<<1, 64, cluster_lds_bytes(n), s>>>(b.d, b.e, sz, n, b.lam, b.Z, b.flag);
