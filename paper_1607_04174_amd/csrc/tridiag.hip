@@ -284,8 +284,9 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
 //   * the wave that holds column k (wave k mod 8) forms reflector k from its registers, one step ahead:
 //     during the update of step k-1, right after updating that column, while the other waves update theirs;
 //     v (zero at i <= k and i >= n, 1 at k+1) goes to LDS (two buffers, by the parity of k);
-//   * barrier; each thread sums A(i, j) v_j over its columns for each of its rows (v_j from a copy of v held
-//     one entry per lane, read out by lane reads); the row partials of the eight waves go to LDS;
+//   * barrier; each thread sums A(i, j) v_j over its columns for each of its rows (v_j by a row broadcast
+//     from a copy of v that holds the wave's columns in the 16 lanes of each row); the row partials of the
+//     eight waves go to LDS;
 //   * barrier; 256 threads add a row's eight partials in a fixed order: p = tau A22 v (zero at i <= k);
 //   * barrier; every wave forms K = tau/2 p^T v and w = p - K v, and each thread applies
 //     A -= v w^T + w v^T to its elements.  Elements in finished rows or columns see v = w = 0 there and keep
@@ -294,6 +295,12 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
 constexpr int kTriRegMax = 200;
 constexpr int kTriRegThreads = 512;
 static size_t tridiag_reg_lds_bytes() { return (size_t)(2 * 256 + 256 + 8 * 256) * sizeof(double); }
+
+// lane U of each row of 16 lanes, in every lane of that row (64-bit DPP row broadcast)
+template <int U>
+__device__ __forceinline__ double row_bcast(double x) {
+  return __builtin_amdgcn_update_dpp(0.0, x, 0x150 + U, 0xF, 0xF, true);
+}
 
 // f(integral_constant<int, I>) for I = B .. E-1, in order
 template <int B, int E, class F>
@@ -380,16 +387,27 @@ __global__ __launch_bounds__(kTriRegThreads) void k_tridiag_reg(const double* A,
     constexpr int T = decltype(Tc)::value, SLO = decltype(SLOc)::value, T1 = decltype(T1c)::value;
     const double* vb = sv + 256 * (k & 1);
     const double tk = s_tau[k & 1];
+    // v at this wave's columns, slot t in lane t mod 16 of every row of 16 lanes (of vc0 for t < 16, of vc1
+    // above), handed to all lanes by row broadcasts
+    const int c16 = wave + 8 * (lane & 15);
+    const double vc0 = vb[c16], vc1 = vb[c16 + 128];
+    auto colv = [&](auto tc, double x0, double x1) {
+      constexpr int t = decltype(tc)::value;
+      if constexpr (t < 16)
+        return row_bcast<t>(x0);
+      else
+        return row_bcast<(t >= 16 ? t - 16 : 0)>(x1);
+    };
     // p partials: r_s = sum over this thread's columns of A(i, j) v_j
-    const double vcol = lane < CS ? vb[wave + 8 * lane] : 0.0;
     double r[RS];
 #pragma unroll
     for (int s = SLO; s < RS; ++s) r[s] = 0.0;
     static_for<T, CS>([&](auto tc) {
       constexpr int t = decltype(tc)::value;
-      const double vj = lane_read(vcol, t);
+      const double vj = colv(tc, vc0, vc1);
 #pragma unroll
       for (int s = SLO; s < RS; ++s) r[s] = fma(a[s][t], vj, r[s]);
+      __builtin_amdgcn_sched_barrier(0);   // each broadcast next to its use (not all hoisted into registers)
     });
 #pragma unroll
     for (int s = SLO; s < RS; ++s) sPr[wave * 256 + lane + 64 * s] = r[s];
@@ -415,14 +433,17 @@ __global__ __launch_bounds__(kTriRegThreads) void k_tridiag_reg(const double* A,
     const double K = 0.5 * tk * wave_sum64(dot);
 #pragma unroll
     for (int s = SLO; s < RS; ++s) nw[s] = fma(-K, nv[s], nw[s]);
-    const double wcol = lane < CS ? fma(-K, vcol, sp[wave + 8 * lane]) : 0.0;
+    const double wc0 = fma(-K, vc0, sp[c16]), wc1 = fma(-K, vc1, sp[c16 + 128]);
     // A -= v w^T + w v^T on this thread's elements, as two rounded FMAs per element
     auto updated = [&](int s, double aij, double vj, double wj) { return fma(nw[s], vj, fma(nv[s], wj, aij)); };
     static_for<T, CS>([&](auto tc) {
       constexpr int t = decltype(tc)::value;
-      const double vj = lane_read(vcol, t), wj = lane_read(wcol, t);
+      const double vj = colv(tc, vc0, vc1), wj = colv(tc, wc0, wc1);
 #pragma unroll
-      for (int s = SLO; s < RS; ++s) a[s][t] = updated(s, a[s][t], vj, wj);
+      for (int s = SLO; s < RS; ++s) {
+        a[s][t] = updated(s, a[s][t], vj, wj);
+        asm volatile("" : "+v"(a[s][t]));   // updated here, not sunk to later uses with the broadcasts held live
+      }
     });
     if constexpr (T1 < CS) {
       if (k + 1 < n - 2 && wave == ((w + 1) & 7)) {   // reflector k+1 from the updated column k+1
