@@ -76,6 +76,58 @@ def test_syev_tridiag_matches_numpy(n):
             rw.dense_syev_tridiag(to_dev(0.5 * (A + A.T).T, torch.float64))
 
 
+@pytest.mark.parametrize("n", [40, 150, 199])
+def test_syev_tridiag_already_reduced(n):
+    """Inputs whose columns are already reduced, so that the reflectors are the identity (tau = 0) and the
+    reduction must leave the matrix unchanged: a tridiagonal matrix, a diagonal one, and a block-diagonal
+    one (two tridiagonal blocks), against numpy."""
+    need_gpu()
+    banner(f"syev tridiag already reduced n={n}")
+    rng = np.random.default_rng(300 + n)
+    d = rng.standard_normal(n)
+    e = rng.uniform(0.5, 1.5, n - 1) * rng.choice([-1.0, 1.0], n - 1)
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    D = np.diag(np.linspace(-1.0, 1.0, n))
+    B = T.copy()
+    B[n // 2, n // 2 - 1] = B[n // 2 - 1, n // 2] = 0.0
+    for A in (T, D, B):
+        ev = np.linalg.eigvalsh(A)
+        w, V = rw.dense_syev_tridiag(to_dev(A.T, torch.float64))
+        w, V = w.cpu().numpy(), V.cpu().numpy().T
+        scale = np.abs(ev).max()
+        np.testing.assert_allclose(w, ev, atol=1e-13 * scale * max(1, n / 20))
+        assert np.abs(A @ V - V * w).max() < 1e-12 * scale * max(1, n / 20)
+        assert np.abs(V.T @ V - np.eye(n)).max() < 1e-11 * max(1, n / 50)
+
+
+@pytest.mark.parametrize("sizes", [[64, 7, 50], [150, 129, 192, 100]], ids=["to64", "to192"])
+def test_eig_rhs_batched_other_orders(sizes):
+    """The batched eigenproblem at the other register layouts (orders up to 64, and 129 to 192): ascending
+    eigenvalues against numpy and the sign-free products of the rotated right-hand sides."""
+    need_gpu()
+    banner(f"eig rhs batched sizes={sizes}")
+    rng = np.random.default_rng(sum(sizes))
+    ld, nrhs = max(sizes), 2
+    A = rng.standard_normal((len(sizes), ld, ld))
+    R = rng.standard_normal((len(sizes), nrhs, ld))
+    for b, n in enumerate(sizes):
+        X = rng.standard_normal((n + 40, n))
+        A[b, :n, :n] = (X.T @ X).T
+    w, Rp = rw.dense_eig_rhs_batched(to_dev(A, torch.float64), sizes, to_dev(R, torch.float64))
+    w, Rp = w.cpu().numpy(), Rp.cpu().numpy()
+    for b, n in enumerate(sizes):
+        ev, V = np.linalg.eigh(A[b, :n, :n].T)
+        scale = np.abs(ev).max()
+        np.testing.assert_allclose(w[b, :n], ev, atol=1e-12 * scale)
+        ref = V.T @ R[b, :, :n].T
+        got = Rp[b, :, :n].T
+        gap = np.min(np.diff(ev))
+        tol = 1e-12 * scale / gap * np.abs(R[b, :, :n]).max() ** 2 * n
+        for c in range(nrhs):
+            for dd in range(nrhs):
+                np.testing.assert_allclose(got[:, c] * got[:, dd], ref[:, c] * ref[:, dd], atol=tol)
+
+
 def test_eig_rhs_batched_matches_numpy():
     """The choice-of-m eigenproblem through the tridiagonal form: a batch of Gram matrices of different
     orders inside one leading dimension (entries beyond each order hold garbage that must not be read),
