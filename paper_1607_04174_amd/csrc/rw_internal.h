@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/rw.h"
@@ -73,6 +74,21 @@ __device__ __forceinline__ double wave_max64(double x) {
 __device__ __forceinline__ double wave_min64(double x) {
   x = row16_min(x);
   return fmin(fmin(lane_read(x, 0), lane_read(x, 16)), fmin(lane_read(x, 32), lane_read(x, 48)));
+}
+
+// lane U of each row of 16 lanes, in every lane of that row (64-bit DPP row broadcast)
+template <int U>
+__device__ __forceinline__ double row_bcast(double x) {
+  return __builtin_amdgcn_update_dpp(0.0, x, 0x150 + U, 0xF, 0xF, true);
+}
+
+// f(integral_constant<int, I>) for I = B .. E-1, in order
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
 }
 
 __device__ __forceinline__ void lds_barrier() {

@@ -296,21 +296,6 @@ constexpr int kTriRegMax = 200;
 constexpr int kTriRegThreads = 512;
 static size_t tridiag_reg_lds_bytes() { return (size_t)(2 * 256 + 256 + 8 * 256) * sizeof(double); }
 
-// lane U of each row of 16 lanes, in every lane of that row (64-bit DPP row broadcast)
-template <int U>
-__device__ __forceinline__ double row_bcast(double x) {
-  return __builtin_amdgcn_update_dpp(0.0, x, 0x150 + U, 0xF, 0xF, true);
-}
-
-// f(integral_constant<int, I>) for I = B .. E-1, in order
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
-  }
-}
-
 template <int RS, int CS>
 __global__ __launch_bounds__(kTriRegThreads) void k_tridiag_reg(const double* A, int lda, int64_t strideA,
                                                                 TriSizes sz, int nmax, double* refl, double* tau,

@@ -182,8 +182,9 @@ def test_eig_rhs_batched_matches_numpy():
         rw.dense_eig_rhs_batched(to_dev(C, torch.float64), [40], to_dev(R[:1], torch.float64))
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (2, 1), (50, 3), (64, 9), (129, 2), (150, 3), (192, 4), (193, 1),
-                                    (201, 4), (200, 20), (208, 8), (209, 2), (75, 260)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (2, 1), (3, 2), (50, 3), (63, 1), (64, 9), (65, 3), (80, 3), (90, 4), (100, 12), (112, 2),
+                                    (128, 5), (129, 2), (150, 3), (192, 4), (193, 1), (201, 4), (200, 20), (208, 8),
+                                    (209, 2), (75, 260)])
 def test_lu_solve_matches_numpy(n, nrhs):
     need_gpu()
     rng = np.random.default_rng(n)
