@@ -72,85 +72,163 @@ int chol_upper_inverse(const double* L, double* Rinv, int n, hipStream_t s) {
   return RW_OK;
 }
 
-// Cholesky factor and its transposed inverse in one workgroup, in LDS (n <= 200): W = (L^T)^{-1}
-// (upper triangular, zero below) for A = L L^T.  The factorization is right-looking with unscaled
-// columns (Schur complements A(i,j) -= A(i,k) A(j,k) / A(k,k)), one barrier per column; then one wave
-// per column of W solves L^T x = e_j by back substitution in axpy form, the solved entry broadcast from
-// its lane.  info = k + 1 at the first pivot that is not positive and finite (W untouched), else 0.
+// Cholesky factor and its transposed inverse in one workgroup (n <= 200): W = (L^T)^{-1} (upper triangular,
+// zero below) for A = L L^T, A given by its lower triangle.  info = k + 1 at the first pivot that is not
+// positive and finite (W untouched), else 0.
+constexpr int kCholInvMaxN = 200;   // the packed factor plus n reciprocal roots within the LDS budget
+
+// The factorization is right-looking with unscaled columns (Schur complements A(i,j) -= A(i,k) A(j,k) /
+// A(k,k)), with the matrix in registers: 512 threads, thread (lane, wave) holds A(i, j) for the rows
+// i = lane + 64 s (s < RS) and the columns j = wave + 8 t (t < CS), both triangles filled from the lower
+// one.  Step k: the wave holding column k has put the column below the diagonal, u_i = A(i, k), in the
+// packed factor in LDS (column k, with 1 / A(k,k) in its diagonal place); after one barrier every thread
+// applies A(i, j) -= u_i m_j with m_j = u_j / A(k,k) (only the lower triangle is read later; the upper one
+// is updated alongside), m_j handed to all lanes by row broadcasts, and the wave holding column k+1 checks
+// its pivot and writes its column at once.  Steps k = 8 T + w with T unrolled at compile time (the column
+// slots of a step and the row slots below k are then known without tests); entries at or left of column k
+// and at or above row k take exact zero updates.
+// Then W: with D = diag(L) and the unit lower factor M = L D^{-1} (M(i, k) = m_i of step k), L^{-1} =
+// D^{-1} M^{-1}; Y = M^{-1} by forward substitution on all columns at once in the same registers (each wave
+// its own columns: no barriers), and W(j, i) = Y(i, j) / L(i, i).
 __device__ __forceinline__ int cw_lo(int i, int j, int n) { return j * n - ((j * (j - 1)) >> 1) + (i - j); }  // i >= j
 
-__device__ __forceinline__ double cw_readlane(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
-}
+constexpr int kCholRegThreads = 512;
+static size_t chol_reg_lds_bytes(int n) { return ((size_t)n * (n + 1) / 2 + n) * sizeof(double); }
 
-constexpr int kCholInvMaxN = 200;   // packed factor plus n pivots within the LDS budget; 4 entries per lane
-
-__global__ __launch_bounds__(1024) void k_chol_inv_lds(const double* G, int n, double* W, int* info) {
-  extern __shared__ double sA[];   // packed lower factor (column-major), then 1 / L(k, k)
-  double* rd = sA + n * (n + 1) / 2;
-  __shared__ int s_bad;
-  const int tid = threadIdx.x;
-  for (int t = tid; t < n * n; t += blockDim.x) {
-    const int i = t % n, j = t / n;
-    if (i >= j) sA[cw_lo(i, j, n)] = G[t];
-  }
-  if (tid == 0) s_bad = 0;
-  __syncthreads();
-  const int tx = tid & 31, ty = tid >> 5;
-  for (int k = 0; k < n; ++k) {
-    const double dkk = sA[cw_lo(k, k, n)];
-    if (!(dkk > 0.0) || !isfinite(dkk)) {   // uniform
-      if (tid == 0) s_bad = k + 1;
-      break;
+template <int RS, int CS>
+__global__ __launch_bounds__(kCholRegThreads) void k_chol_inv_reg(const double* G, int n, double* W, int* info) {
+  static_assert(RS >= 1 && RS <= 4 && 8 * CS <= 64 * RS, "layout");
+  extern __shared__ double sP[];   // packed lower (column-major): u below the diagonal, 1 / A(k,k) on it
+  double* rd = sP + n * (n + 1) / 2;   // 1 / sqrt(A(k, k)) = 1 / L(k, k)
+  __shared__ int s_bad[2], s_n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (tid == 0) s_n = n;
+  double a[RS][CS];
+#pragma unroll
+  for (int s = 0; s < RS; ++s)
+#pragma unroll
+    for (int t = 0; t < CS; ++t) {
+      const int i = lane + 64 * s, j = wave + 8 * t;
+      const int hi = max(i, j), lo = min(i, j);   // the lower triangle's entry, one load with no branch
+      a[s][t] = (i < n && j < n) ? G[hi + (int64_t)lo * n] : 0.0;
     }
-    if (tid == 0) rd[k] = 1.0 / sqrt(dkk);
-    const double inv = 1.0 / dkk;
-    for (int j = k + 1 + ty; j < n; j += 32) {
-      const double ajk = sA[cw_lo(j, k, n)] * inv;
-      for (int i = j + tx; i < n; i += 32) sA[cw_lo(i, j, n)] -= sA[cw_lo(i, k, n)] * ajk;
+  // entry (i, k) of the packed factor for rows below k (clamped to a valid place; the caller zeroes the rest)
+  auto below = [&](int i, int k) { return sP[cw_lo(min(max(i, k + 1), n - 1), k, n)]; };   // k <= n - 1
+  // column k from slot TK (its diagonal in row slot k >> 6), by the wave holding it
+  auto column = [&](int k, auto tkc) {
+    constexpr int TK = decltype(tkc)::value;
+    double xk = a[0][TK];
+#pragma unroll
+    for (int s = 1; s < RS; ++s) xk = s == (k >> 6) ? a[s][TK] : xk;
+    const double dkk = lane_read(xk, k & 63);
+    const bool bad = !(dkk > 0.0) || !isfinite(dkk);
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int i = lane + 64 * s;
+      if (i > k && i < n) sP[cw_lo(i, k, n)] = a[s][TK];
     }
-    lds_barrier();
-  }
+    if (lane == 0) {
+      sP[cw_lo(k, k, n)] = 1.0 / dkk;
+      s_bad[k & 1] = bad ? k + 1 : 0;
+      rd[k] = bad ? 0.0 : 1.0 / sqrt(dkk);
+    }
+  };
+  auto step = [&](int k, int w, auto Tc) {
+    constexpr int T = decltype(Tc)::value, SLO = T / 8;   // rows in slots below SLO are at or above k
+    const double inv = sP[cw_lo(k, k, n)];
+    double u[RS];
+#pragma unroll
+    for (int s = SLO; s < RS; ++s) {
+      const int i = lane + 64 * s;
+      const double v = below(i, k);
+      u[s] = (i > k && i < n) ? v : 0.0;
+    }
+    const int c16 = wave + 8 * (lane & 15);
+    const double v0 = below(c16, k), v1 = below(c16 + 128, k);
+    const double mc0 = (c16 > k && c16 < n) ? v0 * inv : 0.0;
+    const double mc1 = (c16 + 128 > k && c16 + 128 < n) ? v1 * inv : 0.0;
+    static_for<T, CS>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
+      double mj;
+      if constexpr (t < 16)
+        mj = row_bcast<t>(mc0);
+      else
+        mj = row_bcast<(t >= 16 ? t - 16 : 0)>(mc1);
+#pragma unroll
+      for (int s = SLO; s < RS; ++s) {
+        a[s][t] -= u[s] * mj;
+        asm volatile("" : "+v"(a[s][t]));   // updated here, not sunk to later uses
+      }
+    });
+    // column k+1 sits in slot T, or T + 1 after the last step of the group (a branch that only reads the tile)
+    if (k + 1 < n && wave == ((w + 1) & 7)) {
+      if (w < 7)
+        column(k + 1, std::integral_constant<int, T>{});
+      else if constexpr (T + 1 < CS)
+        column(k + 1, std::integral_constant<int, T + 1>{});
+    }
+  };
+  if (wave == 0) column(0, std::integral_constant<int, 0>{});
+  // a pivot that is not positive and finite is recorded (the first one) and the steps run on to the end with
+  // meaningless values, with no early exit (every index stays within the matrix either way): merging the
+  // register tile at many exits would cost registers
+  int bad = 0;
+  static_for<0, CS>([&](auto Tc) {
+    constexpr int T = decltype(Tc)::value;
+    using TT = std::integral_constant<int, T>;
+    for (int w = 0; w < 8; ++w) {   // one loop of the eight steps (a second copy of the step would hold a
+      const int k = 8 * T + w;       // second register tile at the join)
+      if (k >= n) return;   // uniform
+      lds_barrier();        // column k in LDS, its pivot checked
+      if (bad == 0) bad = s_bad[k & 1];
+      step(k, w, TT{});
+    }
+  });
   __syncthreads();
-  if (s_bad) {
-    if (tid == 0) info[0] = s_bad;
+  if (bad) {
+    if (tid == 0) info[0] = bad;
     return;
   }
-  for (int t = tid; t < n * n; t += blockDim.x) {   // scale the columns: L(i, j) = A(i, j) / sqrt(A(j, j))
-    const int i = t % n, j = t / n;
-    if (i > j) sA[cw_lo(i, j, n)] *= rd[j];
-  }
-  __syncthreads();
-  const int wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
-  for (int g0 = 0; g0 < n; g0 += nw) {
-    const int grp = g0 / nw;
-    const int j = (grp & 1) ? g0 + nw - 1 - wave : g0 + wave;   // zigzag: long and short columns pair up
-    if (j >= n) continue;
-    double bv[4], xv[4];
+  // Y = M^{-1}: start from I; step k subtracts M(i, k) Y(k, :) from the rows below k, where row k (final by
+  // then) is read from the lane holding it and only the columns j <= k (slots up to T) are nonzero
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      bv[r] = (lane + 64 * r == j) ? 1.0 : 0.0;
-      xv[r] = 0.0;
-    }
-    for (int k = j; k >= 0; --k) {
-      const int rk = k >> 6;
-      const double bk = rk == 0 ? bv[0] : (rk == 1 ? bv[1] : (rk == 2 ? bv[2] : bv[3]));
-      const double xk = cw_readlane(bk, k & 63) * rd[k];
+  for (int s = 0; s < RS; ++s)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = lane + 64 * r;
-        if (i == k) xv[r] = xk;
-        if (i < k) bv[r] -= sA[cw_lo(k, i, n)] * xk;
+    for (int t = 0; t < CS; ++t) a[s][t] = (lane + 64 * s == wave + 8 * t) ? 1.0 : 0.0;
+  static_for<0, CS>([&](auto Tc) {
+    constexpr int T = decltype(Tc)::value, SK = T / 8, SLO = T / 8;
+    for (int w = 0; w < 8; ++w) {
+      const int k = 8 * T + w;
+      if (k >= n - 1) return;   // uniform
+      const double inv = sP[cw_lo(k, k, n)];
+      double l[RS];
+#pragma unroll
+      for (int s = SLO; s < RS; ++s) {
+        const int i = lane + 64 * s;
+        const double v = below(i, k);
+        l[s] = (i > k && i < n) ? v * inv : 0.0;
       }
-    }
+      static_for<0, T + 1>([&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        const double yk = lane_read(a[SK][t], k & 63);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = lane + 64 * r;
-      if (i < n) W[i + (int64_t)j * n] = i <= j ? xv[r] : 0.0;
+        for (int s = SLO; s < RS; ++s) {
+          a[s][t] -= l[s] * yk;
+          asm volatile("" : "+v"(a[s][t]));
+        }
+      });
     }
-  }
+  });
+  // W(j, i) = Y(i, j) / L(i, i) on and above the diagonal, zero below (the order read back from LDS here, so
+  // that these addresses are formed now and not held through the steps)
+  const int n2 = __builtin_amdgcn_readfirstlane(s_n);
+#pragma unroll
+  for (int s = 0; s < RS; ++s)
+#pragma unroll
+    for (int t = 0; t < CS; ++t) {
+      const int i = lane + 64 * s, j = wave + 8 * t;
+      if (i < n2 && j < n2) W[j + (int64_t)i * n2] = i >= j ? a[s][t] * rd[i] : 0.0;
+    }
   if (tid == 0) info[0] = 0;
 }
 
@@ -166,12 +244,22 @@ int chol_inverse(double* G, double* W, int n, int* info, hipStream_t s) {
   }
   static bool attr = false;
   if (!attr) {
-    RW_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_inv_lds),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
+    const void* ks[] = {reinterpret_cast<const void*>(k_chol_inv_reg<1, 8>),
+                        reinterpret_cast<const void*>(k_chol_inv_reg<2, 16>),
+                        reinterpret_cast<const void*>(k_chol_inv_reg<3, 24>),
+                        reinterpret_cast<const void*>(k_chol_inv_reg<4, 25>)};
+    for (const void* f : ks) RW_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
     attr = true;
   }
-  const size_t sh = ((size_t)n * (n + 1) / 2 + n) * sizeof(double);
-  k_chol_inv_lds<<<1, 1024, sh, s>>>(G, n, W, info);
+  const size_t sh = chol_reg_lds_bytes(n);
+  if (n <= 64)
+    k_chol_inv_reg<1, 8><<<1, kCholRegThreads, sh, s>>>(G, n, W, info);
+  else if (n <= 128)
+    k_chol_inv_reg<2, 16><<<1, kCholRegThreads, sh, s>>>(G, n, W, info);
+  else if (n <= 192)
+    k_chol_inv_reg<3, 24><<<1, kCholRegThreads, sh, s>>>(G, n, W, info);
+  else
+    k_chol_inv_reg<4, 25><<<1, kCholRegThreads, sh, s>>>(G, n, W, info);
   RW_LAUNCH_CHECK();
   return RW_OK;
 }
