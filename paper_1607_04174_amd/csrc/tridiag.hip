@@ -292,7 +292,7 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
 //     A -= v w^T + w v^T to its elements.  Elements in finished rows or columns see v = w = 0 there and keep
 //     their values; columns wholly at or left of k and row blocks wholly at or above k are skipped.
 // Outputs as k_tridiag: reflector k in refl[k n ..], tau, d and e.
-constexpr int kTriRegMax = 200;
+constexpr int kTriRegMax = 224;
 constexpr int kTriRegThreads = 512;
 static size_t tridiag_reg_lds_bytes() { return (size_t)(2 * 256 + 256 + 8 * 256) * sizeof(double); }
 
@@ -363,13 +363,13 @@ __global__ __launch_bounds__(kTriRegThreads) void k_tridiag_reg(const double* A,
       d[k] = dk;
     }
   };
-  // step k = 8 T + w (w = k mod 8, a runtime value; T, the first row slot below k (SLO) and the slot of column
-  // k+1 (T1 = T, or T + 1 when w = 7) fixed at compile time, so that no register is chosen at run time).  The
+  // step k = 8 T + w (w = k mod 8, a runtime value; T and the first row slot that can hold a row below k
+  // (SLO = T / 8) fixed at compile time, so that no register is chosen at run time).  The
   // products run over all column slots from T on, with no tests: v and p are zero at the columns j <= k and
   // j >= n and at the rows i <= k, so those elements take exact zero updates (also when tau = 0, which makes
   // p and w zero)
-  auto step = [&](int k, int w, auto Tc, auto SLOc, auto T1c) {
-    constexpr int T = decltype(Tc)::value, SLO = decltype(SLOc)::value, T1 = decltype(T1c)::value;
+  auto step = [&](int k, int w, auto Tc) {
+    constexpr int T = decltype(Tc)::value, SLO = T / 8;   // rows in slots below SLO are at or above k
     const double* vb = sv + 256 * (k & 1);
     const double tk = s_tau[k & 1];
     // v at this wave's columns, slot t in lane t mod 16 of every row of 16 lanes (of vc0 for t < 16, of vc1
@@ -430,11 +430,17 @@ __global__ __launch_bounds__(kTriRegThreads) void k_tridiag_reg(const double* A,
         asm volatile("" : "+v"(a[s][t]));   // updated here, not sunk to later uses with the broadcasts held live
       }
     });
-    if constexpr (T1 < CS) {
-      if (k + 1 < n - 2 && wave == ((w + 1) & 7)) {   // reflector k+1 from the updated column k+1
-        double x[RS];
+    // reflector k+1 from the updated column k+1, in slot T, or T + 1 after the last step of the group (a
+    // branch that only reads the tile)
+    if (k + 1 < n - 2 && wave == ((w + 1) & 7)) {
+      double x[RS];
+      if (w < 7) {
 #pragma unroll
-        for (int s = 0; s < RS; ++s) x[s] = a[s][T1];
+        for (int s = 0; s < RS; ++s) x[s] = a[s][T];
+        reflector(k + 1, x);
+      } else if constexpr (T + 1 < CS) {
+#pragma unroll
+        for (int s = 0; s < RS; ++s) x[s] = a[s][T + 1];
         reflector(k + 1, x);
       }
     }
@@ -456,20 +462,15 @@ __global__ __launch_bounds__(kTriRegThreads) void k_tridiag_reg(const double* A,
     for (int s = 0; s < RS; ++s) x[s] = a[s][0];
     reflector(0, x);
   }
-  // steps 8T .. 8T+6 in a loop, step 8T+7 (whose column k+1 sits in slot T+1) after it
+  // the eight steps of a group in one loop (a second copy of the step would hold a second register tile at
+  // the join)
   static_for<0, CS>([&](auto Tc) {
     constexpr int T = decltype(Tc)::value;
-    using TT = std::integral_constant<int, T>;
-    for (int w = 0; w < 7; ++w) {
+    for (int w = 0; w < 8; ++w) {
       const int k = 8 * T + w;
       if (k >= n - 2) break;   // uniform
       lds_barrier();           // v_k and tau_k
-      step(k, w, TT{}, std::integral_constant<int, T / 8>{}, TT{});
-    }
-    const int k = 8 * T + 7;
-    if (k < n - 2) {
-      lds_barrier();
-      step(k, 7, TT{}, std::integral_constant<int, (8 * T + 8) / 64>{}, std::integral_constant<int, T + 1>{});
+      step(k, w, std::integral_constant<int, T>{});
     }
   });
   if (tid == 0) {
@@ -491,8 +492,10 @@ static void launch_tridiag_reg(const double* A, int lda, int64_t strideA, const 
     RW_TRI_REG(2, 16);
   else if (nmax <= 192)
     RW_TRI_REG(3, 24);
-  else
+  else if (nmax <= 200)
     RW_TRI_REG(4, 25);
+  else
+    RW_TRI_REG(4, 28);
 #undef RW_TRI_REG
 }
 
@@ -1007,7 +1010,8 @@ static void tri_attrs() {
     const void* reg[] = {reinterpret_cast<const void*>(k_tridiag_reg<1, 8>),
                          reinterpret_cast<const void*>(k_tridiag_reg<2, 16>),
                          reinterpret_cast<const void*>(k_tridiag_reg<3, 24>),
-                         reinterpret_cast<const void*>(k_tridiag_reg<4, 25>)};
+                         reinterpret_cast<const void*>(k_tridiag_reg<4, 25>),
+                         reinterpret_cast<const void*>(k_tridiag_reg<4, 28>)};
     for (const void* f : reg)
       (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)tridiag_reg_lds_bytes());
     attr = true;

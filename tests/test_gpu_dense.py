@@ -36,7 +36,7 @@ def test_syev_matches_numpy(n, count):
         assert np.abs(Vb.T @ Vb - np.eye(n)).max() < 1e-12 * max(1, n / 50)
 
 
-@pytest.mark.parametrize("n", [3, 10, 64, 65, 128, 129, 150, 192, 193, 199, 200, 219, 256])
+@pytest.mark.parametrize("n", [3, 10, 64, 65, 128, 129, 150, 192, 193, 199, 200, 201, 219, 224, 225, 256])
 def test_syev_tridiag_matches_numpy(n):
     """Householder + bisection + inverse iteration on matrices with separated eigenvalues (a random
     symmetric matrix, and a Rayleigh-Ritz-like one: a positive spectrum of width 1e-2 rotated by a random
