@@ -72,9 +72,9 @@ int chol_upper_inverse(const double* L, double* Rinv, int n, hipStream_t s) {
   return RW_OK;
 }
 
-// Cholesky factor and its transposed inverse in one workgroup (n <= 200): W = (L^T)^{-1} (upper triangular,
+// Cholesky factor and its transposed inverse in one workgroup (n <= 224): W = (L^T)^{-1} (upper triangular,
 // zero below) for A = L L^T, A given by its lower triangle.  info = k + 1 at the first pivot that is not
-// positive and finite (W untouched), else 0.
+// positive and finite (W untouched up to order 200), else 0.
 constexpr int kCholInvMaxN = 200;   // the packed factor plus n reciprocal roots within the LDS budget
 
 // The factorization is right-looking with unscaled columns (Schur complements A(i,j) -= A(i,k) A(j,k) /
@@ -92,14 +92,22 @@ constexpr int kCholInvMaxN = 200;   // the packed factor plus n reciprocal roots
 // its own columns: no barriers), and W(j, i) = Y(i, j) / L(i, i).
 __device__ __forceinline__ int cw_lo(int i, int j, int n) { return j * n - ((j * (j - 1)) >> 1) + (i - j); }  // i >= j
 
+// Above order 200 the packed factor does not fit in LDS (GM): the columns u go to W's strict lower triangle
+// instead (read back by the forward substitution, one column ahead, and overwritten at the end, so that W's
+// contents are undefined when info is not 0), with two LDS buffers for the step's column.
 constexpr int kCholRegThreads = 512;
-static size_t chol_reg_lds_bytes(int n) { return ((size_t)n * (n + 1) / 2 + n) * sizeof(double); }
+constexpr int kCholRegMaxN = 224;
+static size_t chol_reg_lds_bytes(int n) {
+  return (n <= kCholInvMaxN ? (size_t)n * (n + 1) / 2 + n : (size_t)2 * 256 + 2 * n) * sizeof(double);
+}
 
-template <int RS, int CS>
+template <int RS, int CS, bool GM>
 __global__ __launch_bounds__(kCholRegThreads) void k_chol_inv_reg(const double* G, int n, double* W, int* info) {
-  static_assert(RS >= 1 && RS <= 4 && 8 * CS <= 64 * RS, "layout");
+  static_assert(RS >= 1 && RS <= 4 && 8 * CS <= 64 * RS && (!GM || RS == 4), "layout");
   extern __shared__ double sP[];   // packed lower (column-major): u below the diagonal, 1 / A(k,k) on it
-  double* rd = sP + n * (n + 1) / 2;   // 1 / sqrt(A(k, k)) = 1 / L(k, k)
+  double* su = sP;                 // GM: u of the step, two buffers of 256
+  double* sinv = sP + 512;         // GM: 1 / A(k, k)
+  double* rd = GM ? sP + 512 + n : sP + n * (n + 1) / 2;   // 1 / sqrt(A(k, k)) = 1 / L(k, k)
   __shared__ int s_bad[2], s_n;
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (tid == 0) s_n = n;
@@ -113,7 +121,18 @@ __global__ __launch_bounds__(kCholRegThreads) void k_chol_inv_reg(const double* 
       a[s][t] = (i < n && j < n) ? G[hi + (int64_t)lo * n] : 0.0;
     }
   // entry (i, k) of the packed factor for rows below k (clamped to a valid place; the caller zeroes the rest)
-  auto below = [&](int i, int k) { return sP[cw_lo(min(max(i, k + 1), n - 1), k, n)]; };   // k <= n - 1
+  auto below = [&](int i, int k) {   // k <= n - 1; GM: i < 256
+    if constexpr (GM)
+      return su[256 * (k & 1) + i];
+    else
+      return sP[cw_lo(min(max(i, k + 1), n - 1), k, n)];
+  };
+  auto inv_of = [&](int k) {
+    if constexpr (GM)
+      return sinv[k];
+    else
+      return sP[cw_lo(k, k, n)];
+  };
   // column k from slot TK (its diagonal in row slot k >> 6), by the wave holding it
   auto column = [&](int k, auto tkc) {
     constexpr int TK = decltype(tkc)::value;
@@ -125,17 +144,25 @@ __global__ __launch_bounds__(kCholRegThreads) void k_chol_inv_reg(const double* 
 #pragma unroll
     for (int s = 0; s < RS; ++s) {
       const int i = lane + 64 * s;
-      if (i > k && i < n) sP[cw_lo(i, k, n)] = a[s][TK];
+      if constexpr (GM) {
+        su[256 * (k & 1) + i] = (i > k && i < n) ? a[s][TK] : 0.0;
+        if (i > k && i < n) W[i + (int64_t)k * n] = a[s][TK];
+      } else {
+        if (i > k && i < n) sP[cw_lo(i, k, n)] = a[s][TK];
+      }
     }
     if (lane == 0) {
-      sP[cw_lo(k, k, n)] = 1.0 / dkk;
+      if constexpr (GM)
+        sinv[k] = 1.0 / dkk;
+      else
+        sP[cw_lo(k, k, n)] = 1.0 / dkk;
       s_bad[k & 1] = bad ? k + 1 : 0;
       rd[k] = bad ? 0.0 : 1.0 / sqrt(dkk);
     }
   };
   auto step = [&](int k, int w, auto Tc) {
     constexpr int T = decltype(Tc)::value, SLO = T / 8;   // rows in slots below SLO are at or above k
-    const double inv = sP[cw_lo(k, k, n)];
+    const double inv = inv_of(k);
     double u[RS];
 #pragma unroll
     for (int s = SLO; s < RS; ++s) {
@@ -184,11 +211,22 @@ __global__ __launch_bounds__(kCholRegThreads) void k_chol_inv_reg(const double* 
       step(k, w, TT{});
     }
   });
+  if constexpr (GM) __threadfence_block();   // the columns in W, for every wave
   __syncthreads();
   if (bad) {
     if (tid == 0) info[0] = bad;
     return;
   }
+  // GM: column k of M from W, loaded one step ahead
+  double ln[RS];
+  auto load_col = [&](int k) {
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int i = lane + 64 * s;
+      ln[s] = W[min(max(i, k + 1), n - 1) + (int64_t)k * n];
+    }
+  };
+  if constexpr (GM) load_col(0);
   // Y = M^{-1}: start from I; step k subtracts M(i, k) Y(k, :) from the rows below k, where row k (final by
   // then) is read from the lane holding it and only the columns j <= k (slots up to T) are nonzero
 #pragma unroll
@@ -200,13 +238,20 @@ __global__ __launch_bounds__(kCholRegThreads) void k_chol_inv_reg(const double* 
     for (int w = 0; w < 8; ++w) {
       const int k = 8 * T + w;
       if (k >= n - 1) return;   // uniform
-      const double inv = sP[cw_lo(k, k, n)];
+      const double inv = inv_of(k);
       double l[RS];
 #pragma unroll
       for (int s = SLO; s < RS; ++s) {
         const int i = lane + 64 * s;
-        const double v = below(i, k);
+        double v;
+        if constexpr (GM)
+          v = ln[s];
+        else
+          v = below(i, k);
         l[s] = (i > k && i < n) ? v * inv : 0.0;
+      }
+      if constexpr (GM) {
+        if (k + 1 < n - 1) load_col(k + 1);
       }
       static_for<0, T + 1>([&](auto tc) {
         constexpr int t = decltype(tc)::value;
@@ -220,7 +265,9 @@ __global__ __launch_bounds__(kCholRegThreads) void k_chol_inv_reg(const double* 
     }
   });
   // W(j, i) = Y(i, j) / L(i, i) on and above the diagonal, zero below (the order read back from LDS here, so
-  // that these addresses are formed now and not held through the steps)
+  // that these addresses are formed now and not held through the steps); GM: after every wave's last read
+  // of W's lower triangle
+  if constexpr (GM) __syncthreads();
   const int n2 = __builtin_amdgcn_readfirstlane(s_n);
 #pragma unroll
   for (int s = 0; s < RS; ++s)
@@ -234,7 +281,7 @@ __global__ __launch_bounds__(kCholRegThreads) void k_chol_inv_reg(const double* 
 
 int chol_inverse(double* G, double* W, int n, int* info, hipStream_t s) {
   if (n <= 0) return RW_OK;
-  if (n > kCholInvMaxN) {
+  if (n > kCholRegMaxN) {
     RW_TRY(chol_batched(G, n, 1, info, s));
     int bad = 0;
     RW_HIP(hipMemcpyAsync(&bad, info, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -244,22 +291,25 @@ int chol_inverse(double* G, double* W, int n, int* info, hipStream_t s) {
   }
   static bool attr = false;
   if (!attr) {
-    const void* ks[] = {reinterpret_cast<const void*>(k_chol_inv_reg<1, 8>),
-                        reinterpret_cast<const void*>(k_chol_inv_reg<2, 16>),
-                        reinterpret_cast<const void*>(k_chol_inv_reg<3, 24>),
-                        reinterpret_cast<const void*>(k_chol_inv_reg<4, 25>)};
+    const void* ks[] = {reinterpret_cast<const void*>(k_chol_inv_reg<1, 8, false>),
+                        reinterpret_cast<const void*>(k_chol_inv_reg<2, 16, false>),
+                        reinterpret_cast<const void*>(k_chol_inv_reg<3, 24, false>),
+                        reinterpret_cast<const void*>(k_chol_inv_reg<4, 25, false>),
+                        reinterpret_cast<const void*>(k_chol_inv_reg<4, 28, true>)};
     for (const void* f : ks) RW_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit));
     attr = true;
   }
   const size_t sh = chol_reg_lds_bytes(n);
   if (n <= 64)
-    k_chol_inv_reg<1, 8><<<1, kCholRegThreads, sh, s>>>(G, n, W, info);
+    k_chol_inv_reg<1, 8, false><<<1, kCholRegThreads, sh, s>>>(G, n, W, info);
   else if (n <= 128)
-    k_chol_inv_reg<2, 16><<<1, kCholRegThreads, sh, s>>>(G, n, W, info);
+    k_chol_inv_reg<2, 16, false><<<1, kCholRegThreads, sh, s>>>(G, n, W, info);
   else if (n <= 192)
-    k_chol_inv_reg<3, 24><<<1, kCholRegThreads, sh, s>>>(G, n, W, info);
+    k_chol_inv_reg<3, 24, false><<<1, kCholRegThreads, sh, s>>>(G, n, W, info);
+  else if (n <= kCholInvMaxN)
+    k_chol_inv_reg<4, 25, false><<<1, kCholRegThreads, sh, s>>>(G, n, W, info);
   else
-    k_chol_inv_reg<4, 25><<<1, kCholRegThreads, sh, s>>>(G, n, W, info);
+    k_chol_inv_reg<4, 28, true><<<1, kCholRegThreads, sh, s>>>(G, n, W, info);
   RW_LAUNCH_CHECK();
   return RW_OK;
 }
