@@ -1,11 +1,11 @@
 // Symmetric eigendecomposition through a tridiagonal form, for one matrix of order n <= 256 (batches of
 // matrices up to order 199):
-//   1. Householder reduction A = U T U^T (Golub & Van Loan Sec. 8.3.1) in one workgroup with the
-//      packed lower triangle in LDS: per column, one wave forms the reflector (the next column's while
-//      the other waves finish the rank-2 update), 4 to 16 lanes per row form p = tau A22 v, every wave
-//      forms K = tau/2 p^T v, and all threads apply the rank-2 update A22 -= v w^T + w v^T with
-//      w = p - K v.  Above order 199 the packed triangle exceeds the LDS: the first n - 199 columns are
-//      reduced on a full copy in global memory (L2-resident) and the rest in LDS;
+//   1. Householder reduction A = U T U^T (Golub & Van Loan Sec. 8.3.1) in one workgroup: up to order 224
+//      with the matrix in registers (k_tridiag_reg, below); above, with the packed lower triangle in LDS:
+//      per column, one wave forms the reflector (the next column's while the other waves finish the
+//      rank-2 update), 4 to 16 lanes per row form p = tau A22 v, every wave forms K = tau/2 p^T v, and all
+//      threads apply the rank-2 update A22 -= v w^T + w v^T with w = p - K v; the first n - 199 columns
+//      are reduced on a full copy in global memory (L2-resident) and the rest in LDS;
 //   2. eigenvalues of T by multisection on Sturm counts (Sec. 8.4.1), kBisThreads points per pass, one
 //      workgroup per eigenvalue (the interval shrinks kBisThreads + 1-fold per pass);
 //   3. eigenvectors of T by inverse iteration with the LDL^T factorization of T - lambda I (one lane
@@ -281,16 +281,17 @@ __global__ __launch_bounds__(1024) void k_tridiag(const double* A, int lda, int6
 // 1'. The same reduction with the matrix in registers, for orders up to kTriRegMax: 512 threads, thread
 // (lane, wave) holds A(i, j) for the rows i = lane + 64 s (s < RS) and the columns j = wave + 8 t (t < CS),
 // both triangles, so that no step reads or writes the matrix in LDS.  Per column k:
-//   * the wave that holds column k (wave k mod 8) forms reflector k from its registers, one step ahead:
-//     during the update of step k-1, right after updating that column, while the other waves update theirs;
-//     v (zero at i <= k and i >= n, 1 at k+1) goes to LDS (two buffers, by the parity of k);
+//   * the wave that holds column k (wave k mod 8) forms reflector k from its registers at the end of step
+//     k-1, once its update is done; v (zero at i <= k and i >= n, 1 at k+1) goes to LDS (two buffers, by the
+//     parity of k);
 //   * barrier; each thread sums A(i, j) v_j over its columns for each of its rows (v_j by a row broadcast
 //     from a copy of v that holds the wave's columns in the 16 lanes of each row); the row partials of the
 //     eight waves go to LDS;
 //   * barrier; 256 threads add a row's eight partials in a fixed order: p = tau A22 v (zero at i <= k);
 //   * barrier; every wave forms K = tau/2 p^T v and w = p - K v, and each thread applies
 //     A -= v w^T + w v^T to its elements.  Elements in finished rows or columns see v = w = 0 there and keep
-//     their values; columns wholly at or left of k and row blocks wholly at or above k are skipped.
+//     their values; column slots left of the step's group of eight columns and row slots above it are
+//     skipped.
 // Outputs as k_tridiag: reflector k in refl[k n ..], tau, d and e.
 constexpr int kTriRegMax = 224;
 constexpr int kTriRegThreads = 512;
