@@ -705,7 +705,7 @@ __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_lds(const double* As,
 __global__ __launch_bounds__(kJacobiThreads) void k_jacobi_glb(const double* As, int n, double* ws, double* Rs, int nrhs,
                                                                 double* work, int64_t stride, int want_log,
                                                                 double min_rel_tol) {
-  const int n2 = n + (n & 1), np = n2 / 2;
+  const int n2 = n + (n & 1);
   __shared__ double cs[512], sn[512];
   __shared__ int pq[1024];
   const double* A = As + (int64_t)blockIdx.x * n * n;
@@ -878,7 +878,7 @@ int syev_batched(const double* A, double* w, double* V, double* R, int nrhs, int
 // pivot falls below 1e-14 max |a_ij| (the solve is then abandoned).
 // ---------------------------------------------------------------------------------------------
 __device__ void lu_body(double* A, int n, double* B, int nrhs, double* stat) {
-  __shared__ double s_amax, s_piv, s_minpiv;
+  __shared__ double s_amax, s_minpiv;
   __shared__ int s_prow, s_bad;
   if (threadIdx.x < 64) {
     double m = 0.0;
@@ -903,7 +903,6 @@ __device__ void lu_body(double* A, int n, double* B, int nrhs, double* stat) {
       }
       if (threadIdx.x == 0) {
         s_prow = brow;
-        s_piv = best;
         if (!(best > 1e-14 * amax)) s_bad = 1;
         s_minpiv = fmin(s_minpiv, best);
       }
