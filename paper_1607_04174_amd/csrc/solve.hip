@@ -567,7 +567,7 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-constexpr int kScreenMaxKM = 192;   // three entries per lane in the inverse's back substitution
+constexpr int kScreenMaxKM = 192;   // the inverse's forward substitution: 3 row slots x 12 column slots
 
 static size_t screen_lds_bytes(int KM, int C) {
   return ((size_t)KM * (KM + 1) + 2 * (size_t)KM * C + 2 * (size_t)KM + 3 * (size_t)C) * sizeof(double);
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int6
   extern __shared__ double sm[];
   const int tri = KM * (KM + 1) / 2;
   double* A = sm;              // packed lower (column-major): G_m, then L column by column; later Ri (packed upper)
-  double* B = A + tri;         // packed upper: L^T, later the prefix sums P
+  double* B = A + tri;         // packed upper: the prefix sums P
   double* G = B + tri;         // KM x C right-hand sides g = Q_s^T u, updated
   double* Z = G + KM * C;      // KM x C, z = L^{-1} g
   double* rd = Z + KM * C;     // 1 / L(k, k)
@@ -727,39 +727,51 @@ __global__ __launch_bounds__(1024) void k_fit_screen(int ma, int KM, int C, int6
   if (pend_k >= 0 && tid == 0) A[scr_lo(pend_k + 1, pend_k, KM)] = pend_l;
   __syncthreads();
   const int kf = s_kf;      // leading blocks of size <= kf are factorized
-  // L^T (packed upper)
-  for (int t = tid; t < kf * kf; t += blockDim.x) {
-    const int i = t % kf, j = t / kf;
-    if (i > j) B[scr_up(j, i)] = A[scr_lo(i, j, KM)];
-  }
-  __syncthreads();
-  // Ri = L^{-T} (packed upper, over A): column j solves L^T x = e_j; columns are spread over the waves
-  // in a zigzag so that long and short columns pair up
-  const int wave = tid >> 6, lane = tid & 63, nw = blockDim.x >> 6;
-  for (int g0 = 0; g0 < kf; g0 += nw) {
-    const int grp = g0 / nw;
-    const int j = (grp & 1) ? g0 + nw - 1 - wave : g0 + wave;
-    if (j >= kf) continue;
-    double bv[3];
+  // Ri = L^{-T} (packed upper, over A): with D = diag(L) and the unit lower M = L D^{-1} (M(i, k) = L(i, k)
+  // rd[k]), L^{-1} = D^{-1} M^{-1}.  Y = M^{-1} by forward substitution on all columns at once, thread
+  // (lane, wave) holding Y(i, j) for the rows i = lane + 64 s and the columns j = wave + 16 t (each wave its
+  // own columns: no barriers; step k = 16 T + w with T unrolled, so that row k's slot is known at compile
+  // time); then Ri(j, i) = Y(i, j) rd[i], written over L once every wave has read it
+  {
+    constexpr int YR = (kScreenMaxKM + 63) / 64, YC = (kScreenMaxKM + 15) / 16;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    double y[YR][YC];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) bv[r] = (lane + 64 * r == j) ? 1.0 : 0.0;
-    double xv[3] = {0.0, 0.0, 0.0};
-    for (int k = j; k >= 0; --k) {
-      const int rk = k >> 6;
-      const double bk = rk == 0 ? bv[0] : (rk == 1 ? bv[1] : bv[2]);
-      const double xk = readlane_d(bk, k & 63) * rd[k];
+    for (int s = 0; s < YR; ++s)
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const int i = lane + 64 * r;
-        if (i == k) xv[r] = xk;
-        if (i < k) bv[r] -= B[scr_up(i, k)] * xk;   // L(k, i) = L^T(i, k)
+      for (int t = 0; t < YC; ++t) y[s][t] = (lane + 64 * s == wave + 16 * t && lane + 64 * s < kf) ? 1.0 : 0.0;
+    static_for<0, YC>([&](auto Tc) {
+      constexpr int T = decltype(Tc)::value, SK = T / 4;   // row slot of k = 16 T + w
+      for (int w = 0; w < 16; ++w) {
+        const int k = 16 * T + w;
+        if (k >= kf - 1) return;   // uniform
+        const double rk = rd[k];
+        double l[YR];
+#pragma unroll
+        for (int s = 0; s < YR; ++s) {
+          const int i = lane + 64 * s;
+          const double v = A[scr_lo(min(max(i, k + 1), kf - 1), k, KM)];
+          l[s] = (i > k && i < kf) ? v * rk : 0.0;
+        }
+        static_for<0, T + 1>([&](auto tc) {
+          constexpr int t = decltype(tc)::value;
+          const double yk = lane_read(y[SK][t], k & 63);
+#pragma unroll
+          for (int s = 0; s < YR; ++s) {
+            y[s][t] -= l[s] * yk;
+            asm volatile("" : "+v"(y[s][t]));   // updated here, not sunk to later uses
+          }
+        });
       }
-    }
+    });
+    __syncthreads();   // every wave has read L
 #pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const int i = lane + 64 * r;
-      if (i <= j) A[scr_up(i, j)] = xv[r];
-    }
+    for (int s = 0; s < YR; ++s)
+#pragma unroll
+      for (int t = 0; t < YC; ++t) {
+        const int i = lane + 64 * s, j = wave + 16 * t;
+        if (i < kf && j <= i) A[scr_up(j, i)] = y[s][t] * rd[i];
+      }
   }
   __syncthreads();
   // per m in [1, ma]: residual r(m) = ||b||^2 - sum_{j<m} z_j^2 and the fit's squared norm
