@@ -79,7 +79,6 @@ static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base,
   t.Bg = c.take<double>(S);
   t.cn = c.take<double>(2 * (size_t)ma);
   t.npart = c.take<double>(null_stats_partial_count(g->N, ma));
-  t.nbad = c.take<int>(4);
   t.Gq = c.take<double>((size_t)ma * ma);
   t.Gb = c.take<double>((size_t)ma * C);
   const int nc = fit ? fit_cands(ma) : 0;
@@ -94,6 +93,7 @@ static size_t solve_layout(const Graph* g, int ma, int64_t S, int C, void* base,
   t.K = c.take<double>((size_t)ma * ma);
   t.Y = c.take<double>((size_t)ma * C);
   t.stat = c.take<double>(8);
+  t.nbad = c.take<int>(4);   // after stat: the two are read back with one copy
   size_t pc = std::max(gram_partial_count(S, ma, ma), gram_partial_count(S, ma, C));
   t.partial = c.take<double>(pc);
   t.scrF = c.take<double>((size_t)ma + 1);
@@ -878,8 +878,11 @@ static int host_seeds_into(const Graph* g, const int64_t* seed_node, const int32
   return RW_OK;
 }
 
+// Host bytes that hold the status words read back at the end of a solve.
+constexpr size_t kStatusStageBytes = 512;
+
 // The solve on sorted, distinct seeds (S of them; the workspace is laid out for S_cap >= S).  final_stage:
-// host memory for the three status words read at the end (pinned staging when null).
+// host memory (kStatusStageBytes) for the three status words read at the end (pinned staging when null).
 static int solve_impl(rw_graph h, const void* Q, int q_dtype, const double* lambda, int m_avail, const int64_t* nodes,
                       const int32_t* labels, int64_t S, int64_t S_cap, int C, double eps, void* U, const SolveWork& w,
                       hipStream_t stream, rw_solve_info* info, void* final_stage) {
@@ -922,12 +925,14 @@ static int solve_impl(rw_graph h, const void* Q, int q_dtype, const double* lamb
       k_fit_screen<<<1, 1024, screen_lds_bytes(KM, C), stream>>>(ma, KM, C, S, w.Gq, w.Gb, w.Us, rho_sums,
                                                                   (double)g->N, f_max, w.scrF, w.scrCls);
       RW_LAUNCH_CHECK();
+      // F and the classes are adjacent in the workspace: one copy of the span that holds both
+      const size_t cls_off = reinterpret_cast<const char*>(w.scrCls) - reinterpret_cast<const char*>(w.scrF);
+      const size_t span = cls_off + (size_t)(ma + 1) * sizeof(int);
       void* stage = nullptr;
-      RW_TRY(host_stage((size_t)(ma + 1) * (sizeof(double) + sizeof(int)), &stage));
-      double* frs = static_cast<double*>(stage);
-      int* clss = reinterpret_cast<int*>(frs + ma + 1);
-      RW_HIP(hipMemcpyAsync(clss, w.scrCls, (ma + 1) * sizeof(int), hipMemcpyDeviceToHost, stream));
-      RW_HIP(hipMemcpyAsync(frs, w.scrF, (ma + 1) * sizeof(double), hipMemcpyDeviceToHost, stream));
+      RW_TRY(host_stage(span, &stage));
+      const double* frs = static_cast<const double*>(stage);
+      const int* clss = reinterpret_cast<const int*>(static_cast<const char*>(stage) + cls_off);
+      RW_HIP(hipMemcpyAsync(stage, w.scrF, span, hipMemcpyDeviceToHost, stream));
       RW_HIP(hipStreamSynchronize(stream));
       const std::vector<int> cls(clss, clss + ma + 1);
       const std::vector<double> fr(frs, frs + ma + 1);
@@ -1043,17 +1048,21 @@ static int solve_impl(rw_graph h, const void* Q, int q_dtype, const double* lamb
   // the reconstruction is queued before the pivot test is read (one wait for both); U is not valid when
   // the test fails
   RW_TRY(reconstruct(g, Q, q_dtype, m, w.Y, C, w.map, U, stream));
+  // stat and the null-column flag are adjacent in the workspace (one copy); the anchor flag follows them
+  const size_t nbad_off = reinterpret_cast<const char*>(w.nbad) - reinterpret_cast<const char*>(w.stat);
+  const size_t bad_off = (nbad_off + sizeof(int) + 7) & ~size_t(7);
+  RW_CHECK(bad_off + sizeof(int) <= kStatusStageBytes, RW_EINVAL, "status staging too small (%zu bytes)", bad_off);
   void* stage = final_stage;
-  if (stage == nullptr) RW_TRY(host_stage(2 * sizeof(double), &stage));
-  double* hs = static_cast<double*>(stage);
-  RW_HIP(hipMemcpyAsync(hs, w.stat, sizeof(double), hipMemcpyDeviceToHost, stream));
-  RW_HIP(hipMemcpyAsync(hs + 1, unanchored, sizeof(int), hipMemcpyDeviceToHost, stream));
-  RW_HIP(hipMemcpyAsync(reinterpret_cast<int*>(hs + 1) + 1, w.nbad, sizeof(int), hipMemcpyDeviceToHost, stream));
+  if (stage == nullptr) RW_TRY(host_stage(kStatusStageBytes, &stage));
+  char* hs = static_cast<char*>(stage);
+  RW_HIP(hipMemcpyAsync(hs, w.stat, nbad_off + sizeof(int), hipMemcpyDeviceToHost, stream));
+  RW_HIP(hipMemcpyAsync(hs + bad_off, unanchored, sizeof(int), hipMemcpyDeviceToHost, stream));
   RW_HIP(hipStreamSynchronize(stream));
-  const double stat = hs[0];
+  double stat = 0.0;
   int bad = 0, nbad = 0;
-  std::memcpy(&bad, hs + 1, sizeof(int));
-  std::memcpy(&nbad, reinterpret_cast<int*>(hs + 1) + 1, sizeof(int));
+  std::memcpy(&stat, hs, sizeof(double));
+  std::memcpy(&bad, hs + bad_off, sizeof(int));
+  std::memcpy(&nbad, hs + nbad_off, sizeof(int));
   RW_CHECK(!bad, RW_EUNANCHORED,
            "a connected component (edges with w >= 1e-30) holds no seed: the gamma = 0 system is singular");
   RW_CHECK(!nbad, RW_EINVAL, "basis column %d lies in the span of the null vector (column 0)", nbad);
@@ -1116,7 +1125,7 @@ static void* g_na_ptr[kNoAllocMaxDevices] = {};
 static std::pair<int64_t, int32_t> g_na_pairs[kNoAllocMaxSeeds];
 static int64_t g_na_nodes[kNoAllocMaxSeeds];
 static int32_t g_na_labels[kNoAllocMaxSeeds];
-static double g_na_stage[2];
+static double g_na_stage[kStatusStageBytes / sizeof(double)];
 
 static int noalloc_scratch(void** ptr) {
   int dev = -1;
@@ -1345,15 +1354,17 @@ static int prior_solve_impl(rw_graph h, const void* Q, int q_dtype, const double
   RW_LAUNCH_CHECK();
   RW_TRY(solve_coeffs(w.Y, m, C, w.cn, g, stream));
   RW_TRY(reconstruct(g, Q, q_dtype, m, w.Y, C, w.map, U, stream));
+  // stat and the null-column flag are adjacent in the workspace: one copy
+  const size_t nbad_off = reinterpret_cast<const char*>(w.nbad) - reinterpret_cast<const char*>(w.stat);
   void* stage = nullptr;
-  RW_TRY(host_stage(2 * sizeof(double), &stage));
-  double* hs = static_cast<double*>(stage);
-  RW_HIP(hipMemcpyAsync(hs, w.stat, sizeof(double), hipMemcpyDeviceToHost, stream));
-  RW_HIP(hipMemcpyAsync(hs + 1, w.nbad, sizeof(int), hipMemcpyDeviceToHost, stream));
+  RW_TRY(host_stage(nbad_off + sizeof(int), &stage));
+  const char* hs = static_cast<const char*>(stage);
+  RW_HIP(hipMemcpyAsync(stage, w.stat, nbad_off + sizeof(int), hipMemcpyDeviceToHost, stream));
   RW_HIP(hipStreamSynchronize(stream));
-  const double stat = hs[0];
+  double stat = 0.0;
   int nbad = 0;
-  std::memcpy(&nbad, hs + 1, sizeof(int));
+  std::memcpy(&stat, hs, sizeof(double));
+  std::memcpy(&nbad, hs + nbad_off, sizeof(int));
   RW_CHECK(!nbad, RW_EINVAL, "basis column %d lies in the span of the null vector (column 0)", nbad);
   RW_CHECK(stat > 0.0, RW_ESINGULAR, "reduced seed system is singular to working precision (m = %d)", m);
   if (info) {
