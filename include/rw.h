@@ -576,8 +576,9 @@ int rw_dense_syev(const double* A, double* w, double* V, int n, int count, void*
 /* Symmetric eigendecomposition of one matrix A (device, n x n column-major, read only; only the
  * symmetric part is used) through its tridiagonal form: Householder reduction A = U T U^T (Golub & Van
  * Loan Sec. 8.3.1), eigenvalues of T by bisection on Sturm counts (Sec. 8.4.1), eigenvectors of T by
- * inverse iteration, V = U Z.  w (device, n, ascending) and V (device, n x n, eigenvectors as columns).
- * 3 <= n <= 256 (above 199 the first n - 199 columns are reduced in global memory, the rest in LDS).
+ * inverse iteration, V = U Z.  w (device, n, ascending) and V (device, n x n, eigenvectors as columns);
+ * w, V and work do not overlap one another.  3 <= n <= 256 (up to 224 the reduction holds the matrix in
+ * registers; above, the first n - 199 columns are reduced in global memory, the rest in LDS).
  * Inverse iteration needs separated eigenvalues: when two are closer than 1e-6 of the
  * largest Gershgorin row sum it returns RW_ENOCONV (w holds the eigenvalues; V is not reliable) and the
  * Jacobi routine above should be used.  work: device buffer of rw_dense_syev_tridiag_workspace_bytes.

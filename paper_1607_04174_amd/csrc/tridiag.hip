@@ -1086,19 +1086,18 @@ int syev_tridiag(const double* A, double* w, double* V, int n, double* work, hip
     const int nl = std::min(n, kTriLdsMax);
     k_tridiag<<<1, 1024, tridiag_lds_bytes(nl), s>>>(A, n, 0, sz, n, b.refl, b.tau, b.d, b.e, b.flag, b.Lf, n - nl);
   }
-  k_tri_bisect<<<n, kBisThreads, 0, s>>>(b.d, b.e, sz, n, b.lam, b.flag);
-  launch_invit(b.d, b.e, sz, n, 1, b.lam, b.Z, s);
-  k_tri_cluster<<<1, 64, cluster_lds_bytes(n), s>>>(b.d, b.e, sz, n, b.lam, b.Z, b.flag);
+  // the eigenvalues go straight to w (bisection, inverse iteration and the cluster pass read them there)
+  k_tri_bisect<<<n, kBisThreads, 0, s>>>(b.d, b.e, sz, n, w, b.flag);
+  launch_invit(b.d, b.e, sz, n, 1, w, b.Z, s);
+  k_tri_cluster<<<1, 64, cluster_lds_bytes(n), s>>>(b.d, b.e, sz, n, w, b.Z, b.flag);
   k_tri_back<<<n, 64, 0, s>>>(b.refl, b.tau, n, b.Z, V);
   RW_LAUNCH_CHECK();
   if (flag_dev != nullptr) {
     *flag_dev = b.flag;
-    RW_HIP(hipMemcpyAsync(w, b.lam, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
     return RW_OK;
   }
   double flag = 0.0;
   RW_HIP(hipMemcpyAsync(&flag, b.flag, sizeof(double), hipMemcpyDeviceToHost, s));
-  RW_HIP(hipMemcpyAsync(w, b.lam, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
   RW_HIP(hipStreamSynchronize(s));
   if (flag != 0.0) return RW_ENOCONV;   // clustered eigenvalues: the caller uses the Jacobi solver
   return RW_OK;
