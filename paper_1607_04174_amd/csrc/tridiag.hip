@@ -31,7 +31,7 @@ static size_t tridiag_lds_bytes(int n) { return ((size_t)n * (n + 1) / 2 + 2 * (
 constexpr int kTriLdsMax = 199;   // the largest order whose packed triangle (and two vectors) fit in LDS
 
 static size_t invit_lds_bytes(int n, int tpb);
-bool tridiag_batch_fits(int n) {   // n <= 199: the whole reduction in LDS
+bool tridiag_batch_fits(int n) {   // n <= 199: the batched range (inverse iteration stages 32 vectors in LDS)
   return n >= 3 && n <= kTriLdsMax && tridiag_lds_bytes(n) <= kLdsLimit && invit_lds_bytes(n, 32) <= kLdsLimit;
 }
 bool tridiag_fits(int n) { return n >= 3 && n <= 256; }
